@@ -1,0 +1,157 @@
+"""Python access to the plain FP64 CPU oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the GPU library or its binding.  The
+oracle shares no code with the GPU path; it follows the paper's Algorithm 1
+(LOWD) and Algorithm 2 (Pruning) step by step, sequentially, in FP64.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_u8p = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc; -ffp-contract=off keeps every product and
+    sum rounded on its own, exactly as written."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
+                               "-Wall", "-fPIC", "-shared", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = C.CDLL(_LIB)
+        i64 = C.c_int64
+        fptr = C.c_void_p
+        lib.oracle_prune.argtypes = [i64, i64, _i32p, _i32p, _u8p, C.POINTER(C.c_int32),
+                                     C.POINTER(i64), C.POINTER(i64)]
+        lib.oracle_schedule.argtypes = [i64, i64, _i32p, _i32p, C.c_int32, _i32p, _i32p, _i32p,
+                                        C.POINTER(C.c_int32)]
+        lib.oracle_init.argtypes = [i64, i64, _i32p, _i32p, fptr, _f64p, _f64p]
+        lib.oracle_sweep.argtypes = [i64, i64, _i32p, _i32p, fptr, _i32p, i64, C.c_int32, _f64p, _f64p]
+        lib.oracle_stats.argtypes = [i64, _f64p, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double)]
+        lib.oracle_extract.argtypes = [i64, i64, _i32p, _i32p, fptr, _f64p, _u8p, C.POINTER(i64),
+                                       C.POINTER(i64), C.POINTER(C.c_double), C.POINTER(i64)]
+        for f in (lib.oracle_prune, lib.oracle_schedule, lib.oracle_init, lib.oracle_sweep,
+                  lib.oracle_stats, lib.oracle_extract):
+            f.restype = C.c_int
+        _lib = lib
+    return _lib
+
+
+def _wptr(w: Optional[np.ndarray]):
+    if w is None:
+        return None, None
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    return w, w.ctypes.data_as(C.c_void_p)
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise RuntimeError(f"{what} failed with status {rc}")
+
+
+def prune(n: int, src: np.ndarray, dst: np.ndarray):
+    """Algorithm 2 on an unweighted graph -> (node_keep u8[n], rounds, n_h, m_h)."""
+    lib = _load()
+    keep = np.zeros(n, dtype=np.uint8)
+    r = C.c_int32(0)
+    nh = C.c_int64(0)
+    mh = C.c_int64(0)
+    _check(lib.oracle_prune(n, src.size, src, dst, keep, C.byref(r), C.byref(nh), C.byref(mh)),
+           "oracle_prune")
+    return keep, int(r.value), int(nh.value), int(mh.value)
+
+
+def schedule(n: int, src: np.ndarray, dst: np.ndarray, smax: int = 16):
+    """Phase schedule -> (phase i32[m], center i32[m], order i32[m], nphases)."""
+    lib = _load()
+    m = src.size
+    phase = np.zeros(m, dtype=np.int32)
+    center = np.zeros(m, dtype=np.int32)
+    order = np.zeros(m, dtype=np.int32)
+    P = C.c_int32(0)
+    _check(lib.oracle_schedule(n, m, src, dst, smax, phase, center, order, C.byref(P)),
+           "oracle_schedule")
+    return phase, center, order, int(P.value)
+
+
+def init(n: int, src: np.ndarray, dst: np.ndarray, w: Optional[np.ndarray]):
+    """Algorithm 1 initialisation -> (x f64[m], L f64[n])."""
+    lib = _load()
+    m = src.size
+    x = np.zeros(m, dtype=np.float64)
+    L = np.zeros(n, dtype=np.float64)
+    w, wp = _wptr(w)
+    _check(lib.oracle_init(n, m, src, dst, wp, x, L), "oracle_init")
+    return x, L
+
+
+def sweep(n: int, src: np.ndarray, dst: np.ndarray, w: Optional[np.ndarray], order: np.ndarray,
+          T: int, x: np.ndarray, L: np.ndarray) -> None:
+    """T sweeps of the locally optimal step over `order`, in place on x, L."""
+    lib = _load()
+    w, wp = _wptr(w)
+    order = np.ascontiguousarray(order, dtype=np.int32)
+    _check(lib.oracle_sweep(n, src.size, src, dst, wp, order, order.size, T, x, L),
+           "oracle_sweep")
+
+
+def stats(L: np.ndarray):
+    """(D = max load, sum of loads, sum of squared loads)."""
+    lib = _load()
+    D = C.c_double(0)
+    s = C.c_double(0)
+    s2 = C.c_double(0)
+    _check(lib.oracle_stats(L.size, L, C.byref(D), C.byref(s), C.byref(s2)), "oracle_stats")
+    return D.value, s.value, s2.value
+
+
+def extract(n: int, src: np.ndarray, dst: np.ndarray, w: Optional[np.ndarray], L: np.ndarray):
+    """Sort-and-peel extraction -> dict(in_set u8[n], best_i, num, num_w, den)."""
+    lib = _load()
+    in_set = np.zeros(n, dtype=np.uint8)
+    bi = C.c_int64(0)
+    nu = C.c_int64(0)
+    nw = C.c_double(0)
+    den = C.c_int64(0)
+    w, wp = _wptr(w)
+    _check(lib.oracle_extract(n, src.size, src, dst, wp, L, in_set, C.byref(bi), C.byref(nu),
+                              C.byref(nw), C.byref(den)), "oracle_extract")
+    return dict(in_set=in_set, best_i=int(bi.value), num=int(nu.value), num_w=float(nw.value),
+                den=int(den.value))
+
+
+def solve(n: int, src: np.ndarray, dst: np.ndarray, w: Optional[np.ndarray], T: int,
+          smax: int = 16):
+    """Init, T sweeps in schedule order, extraction, statistics."""
+    phase, center, order, P = schedule(n, src, dst, smax)
+    x, L = init(n, src, dst, w)
+    sweep(n, src, dst, w, order, T, x, L)
+    ex = extract(n, src, dst, w, L)
+    D, s, s2 = stats(L)
+    rho = (ex["num"] if w is None else ex["num_w"]) / ex["den"]
+    ex.update(x=x, L=L, D=D, sumL=s, sumL2=s2, rho=rho, gap=(D - rho) / rho, order=order,
+              phase=phase, nphases=P)
+    return ex
