@@ -1,0 +1,238 @@
+/*
+ * lowd.h -- C interface of liblowd.so, the MI355X (gfx950) implementation of
+ * the LOWD densest-subgraph method: Locally Optimal Weight Distribution
+ * (Algorithm 1) and its pruning pre-process (Algorithm 2) from Zhu, Liu, Feng,
+ * Cheng, "Fast Searching The Densest Subgraph And Decomposition With Local
+ * Optimality" (arXiv 2307.15969).
+ *
+ * Conventions for every entry point
+ *  - Graphs are COO edge lists, one entry per undirected edge (Section II,
+ *    Problem 1: G = (V, E, W), w_e > 0, w_e = 1 when unweighted).  Node ids
+ *    are int32 in [0, n); an edge list must be simple: src[e] != dst[e], no
+ *    unordered pair twice.  Weights are float32 > 0 and finite, or NULL for
+ *    an unweighted graph.
+ *  - Pointers marked [device] are HIP device pointers that the caller owns;
+ *    the library borrows them for the duration of the call (or, for a
+ *    solver, until lowd_solver_free) and never frees them.  Pointers marked
+ *    [host] are ordinary host memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued on that stream.  Calls that return host values
+ *    synchronise the stream before returning; that is stated per call.
+ *  - Every call returns a lowd_status.  Negative values are errors; the
+ *    message of the last error on the calling thread is available from
+ *    lowd_last_error().  No C++ exception crosses this interface.
+ */
+#ifndef LOWD_H
+#define LOWD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lowd_status;
+#define LOWD_OK 0
+#define LOWD_E_ARG (-1)         /* bad pointer, size or option */
+#define LOWD_E_GRAPH (-2)       /* id out of range, self-loop, repeated pair, bad weight */
+#define LOWD_E_HIP (-4)         /* a HIP runtime call failed */
+#define LOWD_E_UNSUPPORTED (-5) /* valid request this build does not implement */
+#define LOWD_E_NOMEM (-6)       /* host or device allocation failed */
+
+/* Precision of the solver state (edge fractions and node loads). */
+#define LOWD_STATE_F64 0  /* FP64 fractions and loads; bit-reproducible */
+#define LOWD_STATE_F32K 1 /* FP32 fractions, FP32 loads with a compensation term */
+
+typedef struct lowd_solver lowd_solver;
+
+/* Library version string. */
+const char *lowd_version(void);
+
+/* Message of the last failed call on this thread ("" if none).  Valid until
+ * the next call on the same thread. */
+const char *lowd_last_error(void);
+
+/*
+ * lowd_prune -- Algorithm 2 (Pruning) on an unweighted graph, with the
+ * counting-sort bucket scheme of Section III-D: starting from H = G, each
+ * round removes every node whose degree in H is below the density
+ * rho(H) = |E(H)| / |V(H)| (decided exactly as deg * |V(H)| < |E(H)|), then
+ * recomputes rho(H); it stops when a round removes nothing.  By Theorem 3 no
+ * node of a densest subgraph is removed.
+ *
+ *   n, m          nodes and edges of G (n >= 1, m >= 0)
+ *   src, dst      [device] int32[m] edge list of G
+ *   node_keep     [device] uint8[n] out: 1 if the node is in H
+ *   relabel       [device] int32[n] out: id of the node in H (kept nodes are
+ *                 numbered 0..n_h-1 in ascending original id), -1 if removed;
+ *                 may be NULL
+ *   h_src, h_dst  [device] int32[m] out: the edge list of H in H's ids, the
+ *                 kept edges in their original relative order (the first
+ *                 *m_h entries are written); may both be NULL
+ *   edge_map      [device] int64[m] out: original index of each H edge; may
+ *                 be NULL
+ *   rounds, n_h, m_h  [host] out: removal rounds, |V(H)|, |E(H)|
+ * Synchronises `stream`.  Weighted pruning is not provided: weights are not
+ * an argument.
+ */
+lowd_status lowd_prune(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                       uint8_t *node_keep, int32_t *relabel, int32_t *h_src, int32_t *h_dst,
+                       int64_t *edge_map, int32_t *rounds, int32_t *n_h, int64_t *m_h,
+                       void *stream);
+
+/*
+ * lowd_init_loads -- Algorithm 1, initialisation: every edge gives half its
+ * weight to each endpoint (f_e(u) = f_e(v) = w_e / 2) and the load of a node
+ * is the sum of the halves it receives, summed in ascending edge index.
+ * Also validates the graph and builds, once, the edge schedule the sweeps
+ * follow: the edges are split into phases, each phase a set of vertex-
+ * disjoint stars of at most `star_max` leaves (the center of an edge is its
+ * endpoint of larger degree, ties to the smaller id; edge e, in ascending
+ * index, joins the first phase where its center is not a leaf and has fewer
+ * than star_max leaves and its leaf is unused).  A sweep processes the phases
+ * in order; the result equals processing the edges one by one in ascending
+ * (phase, edge index).
+ *
+ *   n, m          nodes and edges (n >= 1, m >= 0, m < 2^31)
+ *   src, dst      [device] int32[m]; read during this call only
+ *   w             [device] float32[m] or NULL (unit weights); read during
+ *                 this call only
+ *   state         LOWD_STATE_F64 or LOWD_STATE_F32K
+ *   star_max      leaves per star per phase, 1..254 (1 gives a proper edge
+ *                 colouring: every phase is a matching); 16 is the default
+ *   out           [host] receives the solver; free with lowd_solver_free
+ * The solver owns its device memory (schedule, fractions, loads, about
+ * 40 bytes per edge and 40 per node for LOWD_STATE_F64).  Synchronises
+ * `stream`.  LOWD_E_GRAPH names the first offending edge.
+ */
+lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                            const float *w, int32_t state, int32_t star_max, lowd_solver **out,
+                            void *stream);
+
+/*
+ * lowd_reset_loads -- returns the solver to Algorithm 1's initial state
+ * (f_e = w_e / 2 on both ends, loads as after lowd_init_loads) without
+ * rebuilding the schedule.  Asynchronous on `stream`.
+ */
+lowd_status lowd_reset_loads(lowd_solver *s, void *stream);
+
+/*
+ * lowd_iterate -- `sweeps` passes of Algorithm 1's edge loop: for each edge
+ * (u, v), if l_u > l_v move d = min((l_u - l_v)/2, f_e(u)) from u to v,
+ * otherwise move d = min((l_v - l_u)/2, f_e(v)) from v to u.  With
+ * LOWD_STATE_F64 the result is bit-identical to the sequential loop in
+ * schedule order.  Asynchronous: only enqueues work on `stream`.
+ */
+lowd_status lowd_iterate(lowd_solver *s, int32_t sweeps, void *stream);
+
+/*
+ * lowd_check -- convergence statistics of the current state (Section III-B):
+ * D = max_u l_u, the dual objective (an upper bound on the maximum density
+ * by weak duality), the sum of loads (equal to the total weight) and the QP
+ * objective sum_u l_u^2 (Section III-C).  For LOWD_STATE_F32K the loads are
+ * first recomputed in FP64 from the FP32 fractions, so D is the objective of
+ * a feasible dual point.  Any output may be NULL.  Synchronises `stream`.
+ */
+lowd_status lowd_check(lowd_solver *s, double *D, double *sum_loads, double *sum_sq_loads,
+                       void *stream);
+
+/*
+ * lowd_extract_densest -- Algorithm 1, extraction: sort the nodes by load,
+ * ascending (stable on node id), remove them one by one and keep the
+ * remaining set of largest density, the first (largest) one on ties; the
+ * empty set is never a candidate.  Densities use the graph's own weights
+ * (Problem 1): unweighted graphs give an exact rational num_unit / den;
+ * weighted graphs give num_w / den with num_w in FP64.  Loads are FP64 (for
+ * LOWD_STATE_F32K the FP64 recomputation from the fractions).
+ *
+ *   in_set    [device] uint8[n] out: 1 if the node is in the extracted set
+ *   num_unit  [host] out: |E(S*)| for an unweighted graph, else 0; may be NULL
+ *   num_w     [host] out: W(S*) as FP64; may be NULL
+ *   den       [host] out: |S*|; may be NULL
+ *   D         [host] out: max load (as lowd_check); may be NULL
+ *   gap       [host] out: (D - rho) / rho with rho = num / den; may be NULL
+ * Synchronises `stream`.
+ */
+lowd_status lowd_extract_densest(lowd_solver *s, uint8_t *in_set, int64_t *num_unit,
+                                 double *num_w, int64_t *den, double *D, double *gap,
+                                 void *stream);
+
+/*
+ * lowd_read_state -- copies the current fractions and loads out, in the
+ * caller's edge order: x[e] = f_e(src[e]) and load[u] = l_u, both FP64
+ * (LOWD_STATE_F32K: the FP32 fraction widened, and the load as its value
+ * plus compensation).  Either pointer may be NULL.
+ *   x     [device] double[m]
+ *   load  [device] double[n]
+ * Asynchronous on `stream`.
+ */
+lowd_status lowd_read_state(const lowd_solver *s, double *x, double *load, void *stream);
+
+/*
+ * lowd_schedule_export -- the schedule built by lowd_init_loads, per edge in
+ * the caller's edge order: its phase and its star center.
+ *   phase   [host] int32[m] out; may be NULL
+ *   center  [host] int32[m] out; may be NULL
+ *   nphases [host] out; may be NULL
+ */
+lowd_status lowd_schedule_export(const lowd_solver *s, int32_t *phase, int32_t *center,
+                                 int32_t *nphases);
+
+/*
+ * lowd_schedule_build -- the same phase schedule as lowd_init_loads builds,
+ * computed on the host from host arrays, without a GPU (for inspection and
+ * for precomputing schedules).
+ *   src, dst  [host] int32[m], validated as for lowd_init_loads except for
+ *             repeated pairs
+ *   phase     [host] int32[m] out; may be NULL
+ *   center    [host] int32[m] out; may be NULL
+ *   nphases   [host] out; may be NULL
+ */
+lowd_status lowd_schedule_build(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                                int32_t star_max, int32_t *phase, int32_t *center,
+                                int32_t *nphases);
+
+/*
+ * lowd_solver_info -- sizes of the solver, for reports.
+ *   info [host] int64[8] out: n, m, phases, phases run by whole-GPU launches,
+ *        phases run inside one workgroup from LDS, nodes held in LDS by that
+ *        workgroup, edges in those phases, state type.
+ */
+lowd_status lowd_solver_info(const lowd_solver *s, int64_t *info);
+
+/* Releases the solver's host and device memory (never caller memory).
+ * Waits for the solver's pending work first.  NULL is accepted. */
+void lowd_solver_free(lowd_solver *s);
+
+/*
+ * lowd_batch_solve -- many independent unweighted graphs solved together:
+ * Algorithm 1 (init, `sweeps` sweeps in each graph's own schedule,
+ * extraction) on every graph, one workgroup per graph with its loads held in
+ * LDS, in a single persistent launch.  Each graph's result equals its own
+ * single-graph solve with the same star_max.
+ *
+ *   G          number of graphs (>= 1)
+ *   node_ptr   [host] int64[G+1]: graph g owns nodes node_ptr[g]..node_ptr[g+1]-1
+ *   edge_ptr   [host] int64[G+1]: graph g owns edges edge_ptr[g]..edge_ptr[g+1]-1
+ *   src, dst   [device] int32[total edges], node ids local to their graph
+ *   state      LOWD_STATE_F64 or LOWD_STATE_F32K
+ *   star_max   as for lowd_init_loads
+ *   sweeps     sweeps per graph (>= 0)
+ *   in_set     [device] uint8[total nodes] out
+ *   num        [device] int64[G] out: |E(S*)| per graph
+ *   den        [device] int64[G] out: |S*| per graph
+ *   load       [device] double[total nodes] out, or NULL: final loads
+ * Graphs whose nodes do not fit one workgroup's LDS are rejected with
+ * LOWD_E_UNSUPPORTED.  Synchronises `stream`.
+ */
+lowd_status lowd_batch_solve(int32_t G, const int64_t *node_ptr, const int64_t *edge_ptr,
+                             const int32_t *src, const int32_t *dst, int32_t state,
+                             int32_t star_max, int32_t sweeps, uint8_t *in_set, int64_t *num,
+                             int64_t *den, double *load, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LOWD_H */

@@ -1,0 +1,232 @@
+"""Python binding of liblowd.so, the gfx950 implementation of LOWD (Locally
+Optimal Weight Distribution, Algorithm 1) and its pruning pre-process
+(Algorithm 2) from arXiv 2307.15969.
+
+The binding only marshals arguments: PyTorch supplies device memory and the
+current HIP stream; every step runs in the library's HIP kernels.  There is
+no CPU fallback: if the library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblowd.so")
+
+LOWD_OK = 0
+STATE_F64 = 0
+STATE_F32K = 1
+_STATES = {"f64": STATE_F64, "f32k": STATE_F32K}
+
+_lib = None
+
+
+class LowdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"lowd status {status}: {msg}")
+        self.status = status
+
+
+def lib() -> C.CDLL:
+    """The loaded liblowd.so (built by paper_2307_15969_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LowdError(-5, f"{LIB_PATH} is missing: run paper_2307_15969_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        P = C.POINTER
+        L.lowd_version.restype = C.c_char_p
+        L.lowd_last_error.restype = C.c_char_p
+        L.lowd_prune.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp, vp, P(i32), P(i32), P(i64), vp]
+        L.lowd_init_loads.argtypes = [i32, i64, vp, vp, vp, i32, i32, P(vp), vp]
+        L.lowd_iterate.argtypes = [vp, i32, vp]
+        L.lowd_reset_loads.argtypes = [vp, vp]
+        L.lowd_check.argtypes = [vp, P(C.c_double), P(C.c_double), P(C.c_double), vp]
+        L.lowd_extract_densest.argtypes = [vp, vp, P(i64), P(C.c_double), P(i64),
+                                           P(C.c_double), P(C.c_double), vp]
+        L.lowd_read_state.argtypes = [vp, vp, vp, vp]
+        L.lowd_schedule_export.argtypes = [vp, vp, vp, P(i32)]
+        L.lowd_solver_info.argtypes = [vp, vp]
+        L.lowd_schedule_build.argtypes = [i32, i64, vp, vp, i32, vp, vp, P(i32)]
+        L.lowd_solver_free.argtypes = [vp]
+        L.lowd_solver_free.restype = None
+        L.lowd_batch_solve.argtypes = [i32, vp, vp, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp]
+        for f in (L.lowd_prune, L.lowd_init_loads, L.lowd_iterate, L.lowd_check,
+                  L.lowd_extract_densest, L.lowd_read_state, L.lowd_schedule_export,
+                  L.lowd_solver_info, L.lowd_batch_solve, L.lowd_schedule_build, L.lowd_reset_loads):
+            f.restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status < 0:
+        raise LowdError(status, lib().lowd_last_error().decode())
+    return status
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype, name, allow_none=False):
+    torch = _torch()
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(np.ascontiguousarray(t))
+    if t.dtype != dtype:
+        t = t.to(dtype)
+    if not t.is_cuda:
+        t = t.cuda()
+    return t.contiguous()
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def prune(n: int, src, dst, stream=None) -> dict:
+    """Algorithm 2 on an unweighted graph (device arrays) -> dict with the
+    node mask, the renumbering, the compacted edge list of H and its sizes."""
+    torch = _torch()
+    s = _dev(src, torch.int32, "src")
+    d = _dev(dst, torch.int32, "dst")
+    m = s.numel()
+    keep = torch.empty(n, dtype=torch.uint8, device=s.device)
+    relabel = torch.empty(n, dtype=torch.int32, device=s.device)
+    hs = torch.empty(max(m, 1), dtype=torch.int32, device=s.device)
+    hd = torch.empty(max(m, 1), dtype=torch.int32, device=s.device)
+    emap = torch.empty(max(m, 1), dtype=torch.int64, device=s.device)
+    r, nh, mh = C.c_int32(0), C.c_int32(0), C.c_int64(0)
+    _check(lib().lowd_prune(n, m, _ptr(s), _ptr(d), _ptr(keep), _ptr(relabel), _ptr(hs), _ptr(hd),
+                            _ptr(emap), C.byref(r), C.byref(nh), C.byref(mh), _stream(stream)))
+    mh = int(mh.value)
+    return dict(node_keep=keep, relabel=relabel, src=hs[:mh], dst=hd[:mh], edge_map=emap[:mh],
+                rounds=int(r.value), n_h=int(nh.value), m_h=mh)
+
+
+class Solver:
+    """LOWD on one graph: schedule, fractions and loads live on the GPU."""
+
+    def __init__(self, n: int, src, dst, w=None, state: str = "f64", star_max: int = 16,
+                 stream=None):
+        torch = _torch()
+        self.n = int(n)
+        s = _dev(src, torch.int32, "src")
+        d = _dev(dst, torch.int32, "dst")
+        ww = _dev(w, torch.float32, "w", allow_none=True)
+        self.m = s.numel()
+        self.device = s.device
+        self.weighted = ww is not None
+        self.state = state
+        h = C.c_void_p()
+        _check(lib().lowd_init_loads(self.n, self.m, _ptr(s), _ptr(d), _ptr(ww), _STATES[state],
+                                     star_max, C.byref(h), _stream(stream)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().lowd_solver_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reset(self, stream=None):
+        """Back to the equal-split initial state (schedule kept)."""
+        _check(lib().lowd_reset_loads(self._h, _stream(stream)))
+
+    def iterate(self, sweeps: int = 1, stream=None):
+        _check(lib().lowd_iterate(self._h, int(sweeps), _stream(stream)))
+
+    def check(self, stream=None):
+        D, s, s2 = C.c_double(), C.c_double(), C.c_double()
+        _check(lib().lowd_check(self._h, C.byref(D), C.byref(s), C.byref(s2), _stream(stream)))
+        return D.value, s.value, s2.value
+
+    def extract(self, stream=None) -> dict:
+        torch = _torch()
+        in_set = torch.empty(self.n, dtype=torch.uint8, device=self.device)
+        nu, nw, den, D, gap = C.c_int64(), C.c_double(), C.c_int64(), C.c_double(), C.c_double()
+        _check(lib().lowd_extract_densest(self._h, _ptr(in_set), C.byref(nu), C.byref(nw),
+                                          C.byref(den), C.byref(D), C.byref(gap),
+                                          _stream(stream)))
+        return dict(in_set=in_set, num=int(nu.value), num_w=float(nw.value), den=int(den.value),
+                    D=float(D.value), gap=float(gap.value))
+
+    def read_state(self, stream=None):
+        torch = _torch()
+        x = torch.empty(max(self.m, 1), dtype=torch.float64, device=self.device)
+        L = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        _check(lib().lowd_read_state(self._h, _ptr(x), _ptr(L), _stream(stream)))
+        return x[:self.m], L
+
+    def schedule(self):
+        phase = np.zeros(max(self.m, 1), dtype=np.int32)
+        center = np.zeros(max(self.m, 1), dtype=np.int32)
+        P = C.c_int32()
+        _check(lib().lowd_schedule_export(self._h, phase.ctypes.data_as(C.c_void_p),
+                                          center.ctypes.data_as(C.c_void_p), C.byref(P)))
+        return phase[:self.m], center[:self.m], int(P.value)
+
+    def info(self) -> dict:
+        a = np.zeros(8, dtype=np.int64)
+        _check(lib().lowd_solver_info(self._h, a.ctypes.data_as(C.c_void_p)))
+        keys = ["n", "m", "phases", "grid_phases", "lds_phases", "lds_nodes", "lds_edges", "state"]
+        return {k: int(v) for k, v in zip(keys, a)}
+
+
+def solve(n: int, src, dst, w=None, state: str = "f64", star_max: int = 16, tol: float = 1e-6,
+          check_every: int = 10, max_sweeps: int = 10000, stream=None) -> dict:
+    """Sweeps until the density gap (D - rho) / rho is at most `tol` (D is
+    the dual objective, an upper bound on the optimum; rho the density of the
+    extracted set, a lower bound), checking every `check_every` sweeps."""
+    sv = Solver(n, src, dst, w, state, star_max, stream)
+    sweeps = 0
+    ex = sv.extract(stream)
+    while ex["gap"] > tol and sweeps < max_sweeps:
+        k = min(check_every, max_sweeps - sweeps)
+        sv.iterate(k, stream)
+        sweeps += k
+        ex = sv.extract(stream)
+    ex["sweeps"] = sweeps
+    ex["solver"] = sv
+    return ex
+
+
+def schedule_build(n: int, src: np.ndarray, dst: np.ndarray, star_max: int = 16):
+    """The phase schedule computed on the host (no GPU needed):
+    (phase int32[m], center int32[m], nphases)."""
+    src = np.ascontiguousarray(src, dtype=np.int32)
+    dst = np.ascontiguousarray(dst, dtype=np.int32)
+    m = src.size
+    phase = np.zeros(max(m, 1), dtype=np.int32)
+    center = np.zeros(max(m, 1), dtype=np.int32)
+    P = C.c_int32()
+    _check(lib().lowd_schedule_build(n, m, src.ctypes.data_as(C.c_void_p),
+                                     dst.ctypes.data_as(C.c_void_p), star_max,
+                                     phase.ctypes.data_as(C.c_void_p),
+                                     center.ctypes.data_as(C.c_void_p), C.byref(P)))
+    return phase[:m], center[:m], int(P.value)
+
+
+def version() -> str:
+    return lib().lowd_version().decode()

@@ -1,0 +1,40 @@
+// extract.h -- densest-set extraction (k_extract.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lowd_internal.h"
+
+namespace lowd {
+
+struct ExtractArgs {
+    int32_t n = 0;
+    int64_t m = 0;
+    bool weighted = false;
+    const double *L64 = nullptr;      // [n] FP64 loads
+    const int64_t *row_ptr = nullptr; // incidence CSR
+    const uint32_t *inc = nullptr;
+    const int32_t *src = nullptr;     // [m] edge list
+    const int32_t *dst = nullptr;
+    const float *w = nullptr;         // [m] or nullptr
+    uint8_t *in_set = nullptr;        // [n] out
+};
+
+struct ExtractScratch {
+    int64_t cap = -1;
+    DBuf<uint64_t> keys, keys_alt;
+    DBuf<uint32_t> vals, vals_alt;
+    DBuf<int32_t> pos;
+    DBuf<int64_t> hist, rev, W;   // int64 or (reinterpreted) FP64
+    DBuf<int64_t> part, best;     // best[0] = index, best[1] = W at that index
+    DBuf<char> tmp;
+    void ensure(int64_t n);
+};
+
+// Enqueues the extraction; after the stream completes, best.p[0] holds the
+// number of removed nodes i* and best.p[1] holds W(S_{i*}) (int64 for
+// unweighted graphs, FP64 bits otherwise).
+void launch_extract(const ExtractArgs &a, ExtractScratch &sc, hipStream_t s);
+
+}  // namespace lowd

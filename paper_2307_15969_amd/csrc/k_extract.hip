@@ -1,0 +1,196 @@
+// k_extract.hip -- Algorithm 1's extraction on the GPU: a stable ascending
+// sort of the FP64 loads (ties by node id), the weight W(S_i) of every
+// remaining set S_i = V minus the first i sorted nodes, and the first index
+// of maximal density W(S_i) / (n - i).
+//
+// An edge lies inside S_i exactly when both endpoints sit at position >= i,
+// so W(S_i) is the suffix sum of each node's weight towards higher
+// positions.  That per-node weight is summed over the node's incidence row
+// (ascending edge index) without atomics.  Unweighted graphs use int64
+// throughout, so densities compare exactly by cross-multiplication.
+#include "extract.h"
+#include "lowd_internal.h"
+
+namespace lowd {
+namespace {
+
+// order-preserving map of an FP64 value onto uint64 (-0 folded onto +0)
+__device__ inline uint64_t sortable(double v) {
+    v = v + 0.0;
+    uint64_t b = __builtin_bit_cast(uint64_t, v);
+    return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__global__ void k_keys(int32_t n, const double *L, uint64_t *keys, uint32_t *vals) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        keys[u] = sortable(L[u]);
+        vals[u] = (uint32_t)u;
+    }
+}
+
+__global__ void k_positions(int32_t n, const uint32_t *asc, int32_t *pos) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        pos[asc[i]] = (int32_t)i;
+}
+
+// weight from node u towards nodes at higher positions, stored at pos[u]
+template <class T, bool kWeighted>
+__global__ void k_towards_higher(int32_t n, const int64_t *row_ptr, const uint32_t *inc,
+                                 const int32_t *src, const int32_t *dst, const float *w,
+                                 const int32_t *pos, T *hist) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t pu = pos[u];
+        T acc = 0;
+        for (int64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j) {
+            uint32_t ent = inc[j];
+            int64_t e = ent >> 1;
+            int32_t other = (ent & 1) ? src[e] : dst[e];
+            if (pos[other] > pu) acc = acc + (kWeighted ? (T)w[e] : (T)1);
+        }
+        hist[pu] = acc;
+    }
+}
+
+// W(S_i) from the exclusive prefix P of the reversed histogram:
+// W[i] = P[n-1-i] + hist[i]
+template <class T>
+__global__ void k_reverse(int64_t n, const T *in, T *out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[n - 1 - i] = in[i];
+}
+
+template <class T>
+__global__ void k_suffix(int64_t n, const T *prefix_rev, const T *hist, T *W) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        W[i] = prefix_rev[n - 1 - i] + hist[i];
+}
+
+// is candidate i strictly better than j (denser, or as dense and larger)?
+__device__ inline bool better(int64_t i, int64_t j, const int64_t *W, int64_t n) {
+    if (j < 0) return i >= 0;
+    if (i < 0) return false;
+    // W_i / (n-i) vs W_j / (n-j), exact in int64 (W < 2^31, n < 2^31)
+    int64_t a = W[i] * (n - j), b = W[j] * (n - i);
+    return a > b || (a == b && i < j);
+}
+__device__ inline bool better(int64_t i, int64_t j, const double *W, int64_t n) {
+    if (j < 0) return i >= 0;
+    if (i < 0) return false;
+    double a = W[i] / (double)(n - i), b = W[j] / (double)(n - j);
+    return a > b || (a == b && i < j);
+}
+
+constexpr int kArgBlock = 256;
+
+template <class T>
+__device__ inline int64_t block_best(int64_t cand, const T *W, int64_t n, int64_t *lds) {
+    lds[threadIdx.x] = cand;
+    __syncthreads();
+    for (int s = kArgBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            int64_t o = lds[threadIdx.x + s];
+            if (better(o, lds[threadIdx.x], W, n)) lds[threadIdx.x] = o;
+        }
+        __syncthreads();
+    }
+    return lds[0];
+}
+
+template <class T>
+__global__ void __launch_bounds__(kArgBlock) k_best_partial(int64_t n, const T *W, int64_t *part) {
+    __shared__ int64_t lds[kArgBlock];
+    int64_t cand = -1;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (better(i, cand, W, n)) cand = i;
+    int64_t b = block_best(cand, W, n, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = b;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kArgBlock) k_best_final(int64_t n, int32_t nb, const int64_t *part,
+                                                          const T *W, int64_t *best, T *best_w) {
+    __shared__ int64_t lds[kArgBlock];
+    int64_t cand = -1;
+    for (int32_t b = threadIdx.x; b < nb; b += blockDim.x)
+        if (better(part[b], cand, W, n)) cand = part[b];
+    int64_t r = block_best(cand, W, n, lds);
+    if (threadIdx.x == 0) {
+        *best = r;
+        *best_w = W[r];
+    }
+}
+
+__global__ void k_in_set(int32_t n, const int32_t *pos, const int64_t *best, uint8_t *in_set) {
+    const int64_t b = *best;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+         u += (int64_t)gridDim.x * blockDim.x)
+        in_set[u] = pos[u] >= b ? 1 : 0;
+}
+
+template <class T, bool kWeighted>
+void extract_impl(const ExtractArgs &a, ExtractScratch &sc, hipStream_t s) {
+    const int32_t n = a.n;
+    hipLaunchKernelGGL(k_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, n, a.L64, sc.keys.p,
+                       sc.vals.p);
+    bool alt = false;
+    radix_sort_u64(sc.keys.p, sc.vals.p, sc.keys_alt.p, sc.vals_alt.p, n, 64, sc.tmp.p,
+                   sc.tmp.bytes(), &alt, s);
+    const uint32_t *asc = alt ? sc.vals_alt.p : sc.vals.p;
+    hipLaunchKernelGGL(k_positions, dim3(grid_for(n, 256)), dim3(256), 0, s, n, asc, sc.pos.p);
+    T *hist = (T *)sc.hist.p;
+    T *rev = (T *)sc.rev.p;
+    T *W = (T *)sc.W.p;
+    hipLaunchKernelGGL((k_towards_higher<T, kWeighted>), dim3(grid_for(n, 256)), dim3(256), 0, s,
+                       n, a.row_ptr, a.inc, a.src, a.dst, a.w, sc.pos.p, hist);
+    hipLaunchKernelGGL(k_reverse<T>, dim3(grid_for(n, 256)), dim3(256), 0, s, (int64_t)n, hist,
+                       rev);
+    if constexpr (kWeighted)
+        exclusive_scan_f64(rev, rev, n, nullptr, sc.tmp.p, sc.tmp.bytes(), s);
+    else
+        exclusive_scan_i64(rev, rev, n, nullptr, sc.tmp.p, sc.tmp.bytes(), s);
+    hipLaunchKernelGGL(k_suffix<T>, dim3(grid_for(n, 256)), dim3(256), 0, s, (int64_t)n, rev, hist,
+                       W);
+    int32_t nb = (int32_t)grid_for(n, kArgBlock, 1024);
+    hipLaunchKernelGGL(k_best_partial<T>, dim3((unsigned)nb), dim3(kArgBlock), 0, s, (int64_t)n, W,
+                       sc.part.p);
+    hipLaunchKernelGGL(k_best_final<T>, dim3(1), dim3(kArgBlock), 0, s, (int64_t)n, nb, sc.part.p,
+                       W, sc.best.p, (T *)(sc.best.p + 1));
+    hipLaunchKernelGGL(k_in_set, dim3(grid_for(n, 256)), dim3(256), 0, s, n, sc.pos.p, sc.best.p,
+                       a.in_set);
+    LOWD_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void ExtractScratch::ensure(int64_t n) {
+    if (cap >= n) return;
+    int64_t c = n > 0 ? n : 1;
+    keys.alloc((size_t)c);
+    keys_alt.alloc((size_t)c);
+    vals.alloc((size_t)c);
+    vals_alt.alloc((size_t)c);
+    pos.alloc((size_t)c);
+    hist.alloc((size_t)c);
+    rev.alloc((size_t)c);
+    W.alloc((size_t)c);
+    part.alloc(1024);
+    best.alloc(2);
+    size_t t = radix_sort_tmp_bytes(c);
+    size_t t2 = exclusive_scan_tmp_bytes(c);
+    tmp.alloc(t > t2 ? t : t2);
+    cap = c;
+}
+
+void launch_extract(const ExtractArgs &a, ExtractScratch &sc, hipStream_t s) {
+    sc.ensure(a.n);
+    if (a.weighted) extract_impl<double, true>(a, sc, s);
+    else extract_impl<int64_t, false>(a, sc, s);
+}
+
+}  // namespace lowd

@@ -1,0 +1,136 @@
+// k_graph.hip -- input validation and the incidence CSR (node -> incident
+// edge entries in ascending edge index), built with the stable radix sort.
+#include <limits.h>
+
+#include <utility>
+
+#include "lowd_internal.h"
+
+namespace lowd {
+namespace {
+
+__global__ void k_validate(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                           const float *w, unsigned long long *bad) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        int32_t a = src[e], b = dst[e];
+        bool ok = a >= 0 && a < n && b >= 0 && b < n && a != b;
+        if (w) {
+            float x = w[e];
+            ok = ok && (x > 0.0f) && (x <= 3.402823466e38f);   // positive and finite
+        }
+        if (!ok) atomicMin(bad, (unsigned long long)e);
+    }
+}
+
+__global__ void k_incidence_keys(int64_t m, const int32_t *src, const int32_t *dst, uint32_t *keys,
+                                 uint32_t *vals) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < 2 * m;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        int64_t e = j >> 1;
+        keys[j] = (uint32_t)((j & 1) ? dst[e] : src[e]);
+        vals[j] = (uint32_t)j;
+    }
+}
+
+// row_ptr[u] = first position of key u in the sorted keys (lower bound)
+__global__ void k_row_ptr(const uint32_t *sorted, int64_t len, int32_t n, int64_t *row_ptr) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u <= n;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = 0, hi = len;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if ((int64_t)sorted[mid] < u) lo = mid + 1;
+            else hi = mid;
+        }
+        row_ptr[u] = lo;
+    }
+}
+
+}  // namespace
+
+void launch_validate(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const float *w,
+                     int64_t *bad_dev, hipStream_t s) {
+    unsigned long long init = ULLONG_MAX;
+    LOWD_HIP(hipMemcpyAsync(bad_dev, &init, sizeof(init), hipMemcpyHostToDevice, s));
+    if (m > 0)
+        hipLaunchKernelGGL(k_validate, dim3(grid_for(m, 256)), dim3(256), 0, s, n, m, src, dst, w,
+                           (unsigned long long *)bad_dev);
+    LOWD_HIP(hipGetLastError());
+    LOWD_HIP(hipStreamSynchronize(s));   // `init` must outlive the copy
+}
+
+void build_incidence(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, Csr &csr,
+                     hipStream_t s) {
+    int64_t len = 2 * m;
+    csr.row_ptr.alloc((size_t)n + 1);
+    int bits = 1;
+    while (bits < 32 && ((int64_t)1 << bits) < (int64_t)n) ++bits;
+    size_t cap = (size_t)(len > 0 ? len : 1);
+    DBuf<uint32_t> k0(cap), v0(cap), k1(cap), v1(cap);
+    DBuf<char> tmp(radix_sort_tmp_bytes(len));
+    if (len > 0)
+        hipLaunchKernelGGL(k_incidence_keys, dim3(grid_for(len, 256)), dim3(256), 0, s, m, src, dst,
+                           k0.p, v0.p);
+    bool alt = false;
+    radix_sort_u32(k0.p, v0.p, k1.p, v1.p, len, bits, tmp.p, tmp.bytes(), &alt, s);
+    uint32_t *keys = alt ? k1.p : k0.p;
+    hipLaunchKernelGGL(k_row_ptr, dim3(grid_for((int64_t)n + 1, 256)), dim3(256), 0, s, keys, len,
+                       n, csr.row_ptr.p);
+    LOWD_HIP(hipGetLastError());
+    LOWD_HIP(hipStreamSynchronize(s));
+    csr.inc = alt ? std::move(v1) : std::move(v0);
+}
+
+}  // namespace lowd
+
+// --------------------------------------------------- repeated pairs ------
+namespace lowd {
+namespace {
+
+__global__ void k_pair_keys(int64_t m, const int32_t *src, const int32_t *dst, uint64_t *keys,
+                            uint32_t *vals) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t a = (uint32_t)src[e], b = (uint32_t)dst[e];
+        uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+        keys[e] = ((uint64_t)lo << 32) | hi;
+        vals[e] = (uint32_t)e;
+    }
+}
+
+__global__ void k_adjacent_equal(int64_t m, const uint64_t *keys, const uint32_t *vals,
+                                 unsigned long long *bad) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + 1; i < m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (keys[i] == keys[i - 1]) atomicMin(bad, (unsigned long long)vals[i]);
+}
+
+}  // namespace
+
+// Index of the later edge of the first repeated unordered pair found, or -1.
+int64_t find_duplicate_pair(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                            hipStream_t s) {
+    if (m < 2) return -1;
+    int nb = 1;
+    while (nb < 32 && ((int64_t)1 << nb) < (int64_t)n) ++nb;
+    DBuf<uint64_t> k0((size_t)m), k1((size_t)m);
+    DBuf<uint32_t> v0((size_t)m), v1((size_t)m);
+    DBuf<char> tmp(radix_sort_tmp_bytes(m));
+    DBuf<int64_t> bad(1);
+    hipLaunchKernelGGL(k_pair_keys, dim3(grid_for(m, 256)), dim3(256), 0, s, m, src, dst, k0.p,
+                       v0.p);
+    bool alt = false;
+    radix_sort_u64(k0.p, v0.p, k1.p, v1.p, m, 32 + nb, tmp.p, tmp.bytes(), &alt, s);
+    unsigned long long init = ~0ull;
+    LOWD_HIP(hipMemcpyAsync(bad.p, &init, sizeof(init), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_adjacent_equal, dim3(grid_for(m, 256)), dim3(256), 0, s, m,
+                       alt ? k1.p : k0.p, alt ? v1.p : v0.p, (unsigned long long *)bad.p);
+    LOWD_HIP(hipGetLastError());
+    unsigned long long r = 0;
+    LOWD_HIP(hipMemcpyAsync(&r, bad.p, sizeof(r), hipMemcpyDeviceToHost, s));
+    LOWD_HIP(hipStreamSynchronize(s));
+    return r == ~0ull ? -1 : (int64_t)r;
+}
+
+}  // namespace lowd

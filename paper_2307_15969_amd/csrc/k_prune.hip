@@ -1,0 +1,255 @@
+// k_prune.hip -- Algorithm 2 (Pruning) for unweighted graphs.
+//
+// Section III-D prunes in O(M + N) with a counting sort of the nodes by
+// degree: a round removes every node whose degree is below the current
+// density delta = |E(H)| / |V(H)|, and the nodes of the first round are
+// exactly a prefix of the degree-sorted order.  On the GPU:
+//   1. degrees from the incidence rows; an LDS-privatised degree histogram
+//      (4096 bins, the last one collecting larger degrees) and a wave-scan
+//      exclusive prefix give the bucket starts; a scatter sorts the nodes by
+//      degree bucket;
+//   2. round 1 removes the bucket prefix below delta without looking at the
+//      other nodes; the surviving suffix becomes the alive list;
+//   3. every later round tests the alive list (deg * |V(H)| < |E(H)|, exact
+//      in int64), splits it with two prefix sums into the removed list and
+//      the next alive list, and walks the removed nodes' rows to lower their
+//      neighbours' degrees and count the removed edges;
+//   4. the kept nodes are renumbered by a prefix sum (ascending original id)
+//      and the kept edges compacted by another, in their original order.
+// The alive list shrinks quickly (the number of removed nodes decays
+// exponentially, as the paper observes), so the rounds after the first cost
+// little.
+#include <vector>
+
+#include "lowd_internal.h"
+#include "prune.h"
+
+namespace lowd {
+namespace {
+
+constexpr int kBins = 4096;
+
+__global__ void k_degrees(int32_t n, const int64_t *row_ptr, int32_t *deg) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+         u += (int64_t)gridDim.x * blockDim.x)
+        deg[u] = (int32_t)(row_ptr[u + 1] - row_ptr[u]);
+}
+
+__global__ void __launch_bounds__(256) k_degree_hist(int32_t n, const int32_t *deg,
+                                                     unsigned long long *hist) {
+    __shared__ uint32_t h[kBins];
+    for (int b = threadIdx.x; b < kBins; b += blockDim.x) h[b] = 0;
+    __syncthreads();
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        int32_t d = deg[u];
+        atomicAdd(&h[d < kBins - 1 ? d : kBins - 1], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < kBins; b += blockDim.x)
+        if (h[b]) atomicAdd(&hist[b], (unsigned long long)h[b]);
+}
+
+__global__ void k_bucket_scatter(int32_t n, const int32_t *deg, const int64_t *bin_start,
+                                 unsigned long long *cursor, int32_t *by_deg) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        int32_t d = deg[u];
+        int b = d < kBins - 1 ? d : kBins - 1;
+        int64_t at = bin_start[b] + (int64_t)atomicAdd(&cursor[b], 1ull);
+        by_deg[at] = (int32_t)u;
+    }
+}
+
+// flags for the split of a candidate list into removed / kept
+__global__ void k_test(int64_t c, const int32_t *cand, const int32_t *deg, int64_t N, int64_t M,
+                       int64_t *rm, int64_t *keep) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        bool r = (int64_t)deg[cand[i]] * N < M;
+        rm[i] = r ? 1 : 0;
+        keep[i] = r ? 0 : 1;
+    }
+}
+
+__global__ void k_split(int64_t c, const int32_t *cand, const int64_t *rm, const int64_t *rm_pos,
+                        const int64_t *keep_pos, int32_t *removed, int32_t *alive) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (rm[i]) removed[rm_pos[i]] = cand[i];
+        else alive[keep_pos[i]] = cand[i];
+    }
+}
+
+__global__ void k_stamp(int64_t k, const int32_t *list, int32_t *stamp, int32_t round) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
+         i += (int64_t)gridDim.x * blockDim.x)
+        stamp[list[i]] = round;
+}
+
+// for each removed node: lower alive neighbours' degrees; count each removed
+// edge once (an edge between two nodes removed this round by its smaller end)
+__global__ void k_remove_edges(int64_t k, const int32_t *removed, const int64_t *row_ptr,
+                               const uint32_t *inc, const int32_t *src, const int32_t *dst,
+                               const int32_t *stamp, int32_t round, int32_t *deg,
+                               unsigned long long *gone) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t u = removed[i];
+        unsigned long long cnt = 0;
+        for (int64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j) {
+            uint32_t ent = inc[j];
+            int64_t e = ent >> 1;
+            int32_t v = (ent & 1) ? src[e] : dst[e];
+            int32_t sv = stamp[v];
+            if (sv == 0) {
+                atomicSub(&deg[v], 1);
+                ++cnt;
+            } else if (sv == round && u < v) {
+                ++cnt;
+            }
+        }
+        if (cnt) atomicAdd(gone, cnt);
+    }
+}
+
+__global__ void k_keep_flags(int32_t n, const int32_t *stamp, uint8_t *node_keep, int64_t *flag) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        bool k = stamp[u] == 0;
+        node_keep[u] = k ? 1 : 0;
+        flag[u] = k ? 1 : 0;
+    }
+}
+
+__global__ void k_relabel(int32_t n, const int64_t *flag, const int64_t *pos, int32_t *relabel) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+         u += (int64_t)gridDim.x * blockDim.x)
+        relabel[u] = flag[u] ? (int32_t)pos[u] : -1;
+}
+
+__global__ void k_edge_flags(int64_t m, const int32_t *src, const int32_t *dst,
+                             const int32_t *stamp, int64_t *flag) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x)
+        flag[e] = (stamp[src[e]] == 0 && stamp[dst[e]] == 0) ? 1 : 0;
+}
+
+__global__ void k_edge_compact(int64_t m, const int32_t *src, const int32_t *dst,
+                               const int64_t *flag, const int64_t *pos, const int64_t *npos,
+                               int32_t *h_src, int32_t *h_dst, int64_t *edge_map) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        if (!flag[e]) continue;
+        int64_t at = pos[e];
+        if (h_src) {
+            h_src[at] = (int32_t)npos[src[e]];
+            h_dst[at] = (int32_t)npos[dst[e]];
+        }
+        if (edge_map) edge_map[at] = e;
+    }
+}
+
+}  // namespace
+
+PruneResult run_prune(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                      uint8_t *node_keep, int32_t *relabel, int32_t *h_src, int32_t *h_dst,
+                      int64_t *edge_map, hipStream_t s) {
+    PruneResult res;
+    const unsigned gn = grid_for(n, 256);
+    Csr csr;
+    build_incidence(n, m, src, dst, csr, s);
+    DBuf<int32_t> deg((size_t)n), stamp((size_t)n), by_deg((size_t)n), list_a((size_t)n),
+        list_b((size_t)n), removed((size_t)n);
+    DBuf<unsigned long long> hist(kBins), cursor(kBins), gone(1);
+    DBuf<int64_t> bin_start(kBins), f_rm((size_t)n), f_keep((size_t)n), p_rm((size_t)n),
+        p_keep((size_t)n), tot(2);
+    int64_t big = n > m ? (int64_t)n : m;
+    if (big < kBins) big = kBins;
+    DBuf<char> scan_tmp(exclusive_scan_tmp_bytes(big));
+
+    hipLaunchKernelGGL(k_degrees, dim3(gn), dim3(256), 0, s, n, csr.row_ptr.p, deg.p);
+    LOWD_HIP(hipMemsetAsync(hist.p, 0, kBins * sizeof(unsigned long long), s));
+    LOWD_HIP(hipMemsetAsync(cursor.p, 0, kBins * sizeof(unsigned long long), s));
+    LOWD_HIP(hipMemsetAsync(stamp.p, 0, (size_t)n * sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_degree_hist, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, n, deg.p,
+                       hist.p);
+    exclusive_scan_i64((const int64_t *)hist.p, bin_start.p, kBins, nullptr, scan_tmp.p,
+                       scan_tmp.bytes(), s);
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(gn), dim3(256), 0, s, n, deg.p, bin_start.p,
+                       cursor.p, by_deg.p);
+    std::vector<int64_t> hstart(kBins);
+    LOWD_HIP(hipMemcpyAsync(hstart.data(), bin_start.p, kBins * sizeof(int64_t),
+                            hipMemcpyDeviceToHost, s));
+    LOWD_HIP(hipStreamSynchronize(s));
+
+    int64_t N = n, M = m;
+    const int32_t *alive = by_deg.p;   // current alive list (read only)
+    int64_t nalive = n;
+    for (int32_t round = 1;; ++round) {
+        const int32_t *rm_list;
+        int64_t nrm;
+        if (round == 1 && M > 0 && (M + N - 1) / N <= kBins - 1) {
+            // the removed nodes are the buckets of degree < ceil(M / N)
+            int64_t cut = hstart[(size_t)((M + N - 1) / N)];
+            rm_list = by_deg.p;
+            nrm = cut;
+            alive = by_deg.p + cut;
+            nalive = n - cut;
+        } else {
+            if (nalive == 0 || M == 0) break;
+            const unsigned gc = grid_for(nalive, 256);
+            hipLaunchKernelGGL(k_test, dim3(gc), dim3(256), 0, s, nalive, alive, deg.p, N, M,
+                               f_rm.p, f_keep.p);
+            exclusive_scan_i64(f_rm.p, p_rm.p, nalive, tot.p, scan_tmp.p, scan_tmp.bytes(), s);
+            exclusive_scan_i64(f_keep.p, p_keep.p, nalive, tot.p + 1, scan_tmp.p, scan_tmp.bytes(),
+                               s);
+            int32_t *out = (alive == list_a.p) ? list_b.p : list_a.p;
+            hipLaunchKernelGGL(k_split, dim3(gc), dim3(256), 0, s, nalive, alive, f_rm.p, p_rm.p,
+                               p_keep.p, removed.p, out);
+            int64_t t[2];
+            LOWD_HIP(hipMemcpyAsync(t, tot.p, sizeof(t), hipMemcpyDeviceToHost, s));
+            LOWD_HIP(hipStreamSynchronize(s));
+            rm_list = removed.p;
+            nrm = t[0];
+            alive = out;
+            nalive = t[1];
+        }
+        if (nrm == 0) break;
+        LOWD_HIP(hipMemsetAsync(gone.p, 0, sizeof(unsigned long long), s));
+        const unsigned gr = grid_for(nrm, 256);
+        hipLaunchKernelGGL(k_stamp, dim3(gr), dim3(256), 0, s, nrm, rm_list, stamp.p, round);
+        hipLaunchKernelGGL(k_remove_edges, dim3(gr), dim3(256), 0, s, nrm, rm_list, csr.row_ptr.p,
+                           csr.inc.p, src, dst, stamp.p, round, deg.p, gone.p);
+        LOWD_HIP(hipGetLastError());
+        unsigned long long g = 0;
+        LOWD_HIP(hipMemcpyAsync(&g, gone.p, sizeof(g), hipMemcpyDeviceToHost, s));
+        LOWD_HIP(hipStreamSynchronize(s));
+        N -= nrm;
+        M -= (int64_t)g;
+        res.rounds = round;
+    }
+
+    // outputs: mask, renumbering, compacted edge list
+    hipLaunchKernelGGL(k_keep_flags, dim3(gn), dim3(256), 0, s, n, stamp.p, node_keep, f_keep.p);
+    exclusive_scan_i64(f_keep.p, p_keep.p, n, nullptr, scan_tmp.p, scan_tmp.bytes(), s);
+    if (relabel)
+        hipLaunchKernelGGL(k_relabel, dim3(gn), dim3(256), 0, s, n, f_keep.p, p_keep.p, relabel);
+    if ((h_src || edge_map) && m > 0) {
+        DBuf<int64_t> ef((size_t)m), ep((size_t)m);
+        hipLaunchKernelGGL(k_edge_flags, dim3(grid_for(m, 256)), dim3(256), 0, s, m, src, dst,
+                           stamp.p, ef.p);
+        exclusive_scan_i64(ef.p, ep.p, m, nullptr, scan_tmp.p, scan_tmp.bytes(), s);
+        hipLaunchKernelGGL(k_edge_compact, dim3(grid_for(m, 256)), dim3(256), 0, s, m, src, dst,
+                           ef.p, ep.p, p_keep.p, h_src, h_dst, edge_map);
+        LOWD_HIP(hipGetLastError());
+        LOWD_HIP(hipStreamSynchronize(s));
+    }
+    LOWD_HIP(hipGetLastError());
+    LOWD_HIP(hipStreamSynchronize(s));
+    res.n_h = (int32_t)N;
+    res.m_h = M;
+    return res;
+}
+
+}  // namespace lowd

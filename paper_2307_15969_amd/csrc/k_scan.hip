@@ -1,0 +1,280 @@
+// k_scan.hip -- device-wide exclusive scan (int64) and stable LSD radix sort
+// of (key, value) pairs, written for 64-lane wavefronts.
+//
+// Scan: reduce-then-scan in three launches; inside a block every wavefront
+// scans its 64 lanes with shuffles and the wave totals are scanned in LDS.
+// Radix sort: 8-bit digits; per block an LDS digit histogram, one global
+// exclusive scan of the digit-major block histograms, then a stable scatter
+// in which every wavefront ranks its keys among equal digits with eight
+// ballots (the lanes whose digit matches in all eight bits).
+#include <utility>
+
+#include "lowd_internal.h"
+
+namespace lowd {
+namespace {
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+template <class T>
+__device__ inline T shfl_up_64(T v, int d) {
+    uint64_t u = __builtin_bit_cast(uint64_t, v);
+    int lo = (int)(uint32_t)u;
+    int hi = (int)(uint32_t)(u >> 32);
+    lo = __shfl_up(lo, d, kWave);
+    hi = __shfl_up(hi, d, kWave);
+    return __builtin_bit_cast(T, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// inclusive scan over the 64 lanes of a wavefront
+template <class T>
+__device__ inline T wave_inclusive_scan(T v) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        T y = shfl_up_64(v, d);
+        if (lane >= d) v = v + y;
+    }
+    return v;
+}
+
+// exclusive scan over the block; returns the block total in *total
+template <class T>
+__device__ inline T block_exclusive_scan(T v, T *lds_waves, T *total) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int nwaves = blockDim.x / kWave;
+    T inc = wave_inclusive_scan(v);
+    if (lane == kWave - 1) lds_waves[wave] = inc;
+    __syncthreads();
+    if (wave == 0) {
+        T t = lane < nwaves ? lds_waves[lane] : (T)0;
+        T ti = wave_inclusive_scan(t);
+        if (lane < nwaves) lds_waves[lane] = ti - t;   // exclusive wave offsets
+        if (lane == nwaves - 1) lds_waves[kWave] = ti;  // block total
+    }
+    __syncthreads();
+    T r = (inc - v) + lds_waves[wave];
+    *total = lds_waves[kWave];
+    __syncthreads();
+    return r;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kScanBlock) k_scan_reduce(const T *in, int64_t n, T *partial) {
+    __shared__ T lds[kWave + 1];
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    T s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + (int64_t)k * kScanBlock + threadIdx.x;
+        if (i < n) s = s + in[i];
+    }
+    T tot;
+    block_exclusive_scan(s, lds, &tot);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// single block: exclusive scan of `partial` in place, total to *total
+template <class T>
+__global__ void __launch_bounds__(kScanBlock) k_scan_partials(T *partial, int64_t nb, T *total) {
+    __shared__ T lds[kWave + 1];
+    T carry = 0;
+    for (int64_t base = 0; base < nb; base += kScanBlock) {
+        int64_t i = base + threadIdx.x;
+        T v = i < nb ? partial[i] : (T)0;
+        T tot;
+        T ex = block_exclusive_scan(v, lds, &tot);
+        if (i < nb) partial[i] = ex + carry;
+        carry = carry + tot;
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kScanBlock) k_scan_apply(const T *in, T *out, int64_t n,
+                                                           const T *partial) {
+    __shared__ T lds[kWave + 1];
+    // each thread owns kScanItems consecutive items of the tile
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    T v[kScanItems];
+    T s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k;
+        v[k] = i < n ? in[i] : (T)0;
+        s = s + v[k];
+    }
+    T tot;
+    T ex = block_exclusive_scan(s, lds, &tot) + partial[blockIdx.x];
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k;
+        if (i < n) out[i] = ex;
+        ex = ex + v[k];
+    }
+}
+
+
+// ------------------------------------------------------------ radix sort --
+constexpr int kRadixBlock = 256;
+constexpr int kRadixTiles = 64;                       // tiles of 256 keys per block
+constexpr int64_t kRadixChunk = (int64_t)kRadixBlock * kRadixTiles;
+constexpr int kDigits = 256;
+
+template <class K>
+__global__ void __launch_bounds__(kRadixBlock) k_radix_hist(const K *keys, int64_t n, int shift,
+                                                            int64_t *blockhist, int64_t nb) {
+    __shared__ uint32_t h[kDigits];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * kRadixChunk;
+    int64_t end = base + kRadixChunk < n ? base + kRadixChunk : n;
+    for (int64_t i = base + threadIdx.x; i < end; i += kRadixBlock) {
+        uint32_t d = (uint32_t)(keys[i] >> shift) & (kDigits - 1);
+        atomicAdd(&h[d], 1u);
+    }
+    __syncthreads();
+    blockhist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+template <class K>
+__global__ void __launch_bounds__(kRadixBlock) k_radix_scatter(const K *keys, const uint32_t *vals,
+                                                               K *keys_out, uint32_t *vals_out,
+                                                               int64_t n, int shift,
+                                                               const int64_t *offsets,
+                                                               int64_t nb) {
+    constexpr int kWaves = kRadixBlock / kWave;
+    __shared__ int64_t running[kDigits];
+    __shared__ int32_t wave_cnt[kWaves][kDigits];
+    __shared__ int64_t wave_off[kWaves][kDigits];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    running[threadIdx.x] = offsets[(int64_t)threadIdx.x * nb + blockIdx.x];
+    int64_t base = (int64_t)blockIdx.x * kRadixChunk;
+    for (int t = 0; t < kRadixTiles; ++t) {
+        int64_t tile0 = base + (int64_t)t * kRadixBlock;
+        if (tile0 >= n) break;                       // uniform across the block
+        int64_t i = tile0 + threadIdx.x;
+        bool valid = i < n;
+        K key = valid ? keys[i] : (K)0;
+        uint32_t val = valid ? vals[i] : 0u;
+        uint32_t d = (uint32_t)(key >> shift) & (kDigits - 1);
+        for (int k = 0; k < kWaves; ++k) wave_cnt[k][threadIdx.x] = 0;
+        // lanes of this wave holding the same digit
+        uint64_t same = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            bool bit = (d >> b) & 1u;
+            uint64_t ones = __ballot(valid && bit);
+            same &= bit ? ones : ~ones;
+        }
+        int rank = __popcll(same & lt_mask);
+        __syncthreads();
+        if (valid && rank == 0) wave_cnt[wave][d] = __popcll(same);
+        __syncthreads();
+        {   // one thread per digit: offsets of each wave's group, in wave order
+            int dd = threadIdx.x;
+            int64_t r = running[dd];
+            for (int k = 0; k < kWaves; ++k) {
+                wave_off[k][dd] = r;
+                r += wave_cnt[k][dd];
+            }
+            running[dd] = r;
+        }
+        __syncthreads();
+        if (valid) {
+            int64_t dst = wave_off[wave][d] + rank;
+            keys_out[dst] = key;
+            vals_out[dst] = val;
+        }
+        __syncthreads();
+    }
+}
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+template <class K>
+void radix_sort_impl(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, int64_t n, int bits,
+                     void *tmp, size_t tmp_bytes, bool *result_in_alt, hipStream_t s) {
+    *result_in_alt = false;
+    if (n <= 1 || bits <= 0) return;
+    int64_t nb = cdiv(n, kRadixChunk);
+    int64_t nh = nb * kDigits;
+    if (tmp_bytes < radix_sort_tmp_bytes(n)) fail(-1, "radix sort scratch too small");
+    int64_t *hist = (int64_t *)tmp;
+    int64_t *scan_tmp = hist + nh;
+    size_t scan_bytes = tmp_bytes - (size_t)nh * sizeof(int64_t);
+    K *kin = keys, *kout = keys_alt;
+    uint32_t *vin = vals, *vout = vals_alt;
+    bool in_alt = false;
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)nb), dim3(kRadixBlock), 0, s, kin, n,
+                           shift, hist, nb);
+        exclusive_scan_i64(hist, hist, nh, nullptr, scan_tmp, scan_bytes, s);
+        hipLaunchKernelGGL(k_radix_scatter<K>, dim3((unsigned)nb), dim3(kRadixBlock), 0, s, kin,
+                           vin, kout, vout, n, shift, hist, nb);
+        LOWD_HIP(hipGetLastError());
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+        in_alt = !in_alt;
+    }
+    *result_in_alt = in_alt;
+}
+
+}  // namespace
+
+size_t exclusive_scan_tmp_bytes(int64_t n) {
+    int64_t nb = cdiv(n > 0 ? n : 1, kScanTile);
+    return (size_t)(nb + 1) * sizeof(int64_t);
+}
+
+namespace {
+template <class T>
+void exclusive_scan_impl(const T *in, T *out, int64_t n, T *total_dev, void *tmp,
+                         size_t tmp_bytes, hipStream_t s) {
+    if (n <= 0) return;
+    int64_t nb = cdiv(n, kScanTile);
+    if (tmp_bytes < exclusive_scan_tmp_bytes(n)) fail(-1, "scan scratch too small");
+    T *partial = (T *)tmp;
+    hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, n,
+                       partial);
+    hipLaunchKernelGGL(k_scan_partials<T>, dim3(1), dim3(kScanBlock), 0, s, partial, nb,
+                       total_dev);
+    hipLaunchKernelGGL(k_scan_apply<T>, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, out, n,
+                       partial);
+    LOWD_HIP(hipGetLastError());
+}
+}  // namespace
+
+void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total_dev, void *tmp,
+                        size_t tmp_bytes, hipStream_t s) {
+    exclusive_scan_impl<int64_t>(in, out, n, total_dev, tmp, tmp_bytes, s);
+}
+
+void exclusive_scan_f64(const double *in, double *out, int64_t n, double *total_dev, void *tmp,
+                        size_t tmp_bytes, hipStream_t s) {
+    exclusive_scan_impl<double>(in, out, n, total_dev, tmp, tmp_bytes, s);
+}
+
+size_t radix_sort_tmp_bytes(int64_t n) {
+    int64_t nb = cdiv(n > 0 ? n : 1, kRadixChunk);
+    int64_t nh = nb * kDigits;
+    return (size_t)nh * sizeof(int64_t) + exclusive_scan_tmp_bytes(nh);
+}
+
+void radix_sort_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
+                    int64_t n, int bits, void *tmp, size_t tmp_bytes, bool *result_in_alt,
+                    hipStream_t s) {
+    radix_sort_impl<uint32_t>(keys, vals, keys_alt, vals_alt, n, bits, tmp, tmp_bytes,
+                              result_in_alt, s);
+}
+
+void radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt,
+                    int64_t n, int bits, void *tmp, size_t tmp_bytes, bool *result_in_alt,
+                    hipStream_t s) {
+    radix_sort_impl<uint64_t>(keys, vals, keys_alt, vals_alt, n, bits, tmp, tmp_bytes,
+                              result_in_alt, s);
+}
+
+}  // namespace lowd

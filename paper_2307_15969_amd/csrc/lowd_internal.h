@@ -1,0 +1,121 @@
+// lowd_internal.h -- shared declarations between the host orchestration
+// (api.hip, schedule.cpp) and the device kernels (k_*.hip).  Not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace lowd {
+
+// ---------------------------------------------------------------- errors --
+struct Error {
+    int32_t status;
+    std::string msg;
+};
+[[noreturn]] void fail(int32_t status, const std::string &msg);
+void hip_check(hipError_t e, const char *what);
+#define LOWD_HIP(call) ::lowd::hip_check((call), #call)
+
+// Owning device buffer (hipMalloc / hipFree).
+template <class T>
+struct DBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    explicit DBuf(size_t count) { alloc(count); }
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf &operator=(DBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DBuf() { release(); }
+    void alloc(size_t count) {
+        release();
+        if (count == 0) count = 1;
+        LOWD_HIP(hipMalloc((void **)&p, count * sizeof(T)));
+        n = count;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
+// Slot encoding of a star leaf: bits 0..30 node id (global or LDS-local),
+// bit 31 set when the star's center is the edge's dst (so the leaf is src).
+constexpr uint32_t kLeafPad = 0xFFFFFFFFu;   // padding slot (no edge)
+constexpr uint32_t kCenterIsDst = 0x80000000u;
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------- schedule --
+// Host-side result of the phase schedule and its device layout.
+struct Schedule {
+    int32_t n = 0;
+    int64_t m = 0;
+    int32_t smax = 16;
+    int32_t P = 0;                  // phases
+    std::vector<int32_t> phase;     // per edge
+    std::vector<int32_t> center;    // per edge (node id)
+    // tile layout (phases in order; stars sorted by size desc, 64 per tile)
+    int32_t P0 = 0;                 // phases [0, P0) run as whole-GPU launches
+    std::vector<int32_t> phase_tile_ptr;   // [P+1] tile range per phase
+    std::vector<int32_t> tile_center;      // [ntiles*64] node id (local ids for tail tiles), -1 empty
+    std::vector<int64_t> tile_base;        // [ntiles] first slot of the tile
+    std::vector<int32_t> tile_depth;       // [ntiles] rows of the tile
+    std::vector<uint32_t> slot_leaf;       // [nslots] leaf | orientation, kLeafPad for padding
+    std::vector<int64_t> slot_edge;        // [nslots] edge index, -1 for padding
+    std::vector<int64_t> edge_slot;        // [m] slot of each edge
+    std::vector<int32_t> tail_nodes;       // global ids of the nodes held in LDS by the tail
+    int64_t tail_edges = 0;
+};
+
+// Builds the phase schedule (first fit over edges in ascending index) and
+// the tile layout; `lds_nodes` bounds the tail's node set (0 = no tail).
+void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, int32_t smax,
+                    int64_t lds_nodes, int64_t force_p0, Schedule &out);
+
+// --------------------------------------------------------------- kernels --
+// Device-wide primitives (k_scan.hip)
+void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total_dev,
+                        void *tmp, size_t tmp_bytes, hipStream_t s);
+void exclusive_scan_f64(const double *in, double *out, int64_t n, double *total_dev, void *tmp,
+                        size_t tmp_bytes, hipStream_t s);
+size_t exclusive_scan_tmp_bytes(int64_t n);
+// Stable LSD radix sort of (key, value) pairs on bits [0, bits) of the key.
+void radix_sort_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
+                    int64_t n, int bits, void *tmp, size_t tmp_bytes, bool *result_in_alt,
+                    hipStream_t s);
+void radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt,
+                    int64_t n, int bits, void *tmp, size_t tmp_bytes, bool *result_in_alt,
+                    hipStream_t s);
+size_t radix_sort_tmp_bytes(int64_t n);
+
+// Graph validation (k_graph.hip): first bad edge index or -1 in *bad_dev.
+void launch_validate(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                     const float *w, int64_t *bad_dev, hipStream_t s);
+// Index of the later edge of the first repeated unordered pair, or -1.
+int64_t find_duplicate_pair(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                            hipStream_t s);
+// Incidence CSR, rows in ascending edge index: entry j = 2*e + side
+// (side 0: the row node is src[e]; side 1: dst[e]).  row_ptr has n+1 entries.
+struct Csr {
+    DBuf<int64_t> row_ptr;   // [n+1]
+    DBuf<uint32_t> inc;      // [2m]
+};
+void build_incidence(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, Csr &csr,
+                     hipStream_t s);
+inline unsigned grid_for(int64_t work, int block, int64_t cap = 65536) {
+    int64_t g = (work + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+}  // namespace lowd

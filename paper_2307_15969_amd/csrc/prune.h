@@ -1,0 +1,20 @@
+// prune.h -- Algorithm 2 (Pruning) on the GPU (k_prune.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lowd {
+
+struct PruneResult {
+    int32_t rounds = 0;
+    int32_t n_h = 0;
+    int64_t m_h = 0;
+};
+
+// Inputs validated by the caller.  Outputs as documented for lowd_prune.
+PruneResult run_prune(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                      uint8_t *node_keep, int32_t *relabel, int32_t *h_src, int32_t *h_dst,
+                      int64_t *edge_map, hipStream_t s);
+
+}  // namespace lowd

@@ -1,0 +1,240 @@
+// schedule.cpp -- the edge schedule of the sweep, computed once on the host.
+//
+// Algorithm 1 visits the edges in an order it does not fix.  The sweep here
+// uses a phase schedule: every phase is a set of vertex-disjoint stars (a
+// star = one center node and up to smax leaves, one edge per leaf), so all
+// stars of a phase can run at the same time, each as one sequential chain on
+// one lane, and the result is exactly that of visiting the phase's edges one
+// after another.  A proper edge colouring is the special case smax = 1.
+//
+// Definition (first fit):
+//   center of edge e = its endpoint of larger degree (ties: smaller id);
+//   edges are visited in ascending index; e goes to the first phase in which
+//   its center is not a leaf and has fewer than smax leaves, and its leaf
+//   does not appear at all.
+// Sequential order: ascending (phase, edge index).
+//
+// Device layout: within a phase the stars are sorted by size (descending,
+// then center id) and dealt to tiles of 64, one star per lane.  Tile t owns
+// depth_t * 64 consecutive slots; slot (k, lane) holds the k-th leaf of the
+// lane's star, so row k of a tile is one coalesced 64-wide access.
+//
+// The last phases of a power-law graph are small and touch few nodes (the
+// dense core); the schedule picks a split phase P0 such that the nodes of
+// phases [P0, P) fit in one workgroup's LDS, and those phases run inside a
+// single workgroup separated by LDS barriers instead of kernel boundaries.
+#include <stdint.h>
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "lowd_internal.h"
+
+namespace lowd {
+
+namespace {
+
+struct Bits {
+    std::vector<uint64_t> w;
+    inline uint64_t word(size_t i) const { return i < w.size() ? w[i] : 0ull; }
+    inline void set(int32_t p) {
+        size_t i = (size_t)p >> 6;
+        if (i >= w.size()) w.resize(i + 1 + (i >> 1), 0ull);
+        w[i] |= 1ull << (p & 63);
+    }
+};
+
+// Per-phase cost model (microseconds) used to place the split P0.  A phase
+// run by a whole-GPU launch costs one kernel boundary inside a HIP graph plus
+// its streamed bytes; a phase inside the LDS-resident workgroup costs a
+// barrier plus its longest star chain plus one CU's streaming time.
+struct CostModel {
+    double grid_fixed_us = 1.7;
+    double grid_us_per_edge = 48.0 / 4.0e6;      // ~48 B per edge at ~4 TB/s
+    double tail_fixed_us = 0.25;
+    double tail_us_per_depth = 0.035;            // one dependent LDS step
+    double tail_us_per_edge = 24.0 / 1.2e5;      // ~24 B per edge at ~120 GB/s
+};
+
+}  // namespace
+
+void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, int32_t smax,
+                    int64_t lds_nodes, int64_t force_p0, Schedule &out) {
+    out = Schedule();
+    out.n = n;
+    out.m = m;
+    out.smax = smax;
+    out.phase.assign((size_t)m, 0);
+    out.center.assign((size_t)m, 0);
+
+    std::vector<int64_t> deg((size_t)n, 0);
+    for (int64_t e = 0; e < m; ++e) {
+        ++deg[(size_t)src[e]];
+        ++deg[(size_t)dst[e]];
+    }
+
+    // ---- first fit --------------------------------------------------------
+    // used[u]: phases where u has any role; noc[u]: phases where u cannot be
+    // a center (it is a leaf there, or its star is full).
+    std::vector<Bits> used((size_t)n), noc((size_t)n);
+    std::vector<std::vector<uint8_t>> cnt((size_t)n);
+    int32_t P = 0;
+    for (int64_t e = 0; e < m; ++e) {
+        int32_t a = src[e], b = dst[e];
+        int32_t c, l;
+        if (deg[(size_t)a] > deg[(size_t)b] || (deg[(size_t)a] == deg[(size_t)b] && a < b)) {
+            c = a;
+            l = b;
+        } else {
+            c = b;
+            l = a;
+        }
+        const Bits &bc = noc[(size_t)c];
+        const Bits &bl = used[(size_t)l];
+        int32_t p = 0;
+        for (size_t wi = 0;; ++wi) {
+            uint64_t busy = bc.word(wi) | bl.word(wi);
+            if (~busy) {
+                p = (int32_t)(wi * 64 + (size_t)__builtin_ctzll(~busy));
+                break;
+            }
+        }
+        used[(size_t)c].set(p);
+        used[(size_t)l].set(p);
+        noc[(size_t)l].set(p);
+        std::vector<uint8_t> &cc = cnt[(size_t)c];
+        if ((size_t)p >= cc.size()) cc.resize((size_t)p + 1 + ((size_t)p >> 1), 0);
+        if (++cc[(size_t)p] >= smax) noc[(size_t)c].set(p);
+        out.phase[(size_t)e] = p;
+        out.center[(size_t)e] = c;
+        if (p + 1 > P) P = p + 1;
+    }
+    out.P = P;
+    { std::vector<Bits>().swap(used); std::vector<Bits>().swap(noc); }
+    std::vector<std::vector<uint8_t>>().swap(cnt);
+
+    // ---- edges by (phase, center, index) -----------------------------------
+    std::vector<int64_t> pstart((size_t)P + 1, 0);
+    for (int64_t e = 0; e < m; ++e) ++pstart[(size_t)out.phase[(size_t)e] + 1];
+    for (int32_t p = 0; p < P; ++p) pstart[(size_t)p + 1] += pstart[(size_t)p];
+    std::vector<int64_t> byphase((size_t)m);
+    {
+        std::vector<int64_t> cur(pstart.begin(), pstart.end() - 1);
+        for (int64_t e = 0; e < m; ++e) byphase[(size_t)cur[(size_t)out.phase[(size_t)e]]++] = e;
+    }
+    std::vector<int64_t> ecount((size_t)P, 0), maxstar((size_t)P, 0);
+    // stars per phase: (begin, len) into byphase after sorting by center
+    struct Star { int64_t begin; int32_t len; int32_t center; };
+    std::vector<std::vector<Star>> stars((size_t)P);
+    for (int32_t p = 0; p < P; ++p) {
+        auto b = byphase.begin() + pstart[(size_t)p], en = byphase.begin() + pstart[(size_t)p + 1];
+        std::stable_sort(b, en, [&](int64_t x, int64_t y) {
+            return out.center[(size_t)x] < out.center[(size_t)y];
+        });
+        ecount[(size_t)p] = pstart[(size_t)p + 1] - pstart[(size_t)p];
+        std::vector<Star> &st = stars[(size_t)p];
+        for (int64_t i = pstart[(size_t)p]; i < pstart[(size_t)p + 1];) {
+            int32_t c = out.center[(size_t)byphase[(size_t)i]];
+            int64_t j = i;
+            while (j < pstart[(size_t)p + 1] && out.center[(size_t)byphase[(size_t)j]] == c) ++j;
+            st.push_back(Star{i, (int32_t)(j - i), c});
+            maxstar[(size_t)p] = std::max<int64_t>(maxstar[(size_t)p], j - i);
+            i = j;
+        }
+        std::sort(st.begin(), st.end(), [](const Star &x, const Star &y) {
+            return x.len != y.len ? x.len > y.len : x.center < y.center;
+        });
+    }
+
+    // ---- split P0 ---------------------------------------------------------
+    std::vector<int32_t> last((size_t)n, -1);
+    for (int64_t e = 0; e < m; ++e) {
+        int32_t p = out.phase[(size_t)e];
+        last[(size_t)src[e]] = std::max(last[(size_t)src[e]], p);
+        last[(size_t)dst[e]] = std::max(last[(size_t)dst[e]], p);
+    }
+    std::vector<int64_t> nodes_from((size_t)P + 2, 0);   // nodes with last >= p
+    for (int32_t u = 0; u < n; ++u)
+        if (last[(size_t)u] >= 0) ++nodes_from[(size_t)last[(size_t)u]];
+    for (int32_t p = P - 1; p >= 0; --p) nodes_from[(size_t)p] += nodes_from[(size_t)p + 1];
+    CostModel cm;
+    int32_t P0 = P;
+    if (force_p0 >= 0) {
+        P0 = (int32_t)std::min<int64_t>(force_p0, P);
+        while (P0 < P && nodes_from[(size_t)P0] > lds_nodes) ++P0;
+    } else if (lds_nodes > 0 && P > 0) {
+        // cost(P0) = sum_{p<P0} grid(p) + sum_{p>=P0} tail(p)
+        std::vector<double> gpre((size_t)P + 1, 0.0), tsuf((size_t)P + 1, 0.0);
+        for (int32_t p = 0; p < P; ++p)
+            gpre[(size_t)p + 1] = gpre[(size_t)p] + cm.grid_fixed_us +
+                                  cm.grid_us_per_edge * (double)ecount[(size_t)p];
+        for (int32_t p = P - 1; p >= 0; --p)
+            tsuf[(size_t)p] = tsuf[(size_t)p + 1] + cm.tail_fixed_us +
+                              cm.tail_us_per_depth * (double)maxstar[(size_t)p] +
+                              cm.tail_us_per_edge * (double)ecount[(size_t)p];
+        double best = gpre[(size_t)P];
+        for (int32_t p0 = P - 1; p0 >= 0; --p0) {
+            if (nodes_from[(size_t)p0] > lds_nodes) break;   // monotone in p0
+            double c = gpre[(size_t)p0] + tsuf[(size_t)p0];
+            if (c < best) { best = c; P0 = p0; }
+        }
+    }
+    out.P0 = P0;
+
+    // tail node ids (ascending) -> local index
+    std::vector<int32_t> local((size_t)n, -1);
+    if (P0 < P) {
+        for (int32_t u = 0; u < n; ++u)
+            if (last[(size_t)u] >= P0) {
+                local[(size_t)u] = (int32_t)out.tail_nodes.size();
+                out.tail_nodes.push_back(u);
+            }
+    }
+
+    // ---- tiles and slots ----------------------------------------------------
+    out.phase_tile_ptr.assign((size_t)P + 1, 0);
+    int64_t ntiles = 0, nslots = 0;
+    for (int32_t p = 0; p < P; ++p) {
+        const std::vector<Star> &st = stars[(size_t)p];
+        int64_t t = ((int64_t)st.size() + kWave - 1) / kWave;
+        for (int64_t k = 0; k < t; ++k) nslots += (int64_t)st[(size_t)(k * kWave)].len * kWave;
+        ntiles += t;
+        out.phase_tile_ptr[(size_t)p + 1] = (int32_t)ntiles;
+    }
+    out.tile_center.assign((size_t)ntiles * kWave, -1);
+    out.tile_base.assign((size_t)ntiles, 0);
+    out.tile_depth.assign((size_t)ntiles, 0);
+    out.slot_leaf.assign((size_t)nslots, kLeafPad);
+    out.slot_edge.assign((size_t)nslots, -1);
+    out.edge_slot.assign((size_t)m, -1);
+    int64_t slot = 0, tile = 0;
+    for (int32_t p = 0; p < P; ++p) {
+        const bool tail = p >= P0;
+        if (tail) out.tail_edges += ecount[(size_t)p];
+        const std::vector<Star> &st = stars[(size_t)p];
+        for (size_t s0 = 0; s0 < st.size(); s0 += kWave, ++tile) {
+            int32_t depth = st[s0].len;
+            out.tile_base[(size_t)tile] = slot;
+            out.tile_depth[(size_t)tile] = depth;
+            for (int lane = 0; lane < kWave && s0 + (size_t)lane < st.size(); ++lane) {
+                const Star &sr = st[s0 + (size_t)lane];
+                out.tile_center[(size_t)tile * kWave + (size_t)lane] =
+                    tail ? local[(size_t)sr.center] : sr.center;
+                for (int32_t k = 0; k < sr.len; ++k) {
+                    int64_t e = byphase[(size_t)(sr.begin + k)];
+                    bool c_is_dst = dst[e] == sr.center;
+                    int32_t leaf = c_is_dst ? src[e] : dst[e];
+                    int32_t id = tail ? local[(size_t)leaf] : leaf;
+                    int64_t sl = slot + (int64_t)k * kWave + lane;
+                    out.slot_leaf[(size_t)sl] = (uint32_t)id | (c_is_dst ? kCenterIsDst : 0u);
+                    out.slot_edge[(size_t)sl] = e;
+                    out.edge_slot[(size_t)e] = sl;
+                }
+            }
+            slot += (int64_t)depth * kWave;
+        }
+    }
+}
+
+}  // namespace lowd
