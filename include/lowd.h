@@ -99,7 +99,7 @@ lowd_status lowd_prune(int32_t n, int64_t m, const int32_t *src, const int32_t *
  *   w             [device] float32[m] or NULL (unit weights); read during
  *                 this call only
  *   state         LOWD_STATE_F64 or LOWD_STATE_F32K
- *   star_max      leaves per star per phase, 1..254 (1 gives a proper edge
+ *   star_max      leaves per star per phase, 1..16 (1 gives a proper edge
  *                 colouring: every phase is a matching); 16 is the default
  *   out           [host] receives the solver; free with lowd_solver_free
  * The solver owns its device memory (schedule, fractions, loads, about
@@ -180,9 +180,9 @@ lowd_status lowd_schedule_export(const lowd_solver *s, int32_t *phase, int32_t *
                                  int32_t *nphases);
 
 /*
- * lowd_schedule_build -- the same phase schedule as lowd_init_loads builds,
+ * lowd_schedule_build -- the same phase assignment as lowd_init_loads builds,
  * computed on the host from host arrays, without a GPU (for inspection and
- * for precomputing schedules).
+ * for precomputing schedules); star_max may here be 1..254.
  *   src, dst  [host] int32[m], validated as for lowd_init_loads except for
  *             repeated pairs
  *   phase     [host] int32[m] out; may be NULL

@@ -105,8 +105,9 @@ struct lowd_solver {
     DBuf<float> e_w;
     Csr csr;
     // schedule layout
-    DBuf<int32_t> tile_center, tile_depth, tail_ph_ptr, tail_nodes;
-    DBuf<int64_t> tile_base, slot_edge, edge_slot;
+    DBuf<int32_t> tile_center, tail_nodes;
+    DBuf<PhaseDesc> tail_desc;
+    DBuf<int64_t> slot_edge, edge_slot;
     DBuf<uint32_t> slot_leaf;
     // state
     DBuf<char> slot_x, L;
@@ -148,7 +149,7 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
         if (m < 0 || m >= ((int64_t)1 << 31)) fail(LOWD_E_ARG, "m must be in [0, 2^31)");
         if (m > 0 && (!src || !dst)) fail(LOWD_E_ARG, "src/dst is NULL");
         if (state != LOWD_STATE_F64 && state != LOWD_STATE_F32K) fail(LOWD_E_ARG, "bad state");
-        if (star_max < 1 || star_max > 254) fail(LOWD_E_ARG, "star_max must be in [1, 254]");
+        if (star_max < 1 || star_max > kMaxStar) fail(LOWD_E_ARG, "star_max must be in [1, 16]");
         hipStream_t s = (hipStream_t)stream;
         validate_graph(n, m, src, dst, w, s);
 
@@ -167,11 +168,11 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
             LOWD_HIP(hipMemcpyAsync(hd.data(), dst, (size_t)m * 4, hipMemcpyDeviceToHost, s));
             LOWD_HIP(hipStreamSynchronize(s));
         }
-        size_t lds = lds_capacity_bytes();
-        int64_t lds_nodes = (int64_t)(lds / sv->fn.l_bytes);
+        const int64_t lds = (int64_t)lds_capacity_bytes();
         int64_t force = -1;
         if (const char *e = getenv("LOWD_TAIL_SPLIT")) force = atoll(e);
-        build_schedule(n, m, hs.data(), hd.data(), star_max, lds_nodes, force, sv->sch);
+        build_schedule(n, m, hs.data(), hd.data(), star_max, lds, (int64_t)sv->fn.l_bytes, force,
+                       sv->sch);
         const Schedule &sc = sv->sch;
 
         // device copies of the graph, incidence rows
@@ -191,13 +192,11 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
 
         // schedule layout
         upload(sv->tile_center, sc.tile_center, s);
-        upload(sv->tile_depth, sc.tile_depth, s);
-        upload(sv->tile_base, sc.tile_base, s);
         upload(sv->slot_leaf, sc.slot_leaf, s);
         upload(sv->slot_edge, sc.slot_edge, s);
         upload(sv->edge_slot, sc.edge_slot, s);
-        std::vector<int32_t> tptr(sc.phase_tile_ptr.begin() + sc.P0, sc.phase_tile_ptr.end());
-        upload(sv->tail_ph_ptr, tptr, s);
+        std::vector<PhaseDesc> tdesc(sc.desc.begin() + sc.P0, sc.desc.end());
+        upload(sv->tail_desc, tdesc, s);
         upload(sv->tail_nodes, sc.tail_nodes, s);
         sv->ntail = (int32_t)sc.tail_nodes.size();
 
@@ -205,7 +204,7 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
         const int64_t nslots = (int64_t)sc.slot_leaf.size();
         sv->slot_x.alloc((size_t)nslots * sv->fn.x_bytes);
         if (sv->weighted) sv->slot_w.alloc((size_t)nslots);
-        sv->L.alloc((size_t)n * sv->fn.l_bytes);
+        sv->L.alloc(((size_t)n + 1) * sv->fn.l_bytes);   // [n] = dummy center of empty lanes
         sv->L64.alloc((size_t)n);
         sv->stats_partial.alloc(3 * 1024);
         sv->stats_out.alloc(3);
@@ -214,20 +213,20 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
         // one sweep as a HIP graph: a kernel per whole-GPU phase, then the
         // LDS-resident workgroup for the last phases
         if (sc.P > 0) {
-            size_t tail_lds = (size_t)sv->ntail * sv->fn.l_bytes;
+            size_t tail_lds =
+                tail_desc_bytes(sc.P - sc.P0) + ((size_t)sv->ntail + 1) * sv->fn.l_bytes;
             if (sc.P0 < sc.P) sv->fn.set_tail_lds(tail_lds);
             hipStream_t cs;
             LOWD_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
             hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             if (err == hipSuccess) {
                 for (int32_t p = 0; p < sc.P0; ++p)
-                    sv->fn.phase(sc.phase_tile_ptr[(size_t)p], sc.phase_tile_ptr[(size_t)p + 1],
-                                 sv->tile_center.p, sv->tile_base.p, sv->tile_depth.p,
-                                 sv->slot_leaf.p, sv->slot_x.p,
-                                 sv->weighted ? sv->slot_w.p : nullptr, sv->L.p, cs);
+                    sv->fn.phase(sc.desc[(size_t)p], sv->tile_center.p, sv->slot_leaf.p,
+                                 sv->slot_x.p, sv->weighted ? sv->slot_w.p : nullptr, sv->L.p,
+                                 cs);
                 if (sc.P0 < sc.P)
-                    sv->fn.tail(sc.P - sc.P0, sv->tail_ph_ptr.p, sv->tile_center.p,
-                                sv->tile_base.p, sv->tile_depth.p, sv->slot_leaf.p, sv->slot_x.p,
+                    sv->fn.tail(sc.P - sc.P0, sv->tail_desc.p, sv->tile_center.p,
+                                sv->slot_leaf.p, sv->slot_x.p,
                                 sv->weighted ? sv->slot_w.p : nullptr, sv->tail_nodes.p,
                                 sv->ntail, sv->L.p, cs);
                 err = hipStreamEndCapture(cs, &sv->graph);
@@ -353,7 +352,7 @@ lowd_status lowd_schedule_build(int32_t n, int64_t m, const int32_t *src, const 
             if (src[e] < 0 || src[e] >= n || dst[e] < 0 || dst[e] >= n || src[e] == dst[e])
                 fail(LOWD_E_GRAPH, "invalid edge at index " + std::to_string(e));
         Schedule sc;
-        build_schedule(n, m, src, dst, star_max, 0, -1, sc);
+        build_schedule(n, m, src, dst, star_max, 0, 0, -2, sc);
         if (phase && m > 0) memcpy(phase, sc.phase.data(), (size_t)m * 4);
         if (center && m > 0) memcpy(center, sc.center.data(), (size_t)m * 4);
         if (nphases) *nphases = sc.P;

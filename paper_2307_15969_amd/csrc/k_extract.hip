@@ -4,10 +4,10 @@
 // of maximal density W(S_i) / (n - i).
 //
 // An edge lies inside S_i exactly when both endpoints sit at position >= i,
-// so W(S_i) is the suffix sum of each node's weight towards higher
-// positions.  That per-node weight is summed over the node's incidence row
-// (ascending edge index) without atomics.  Unweighted graphs use int64
-// throughout, so densities compare exactly by cross-multiplication.
+// so W(S_i) is the suffix sum of the weights binned at min(pos_u, pos_v).
+// Unweighted graphs bin with integer atomics and use int64 throughout, so
+// densities compare exactly by cross-multiplication; weighted graphs sum
+// each node's weight towards higher positions over its incidence row.
 #include "extract.h"
 #include "lowd_internal.h"
 
@@ -35,22 +35,44 @@ __global__ void k_positions(int32_t n, const uint32_t *asc, int32_t *pos) {
         pos[asc[i]] = (int32_t)i;
 }
 
-// weight from node u towards nodes at higher positions, stored at pos[u]
-template <class T, bool kWeighted>
-__global__ void k_towards_higher(int32_t n, const int64_t *row_ptr, const uint32_t *inc,
-                                 const int32_t *src, const int32_t *dst, const float *w,
-                                 const int32_t *pos, T *hist) {
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
-         u += (int64_t)gridDim.x * blockDim.x) {
+// Unweighted: each edge adds 1 at min(pos_u, pos_v) (integer atomics, exact
+// in any order).
+__global__ void k_fill_i64(int64_t n, int64_t *a) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0;
+}
+
+__global__ void k_edge_min_pos(int64_t m, const int32_t *src, const int32_t *dst,
+                               const int32_t *pos, unsigned long long *hist) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        int32_t a = pos[src[e]], b = pos[dst[e]];
+        atomicAdd(&hist[a < b ? a : b], 1ull);
+    }
+}
+
+// Weighted: the weight from node u towards nodes at higher positions, stored
+// at pos[u]; one wavefront per node, lanes stride over the row, fixed-order
+// reduction (deterministic).
+__global__ void __launch_bounds__(256) k_towards_higher_w(int32_t n, const int64_t *row_ptr,
+                                                          const uint32_t *inc, const int32_t *src,
+                                                          const int32_t *dst, const float *w,
+                                                          const int32_t *pos, double *hist) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; u < n;
+         u += waves) {
         const int32_t pu = pos[u];
-        T acc = 0;
-        for (int64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j) {
+        double acc = 0.0;
+        for (int64_t j = row_ptr[u] + lane; j < row_ptr[u + 1]; j += kWave) {
             uint32_t ent = inc[j];
             int64_t e = ent >> 1;
             int32_t other = (ent & 1) ? src[e] : dst[e];
-            if (pos[other] > pu) acc = acc + (kWeighted ? (T)w[e] : (T)1);
+            if (pos[other] > pu) acc = acc + (double)w[e];
         }
-        hist[pu] = acc;
+        for (int d = kWave / 2; d > 0; d >>= 1) acc = acc + __shfl_down(acc, d, kWave);
+        if (lane == 0) hist[pu] = acc;
     }
 }
 
@@ -146,8 +168,15 @@ void extract_impl(const ExtractArgs &a, ExtractScratch &sc, hipStream_t s) {
     T *hist = (T *)sc.hist.p;
     T *rev = (T *)sc.rev.p;
     T *W = (T *)sc.W.p;
-    hipLaunchKernelGGL((k_towards_higher<T, kWeighted>), dim3(grid_for(n, 256)), dim3(256), 0, s,
-                       n, a.row_ptr, a.inc, a.src, a.dst, a.w, sc.pos.p, hist);
+    if constexpr (kWeighted) {
+        hipLaunchKernelGGL(k_towards_higher_w, dim3(grid_for((int64_t)n * kWave, 256)), dim3(256),
+                           0, s, n, a.row_ptr, a.inc, a.src, a.dst, a.w, sc.pos.p, hist);
+    } else {
+        hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n, 256)), dim3(256), 0, s, (int64_t)n, hist);
+        if (a.m > 0)
+            hipLaunchKernelGGL(k_edge_min_pos, dim3(grid_for(a.m, 256)), dim3(256), 0, s, a.m,
+                               a.src, a.dst, sc.pos.p, (unsigned long long *)hist);
+    }
     hipLaunchKernelGGL(k_reverse<T>, dim3(grid_for(n, 256)), dim3(256), 0, s, (int64_t)n, hist,
                        rev);
     if constexpr (kWeighted)

@@ -27,110 +27,214 @@ __global__ void k_init_slots(int64_t nslots, const int64_t *slot_edge, const flo
     }
 }
 
-// l_u = sum of w_e / 2 over the edges at u, in ascending edge index
+// l_u = sum of w_e / 2 over the edges at u, in ascending edge index; entry
+// n (the dummy center of lanes without a star) is set to zero
 template <class St, bool kWeighted>
 __global__ void k_init_loads(int32_t n, const int64_t *row_ptr, const uint32_t *inc,
                              const float *w, typename St::L *L) {
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u <= n;
          u += (int64_t)gridDim.x * blockDim.x) {
         double acc = 0.0;
-        for (int64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j) {
-            double we = kWeighted ? (double)w[inc[j] >> 1] : 1.0;
-            acc = acc + we / 2.0;
+        if (u < n) {
+            if (kWeighted) {
+                for (int64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j)
+                    acc = acc + (double)w[inc[j] >> 1] / 2.0;
+            } else {
+                // a sum of halves is exact in any order: deg / 2
+                acc = (double)(row_ptr[u + 1] - row_ptr[u]) * 0.5;
+            }
         }
         L[u] = St::from_f64(acc);
     }
 }
 
 // ------------------------------------------------------------ one tile ---
-// The lane's star: center c (load in a register), leaves in rows 0..depth-1.
-// Rows are read four at a time so the leaf loads of a group are in flight
-// together; leaves of one star are distinct and belong to no other star of
-// the phase, so a prefetched leaf load cannot be stale.
-template <class St, bool kWeighted, class LPtr>
-__device__ __forceinline__ void run_star(int32_t c, int64_t base, int32_t depth, int lane,
-                                         const uint32_t *__restrict__ slot_leaf,
-                                         typename St::X *__restrict__ slot_x,
-                                         const float *__restrict__ slot_w, LPtr L) {
-    typename St::L Lc = L[c];
-    constexpr int G = 4;
-    for (int k0 = 0; k0 < depth; k0 += G) {
-        uint32_t enc[G];
-        typename St::X xv[G];
-        float wv[G];
-        typename St::L Ll[G];
+// One wave = one tile of 64 stars of a phase; the lane's star has a center c
+// and depth leaves in rows 0..depth-1 of the tile.  A tile is loaded in one
+// go (center, leaf ids, fractions, weights: every address follows from the
+// phase descriptor), then the endpoint loads are read together, then the
+// lane runs its chain of depth steps in registers, carrying the center's
+// load.  Leaves of one star are distinct and belong to no other star of the
+// phase, so all reads of a tile can be in flight at once.
+template <class St, bool kWeighted>
+struct Tile {
+    int32_t c;
+    int32_t depth;        // wave-uniform
+    int64_t base;         // wave-uniform: first slot of the tile
+    uint32_t enc[kMaxStar];
+    typename St::X x[kMaxStar];
+    float w[kMaxStar];
+};
+
+template <class St, bool kWeighted>
+__device__ __forceinline__ void load_tile(Tile<St, kWeighted> &tl, const PhaseDesc &d, int32_t t,
+                                          int lane, const int32_t *__restrict__ tile_center,
+                                          const uint32_t *__restrict__ slot_leaf,
+                                          const typename St::X *__restrict__ slot_x,
+                                          const float *__restrict__ slot_w) {
+    int32_t depth = 0;
+    int64_t rows = 0;
 #pragma unroll
-        for (int j = 0; j < G; ++j) {
-            int64_t s = base + (int64_t)(k0 + j) * kWave + lane;
-            enc[j] = (k0 + j < depth) ? slot_leaf[s] : kLeafPad;
-        }
-#pragma unroll
-        for (int j = 0; j < G; ++j) {
-            int64_t s = base + (int64_t)(k0 + j) * kWave + lane;
-            if (enc[j] != kLeafPad) {
-                xv[j] = slot_x[s];
-                wv[j] = kWeighted ? slot_w[s] : 1.0f;
-                Ll[j] = L[enc[j] & ~kCenterIsDst];
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < G; ++j) {
-            if (enc[j] == kLeafPad) break;
-            int64_t s = base + (int64_t)(k0 + j) * kWave + lane;
-            if (enc[j] & kCenterIsDst) St::step(Ll[j], Lc, xv[j], wv[j]);   // u = leaf
-            else St::step(Lc, Ll[j], xv[j], wv[j]);                          // u = center
-            slot_x[s] = xv[j];
-            L[enc[j] & ~kCenterIsDst] = Ll[j];
-        }
-        if (enc[G - 1] == kLeafPad) break;
+    for (int k = 0; k < kMaxStar; ++k) {
+        depth += (d.T[k] > t) ? 1 : 0;
+        rows += (int64_t)(d.T[k] < t ? d.T[k] : t);
     }
-    L[c] = Lc;
+    tl.depth = __builtin_amdgcn_readfirstlane(depth);
+    const int64_t base = d.slot_base + rows * kWave;
+    tl.base = base;
+    tl.c = tile_center[(int64_t)(d.tile0 + t) * kWave + lane];
+    const uint32_t *pl = slot_leaf + base + lane;
+    const typename St::X *px = slot_x + base + lane;
+    const float *pw = kWeighted ? slot_w + base + lane : nullptr;
+#pragma unroll
+    for (int k = 0; k < kMaxStar; ++k) {
+        if (k < tl.depth) {
+            tl.enc[k] = pl[k * kWave];
+            tl.x[k] = px[k * kWave];
+            tl.w[k] = kWeighted ? pw[k * kWave] : 1.0f;
+        } else {
+            tl.enc[k] = kLeafPad;
+        }
+    }
+}
+
+// Branch-free per lane: a padding row (the lane's star is shorter than the
+// tile) reads and rewrites the lane's own center, and its step result is
+// discarded by a select; the center is written last.  A lane without a star
+// has the dummy node (index n, or the tail's last LDS entry) as its center.
+template <class St, bool kWeighted, class LPtr>
+__device__ __forceinline__ void run_tile(Tile<St, kWeighted> &tl, int lane,
+                                         typename St::X *__restrict__ slot_x, LPtr L) {
+    typename St::L Lc = L[tl.c];
+    typename St::L Ll[kMaxStar];
+    int32_t at[kMaxStar];
+#pragma unroll
+    for (int k = 0; k < kMaxStar; ++k) {
+        if (k < tl.depth) {
+            at[k] = (tl.enc[k] != kLeafPad) ? (int32_t)(tl.enc[k] & ~kCenterIsDst) : tl.c;
+            Ll[k] = L[at[k]];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxStar; ++k) {
+        if (k < tl.depth) {
+            const bool live = tl.enc[k] != kLeafPad;
+            const bool c_is_u = !(tl.enc[k] & kCenterIsDst);   // u = src
+            typename St::L lc = Lc, ll = Ll[k];
+            typename St::X xx = tl.x[k];
+            St::step_center(lc, ll, c_is_u, xx, tl.w[k]);
+            Lc = live ? lc : Lc;
+            Ll[k] = live ? ll : Ll[k];
+            tl.x[k] = live ? xx : tl.x[k];
+        }
+    }
+    typename St::X *px = slot_x + tl.base + lane;
+#pragma unroll
+    for (int k = 0; k < kMaxStar; ++k) {
+        if (k < tl.depth) {
+            px[k * kWave] = tl.x[k];
+            L[at[k]] = Ll[k];
+        }
+    }
+    L[tl.c] = Lc;
 }
 
 // --------------------------------------------------- whole-GPU phase -----
-constexpr int kPhaseBlock = 256;   // four tiles per block
+constexpr int kPhaseBlock = 64;    // one tile per block: spread over many CUs
 
 template <class St, bool kWeighted>
 __global__ void __launch_bounds__(kPhaseBlock)
-k_phase(int32_t tile_begin, int32_t tile_end, const int32_t *__restrict__ tile_center,
-        const int64_t *__restrict__ tile_base, const int32_t *__restrict__ tile_depth,
+k_phase(PhaseDesc d, const int32_t *__restrict__ tile_center,
         const uint32_t *__restrict__ slot_leaf, typename St::X *__restrict__ slot_x,
         const float *__restrict__ slot_w, typename St::L *__restrict__ L) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int32_t tile = tile_begin + (int32_t)(blockIdx.x * (kPhaseBlock / kWave) + threadIdx.x / kWave);
-    if (tile >= tile_end) return;
-    const int32_t c = tile_center[(int64_t)tile * kWave + lane];
-    if (c < 0) return;
-    run_star<St, kWeighted>(c, tile_base[tile], tile_depth[tile], lane, slot_leaf, slot_x, slot_w,
-                            L);
+    const int32_t t = __builtin_amdgcn_readfirstlane(
+        (int32_t)(blockIdx.x * (kPhaseBlock / kWave) + threadIdx.x / kWave));
+    if (t >= d.T[0]) return;
+    Tile<St, kWeighted> tl;
+    load_tile(tl, d, t, lane, tile_center, slot_leaf, slot_x, slot_w);
+    run_tile(tl, lane, slot_x, L);
 }
 
 // ----------------------------------------- LDS-resident last phases ------
-constexpr int kTailBlock = 1024;
+// One workgroup runs the last phases with the loads of their nodes in LDS
+// and an LDS barrier between phases.  Wave w owns tile w of every phase and
+// keeps two tile buffers: while it runs phase p from one, the other already
+// receives phase p+1's leaf ids and fractions (they do not depend on phase
+// p; only the loads do, and those come from LDS after the barrier).  The
+// buffers alternate, so no register copy forces the prefetch to complete.
+// The phase descriptors are staged in LDS next to the loads.  The schedule
+// puts no phase with more tiles than the workgroup has waves in the tail.
+constexpr int kTailBlock = 512;
+static_assert(kTailBlock / kWave == kTailWaves, "tail width");
+
+// Barrier that orders LDS only: every wave's LDS writes are complete before
+// any wave passes.  Outstanding global loads (the next phase's prefetch) and
+// stores (fractions, read again only in the next sweep) are not waited for.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// The descriptor of phase p, read from LDS into one VGPR (lane i holds
+// word i) and broadcast into scalar registers.
+__device__ __forceinline__ PhaseDesc desc_from_lds(const PhaseDesc *sd, int32_t p, int lane) {
+    constexpr int kWords = (int)(sizeof(PhaseDesc) / 4);
+    const int32_t *w = reinterpret_cast<const int32_t *>(sd + p);
+    const int32_t v = lane < kWords ? w[lane] : 0;
+    PhaseDesc d;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane(v, 0);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane(v, 1);
+    d.slot_base = (int64_t)(((uint64_t)hi << 32) | lo);
+    d.tile0 = __builtin_amdgcn_readlane(v, 2);
+#pragma unroll
+    for (int k = 0; k < kMaxStar; ++k) d.T[k] = __builtin_amdgcn_readlane(v, 3 + k);
+    d.pad = 0;
+    return d;
+}
 
 template <class St, bool kWeighted>
 __global__ void __launch_bounds__(kTailBlock)
-k_tail(int32_t nph, const int32_t *__restrict__ ph_tile_ptr, const int32_t *__restrict__ tile_center,
-       const int64_t *__restrict__ tile_base, const int32_t *__restrict__ tile_depth,
+k_tail(int32_t nph, const PhaseDesc *__restrict__ descs, const int32_t *__restrict__ tile_center,
        const uint32_t *__restrict__ slot_leaf, typename St::X *__restrict__ slot_x,
        const float *__restrict__ slot_w, const int32_t *__restrict__ tail_nodes, int32_t ntail,
        typename St::L *__restrict__ L) {
-    extern __shared__ unsigned char lds_raw[];
-    typename St::L *sL = reinterpret_cast<typename St::L *>(lds_raw);
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    PhaseDesc *sd = reinterpret_cast<PhaseDesc *>(lds_raw);
+    typename St::L *sL = reinterpret_cast<typename St::L *>(lds_raw + tail_desc_bytes(nph));
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
-    constexpr int kWaves = kTailBlock / kWave;
-    for (int32_t i = threadIdx.x; i < ntail; i += kTailBlock) sL[i] = L[tail_nodes[i]];
-    __syncthreads();
-    for (int32_t p = 0; p < nph; ++p) {
-        const int32_t t0 = ph_tile_ptr[p], t1 = ph_tile_ptr[p + 1];
-        for (int32_t t = t0 + wave; t < t1; t += kWaves) {
-            const int32_t c = tile_center[(int64_t)t * kWave + lane];
-            if (c >= 0)
-                run_star<St, kWeighted>(c, tile_base[t], tile_depth[t], lane, slot_leaf, slot_x,
-                                        slot_w, sL);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    {   // stage descriptors (as 32-bit words) and loads
+        const int32_t *src = reinterpret_cast<const int32_t *>(descs);
+        int32_t *dst = reinterpret_cast<int32_t *>(sd);
+        const int32_t words = nph * (int32_t)(sizeof(PhaseDesc) / 4);
+        for (int32_t i = threadIdx.x; i < words; i += kTailBlock) dst[i] = src[i];
+        for (int32_t i = threadIdx.x; i < ntail; i += kTailBlock) sL[i] = L[tail_nodes[i]];
+        if (threadIdx.x == 0) sL[ntail] = St::from_f64(0.0);   // dummy center of empty lanes
+    }
+    lds_barrier();
+    Tile<St, kWeighted> ta, tb;
+    PhaseDesc da = desc_from_lds(sd, 0, lane), db;
+    ta.c = -1;
+    if (wave < da.T[0]) load_tile(ta, da, wave, lane, tile_center, slot_leaf, slot_x, slot_w);
+    for (int32_t p = 0; p < nph; p += 2) {
+        const bool has_b = p + 1 < nph;
+        tb.c = -1;
+        if (has_b) {
+            db = desc_from_lds(sd, p + 1, lane);
+            if (wave < db.T[0]) load_tile(tb, db, wave, lane, tile_center, slot_leaf, slot_x, slot_w);
         }
-        __syncthreads();
+        if (wave < da.T[0]) run_tile(ta, lane, slot_x, sL);
+        lds_barrier();
+        if (!has_b) break;
+        ta.c = -1;
+        if (p + 2 < nph) {
+            da = desc_from_lds(sd, p + 2, lane);
+            if (wave < da.T[0]) load_tile(ta, da, wave, lane, tile_center, slot_leaf, slot_x, slot_w);
+        }
+        if (wave < db.T[0]) run_tile(tb, lane, slot_x, sL);
+        lds_barrier();
     }
     for (int32_t i = threadIdx.x; i < ntail; i += kTailBlock) L[tail_nodes[i]] = sL[i];
 }
@@ -138,22 +242,27 @@ k_tail(int32_t nph, const int32_t *__restrict__ ph_tile_ptr, const int32_t *__re
 // ------------------------------------------------------------ statistics --
 constexpr int kRedBlock = 256;
 
-// FP64 loads recomputed from the fractions (f_e(src) = x, f_e(dst) = w - x)
+// FP64 loads recomputed from the fractions (f_e(src) = x, f_e(dst) = w - x);
+// one wavefront per node, lanes stride over the row, fixed-order reduction
 template <class St, bool kWeighted>
-__global__ void k_recompute(int32_t n, const int64_t *row_ptr, const uint32_t *inc,
-                            const int64_t *edge_slot, const typename St::X *slot_x,
-                            const float *w, double *L64) {
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
-         u += (int64_t)gridDim.x * blockDim.x) {
+__global__ void __launch_bounds__(256) k_recompute(int32_t n, const int64_t *row_ptr,
+                                                   const uint32_t *inc, const int64_t *edge_slot,
+                                                   const typename St::X *slot_x, const float *w,
+                                                   double *L64) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; u < n;
+         u += waves) {
         double acc = 0.0;
-        for (int64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j) {
+        for (int64_t j = row_ptr[u] + lane; j < row_ptr[u + 1]; j += kWave) {
             uint32_t ent = inc[j];
             int64_t e = ent >> 1;
             double x = (double)slot_x[edge_slot[e]];
             double we = kWeighted ? (double)w[e] : 1.0;
             acc = acc + ((ent & 1) ? we - x : x);
         }
-        L64[u] = acc;
+        for (int d = kWave / 2; d > 0; d >>= 1) acc = acc + __shfl_down(acc, d, kWave);
+        if (lane == 0) L64[u] = acc;
     }
 }
 
@@ -246,27 +355,24 @@ static void sweep_launchers(SweepLaunch &fn) {
     };
     fn.init_loads = [](int32_t n, const int64_t *row_ptr, const uint32_t *inc, const float *w,
                        void *L, hipStream_t s) {
-        hipLaunchKernelGGL((k_init_loads<St, kW>), dim3(grid_for(n, 256)), dim3(256), 0, s, n,
+        hipLaunchKernelGGL((k_init_loads<St, kW>), dim3(grid_for((int64_t)n + 1, 256)), dim3(256), 0, s, n,
                            row_ptr, inc, w, (typename St::L *)L);
     };
-    fn.phase = [](int32_t t0, int32_t t1, const int32_t *tile_center, const int64_t *tile_base,
-                  const int32_t *tile_depth, const uint32_t *slot_leaf, void *slot_x,
-                  const float *slot_w, void *L, hipStream_t s) {
-        int32_t tiles = t1 - t0;
+    fn.phase = [](const PhaseDesc &d, const int32_t *tile_center, const uint32_t *slot_leaf,
+                  void *slot_x, const float *slot_w, void *L, hipStream_t s) {
+        int32_t tiles = d.T[0];
         unsigned blocks = (unsigned)((tiles + (kPhaseBlock / kWave) - 1) / (kPhaseBlock / kWave));
-        hipLaunchKernelGGL((k_phase<St, kW>), dim3(blocks), dim3(kPhaseBlock), 0, s, t0, t1,
-                           tile_center, tile_base, tile_depth, slot_leaf,
-                           (typename St::X *)slot_x, slot_w, (typename St::L *)L);
-    };
-    fn.tail = [](int32_t nph, const int32_t *ph_tile_ptr, const int32_t *tile_center,
-                 const int64_t *tile_base, const int32_t *tile_depth, const uint32_t *slot_leaf,
-                 void *slot_x, const float *slot_w, const int32_t *tail_nodes, int32_t ntail,
-                 void *L, hipStream_t s) {
-        size_t lds = (size_t)ntail * sizeof(typename St::L);
-        hipLaunchKernelGGL((k_tail<St, kW>), dim3(1), dim3(kTailBlock), lds, s, nph, ph_tile_ptr,
-                           tile_center, tile_base, tile_depth, slot_leaf,
-                           (typename St::X *)slot_x, slot_w, tail_nodes, ntail,
+        hipLaunchKernelGGL((k_phase<St, kW>), dim3(blocks), dim3(kPhaseBlock), 0, s, d,
+                           tile_center, slot_leaf, (typename St::X *)slot_x, slot_w,
                            (typename St::L *)L);
+    };
+    fn.tail = [](int32_t nph, const PhaseDesc *descs, const int32_t *tile_center,
+                 const uint32_t *slot_leaf, void *slot_x, const float *slot_w,
+                 const int32_t *tail_nodes, int32_t ntail, void *L, hipStream_t s) {
+        size_t lds = tail_desc_bytes(nph) + (size_t)(ntail + 1) * sizeof(typename St::L);
+        hipLaunchKernelGGL((k_tail<St, kW>), dim3(1), dim3(kTailBlock), lds, s, nph, descs,
+                           tile_center, slot_leaf, (typename St::X *)slot_x, slot_w, tail_nodes,
+                           ntail, (typename St::L *)L);
     };
     fn.set_tail_lds = [](size_t bytes) {
         LOWD_HIP(hipFuncSetAttribute((const void *)k_tail<St, kW>,
@@ -276,8 +382,9 @@ static void sweep_launchers(SweepLaunch &fn) {
                       const int64_t *edge_slot, const void *slot_x, const float *w, const void *L,
                       double *L64, hipStream_t s) {
         if (St::kRecompute)
-            hipLaunchKernelGGL((k_recompute<St, kW>), dim3(grid_for(n, 256)), dim3(256), 0, s, n,
-                               row_ptr, inc, edge_slot, (const typename St::X *)slot_x, w, L64);
+            hipLaunchKernelGGL((k_recompute<St, kW>), dim3(grid_for((int64_t)n * kWave, 256)),
+                               dim3(256), 0, s, n, row_ptr, inc, edge_slot,
+                               (const typename St::X *)slot_x, w, L64);
         else
             hipLaunchKernelGGL((k_loads_to_f64<St>), dim3(grid_for(n, 256)), dim3(256), 0, s, n,
                                (const typename St::L *)L, L64);

@@ -55,6 +55,29 @@ constexpr uint32_t kCenterIsDst = 0x80000000u;
 constexpr int kWave = 64;
 
 // ------------------------------------------------------------- schedule --
+// Stars of a phase are sorted by size (descending) and dealt to tiles of 64,
+// one star per lane, so tile depths are non-increasing.  T[k] = number of
+// tiles of the phase deeper than k; tile t is depth_t = #{k : T[k] > t} rows
+// deep and its rows are contiguous:
+//   slot(t, k, lane) = slot_base + 64 * (sum_k' min(T[k'], t)) + 64 * k + lane
+// (the tiles before t hold sum_{i<t} depth_i = sum_k' min(T[k'], t) rows).
+// Every slot address follows from the phase descriptor alone (a kernel
+// argument), so a phase needs no metadata load before its slot rows.
+constexpr int kMaxStar = 16;          // largest star the sweep kernels take
+constexpr int kTailWaves = 8;         // waves of the LDS-resident tail workgroup
+
+struct PhaseDesc {
+    int64_t slot_base;                // first slot of the phase
+    int32_t tile0;                    // first tile (index into tile_center / 64)
+    int32_t T[kMaxStar];              // T[k] = tiles of depth > k; T[0] = tiles
+    int32_t pad;
+};
+
+// LDS bytes the tail workgroup spends on its phase descriptors.
+__host__ __device__ inline size_t tail_desc_bytes(int64_t nph) {
+    return ((size_t)nph * sizeof(PhaseDesc) + 15) & ~(size_t)15;
+}
+
 // Host-side result of the phase schedule and its device layout.
 struct Schedule {
     int32_t n = 0;
@@ -63,23 +86,25 @@ struct Schedule {
     int32_t P = 0;                  // phases
     std::vector<int32_t> phase;     // per edge
     std::vector<int32_t> center;    // per edge (node id)
-    // tile layout (phases in order; stars sorted by size desc, 64 per tile)
     int32_t P0 = 0;                 // phases [0, P0) run as whole-GPU launches
-    std::vector<int32_t> phase_tile_ptr;   // [P+1] tile range per phase
-    std::vector<int32_t> tile_center;      // [ntiles*64] node id (local ids for tail tiles), -1 empty
-    std::vector<int64_t> tile_base;        // [ntiles] first slot of the tile
-    std::vector<int32_t> tile_depth;       // [ntiles] rows of the tile
-    std::vector<uint32_t> slot_leaf;       // [nslots] leaf | orientation, kLeafPad for padding
-    std::vector<int64_t> slot_edge;        // [nslots] edge index, -1 for padding
-    std::vector<int64_t> edge_slot;        // [m] slot of each edge
-    std::vector<int32_t> tail_nodes;       // global ids of the nodes held in LDS by the tail
+    std::vector<PhaseDesc> desc;          // [P]
+    std::vector<int32_t> tile_center;     // [ntiles*64] node id (local ids for tail tiles), -1 empty
+    std::vector<uint32_t> slot_leaf;      // [nslots] leaf | orientation, kLeafPad for padding
+    std::vector<int64_t> slot_edge;       // [nslots] edge index, -1 for padding
+    std::vector<int64_t> edge_slot;       // [m] slot of each edge
+    std::vector<int32_t> tail_nodes;      // global ids of the nodes held in LDS by the tail
     int64_t tail_edges = 0;
+    std::vector<int64_t> phase_edges;     // [P]
+    std::vector<int32_t> phase_depth;     // [P] deepest star
 };
 
 // Builds the phase schedule (first fit over edges in ascending index) and
-// the tile layout; `lds_nodes` bounds the tail's node set (0 = no tail).
+// the tile layout.
+// lds_bytes bounds the tail's LDS (descriptors + node loads of l_bytes each;
+// 0 = no tail); force_p0 >= 0 asks for the split (moved later until the tail
+// fits); force_p0 == -2 computes the phase assignment only.
 void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, int32_t smax,
-                    int64_t lds_nodes, int64_t force_p0, Schedule &out);
+                    int64_t lds_bytes, int64_t l_bytes, int64_t force_p0, Schedule &out);
 
 // --------------------------------------------------------------- kernels --
 // Device-wide primitives (k_scan.hip)

@@ -15,9 +15,10 @@
 // Sequential order: ascending (phase, edge index).
 //
 // Device layout: within a phase the stars are sorted by size (descending,
-// then center id) and dealt to tiles of 64, one star per lane.  Tile t owns
-// depth_t * 64 consecutive slots; slot (k, lane) holds the k-th leaf of the
-// lane's star, so row k of a tile is one coalesced 64-wide access.
+// then center id) and dealt to tiles of 64, one star per lane; row k of the
+// phase holds the k-th leaf of every tile deeper than k (see PhaseDesc), so
+// a row is one coalesced 64-wide access and every address follows from the
+// phase descriptor.
 //
 // The last phases of a power-law graph are small and touch few nodes (the
 // dense core); the schedule picks a split phase P0 such that the nodes of
@@ -50,18 +51,23 @@ struct Bits {
 // its streamed bytes; a phase inside the LDS-resident workgroup costs a
 // barrier plus its longest star chain plus one CU's streaming time.
 struct CostModel {
-    double grid_fixed_us = 1.7;
+    double grid_fixed_us = 3.5;                  // boundary + two memory round trips
     double grid_us_per_edge = 48.0 / 4.0e6;      // ~48 B per edge at ~4 TB/s
-    double tail_fixed_us = 0.25;
-    double tail_us_per_depth = 0.035;            // one dependent LDS step
-    double tail_us_per_edge = 24.0 / 1.2e5;      // ~24 B per edge at ~120 GB/s
+    double tail_fixed_us = 0.4;                  // barrier + LDS gathers
+    double tail_us_per_depth = 0.03;             // one dependent step of the chain
+    double tail_us_per_edge = 24.0 / 1.0e5;      // ~24 B per edge at ~100 GB/s
 };
 
 }  // namespace
 
 void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, int32_t smax,
-                    int64_t lds_nodes, int64_t force_p0, Schedule &out) {
+                    int64_t lds_bytes, int64_t l_bytes, int64_t force_p0, Schedule &out) {
     out = Schedule();
+    if (smax > kMaxStar && force_p0 != -2) {
+        // the device layout holds stars of up to kMaxStar leaves; callers that
+        // only want the phase assignment pass force_p0 = -2
+        fail(-1, "star_max must be at most 16 for the sweep kernels");
+    }
     out.n = n;
     out.m = m;
     out.smax = smax;
@@ -114,6 +120,8 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
     { std::vector<Bits>().swap(used); std::vector<Bits>().swap(noc); }
     std::vector<std::vector<uint8_t>>().swap(cnt);
 
+    if (force_p0 == -2) return;   // phase assignment only
+
     // ---- edges by (phase, center, index) -----------------------------------
     std::vector<int64_t> pstart((size_t)P + 1, 0);
     for (int64_t e = 0; e < m; ++e) ++pstart[(size_t)out.phase[(size_t)e] + 1];
@@ -159,11 +167,21 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
         if (last[(size_t)u] >= 0) ++nodes_from[(size_t)last[(size_t)u]];
     for (int32_t p = P - 1; p >= 0; --p) nodes_from[(size_t)p] += nodes_from[(size_t)p + 1];
     CostModel cm;
+    // the tail [p0, P) fits when its descriptors and node loads fit in LDS
+    // the last phase with more tiles than the tail has waves bounds the split
+    int32_t min_p0 = 0;
+    for (int32_t p = 0; p < P; ++p)
+        if ((int64_t)stars[(size_t)p].size() > (int64_t)kTailWaves * kWave) min_p0 = p + 1;
+    auto fits = [&](int32_t p0) {
+        if (lds_bytes <= 0) return p0 >= P;
+        if (p0 < min_p0) return false;
+        return (int64_t)tail_desc_bytes(P - p0) + (nodes_from[(size_t)p0] + 1) * l_bytes <= lds_bytes;
+    };
     int32_t P0 = P;
     if (force_p0 >= 0) {
         P0 = (int32_t)std::min<int64_t>(force_p0, P);
-        while (P0 < P && nodes_from[(size_t)P0] > lds_nodes) ++P0;
-    } else if (lds_nodes > 0 && P > 0) {
+        while (P0 < P && !fits(P0)) ++P0;
+    } else if (lds_bytes > 0 && P > 0) {
         // cost(P0) = sum_{p<P0} grid(p) + sum_{p>=P0} tail(p)
         std::vector<double> gpre((size_t)P + 1, 0.0), tsuf((size_t)P + 1, 0.0);
         for (int32_t p = 0; p < P; ++p)
@@ -175,7 +193,7 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
                               cm.tail_us_per_edge * (double)ecount[(size_t)p];
         double best = gpre[(size_t)P];
         for (int32_t p0 = P - 1; p0 >= 0; --p0) {
-            if (nodes_from[(size_t)p0] > lds_nodes) break;   // monotone in p0
+            if (!fits(p0)) break;   // fits(p0) implies fits(p0 + 1)
             double c = gpre[(size_t)p0] + tsuf[(size_t)p0];
             if (c < best) { best = c; P0 = p0; }
         }
@@ -193,46 +211,63 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
     }
 
     // ---- tiles and slots ----------------------------------------------------
-    out.phase_tile_ptr.assign((size_t)P + 1, 0);
+    out.desc.assign((size_t)P, PhaseDesc{});
+    out.phase_edges = ecount;
+    out.phase_depth.assign((size_t)P, 0);
     int64_t ntiles = 0, nslots = 0;
     for (int32_t p = 0; p < P; ++p) {
         const std::vector<Star> &st = stars[(size_t)p];
-        int64_t t = ((int64_t)st.size() + kWave - 1) / kWave;
-        for (int64_t k = 0; k < t; ++k) nslots += (int64_t)st[(size_t)(k * kWave)].len * kWave;
+        PhaseDesc &d = out.desc[(size_t)p];
+        d.slot_base = nslots;
+        d.tile0 = (int32_t)ntiles;
+        d.pad = 0;
+        int32_t t = (int32_t)((st.size() + kWave - 1) / kWave);
+        for (int k = 0; k < kMaxStar; ++k) {
+            int32_t cnt = 0;   // tiles whose first (deepest) star is longer than k
+            for (int32_t i = 0; i < t; ++i)
+                if (st[(size_t)i * kWave].len > k) ++cnt;
+            d.T[k] = cnt;
+            nslots += (int64_t)cnt * kWave;
+        }
+        out.phase_depth[(size_t)p] = st.empty() ? 0 : st[0].len;
         ntiles += t;
-        out.phase_tile_ptr[(size_t)p + 1] = (int32_t)ntiles;
     }
-    out.tile_center.assign((size_t)ntiles * kWave, -1);
-    out.tile_base.assign((size_t)ntiles, 0);
-    out.tile_depth.assign((size_t)ntiles, 0);
+    // lanes without a star get the dummy node: n (whole-GPU phases) or the
+    // tail's LDS entry after its nodes
+    out.tile_center.assign((size_t)ntiles * kWave, n);
     out.slot_leaf.assign((size_t)nslots, kLeafPad);
     out.slot_edge.assign((size_t)nslots, -1);
     out.edge_slot.assign((size_t)m, -1);
-    int64_t slot = 0, tile = 0;
+    const int32_t ntail_nodes = (int32_t)out.tail_nodes.size();
     for (int32_t p = 0; p < P; ++p) {
         const bool tail = p >= P0;
         if (tail) out.tail_edges += ecount[(size_t)p];
+        if (tail) {
+            const int64_t t = (int64_t)((stars[(size_t)p].size() + kWave - 1) / kWave);
+            for (int64_t i = 0; i < t * kWave; ++i)
+                out.tile_center[(size_t)(out.desc[(size_t)p].tile0 * kWave + i)] = ntail_nodes;
+        }
         const std::vector<Star> &st = stars[(size_t)p];
-        for (size_t s0 = 0; s0 < st.size(); s0 += kWave, ++tile) {
-            int32_t depth = st[s0].len;
-            out.tile_base[(size_t)tile] = slot;
-            out.tile_depth[(size_t)tile] = depth;
-            for (int lane = 0; lane < kWave && s0 + (size_t)lane < st.size(); ++lane) {
-                const Star &sr = st[s0 + (size_t)lane];
-                out.tile_center[(size_t)tile * kWave + (size_t)lane] =
-                    tail ? local[(size_t)sr.center] : sr.center;
-                for (int32_t k = 0; k < sr.len; ++k) {
-                    int64_t e = byphase[(size_t)(sr.begin + k)];
-                    bool c_is_dst = dst[e] == sr.center;
-                    int32_t leaf = c_is_dst ? src[e] : dst[e];
-                    int32_t id = tail ? local[(size_t)leaf] : leaf;
-                    int64_t sl = slot + (int64_t)k * kWave + lane;
-                    out.slot_leaf[(size_t)sl] = (uint32_t)id | (c_is_dst ? kCenterIsDst : 0u);
-                    out.slot_edge[(size_t)sl] = e;
-                    out.edge_slot[(size_t)e] = sl;
-                }
+        const PhaseDesc &d = out.desc[(size_t)p];
+        for (size_t i = 0; i < st.size(); ++i) {
+            const Star &sr = st[i];
+            const int64_t tt = (int64_t)(i / kWave);
+            const int lane = (int)(i % kWave);
+            int64_t rows_before = 0;   // sum_k min(T[k], tt)
+            for (int k = 0; k < kMaxStar; ++k) rows_before += std::min<int64_t>(d.T[k], tt);
+            const int64_t tile_base = d.slot_base + rows_before * kWave;
+            out.tile_center[(size_t)((d.tile0 + tt) * kWave + lane)] =
+                tail ? local[(size_t)sr.center] : sr.center;
+            for (int32_t k = 0; k < sr.len; ++k) {
+                int64_t e = byphase[(size_t)(sr.begin + k)];
+                bool c_is_dst = dst[e] == sr.center;
+                int32_t leaf = c_is_dst ? src[e] : dst[e];
+                int32_t id = tail ? local[(size_t)leaf] : leaf;
+                int64_t sl = tile_base + (int64_t)k * kWave + lane;
+                out.slot_leaf[(size_t)sl] = (uint32_t)id | (c_is_dst ? kCenterIsDst : 0u);
+                out.slot_edge[(size_t)sl] = e;
+                out.edge_slot[(size_t)e] = sl;
             }
-            slot += (int64_t)depth * kWave;
         }
     }
 }

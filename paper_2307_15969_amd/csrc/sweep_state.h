@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "lowd_internal.h"
+
 namespace lowd {
 
 // Algorithm 1's step on edge e = (u, v) with u = src[e]: x = f_e(u) and
@@ -14,6 +16,12 @@ namespace lowd {
 // set to w exactly, so f_e(v) never becomes negative through rounding.  On
 // l_u == l_v the else-branch runs with d = 0.  The library is compiled with
 // -ffp-contract=off: every operation rounds on its own, as written.
+//
+// The kernels evaluate it without branches: both candidate moves are formed
+// and selected, which performs the same FP64 operations on the same operands
+// as the two-branch form (l_v - l_u equals -(l_u - l_v) exactly, so
+// |l_u - l_v| * 0.5 is the else-branch's half), hence the same bits.  A
+// chain of steps on one star then has no divergence between lanes.
 struct StateF64 {
     using X = double;
     using L = double;
@@ -25,19 +33,40 @@ struct StateF64 {
         const double w = (double)wf;
         const double a = x;
         const double b = w - a;
-        if (lu > lv) {
-            const double half = (lu - lv) * 0.5;
-            const double d = half < a ? half : a;
-            lu = lu - d;
-            x = a - d;
-            lv = lv + d;
-        } else {
-            const double half = (lv - lu) * 0.5;
-            const double d = half < b ? half : b;
-            lu = lu + d;
-            x = (d == b) ? w : a + d;
-            lv = lv - d;
-        }
+        const double diff = lu - lv;
+        const bool down = diff > 0.0;                 // l_u > l_v: move from u to v
+        const double half = __builtin_fabs(diff) * 0.5;
+        const double cap = down ? a : b;
+        const double d = half < cap ? half : cap;
+        const double lu_dn = lu - d, lu_up = lu + d;
+        const double lv_dn = lv - d, lv_up = lv + d;
+        const double x_dn = a - d, x_up = a + d;
+        lu = down ? lu_dn : lu_up;
+        lv = down ? lv_up : lv_dn;
+        x = down ? x_dn : ((d == b) ? w : x_up);
+    }
+    // The same step written for a star: lc is the center's load, ll the
+    // leaf's, c_is_u tells whether the center is u = src.  With
+    // diff_c = lc - ll, u's excess is diff_c (center is u) or -diff_c (center
+    // is v, exact negation), so |diff_c| * 0.5 is the step's half, the move
+    // goes from u to v exactly when (c_is_u ? diff_c > 0 : diff_c < 0), and
+    // the center loses d exactly when (c_is_u ? diff_c > 0 : diff_c >= 0).
+    // Every operation equals one of step()'s, so the bits agree.
+    __device__ static inline void step_center(L &lc, L &ll, bool c_is_u, X &x, float wf) {
+        const double w = (double)wf;
+        const double a = x;
+        const double b = w - a;
+        const double diff = lc - ll;
+        const bool down = c_is_u ? (diff > 0.0) : (diff < 0.0);
+        const bool c_dec = c_is_u ? (diff > 0.0) : (diff >= 0.0);
+        const double half = __builtin_fabs(diff) * 0.5;
+        const double cap = down ? a : b;
+        const double d = half < cap ? half : cap;
+        const double lc_dn = lc - d, lc_up = lc + d;
+        const double ll_dn = ll - d, ll_up = ll + d;
+        lc = c_dec ? lc_dn : lc_up;
+        ll = c_dec ? ll_up : ll_dn;
+        x = down ? a - d : ((d == b) ? w : a + d);
     }
 };
 
@@ -72,19 +101,28 @@ struct StateF32K {
         const float a = x;
         const float b = w - a;
         const float diff = (lu.s - lv.s) + (lu.c - lv.c);
-        if (diff > 0.0f) {
-            const float half = diff * 0.5f;
-            const float d = half < a ? half : a;
-            add(lu, -d);
-            x = a - d;
-            add(lv, d);
-        } else {
-            const float half = -diff * 0.5f;
-            const float d = half < b ? half : b;
-            add(lu, d);
-            x = (d == b) ? w : a + d;
-            add(lv, -d);
-        }
+        const bool down = diff > 0.0f;
+        const float half = __builtin_fabsf(diff) * 0.5f;
+        const float cap = down ? a : b;
+        const float d = half < cap ? half : cap;
+        const float du = down ? -d : d;               // change of l_u
+        add(lu, du);
+        add(lv, -du);
+        x = down ? a - d : ((d == b) ? w : a + d);
+    }
+    __device__ static inline void step_center(L &lc, L &ll, bool c_is_u, X &x, float w) {
+        const float a = x;
+        const float b = w - a;
+        const float diff = (lc.s - ll.s) + (lc.c - ll.c);
+        const bool down = c_is_u ? (diff > 0.0f) : (diff < 0.0f);
+        const bool c_dec = c_is_u ? (diff > 0.0f) : (diff >= 0.0f);
+        const float half = __builtin_fabsf(diff) * 0.5f;
+        const float cap = down ? a : b;
+        const float d = half < cap ? half : cap;
+        const float dc = c_dec ? -d : d;              // change of the center's load
+        add(lc, dc);
+        add(ll, -dc);
+        x = down ? a - d : ((d == b) ? w : a + d);
     }
 };
 
@@ -94,13 +132,11 @@ struct SweepLaunch {
                        float *slot_w, hipStream_t s);
     void (*init_loads)(int32_t n, const int64_t *row_ptr, const uint32_t *inc, const float *w,
                        void *L, hipStream_t s);
-    void (*phase)(int32_t t0, int32_t t1, const int32_t *tile_center, const int64_t *tile_base,
-                  const int32_t *tile_depth, const uint32_t *slot_leaf, void *slot_x,
-                  const float *slot_w, void *L, hipStream_t s);
-    void (*tail)(int32_t nph, const int32_t *ph_tile_ptr, const int32_t *tile_center,
-                 const int64_t *tile_base, const int32_t *tile_depth, const uint32_t *slot_leaf,
-                 void *slot_x, const float *slot_w, const int32_t *tail_nodes, int32_t ntail,
-                 void *L, hipStream_t s);
+    void (*phase)(const PhaseDesc &d, const int32_t *tile_center, const uint32_t *slot_leaf,
+                  void *slot_x, const float *slot_w, void *L, hipStream_t s);
+    void (*tail)(int32_t nph, const PhaseDesc *descs, const int32_t *tile_center,
+                 const uint32_t *slot_leaf, void *slot_x, const float *slot_w,
+                 const int32_t *tail_nodes, int32_t ntail, void *L, hipStream_t s);
     void (*set_tail_lds)(size_t bytes);
     void (*loads_f64)(int32_t n, const int64_t *row_ptr, const uint32_t *inc,
                       const int64_t *edge_slot, const void *slot_x, const float *w, const void *L,
