@@ -195,9 +195,11 @@ lowd_status lowd_schedule_build(int32_t n, int64_t m, const int32_t *src, const 
 
 /*
  * lowd_solver_info -- sizes of the solver, for reports.
- *   info [host] int64[8] out: n, m, phases, phases run by whole-GPU launches,
- *        phases run inside one workgroup from LDS, nodes held in LDS by that
- *        workgroup, edges in those phases, state type.
+ *   info [host] int64[10] out: n, m, phases, phases run by whole-GPU
+ *        launches, phases run inside one workgroup with loads in global
+ *        memory, phases run inside one workgroup with loads in LDS, nodes
+ *        held in LDS, edges of the LDS phases, edges of the global-memory
+ *        single-workgroup phases, state type.
  */
 lowd_status lowd_solver_info(const lowd_solver *s, int64_t *info);
 

@@ -188,9 +188,10 @@ class Solver:
         return phase[:self.m], center[:self.m], int(P.value)
 
     def info(self) -> dict:
-        a = np.zeros(8, dtype=np.int64)
+        a = np.zeros(10, dtype=np.int64)
         _check(lib().lowd_solver_info(self._h, a.ctypes.data_as(C.c_void_p)))
-        keys = ["n", "m", "phases", "grid_phases", "lds_phases", "lds_nodes", "lds_edges", "state"]
+        keys = ["n", "m", "phases", "grid_phases", "mid_phases", "lds_phases", "lds_nodes",
+                "lds_edges", "mid_edges", "state"]
         return {k: int(v) for k, v in zip(keys, a)}
 
 
@@ -210,6 +211,34 @@ def solve(n: int, src, dst, w=None, state: str = "f64", star_max: int = 16, tol:
     ex["sweeps"] = sweeps
     ex["solver"] = sv
     return ex
+
+
+def batch_solve(graphs, sweeps: int, state: str = "f64", star_max: int = 16, stream=None,
+                return_loads: bool = True) -> dict:
+    """Many unweighted graphs (each with .n, .src, .dst in local ids) solved
+    in one persistent launch: `sweeps` sweeps each, then every graph's
+    densest set.  Returns per-graph num/den (int64 numpy), the concatenated
+    in_set and loads (device tensors) and node offsets."""
+    torch = _torch()
+    G = len(graphs)
+    node_ptr = np.zeros(G + 1, dtype=np.int64)
+    edge_ptr = np.zeros(G + 1, dtype=np.int64)
+    for i, g in enumerate(graphs):
+        node_ptr[i + 1] = node_ptr[i] + g.n
+        edge_ptr[i + 1] = edge_ptr[i] + g.src.size
+    src = torch.from_numpy(np.concatenate([g.src for g in graphs]).astype(np.int32)).cuda()
+    dst = torch.from_numpy(np.concatenate([g.dst for g in graphs]).astype(np.int32)).cuda()
+    N = int(node_ptr[-1])
+    in_set = torch.empty(N, dtype=torch.uint8, device=src.device)
+    num = torch.empty(G, dtype=torch.int64, device=src.device)
+    den = torch.empty(G, dtype=torch.int64, device=src.device)
+    load = torch.empty(N, dtype=torch.float64, device=src.device) if return_loads else None
+    _check(lib().lowd_batch_solve(G, node_ptr.ctypes.data_as(C.c_void_p),
+                                  edge_ptr.ctypes.data_as(C.c_void_p), _ptr(src), _ptr(dst),
+                                  _STATES[state], star_max, sweeps, _ptr(in_set), _ptr(num),
+                                  _ptr(den), _ptr(load), _stream(stream)))
+    return dict(num=num.cpu().numpy(), den=den.cpu().numpy(), in_set=in_set, load=load,
+                node_ptr=node_ptr, edge_ptr=edge_ptr)
 
 
 def schedule_build(n: int, src: np.ndarray, dst: np.ndarray, star_max: int = 16):

@@ -3,7 +3,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
+#include <atomic>
 #include <exception>
+#include <thread>
 #include <memory>
 #include <new>
 #include <string>
@@ -106,7 +109,7 @@ struct lowd_solver {
     Csr csr;
     // schedule layout
     DBuf<int32_t> tile_center, tail_nodes;
-    DBuf<PhaseDesc> tail_desc;
+    DBuf<PhaseDesc> tail_desc, mid_desc;
     DBuf<int64_t> slot_edge, edge_slot;
     DBuf<uint32_t> slot_leaf;
     // state
@@ -145,7 +148,7 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
     return guarded([&] {
         if (!out) fail(LOWD_E_ARG, "out is NULL");
         *out = nullptr;
-        if (n < 1) fail(LOWD_E_ARG, "n must be >= 1");
+        if (n < 1 || n > 0x7FFFFFFD) fail(LOWD_E_ARG, "n must be in [1, 2^31 - 3]");
         if (m < 0 || m >= ((int64_t)1 << 31)) fail(LOWD_E_ARG, "m must be in [0, 2^31)");
         if (m > 0 && (!src || !dst)) fail(LOWD_E_ARG, "src/dst is NULL");
         if (state != LOWD_STATE_F64 && state != LOWD_STATE_F32K) fail(LOWD_E_ARG, "bad state");
@@ -169,10 +172,11 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
             LOWD_HIP(hipStreamSynchronize(s));
         }
         const int64_t lds = (int64_t)lds_capacity_bytes();
-        int64_t force = -1;
-        if (const char *e = getenv("LOWD_TAIL_SPLIT")) force = atoll(e);
-        build_schedule(n, m, hs.data(), hd.data(), star_max, lds, (int64_t)sv->fn.l_bytes, force,
-                       sv->sch);
+        int64_t force0 = -1, force1 = -1;
+        if (const char *e = getenv("LOWD_TAIL_SPLIT")) force0 = atoll(e);
+        if (const char *e = getenv("LOWD_MID_SPLIT")) force1 = atoll(e);
+        build_schedule(n, m, hs.data(), hd.data(), star_max, lds, (int64_t)sv->fn.l_bytes, force0,
+                       force1, sv->sch);
         const Schedule &sc = sv->sch;
 
         // device copies of the graph, incidence rows
@@ -197,6 +201,8 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
         upload(sv->edge_slot, sc.edge_slot, s);
         std::vector<PhaseDesc> tdesc(sc.desc.begin() + sc.P0, sc.desc.end());
         upload(sv->tail_desc, tdesc, s);
+        std::vector<PhaseDesc> mdesc(sc.desc.begin() + sc.P1, sc.desc.begin() + sc.P0);
+        upload(sv->mid_desc, mdesc, s);
         upload(sv->tail_nodes, sc.tail_nodes, s);
         sv->ntail = (int32_t)sc.tail_nodes.size();
 
@@ -204,7 +210,8 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
         const int64_t nslots = (int64_t)sc.slot_leaf.size();
         sv->slot_x.alloc((size_t)nslots * sv->fn.x_bytes);
         if (sv->weighted) sv->slot_w.alloc((size_t)nslots);
-        sv->L.alloc(((size_t)n + 1) * sv->fn.l_bytes);   // [n] = dummy center of empty lanes
+        // [n]: zero dummy center of empty lanes; [n+1]: infinite dummy leaf of padding
+        sv->L.alloc(((size_t)n + 2) * sv->fn.l_bytes);
         sv->L64.alloc((size_t)n);
         sv->stats_partial.alloc(3 * 1024);
         sv->stats_out.alloc(3);
@@ -214,16 +221,20 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
         // LDS-resident workgroup for the last phases
         if (sc.P > 0) {
             size_t tail_lds =
-                tail_desc_bytes(sc.P - sc.P0) + ((size_t)sv->ntail + 1) * sv->fn.l_bytes;
+                tail_desc_bytes(sc.P - sc.P0) + ((size_t)sv->ntail + 2) * sv->fn.l_bytes;
             if (sc.P0 < sc.P) sv->fn.set_tail_lds(tail_lds);
+            if (sc.P1 < sc.P0) sv->fn.set_mid_lds(tail_desc_bytes(sc.P0 - sc.P1));
             hipStream_t cs;
             LOWD_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
             hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             if (err == hipSuccess) {
-                for (int32_t p = 0; p < sc.P0; ++p)
+                for (int32_t p = 0; p < sc.P1; ++p)
                     sv->fn.phase(sc.desc[(size_t)p], sv->tile_center.p, sv->slot_leaf.p,
                                  sv->slot_x.p, sv->weighted ? sv->slot_w.p : nullptr, sv->L.p,
                                  cs);
+                if (sc.P1 < sc.P0)
+                    sv->fn.mid(sc.P0 - sc.P1, sv->mid_desc.p, sv->tile_center.p, sv->slot_leaf.p,
+                               sv->slot_x.p, sv->weighted ? sv->slot_w.p : nullptr, sv->L.p, cs);
                 if (sc.P0 < sc.P)
                     sv->fn.tail(sc.P - sc.P0, sv->tail_desc.p, sv->tile_center.p,
                                 sv->slot_leaf.p, sv->slot_x.p,
@@ -352,7 +363,7 @@ lowd_status lowd_schedule_build(int32_t n, int64_t m, const int32_t *src, const 
             if (src[e] < 0 || src[e] >= n || dst[e] < 0 || dst[e] >= n || src[e] == dst[e])
                 fail(LOWD_E_GRAPH, "invalid edge at index " + std::to_string(e));
         Schedule sc;
-        build_schedule(n, m, src, dst, star_max, 0, 0, -2, sc);
+        build_schedule(n, m, src, dst, star_max, 0, 0, -2, -1, sc);
         if (phase && m > 0) memcpy(phase, sc.phase.data(), (size_t)m * 4);
         if (center && m > 0) memcpy(center, sc.center.data(), (size_t)m * 4);
         if (nphases) *nphases = sc.P;
@@ -362,14 +373,18 @@ lowd_status lowd_schedule_build(int32_t n, int64_t m, const int32_t *src, const 
 lowd_status lowd_solver_info(const lowd_solver *sv, int64_t *info) {
     return guarded([&] {
         if (!sv || !info) fail(LOWD_E_ARG, "NULL argument");
+        int64_t mid_edges = 0;
+        for (int32_t p = sv->sch.P1; p < sv->sch.P0; ++p) mid_edges += sv->sch.phase_edges[(size_t)p];
         info[0] = sv->n;
         info[1] = sv->m;
         info[2] = sv->sch.P;
-        info[3] = sv->sch.P0;
-        info[4] = sv->sch.P - sv->sch.P0;
-        info[5] = sv->ntail;
-        info[6] = sv->sch.tail_edges;
-        info[7] = sv->state;
+        info[3] = sv->sch.P1;
+        info[4] = sv->sch.P0 - sv->sch.P1;
+        info[5] = sv->sch.P - sv->sch.P0;
+        info[6] = sv->ntail;
+        info[7] = sv->sch.tail_edges;
+        info[8] = mid_edges;
+        info[9] = sv->state;
     });
 }
 
@@ -402,10 +417,187 @@ lowd_status lowd_batch_solve(int32_t G, const int64_t *node_ptr, const int64_t *
                              const int32_t *src, const int32_t *dst, int32_t state,
                              int32_t star_max, int32_t sweeps, uint8_t *in_set, int64_t *num,
                              int64_t *den, double *load, void *stream) {
-    (void)G; (void)node_ptr; (void)edge_ptr; (void)src; (void)dst; (void)state; (void)star_max;
-    (void)sweeps; (void)in_set; (void)num; (void)den; (void)load; (void)stream;
-    g_last_error = "lowd_batch_solve is not built yet";
-    return LOWD_E_UNSUPPORTED;
+    return guarded([&] {
+        if (G < 1 || !node_ptr || !edge_ptr) fail(LOWD_E_ARG, "G >= 1 and node_ptr/edge_ptr needed");
+        if (state != LOWD_STATE_F64 && state != LOWD_STATE_F32K) fail(LOWD_E_ARG, "bad state");
+        if (star_max < 1 || star_max > kMaxStar) fail(LOWD_E_ARG, "star_max must be in [1, 16]");
+        if (sweeps < 0) fail(LOWD_E_ARG, "sweeps must be >= 0");
+        if (!in_set || !num || !den) fail(LOWD_E_ARG, "in_set/num/den is NULL");
+        if (node_ptr[0] != 0 || edge_ptr[0] != 0) fail(LOWD_E_ARG, "node_ptr[0], edge_ptr[0] must be 0");
+        for (int32_t g = 0; g < G; ++g) {
+            if (node_ptr[g + 1] - node_ptr[g] < 1) fail(LOWD_E_ARG, "every graph needs a node");
+            if (edge_ptr[g + 1] < edge_ptr[g]) fail(LOWD_E_ARG, "edge_ptr must not decrease");
+        }
+        const int64_t N = node_ptr[G], M = edge_ptr[G];
+        if (N > 0x7FFFFFFD || M >= ((int64_t)1 << 31)) fail(LOWD_E_ARG, "batch too large");
+        if (M > 0 && (!src || !dst)) fail(LOWD_E_ARG, "src/dst is NULL");
+        hipStream_t s = (hipStream_t)stream;
+        SweepLaunch fn{};
+        get_sweep_launchers(state, false, fn);
+
+        std::vector<int32_t> hs((size_t)M), hd((size_t)M);
+        if (M > 0) {
+            LOWD_HIP(hipMemcpyAsync(hs.data(), src, (size_t)M * 4, hipMemcpyDeviceToHost, s));
+            LOWD_HIP(hipMemcpyAsync(hd.data(), dst, (size_t)M * 4, hipMemcpyDeviceToHost, s));
+            LOWD_HIP(hipStreamSynchronize(s));
+        }
+        std::vector<int32_t> gsrc((size_t)M), gdst((size_t)M), node_graph((size_t)N);
+        for (int32_t g = 0; g < G; ++g) {
+            const int64_t ng = node_ptr[g + 1] - node_ptr[g];
+            for (int64_t u = node_ptr[g]; u < node_ptr[g + 1]; ++u) node_graph[(size_t)u] = g;
+            for (int64_t e = edge_ptr[g]; e < edge_ptr[g + 1]; ++e) {
+                const int32_t a = hs[(size_t)e], b = hd[(size_t)e];
+                if (a < 0 || a >= ng || b < 0 || b >= ng || a == b)
+                    fail(LOWD_E_GRAPH, "invalid edge " + std::to_string(e) + " of graph " +
+                                           std::to_string(g) + ": (" + std::to_string(a) + ", " +
+                                           std::to_string(b) + "), n = " + std::to_string(ng));
+                gsrc[(size_t)e] = a + (int32_t)node_ptr[g];
+                gdst[(size_t)e] = b + (int32_t)node_ptr[g];
+            }
+        }
+        DBuf<int32_t> d_gsrc, d_gdst, d_node_graph;
+        upload(d_gsrc, gsrc, s);
+        upload(d_gdst, gdst, s);
+        upload(d_node_graph, node_graph, s);
+        {
+            int64_t b = find_duplicate_pair((int32_t)N, M, d_gsrc.p, d_gdst.p, s);
+            if (b >= 0) fail(LOWD_E_GRAPH, "repeated pair at edge " + std::to_string(b));
+        }
+
+        // per-graph schedules (every phase from LDS), built in parallel
+        const int64_t lds = (int64_t)lds_capacity_bytes() - 64;
+        std::vector<Schedule> sch((size_t)G);
+        {
+            std::atomic<int32_t> next(0);
+            std::atomic<int32_t> bad(-1);
+            unsigned nt = std::thread::hardware_concurrency();
+            if (nt < 1) nt = 1;
+            if (nt > 16) nt = 16;
+            std::vector<std::thread> pool;
+            std::vector<std::string> errs(nt);
+            for (unsigned t = 0; t < nt; ++t)
+                pool.emplace_back([&, t] {
+                    try {
+                        for (int32_t g = next++; g < G; g = next++) {
+                            const int64_t e0 = edge_ptr[g];
+                            build_schedule((int32_t)(node_ptr[g + 1] - node_ptr[g]),
+                                           edge_ptr[g + 1] - e0, hs.data() + e0, hd.data() + e0,
+                                           star_max, lds, (int64_t)fn.l_bytes, 0, 0,
+                                           sch[(size_t)g], true);
+                        }
+                    } catch (const Error &e) {
+                        errs[t] = e.msg;
+                        bad = 1;
+                    } catch (...) {
+                        errs[t] = "schedule failed";
+                        bad = 1;
+                    }
+                });
+            for (auto &th : pool) th.join();
+            if (bad >= 0)
+                for (auto &e : errs)
+                    if (!e.empty()) fail(LOWD_E_ARG, e);
+        }
+        // concatenate the layouts; check that every graph fits one workgroup's LDS
+        std::vector<PhaseDesc> descs;
+        std::vector<int32_t> tile_center;
+        std::vector<uint32_t> slot_leaf;
+        std::vector<int64_t> slot_edge, desc_ptr((size_t)G + 1, 0);
+        size_t lds_need = 0;
+        for (int32_t g = 0; g < G; ++g) {
+            const Schedule &sc = sch[(size_t)g];
+            const int64_t ng = node_ptr[g + 1] - node_ptr[g];
+            const size_t need = tail_desc_bytes(sc.P) + (size_t)(ng + 2) * fn.l_bytes;
+            if ((int64_t)need > lds)
+                fail(LOWD_E_UNSUPPORTED, "graph " + std::to_string(g) + " (" + std::to_string(ng) +
+                                             " nodes, " + std::to_string(sc.P) +
+                                             " phases) does not fit one workgroup's LDS");
+            if (need > lds_need) lds_need = need;
+            const int64_t slot0 = (int64_t)slot_leaf.size();
+            const int32_t tile0 = (int32_t)(tile_center.size() / kWave);
+            for (PhaseDesc d : sc.desc) {
+                d.slot_base += slot0;
+                d.tile0 += tile0;
+                descs.push_back(d);
+            }
+            desc_ptr[(size_t)g + 1] = (int64_t)descs.size();
+            tile_center.insert(tile_center.end(), sc.tile_center.begin(), sc.tile_center.end());
+            slot_leaf.insert(slot_leaf.end(), sc.slot_leaf.begin(), sc.slot_leaf.end());
+            for (int64_t e : sc.slot_edge) slot_edge.push_back(e >= 0 ? e + edge_ptr[g] : -1);
+        }
+        std::vector<int32_t> order((size_t)G);
+        for (int32_t g = 0; g < G; ++g) order[(size_t)g] = g;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+            return edge_ptr[a + 1] - edge_ptr[a] > edge_ptr[b + 1] - edge_ptr[b];
+        });
+        std::vector<int64_t> hnode(node_ptr, node_ptr + G + 1), hedge(edge_ptr, edge_ptr + G + 1);
+        DBuf<int64_t> d_node_ptr, d_edge_ptr, d_desc_ptr, d_slot_edge;
+        DBuf<int32_t> d_order, d_tile_center;
+        DBuf<PhaseDesc> d_descs;
+        DBuf<uint32_t> d_slot_leaf;
+        upload(d_node_ptr, hnode, s);
+        upload(d_edge_ptr, hedge, s);
+        upload(d_desc_ptr, desc_ptr, s);
+        upload(d_slot_edge, slot_edge, s);
+        upload(d_order, order, s);
+        upload(d_tile_center, tile_center, s);
+        upload(d_descs, descs, s);
+        upload(d_slot_leaf, slot_leaf, s);
+        const int64_t nslots = (int64_t)slot_leaf.size();
+        DBuf<char> slot_x((size_t)(nslots > 0 ? nslots : 1) * fn.x_bytes);
+        DBuf<double> Lout((size_t)N);
+        DBuf<unsigned> queue(1);
+        if (nslots > 0) fn.init_slots(nslots, d_slot_edge.p, nullptr, slot_x.p, nullptr, s);
+
+        // one persistent launch, captured in a HIP graph
+        int dev = 0, cus = 0;
+        LOWD_HIP(hipGetDevice(&dev));
+        LOWD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        const size_t per_cu = 160 * 1024;
+        int32_t per = (int32_t)(per_cu / (lds_need + 64));
+        if (per < 1) per = 1;
+        if (per > 4) per = 4;
+        int32_t blocks = cus * per;
+        if (blocks > G) blocks = G;
+        fn.set_batch_lds(lds_need);
+        hipStream_t cs;
+        LOWD_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (err == hipSuccess) {
+            fn.batch(G, d_order.p, queue.p, d_node_ptr.p, d_edge_ptr.p, src, dst, d_desc_ptr.p,
+                     d_descs.p, d_tile_center.p, d_slot_leaf.p, slot_x.p, sweeps, Lout.p,
+                     lds_need, blocks, cs);
+            err = hipStreamEndCapture(cs, &graph);
+        }
+        (void)hipStreamDestroy(cs);
+        LOWD_HIP(err);
+        err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (err == hipSuccess) err = hipGraphLaunch(exec, s);
+        if (err == hipSuccess) err = hipStreamSynchronize(s);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        LOWD_HIP(err);
+
+        BatchExtractArgs a;
+        a.G = G;
+        a.N = N;
+        a.M = M;
+        a.node_ptr = d_node_ptr.p;
+        a.node_graph = d_node_graph.p;
+        a.gsrc = d_gsrc.p;
+        a.gdst = d_gdst.p;
+        a.L64 = Lout.p;
+        a.in_set = in_set;
+        a.num = num;
+        a.den = den;
+        launch_extract_batch(a, s);
+        if (load)
+            LOWD_HIP(hipMemcpyAsync(load, Lout.p, (size_t)N * sizeof(double),
+                                    hipMemcpyDeviceToDevice, s));
+        LOWD_HIP(hipStreamSynchronize(s));
+    });
 }
 
 }  // extern "C"

@@ -37,4 +37,21 @@ struct ExtractScratch {
 // unweighted graphs, FP64 bits otherwise).
 void launch_extract(const ExtractArgs &a, ExtractScratch &sc, hipStream_t s);
 
+// Extraction for many unweighted graphs whose nodes and edges are
+// concatenated (global node ids); synchronises the stream.
+struct BatchExtractArgs {
+    int32_t G = 0;
+    int64_t N = 0;                     // total nodes
+    int64_t M = 0;                     // total edges
+    const int64_t *node_ptr = nullptr; // [G+1] device
+    const int32_t *node_graph = nullptr; // [N] graph of each node
+    const int32_t *gsrc = nullptr;     // [M] global node ids
+    const int32_t *gdst = nullptr;
+    const double *L64 = nullptr;       // [N]
+    uint8_t *in_set = nullptr;         // [N] out
+    int64_t *num = nullptr;            // [G] out
+    int64_t *den = nullptr;            // [G] out
+};
+void launch_extract_batch(const BatchExtractArgs &a, hipStream_t s);
+
 }  // namespace lowd

@@ -223,3 +223,129 @@ void launch_extract(const ExtractArgs &a, ExtractScratch &sc, hipStream_t s) {
 }
 
 }  // namespace lowd
+
+// ------------------------------------------------ batched extraction -----
+// The same extraction for many graphs at once (unweighted): one stable sort
+// of all loads, then a stable sort by graph id, gives every graph's
+// ascending order as one contiguous segment; positions, the W(S_i) suffix
+// sums and the densest prefix are then taken per segment.
+namespace lowd {
+namespace {
+
+__global__ void k_graph_keys(int64_t N, const uint32_t *vals, const int32_t *node_graph,
+                             uint32_t *keys2) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < N;
+         k += (int64_t)gridDim.x * blockDim.x)
+        keys2[k] = (uint32_t)node_graph[vals[k]];
+}
+
+__global__ void k_local_positions(int64_t N, const uint32_t *asc, const int32_t *node_graph,
+                                  const int64_t *node_ptr, int32_t *pos) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < N;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t u = asc[k];
+        pos[u] = (int32_t)(k - node_ptr[node_graph[u]]);
+    }
+}
+
+__global__ void k_edge_min_pos_batch(int64_t M, const int32_t *gsrc, const int32_t *gdst,
+                                     const int32_t *node_graph, const int64_t *node_ptr,
+                                     const int32_t *pos, unsigned long long *hist) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < M;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t u = gsrc[e], v = gdst[e];
+        const int32_t a = pos[u], b = pos[v];
+        atomicAdd(&hist[node_ptr[node_graph[u]] + (a < b ? a : b)], 1ull);
+    }
+}
+
+// one block per graph: first index of maximal density W_g[i] / (n_g - i)
+__global__ void __launch_bounds__(kArgBlock) k_best_batch(int32_t G, const int64_t *node_ptr,
+                                                          int64_t N, const int64_t *W,
+                                                          int64_t *best, int64_t *num,
+                                                          int64_t *den) {
+    __shared__ int64_t lds_i[kArgBlock];
+    __shared__ int64_t lds_w[kArgBlock];
+    const int32_t g = blockIdx.x;
+    const int64_t start = node_ptr[g], end = node_ptr[g + 1];
+    const int64_t n = end - start;
+    const int64_t tail = end < N ? W[end] : 0;
+    int64_t bi = -1, bw = 0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const int64_t wi = W[start + i] - tail;
+        // wi / (n - i) > bw / (n - bi), exact in int64
+        if (bi < 0 || wi * (n - bi) > bw * (n - i)) { bi = i; bw = wi; }
+    }
+    lds_i[threadIdx.x] = bi;
+    lds_w[threadIdx.x] = bw;
+    __syncthreads();
+    for (int s = kArgBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const int64_t oi = lds_i[threadIdx.x + s], ow = lds_w[threadIdx.x + s];
+            const int64_t ci = lds_i[threadIdx.x], cw = lds_w[threadIdx.x];
+            bool take;
+            if (oi < 0) take = false;
+            else if (ci < 0) take = true;
+            else {
+                const int64_t a = ow * (n - ci), b = cw * (n - oi);
+                take = a > b || (a == b && oi < ci);
+            }
+            if (take) { lds_i[threadIdx.x] = oi; lds_w[threadIdx.x] = ow; }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        best[g] = lds_i[0];
+        num[g] = lds_w[0];
+        den[g] = n - lds_i[0];
+    }
+}
+
+__global__ void k_in_set_batch(int64_t N, const int32_t *pos, const int32_t *node_graph,
+                               const int64_t *best, uint8_t *in_set) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < N;
+         u += (int64_t)gridDim.x * blockDim.x)
+        in_set[u] = pos[u] >= best[node_graph[u]] ? 1 : 0;
+}
+
+}  // namespace
+
+void launch_extract_batch(const BatchExtractArgs &a, hipStream_t s) {
+    const int64_t N = a.N;
+    int gbits = 1;
+    while (gbits < 31 && ((int64_t)1 << gbits) < (int64_t)a.G) ++gbits;
+    DBuf<uint64_t> k0((size_t)N), k1((size_t)N);
+    DBuf<uint32_t> v0((size_t)N), v1((size_t)N), g0((size_t)N), g1((size_t)N);
+    DBuf<int32_t> pos((size_t)N);
+    DBuf<int64_t> hist((size_t)N), rev((size_t)N), W((size_t)N), best((size_t)a.G);
+    size_t tb = radix_sort_tmp_bytes(N), tb2 = exclusive_scan_tmp_bytes(N);
+    DBuf<char> tmp(tb > tb2 ? tb : tb2);
+    const unsigned gn = grid_for(N, 256);
+    hipLaunchKernelGGL(k_keys, dim3(gn), dim3(256), 0, s, (int32_t)N, a.L64, k0.p, v0.p);
+    bool alt = false;
+    radix_sort_u64(k0.p, v0.p, k1.p, v1.p, N, 64, tmp.p, tmp.bytes(), &alt, s);
+    uint32_t *vals = alt ? v1.p : v0.p;
+    uint32_t *vals_alt = alt ? v0.p : v1.p;
+    hipLaunchKernelGGL(k_graph_keys, dim3(gn), dim3(256), 0, s, N, vals, a.node_graph, g0.p);
+    bool alt2 = false;
+    radix_sort_u32(g0.p, vals, g1.p, vals_alt, N, gbits, tmp.p, tmp.bytes(), &alt2, s);
+    const uint32_t *asc = alt2 ? vals_alt : vals;
+    hipLaunchKernelGGL(k_local_positions, dim3(gn), dim3(256), 0, s, N, asc, a.node_graph,
+                       a.node_ptr, pos.p);
+    hipLaunchKernelGGL(k_fill_i64, dim3(gn), dim3(256), 0, s, N, hist.p);
+    if (a.M > 0)
+        hipLaunchKernelGGL(k_edge_min_pos_batch, dim3(grid_for(a.M, 256)), dim3(256), 0, s, a.M,
+                           a.gsrc, a.gdst, a.node_graph, a.node_ptr, pos.p,
+                           (unsigned long long *)hist.p);
+    hipLaunchKernelGGL(k_reverse<int64_t>, dim3(gn), dim3(256), 0, s, N, hist.p, rev.p);
+    exclusive_scan_i64(rev.p, rev.p, N, nullptr, tmp.p, tmp.bytes(), s);
+    hipLaunchKernelGGL(k_suffix<int64_t>, dim3(gn), dim3(256), 0, s, N, rev.p, hist.p, W.p);
+    hipLaunchKernelGGL(k_best_batch, dim3((unsigned)a.G), dim3(kArgBlock), 0, s, a.G, a.node_ptr,
+                       N, W.p, best.p, a.num, a.den);
+    hipLaunchKernelGGL(k_in_set_batch, dim3(gn), dim3(256), 0, s, N, pos.p, a.node_graph, best.p,
+                       a.in_set);
+    LOWD_HIP(hipGetLastError());
+    LOWD_HIP(hipStreamSynchronize(s));   // scratch is released on return
+}
+
+}  // namespace lowd

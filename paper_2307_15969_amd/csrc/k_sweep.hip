@@ -22,18 +22,24 @@ __global__ void k_init_slots(int64_t nslots, const int64_t *slot_edge, const flo
          s += (int64_t)gridDim.x * blockDim.x) {
         int64_t e = slot_edge[s];
         float we = (kWeighted && e >= 0) ? w[e] : 1.0f;
-        slot_x[s] = St::half_weight(we);
+        // a padding slot holds its whole weight (1): its step is a no-op
+        slot_x[s] = e >= 0 ? St::half_weight(we) : (typename St::X)1.0f;
         if (kWeighted) slot_w[s] = we;
     }
 }
 
 // l_u = sum of w_e / 2 over the edges at u, in ascending edge index; entry
-// n (the dummy center of lanes without a star) is set to zero
+// n (the dummy center of lanes without a star) is zero and entry n+1 (the
+// dummy leaf of padding rows) is +infinity
 template <class St, bool kWeighted>
 __global__ void k_init_loads(int32_t n, const int64_t *row_ptr, const uint32_t *inc,
                              const float *w, typename St::L *L) {
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u <= n;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u <= n + 1;
          u += (int64_t)gridDim.x * blockDim.x) {
+        if (u == n + 1) {
+            L[u] = St::infinite();
+            continue;
+        }
         double acc = 0.0;
         if (u < n) {
             if (kWeighted) {
@@ -92,48 +98,31 @@ __device__ __forceinline__ void load_tile(Tile<St, kWeighted> &tl, const PhaseDe
             tl.enc[k] = pl[k * kWave];
             tl.x[k] = px[k * kWave];
             tl.w[k] = kWeighted ? pw[k * kWave] : 1.0f;
-        } else {
-            tl.enc[k] = kLeafPad;
         }
     }
 }
 
-// Branch-free per lane: a padding row (the lane's star is shorter than the
-// tile) reads and rewrites the lane's own center, and its step result is
-// discarded by a select; the center is written last.  A lane without a star
-// has the dummy node (index n, or the tail's last LDS entry) as its center.
+// Branch-free per lane.  A padding row (the lane's star is shorter than the
+// tile) names the "infinite" dummy leaf with fraction equal to its weight:
+// there the step moves d = min(inf, 0) = 0, an exact no-op for the center.
+// A lane without a star has the zero dummy as its center and only padding.
 template <class St, bool kWeighted, class LPtr>
 __device__ __forceinline__ void run_tile(Tile<St, kWeighted> &tl, int lane,
                                          typename St::X *__restrict__ slot_x, LPtr L) {
     typename St::L Lc = L[tl.c];
     typename St::L Ll[kMaxStar];
-    int32_t at[kMaxStar];
 #pragma unroll
-    for (int k = 0; k < kMaxStar; ++k) {
-        if (k < tl.depth) {
-            at[k] = (tl.enc[k] != kLeafPad) ? (int32_t)(tl.enc[k] & ~kCenterIsDst) : tl.c;
-            Ll[k] = L[at[k]];
-        }
-    }
+    for (int k = 0; k < kMaxStar; ++k)
+        if (k < tl.depth) Ll[k] = L[tl.enc[k] & ~kCenterIsDst];
 #pragma unroll
-    for (int k = 0; k < kMaxStar; ++k) {
-        if (k < tl.depth) {
-            const bool live = tl.enc[k] != kLeafPad;
-            const bool c_is_u = !(tl.enc[k] & kCenterIsDst);   // u = src
-            typename St::L lc = Lc, ll = Ll[k];
-            typename St::X xx = tl.x[k];
-            St::step_center(lc, ll, c_is_u, xx, tl.w[k]);
-            Lc = live ? lc : Lc;
-            Ll[k] = live ? ll : Ll[k];
-            tl.x[k] = live ? xx : tl.x[k];
-        }
-    }
+    for (int k = 0; k < kMaxStar; ++k)
+        if (k < tl.depth) St::step_center(Lc, Ll[k], tl.enc[k] & kCenterIsDst, tl.x[k], tl.w[k]);
     typename St::X *px = slot_x + tl.base + lane;
 #pragma unroll
     for (int k = 0; k < kMaxStar; ++k) {
         if (k < tl.depth) {
             px[k * kWave] = tl.x[k];
-            L[at[k]] = Ll[k];
+            L[tl.enc[k] & ~kCenterIsDst] = Ll[k];
         }
     }
     L[tl.c] = Lc;
@@ -156,15 +145,23 @@ k_phase(PhaseDesc d, const int32_t *__restrict__ tile_center,
     run_tile(tl, lane, slot_x, L);
 }
 
-// ----------------------------------------- LDS-resident last phases ------
-// One workgroup runs the last phases with the loads of their nodes in LDS
-// and an LDS barrier between phases.  Wave w owns tile w of every phase and
-// keeps two tile buffers: while it runs phase p from one, the other already
-// receives phase p+1's leaf ids and fractions (they do not depend on phase
-// p; only the loads do, and those come from LDS after the barrier).  The
-// buffers alternate, so no register copy forces the prefetch to complete.
-// The phase descriptors are staged in LDS next to the loads.  The schedule
-// puts no phase with more tiles than the workgroup has waves in the tail.
+// ----------------------------------------- single-workgroup phases -------
+// The narrow phases after the whole-GPU ones run inside ONE workgroup, one
+// after another, separated by workgroup barriers instead of kernel
+// boundaries:
+//  * middle phases: the node loads stay in global memory; all accesses come
+//    from one CU, so they are coherent through its L1/L2 and a workgroup
+//    barrier orders them (one CU's random-access rate, about one cache line
+//    per clock, bounds this tier: it pays only for phases of a few hundred
+//    edges);
+//  * last phases: their nodes' loads are staged in LDS (with the tail's own
+//    dummy entries) and written back at the end; an LDS-only barrier orders
+//    them.
+// Wave w owns tiles w, w + W, ... of every phase.  Each wave keeps two tile
+// buffers: while it runs phase p from one, the other already receives its
+// first tile of phase p+1 (leaf ids and fractions do not depend on phase p;
+// only the loads do).  The buffers alternate, so no register copy forces
+// the prefetch to complete.  Phase descriptors are staged in LDS.
 constexpr int kTailBlock = 512;
 static_assert(kTailBlock / kWave == kTailWaves, "tail width");
 
@@ -194,50 +191,170 @@ __device__ __forceinline__ PhaseDesc desc_from_lds(const PhaseDesc *sd, int32_t 
     return d;
 }
 
-template <class St, bool kWeighted>
-__global__ void __launch_bounds__(kTailBlock)
-k_tail(int32_t nph, const PhaseDesc *__restrict__ descs, const int32_t *__restrict__ tile_center,
-       const uint32_t *__restrict__ slot_leaf, typename St::X *__restrict__ slot_x,
-       const float *__restrict__ slot_w, const int32_t *__restrict__ tail_nodes, int32_t ntail,
-       typename St::L *__restrict__ L) {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    PhaseDesc *sd = reinterpret_cast<PhaseDesc *>(lds_raw);
-    typename St::L *sL = reinterpret_cast<typename St::L *>(lds_raw + tail_desc_bytes(nph));
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    {   // stage descriptors (as 32-bit words) and loads
-        const int32_t *src = reinterpret_cast<const int32_t *>(descs);
-        int32_t *dst = reinterpret_cast<int32_t *>(sd);
-        const int32_t words = nph * (int32_t)(sizeof(PhaseDesc) / 4);
-        for (int32_t i = threadIdx.x; i < words; i += kTailBlock) dst[i] = src[i];
-        for (int32_t i = threadIdx.x; i < ntail; i += kTailBlock) sL[i] = L[tail_nodes[i]];
-        if (threadIdx.x == 0) sL[ntail] = St::from_f64(0.0);   // dummy center of empty lanes
+// Runs the wave's tiles of one phase: the first from the prefetched buffer,
+// any further ones (phase wider than the workgroup) loaded into that same
+// buffer afterwards.
+template <class St, bool kWeighted, class LPtr>
+__device__ __forceinline__ void serial_phase(Tile<St, kWeighted> &tl, const PhaseDesc &d, int wave,
+                                             int lane, const int32_t *__restrict__ tile_center,
+                                             const uint32_t *__restrict__ slot_leaf,
+                                             typename St::X *__restrict__ slot_x,
+                                             const float *__restrict__ slot_w, LPtr L) {
+    if (wave >= d.T[0]) return;
+    run_tile(tl, lane, slot_x, L);
+    for (int32_t t = wave + kTailWaves; t < d.T[0]; t += kTailWaves) {
+        load_tile(tl, d, t, lane, tile_center, slot_leaf, slot_x, slot_w);
+        run_tile(tl, lane, slot_x, L);
     }
-    lds_barrier();
+}
+
+template <bool kLds>
+__device__ __forceinline__ void serial_barrier() {
+    if (kLds) lds_barrier();
+    else __syncthreads();
+}
+
+// The phase loop of a single-workgroup tier: phases [0, nph) whose
+// descriptors are staged at sd, node loads at L (LDS or global).
+template <class St, bool kWeighted, bool kLds, class LPtr>
+__device__ __forceinline__ void run_phases(int32_t nph, const PhaseDesc *sd, int wave, int lane,
+                                           const int32_t *__restrict__ tile_center,
+                                           const uint32_t *__restrict__ slot_leaf,
+                                           typename St::X *__restrict__ slot_x,
+                                           const float *__restrict__ slot_w, LPtr L) {
+    if (nph <= 0) return;
     Tile<St, kWeighted> ta, tb;
     PhaseDesc da = desc_from_lds(sd, 0, lane), db;
-    ta.c = -1;
     if (wave < da.T[0]) load_tile(ta, da, wave, lane, tile_center, slot_leaf, slot_x, slot_w);
     for (int32_t p = 0; p < nph; p += 2) {
         const bool has_b = p + 1 < nph;
-        tb.c = -1;
         if (has_b) {
             db = desc_from_lds(sd, p + 1, lane);
             if (wave < db.T[0]) load_tile(tb, db, wave, lane, tile_center, slot_leaf, slot_x, slot_w);
         }
-        if (wave < da.T[0]) run_tile(ta, lane, slot_x, sL);
-        lds_barrier();
+        serial_phase(ta, da, wave, lane, tile_center, slot_leaf, slot_x, slot_w, L);
+        serial_barrier<kLds>();
         if (!has_b) break;
-        ta.c = -1;
         if (p + 2 < nph) {
             da = desc_from_lds(sd, p + 2, lane);
             if (wave < da.T[0]) load_tile(ta, da, wave, lane, tile_center, slot_leaf, slot_x, slot_w);
         }
-        if (wave < db.T[0]) run_tile(tb, lane, slot_x, sL);
-        lds_barrier();
+        serial_phase(tb, db, wave, lane, tile_center, slot_leaf, slot_x, slot_w, L);
+        serial_barrier<kLds>();
     }
-    for (int32_t i = threadIdx.x; i < ntail; i += kTailBlock) L[tail_nodes[i]] = sL[i];
 }
+
+__device__ __forceinline__ void stage_descs(int32_t nph, const PhaseDesc *descs, PhaseDesc *sd) {
+    const int32_t *src = reinterpret_cast<const int32_t *>(descs);
+    int32_t *dst = reinterpret_cast<int32_t *>(sd);
+    const int32_t words = nph * (int32_t)(sizeof(PhaseDesc) / 4);
+    for (int32_t i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+}
+
+template <class St, bool kWeighted, bool kLds>
+__global__ void __launch_bounds__(kTailBlock)
+k_serial(int32_t nph, const PhaseDesc *__restrict__ descs, const int32_t *__restrict__ tile_center,
+         const uint32_t *__restrict__ slot_leaf, typename St::X *__restrict__ slot_x,
+         const float *__restrict__ slot_w, const int32_t *__restrict__ tail_nodes, int32_t ntail,
+         typename St::L *__restrict__ Lg) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    PhaseDesc *sd = reinterpret_cast<PhaseDesc *>(lds_raw);
+    typename St::L *sL = reinterpret_cast<typename St::L *>(lds_raw + tail_desc_bytes(nph));
+    typename St::L *L = kLds ? sL : Lg;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    stage_descs(nph, descs, sd);
+    if (kLds) {
+        constexpr int U = 8;   // eight gathers in flight per thread
+        for (int32_t i0 = threadIdx.x; i0 < ntail; i0 += U * kTailBlock) {
+            typename St::L v[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const int32_t i = i0 + j * kTailBlock;
+                if (i < ntail) v[j] = Lg[tail_nodes[i]];
+            }
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const int32_t i = i0 + j * kTailBlock;
+                if (i < ntail) sL[i] = v[j];
+            }
+        }
+        if (threadIdx.x == 0) {
+            sL[ntail] = St::from_f64(0.0);      // dummy center of empty lanes
+            sL[ntail + 1] = St::infinite();     // dummy leaf of padding rows
+        }
+    }
+    __syncthreads();
+    run_phases<St, kWeighted, kLds>(nph, sd, wave, lane, tile_center, slot_leaf, slot_x, slot_w, L);
+    if (kLds) {
+        for (int32_t i = threadIdx.x; i < ntail; i += kTailBlock) Lg[tail_nodes[i]] = sL[i];
+    }
+}
+
+// ------------------------------------------------------- batched graphs --
+// Many independent unweighted graphs in one persistent launch: each
+// workgroup takes the next graph from a queue (graphs ordered by edge count,
+// largest first), builds its loads in LDS (deg / 2: a sum of halves, exact
+// in any order), runs `sweeps` sweeps of the graph's phases from LDS, and
+// writes the loads out.  Node ids of a graph are local (0..n_g-1); n_g and
+// n_g + 1 are its dummy entries.
+template <class St>
+__global__ void __launch_bounds__(kTailBlock)
+k_batch(int32_t G, const int32_t *__restrict__ order, unsigned *__restrict__ queue,
+        const int64_t *__restrict__ node_ptr, const int64_t *__restrict__ edge_ptr,
+        const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
+        const int64_t *__restrict__ desc_ptr, const PhaseDesc *__restrict__ descs,
+        const int32_t *__restrict__ tile_center, const uint32_t *__restrict__ slot_leaf,
+        typename St::X *__restrict__ slot_x, int32_t sweeps, double *__restrict__ Lout) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ int32_t s_graph;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const unsigned k = atomicAdd(queue, 1u);
+            s_graph = k < (unsigned)G ? order[k] : -1;
+        }
+        __syncthreads();
+        const int32_t g = s_graph;
+        if (g < 0) break;
+        const int32_t n = (int32_t)(node_ptr[g + 1] - node_ptr[g]);
+        const int64_t e0 = edge_ptr[g];
+        const int64_t m = edge_ptr[g + 1] - e0;
+        const int32_t nph = (int32_t)(desc_ptr[g + 1] - desc_ptr[g]);
+        PhaseDesc *sd = reinterpret_cast<PhaseDesc *>(lds_raw);
+        typename St::L *sL = reinterpret_cast<typename St::L *>(lds_raw + tail_desc_bytes(nph));
+        double *cnt = reinterpret_cast<double *>(sL);   // degree halves, then loads in place
+        stage_descs(nph, descs + desc_ptr[g], sd);
+        // init: each edge adds one half to both ends (kept in FP64 first)
+        for (int32_t u = threadIdx.x; u < n; u += kTailBlock) cnt[u] = 0.0;
+        __syncthreads();
+        for (int64_t e = threadIdx.x; e < m; e += kTailBlock) {
+            atomicAdd(&cnt[src[e0 + e]], 0.5);
+            atomicAdd(&cnt[dst[e0 + e]], 0.5);
+        }
+        __syncthreads();
+        static_assert(sizeof(typename St::L) == sizeof(double), "loads converted in place");
+        for (int32_t u = threadIdx.x; u < n; u += kTailBlock) {
+            const double v = cnt[u];
+            sL[u] = St::from_f64(v);
+        }
+        if (threadIdx.x == 0) {
+            sL[n] = St::from_f64(0.0);
+            sL[n + 1] = St::infinite();
+        }
+        __syncthreads();
+        for (int32_t t = 0; t < sweeps; ++t)
+            run_phases<St, false, true>(nph, sd, wave, lane, tile_center, slot_leaf, slot_x,
+                                        nullptr, sL);
+        __syncthreads();
+        const int64_t n0 = node_ptr[g];
+        for (int32_t u = threadIdx.x; u < n; u += kTailBlock) Lout[n0 + u] = St::to_f64(sL[u]);
+        __syncthreads();   // LDS reuse by the next graph
+    }
+}
+
+__global__ void k_zero_u32(unsigned *p) { *p = 0u; }
 
 // ------------------------------------------------------------ statistics --
 constexpr int kRedBlock = 256;
@@ -355,7 +472,7 @@ static void sweep_launchers(SweepLaunch &fn) {
     };
     fn.init_loads = [](int32_t n, const int64_t *row_ptr, const uint32_t *inc, const float *w,
                        void *L, hipStream_t s) {
-        hipLaunchKernelGGL((k_init_loads<St, kW>), dim3(grid_for((int64_t)n + 1, 256)), dim3(256), 0, s, n,
+        hipLaunchKernelGGL((k_init_loads<St, kW>), dim3(grid_for((int64_t)n + 2, 256)), dim3(256), 0, s, n,
                            row_ptr, inc, w, (typename St::L *)L);
     };
     fn.phase = [](const PhaseDesc &d, const int32_t *tile_center, const uint32_t *slot_leaf,
@@ -369,13 +486,25 @@ static void sweep_launchers(SweepLaunch &fn) {
     fn.tail = [](int32_t nph, const PhaseDesc *descs, const int32_t *tile_center,
                  const uint32_t *slot_leaf, void *slot_x, const float *slot_w,
                  const int32_t *tail_nodes, int32_t ntail, void *L, hipStream_t s) {
-        size_t lds = tail_desc_bytes(nph) + (size_t)(ntail + 1) * sizeof(typename St::L);
-        hipLaunchKernelGGL((k_tail<St, kW>), dim3(1), dim3(kTailBlock), lds, s, nph, descs,
+        size_t lds = tail_desc_bytes(nph) + (size_t)(ntail + 2) * sizeof(typename St::L);
+        hipLaunchKernelGGL((k_serial<St, kW, true>), dim3(1), dim3(kTailBlock), lds, s, nph, descs,
                            tile_center, slot_leaf, (typename St::X *)slot_x, slot_w, tail_nodes,
                            ntail, (typename St::L *)L);
     };
+    fn.mid = [](int32_t nph, const PhaseDesc *descs, const int32_t *tile_center,
+                const uint32_t *slot_leaf, void *slot_x, const float *slot_w, void *L,
+                hipStream_t s) {
+        size_t lds = tail_desc_bytes(nph);
+        hipLaunchKernelGGL((k_serial<St, kW, false>), dim3(1), dim3(kTailBlock), lds, s, nph,
+                           descs, tile_center, slot_leaf, (typename St::X *)slot_x, slot_w,
+                           nullptr, 0, (typename St::L *)L);
+    };
     fn.set_tail_lds = [](size_t bytes) {
-        LOWD_HIP(hipFuncSetAttribute((const void *)k_tail<St, kW>,
+        LOWD_HIP(hipFuncSetAttribute((const void *)k_serial<St, kW, true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    };
+    fn.set_mid_lds = [](size_t bytes) {
+        LOWD_HIP(hipFuncSetAttribute((const void *)k_serial<St, kW, false>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     };
     fn.loads_f64 = [](int32_t n, const int64_t *row_ptr, const uint32_t *inc,
@@ -397,6 +526,20 @@ static void sweep_launchers(SweepLaunch &fn) {
     fn.read_loads = [](int32_t n, const void *L, double *out, hipStream_t s) {
         hipLaunchKernelGGL((k_loads_to_f64<St>), dim3(grid_for(n, 256)), dim3(256), 0, s, n,
                            (const typename St::L *)L, out);
+    };
+    fn.batch = [](int32_t G, const int32_t *order, unsigned *queue, const int64_t *node_ptr,
+                  const int64_t *edge_ptr, const int32_t *src, const int32_t *dst,
+                  const int64_t *desc_ptr, const PhaseDesc *descs, const int32_t *tile_center,
+                  const uint32_t *slot_leaf, void *slot_x, int32_t sweeps, double *Lout,
+                  size_t lds, int32_t blocks, hipStream_t s) {
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, queue);
+        hipLaunchKernelGGL((k_batch<St>), dim3((unsigned)blocks), dim3(kTailBlock), lds, s, G,
+                           order, queue, node_ptr, edge_ptr, src, dst, desc_ptr, descs,
+                           tile_center, slot_leaf, (typename St::X *)slot_x, sweeps, Lout);
+    };
+    fn.set_batch_lds = [](size_t bytes) {
+        LOWD_HIP(hipFuncSetAttribute((const void *)k_batch<St>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     };
     fn.x_bytes = sizeof(typename St::X);
     fn.l_bytes = sizeof(typename St::L);

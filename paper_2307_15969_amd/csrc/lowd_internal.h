@@ -50,7 +50,8 @@ struct DBuf {
 
 // Slot encoding of a star leaf: bits 0..30 node id (global or LDS-local),
 // bit 31 set when the star's center is the edge's dst (so the leaf is src).
-constexpr uint32_t kLeafPad = 0xFFFFFFFFu;   // padding slot (no edge)
+// Padding slots name the infinite dummy node (n + 1, or the tail's second
+// dummy) with orientation bit 0.
 constexpr uint32_t kCenterIsDst = 0x80000000u;
 constexpr int kWave = 64;
 
@@ -86,10 +87,12 @@ struct Schedule {
     int32_t P = 0;                  // phases
     std::vector<int32_t> phase;     // per edge
     std::vector<int32_t> center;    // per edge (node id)
-    int32_t P0 = 0;                 // phases [0, P0) run as whole-GPU launches
+    int32_t P1 = 0;                 // phases [0, P1) run as whole-GPU launches
+    int32_t P0 = 0;                 // [P1, P0) in one workgroup, loads in global memory;
+                                    // [P0, P) in one workgroup, loads in LDS
     std::vector<PhaseDesc> desc;          // [P]
     std::vector<int32_t> tile_center;     // [ntiles*64] node id (local ids for tail tiles), -1 empty
-    std::vector<uint32_t> slot_leaf;      // [nslots] leaf | orientation, kLeafPad for padding
+    std::vector<uint32_t> slot_leaf;      // [nslots] leaf | orientation (padding: dummy leaf)
     std::vector<int64_t> slot_edge;       // [nslots] edge index, -1 for padding
     std::vector<int64_t> edge_slot;       // [m] slot of each edge
     std::vector<int32_t> tail_nodes;      // global ids of the nodes held in LDS by the tail
@@ -100,11 +103,16 @@ struct Schedule {
 
 // Builds the phase schedule (first fit over edges in ascending index) and
 // the tile layout.
-// lds_bytes bounds the tail's LDS (descriptors + node loads of l_bytes each;
-// 0 = no tail); force_p0 >= 0 asks for the split (moved later until the tail
-// fits); force_p0 == -2 computes the phase assignment only.
+// lds_bytes bounds the single-workgroup tiers' LDS (descriptors, and node
+// loads of l_bytes each for the last tier; 0 = whole-GPU launches only);
+// force_p0 / force_p1 >= 0 ask for the splits (P0 moved later until the tail
+// fits; P1 clamped to P0); force_p0 == -2 computes the phase assignment only.
+// whole_in_lds: every phase runs from LDS with node ids unchanged (all n
+// nodes staged; dummies n and n + 1) -- the batched form; the caller checks
+// that the graph fits.
 void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, int32_t smax,
-                    int64_t lds_bytes, int64_t l_bytes, int64_t force_p0, Schedule &out);
+                    int64_t lds_bytes, int64_t l_bytes, int64_t force_p0, int64_t force_p1,
+                    Schedule &out, bool whole_in_lds = false);
 
 // --------------------------------------------------------------- kernels --
 // Device-wide primitives (k_scan.hip)

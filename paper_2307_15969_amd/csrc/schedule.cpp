@@ -27,6 +27,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cmath>
 #include <numeric>
 #include <vector>
 
@@ -51,17 +52,21 @@ struct Bits {
 // its streamed bytes; a phase inside the LDS-resident workgroup costs a
 // barrier plus its longest star chain plus one CU's streaming time.
 struct CostModel {
-    double grid_fixed_us = 3.5;                  // boundary + two memory round trips
+    double grid_fixed_us = 6.5;                  // boundary + dependent memory round trips
     double grid_us_per_edge = 48.0 / 4.0e6;      // ~48 B per edge at ~4 TB/s
-    double tail_fixed_us = 0.4;                  // barrier + LDS gathers
-    double tail_us_per_depth = 0.03;             // one dependent step of the chain
-    double tail_us_per_edge = 24.0 / 1.0e5;      // ~24 B per edge at ~100 GB/s
+    double mid_fixed_us = 2.0;                   // barrier + gathers through one CU
+    double mid_us_per_round = 1.2;               // each further tile per wave (no prefetch)
+    double mid_us_per_edge = 0.0018;             // ~4 random cache lines per edge, one CU
+    double tail_fixed_us = 1.0;                  // barrier + LDS gathers
+    double us_per_depth = 0.06;                  // one dependent step of a star chain
+    double serial_us_per_edge = 24.0 / 1.0e5;    // ~24 B per edge at ~100 GB/s (one CU)
 };
 
 }  // namespace
 
 void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, int32_t smax,
-                    int64_t lds_bytes, int64_t l_bytes, int64_t force_p0, Schedule &out) {
+                    int64_t lds_bytes, int64_t l_bytes, int64_t force_p0, int64_t force_p1,
+                    Schedule &out, bool whole_in_lds) {
     out = Schedule();
     if (smax > kMaxStar && force_p0 != -2) {
         // the device layout holds stars of up to kMaxStar leaves; callers that
@@ -167,42 +172,77 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
         if (last[(size_t)u] >= 0) ++nodes_from[(size_t)last[(size_t)u]];
     for (int32_t p = P - 1; p >= 0; --p) nodes_from[(size_t)p] += nodes_from[(size_t)p + 1];
     CostModel cm;
-    // the tail [p0, P) fits when its descriptors and node loads fit in LDS
-    // the last phase with more tiles than the tail has waves bounds the split
+    // the tail [p0, P) fits when its descriptors and node loads fit in LDS,
+    // and no tail phase is wider than the workgroup
     int32_t min_p0 = 0;
     for (int32_t p = 0; p < P; ++p)
         if ((int64_t)stars[(size_t)p].size() > (int64_t)kTailWaves * kWave) min_p0 = p + 1;
     auto fits = [&](int32_t p0) {
         if (lds_bytes <= 0) return p0 >= P;
         if (p0 < min_p0) return false;
-        return (int64_t)tail_desc_bytes(P - p0) + (nodes_from[(size_t)p0] + 1) * l_bytes <= lds_bytes;
+        return (int64_t)tail_desc_bytes(P - p0) + (nodes_from[(size_t)p0] + 2) * l_bytes <= lds_bytes;
     };
-    int32_t P0 = P;
-    if (force_p0 >= 0) {
-        P0 = (int32_t)std::min<int64_t>(force_p0, P);
+    // the middle tier keeps only its descriptors in LDS
+    const int64_t max_mid = lds_bytes > 0 ? lds_bytes / (int64_t)sizeof(PhaseDesc) - 1 : 0;
+    std::vector<double> gpre((size_t)P + 1, 0.0), mpre((size_t)P + 1, 0.0), tsuf((size_t)P + 1, 0.0);
+    for (int32_t p = 0; p < P; ++p) {
+        const double tiles = (double)((stars[(size_t)p].size() + kWave - 1) / kWave);
+        const double rounds = std::ceil(tiles / kTailWaves);
+        gpre[(size_t)p + 1] = gpre[(size_t)p] + cm.grid_fixed_us +
+                              cm.grid_us_per_edge * (double)ecount[(size_t)p];
+        mpre[(size_t)p + 1] = mpre[(size_t)p] + cm.mid_fixed_us +
+                              cm.mid_us_per_round * (rounds > 1 ? rounds - 1 : 0) +
+                              cm.us_per_depth * (double)maxstar[(size_t)p] * rounds +
+                              cm.mid_us_per_edge * (double)ecount[(size_t)p];
+    }
+    for (int32_t p = P - 1; p >= 0; --p)
+        tsuf[(size_t)p] = tsuf[(size_t)p + 1] + cm.tail_fixed_us +
+                          cm.us_per_depth * (double)maxstar[(size_t)p] +
+                          cm.serial_us_per_edge * (double)ecount[(size_t)p];
+    // best P1 <= p0 for the middle tier: min over p1 of gpre[p1] - mpre[p1]
+    auto best_p1 = [&](int32_t p0, double *cost) {
+        int32_t b = p0;
+        double bc = gpre[(size_t)p0] - mpre[(size_t)p0];
+        for (int32_t p1 = p0 - 1; p1 >= 0 && p0 - p1 <= max_mid; --p1) {
+            const double c = gpre[(size_t)p1] - mpre[(size_t)p1];
+            if (c < bc) { bc = c; b = p1; }
+        }
+        *cost = bc + mpre[(size_t)p0];
+        return b;
+    };
+    int32_t P0 = P, P1 = P;
+    if (whole_in_lds) {
+        P0 = 0;
+        P1 = 0;
+    } else if (force_p0 >= 0 || force_p1 >= 0) {
+        P0 = (int32_t)std::min<int64_t>(force_p0 >= 0 ? force_p0 : P, P);
         while (P0 < P && !fits(P0)) ++P0;
+        P1 = (int32_t)std::min<int64_t>(force_p1 >= 0 ? force_p1 : P0, P0);
+        if (lds_bytes <= 0) P1 = P0;
+        if (P0 - P1 > max_mid) P1 = (int32_t)(P0 - max_mid);
     } else if (lds_bytes > 0 && P > 0) {
-        // cost(P0) = sum_{p<P0} grid(p) + sum_{p>=P0} tail(p)
-        std::vector<double> gpre((size_t)P + 1, 0.0), tsuf((size_t)P + 1, 0.0);
-        for (int32_t p = 0; p < P; ++p)
-            gpre[(size_t)p + 1] = gpre[(size_t)p] + cm.grid_fixed_us +
-                                  cm.grid_us_per_edge * (double)ecount[(size_t)p];
-        for (int32_t p = P - 1; p >= 0; --p)
-            tsuf[(size_t)p] = tsuf[(size_t)p + 1] + cm.tail_fixed_us +
-                              cm.tail_us_per_depth * (double)maxstar[(size_t)p] +
-                              cm.tail_us_per_edge * (double)ecount[(size_t)p];
-        double best = gpre[(size_t)P];
+        double c0;
+        P1 = best_p1(P, &c0);
+        double best = c0;
         for (int32_t p0 = P - 1; p0 >= 0; --p0) {
             if (!fits(p0)) break;   // fits(p0) implies fits(p0 + 1)
-            double c = gpre[(size_t)p0] + tsuf[(size_t)p0];
-            if (c < best) { best = c; P0 = p0; }
+            double c;
+            int32_t p1 = best_p1(p0, &c);
+            c += tsuf[(size_t)p0];
+            if (c < best) { best = c; P0 = p0; P1 = p1; }
         }
     }
+    out.P1 = P1;
     out.P0 = P0;
 
     // tail node ids (ascending) -> local index
     std::vector<int32_t> local((size_t)n, -1);
-    if (P0 < P) {
+    if (whole_in_lds) {
+        for (int32_t u = 0; u < n; ++u) {
+            local[(size_t)u] = u;
+            out.tail_nodes.push_back(u);
+        }
+    } else if (P0 < P) {
         for (int32_t u = 0; u < n; ++u)
             if (last[(size_t)u] >= P0) {
                 local[(size_t)u] = (int32_t)out.tail_nodes.size();
@@ -235,7 +275,7 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
     // lanes without a star get the dummy node: n (whole-GPU phases) or the
     // tail's LDS entry after its nodes
     out.tile_center.assign((size_t)ntiles * kWave, n);
-    out.slot_leaf.assign((size_t)nslots, kLeafPad);
+    out.slot_leaf.assign((size_t)nslots, (uint32_t)n + 1u);   // padding: the infinite dummy
     out.slot_edge.assign((size_t)nslots, -1);
     out.edge_slot.assign((size_t)m, -1);
     const int32_t ntail_nodes = (int32_t)out.tail_nodes.size();
@@ -243,9 +283,15 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
         const bool tail = p >= P0;
         if (tail) out.tail_edges += ecount[(size_t)p];
         if (tail) {
+            // tail dummies are the LDS entries after the tail's nodes
             const int64_t t = (int64_t)((stars[(size_t)p].size() + kWave - 1) / kWave);
             for (int64_t i = 0; i < t * kWave; ++i)
                 out.tile_center[(size_t)(out.desc[(size_t)p].tile0 * kWave + i)] = ntail_nodes;
+            const PhaseDesc &dd = out.desc[(size_t)p];
+            int64_t rows = 0;
+            for (int k = 0; k < kMaxStar; ++k) rows += dd.T[k];
+            for (int64_t i = 0; i < rows * kWave; ++i)
+                out.slot_leaf[(size_t)(dd.slot_base + i)] = (uint32_t)ntail_nodes + 1u;
         }
         const std::vector<Star> &st = stars[(size_t)p];
         const PhaseDesc &d = out.desc[(size_t)p];

@@ -27,6 +27,7 @@ struct StateF64 {
     using L = double;
     static constexpr bool kRecompute = false;
     __host__ __device__ static inline X half_weight(float w) { return (double)w / 2.0; }
+    __device__ static inline L infinite() { return __builtin_inf(); }
     __device__ static inline L from_f64(double v) { return v; }
     __device__ static inline double to_f64(L v) { return v; }
     __device__ static inline void step(L &lu, L &lv, X &x, float wf) {
@@ -45,28 +46,40 @@ struct StateF64 {
         lv = down ? lv_up : lv_dn;
         x = down ? x_dn : ((d == b) ? w : x_up);
     }
-    // The same step written for a star: lc is the center's load, ll the
-    // leaf's, c_is_u tells whether the center is u = src.  With
-    // diff_c = lc - ll, u's excess is diff_c (center is u) or -diff_c (center
-    // is v, exact negation), so |diff_c| * 0.5 is the step's half, the move
-    // goes from u to v exactly when (c_is_u ? diff_c > 0 : diff_c < 0), and
-    // the center loses d exactly when (c_is_u ? diff_c > 0 : diff_c >= 0).
-    // Every operation equals one of step()'s, so the bits agree.
-    __device__ static inline void step_center(L &lc, L &ll, bool c_is_u, X &x, float wf) {
+    // The same step written for a star, as the sweep kernels run it: lc is
+    // the center's load, ll the leaf's; flip = 0x80000000 when the center is
+    // v = dst (else 0).  u's excess over v is s = diff_c (center is u) or
+    // -diff_c (center is v; exact negation by the sign bit), so the move goes
+    // from u to v exactly when s > 0, its size is d = min(|s| * 0.5, cap),
+    // and the center loses d exactly when that direction and the center's
+    // role agree.  Only exact rewrites of step() are used: x - y == x + (-y);
+    // min picks one of its operands (none is NaN or -0 here); negation flips
+    // the sign bit.  So the bits agree with step().
+    __device__ static inline void step_center(L &lc, L &ll, uint32_t flip, X &x, float wf) {
         const double w = (double)wf;
         const double a = x;
         const double b = w - a;
         const double diff = lc - ll;
-        const bool down = c_is_u ? (diff > 0.0) : (diff < 0.0);
-        const bool c_dec = c_is_u ? (diff > 0.0) : (diff >= 0.0);
+        const double s = flip_sign(diff, flip);
+        const bool down = s > 0.0;
         const double half = __builtin_fabs(diff) * 0.5;
         const double cap = down ? a : b;
-        const double d = half < cap ? half : cap;
-        const double lc_dn = lc - d, lc_up = lc + d;
-        const double ll_dn = ll - d, ll_up = ll + d;
-        lc = c_dec ? lc_dn : lc_up;
-        ll = c_dec ? ll_up : ll_dn;
-        x = down ? a - d : ((d == b) ? w : a + d);
+        const double d = min_f64(half, cap);
+        const uint32_t sx = down ? 0x80000000u : 0u;      // x loses d when moving down
+        const double dc = flip_sign(d, sx ^ flip);         // the center loses d iff sx ^ flip
+        lc = lc + dc;
+        ll = ll - dc;
+        const double xs = a + flip_sign(d, sx);
+        x = (!down && d == b) ? w : xs;
+    }
+    __device__ static inline double flip_sign(double v, uint32_t bit) {
+        uint64_t u = __builtin_bit_cast(uint64_t, v) ^ ((uint64_t)bit << 32);
+        return __builtin_bit_cast(double, u);
+    }
+    __device__ static inline double min_f64(double p, double q) {
+        double r;
+        asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(p), "v"(q));
+        return r;
     }
 };
 
@@ -83,6 +96,7 @@ struct StateF32K {
     using L = LoadK32;
     static constexpr bool kRecompute = true;
     __host__ __device__ static inline X half_weight(float w) { return w * 0.5f; }
+    __device__ static inline L infinite() { return L{__builtin_inff(), 0.0f}; }
     __device__ static inline L from_f64(double v) {
         L r;
         r.s = (float)v;
@@ -110,19 +124,21 @@ struct StateF32K {
         add(lv, -du);
         x = down ? a - d : ((d == b) ? w : a + d);
     }
-    __device__ static inline void step_center(L &lc, L &ll, bool c_is_u, X &x, float w) {
+    __device__ static inline void step_center(L &lc, L &ll, uint32_t flip, X &x, float w) {
         const float a = x;
         const float b = w - a;
         const float diff = (lc.s - ll.s) + (lc.c - ll.c);
-        const bool down = c_is_u ? (diff > 0.0f) : (diff < 0.0f);
-        const bool c_dec = c_is_u ? (diff > 0.0f) : (diff >= 0.0f);
+        const float sdiff = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, diff) ^ flip);
+        const bool down = sdiff > 0.0f;
         const float half = __builtin_fabsf(diff) * 0.5f;
         const float cap = down ? a : b;
         const float d = half < cap ? half : cap;
-        const float dc = c_dec ? -d : d;              // change of the center's load
+        const uint32_t sx = down ? 0x80000000u : 0u;
+        const float dc = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, d) ^ sx ^ flip);
         add(lc, dc);
         add(ll, -dc);
-        x = down ? a - d : ((d == b) ? w : a + d);
+        const float xs = a + __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, d) ^ sx);
+        x = (!down && d == b) ? w : xs;
     }
 };
 
@@ -137,13 +153,23 @@ struct SweepLaunch {
     void (*tail)(int32_t nph, const PhaseDesc *descs, const int32_t *tile_center,
                  const uint32_t *slot_leaf, void *slot_x, const float *slot_w,
                  const int32_t *tail_nodes, int32_t ntail, void *L, hipStream_t s);
+    void (*mid)(int32_t nph, const PhaseDesc *descs, const int32_t *tile_center,
+                const uint32_t *slot_leaf, void *slot_x, const float *slot_w, void *L,
+                hipStream_t s);
     void (*set_tail_lds)(size_t bytes);
+    void (*set_mid_lds)(size_t bytes);
     void (*loads_f64)(int32_t n, const int64_t *row_ptr, const uint32_t *inc,
                       const int64_t *edge_slot, const void *slot_x, const float *w, const void *L,
                       double *L64, hipStream_t s);
     void (*read_x)(int64_t m, const int64_t *edge_slot, const void *slot_x, double *x,
                    hipStream_t s);
     void (*read_loads)(int32_t n, const void *L, double *out, hipStream_t s);
+    void (*batch)(int32_t G, const int32_t *order, unsigned *queue, const int64_t *node_ptr,
+                  const int64_t *edge_ptr, const int32_t *src, const int32_t *dst,
+                  const int64_t *desc_ptr, const PhaseDesc *descs, const int32_t *tile_center,
+                  const uint32_t *slot_leaf, void *slot_x, int32_t sweeps, double *Lout,
+                  size_t lds, int32_t blocks, hipStream_t s);
+    void (*set_batch_lds)(size_t bytes);
     size_t x_bytes;
     size_t l_bytes;
 };

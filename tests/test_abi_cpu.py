@@ -37,6 +37,7 @@ def test_argument_errors_need_no_device():
     # n < 1
     st = L.lowd_init_loads(0, 0, None, None, None, 0, 16, C.byref(h), None)
     assert st == -1 and b"n must be" in L.lowd_last_error()
+    assert L.lowd_init_loads(0x7FFFFFFE, 0, None, None, None, 0, 16, C.byref(h), None) == -1
     # bad state / star_max
     assert L.lowd_init_loads(5, 0, None, None, None, 7, 16, C.byref(h), None) == -1
     assert L.lowd_init_loads(5, 0, None, None, None, 0, 0, C.byref(h), None) == -1

@@ -27,13 +27,22 @@ def log(msg):
     print(msg, flush=True)
 
 
+SPLITS = {"auto": (None, None),            # cost model
+          "all_lds": (0, None),             # every phase that fits runs from LDS
+          "no_lds": (1 << 30, 1 << 30),     # whole-GPU launches only
+          "all_mid": (1 << 30, 0),          # every phase in one workgroup, loads in memory
+          "mid_lds": (None, 0)}             # middle tier then LDS tier
+
+
 @pytest.fixture
 def split(monkeypatch):
-    def _set(v):
-        if v is None:
-            monkeypatch.delenv("LOWD_TAIL_SPLIT", raising=False)
-        else:
-            monkeypatch.setenv("LOWD_TAIL_SPLIT", str(v))
+    def _set(name):
+        tail, mid = SPLITS[name]
+        for var, v in (("LOWD_TAIL_SPLIT", tail), ("LOWD_MID_SPLIT", mid)):
+            if v is None:
+                monkeypatch.delenv(var, raising=False)
+            else:
+                monkeypatch.setenv(var, str(v))
     return _set
 
 
@@ -74,17 +83,19 @@ def test_init_is_bit_exact(name, g):
     assert np.array_equal(L, Lo)
 
 
-@pytest.mark.parametrize("tail", [None, 0, 1 << 30], ids=["auto", "all_lds", "no_lds"])
+@pytest.mark.parametrize("tier", list(SPLITS))
 @pytest.mark.parametrize("smax", [1, 16])
 @pytest.mark.parametrize("name,g", GRAPHS, ids=[n for n, _ in GRAPHS])
-def test_sweeps_are_bit_exact(name, g, smax, tail, split):
-    split(tail)
-    log(f"sweeps {name} smax={smax} tail={tail}")
+def test_sweeps_are_bit_exact(name, g, smax, tier, split):
+    split(tier)
+    log(f"sweeps {name} smax={smax} tier={tier}")
     sv = lowd.Solver(g.n, g.src, g.dst, g.w, "f64", star_max=smax)
     info = sv.info()
     log(f"  info {info}")
-    if tail == 1 << 30:
-        assert info["lds_phases"] == 0
+    if tier == "no_lds":
+        assert info["lds_phases"] == 0 and info["mid_phases"] == 0
+    if tier == "all_mid":
+        assert info["grid_phases"] == 0 and info["lds_phases"] == 0
     T = 7
     # several launches of the sweep graph with eager work in between
     sv.iterate(1)
@@ -289,3 +300,51 @@ def test_chunglu_1m_10m_fp64_is_bit_exact():
     ro = oracle.extract(g.n, g.src, g.dst, None, Lo)
     assert (ex["num"], ex["den"]) == (ro["num"], ro["den"])
     assert np.array_equal(ex["in_set"].cpu().numpy(), ro["in_set"])
+
+
+# -------------------------------------------------------- batched form --
+def batch_graphs(count, seed):
+    gs = synth.batch_of_graphs(count, seed=seed, m_lo=20, m_hi=3000)
+    rng = np.random.default_rng(seed)
+    gs.append(synth.canonical(4, np.zeros(0, np.int64), np.zeros(0, np.int64)))   # no edges
+    gs.append(synth.random_small(rng, 9, 0.4))
+    gs.append(synth.workload(0))
+    return gs
+
+
+@pytest.mark.parametrize("T", [0, 1, 6])
+def test_batch_matches_single_graph_oracle(T):
+    """Each graph of the batch equals its own single-graph oracle run:
+    loads bit-exact (FP64), densest set and exact density equal."""
+    gs = batch_graphs(40, 3)
+    log(f"batch of {len(gs)} graphs, T={T}")
+    r = lowd.batch_solve(gs, T, "f64")
+    L = r["load"].cpu().numpy()
+    ins = r["in_set"].cpu().numpy()
+    for i, g in enumerate(gs):
+        a, b = r["node_ptr"][i], r["node_ptr"][i + 1]
+        xo, Lo, *_ = oracle_run(g, T, 16)
+        assert np.array_equal(L[a:b], Lo), i
+        ro = oracle.extract(g.n, g.src, g.dst, None, Lo)
+        assert (r["num"][i], r["den"][i]) == (ro["num"], ro["den"]), i
+        assert np.array_equal(ins[a:b], ro["in_set"]), i
+
+
+def test_batch_f32k_within_tolerance():
+    gs = batch_graphs(20, 5)
+    T = 30
+    r = lowd.batch_solve(gs, T, "f32k")
+    L = r["load"].cpu().numpy()
+    for i, g in enumerate(gs):
+        a, b = r["node_ptr"][i], r["node_ptr"][i + 1]
+        xo, Lo, *_ = oracle_run(g, T, 16)
+        if g.m:
+            assert np.max(np.abs(L[a:b] - Lo)) <= 1e-5 * np.max(np.abs(Lo)), i
+
+
+def test_batch_rejects_bad_graphs():
+    g = synth.canonical(5, np.array([0, 1]), np.array([1, 2]))
+    bad = synth.Graph(3, np.array([0, 1], np.int32), np.array([1, 5], np.int32), None)
+    with pytest.raises(lowd.LowdError) as ei:
+        lowd.batch_solve([g, bad], 1)
+    assert ei.value.status == -2
