@@ -68,6 +68,9 @@ def main():
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one plain device-to-device copy of this many MiB (a "
+                         "known-size kernel for scaling memory counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -81,6 +84,15 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.copy_calibration_mib > 0:
+        nbytes = args.copy_calibration_mib << 20
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: one copy of {nbytes} bytes", flush=True)
+        del a, b
     t0 = time.perf_counter()
     g = synth.workload(1, seed=args.seed)
     t_gen = time.perf_counter() - t0

@@ -100,9 +100,11 @@ int oracle_prune(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
  *   deg(u)  = number of edges at u;
  *   center  of edge e = the endpoint of larger degree, ties to the smaller id;
  *   leaf    = the other endpoint;
- *   edges are visited in ascending index; edge e goes to the smallest phase
- *   p in which its center is not a leaf and is the center of fewer than smax
- *   leaves, and its leaf does not appear at all.
+ *   demand(u) = number of edges whose leaf is u;
+ *   edges are visited by descending demand of their leaf, ties by ascending
+ *   index; edge e goes to the smallest phase p in which its center is not a
+ *   leaf and is the center of fewer than smax leaves, and its leaf does not
+ *   appear at all.
  * Sequential order: ascending (phase, edge index).
  *
  * Plain implementation: one byte per (node, phase):
@@ -110,6 +112,16 @@ int oracle_prune(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
  * phase_out[e], center_out[e] (the center node of e) and order_out[m] are
  * written; *nphases_out = number of phases.
  * ------------------------------------------------------------------------ */
+static const int64_t *g_sort_demand;
+static const int32_t *g_sort_leaf;
+static int cmp_demand_then_index(const void *pa, const void *pb)
+{
+    int64_t a = *(const int64_t *)pa, b = *(const int64_t *)pb;
+    int64_t da = g_sort_demand[g_sort_leaf[a]], db = g_sort_demand[g_sort_leaf[b]];
+    if (da != db) return da > db ? -1 : 1;   /* larger demand first */
+    return (a > b) - (a < b);
+}
+
 int oracle_schedule(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, int32_t smax,
                     int32_t *phase_out, int32_t *center_out, int32_t *order_out, int32_t *nphases_out)
 {
@@ -119,13 +131,30 @@ int oracle_schedule(int64_t n, int64_t m, const int32_t *src, const int32_t *dst
     int32_t *len = (int32_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
     if (!deg || !role || !len) { free(deg); free(role); free(len); return ORACLE_E_NOMEM; }
     for (int64_t e = 0; e < m; ++e) { ++deg[src[e]]; ++deg[dst[e]]; }
+    /* orientation and leaf demand */
+    int32_t *ctr = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    int32_t *lf = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    int64_t *demand = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    int64_t *visit = (int64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    if (!ctr || !lf || !demand || !visit) {
+        free(ctr); free(lf); free(demand); free(visit); free(deg); free(role); free(len);
+        return ORACLE_E_NOMEM;
+    }
+    for (int64_t e = 0; e < m; ++e) {
+        int32_t a = src[e], b = dst[e];
+        if (deg[a] > deg[b] || (deg[a] == deg[b] && a < b)) { ctr[e] = a; lf[e] = b; }
+        else { ctr[e] = b; lf[e] = a; }
+        ++demand[lf[e]];
+        visit[e] = e;
+    }
+    g_sort_demand = demand;
+    g_sort_leaf = lf;
+    qsort(visit, (size_t)m, sizeof(int64_t), cmp_demand_then_index);
     int32_t P = 0;
     int rc = ORACLE_OK;
-    for (int64_t e = 0; e < m && rc == ORACLE_OK; ++e) {
-        int32_t a = src[e], b = dst[e];
-        int32_t c, l;
-        if (deg[a] > deg[b] || (deg[a] == deg[b] && a < b)) { c = a; l = b; }
-        else { c = b; l = a; }
+    for (int64_t i = 0; i < m && rc == ORACLE_OK; ++i) {
+        const int64_t e = visit[i];
+        const int32_t c = ctr[e], l = lf[e];
         int32_t p = 0;
         for (;; ++p) {
             uint8_t rc_ = p < len[c] ? role[c][p] : 0;
@@ -156,6 +185,7 @@ int oracle_schedule(int64_t n, int64_t m, const int32_t *src, const int32_t *dst
     }
     for (int64_t u = 0; u < n; ++u) free(role[u]);
     free(role); free(len); free(deg);
+    free(ctr); free(lf); free(demand); free(visit);
     if (rc != ORACLE_OK) return rc;
     /* order: ascending (phase, edge index), by counting */
     if (order_out) {

@@ -9,9 +9,13 @@
 //
 // Definition (first fit):
 //   center of edge e = its endpoint of larger degree (ties: smaller id);
-//   edges are visited in ascending index; e goes to the first phase in which
-//   its center is not a leaf and has fewer than smax leaves, and its leaf
-//   does not appear at all.
+//   demand(u) = number of edges whose leaf is u;
+//   edges are visited by descending demand of their leaf (ties: ascending
+//   index); e goes to the first phase in which its center is not a leaf and
+//   has fewer than smax leaves, and its leaf does not appear at all.
+// Visiting the most constrained leaves first packs the phases tighter: a
+// node that is the leaf of k edges needs k phases, and placing its edges
+// early keeps them from being pushed behind everything else.
 // Sequential order: ascending (phase, edge index).
 //
 // Device layout: within a phase the stars are sorted by size (descending,
@@ -88,19 +92,36 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
     // ---- first fit --------------------------------------------------------
     // used[u]: phases where u has any role; noc[u]: phases where u cannot be
     // a center (it is a leaf there, or its star is full).
+    // orientation, leaf demand, visiting order (counting sort by demand,
+    // descending; stable, so ties keep ascending edge index)
+    std::vector<int32_t> ctr((size_t)m), lf((size_t)m);
+    std::vector<int64_t> demand((size_t)n, 0);
+    int64_t maxd = 0;
+    for (int64_t e = 0; e < m; ++e) {
+        const int32_t a = src[e], b = dst[e];
+        if (deg[(size_t)a] > deg[(size_t)b] || (deg[(size_t)a] == deg[(size_t)b] && a < b)) {
+            ctr[(size_t)e] = a;
+            lf[(size_t)e] = b;
+        } else {
+            ctr[(size_t)e] = b;
+            lf[(size_t)e] = a;
+        }
+        maxd = std::max(maxd, ++demand[(size_t)lf[(size_t)e]]);
+    }
+    std::vector<int64_t> visit((size_t)m);
+    {
+        std::vector<int64_t> start((size_t)maxd + 2, 0);   // by (maxd - demand)
+        for (int64_t e = 0; e < m; ++e) ++start[(size_t)(maxd - demand[(size_t)lf[(size_t)e]]) + 1];
+        for (int64_t k = 0; k <= maxd; ++k) start[(size_t)k + 1] += start[(size_t)k];
+        for (int64_t e = 0; e < m; ++e)
+            visit[(size_t)start[(size_t)(maxd - demand[(size_t)lf[(size_t)e]])]++] = e;
+    }
     std::vector<Bits> used((size_t)n), noc((size_t)n);
     std::vector<std::vector<uint8_t>> cnt((size_t)n);
     int32_t P = 0;
-    for (int64_t e = 0; e < m; ++e) {
-        int32_t a = src[e], b = dst[e];
-        int32_t c, l;
-        if (deg[(size_t)a] > deg[(size_t)b] || (deg[(size_t)a] == deg[(size_t)b] && a < b)) {
-            c = a;
-            l = b;
-        } else {
-            c = b;
-            l = a;
-        }
+    for (int64_t i = 0; i < m; ++i) {
+        const int64_t e = visit[(size_t)i];
+        const int32_t c = ctr[(size_t)e], l = lf[(size_t)e];
         const Bits &bc = noc[(size_t)c];
         const Bits &bl = used[(size_t)l];
         int32_t p = 0;

@@ -360,14 +360,23 @@ def test_schedule_phases_are_star_forests():
 
 
 def test_schedule_first_fit_is_minimal():
-    """Each edge sits in the first phase that admits it: moving it to any
+    """Each edge sits in the first phase that admits it when the edges are
+    visited by descending leaf demand (ties by index): moving it to any
     earlier phase would break the star-forest rule or the size limit."""
     rng = np.random.default_rng(2)
     g = synth.random_small(rng, 40, 0.3)
     smax = 3
     phase, center, order, P = oracle.schedule(g.n, g.src, g.dst, smax)
+    deg = np.bincount(g.src, minlength=g.n) + np.bincount(g.dst, minlength=g.n)
+    # the center is the endpoint of larger degree, ties to the smaller id
+    exp_c = np.where((deg[g.src] > deg[g.dst]) | ((deg[g.src] == deg[g.dst]) & (g.src < g.dst)),
+                     g.src, g.dst)
+    assert np.array_equal(center, exp_c)
+    leaf = np.where(center == g.src, g.dst, g.src)
+    demand = np.bincount(leaf, minlength=g.n)
+    visit = sorted(range(g.m), key=lambda e: (-demand[leaf[e]], e))
     role = {}
-    for e in range(g.m):
+    for e in visit:
         c = int(center[e])
         l = int(g.dst[e] if g.src[e] == c else g.src[e])
         for p in range(phase[e]):
