@@ -25,6 +25,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILE = os.path.join(ROOT, "profiles", "sweep_chunglu_1M_10M_f64.md")
+SWEEP_SOURCES = ["paper_2307_15969_amd/csrc/k_sweep.hip", "paper_2307_15969_amd/csrc/sweep_state.h",
+                 "paper_2307_15969_amd/csrc/schedule.cpp", "paper_2307_15969_amd/csrc/lowd_internal.h",
+                 "paper_2307_15969_amd/csrc/api.hip"]
+
+
+def profiled_traffic():
+    """HBM bytes per sweep from the committed FETCH_SIZE/WRITE_SIZE summary,
+    or None when the sweep sources changed since the counters were taken
+    (the summary records a hash of those sources)."""
+    import hashlib
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for p in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    fields = dict(l.split(": ", 1) for l in text.splitlines()
+                  if l.startswith(("traffic_bytes_per_sweep: ", "sources_sha256_16: ")))
+    if fields.get("sources_sha256_16", "").strip() != h.hexdigest()[:16]:
+        return None
+    return int(fields["traffic_bytes_per_sweep"])
 
 
 def sweep_bytes(n: int, m: int, x_bytes: int = 8, w_bytes: int = 0, l_bytes: int = 8) -> int:
@@ -179,7 +203,7 @@ def main():
         "setup_s": t_setup,
         "schedule": info,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(),
                      "kernel": "one sweep (the HIP graph of phase kernels + LDS tail kernel)",
                      "algorithmic_bytes": bytes_sweep},
     }
