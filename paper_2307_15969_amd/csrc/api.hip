@@ -111,9 +111,9 @@ struct lowd_solver {
     DBuf<int32_t> tile_center, tail_nodes;
     DBuf<PhaseDesc> tail_desc, mid_desc;
     DBuf<int64_t> slot_edge, edge_slot;
-    DBuf<uint32_t> slot_leaf;
-    // state
-    DBuf<char> slot_x, L;
+    DBuf<uint32_t> slot_leaf, slot_next, center_next, tail_next, home;
+    // state: fractions per slot, loads at their stations
+    DBuf<char> slot_x, E;
     DBuf<float> slot_w;
     DBuf<double> L64, stats_partial, stats_out;
     ExtractScratch ex;
@@ -132,7 +132,7 @@ static void reset_state(lowd_solver *sv, hipStream_t s) {
         sv->fn.init_slots(nslots, sv->slot_edge.p, sv->weighted ? sv->e_w.p : nullptr,
                           sv->slot_x.p, sv->weighted ? sv->slot_w.p : nullptr, s);
     sv->fn.init_loads(sv->n, sv->csr.row_ptr.p, sv->csr.inc.p, sv->weighted ? sv->e_w.p : nullptr,
-                      sv->L.p, s);
+                      sv->home.p, sv->sch.entries, sv->sch.center_base, sv->E.p, s);
     LOWD_HIP(hipGetLastError());
 }
 
@@ -204,14 +204,17 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
         std::vector<PhaseDesc> mdesc(sc.desc.begin() + sc.P1, sc.desc.begin() + sc.P0);
         upload(sv->mid_desc, mdesc, s);
         upload(sv->tail_nodes, sc.tail_nodes, s);
+        upload(sv->slot_next, sc.slot_next, s);
+        upload(sv->center_next, sc.center_next, s);
+        upload(sv->tail_next, sc.tail_next, s);
+        upload(sv->home, sc.home, s);
         sv->ntail = (int32_t)sc.tail_nodes.size();
 
         // state
         const int64_t nslots = (int64_t)sc.slot_leaf.size();
         sv->slot_x.alloc((size_t)nslots * sv->fn.x_bytes);
         if (sv->weighted) sv->slot_w.alloc((size_t)nslots);
-        // [n]: zero dummy center of empty lanes; [n+1]: infinite dummy leaf of padding
-        sv->L.alloc(((size_t)n + 2) * sv->fn.l_bytes);
+        sv->E.alloc((size_t)sc.entries * sv->fn.l_bytes);
         sv->L64.alloc((size_t)n);
         sv->stats_partial.alloc(3 * 1024);
         sv->stats_out.alloc(3);
@@ -228,18 +231,17 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
             LOWD_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
             hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             if (err == hipSuccess) {
+                const float *sw = sv->weighted ? sv->slot_w.p : nullptr;
                 for (int32_t p = 0; p < sc.P1; ++p)
-                    sv->fn.phase(sc.desc[(size_t)p], sv->tile_center.p, sv->slot_leaf.p,
-                                 sv->slot_x.p, sv->weighted ? sv->slot_w.p : nullptr, sv->L.p,
-                                 cs);
+                    sv->fn.phase(sc.desc[(size_t)p], sc.center_base, sv->center_next.p,
+                                 sv->slot_next.p, sv->slot_x.p, sw, sv->E.p, cs);
                 if (sc.P1 < sc.P0)
-                    sv->fn.mid(sc.P0 - sc.P1, sv->mid_desc.p, sv->tile_center.p, sv->slot_leaf.p,
-                               sv->slot_x.p, sv->weighted ? sv->slot_w.p : nullptr, sv->L.p, cs);
+                    sv->fn.mid(sc.P0 - sc.P1, sv->mid_desc.p, sc.center_base, sv->center_next.p,
+                               sv->slot_next.p, sv->slot_x.p, sw, sv->E.p, cs);
                 if (sc.P0 < sc.P)
                     sv->fn.tail(sc.P - sc.P0, sv->tail_desc.p, sv->tile_center.p,
-                                sv->slot_leaf.p, sv->slot_x.p,
-                                sv->weighted ? sv->slot_w.p : nullptr, sv->tail_nodes.p,
-                                sv->ntail, sv->L.p, cs);
+                                sv->slot_leaf.p, sv->slot_x.p, sw, sc.tail_base,
+                                sv->tail_next.p, sv->ntail, sv->E.p, cs);
                 err = hipStreamEndCapture(cs, &sv->graph);
             }
             (void)hipStreamDestroy(cs);
@@ -269,7 +271,7 @@ lowd_status lowd_iterate(lowd_solver *sv, int32_t sweeps, void *stream) {
 
 static void loads_f64(lowd_solver *sv, hipStream_t s) {
     sv->fn.loads_f64(sv->n, sv->csr.row_ptr.p, sv->csr.inc.p, sv->edge_slot.p, sv->slot_x.p,
-                     sv->weighted ? sv->e_w.p : nullptr, sv->L.p, sv->L64.p, s);
+                     sv->weighted ? sv->e_w.p : nullptr, sv->home.p, sv->E.p, sv->L64.p, s);
 }
 
 static void stats(lowd_solver *sv, double out[3], hipStream_t s) {
@@ -336,7 +338,7 @@ lowd_status lowd_read_state(const lowd_solver *sv, double *x, double *load, void
         if (!sv) fail(LOWD_E_ARG, "solver is NULL");
         hipStream_t s = (hipStream_t)stream;
         if (x && sv->m > 0) sv->fn.read_x(sv->m, sv->edge_slot.p, sv->slot_x.p, x, s);
-        if (load) sv->fn.read_loads(sv->n, sv->L.p, load, s);
+        if (load) sv->fn.read_loads(sv->n, sv->home.p, sv->E.p, load, s);
         LOWD_HIP(hipGetLastError());
     });
 }

@@ -2,12 +2,18 @@
 // statistics.
 //
 // The sweep follows the phase schedule (schedule.cpp): one kernel per phase
-// for the wide phases; the narrow last phases run inside one workgroup that
-// keeps their nodes' loads in LDS.  Inside a phase every lane owns one star:
-// it keeps the center's load in a register, and walks the star's leaves in
-// order, applying Algorithm 1's locally optimal step to each edge.  The
-// stars of a phase share no node, so no atomics are needed and the result is
-// that of the sequential edge loop in schedule order.
+// for the wide phases, then narrower phases inside one workgroup, and the
+// narrow last phases inside one workgroup that keeps their nodes' loads in
+// LDS.  Inside a phase every lane owns one star: it keeps the center's load
+// in a register, and walks the star's leaves in order, applying Algorithm
+// 1's locally optimal step to each edge.  The stars of a phase share no
+// node, so no atomics are needed and the result is that of the sequential
+// edge loop in schedule order.
+//
+// Outside the LDS tier a node's load lives at its next station (see the
+// schedule): a phase reads the loads of its leaves and centers in slot
+// order, together with the fractions, and writes every updated load to the
+// node's next station, so no read of a phase waits for an address.
 #include "lowd_internal.h"
 #include "sweep_state.h"
 
@@ -28,29 +34,33 @@ __global__ void k_init_slots(int64_t nslots, const int64_t *slot_edge, const flo
     }
 }
 
-// l_u = sum of w_e / 2 over the edges at u, in ascending edge index; entry
-// n (the dummy center of lanes without a star) is zero and entry n+1 (the
-// dummy leaf of padding rows) is +infinity
+// Station entries before any load is placed: slot entries +infinity (the
+// load a padding row reads: its step is then a no-op), lane entries and the
+// rest zero (the center of a lane without a star).  Non-station entries keep
+// these values: no station names them as next.
+template <class St>
+__global__ void k_fill_entries(int64_t entries, int64_t center_base, typename St::L *E) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < entries;
+         i += (int64_t)gridDim.x * blockDim.x)
+        E[i] = i < center_base ? St::infinite() : St::from_f64(0.0);
+}
+
+// l_u = sum of w_e / 2 over the edges at u, in ascending edge index, placed
+// at u's first station
 template <class St, bool kWeighted>
 __global__ void k_init_loads(int32_t n, const int64_t *row_ptr, const uint32_t *inc,
-                             const float *w, typename St::L *L) {
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u <= n + 1;
+                             const float *w, const uint32_t *home, typename St::L *E) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
          u += (int64_t)gridDim.x * blockDim.x) {
-        if (u == n + 1) {
-            L[u] = St::infinite();
-            continue;
-        }
         double acc = 0.0;
-        if (u < n) {
-            if (kWeighted) {
-                for (int64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j)
-                    acc = acc + (double)w[inc[j] >> 1] / 2.0;
-            } else {
-                // a sum of halves is exact in any order: deg / 2
-                acc = (double)(row_ptr[u + 1] - row_ptr[u]) * 0.5;
-            }
+        if (kWeighted) {
+            for (int64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j)
+                acc = acc + (double)w[inc[j] >> 1] / 2.0;
+        } else {
+            // a sum of halves is exact in any order: deg / 2
+            acc = (double)(row_ptr[u + 1] - row_ptr[u]) * 0.5;
         }
-        L[u] = St::from_f64(acc);
+        E[home[u]] = St::from_f64(acc);
     }
 }
 
@@ -128,40 +138,133 @@ __device__ __forceinline__ void run_tile(Tile<St, kWeighted> &tl, int lane,
     L[tl.c] = Lc;
 }
 
+// ---------------------------------------------- one tile, station form --
+// The same tile for the phases outside the LDS tier: besides the fractions
+// the lane reads its center's load (the lane's own station entry) and its
+// leaves' loads (the slots' station entries) in slot order, plus where each
+// goes next.  Padding rows read +infinity and lanes without a star read a
+// zero center; neither is written back.
+template <class St, bool kWeighted>
+struct StationTile {
+    int32_t depth;        // wave-uniform
+    int64_t base;         // wave-uniform: first slot of the tile
+    int64_t lane_entry;   // the lane's center station
+    uint32_t cnext;
+    uint32_t nx[kMaxStar];
+    typename St::X x[kMaxStar];
+    float w[kMaxStar];
+    typename St::L lc;
+    typename St::L ll[kMaxStar];
+};
+
+// the parts that do not depend on the previous phase
+template <class St, bool kWeighted>
+__device__ __forceinline__ void load_static(StationTile<St, kWeighted> &tl, const PhaseDesc &d,
+                                            int32_t t, int lane, int64_t center_base,
+                                            const uint32_t *__restrict__ center_next,
+                                            const uint32_t *__restrict__ slot_next,
+                                            const typename St::X *__restrict__ slot_x,
+                                            const float *__restrict__ slot_w) {
+    int32_t depth = 0;
+    int64_t rows = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxStar; ++k) {
+        depth += (d.T[k] > t) ? 1 : 0;
+        rows += (int64_t)(d.T[k] < t ? d.T[k] : t);
+    }
+    tl.depth = __builtin_amdgcn_readfirstlane(depth);
+    const int64_t base = d.slot_base + rows * kWave;
+    tl.base = base;
+    const int64_t li = (int64_t)(d.tile0 + t) * kWave + lane;
+    tl.lane_entry = center_base + li;
+    tl.cnext = center_next[li];
+    const uint32_t *pn = slot_next + base + lane;
+    const typename St::X *px = slot_x + base + lane;
+    const float *pw = kWeighted ? slot_w + base + lane : nullptr;
+#pragma unroll
+    for (int k = 0; k < kMaxStar; ++k) {
+        if (k < tl.depth) {
+            tl.nx[k] = pn[k * kWave];
+            tl.x[k] = px[k * kWave];
+            tl.w[k] = kWeighted ? pw[k * kWave] : 1.0f;
+        }
+    }
+}
+
+// the loads, written by earlier phases
+template <class St, bool kWeighted>
+__device__ __forceinline__ void load_loads(StationTile<St, kWeighted> &tl, int lane,
+                                           const typename St::L *E) {
+    tl.lc = E[tl.lane_entry];
+    const typename St::L *pl = E + tl.base + lane;
+#pragma unroll
+    for (int k = 0; k < kMaxStar; ++k)
+        if (k < tl.depth) tl.ll[k] = pl[k * kWave];
+}
+
+template <class St, bool kWeighted>
+__device__ __forceinline__ void run_station_tile(StationTile<St, kWeighted> &tl, int lane,
+                                                 typename St::X *__restrict__ slot_x,
+                                                 typename St::L *E) {
+#pragma unroll
+    for (int k = 0; k < kMaxStar; ++k)
+        if (k < tl.depth) St::step_center(tl.lc, tl.ll[k], tl.nx[k] & kCenterIsDst, tl.x[k], tl.w[k]);
+    typename St::X *px = slot_x + tl.base + lane;
+#pragma unroll
+    for (int k = 0; k < kMaxStar; ++k) {
+        if (k < tl.depth) {
+            px[k * kWave] = tl.x[k];
+            const uint32_t nx = tl.nx[k] & ~kCenterIsDst;
+            if (nx != kNoStation) E[nx] = tl.ll[k];
+        }
+    }
+    if (tl.cnext != kNoStation) E[tl.cnext] = tl.lc;
+}
+
 // --------------------------------------------------- whole-GPU phase -----
-constexpr int kPhaseBlock = 64;    // one tile per block: spread over many CUs
+// One wave per block.  A narrow phase (few tiles) would leave most CUs idle
+// while each busy CU works through up to 16 x 64 random load and store
+// lines of its tile, bounded by the misses one CU keeps in flight; such a
+// phase is spread instead: a tile is shared by 2^spread waves, each running
+// 64 >> spread of its lanes (lanes outside the wave's share exit at once).
+constexpr int kPhaseBlock = 64;
+static_assert(kWave == 64, "lane shares assume 64-wide waves");
+constexpr int kMaxSpreadLog2 = 3;    // at least 8 lanes per wave
+constexpr int32_t kSpreadWaves = 256;  // spread until about one wave per CU
 
 template <class St, bool kWeighted>
 __global__ void __launch_bounds__(kPhaseBlock)
-k_phase(PhaseDesc d, const int32_t *__restrict__ tile_center,
-        const uint32_t *__restrict__ slot_leaf, typename St::X *__restrict__ slot_x,
-        const float *__restrict__ slot_w, typename St::L *__restrict__ L) {
+k_phase(PhaseDesc d, int32_t spread, int64_t center_base, const uint32_t *__restrict__ center_next,
+        const uint32_t *__restrict__ slot_next, typename St::X *__restrict__ slot_x,
+        const float *__restrict__ slot_w, typename St::L *__restrict__ E) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int32_t t = __builtin_amdgcn_readfirstlane(
-        (int32_t)(blockIdx.x * (kPhaseBlock / kWave) + threadIdx.x / kWave));
+    const int32_t t = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x >> spread));
     if (t >= d.T[0]) return;
-    Tile<St, kWeighted> tl;
-    load_tile(tl, d, t, lane, tile_center, slot_leaf, slot_x, slot_w);
-    run_tile(tl, lane, slot_x, L);
+    const int32_t share = (int32_t)(blockIdx.x & ((1u << spread) - 1));
+    if ((lane >> (6 - spread)) != share) return;
+    StationTile<St, kWeighted> tl;
+    load_static(tl, d, t, lane, center_base, center_next, slot_next, slot_x, slot_w);
+    load_loads(tl, lane, E);
+    run_station_tile(tl, lane, slot_x, E);
 }
 
 // ----------------------------------------- single-workgroup phases -------
 // The narrow phases after the whole-GPU ones run inside ONE workgroup, one
 // after another, separated by workgroup barriers instead of kernel
 // boundaries:
-//  * middle phases: the node loads stay in global memory; all accesses come
-//    from one CU, so they are coherent through its L1/L2 and a workgroup
-//    barrier orders them (one CU's random-access rate, about one cache line
-//    per clock, bounds this tier: it pays only for phases of a few hundred
-//    edges);
-//  * last phases: their nodes' loads are staged in LDS (with the tail's own
-//    dummy entries) and written back at the end; an LDS-only barrier orders
-//    them.
+//  * middle phases (k_mid): the loads stay at their stations in global
+//    memory; all accesses come from one CU, so they are coherent through its
+//    caches and a workgroup barrier orders them (one CU's memory rate bounds
+//    this tier: it pays only for phases of a few hundred edges);
+//  * last phases (k_tail): their nodes' loads are staged in LDS (with the
+//    tail's own dummy entries) and written back to their next stations at
+//    the end; an LDS-only barrier orders them.
 // Wave w owns tiles w, w + W, ... of every phase.  Each wave keeps two tile
 // buffers: while it runs phase p from one, the other already receives its
-// first tile of phase p+1 (leaf ids and fractions do not depend on phase p;
-// only the loads do).  The buffers alternate, so no register copy forces
-// the prefetch to complete.  Phase descriptors are staged in LDS.
+// first tile of phase p+1 (leaf ids, fractions and next stations do not
+// depend on phase p; only the loads do).  The buffers alternate, so no
+// register copy forces the prefetch to complete.  Phase descriptors are
+// staged in LDS.
 constexpr int kTailBlock = 512;
 static_assert(kTailBlock / kWave == kTailWaves, "tail width");
 
@@ -191,9 +294,16 @@ __device__ __forceinline__ PhaseDesc desc_from_lds(const PhaseDesc *sd, int32_t 
     return d;
 }
 
-// Runs the wave's tiles of one phase: the first from the prefetched buffer,
-// any further ones (phase wider than the workgroup) loaded into that same
-// buffer afterwards.
+__device__ __forceinline__ void stage_descs(int32_t nph, const PhaseDesc *descs, PhaseDesc *sd) {
+    const int32_t *src = reinterpret_cast<const int32_t *>(descs);
+    int32_t *dst = reinterpret_cast<int32_t *>(sd);
+    const int32_t words = nph * (int32_t)(sizeof(PhaseDesc) / 4);
+    for (int32_t i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+}
+
+// Runs the wave's tiles of one LDS-tier phase: the first from the
+// prefetched buffer, any further ones (phase wider than the workgroup)
+// loaded into that same buffer afterwards.
 template <class St, bool kWeighted, class LPtr>
 __device__ __forceinline__ void serial_phase(Tile<St, kWeighted> &tl, const PhaseDesc &d, int wave,
                                              int lane, const int32_t *__restrict__ tile_center,
@@ -208,15 +318,9 @@ __device__ __forceinline__ void serial_phase(Tile<St, kWeighted> &tl, const Phas
     }
 }
 
-template <bool kLds>
-__device__ __forceinline__ void serial_barrier() {
-    if (kLds) lds_barrier();
-    else __syncthreads();
-}
-
-// The phase loop of a single-workgroup tier: phases [0, nph) whose
-// descriptors are staged at sd, node loads at L (LDS or global).
-template <class St, bool kWeighted, bool kLds, class LPtr>
+// The phase loop of the LDS tier: phases [0, nph) whose descriptors are
+// staged at sd, node loads in LDS at L (local ids).
+template <class St, bool kWeighted, class LPtr>
 __device__ __forceinline__ void run_phases(int32_t nph, const PhaseDesc *sd, int wave, int lane,
                                            const int32_t *__restrict__ tile_center,
                                            const uint32_t *__restrict__ slot_leaf,
@@ -233,62 +337,96 @@ __device__ __forceinline__ void run_phases(int32_t nph, const PhaseDesc *sd, int
             if (wave < db.T[0]) load_tile(tb, db, wave, lane, tile_center, slot_leaf, slot_x, slot_w);
         }
         serial_phase(ta, da, wave, lane, tile_center, slot_leaf, slot_x, slot_w, L);
-        serial_barrier<kLds>();
+        lds_barrier();
         if (!has_b) break;
         if (p + 2 < nph) {
             da = desc_from_lds(sd, p + 2, lane);
             if (wave < da.T[0]) load_tile(ta, da, wave, lane, tile_center, slot_leaf, slot_x, slot_w);
         }
         serial_phase(tb, db, wave, lane, tile_center, slot_leaf, slot_x, slot_w, L);
-        serial_barrier<kLds>();
+        lds_barrier();
     }
 }
 
-__device__ __forceinline__ void stage_descs(int32_t nph, const PhaseDesc *descs, PhaseDesc *sd) {
-    const int32_t *src = reinterpret_cast<const int32_t *>(descs);
-    int32_t *dst = reinterpret_cast<int32_t *>(sd);
-    const int32_t words = nph * (int32_t)(sizeof(PhaseDesc) / 4);
-    for (int32_t i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+// One middle-tier phase for this wave: its first tile's static part is
+// already in tl; the loads are read now (after the previous barrier).
+template <class St, bool kWeighted>
+__device__ __forceinline__ void mid_phase(StationTile<St, kWeighted> &tl, const PhaseDesc &d,
+                                          int wave, int lane, int64_t center_base,
+                                          const uint32_t *__restrict__ center_next,
+                                          const uint32_t *__restrict__ slot_next,
+                                          typename St::X *__restrict__ slot_x,
+                                          const float *__restrict__ slot_w, typename St::L *E) {
+    if (wave >= d.T[0]) return;
+    load_loads(tl, lane, E);
+    run_station_tile(tl, lane, slot_x, E);
+    for (int32_t t = wave + kTailWaves; t < d.T[0]; t += kTailWaves) {
+        load_static(tl, d, t, lane, center_base, center_next, slot_next, slot_x, slot_w);
+        load_loads(tl, lane, E);
+        run_station_tile(tl, lane, slot_x, E);
+    }
 }
 
-template <class St, bool kWeighted, bool kLds>
+template <class St, bool kWeighted>
 __global__ void __launch_bounds__(kTailBlock)
-k_serial(int32_t nph, const PhaseDesc *__restrict__ descs, const int32_t *__restrict__ tile_center,
-         const uint32_t *__restrict__ slot_leaf, typename St::X *__restrict__ slot_x,
-         const float *__restrict__ slot_w, const int32_t *__restrict__ tail_nodes, int32_t ntail,
-         typename St::L *__restrict__ Lg) {
+k_mid(int32_t nph, const PhaseDesc *__restrict__ descs, int64_t center_base,
+      const uint32_t *__restrict__ center_next, const uint32_t *__restrict__ slot_next,
+      typename St::X *__restrict__ slot_x, const float *__restrict__ slot_w,
+      typename St::L *__restrict__ E) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     PhaseDesc *sd = reinterpret_cast<PhaseDesc *>(lds_raw);
-    typename St::L *sL = reinterpret_cast<typename St::L *>(lds_raw + tail_desc_bytes(nph));
-    typename St::L *L = kLds ? sL : Lg;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     stage_descs(nph, descs, sd);
-    if (kLds) {
-        constexpr int U = 8;   // eight gathers in flight per thread
-        for (int32_t i0 = threadIdx.x; i0 < ntail; i0 += U * kTailBlock) {
-            typename St::L v[U];
-#pragma unroll
-            for (int j = 0; j < U; ++j) {
-                const int32_t i = i0 + j * kTailBlock;
-                if (i < ntail) v[j] = Lg[tail_nodes[i]];
-            }
-#pragma unroll
-            for (int j = 0; j < U; ++j) {
-                const int32_t i = i0 + j * kTailBlock;
-                if (i < ntail) sL[i] = v[j];
-            }
+    __syncthreads();
+    if (nph <= 0) return;
+    StationTile<St, kWeighted> ta, tb;
+    PhaseDesc da = desc_from_lds(sd, 0, lane), db;
+    if (wave < da.T[0])
+        load_static(ta, da, wave, lane, center_base, center_next, slot_next, slot_x, slot_w);
+    for (int32_t p = 0; p < nph; p += 2) {
+        const bool has_b = p + 1 < nph;
+        if (has_b) {
+            db = desc_from_lds(sd, p + 1, lane);
+            if (wave < db.T[0])
+                load_static(tb, db, wave, lane, center_base, center_next, slot_next, slot_x, slot_w);
         }
-        if (threadIdx.x == 0) {
-            sL[ntail] = St::from_f64(0.0);      // dummy center of empty lanes
-            sL[ntail + 1] = St::infinite();     // dummy leaf of padding rows
+        mid_phase(ta, da, wave, lane, center_base, center_next, slot_next, slot_x, slot_w, E);
+        __syncthreads();
+        if (!has_b) break;
+        if (p + 2 < nph) {
+            da = desc_from_lds(sd, p + 2, lane);
+            if (wave < da.T[0])
+                load_static(ta, da, wave, lane, center_base, center_next, slot_next, slot_x, slot_w);
         }
+        mid_phase(tb, db, wave, lane, center_base, center_next, slot_next, slot_x, slot_w, E);
+        __syncthreads();
+    }
+}
+
+// The LDS tier: tail node j's load is read from its station tail_base + j,
+// and written at the end to its next station tail_next[j].
+template <class St, bool kWeighted>
+__global__ void __launch_bounds__(kTailBlock)
+k_tail(int32_t nph, const PhaseDesc *__restrict__ descs, const int32_t *__restrict__ tile_center,
+       const uint32_t *__restrict__ slot_leaf, typename St::X *__restrict__ slot_x,
+       const float *__restrict__ slot_w, int64_t tail_base, const uint32_t *__restrict__ tail_next,
+       int32_t ntail, typename St::L *__restrict__ E) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    PhaseDesc *sd = reinterpret_cast<PhaseDesc *>(lds_raw);
+    typename St::L *sL = reinterpret_cast<typename St::L *>(lds_raw + tail_desc_bytes(nph));
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    stage_descs(nph, descs, sd);
+    for (int32_t i = threadIdx.x; i < ntail; i += kTailBlock) sL[i] = E[tail_base + i];
+    if (threadIdx.x == 0) {
+        sL[ntail] = St::from_f64(0.0);      // dummy center of empty lanes
+        sL[ntail + 1] = St::infinite();     // dummy leaf of padding rows
     }
     __syncthreads();
-    run_phases<St, kWeighted, kLds>(nph, sd, wave, lane, tile_center, slot_leaf, slot_x, slot_w, L);
-    if (kLds) {
-        for (int32_t i = threadIdx.x; i < ntail; i += kTailBlock) Lg[tail_nodes[i]] = sL[i];
-    }
+    run_phases<St, kWeighted>(nph, sd, wave, lane, tile_center, slot_leaf, slot_x, slot_w, sL);
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < ntail; i += kTailBlock) E[tail_next[i]] = sL[i];
 }
 
 // ------------------------------------------------------- batched graphs --
@@ -345,8 +483,8 @@ k_batch(int32_t G, const int32_t *__restrict__ order, unsigned *__restrict__ que
         }
         __syncthreads();
         for (int32_t t = 0; t < sweeps; ++t)
-            run_phases<St, false, true>(nph, sd, wave, lane, tile_center, slot_leaf, slot_x,
-                                        nullptr, sL);
+            run_phases<St, false>(nph, sd, wave, lane, tile_center, slot_leaf, slot_x, nullptr,
+                                  sL);
         __syncthreads();
         const int64_t n0 = node_ptr[g];
         for (int32_t u = threadIdx.x; u < n; u += kTailBlock) Lout[n0 + u] = St::to_f64(sL[u]);
@@ -383,11 +521,13 @@ __global__ void __launch_bounds__(256) k_recompute(int32_t n, const int64_t *row
     }
 }
 
+// the current load of every node, read at its first station (between sweeps)
 template <class St>
-__global__ void k_loads_to_f64(int32_t n, const typename St::L *L, double *L64) {
+__global__ void k_loads_to_f64(int32_t n, const uint32_t *home, const typename St::L *E,
+                               double *L64) {
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
          u += (int64_t)gridDim.x * blockDim.x)
-        L64[u] = St::to_f64(L[u]);
+        L64[u] = St::to_f64(E[home[u]]);
 }
 
 __device__ inline void red3(double &mx, double &s, double &s2, double *lds) {
@@ -471,61 +611,69 @@ static void sweep_launchers(SweepLaunch &fn) {
                            nslots, slot_edge, w, (typename St::X *)slot_x, slot_w);
     };
     fn.init_loads = [](int32_t n, const int64_t *row_ptr, const uint32_t *inc, const float *w,
-                       void *L, hipStream_t s) {
-        hipLaunchKernelGGL((k_init_loads<St, kW>), dim3(grid_for((int64_t)n + 2, 256)), dim3(256), 0, s, n,
-                           row_ptr, inc, w, (typename St::L *)L);
+                       const uint32_t *home, int64_t entries, int64_t center_base, void *E,
+                       hipStream_t s) {
+        hipLaunchKernelGGL((k_fill_entries<St>), dim3(grid_for(entries, 256)), dim3(256), 0, s,
+                           entries, center_base, (typename St::L *)E);
+        hipLaunchKernelGGL((k_init_loads<St, kW>), dim3(grid_for((int64_t)n, 256)), dim3(256), 0, s,
+                           n, row_ptr, inc, w, home, (typename St::L *)E);
     };
-    fn.phase = [](const PhaseDesc &d, const int32_t *tile_center, const uint32_t *slot_leaf,
-                  void *slot_x, const float *slot_w, void *L, hipStream_t s) {
-        int32_t tiles = d.T[0];
-        unsigned blocks = (unsigned)((tiles + (kPhaseBlock / kWave) - 1) / (kPhaseBlock / kWave));
-        hipLaunchKernelGGL((k_phase<St, kW>), dim3(blocks), dim3(kPhaseBlock), 0, s, d,
-                           tile_center, slot_leaf, (typename St::X *)slot_x, slot_w,
-                           (typename St::L *)L);
+    fn.phase = [](const PhaseDesc &d, int64_t center_base, const uint32_t *center_next,
+                  const uint32_t *slot_next, void *slot_x, const float *slot_w, void *E,
+                  hipStream_t s) {
+        const int32_t tiles = d.T[0];
+        int32_t spread = 0;
+        while (spread < kMaxSpreadLog2 && ((int64_t)tiles << (spread + 1)) <= kSpreadWaves)
+            ++spread;
+        const unsigned blocks = (unsigned)((int64_t)tiles << spread);
+        hipLaunchKernelGGL((k_phase<St, kW>), dim3(blocks), dim3(kPhaseBlock), 0, s, d, spread,
+                           center_base, center_next, slot_next, (typename St::X *)slot_x, slot_w,
+                           (typename St::L *)E);
     };
     fn.tail = [](int32_t nph, const PhaseDesc *descs, const int32_t *tile_center,
-                 const uint32_t *slot_leaf, void *slot_x, const float *slot_w,
-                 const int32_t *tail_nodes, int32_t ntail, void *L, hipStream_t s) {
+                 const uint32_t *slot_leaf, void *slot_x, const float *slot_w, int64_t tail_base,
+                 const uint32_t *tail_next, int32_t ntail, void *E, hipStream_t s) {
         size_t lds = tail_desc_bytes(nph) + (size_t)(ntail + 2) * sizeof(typename St::L);
-        hipLaunchKernelGGL((k_serial<St, kW, true>), dim3(1), dim3(kTailBlock), lds, s, nph, descs,
-                           tile_center, slot_leaf, (typename St::X *)slot_x, slot_w, tail_nodes,
-                           ntail, (typename St::L *)L);
+        hipLaunchKernelGGL((k_tail<St, kW>), dim3(1), dim3(kTailBlock), lds, s, nph, descs,
+                           tile_center, slot_leaf, (typename St::X *)slot_x, slot_w, tail_base,
+                           tail_next, ntail, (typename St::L *)E);
     };
-    fn.mid = [](int32_t nph, const PhaseDesc *descs, const int32_t *tile_center,
-                const uint32_t *slot_leaf, void *slot_x, const float *slot_w, void *L,
-                hipStream_t s) {
+    fn.mid = [](int32_t nph, const PhaseDesc *descs, int64_t center_base,
+                const uint32_t *center_next, const uint32_t *slot_next, void *slot_x,
+                const float *slot_w, void *E, hipStream_t s) {
         size_t lds = tail_desc_bytes(nph);
-        hipLaunchKernelGGL((k_serial<St, kW, false>), dim3(1), dim3(kTailBlock), lds, s, nph,
-                           descs, tile_center, slot_leaf, (typename St::X *)slot_x, slot_w,
-                           nullptr, 0, (typename St::L *)L);
+        hipLaunchKernelGGL((k_mid<St, kW>), dim3(1), dim3(kTailBlock), lds, s, nph, descs,
+                           center_base, center_next, slot_next, (typename St::X *)slot_x, slot_w,
+                           (typename St::L *)E);
     };
     fn.set_tail_lds = [](size_t bytes) {
-        LOWD_HIP(hipFuncSetAttribute((const void *)k_serial<St, kW, true>,
+        LOWD_HIP(hipFuncSetAttribute((const void *)k_tail<St, kW>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     };
     fn.set_mid_lds = [](size_t bytes) {
-        LOWD_HIP(hipFuncSetAttribute((const void *)k_serial<St, kW, false>,
+        LOWD_HIP(hipFuncSetAttribute((const void *)k_mid<St, kW>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     };
     fn.loads_f64 = [](int32_t n, const int64_t *row_ptr, const uint32_t *inc,
-                      const int64_t *edge_slot, const void *slot_x, const float *w, const void *L,
-                      double *L64, hipStream_t s) {
+                      const int64_t *edge_slot, const void *slot_x, const float *w,
+                      const uint32_t *home, const void *E, double *L64, hipStream_t s) {
         if (St::kRecompute)
             hipLaunchKernelGGL((k_recompute<St, kW>), dim3(grid_for((int64_t)n * kWave, 256)),
                                dim3(256), 0, s, n, row_ptr, inc, edge_slot,
                                (const typename St::X *)slot_x, w, L64);
         else
             hipLaunchKernelGGL((k_loads_to_f64<St>), dim3(grid_for(n, 256)), dim3(256), 0, s, n,
-                               (const typename St::L *)L, L64);
+                               home, (const typename St::L *)E, L64);
     };
     fn.read_x = [](int64_t m, const int64_t *edge_slot, const void *slot_x, double *x,
                    hipStream_t s) {
         hipLaunchKernelGGL((k_read_x<St>), dim3(grid_for(m, 256)), dim3(256), 0, s, m, edge_slot,
                            (const typename St::X *)slot_x, x);
     };
-    fn.read_loads = [](int32_t n, const void *L, double *out, hipStream_t s) {
-        hipLaunchKernelGGL((k_loads_to_f64<St>), dim3(grid_for(n, 256)), dim3(256), 0, s, n,
-                           (const typename St::L *)L, out);
+    fn.read_loads = [](int32_t n, const uint32_t *home, const void *E, double *out,
+                       hipStream_t s) {
+        hipLaunchKernelGGL((k_loads_to_f64<St>), dim3(grid_for(n, 256)), dim3(256), 0, s, n, home,
+                           (const typename St::L *)E, out);
     };
     fn.batch = [](int32_t G, const int32_t *order, unsigned *queue, const int64_t *node_ptr,
                   const int64_t *edge_ptr, const int32_t *src, const int32_t *dst,

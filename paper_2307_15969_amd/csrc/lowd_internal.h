@@ -54,6 +54,9 @@ struct DBuf {
 // dummy) with orientation bit 0.
 constexpr uint32_t kCenterIsDst = 0x80000000u;
 constexpr int kWave = 64;
+// "no next station" (padding slots, lanes without a star); station entries
+// stay below it
+constexpr uint32_t kNoStation = 0x7FFFFFFFu;
 
 // ------------------------------------------------------------- schedule --
 // Stars of a phase are sorted by size (descending) and dealt to tiles of 64,
@@ -97,6 +100,20 @@ struct Schedule {
     std::vector<int64_t> edge_slot;       // [m] slot of each edge
     std::vector<int32_t> tail_nodes;      // global ids of the nodes held in LDS by the tail
     int64_t tail_edges = 0;
+    // Station layout of the node loads.  A node's load is kept at the place
+    // where the sweep uses it next: one entry per leaf slot and per tile
+    // lane of the phases before P0 (the slot's or the lane's own index, the
+    // lanes after the slots), one per node of the tail, and a home entry
+    // for nodes on no edge.  Each station names its node's next station in
+    // sweep order (the last one names the first), so a phase reads its loads
+    // in slot order and writes each updated load to where it is read next.
+    int64_t center_base = 0;              // entry of tile lane i: center_base + i
+    int64_t tail_base = 0;                // entry of tail node j: tail_base + j
+    int64_t entries = 0;                  // size of the entry array
+    std::vector<uint32_t> slot_next;      // [nslots] next station | orientation bit; padding: kNoStation
+    std::vector<uint32_t> center_next;    // [ntiles*64] next station of the lane's center; empty: kNoStation
+    std::vector<uint32_t> tail_next;      // [ntail] station after the tail (the node's first)
+    std::vector<uint32_t> home;           // [n] first station of each node
     std::vector<int64_t> phase_edges;     // [P]
     std::vector<int32_t> phase_depth;     // [P] deepest star
 };

@@ -300,6 +300,24 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
     out.slot_edge.assign((size_t)nslots, -1);
     out.edge_slot.assign((size_t)m, -1);
     const int32_t ntail_nodes = (int32_t)out.tail_nodes.size();
+    // stations: slots [0, nslots), lanes after them, then the tail's nodes
+    out.center_base = nslots;
+    out.tail_base = nslots + ntiles * kWave;
+    out.slot_next.assign((size_t)nslots, kNoStation);
+    out.center_next.assign((size_t)ntiles * kWave, kNoStation);
+    out.tail_next.assign((size_t)ntail_nodes, kNoStation);
+    std::vector<int64_t> first((size_t)n, -1), prev((size_t)n, -1);
+    auto set_next = [&](int64_t station, int64_t next) {
+        if (station < out.center_base) out.slot_next[(size_t)station] = (uint32_t)next;
+        else if (station < out.tail_base)
+            out.center_next[(size_t)(station - out.center_base)] = (uint32_t)next;
+        else out.tail_next[(size_t)(station - out.tail_base)] = (uint32_t)next;
+    };
+    auto arrive = [&](int32_t v, int64_t station) {
+        if (prev[(size_t)v] < 0) first[(size_t)v] = station;
+        else set_next(prev[(size_t)v], station);
+        prev[(size_t)v] = station;
+    };
     for (int32_t p = 0; p < P; ++p) {
         const bool tail = p >= P0;
         if (tail) out.tail_edges += ecount[(size_t)p];
@@ -325,6 +343,7 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
             const int64_t tile_base = d.slot_base + rows_before * kWave;
             out.tile_center[(size_t)((d.tile0 + tt) * kWave + lane)] =
                 tail ? local[(size_t)sr.center] : sr.center;
+            if (!tail) arrive(sr.center, out.center_base + (d.tile0 + tt) * kWave + lane);
             for (int32_t k = 0; k < sr.len; ++k) {
                 int64_t e = byphase[(size_t)(sr.begin + k)];
                 bool c_is_dst = dst[e] == sr.center;
@@ -334,9 +353,26 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
                 out.slot_leaf[(size_t)sl] = (uint32_t)id | (c_is_dst ? kCenterIsDst : 0u);
                 out.slot_edge[(size_t)sl] = e;
                 out.edge_slot[(size_t)e] = sl;
+                if (!tail) arrive(leaf, sl);
             }
         }
     }
+    for (int32_t j = 0; j < ntail_nodes; ++j) arrive(out.tail_nodes[(size_t)j], out.tail_base + j);
+    // close each node's cycle; nodes on no edge get a home entry of their own
+    int64_t entries = out.tail_base + ntail_nodes;
+    out.home.assign((size_t)n, kNoStation);
+    for (int32_t v = 0; v < n; ++v) {
+        if (prev[(size_t)v] >= 0) set_next(prev[(size_t)v], first[(size_t)v]);
+        else first[(size_t)v] = entries++;
+        out.home[(size_t)v] = (uint32_t)first[(size_t)v];
+    }
+    if (entries >= (int64_t)kNoStation)
+        fail(-5, "graph too large for 31-bit station indices");
+    out.entries = entries;
+    // the orientation bit rides on the leaf slot's next station
+    for (int64_t sl = 0; sl < (P0 < P ? out.desc[(size_t)P0].slot_base : nslots); ++sl)
+        if (out.slot_next[(size_t)sl] != kNoStation)
+            out.slot_next[(size_t)sl] |= out.slot_leaf[(size_t)sl] & kCenterIsDst;
 }
 
 }  // namespace lowd

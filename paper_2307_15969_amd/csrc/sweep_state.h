@@ -147,23 +147,26 @@ struct SweepLaunch {
     void (*init_slots)(int64_t nslots, const int64_t *slot_edge, const float *w, void *slot_x,
                        float *slot_w, hipStream_t s);
     void (*init_loads)(int32_t n, const int64_t *row_ptr, const uint32_t *inc, const float *w,
-                       void *L, hipStream_t s);
-    void (*phase)(const PhaseDesc &d, const int32_t *tile_center, const uint32_t *slot_leaf,
-                  void *slot_x, const float *slot_w, void *L, hipStream_t s);
+                       const uint32_t *home, int64_t entries, int64_t center_base, void *E,
+                       hipStream_t s);
+    void (*phase)(const PhaseDesc &d, int64_t center_base, const uint32_t *center_next,
+                  const uint32_t *slot_next, void *slot_x, const float *slot_w, void *E,
+                  hipStream_t s);
     void (*tail)(int32_t nph, const PhaseDesc *descs, const int32_t *tile_center,
-                 const uint32_t *slot_leaf, void *slot_x, const float *slot_w,
-                 const int32_t *tail_nodes, int32_t ntail, void *L, hipStream_t s);
-    void (*mid)(int32_t nph, const PhaseDesc *descs, const int32_t *tile_center,
-                const uint32_t *slot_leaf, void *slot_x, const float *slot_w, void *L,
-                hipStream_t s);
+                 const uint32_t *slot_leaf, void *slot_x, const float *slot_w, int64_t tail_base,
+                 const uint32_t *tail_next, int32_t ntail, void *E, hipStream_t s);
+    void (*mid)(int32_t nph, const PhaseDesc *descs, int64_t center_base,
+                const uint32_t *center_next, const uint32_t *slot_next, void *slot_x,
+                const float *slot_w, void *E, hipStream_t s);
     void (*set_tail_lds)(size_t bytes);
     void (*set_mid_lds)(size_t bytes);
     void (*loads_f64)(int32_t n, const int64_t *row_ptr, const uint32_t *inc,
-                      const int64_t *edge_slot, const void *slot_x, const float *w, const void *L,
-                      double *L64, hipStream_t s);
+                      const int64_t *edge_slot, const void *slot_x, const float *w,
+                      const uint32_t *home, const void *E, double *L64, hipStream_t s);
     void (*read_x)(int64_t m, const int64_t *edge_slot, const void *slot_x, double *x,
                    hipStream_t s);
-    void (*read_loads)(int32_t n, const void *L, double *out, hipStream_t s);
+    void (*read_loads)(int32_t n, const uint32_t *home, const void *E, double *out,
+                       hipStream_t s);
     void (*batch)(int32_t G, const int32_t *order, unsigned *queue, const int64_t *node_ptr,
                   const int64_t *edge_ptr, const int32_t *src, const int32_t *dst,
                   const int64_t *desc_ptr, const PhaseDesc *descs, const int32_t *tile_center,
