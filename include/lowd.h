@@ -233,6 +233,64 @@ lowd_status lowd_batch_solve(int32_t G, const int64_t *node_ptr, const int64_t *
                              int32_t star_max, int32_t sweeps, uint8_t *in_set, int64_t *num,
                              int64_t *den, double *load, void *stream);
 
+/*
+ * The batched form in steps, for solving to a tolerance: a prepared batch
+ * keeps its schedules, fractions and loads on the device between calls.
+ * lowd_batch_solve is lowd_batch_prepare + lowd_batch_iterate +
+ * lowd_batch_extract.
+ */
+typedef struct lowd_batch lowd_batch;
+
+/*
+ * lowd_batch_prepare -- validates the graphs (as lowd_batch_solve), builds
+ * every graph's schedule, uploads the layout and sets Algorithm 1's initial
+ * state.  With tune = 1 it also times each supported launch shape (waves
+ * per workgroup, prefetching tile buffers or not, workgroups per CU) on a
+ * short run of this batch and keeps the fastest; the shape never changes a
+ * result.  tune = 0 keeps the default shape.  Arguments as for
+ * lowd_batch_solve; the device arrays are copied, not kept.
+ *   out  [host] out: the prepared batch; free with lowd_batch_free
+ * Synchronises `stream`.
+ */
+lowd_status lowd_batch_prepare(int32_t G, const int64_t *node_ptr, const int64_t *edge_ptr,
+                               const int32_t *src, const int32_t *dst, int32_t state,
+                               int32_t star_max, int32_t tune, lowd_batch **out, void *stream);
+
+/* lowd_batch_reset -- back to Algorithm 1's initial state.  Asynchronous. */
+lowd_status lowd_batch_reset(lowd_batch *b, void *stream);
+
+/*
+ * lowd_batch_iterate -- `sweeps` more sweeps of every graph, continuing from
+ * the current state, in one persistent launch (a HIP graph captured once
+ * per distinct sweep count).  Asynchronous.
+ */
+lowd_status lowd_batch_iterate(lowd_batch *b, int32_t sweeps, void *stream);
+
+/*
+ * lowd_batch_extract -- every graph's densest set from its current loads
+ * (Algorithm 1's extraction), and its largest load D_g, the dual bound of
+ * Section III-B (rho_g <= rho*_g <= D_g).
+ *   in_set  [device] uint8[total nodes] out
+ *   num     [device] int64[G] out
+ *   den     [device] int64[G] out
+ *   D       [device] double[G] out, or NULL
+ *   load    [device] double[total nodes] out, or NULL
+ * Asynchronous.
+ */
+lowd_status lowd_batch_extract(lowd_batch *b, uint8_t *in_set, int64_t *num, int64_t *den,
+                               double *D, double *load, void *stream);
+
+/*
+ * lowd_batch_info --
+ *   info [host] int64[9] out: G, total nodes, total edges, total phases,
+ *        most phases of one graph, waves per workgroup, prefetching tile
+ *        buffers (0/1), workgroups of the launch, LDS bytes per workgroup.
+ */
+lowd_status lowd_batch_info(const lowd_batch *b, int64_t *info);
+
+/* Releases the prepared batch (waits for pending work).  NULL is accepted. */
+void lowd_batch_free(lowd_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -56,9 +56,18 @@ def lib() -> C.CDLL:
         L.lowd_solver_free.argtypes = [vp]
         L.lowd_solver_free.restype = None
         L.lowd_batch_solve.argtypes = [i32, vp, vp, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp]
+        L.lowd_batch_prepare.argtypes = [i32, vp, vp, vp, vp, i32, i32, i32, P(vp), vp]
+        L.lowd_batch_reset.argtypes = [vp, vp]
+        L.lowd_batch_iterate.argtypes = [vp, i32, vp]
+        L.lowd_batch_extract.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.lowd_batch_info.argtypes = [vp, vp]
+        L.lowd_batch_free.argtypes = [vp]
+        L.lowd_batch_free.restype = None
         for f in (L.lowd_prune, L.lowd_init_loads, L.lowd_iterate, L.lowd_check,
                   L.lowd_extract_densest, L.lowd_read_state, L.lowd_schedule_export,
-                  L.lowd_solver_info, L.lowd_batch_solve, L.lowd_schedule_build, L.lowd_reset_loads):
+                  L.lowd_solver_info, L.lowd_batch_solve, L.lowd_schedule_build, L.lowd_reset_loads,
+                  L.lowd_batch_prepare, L.lowd_batch_reset, L.lowd_batch_iterate,
+                  L.lowd_batch_extract, L.lowd_batch_info):
             f.restype = C.c_int32
         _lib = L
     return _lib
@@ -239,6 +248,82 @@ def batch_solve(graphs, sweeps: int, state: str = "f64", star_max: int = 16, str
                                   _ptr(den), _ptr(load), _stream(stream)))
     return dict(num=num.cpu().numpy(), den=den.cpu().numpy(), in_set=in_set, load=load,
                 node_ptr=node_ptr, edge_ptr=edge_ptr)
+
+
+def _batch_arrays(graphs):
+    torch = _torch()
+    G = len(graphs)
+    node_ptr = np.zeros(G + 1, dtype=np.int64)
+    edge_ptr = np.zeros(G + 1, dtype=np.int64)
+    for i, g in enumerate(graphs):
+        node_ptr[i + 1] = node_ptr[i] + g.n
+        edge_ptr[i + 1] = edge_ptr[i] + g.src.size
+    src = torch.from_numpy(np.concatenate([g.src for g in graphs]).astype(np.int32)).cuda()
+    dst = torch.from_numpy(np.concatenate([g.dst for g in graphs]).astype(np.int32)).cuda()
+    return node_ptr, edge_ptr, src, dst
+
+
+class Batch:
+    """A prepared batch of unweighted graphs (lowd_batch_prepare): iterate in
+    steps and extract every graph's densest set and dual bound D_g."""
+
+    def __init__(self, graphs, state: str = "f64", star_max: int = 16, tune: bool = False,
+                 stream=None):
+        torch = _torch()
+        self.G = len(graphs)
+        self.node_ptr, self.edge_ptr, src, dst = _batch_arrays(graphs)
+        self.N = int(self.node_ptr[-1])
+        self.device = src.device
+        h = C.c_void_p()
+        _check(lib().lowd_batch_prepare(self.G, self.node_ptr.ctypes.data_as(C.c_void_p),
+                                        self.edge_ptr.ctypes.data_as(C.c_void_p), _ptr(src),
+                                        _ptr(dst), _STATES[state], star_max, 1 if tune else 0,
+                                        C.byref(h), _stream(stream)))
+        self._h = h
+        self.in_set = torch.empty(self.N, dtype=torch.uint8, device=self.device)
+        self.num = torch.empty(self.G, dtype=torch.int64, device=self.device)
+        self.den = torch.empty(self.G, dtype=torch.int64, device=self.device)
+        self.D = torch.empty(self.G, dtype=torch.float64, device=self.device)
+        self.load = torch.empty(self.N, dtype=torch.float64, device=self.device)
+
+    def reset(self, stream=None):
+        _check(lib().lowd_batch_reset(self._h, _stream(stream)))
+
+    def iterate(self, sweeps: int, stream=None):
+        _check(lib().lowd_batch_iterate(self._h, sweeps, _stream(stream)))
+
+    def extract(self, stream=None, loads: bool = False):
+        """Enqueues the extraction into self.in_set/num/den/D (and self.load)."""
+        _check(lib().lowd_batch_extract(self._h, _ptr(self.in_set), _ptr(self.num),
+                                        _ptr(self.den), _ptr(self.D),
+                                        _ptr(self.load) if loads else None, _stream(stream)))
+
+    def gaps(self):
+        """Per-graph relative gap (D_g - rho_g) / rho_g after extract()."""
+        num = self.num.cpu().numpy().astype(np.float64)
+        den = self.den.cpu().numpy().astype(np.float64)
+        D = self.D.cpu().numpy()
+        rho = num / den
+        with np.errstate(divide="ignore", invalid="ignore"):
+            gap = np.where(rho > 0, (D - rho) / rho, np.where(D > 0, np.inf, 0.0))
+        return gap
+
+    def info(self) -> dict:
+        a = np.zeros(9, dtype=np.int64)
+        _check(lib().lowd_batch_info(self._h, a.ctypes.data_as(C.c_void_p)))
+        keys = ["G", "N", "M", "phases", "max_phases", "waves", "prefetch", "blocks", "lds"]
+        return {k: int(v) for k, v in zip(keys, a)}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lowd_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def schedule_build(n: int, src: np.ndarray, dst: np.ndarray, star_max: int = 16):

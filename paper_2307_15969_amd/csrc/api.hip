@@ -1,5 +1,6 @@
 // api.hip -- the C interface (include/lowd.h): argument checks, the solver
 // object, device memory, the HIP graph of one sweep, and error reporting.
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -415,16 +416,127 @@ lowd_status lowd_prune(int32_t n, int64_t m, const int32_t *src, const int32_t *
     });
 }
 
-lowd_status lowd_batch_solve(int32_t G, const int64_t *node_ptr, const int64_t *edge_ptr,
-                             const int32_t *src, const int32_t *dst, int32_t state,
-                             int32_t star_max, int32_t sweeps, uint8_t *in_set, int64_t *num,
-                             int64_t *den, double *load, void *stream) {
+}  // extern "C"
+
+// ---------------------------------------------------------------- batches --
+struct lowd_batch {
+    int32_t G = 0;
+    int64_t N = 0, M = 0;
+    int32_t state = 0;
+    SweepLaunch fn{};
+    std::vector<int64_t> node_ptr_h, edge_ptr_h;
+    int64_t total_phases = 0, max_phases = 0;
+    DBuf<int64_t> node_ptr, edge_ptr, desc_ptr, slot_edge;
+    DBuf<int32_t> gsrc, gdst, node_graph, order, tile_center, deg;
+    DBuf<PhaseDesc> descs;
+    DBuf<uint32_t> slot_leaf;
+    DBuf<char> slot_x, Lstate;
+    DBuf<double> L64;
+    DBuf<unsigned> queue;
+    BatchExtractScratch ex;
+    size_t lds = 0;        // bytes of LDS per workgroup
+    int32_t waves = 8;     // launch shape: waves per workgroup,
+    int32_t prefetch = 1;  // double-buffered tiles or not,
+    int32_t blocks = 1;    // workgroups
+    int32_t shape() const { return waves * 2 + prefetch; }
+    int32_t graph_sweeps = -1;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void drop_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        graph_sweeps = -1;
+    }
+    ~lowd_batch() { drop_graph(); }
+};
+
+static void batch_reset(lowd_batch *b, hipStream_t s) {
+    const int64_t nslots = (int64_t)(b->slot_leaf.n);
+    if (b->M > 0) b->fn.init_slots(nslots, b->slot_edge.p, nullptr, b->slot_x.p, nullptr, s);
+    b->fn.batch_init_loads(b->N, b->M, b->gsrc.p, b->gdst.p, b->deg.p, b->Lstate.p, s);
+    LOWD_HIP(hipGetLastError());
+}
+
+// One launch of the persistent kernel for `sweeps` sweeps, as a HIP graph
+// (captured once per distinct sweep count and launch shape).
+static void batch_launch(lowd_batch *b, int32_t sweeps, hipStream_t s) {
+    if (b->graph_sweeps != sweeps || !b->exec) {
+        b->drop_graph();
+        hipStream_t cs;
+        LOWD_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (err == hipSuccess) {
+            b->fn.batch(b->shape(), b->G, b->order.p, b->queue.p, b->node_ptr.p, b->desc_ptr.p,
+                        b->descs.p, b->tile_center.p, b->slot_leaf.p, b->slot_x.p, sweeps,
+                        b->Lstate.p, b->lds, b->blocks, cs);
+            err = hipStreamEndCapture(cs, &b->graph);
+        }
+        (void)hipStreamDestroy(cs);
+        LOWD_HIP(err);
+        LOWD_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        b->graph_sweeps = sweeps;
+    }
+    LOWD_HIP(hipGraphLaunch(b->exec, s));
+}
+
+// Launch-shape autotuner: every shape (waves per workgroup x workgroups per
+// CU) runs a short stretch of the real batch, timed with events; the
+// fastest is kept and the state is reset.  The shape changes only which
+// workgroup runs which graph and how a graph's tiles are dealt to its waves,
+// never the result.
+static void batch_tune(lowd_batch *b, int32_t cus, hipStream_t s) {
+    struct Shape { int32_t waves, prefetch, per_cu; };
+    const Shape shapes[] = {{8, 1, 1}, {8, 0, 1}, {8, 0, 2}, {4, 1, 1}, {4, 1, 2},
+                            {4, 0, 2}, {4, 0, 3}, {4, 0, 4}};
+    hipEvent_t e0, e1;
+    LOWD_HIP(hipEventCreate(&e0));
+    LOWD_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    Shape pick{b->waves, b->prefetch, 1};
+    const int32_t tune_sweeps = 2;
+    for (const Shape &sh : shapes) {
+        if ((int64_t)b->lds * sh.per_cu > 160 * 1024) continue;
+        b->waves = sh.waves;
+        b->prefetch = sh.prefetch;
+        b->blocks = (int32_t)std::min<int64_t>((int64_t)cus * sh.per_cu, b->G);
+        b->drop_graph();
+        b->fn.set_batch_lds(b->shape(), b->lds);
+        batch_reset(b, s);
+        batch_launch(b, tune_sweeps, s);   // first launch: instantiation, cold caches
+        LOWD_HIP(hipEventRecord(e0, s));
+        batch_launch(b, tune_sweeps, s);
+        LOWD_HIP(hipEventRecord(e1, s));
+        LOWD_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        LOWD_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            pick = sh;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->waves = pick.waves;
+    b->prefetch = pick.prefetch;
+    b->blocks = (int32_t)std::min<int64_t>((int64_t)cus * pick.per_cu, b->G);
+    b->drop_graph();
+    b->fn.set_batch_lds(b->shape(), b->lds);
+}
+
+extern "C" {
+
+lowd_status lowd_batch_prepare(int32_t G, const int64_t *node_ptr, const int64_t *edge_ptr,
+                               const int32_t *src, const int32_t *dst, int32_t state,
+                               int32_t star_max, int32_t tune, lowd_batch **out, void *stream) {
     return guarded([&] {
+        if (!out) fail(LOWD_E_ARG, "out is NULL");
+        *out = nullptr;
         if (G < 1 || !node_ptr || !edge_ptr) fail(LOWD_E_ARG, "G >= 1 and node_ptr/edge_ptr needed");
         if (state != LOWD_STATE_F64 && state != LOWD_STATE_F32K) fail(LOWD_E_ARG, "bad state");
         if (star_max < 1 || star_max > kMaxStar) fail(LOWD_E_ARG, "star_max must be in [1, 16]");
-        if (sweeps < 0) fail(LOWD_E_ARG, "sweeps must be >= 0");
-        if (!in_set || !num || !den) fail(LOWD_E_ARG, "in_set/num/den is NULL");
+        if (tune != 0 && tune != 1) fail(LOWD_E_ARG, "tune must be 0 or 1");
         if (node_ptr[0] != 0 || edge_ptr[0] != 0) fail(LOWD_E_ARG, "node_ptr[0], edge_ptr[0] must be 0");
         for (int32_t g = 0; g < G; ++g) {
             if (node_ptr[g + 1] - node_ptr[g] < 1) fail(LOWD_E_ARG, "every graph needs a node");
@@ -434,8 +546,15 @@ lowd_status lowd_batch_solve(int32_t G, const int64_t *node_ptr, const int64_t *
         if (N > 0x7FFFFFFD || M >= ((int64_t)1 << 31)) fail(LOWD_E_ARG, "batch too large");
         if (M > 0 && (!src || !dst)) fail(LOWD_E_ARG, "src/dst is NULL");
         hipStream_t s = (hipStream_t)stream;
-        SweepLaunch fn{};
-        get_sweep_launchers(state, false, fn);
+        auto b = new lowd_batch();
+        std::unique_ptr<lowd_batch> guard(b);
+        b->G = G;
+        b->N = N;
+        b->M = M;
+        b->state = state;
+        get_sweep_launchers(state, false, b->fn);
+        b->node_ptr_h.assign(node_ptr, node_ptr + G + 1);
+        b->edge_ptr_h.assign(edge_ptr, edge_ptr + G + 1);
 
         std::vector<int32_t> hs((size_t)M), hd((size_t)M);
         if (M > 0) {
@@ -448,26 +567,25 @@ lowd_status lowd_batch_solve(int32_t G, const int64_t *node_ptr, const int64_t *
             const int64_t ng = node_ptr[g + 1] - node_ptr[g];
             for (int64_t u = node_ptr[g]; u < node_ptr[g + 1]; ++u) node_graph[(size_t)u] = g;
             for (int64_t e = edge_ptr[g]; e < edge_ptr[g + 1]; ++e) {
-                const int32_t a = hs[(size_t)e], b = hd[(size_t)e];
-                if (a < 0 || a >= ng || b < 0 || b >= ng || a == b)
+                const int32_t a = hs[(size_t)e], c = hd[(size_t)e];
+                if (a < 0 || a >= ng || c < 0 || c >= ng || a == c)
                     fail(LOWD_E_GRAPH, "invalid edge " + std::to_string(e) + " of graph " +
                                            std::to_string(g) + ": (" + std::to_string(a) + ", " +
-                                           std::to_string(b) + "), n = " + std::to_string(ng));
+                                           std::to_string(c) + "), n = " + std::to_string(ng));
                 gsrc[(size_t)e] = a + (int32_t)node_ptr[g];
-                gdst[(size_t)e] = b + (int32_t)node_ptr[g];
+                gdst[(size_t)e] = c + (int32_t)node_ptr[g];
             }
         }
-        DBuf<int32_t> d_gsrc, d_gdst, d_node_graph;
-        upload(d_gsrc, gsrc, s);
-        upload(d_gdst, gdst, s);
-        upload(d_node_graph, node_graph, s);
+        upload(b->gsrc, gsrc, s);
+        upload(b->gdst, gdst, s);
+        upload(b->node_graph, node_graph, s);
         {
-            int64_t b = find_duplicate_pair((int32_t)N, M, d_gsrc.p, d_gdst.p, s);
-            if (b >= 0) fail(LOWD_E_GRAPH, "repeated pair at edge " + std::to_string(b));
+            int64_t bad = find_duplicate_pair((int32_t)N, M, b->gsrc.p, b->gdst.p, s);
+            if (bad >= 0) fail(LOWD_E_GRAPH, "repeated pair at edge " + std::to_string(bad));
         }
 
         // per-graph schedules (every phase from LDS), built in parallel
-        const int64_t lds = (int64_t)lds_capacity_bytes() - 64;
+        const int64_t lds_cap = (int64_t)lds_capacity_bytes() - 64;
         std::vector<Schedule> sch((size_t)G);
         {
             std::atomic<int32_t> next(0);
@@ -484,7 +602,7 @@ lowd_status lowd_batch_solve(int32_t G, const int64_t *node_ptr, const int64_t *
                             const int64_t e0 = edge_ptr[g];
                             build_schedule((int32_t)(node_ptr[g + 1] - node_ptr[g]),
                                            edge_ptr[g + 1] - e0, hs.data() + e0, hd.data() + e0,
-                                           star_max, lds, (int64_t)fn.l_bytes, 0, 0,
+                                           star_max, lds_cap, (int64_t)b->fn.l_bytes, 0, 0,
                                            sch[(size_t)g], true);
                         }
                     } catch (const Error &e) {
@@ -500,7 +618,7 @@ lowd_status lowd_batch_solve(int32_t G, const int64_t *node_ptr, const int64_t *
                 for (auto &e : errs)
                     if (!e.empty()) fail(LOWD_E_ARG, e);
         }
-        // concatenate the layouts; check that every graph fits one workgroup's LDS
+        // concatenate the layouts; every graph must fit one workgroup's LDS
         std::vector<PhaseDesc> descs;
         std::vector<int32_t> tile_center;
         std::vector<uint32_t> slot_leaf;
@@ -509,12 +627,14 @@ lowd_status lowd_batch_solve(int32_t G, const int64_t *node_ptr, const int64_t *
         for (int32_t g = 0; g < G; ++g) {
             const Schedule &sc = sch[(size_t)g];
             const int64_t ng = node_ptr[g + 1] - node_ptr[g];
-            const size_t need = tail_desc_bytes(sc.P) + (size_t)(ng + 2) * fn.l_bytes;
-            if ((int64_t)need > lds)
+            const size_t need = tail_desc_bytes(sc.P) + (size_t)(ng + 2) * b->fn.l_bytes;
+            if ((int64_t)need > lds_cap)
                 fail(LOWD_E_UNSUPPORTED, "graph " + std::to_string(g) + " (" + std::to_string(ng) +
                                              " nodes, " + std::to_string(sc.P) +
                                              " phases) does not fit one workgroup's LDS");
             if (need > lds_need) lds_need = need;
+            b->total_phases += sc.P;
+            b->max_phases = std::max<int64_t>(b->max_phases, sc.P);
             const int64_t slot0 = (int64_t)slot_leaf.size();
             const int32_t tile0 = (int32_t)(tile_center.size() / kWave);
             for (PhaseDesc d : sc.desc) {
@@ -529,77 +649,135 @@ lowd_status lowd_batch_solve(int32_t G, const int64_t *node_ptr, const int64_t *
         }
         std::vector<int32_t> order((size_t)G);
         for (int32_t g = 0; g < G; ++g) order[(size_t)g] = g;
-        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-            return edge_ptr[a + 1] - edge_ptr[a] > edge_ptr[b + 1] - edge_ptr[b];
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) {
+            return edge_ptr[a + 1] - edge_ptr[a] > edge_ptr[c + 1] - edge_ptr[c];
         });
-        std::vector<int64_t> hnode(node_ptr, node_ptr + G + 1), hedge(edge_ptr, edge_ptr + G + 1);
-        DBuf<int64_t> d_node_ptr, d_edge_ptr, d_desc_ptr, d_slot_edge;
-        DBuf<int32_t> d_order, d_tile_center;
-        DBuf<PhaseDesc> d_descs;
-        DBuf<uint32_t> d_slot_leaf;
-        upload(d_node_ptr, hnode, s);
-        upload(d_edge_ptr, hedge, s);
-        upload(d_desc_ptr, desc_ptr, s);
-        upload(d_slot_edge, slot_edge, s);
-        upload(d_order, order, s);
-        upload(d_tile_center, tile_center, s);
-        upload(d_descs, descs, s);
-        upload(d_slot_leaf, slot_leaf, s);
+        upload(b->node_ptr, b->node_ptr_h, s);
+        upload(b->edge_ptr, b->edge_ptr_h, s);
+        upload(b->desc_ptr, desc_ptr, s);
+        upload(b->slot_edge, slot_edge, s);
+        upload(b->order, order, s);
+        upload(b->tile_center, tile_center, s);
+        upload(b->descs, descs, s);
+        upload(b->slot_leaf, slot_leaf, s);
         const int64_t nslots = (int64_t)slot_leaf.size();
-        DBuf<char> slot_x((size_t)(nslots > 0 ? nslots : 1) * fn.x_bytes);
-        DBuf<double> Lout((size_t)N);
-        DBuf<unsigned> queue(1);
-        if (nslots > 0) fn.init_slots(nslots, d_slot_edge.p, nullptr, slot_x.p, nullptr, s);
+        b->slot_x.alloc((size_t)(nslots > 0 ? nslots : 1) * b->fn.x_bytes);
+        b->Lstate.alloc((size_t)(N > 0 ? N : 1) * b->fn.l_bytes);
+        b->L64.alloc((size_t)(N > 0 ? N : 1));
+        b->deg.alloc((size_t)(N > 0 ? N : 1));
+        b->queue.alloc(1);
+        b->lds = lds_need;
 
-        // one persistent launch, captured in a HIP graph
         int dev = 0, cus = 0;
         LOWD_HIP(hipGetDevice(&dev));
         LOWD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        const size_t per_cu = 160 * 1024;
-        int32_t per = (int32_t)(per_cu / (lds_need + 64));
-        if (per < 1) per = 1;
-        if (per > 4) per = 4;
-        int32_t blocks = cus * per;
-        if (blocks > G) blocks = G;
-        fn.set_batch_lds(lds_need);
-        hipStream_t cs;
-        LOWD_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
-        hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-        if (err == hipSuccess) {
-            fn.batch(G, d_order.p, queue.p, d_node_ptr.p, d_edge_ptr.p, src, dst, d_desc_ptr.p,
-                     d_descs.p, d_tile_center.p, d_slot_leaf.p, slot_x.p, sweeps, Lout.p,
-                     lds_need, blocks, cs);
-            err = hipStreamEndCapture(cs, &graph);
+        b->waves = 8;
+        b->prefetch = 1;
+        int32_t per_cu = 1;
+        if (const char *e = getenv("LOWD_BATCH_SHAPE")) {   // "waves,prefetch,per_cu"
+            int w = 0, pf = 0, pc = 0;
+            if (sscanf(e, "%d,%d,%d", &w, &pf, &pc) != 3 || (w != 4 && w != 8) ||
+                (pf != 0 && pf != 1) || pc < 1 || pc > 4)
+                fail(LOWD_E_ARG, "LOWD_BATCH_SHAPE must be waves(4|8),prefetch(0|1),per_cu(1-4)");
+            b->waves = w;
+            b->prefetch = pf;
+            per_cu = pc;
         }
-        (void)hipStreamDestroy(cs);
-        LOWD_HIP(err);
-        err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (err == hipSuccess) err = hipGraphLaunch(exec, s);
-        if (err == hipSuccess) err = hipStreamSynchronize(s);
-        if (exec) (void)hipGraphExecDestroy(exec);
-        (void)hipGraphDestroy(graph);
-        LOWD_HIP(err);
+        b->blocks = (int32_t)std::min<int64_t>((int64_t)cus * per_cu, G);
+        b->fn.set_batch_lds(b->shape(), b->lds);
+        if (tune) batch_tune(b, cus, s);
+        batch_reset(b, s);
+        LOWD_HIP(hipStreamSynchronize(s));
+        *out = guard.release();
+    });
+}
 
+lowd_status lowd_batch_reset(lowd_batch *b, void *stream) {
+    return guarded([&] {
+        if (!b) fail(LOWD_E_ARG, "batch is NULL");
+        batch_reset(b, (hipStream_t)stream);
+    });
+}
+
+lowd_status lowd_batch_iterate(lowd_batch *b, int32_t sweeps, void *stream) {
+    return guarded([&] {
+        if (!b) fail(LOWD_E_ARG, "batch is NULL");
+        if (sweeps < 0) fail(LOWD_E_ARG, "sweeps must be >= 0");
+        if (sweeps == 0) return;
+        batch_launch(b, sweeps, (hipStream_t)stream);
+    });
+}
+
+lowd_status lowd_batch_extract(lowd_batch *b, uint8_t *in_set, int64_t *num, int64_t *den,
+                               double *D, double *load, void *stream) {
+    return guarded([&] {
+        if (!b) fail(LOWD_E_ARG, "batch is NULL");
+        if (!in_set || !num || !den) fail(LOWD_E_ARG, "in_set/num/den is NULL");
+        hipStream_t s = (hipStream_t)stream;
+        b->fn.batch_loads_f64(b->N, b->Lstate.p, b->L64.p, s);
         BatchExtractArgs a;
-        a.G = G;
-        a.N = N;
-        a.M = M;
-        a.node_ptr = d_node_ptr.p;
-        a.node_graph = d_node_graph.p;
-        a.gsrc = d_gsrc.p;
-        a.gdst = d_gdst.p;
-        a.L64 = Lout.p;
+        a.G = b->G;
+        a.N = b->N;
+        a.M = b->M;
+        a.node_ptr = b->node_ptr.p;
+        a.node_graph = b->node_graph.p;
+        a.gsrc = b->gsrc.p;
+        a.gdst = b->gdst.p;
+        a.L64 = b->L64.p;
         a.in_set = in_set;
         a.num = num;
         a.den = den;
-        launch_extract_batch(a, s);
+        a.D = D;
+        launch_extract_batch(a, b->ex, s);
         if (load)
-            LOWD_HIP(hipMemcpyAsync(load, Lout.p, (size_t)N * sizeof(double),
+            LOWD_HIP(hipMemcpyAsync(load, b->L64.p, (size_t)b->N * sizeof(double),
                                     hipMemcpyDeviceToDevice, s));
-        LOWD_HIP(hipStreamSynchronize(s));
     });
+}
+
+lowd_status lowd_batch_info(const lowd_batch *b, int64_t *info) {
+    return guarded([&] {
+        if (!b || !info) fail(LOWD_E_ARG, "NULL argument");
+        info[0] = b->G;
+        info[1] = b->N;
+        info[2] = b->M;
+        info[3] = b->total_phases;
+        info[4] = b->max_phases;
+        info[5] = b->waves;
+        info[6] = b->prefetch;
+        info[7] = b->blocks;
+        info[8] = (int64_t)b->lds;
+    });
+}
+
+void lowd_batch_free(lowd_batch *b) {
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    delete b;
+}
+
+lowd_status lowd_batch_solve(int32_t G, const int64_t *node_ptr, const int64_t *edge_ptr,
+                             const int32_t *src, const int32_t *dst, int32_t state,
+                             int32_t star_max, int32_t sweeps, uint8_t *in_set, int64_t *num,
+                             int64_t *den, double *load, void *stream) {
+    if (sweeps < 0) {
+        g_last_error = "sweeps must be >= 0";
+        return LOWD_E_ARG;
+    }
+    if (!in_set || !num || !den) {
+        g_last_error = "in_set/num/den is NULL";
+        return LOWD_E_ARG;
+    }
+    lowd_batch *b = nullptr;
+    lowd_status st = lowd_batch_prepare(G, node_ptr, edge_ptr, src, dst, state, star_max, 0, &b,
+                                        stream);
+    if (st != LOWD_OK) return st;
+    std::unique_ptr<lowd_batch, void (*)(lowd_batch *)> guard(b, lowd_batch_free);
+    st = lowd_batch_iterate(b, sweeps, stream);
+    if (st == LOWD_OK) st = lowd_batch_extract(b, in_set, num, den, nullptr, load, stream);
+    if (st == LOWD_OK)
+        st = guarded([&] { LOWD_HIP(hipStreamSynchronize((hipStream_t)stream)); });
+    return st;
 }
 
 }  // extern "C"

@@ -38,7 +38,18 @@ struct ExtractScratch {
 void launch_extract(const ExtractArgs &a, ExtractScratch &sc, hipStream_t s);
 
 // Extraction for many unweighted graphs whose nodes and edges are
-// concatenated (global node ids); synchronises the stream.
+// concatenated (global node ids); enqueued on the stream, scratch owned by
+// the caller.
+struct BatchExtractScratch {
+    int64_t cap_n = -1;
+    int32_t cap_g = -1;
+    DBuf<uint64_t> k0, k1;
+    DBuf<uint32_t> v0, v1, g0, g1;
+    DBuf<int32_t> pos;
+    DBuf<int64_t> hist, rev, W, best;
+    DBuf<char> tmp;
+    void ensure(int64_t N, int32_t G);
+};
 struct BatchExtractArgs {
     int32_t G = 0;
     int64_t N = 0;                     // total nodes
@@ -51,7 +62,8 @@ struct BatchExtractArgs {
     uint8_t *in_set = nullptr;         // [N] out
     int64_t *num = nullptr;            // [G] out
     int64_t *den = nullptr;            // [G] out
+    double *D = nullptr;               // [G] out: largest load per graph, or nullptr
 };
-void launch_extract_batch(const BatchExtractArgs &a, hipStream_t s);
+void launch_extract_batch(const BatchExtractArgs &a, BatchExtractScratch &sc, hipStream_t s);
 
 }  // namespace lowd

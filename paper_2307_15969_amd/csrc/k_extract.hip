@@ -259,28 +259,37 @@ __global__ void k_edge_min_pos_batch(int64_t M, const int32_t *gsrc, const int32
     }
 }
 
-// one block per graph: first index of maximal density W_g[i] / (n_g - i)
+// one block per graph: first index of maximal density W_g[i] / (n_g - i),
+// and the graph's largest load D_g (the dual bound of Section III-B)
 __global__ void __launch_bounds__(kArgBlock) k_best_batch(int32_t G, const int64_t *node_ptr,
                                                           int64_t N, const int64_t *W,
-                                                          int64_t *best, int64_t *num,
-                                                          int64_t *den) {
+                                                          const double *L64, int64_t *best,
+                                                          int64_t *num, int64_t *den,
+                                                          double *D) {
     __shared__ int64_t lds_i[kArgBlock];
     __shared__ int64_t lds_w[kArgBlock];
+    __shared__ double lds_d[kArgBlock];
     const int32_t g = blockIdx.x;
     const int64_t start = node_ptr[g], end = node_ptr[g + 1];
     const int64_t n = end - start;
     const int64_t tail = end < N ? W[end] : 0;
     int64_t bi = -1, bw = 0;
+    double dmax = -1.0e308;
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
         const int64_t wi = W[start + i] - tail;
         // wi / (n - i) > bw / (n - bi), exact in int64
         if (bi < 0 || wi * (n - bi) > bw * (n - i)) { bi = i; bw = wi; }
+        const double l = L64[start + i];
+        dmax = l > dmax ? l : dmax;
     }
     lds_i[threadIdx.x] = bi;
     lds_w[threadIdx.x] = bw;
+    lds_d[threadIdx.x] = dmax;
     __syncthreads();
     for (int s = kArgBlock / 2; s > 0; s >>= 1) {
         if (threadIdx.x < s) {
+            const double od = lds_d[threadIdx.x + s];
+            if (od > lds_d[threadIdx.x]) lds_d[threadIdx.x] = od;
             const int64_t oi = lds_i[threadIdx.x + s], ow = lds_w[threadIdx.x + s];
             const int64_t ci = lds_i[threadIdx.x], cw = lds_w[threadIdx.x];
             bool take;
@@ -298,6 +307,7 @@ __global__ void __launch_bounds__(kArgBlock) k_best_batch(int32_t G, const int64
         best[g] = lds_i[0];
         num[g] = lds_w[0];
         den[g] = n - lds_i[0];
+        if (D) D[g] = lds_d[0];
     }
 }
 
@@ -310,42 +320,57 @@ __global__ void k_in_set_batch(int64_t N, const int32_t *pos, const int32_t *nod
 
 }  // namespace
 
-void launch_extract_batch(const BatchExtractArgs &a, hipStream_t s) {
+void BatchExtractScratch::ensure(int64_t N, int32_t G) {
+    if (N <= cap_n && G <= cap_g) return;
+    const size_t n = (size_t)(N > 0 ? N : 1);
+    k0.alloc(n);
+    k1.alloc(n);
+    v0.alloc(n);
+    v1.alloc(n);
+    g0.alloc(n);
+    g1.alloc(n);
+    pos.alloc(n);
+    hist.alloc(n);
+    rev.alloc(n);
+    W.alloc(n);
+    best.alloc((size_t)(G > 0 ? G : 1));
+    const size_t tb = radix_sort_tmp_bytes(N), tb2 = exclusive_scan_tmp_bytes(N);
+    tmp.alloc(tb > tb2 ? tb : tb2);
+    cap_n = N;
+    cap_g = G;
+}
+
+void launch_extract_batch(const BatchExtractArgs &a, BatchExtractScratch &sc, hipStream_t s) {
     const int64_t N = a.N;
     int gbits = 1;
     while (gbits < 31 && ((int64_t)1 << gbits) < (int64_t)a.G) ++gbits;
-    DBuf<uint64_t> k0((size_t)N), k1((size_t)N);
-    DBuf<uint32_t> v0((size_t)N), v1((size_t)N), g0((size_t)N), g1((size_t)N);
-    DBuf<int32_t> pos((size_t)N);
-    DBuf<int64_t> hist((size_t)N), rev((size_t)N), W((size_t)N), best((size_t)a.G);
-    size_t tb = radix_sort_tmp_bytes(N), tb2 = exclusive_scan_tmp_bytes(N);
-    DBuf<char> tmp(tb > tb2 ? tb : tb2);
+    sc.ensure(N, a.G);
     const unsigned gn = grid_for(N, 256);
-    hipLaunchKernelGGL(k_keys, dim3(gn), dim3(256), 0, s, (int32_t)N, a.L64, k0.p, v0.p);
+    hipLaunchKernelGGL(k_keys, dim3(gn), dim3(256), 0, s, (int32_t)N, a.L64, sc.k0.p, sc.v0.p);
     bool alt = false;
-    radix_sort_u64(k0.p, v0.p, k1.p, v1.p, N, 64, tmp.p, tmp.bytes(), &alt, s);
-    uint32_t *vals = alt ? v1.p : v0.p;
-    uint32_t *vals_alt = alt ? v0.p : v1.p;
-    hipLaunchKernelGGL(k_graph_keys, dim3(gn), dim3(256), 0, s, N, vals, a.node_graph, g0.p);
+    radix_sort_u64(sc.k0.p, sc.v0.p, sc.k1.p, sc.v1.p, N, 64, sc.tmp.p, sc.tmp.bytes(), &alt, s);
+    uint32_t *vals = alt ? sc.v1.p : sc.v0.p;
+    uint32_t *vals_alt = alt ? sc.v0.p : sc.v1.p;
+    hipLaunchKernelGGL(k_graph_keys, dim3(gn), dim3(256), 0, s, N, vals, a.node_graph, sc.g0.p);
     bool alt2 = false;
-    radix_sort_u32(g0.p, vals, g1.p, vals_alt, N, gbits, tmp.p, tmp.bytes(), &alt2, s);
+    radix_sort_u32(sc.g0.p, vals, sc.g1.p, vals_alt, N, gbits, sc.tmp.p, sc.tmp.bytes(), &alt2, s);
     const uint32_t *asc = alt2 ? vals_alt : vals;
     hipLaunchKernelGGL(k_local_positions, dim3(gn), dim3(256), 0, s, N, asc, a.node_graph,
-                       a.node_ptr, pos.p);
-    hipLaunchKernelGGL(k_fill_i64, dim3(gn), dim3(256), 0, s, N, hist.p);
+                       a.node_ptr, sc.pos.p);
+    hipLaunchKernelGGL(k_fill_i64, dim3(gn), dim3(256), 0, s, N, sc.hist.p);
     if (a.M > 0)
         hipLaunchKernelGGL(k_edge_min_pos_batch, dim3(grid_for(a.M, 256)), dim3(256), 0, s, a.M,
-                           a.gsrc, a.gdst, a.node_graph, a.node_ptr, pos.p,
-                           (unsigned long long *)hist.p);
-    hipLaunchKernelGGL(k_reverse<int64_t>, dim3(gn), dim3(256), 0, s, N, hist.p, rev.p);
-    exclusive_scan_i64(rev.p, rev.p, N, nullptr, tmp.p, tmp.bytes(), s);
-    hipLaunchKernelGGL(k_suffix<int64_t>, dim3(gn), dim3(256), 0, s, N, rev.p, hist.p, W.p);
+                           a.gsrc, a.gdst, a.node_graph, a.node_ptr, sc.pos.p,
+                           (unsigned long long *)sc.hist.p);
+    hipLaunchKernelGGL(k_reverse<int64_t>, dim3(gn), dim3(256), 0, s, N, sc.hist.p, sc.rev.p);
+    exclusive_scan_i64(sc.rev.p, sc.rev.p, N, nullptr, sc.tmp.p, sc.tmp.bytes(), s);
+    hipLaunchKernelGGL(k_suffix<int64_t>, dim3(gn), dim3(256), 0, s, N, sc.rev.p, sc.hist.p,
+                       sc.W.p);
     hipLaunchKernelGGL(k_best_batch, dim3((unsigned)a.G), dim3(kArgBlock), 0, s, a.G, a.node_ptr,
-                       N, W.p, best.p, a.num, a.den);
-    hipLaunchKernelGGL(k_in_set_batch, dim3(gn), dim3(256), 0, s, N, pos.p, a.node_graph, best.p,
-                       a.in_set);
+                       N, sc.W.p, a.L64, sc.best.p, a.num, a.den, a.D);
+    hipLaunchKernelGGL(k_in_set_batch, dim3(gn), dim3(256), 0, s, N, sc.pos.p, a.node_graph,
+                       sc.best.p, a.in_set);
     LOWD_HIP(hipGetLastError());
-    LOWD_HIP(hipStreamSynchronize(s));   // scratch is released on return
 }
 
 }  // namespace lowd

@@ -304,7 +304,7 @@ __device__ __forceinline__ void stage_descs(int32_t nph, const PhaseDesc *descs,
 // Runs the wave's tiles of one LDS-tier phase: the first from the
 // prefetched buffer, any further ones (phase wider than the workgroup)
 // loaded into that same buffer afterwards.
-template <class St, bool kWeighted, class LPtr>
+template <int W, class St, bool kWeighted, class LPtr>
 __device__ __forceinline__ void serial_phase(Tile<St, kWeighted> &tl, const PhaseDesc &d, int wave,
                                              int lane, const int32_t *__restrict__ tile_center,
                                              const uint32_t *__restrict__ slot_leaf,
@@ -312,15 +312,15 @@ __device__ __forceinline__ void serial_phase(Tile<St, kWeighted> &tl, const Phas
                                              const float *__restrict__ slot_w, LPtr L) {
     if (wave >= d.T[0]) return;
     run_tile(tl, lane, slot_x, L);
-    for (int32_t t = wave + kTailWaves; t < d.T[0]; t += kTailWaves) {
+    for (int32_t t = wave + W; t < d.T[0]; t += W) {
         load_tile(tl, d, t, lane, tile_center, slot_leaf, slot_x, slot_w);
         run_tile(tl, lane, slot_x, L);
     }
 }
 
 // The phase loop of the LDS tier: phases [0, nph) whose descriptors are
-// staged at sd, node loads in LDS at L (local ids).
-template <class St, bool kWeighted, class LPtr>
+// staged at sd, node loads in LDS at L (local ids), W waves.
+template <int W, class St, bool kWeighted, class LPtr>
 __device__ __forceinline__ void run_phases(int32_t nph, const PhaseDesc *sd, int wave, int lane,
                                            const int32_t *__restrict__ tile_center,
                                            const uint32_t *__restrict__ slot_leaf,
@@ -336,14 +336,34 @@ __device__ __forceinline__ void run_phases(int32_t nph, const PhaseDesc *sd, int
             db = desc_from_lds(sd, p + 1, lane);
             if (wave < db.T[0]) load_tile(tb, db, wave, lane, tile_center, slot_leaf, slot_x, slot_w);
         }
-        serial_phase(ta, da, wave, lane, tile_center, slot_leaf, slot_x, slot_w, L);
+        serial_phase<W>(ta, da, wave, lane, tile_center, slot_leaf, slot_x, slot_w, L);
         lds_barrier();
         if (!has_b) break;
         if (p + 2 < nph) {
             da = desc_from_lds(sd, p + 2, lane);
             if (wave < da.T[0]) load_tile(ta, da, wave, lane, tile_center, slot_leaf, slot_x, slot_w);
         }
-        serial_phase(tb, db, wave, lane, tile_center, slot_leaf, slot_x, slot_w, L);
+        serial_phase<W>(tb, db, wave, lane, tile_center, slot_leaf, slot_x, slot_w, L);
+        lds_barrier();
+    }
+}
+
+// The same loop without the second tile buffer: fewer registers, so more
+// workgroups fit on a CU and hide each other's latency instead.
+template <int W, class St, bool kWeighted, class LPtr>
+__device__ __forceinline__ void run_phases_single(int32_t nph, const PhaseDesc *sd, int wave,
+                                                  int lane,
+                                                  const int32_t *__restrict__ tile_center,
+                                                  const uint32_t *__restrict__ slot_leaf,
+                                                  typename St::X *__restrict__ slot_x,
+                                                  const float *__restrict__ slot_w, LPtr L) {
+    Tile<St, kWeighted> tl;
+    for (int32_t p = 0; p < nph; ++p) {
+        const PhaseDesc d = desc_from_lds(sd, p, lane);
+        for (int32_t t = wave; t < d.T[0]; t += W) {
+            load_tile(tl, d, t, lane, tile_center, slot_leaf, slot_x, slot_w);
+            run_tile(tl, lane, slot_x, L);
+        }
         lds_barrier();
     }
 }
@@ -424,7 +444,8 @@ k_tail(int32_t nph, const PhaseDesc *__restrict__ descs, const int32_t *__restri
         sL[ntail + 1] = St::infinite();     // dummy leaf of padding rows
     }
     __syncthreads();
-    run_phases<St, kWeighted>(nph, sd, wave, lane, tile_center, slot_leaf, slot_x, slot_w, sL);
+    run_phases<kTailWaves, St, kWeighted>(nph, sd, wave, lane, tile_center, slot_leaf, slot_x,
+                                          slot_w, sL);
     __syncthreads();
     for (int32_t i = threadIdx.x; i < ntail; i += kTailBlock) E[tail_next[i]] = sL[i];
 }
@@ -432,18 +453,19 @@ k_tail(int32_t nph, const PhaseDesc *__restrict__ descs, const int32_t *__restri
 // ------------------------------------------------------- batched graphs --
 // Many independent unweighted graphs in one persistent launch: each
 // workgroup takes the next graph from a queue (graphs ordered by edge count,
-// largest first), builds its loads in LDS (deg / 2: a sum of halves, exact
-// in any order), runs `sweeps` sweeps of the graph's phases from LDS, and
-// writes the loads out.  Node ids of a graph are local (0..n_g-1); n_g and
-// n_g + 1 are its dummy entries.
-template <class St>
-__global__ void __launch_bounds__(kTailBlock)
+// largest first), stages its loads and phase descriptors in LDS, runs
+// `sweeps` sweeps of the graph's phases from LDS, and writes the loads back,
+// so consecutive launches continue the same iteration.  Node ids of a graph
+// are local (0..n_g-1); n_g and n_g + 1 are its dummy entries.  W waves per
+// workgroup, with or without the prefetching tile buffer (the tuned launch
+// shape; the result does not depend on it).
+template <class St, int W, bool kPrefetch>
+__global__ void __launch_bounds__(W * kWave)
 k_batch(int32_t G, const int32_t *__restrict__ order, unsigned *__restrict__ queue,
-        const int64_t *__restrict__ node_ptr, const int64_t *__restrict__ edge_ptr,
-        const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
-        const int64_t *__restrict__ desc_ptr, const PhaseDesc *__restrict__ descs,
-        const int32_t *__restrict__ tile_center, const uint32_t *__restrict__ slot_leaf,
-        typename St::X *__restrict__ slot_x, int32_t sweeps, double *__restrict__ Lout) {
+        const int64_t *__restrict__ node_ptr, const int64_t *__restrict__ desc_ptr,
+        const PhaseDesc *__restrict__ descs, const int32_t *__restrict__ tile_center,
+        const uint32_t *__restrict__ slot_leaf, typename St::X *__restrict__ slot_x,
+        int32_t sweeps, typename St::L *__restrict__ Lstate) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ int32_t s_graph;
     const int lane = threadIdx.x & (kWave - 1);
@@ -456,40 +478,54 @@ k_batch(int32_t G, const int32_t *__restrict__ order, unsigned *__restrict__ que
         __syncthreads();
         const int32_t g = s_graph;
         if (g < 0) break;
-        const int32_t n = (int32_t)(node_ptr[g + 1] - node_ptr[g]);
-        const int64_t e0 = edge_ptr[g];
-        const int64_t m = edge_ptr[g + 1] - e0;
+        const int64_t n0 = node_ptr[g];
+        const int32_t n = (int32_t)(node_ptr[g + 1] - n0);
         const int32_t nph = (int32_t)(desc_ptr[g + 1] - desc_ptr[g]);
         PhaseDesc *sd = reinterpret_cast<PhaseDesc *>(lds_raw);
         typename St::L *sL = reinterpret_cast<typename St::L *>(lds_raw + tail_desc_bytes(nph));
-        double *cnt = reinterpret_cast<double *>(sL);   // degree halves, then loads in place
         stage_descs(nph, descs + desc_ptr[g], sd);
-        // init: each edge adds one half to both ends (kept in FP64 first)
-        for (int32_t u = threadIdx.x; u < n; u += kTailBlock) cnt[u] = 0.0;
-        __syncthreads();
-        for (int64_t e = threadIdx.x; e < m; e += kTailBlock) {
-            atomicAdd(&cnt[src[e0 + e]], 0.5);
-            atomicAdd(&cnt[dst[e0 + e]], 0.5);
-        }
-        __syncthreads();
-        static_assert(sizeof(typename St::L) == sizeof(double), "loads converted in place");
-        for (int32_t u = threadIdx.x; u < n; u += kTailBlock) {
-            const double v = cnt[u];
-            sL[u] = St::from_f64(v);
-        }
+        for (int32_t u = threadIdx.x; u < n; u += W * kWave) sL[u] = Lstate[n0 + u];
         if (threadIdx.x == 0) {
             sL[n] = St::from_f64(0.0);
             sL[n + 1] = St::infinite();
         }
         __syncthreads();
-        for (int32_t t = 0; t < sweeps; ++t)
-            run_phases<St, false>(nph, sd, wave, lane, tile_center, slot_leaf, slot_x, nullptr,
-                                  sL);
+        for (int32_t t = 0; t < sweeps; ++t) {
+            if (kPrefetch)
+                run_phases<W, St, false>(nph, sd, wave, lane, tile_center, slot_leaf, slot_x,
+                                         nullptr, sL);
+            else
+                run_phases_single<W, St, false>(nph, sd, wave, lane, tile_center, slot_leaf,
+                                                slot_x, nullptr, sL);
+        }
         __syncthreads();
-        const int64_t n0 = node_ptr[g];
-        for (int32_t u = threadIdx.x; u < n; u += kTailBlock) Lout[n0 + u] = St::to_f64(sL[u]);
+        for (int32_t u = threadIdx.x; u < n; u += W * kWave) Lstate[n0 + u] = sL[u];
         __syncthreads();   // LDS reuse by the next graph
     }
+}
+
+// Initial loads of a batch: deg(u) / 2 (a sum of halves, exact).
+__global__ void k_batch_degrees(int64_t M, const int32_t *gsrc, const int32_t *gdst,
+                                int32_t *deg) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < M;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        atomicAdd(&deg[gsrc[e]], 1);
+        atomicAdd(&deg[gdst[e]], 1);
+    }
+}
+
+template <class St>
+__global__ void k_batch_init_loads(int64_t N, const int32_t *deg, typename St::L *Lstate) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < N;
+         u += (int64_t)gridDim.x * blockDim.x)
+        Lstate[u] = St::from_f64((double)deg[u] * 0.5);
+}
+
+template <class St>
+__global__ void k_batch_loads_f64(int64_t N, const typename St::L *Lstate, double *L64) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < N;
+         u += (int64_t)gridDim.x * blockDim.x)
+        L64[u] = St::to_f64(Lstate[u]);
 }
 
 __global__ void k_zero_u32(unsigned *p) { *p = 0u; }
@@ -675,19 +711,48 @@ static void sweep_launchers(SweepLaunch &fn) {
         hipLaunchKernelGGL((k_loads_to_f64<St>), dim3(grid_for(n, 256)), dim3(256), 0, s, n, home,
                            (const typename St::L *)E, out);
     };
-    fn.batch = [](int32_t G, const int32_t *order, unsigned *queue, const int64_t *node_ptr,
-                  const int64_t *edge_ptr, const int32_t *src, const int32_t *dst,
-                  const int64_t *desc_ptr, const PhaseDesc *descs, const int32_t *tile_center,
-                  const uint32_t *slot_leaf, void *slot_x, int32_t sweeps, double *Lout,
-                  size_t lds, int32_t blocks, hipStream_t s) {
+    fn.batch = [](int32_t shape, int32_t G, const int32_t *order, unsigned *queue,
+                  const int64_t *node_ptr, const int64_t *desc_ptr, const PhaseDesc *descs,
+                  const int32_t *tile_center, const uint32_t *slot_leaf, void *slot_x,
+                  int32_t sweeps, void *Lstate, size_t lds, int32_t blocks, hipStream_t s) {
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, queue);
-        hipLaunchKernelGGL((k_batch<St>), dim3((unsigned)blocks), dim3(kTailBlock), lds, s, G,
-                           order, queue, node_ptr, edge_ptr, src, dst, desc_ptr, descs,
-                           tile_center, slot_leaf, (typename St::X *)slot_x, sweeps, Lout);
+#define LOWD_BATCH_CASE(W, PF)                                                                 \
+    case W * 2 + PF:                                                                           \
+        hipLaunchKernelGGL((k_batch<St, W, PF>), dim3((unsigned)blocks), dim3(W * kWave), lds,  \
+                           s, G, order, queue, node_ptr, desc_ptr, descs, tile_center,         \
+                           slot_leaf, (typename St::X *)slot_x, sweeps,                        \
+                           (typename St::L *)Lstate);                                          \
+        break;
+        switch (shape) {
+            LOWD_BATCH_CASE(4, 0)
+            LOWD_BATCH_CASE(4, 1)
+            LOWD_BATCH_CASE(8, 0)
+            LOWD_BATCH_CASE(8, 1)
+            default: fail(-1, "unsupported batch workgroup shape");
+        }
+#undef LOWD_BATCH_CASE
     };
-    fn.set_batch_lds = [](size_t bytes) {
-        LOWD_HIP(hipFuncSetAttribute((const void *)k_batch<St>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    fn.set_batch_lds = [](int32_t shape, size_t bytes) {
+        const void *k = shape == 8 ? (const void *)k_batch<St, 4, false>
+                        : shape == 9 ? (const void *)k_batch<St, 4, true>
+                        : shape == 16 ? (const void *)k_batch<St, 8, false>
+                        : shape == 17 ? (const void *)k_batch<St, 8, true>
+                                      : nullptr;
+        if (!k) fail(-1, "unsupported batch workgroup shape");
+        LOWD_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    };
+    fn.batch_init_loads = [](int64_t N, int64_t M, const int32_t *gsrc, const int32_t *gdst,
+                             int32_t *deg, void *Lstate, hipStream_t s) {
+        LOWD_HIP(hipMemsetAsync(deg, 0, (size_t)(N > 0 ? N : 1) * sizeof(int32_t), s));
+        if (M > 0)
+            hipLaunchKernelGGL(k_batch_degrees, dim3(grid_for(M, 256)), dim3(256), 0, s, M, gsrc,
+                               gdst, deg);
+        hipLaunchKernelGGL((k_batch_init_loads<St>), dim3(grid_for(N, 256)), dim3(256), 0, s, N,
+                           deg, (typename St::L *)Lstate);
+    };
+    fn.batch_loads_f64 = [](int64_t N, const void *Lstate, double *L64, hipStream_t s) {
+        hipLaunchKernelGGL((k_batch_loads_f64<St>), dim3(grid_for(N, 256)), dim3(256), 0, s, N,
+                           (const typename St::L *)Lstate, L64);
     };
     fn.x_bytes = sizeof(typename St::X);
     fn.l_bytes = sizeof(typename St::L);

@@ -167,12 +167,15 @@ struct SweepLaunch {
                    hipStream_t s);
     void (*read_loads)(int32_t n, const uint32_t *home, const void *E, double *out,
                        hipStream_t s);
-    void (*batch)(int32_t G, const int32_t *order, unsigned *queue, const int64_t *node_ptr,
-                  const int64_t *edge_ptr, const int32_t *src, const int32_t *dst,
-                  const int64_t *desc_ptr, const PhaseDesc *descs, const int32_t *tile_center,
-                  const uint32_t *slot_leaf, void *slot_x, int32_t sweeps, double *Lout,
-                  size_t lds, int32_t blocks, hipStream_t s);
-    void (*set_batch_lds)(size_t bytes);
+    // the batched form; shape = 2 * waves per workgroup (4 or 8) + prefetch (0/1)
+    void (*batch)(int32_t shape, int32_t G, const int32_t *order, unsigned *queue,
+                  const int64_t *node_ptr, const int64_t *desc_ptr, const PhaseDesc *descs,
+                  const int32_t *tile_center, const uint32_t *slot_leaf, void *slot_x,
+                  int32_t sweeps, void *Lstate, size_t lds, int32_t blocks, hipStream_t s);
+    void (*set_batch_lds)(int32_t shape, size_t bytes);
+    void (*batch_init_loads)(int64_t N, int64_t M, const int32_t *gsrc, const int32_t *gdst,
+                             int32_t *deg, void *Lstate, hipStream_t s);
+    void (*batch_loads_f64)(int64_t N, const void *Lstate, double *L64, hipStream_t s);
     size_t x_bytes;
     size_t l_bytes;
 };

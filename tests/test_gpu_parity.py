@@ -342,6 +342,54 @@ def test_batch_f32k_within_tolerance():
             assert np.max(np.abs(L[a:b] - Lo)) <= 1e-5 * np.max(np.abs(Lo)), i
 
 
+def test_prepared_batch_in_steps_equals_oracle():
+    """A prepared, autotuned batch run in steps (2 + 3 sweeps) equals the
+    oracle's 5 sweeps per graph; D_g is the graph's largest load; a reset
+    starts over."""
+    gs = batch_graphs(40, 7)
+    T = 5
+    b = lowd.Batch(gs, "f64", tune=True)
+    log(f"prepared batch {b.info()}")
+    b.iterate(2)
+    b.iterate(3)
+    b.extract(loads=True)
+    L = b.load.cpu().numpy()
+    D = b.D.cpu().numpy()
+    num, den = b.num.cpu().numpy(), b.den.cpu().numpy()
+    for i, g in enumerate(gs):
+        a, c = b.node_ptr[i], b.node_ptr[i + 1]
+        xo, Lo, *_ = oracle_run(g, T, 16)
+        assert np.array_equal(L[a:c], Lo), i
+        assert D[i] == np.max(Lo), i
+        ro = oracle.extract(g.n, g.src, g.dst, None, Lo)
+        assert (num[i], den[i]) == (ro["num"], ro["den"]), i
+    b.reset()
+    b.iterate(T)
+    b.extract(loads=True)
+    assert np.array_equal(b.load.cpu().numpy(), L)
+    b.close()
+
+
+@pytest.mark.parametrize("shape", ["8,1,1", "8,0,2", "4,1,2", "4,0,4"])
+def test_batch_every_launch_shape_is_bit_exact(shape, monkeypatch):
+    monkeypatch.setenv("LOWD_BATCH_SHAPE", shape)
+    gs = batch_graphs(30, 11)
+    T = 4
+    b = lowd.Batch(gs, "f64")
+    info = b.info()
+    log(f"shape {shape}: {info}")
+    w, pf, pc = (int(v) for v in shape.split(","))
+    assert (info["waves"], info["prefetch"]) == (w, pf)
+    b.iterate(T)
+    b.extract(loads=True)
+    L = b.load.cpu().numpy()
+    for i, g in enumerate(gs):
+        a, c = b.node_ptr[i], b.node_ptr[i + 1]
+        xo, Lo, *_ = oracle_run(g, T, 16)
+        assert np.array_equal(L[a:c], Lo), i
+    b.close()
+
+
 def test_batch_rejects_bad_graphs():
     g = synth.canonical(5, np.array([0, 1]), np.array([1, 2]))
     bad = synth.Graph(3, np.array([0, 1], np.int32), np.array([1, 5], np.int32), None)
