@@ -281,6 +281,23 @@ lowd_status lowd_batch_extract(lowd_batch *b, uint8_t *in_set, int64_t *num, int
                                double *D, double *load, void *stream);
 
 /*
+ * lowd_batch_retire -- stops iterating the graphs that have converged: after
+ * lowd_batch_extract, every graph whose relative gap (D_g - rho_g) / rho_g
+ * (rho_g = num_g / den_g; a graph without edges counts as converged) is at
+ * most tol leaves the set that later lowd_batch_iterate calls sweep; the
+ * others keep their order (largest first).  lowd_batch_reset restores all.
+ * A retired graph keeps its state, so its densest set and loads stay
+ * available; its certified gap is at most tol.
+ *   num, den, D   [device] the arrays the last lowd_batch_extract filled
+ *   active        [host] out: graphs still iterating; may be NULL
+ *   active_edges  [host] out: their edges; may be NULL
+ * Synchronises `stream`.
+ */
+lowd_status lowd_batch_retire(lowd_batch *b, const int64_t *num, const int64_t *den,
+                              const double *D, double tol, int32_t *active, int64_t *active_edges,
+                              void *stream);
+
+/*
  * lowd_batch_info --
  *   info [host] int64[9] out: G, total nodes, total edges, total phases,
  *        most phases of one graph, waves per workgroup, prefetching tile

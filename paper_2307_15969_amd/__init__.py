@@ -61,13 +61,14 @@ def lib() -> C.CDLL:
         L.lowd_batch_iterate.argtypes = [vp, i32, vp]
         L.lowd_batch_extract.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.lowd_batch_info.argtypes = [vp, vp]
+        L.lowd_batch_retire.argtypes = [vp, vp, vp, vp, C.c_double, P(i32), P(i64), vp]
         L.lowd_batch_free.argtypes = [vp]
         L.lowd_batch_free.restype = None
         for f in (L.lowd_prune, L.lowd_init_loads, L.lowd_iterate, L.lowd_check,
                   L.lowd_extract_densest, L.lowd_read_state, L.lowd_schedule_export,
                   L.lowd_solver_info, L.lowd_batch_solve, L.lowd_schedule_build, L.lowd_reset_loads,
                   L.lowd_batch_prepare, L.lowd_batch_reset, L.lowd_batch_iterate,
-                  L.lowd_batch_extract, L.lowd_batch_info):
+                  L.lowd_batch_extract, L.lowd_batch_info, L.lowd_batch_retire):
             f.restype = C.c_int32
         _lib = L
     return _lib
@@ -297,6 +298,15 @@ class Batch:
         _check(lib().lowd_batch_extract(self._h, _ptr(self.in_set), _ptr(self.num),
                                         _ptr(self.den), _ptr(self.D),
                                         _ptr(self.load) if loads else None, _stream(stream)))
+
+    def retire(self, tol: float, stream=None):
+        """Stops iterating the graphs whose gap after the last extract() is at
+        most tol; returns (graphs still iterating, their edges)."""
+        a = C.c_int32()
+        ae = C.c_int64()
+        _check(lib().lowd_batch_retire(self._h, _ptr(self.num), _ptr(self.den), _ptr(self.D),
+                                       float(tol), C.byref(a), C.byref(ae), _stream(stream)))
+        return a.value, ae.value
 
     def gaps(self):
         """Per-graph relative gap (D_g - rho_g) / rho_g after extract()."""

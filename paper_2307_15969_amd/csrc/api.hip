@@ -427,7 +427,8 @@ struct lowd_batch {
     std::vector<int64_t> node_ptr_h, edge_ptr_h;
     int64_t total_phases = 0, max_phases = 0;
     DBuf<int64_t> node_ptr, edge_ptr, desc_ptr, slot_edge;
-    DBuf<int32_t> gsrc, gdst, node_graph, order, tile_center, deg;
+    DBuf<int32_t> gsrc, gdst, node_graph, order_all, order, active, tile_center, deg;
+    DBuf<int64_t> active_edges;
     DBuf<PhaseDesc> descs;
     DBuf<uint32_t> slot_leaf;
     DBuf<char> slot_x, Lstate;
@@ -456,6 +457,8 @@ static void batch_reset(lowd_batch *b, hipStream_t s) {
     const int64_t nslots = (int64_t)(b->slot_leaf.n);
     if (b->M > 0) b->fn.init_slots(nslots, b->slot_edge.p, nullptr, b->slot_x.p, nullptr, s);
     b->fn.batch_init_loads(b->N, b->M, b->gsrc.p, b->gdst.p, b->deg.p, b->Lstate.p, s);
+    launch_activate_all(b->G, b->order_all.p, b->edge_ptr.p, b->order.p, b->active.p,
+                        b->active_edges.p, s);
     LOWD_HIP(hipGetLastError());
 }
 
@@ -468,7 +471,7 @@ static void batch_launch(lowd_batch *b, int32_t sweeps, hipStream_t s) {
         LOWD_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
         hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (err == hipSuccess) {
-            b->fn.batch(b->shape(), b->G, b->order.p, b->queue.p, b->node_ptr.p, b->desc_ptr.p,
+            b->fn.batch(b->shape(), b->active.p, b->order.p, b->queue.p, b->node_ptr.p, b->desc_ptr.p,
                         b->descs.p, b->tile_center.p, b->slot_leaf.p, b->slot_x.p, sweeps,
                         b->Lstate.p, b->lds, b->blocks, cs);
             err = hipStreamEndCapture(cs, &b->graph);
@@ -656,7 +659,10 @@ lowd_status lowd_batch_prepare(int32_t G, const int64_t *node_ptr, const int64_t
         upload(b->edge_ptr, b->edge_ptr_h, s);
         upload(b->desc_ptr, desc_ptr, s);
         upload(b->slot_edge, slot_edge, s);
-        upload(b->order, order, s);
+        upload(b->order_all, order, s);
+        b->order.alloc((size_t)G);
+        b->active.alloc(1);
+        b->active_edges.alloc(1);
         upload(b->tile_center, tile_center, s);
         upload(b->descs, descs, s);
         upload(b->slot_leaf, slot_leaf, s);
@@ -732,6 +738,27 @@ lowd_status lowd_batch_extract(lowd_batch *b, uint8_t *in_set, int64_t *num, int
         if (load)
             LOWD_HIP(hipMemcpyAsync(load, b->L64.p, (size_t)b->N * sizeof(double),
                                     hipMemcpyDeviceToDevice, s));
+    });
+}
+
+lowd_status lowd_batch_retire(lowd_batch *b, const int64_t *num, const int64_t *den,
+                              const double *D, double tol, int32_t *active, int64_t *active_edges,
+                              void *stream) {
+    return guarded([&] {
+        if (!b) fail(LOWD_E_ARG, "batch is NULL");
+        if (!num || !den || !D) fail(LOWD_E_ARG, "num/den/D is NULL");
+        if (!(tol >= 0.0)) fail(LOWD_E_ARG, "tol must be >= 0");
+        hipStream_t s = (hipStream_t)stream;
+        launch_retire(b->G, b->order_all.p, b->edge_ptr.p, num, den, D, tol, b->order.p,
+                      b->active.p, b->active_edges.p, s);
+        LOWD_HIP(hipGetLastError());
+        int32_t a = 0;
+        int64_t ae = 0;
+        LOWD_HIP(hipMemcpyAsync(&a, b->active.p, sizeof(a), hipMemcpyDeviceToHost, s));
+        LOWD_HIP(hipMemcpyAsync(&ae, b->active_edges.p, sizeof(ae), hipMemcpyDeviceToHost, s));
+        LOWD_HIP(hipStreamSynchronize(s));
+        if (active) *active = a;
+        if (active_edges) *active_edges = ae;
     });
 }
 

@@ -461,7 +461,8 @@ k_tail(int32_t nph, const PhaseDesc *__restrict__ descs, const int32_t *__restri
 // shape; the result does not depend on it).
 template <class St, int W, bool kPrefetch>
 __global__ void __launch_bounds__(W * kWave)
-k_batch(int32_t G, const int32_t *__restrict__ order, unsigned *__restrict__ queue,
+k_batch(const int32_t *__restrict__ active, const int32_t *__restrict__ order,
+        unsigned *__restrict__ queue,
         const int64_t *__restrict__ node_ptr, const int64_t *__restrict__ desc_ptr,
         const PhaseDesc *__restrict__ descs, const int32_t *__restrict__ tile_center,
         const uint32_t *__restrict__ slot_leaf, typename St::X *__restrict__ slot_x,
@@ -470,10 +471,11 @@ k_batch(int32_t G, const int32_t *__restrict__ order, unsigned *__restrict__ que
     __shared__ int32_t s_graph;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const unsigned G = (unsigned)*active;   // graphs still iterating, order[0..G)
     for (;;) {
         if (threadIdx.x == 0) {
             const unsigned k = atomicAdd(queue, 1u);
-            s_graph = k < (unsigned)G ? order[k] : -1;
+            s_graph = k < G ? order[k] : -1;
         }
         __syncthreads();
         const int32_t g = s_graph;
@@ -501,6 +503,70 @@ k_batch(int32_t G, const int32_t *__restrict__ order, unsigned *__restrict__ que
         __syncthreads();
         for (int32_t u = threadIdx.x; u < n; u += W * kWave) Lstate[n0 + u] = sL[u];
         __syncthreads();   // LDS reuse by the next graph
+    }
+}
+
+// Retires converged graphs: keeps, in order, the graphs of `all` whose
+// relative gap (D_g - rho_g) / rho_g with rho_g = num_g / den_g exceeds tol
+// (a graph without edges has D_g = rho_g = 0 and is converged); writes the
+// kept list, its length and its edge count.  One workgroup.
+constexpr int kRetireBlock = 1024;
+__global__ void __launch_bounds__(kRetireBlock)
+k_retire(int32_t G, const int32_t *all, const int64_t *edge_ptr, const int64_t *num,
+         const int64_t *den, const double *D, double tol, int32_t *order, int32_t *active,
+         int64_t *active_edges) {
+    __shared__ int32_t s_cnt[kRetireBlock];
+    __shared__ int64_t s_edges[kRetireBlock];
+    __shared__ int32_t s_base;
+    __shared__ int64_t s_etot;
+    if (threadIdx.x == 0) {
+        s_base = 0;
+        s_etot = 0;
+    }
+    __syncthreads();
+    for (int32_t i0 = 0; i0 < G; i0 += kRetireBlock) {
+        const int32_t i = i0 + (int32_t)threadIdx.x;
+        int32_t keep = 0, g = -1;
+        if (i < G) {
+            g = all[i];
+            const double rho = (double)num[g] / (double)den[g];
+            const double gap = rho > 0.0 ? (D[g] - rho) / rho : (D[g] > 0.0 ? 1.0e300 : 0.0);
+            keep = gap > tol ? 1 : 0;
+        }
+        s_cnt[threadIdx.x] = keep;
+        s_edges[threadIdx.x] = keep ? edge_ptr[g + 1] - edge_ptr[g] : 0;
+        __syncthreads();
+        // inclusive scan of the flags (Hillis-Steele in LDS) and sum of edges
+        for (int d = 1; d < kRetireBlock; d <<= 1) {
+            const int32_t a = threadIdx.x >= (unsigned)d ? s_cnt[threadIdx.x - d] : 0;
+            const int64_t b = threadIdx.x >= (unsigned)d ? s_edges[threadIdx.x - d] : 0;
+            __syncthreads();
+            s_cnt[threadIdx.x] += a;
+            s_edges[threadIdx.x] += b;
+            __syncthreads();
+        }
+        if (keep) order[s_base + s_cnt[threadIdx.x] - 1] = g;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s_base += s_cnt[kRetireBlock - 1];
+            s_etot += s_edges[kRetireBlock - 1];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *active = s_base;
+        *active_edges = s_etot;
+    }
+}
+
+// the full list again (a reset)
+__global__ void k_activate_all(int32_t G, const int32_t *all, const int64_t *edge_ptr,
+                               int32_t *order, int32_t *active, int64_t *active_edges) {
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < G; i += gridDim.x * blockDim.x)
+        order[i] = all[i];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *active = G;
+        *active_edges = edge_ptr[G];
     }
 }
 
@@ -711,7 +777,7 @@ static void sweep_launchers(SweepLaunch &fn) {
         hipLaunchKernelGGL((k_loads_to_f64<St>), dim3(grid_for(n, 256)), dim3(256), 0, s, n, home,
                            (const typename St::L *)E, out);
     };
-    fn.batch = [](int32_t shape, int32_t G, const int32_t *order, unsigned *queue,
+    fn.batch = [](int32_t shape, const int32_t *active, const int32_t *order, unsigned *queue,
                   const int64_t *node_ptr, const int64_t *desc_ptr, const PhaseDesc *descs,
                   const int32_t *tile_center, const uint32_t *slot_leaf, void *slot_x,
                   int32_t sweeps, void *Lstate, size_t lds, int32_t blocks, hipStream_t s) {
@@ -719,7 +785,7 @@ static void sweep_launchers(SweepLaunch &fn) {
 #define LOWD_BATCH_CASE(W, PF)                                                                 \
     case W * 2 + PF:                                                                           \
         hipLaunchKernelGGL((k_batch<St, W, PF>), dim3((unsigned)blocks), dim3(W * kWave), lds,  \
-                           s, G, order, queue, node_ptr, desc_ptr, descs, tile_center,         \
+                           s, active, order, queue, node_ptr, desc_ptr, descs, tile_center,    \
                            slot_leaf, (typename St::X *)slot_x, sweeps,                        \
                            (typename St::L *)Lstate);                                          \
         break;
@@ -766,6 +832,19 @@ void get_sweep_launchers(int32_t state, bool weighted, SweepLaunch &fn) {
         if (weighted) sweep_launchers<StateF32K, true>(fn);
         else sweep_launchers<StateF32K, false>(fn);
     }
+}
+
+void launch_retire(int32_t G, const int32_t *all, const int64_t *edge_ptr, const int64_t *num,
+                   const int64_t *den, const double *D, double tol, int32_t *order,
+                   int32_t *active, int64_t *active_edges, hipStream_t s) {
+    hipLaunchKernelGGL(k_retire, dim3(1), dim3(kRetireBlock), 0, s, G, all, edge_ptr, num, den, D,
+                       tol, order, active, active_edges);
+}
+
+void launch_activate_all(int32_t G, const int32_t *all, const int64_t *edge_ptr, int32_t *order,
+                         int32_t *active, int64_t *active_edges, hipStream_t s) {
+    hipLaunchKernelGGL(k_activate_all, dim3(grid_for(G, 256)), dim3(256), 0, s, G, all, edge_ptr,
+                       order, active, active_edges);
 }
 
 void launch_stats(int64_t n, const double *L64, double *partial, int32_t nb, double *out,

@@ -168,7 +168,7 @@ struct SweepLaunch {
     void (*read_loads)(int32_t n, const uint32_t *home, const void *E, double *out,
                        hipStream_t s);
     // the batched form; shape = 2 * waves per workgroup (4 or 8) + prefetch (0/1)
-    void (*batch)(int32_t shape, int32_t G, const int32_t *order, unsigned *queue,
+    void (*batch)(int32_t shape, const int32_t *active, const int32_t *order, unsigned *queue,
                   const int64_t *node_ptr, const int64_t *desc_ptr, const PhaseDesc *descs,
                   const int32_t *tile_center, const uint32_t *slot_leaf, void *slot_x,
                   int32_t sweeps, void *Lstate, size_t lds, int32_t blocks, hipStream_t s);
@@ -183,5 +183,11 @@ struct SweepLaunch {
 void get_sweep_launchers(int32_t state, bool weighted, SweepLaunch &fn);
 void launch_stats(int64_t n, const double *L64, double *partial, int32_t nb, double *out,
                   hipStream_t s);
+// batches: keep the graphs (of `all`, in order) whose gap exceeds tol, or all
+void launch_retire(int32_t G, const int32_t *all, const int64_t *edge_ptr, const int64_t *num,
+                   const int64_t *den, const double *D, double tol, int32_t *order,
+                   int32_t *active, int64_t *active_edges, hipStream_t s);
+void launch_activate_all(int32_t G, const int32_t *all, const int64_t *edge_ptr, int32_t *order,
+                         int32_t *active, int64_t *active_edges, hipStream_t s);
 
 }  // namespace lowd

@@ -51,6 +51,19 @@ def test_argument_errors_need_no_device():
     L.lowd_solver_free(None)
     assert L.lowd_prune(0, 0, None, None, None, None, None, None, None, None, None, None,
                         None) == -1
+    # batches
+    b = C.c_void_p()
+    assert L.lowd_batch_prepare(0, None, None, None, None, 0, 16, 0, C.byref(b), None) == -1
+    ptr = np.array([0, 3], dtype=np.int64)
+    zero = np.array([0, 0], dtype=np.int64)
+    vp = lambda a: a.ctypes.data_as(C.c_void_p)
+    assert L.lowd_batch_prepare(1, vp(ptr), vp(zero), None, None, 0, 16, 2, C.byref(b),
+                                None) == -1                               # tune must be 0/1
+    assert L.lowd_batch_prepare(1, vp(ptr), vp(zero), None, None, 0, 17, 0, C.byref(b),
+                                None) == -1                               # star_max
+    assert L.lowd_batch_iterate(None, 1, None) == -1
+    assert L.lowd_batch_retire(None, None, None, None, 0.0, None, None, None) == -1
+    L.lowd_batch_free(None)
 
 
 def test_host_schedule_rejects_invalid_edges():

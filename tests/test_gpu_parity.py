@@ -370,6 +370,49 @@ def test_prepared_batch_in_steps_equals_oracle():
     b.close()
 
 
+def test_batch_retire_freezes_converged_graphs():
+    """After extract + retire(tol), retired graphs keep the oracle's state at
+    the retirement sweep while the others continue; the retired set is the
+    graphs whose oracle gap is within tol (parity on the set itself)."""
+    gs = batch_graphs(40, 13)
+    T1, T2, tol = 10, 5, 1e-4
+    b = lowd.Batch(gs, "f64")
+    b.iterate(T1)
+    b.extract()
+    num, den, D = b.num.cpu().numpy(), b.den.cpu().numpy(), b.D.cpu().numpy()
+    expect_active = []
+    for i, g in enumerate(gs):
+        xo, Lo, *_ = oracle_run(g, T1, 16)
+        ro = oracle.extract(g.n, g.src, g.dst, None, Lo)
+        assert (num[i], den[i]) == (ro["num"], ro["den"]) and D[i] == np.max(Lo, initial=0.0), i
+        rho = ro["num"] / ro["den"]
+        Do = np.max(Lo, initial=0.0)
+        gap = (Do - rho) / rho if rho > 0 else (np.inf if Do > 0 else 0.0)
+        if gap > tol:
+            expect_active.append(i)
+    active, active_edges = b.retire(tol)
+    log(f"retire: {active} active of {len(gs)}")
+    assert active == len(expect_active)
+    assert active_edges == sum(gs[i].m for i in expect_active)
+    assert 0 < active < len(gs)
+    b.iterate(T2)
+    b.extract(loads=True)
+    L = b.load.cpu().numpy()
+    for i, g in enumerate(gs):
+        a, c = b.node_ptr[i], b.node_ptr[i + 1]
+        T = T1 + T2 if i in expect_active else T1
+        xo, Lo, *_ = oracle_run(g, T, 16)
+        assert np.array_equal(L[a:c], Lo), i
+    b.reset()
+    b.iterate(T1 + T2)
+    b.extract(loads=True)
+    for i, g in enumerate(gs):
+        a, c = b.node_ptr[i], b.node_ptr[i + 1]
+        xo, Lo, *_ = oracle_run(g, T1 + T2, 16)
+        assert np.array_equal(b.load.cpu().numpy()[a:c], Lo), i
+    b.close()
+
+
 @pytest.mark.parametrize("shape", ["8,1,1", "8,0,2", "4,1,2", "4,0,4"])
 def test_batch_every_launch_shape_is_bit_exact(shape, monkeypatch):
     monkeypatch.setenv("LOWD_BATCH_SHAPE", shape)
