@@ -456,7 +456,7 @@ struct lowd_batch {
 static void batch_reset(lowd_batch *b, hipStream_t s) {
     const int64_t nslots = (int64_t)(b->slot_leaf.n);
     if (b->M > 0) b->fn.init_slots(nslots, b->slot_edge.p, nullptr, b->slot_x.p, nullptr, s);
-    b->fn.batch_init_loads(b->N, b->M, b->gsrc.p, b->gdst.p, b->deg.p, b->Lstate.p, s);
+    b->fn.batch_init_loads(b->N, b->deg.p, b->Lstate.p, s);
     launch_activate_all(b->G, b->order_all.p, b->edge_ptr.p, b->order.p, b->active.p,
                         b->active_edges.p, s);
     LOWD_HIP(hipGetLastError());
@@ -671,6 +671,7 @@ lowd_status lowd_batch_prepare(int32_t G, const int64_t *node_ptr, const int64_t
         b->Lstate.alloc((size_t)(N > 0 ? N : 1) * b->fn.l_bytes);
         b->L64.alloc((size_t)(N > 0 ? N : 1));
         b->deg.alloc((size_t)(N > 0 ? N : 1));
+        launch_batch_degrees(N, M, b->gsrc.p, b->gdst.p, b->deg.p, s);
         b->queue.alloc(1);
         b->lds = lds_need;
 

@@ -807,12 +807,7 @@ static void sweep_launchers(SweepLaunch &fn) {
         if (!k) fail(-1, "unsupported batch workgroup shape");
         LOWD_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     };
-    fn.batch_init_loads = [](int64_t N, int64_t M, const int32_t *gsrc, const int32_t *gdst,
-                             int32_t *deg, void *Lstate, hipStream_t s) {
-        LOWD_HIP(hipMemsetAsync(deg, 0, (size_t)(N > 0 ? N : 1) * sizeof(int32_t), s));
-        if (M > 0)
-            hipLaunchKernelGGL(k_batch_degrees, dim3(grid_for(M, 256)), dim3(256), 0, s, M, gsrc,
-                               gdst, deg);
+    fn.batch_init_loads = [](int64_t N, const int32_t *deg, void *Lstate, hipStream_t s) {
         hipLaunchKernelGGL((k_batch_init_loads<St>), dim3(grid_for(N, 256)), dim3(256), 0, s, N,
                            deg, (typename St::L *)Lstate);
     };
@@ -845,6 +840,14 @@ void launch_activate_all(int32_t G, const int32_t *all, const int64_t *edge_ptr,
                          int32_t *active, int64_t *active_edges, hipStream_t s) {
     hipLaunchKernelGGL(k_activate_all, dim3(grid_for(G, 256)), dim3(256), 0, s, G, all, edge_ptr,
                        order, active, active_edges);
+}
+
+void launch_batch_degrees(int64_t N, int64_t M, const int32_t *gsrc, const int32_t *gdst,
+                          int32_t *deg, hipStream_t s) {
+    LOWD_HIP(hipMemsetAsync(deg, 0, (size_t)(N > 0 ? N : 1) * sizeof(int32_t), s));
+    if (M > 0)
+        hipLaunchKernelGGL(k_batch_degrees, dim3(grid_for(M, 256)), dim3(256), 0, s, M, gsrc, gdst,
+                           deg);
 }
 
 void launch_stats(int64_t n, const double *L64, double *partial, int32_t nb, double *out,

@@ -173,8 +173,7 @@ struct SweepLaunch {
                   const int32_t *tile_center, const uint32_t *slot_leaf, void *slot_x,
                   int32_t sweeps, void *Lstate, size_t lds, int32_t blocks, hipStream_t s);
     void (*set_batch_lds)(int32_t shape, size_t bytes);
-    void (*batch_init_loads)(int64_t N, int64_t M, const int32_t *gsrc, const int32_t *gdst,
-                             int32_t *deg, void *Lstate, hipStream_t s);
+    void (*batch_init_loads)(int64_t N, const int32_t *deg, void *Lstate, hipStream_t s);
     void (*batch_loads_f64)(int64_t N, const void *Lstate, double *L64, hipStream_t s);
     size_t x_bytes;
     size_t l_bytes;
@@ -183,6 +182,9 @@ struct SweepLaunch {
 void get_sweep_launchers(int32_t state, bool weighted, SweepLaunch &fn);
 void launch_stats(int64_t n, const double *L64, double *partial, int32_t nb, double *out,
                   hipStream_t s);
+// batches: node degrees (once per batch)
+void launch_batch_degrees(int64_t N, int64_t M, const int32_t *gsrc, const int32_t *gdst,
+                          int32_t *deg, hipStream_t s);
 // batches: keep the graphs (of `all`, in order) whose gap exceeds tol, or all
 void launch_retire(int32_t G, const int32_t *all, const int64_t *edge_ptr, const int64_t *num,
                    const int64_t *den, const double *D, double tol, int32_t *order,
