@@ -159,6 +159,28 @@ lowd_status lowd_extract_densest(lowd_solver *s, uint8_t *in_set, int64_t *num_u
                                  void *stream);
 
 /*
+ * lowd_ldd_readout -- the locally-dense decomposition (Problem 2, Property
+ * 2) read from the current loads: with the nodes ranked by descending load
+ * (the reverse of lowd_extract_densest's order) and f(k) the weight of the
+ * edges among the top k nodes, level j ends at the largest k maximising
+ * (f(k) - f(k_{j-1})) / (k - k_{j-1}) (k_0 = 0), until k = n.  Level 0 is
+ * the set lowd_extract_densest returns; at the limit of the iteration the
+ * levels are the decomposition B_1 < B_2 < ... and lambda_j = (f_end[j] -
+ * f_end[j-1]) / (k_end[j] - k_end[j-1]) its level values.  Unit weights are
+ * decided exactly; weighted graphs in FP64.  Corollary 1 then bounds the
+ * density of any k-node subgraph by the envelope of (k_end, f_end) at k,
+ * over k.
+ *   level    [device] int32[n] out: level of each node (0 = densest)
+ *   k_end    [device] int64[n] out: level ends k_1 .. k_L (first L entries)
+ *   f_end    [device] double[n] out: f(k_1) .. f(k_L) (exact integers for
+ *            unit weights)
+ *   nlevels  [host] out: L
+ * Synchronises `stream`.
+ */
+lowd_status lowd_ldd_readout(lowd_solver *s, int32_t *level, int64_t *k_end, double *f_end,
+                             int64_t *nlevels, void *stream);
+
+/*
  * lowd_read_state -- copies the current fractions and loads out, in the
  * caller's edge order: x[e] = f_e(src[e]) and load[u] = l_u, both FP64
  * (LOWD_STATE_F32K: the FP32 fraction widened, and the load as its value

@@ -22,6 +22,7 @@ _lib = None
 _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 _u8p = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
 _f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
 
 
 def build(force: bool = True) -> str:
@@ -53,8 +54,10 @@ def _load():
                                      C.POINTER(C.c_double)]
         lib.oracle_extract.argtypes = [i64, i64, _i32p, _i32p, fptr, _f64p, _u8p, C.POINTER(i64),
                                        C.POINTER(i64), C.POINTER(C.c_double), C.POINTER(i64)]
+        lib.oracle_ldd.argtypes = [i64, i64, _i32p, _i32p, fptr, _f64p, _i32p, _i64p, _f64p,
+                                   C.POINTER(i64)]
         for f in (lib.oracle_prune, lib.oracle_schedule, lib.oracle_init, lib.oracle_sweep,
-                  lib.oracle_stats, lib.oracle_extract):
+                  lib.oracle_stats, lib.oracle_extract, lib.oracle_ldd):
             f.restype = C.c_int
         _lib = lib
     return _lib
@@ -141,6 +144,34 @@ def extract(n: int, src: np.ndarray, dst: np.ndarray, w: Optional[np.ndarray], L
                               C.byref(nw), C.byref(den)), "oracle_extract")
     return dict(in_set=in_set, best_i=int(bi.value), num=int(nu.value), num_w=float(nw.value),
                 den=int(den.value))
+
+
+def ldd(n: int, src: np.ndarray, dst: np.ndarray, w: Optional[np.ndarray], L: np.ndarray):
+    """Locally-dense decomposition read from loads L (prefixes of the
+    descending load order) -> dict(level int32[n], k_end int64[L], f_end
+    float64[L]); lambda_j = (f_end[j] - f_end[j-1]) / (k_end[j] - k_end[j-1])."""
+    lib = _load()
+    level = np.zeros(n, dtype=np.int32)
+    k_end = np.zeros(max(n, 1), dtype=np.int64)
+    f_end = np.zeros(max(n, 1), dtype=np.float64)
+    nl = C.c_int64(0)
+    w, wp = _wptr(w)
+    _check(lib.oracle_ldd(n, src.size, src, dst, wp, np.ascontiguousarray(L, dtype=np.float64),
+                          level, k_end, f_end, C.byref(nl)), "oracle_ldd")
+    k = int(nl.value)
+    return dict(level=level, k_end=k_end[:k], f_end=f_end[:k])
+
+
+def dks_bound(k_end: np.ndarray, f_end: np.ndarray, k: int) -> float:
+    """Corollary 1: an upper bound on the density of any k-node subgraph from
+    the decomposition's levels (the concave envelope of f at k, over k); at
+    k = |B_j| it is the density of B_j itself."""
+    kp, fp = 0, 0.0
+    for kj, fj in zip(k_end, f_end):
+        if k <= kj:
+            return (fp + (k - kp) * (fj - fp) / (kj - kp)) / k
+        kp, fp = int(kj), float(fj)
+    raise ValueError("k exceeds the node count")
 
 
 def solve(n: int, src: np.ndarray, dst: np.ndarray, w: Optional[np.ndarray], T: int,

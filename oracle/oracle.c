@@ -334,3 +334,73 @@ int oracle_extract(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
     free(asc); free(pos); free(Wi); free(Wd);
     return ORACLE_OK;
 }
+
+/* ------------------------------------------------------------------------ *
+ * Locally-dense decomposition read from a load vector (Problem 2, Property
+ * 2).  The nodes are ranked by descending load: the reverse of the
+ * extraction's stable ascending order on (load, id).  Only prefixes of that
+ * ranking are candidate sets.  Let f(k) be the weight of the edges with
+ * both endpoints among the top k nodes (f(0) = 0).  Then, as in the
+ * definition of B_i, starting from k_0 = 0:
+ *     k_j = the largest k > k_{j-1} maximising
+ *           (f(k) - f(k_{j-1})) / (k - k_{j-1}),
+ * until k_j = n.  Level j-1 holds the nodes of rank k_{j-1} .. k_j - 1, and
+ * lambda_j is that maximal ratio.  At the limit of the iteration the
+ * ranking is consistent with the decomposition and this is the exact LDD.
+ * Unit weights compare the ratios exactly by cross-multiplication in
+ * integers; weighted graphs compare FP64 quotients.
+ *   level  [n]  out: level of each node (0 = densest)
+ *   k_end  [n]  out: k_1 .. k_L (L levels)
+ *   f_end  [n]  out: f(k_1) .. f(k_L)
+ * ------------------------------------------------------------------------ */
+int oracle_ldd(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const float *w,
+               const double *L, int32_t *level, int64_t *k_end, double *f_end, int64_t *nlevels)
+{
+    if (n <= 0 || !level || !k_end || !f_end || !nlevels) return ORACLE_E_ARG;
+    int32_t *asc = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    int64_t *rank = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int64_t *fi = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    double *fd = (double *)calloc((size_t)n + 1, sizeof(double));
+    if (!asc || !rank || !fi || !fd) { free(asc); free(rank); free(fi); free(fd); return ORACLE_E_NOMEM; }
+    for (int64_t u = 0; u < n; ++u) asc[u] = (int32_t)u;
+    g_sort_L = L;
+    qsort(asc, (size_t)n, sizeof(int32_t), cmp_load_then_id);
+    for (int64_t i = 0; i < n; ++i) rank[asc[i]] = n - 1 - i;
+    /* an edge is inside the top k exactly when k > the larger rank of its ends */
+    for (int64_t e = 0; e < m; ++e) {
+        int64_t r = rank[src[e]] > rank[dst[e]] ? rank[src[e]] : rank[dst[e]];
+        if (w) fd[r + 1] = fd[r + 1] + (double)w[e];
+        else fi[r + 1] += 1;
+    }
+    for (int64_t k = 1; k <= n; ++k) {
+        fi[k] += fi[k - 1];
+        fd[k] = fd[k] + fd[k - 1];
+    }
+    int64_t L_count = 0, kp = 0;
+    while (kp < n) {
+        int64_t best = kp + 1;
+        for (int64_t k = kp + 2; k <= n; ++k) {
+            int at_least;
+            if (w) {
+                double a = (fd[k] - fd[kp]) / (double)(k - kp);
+                double b = (fd[best] - fd[kp]) / (double)(best - kp);
+                at_least = a >= b;
+            } else {
+                /* (f(k)-f(kp))/(k-kp) >= (f(best)-f(kp))/(best-kp), exactly */
+                __int128 a = (__int128)(fi[k] - fi[kp]) * (best - kp);
+                __int128 b = (__int128)(fi[best] - fi[kp]) * (k - kp);
+                at_least = a >= b;
+            }
+            if (at_least) best = k;
+        }
+        k_end[L_count] = best;
+        f_end[L_count] = w ? fd[best] : (double)fi[best];
+        for (int64_t i = 0; i < n; ++i)
+            if (rank[i] >= kp && rank[i] < best) level[i] = (int32_t)L_count;
+        ++L_count;
+        kp = best;
+    }
+    *nlevels = L_count;
+    free(asc); free(rank); free(fi); free(fd);
+    return ORACLE_OK;
+}

@@ -50,6 +50,7 @@ def lib() -> C.CDLL:
         L.lowd_extract_densest.argtypes = [vp, vp, P(i64), P(C.c_double), P(i64),
                                            P(C.c_double), P(C.c_double), vp]
         L.lowd_read_state.argtypes = [vp, vp, vp, vp]
+        L.lowd_ldd_readout.argtypes = [vp, vp, vp, vp, P(i64), vp]
         L.lowd_schedule_export.argtypes = [vp, vp, vp, P(i32)]
         L.lowd_solver_info.argtypes = [vp, vp]
         L.lowd_schedule_build.argtypes = [i32, i64, vp, vp, i32, vp, vp, P(i32)]
@@ -66,6 +67,7 @@ def lib() -> C.CDLL:
         L.lowd_batch_free.restype = None
         for f in (L.lowd_prune, L.lowd_init_loads, L.lowd_iterate, L.lowd_check,
                   L.lowd_extract_densest, L.lowd_read_state, L.lowd_schedule_export,
+                  L.lowd_ldd_readout,
                   L.lowd_solver_info, L.lowd_batch_solve, L.lowd_schedule_build, L.lowd_reset_loads,
                   L.lowd_batch_prepare, L.lowd_batch_reset, L.lowd_batch_iterate,
                   L.lowd_batch_extract, L.lowd_batch_info, L.lowd_batch_retire):
@@ -181,6 +183,19 @@ class Solver:
                                           _stream(stream)))
         return dict(in_set=in_set, num=int(nu.value), num_w=float(nw.value), den=int(den.value),
                     D=float(D.value), gap=float(gap.value))
+
+    def ldd(self, stream=None) -> dict:
+        """The locally-dense decomposition read from the current loads:
+        level per node (device int32), level ends k_end and f_end (numpy)."""
+        torch = _torch()
+        level = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        k_end = torch.empty(self.n, dtype=torch.int64, device=self.device)
+        f_end = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        nl = C.c_int64()
+        _check(lib().lowd_ldd_readout(self._h, _ptr(level), _ptr(k_end), _ptr(f_end),
+                                      C.byref(nl), _stream(stream)))
+        L = int(nl.value)
+        return dict(level=level, k_end=k_end[:L].cpu().numpy(), f_end=f_end[:L].cpu().numpy())
 
     def read_state(self, stream=None):
         torch = _torch()

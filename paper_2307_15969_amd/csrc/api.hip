@@ -118,6 +118,8 @@ struct lowd_solver {
     DBuf<float> slot_w;
     DBuf<double> L64, stats_partial, stats_out;
     ExtractScratch ex;
+    LddScratch ldd;
+    DBuf<uint8_t> ldd_in_set;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int32_t ntail = 0;
@@ -331,6 +333,29 @@ lowd_status lowd_extract_densest(lowd_solver *sv, uint8_t *in_set, int64_t *num_
         if (D) *D = o[0];
         double rho = wnum / (double)dn;
         if (gap) *gap = rho > 0.0 ? (o[0] - rho) / rho : (o[0] > 0.0 ? 1.0e300 : 0.0);
+    });
+}
+
+lowd_status lowd_ldd_readout(lowd_solver *sv, int32_t *level, int64_t *k_end, double *f_end,
+                             int64_t *nlevels, void *stream) {
+    return guarded([&] {
+        if (!sv) fail(LOWD_E_ARG, "solver is NULL");
+        if (!level || !k_end || !f_end || !nlevels) fail(LOWD_E_ARG, "NULL output");
+        hipStream_t s = (hipStream_t)stream;
+        loads_f64(sv, s);
+        if (sv->ldd_in_set.n < (size_t)sv->n) sv->ldd_in_set.alloc((size_t)sv->n);
+        ExtractArgs a;
+        a.n = sv->n;
+        a.m = sv->m;
+        a.weighted = sv->weighted;
+        a.L64 = sv->L64.p;
+        a.row_ptr = sv->csr.row_ptr.p;
+        a.inc = sv->csr.inc.p;
+        a.src = sv->e_src.p;
+        a.dst = sv->e_dst.p;
+        a.w = sv->weighted ? sv->e_w.p : nullptr;
+        a.in_set = sv->ldd_in_set.p;
+        launch_ldd(a, sv->ex, sv->ldd, level, k_end, f_end, nlevels, s);
     });
 }
 

@@ -37,6 +37,20 @@ struct ExtractScratch {
 // unweighted graphs, FP64 bits otherwise).
 void launch_extract(const ExtractArgs &a, ExtractScratch &sc, hipStream_t s);
 
+// Locally-dense decomposition read from the loads: the extraction, then the
+// upper concave hull of the induced weights of the top-k prefixes of the
+// descending load order.  Synchronises the stream.
+struct LddScratch {
+    int64_t cap_points = -1, cap_chunks = -1;
+    DBuf<int64_t> ck, qk, hk, cnt, off, nv;
+    DBuf<int64_t> cf, qf, hf;   // int64 or (reinterpreted) FP64
+    DBuf<char> tmp;
+    int64_t host_q = 0;
+    void ensure(int64_t points, int64_t chunks);
+};
+void launch_ldd(const ExtractArgs &a, ExtractScratch &sc, LddScratch &ls, int32_t *level,
+                int64_t *k_end, double *f_end, int64_t *nlevels, hipStream_t s);
+
 // Extraction for many unweighted graphs whose nodes and edges are
 // concatenated (global node ids); enqueued on the stream, scratch owned by
 // the caller.

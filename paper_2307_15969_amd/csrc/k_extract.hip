@@ -224,6 +224,169 @@ void launch_extract(const ExtractArgs &a, ExtractScratch &sc, hipStream_t s) {
 
 }  // namespace lowd
 
+// ------------------------------------------------ decomposition read-out --
+// The locally-dense decomposition read from the loads (Problem 2, Property
+// 2): with the nodes ranked by descending load (the reverse of the
+// extraction's order) and f(k) the weight induced by the top k nodes
+// (f(k) = W(S_{n-k}), f(0) = 0), each level ends at the largest k that
+// maximises the average (f(k) - f(k_prev)) / (k - k_prev) beyond the
+// previous level.  Those ends are the strict corners of the upper concave
+// hull of the points (k, f(k)), k = 0..n.  The hull is built in two steps:
+// every chunk of 256 points reduces to its own hull vertices (one thread
+// per chunk, a monotone chain), and one thread chains the surviving
+// candidates in order (a vertex of the whole hull is a vertex of its chunk's
+// hull).  Unit weights decide every turn exactly in 128-bit integers.
+namespace lowd {
+namespace {
+
+constexpr int64_t kHullChunk = 256;
+
+template <class T>
+__device__ __forceinline__ T f_at(const T *W, int64_t n, int64_t k) {
+    return k == 0 ? (T)0 : W[n - k];
+}
+
+// is a not strictly above the segment from o to b?  (cross product >= 0)
+__device__ __forceinline__ bool not_above(int64_t ok, int64_t of, int64_t ak, int64_t af,
+                                          int64_t bk, int64_t bf) {
+    const __int128 l = (__int128)(ak - ok) * (__int128)(bf - of);
+    const __int128 r = (__int128)(af - of) * (__int128)(bk - ok);
+    return l >= r;
+}
+__device__ __forceinline__ bool not_above(int64_t ok, double of, int64_t ak, double af,
+                                          int64_t bk, double bf) {
+    return (double)(ak - ok) * (bf - of) >= (af - of) * (double)(bk - ok);
+}
+
+template <class T>
+__global__ void k_hull_chunks(int64_t n, const T *W, int64_t *ck, T *cf, int64_t *cnt) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t lo = c * kHullChunk;
+    if (lo > n) return;
+    const int64_t hi = lo + kHullChunk < n + 1 ? lo + kHullChunk : n + 1;
+    int64_t *sk = ck + lo;
+    T *sf = cf + lo;
+    int64_t top = 0;
+    for (int64_t k = lo; k < hi; ++k) {
+        const T f = f_at(W, n, k);
+        while (top >= 2 && not_above(sk[top - 2], sf[top - 2], sk[top - 1], sf[top - 1], k, f))
+            --top;
+        sk[top] = k;
+        sf[top] = f;
+        ++top;
+    }
+    cnt[c] = top;
+}
+
+template <class T>
+__global__ void k_hull_compact(int64_t chunks, const int64_t *ck, const T *cf, const int64_t *cnt,
+                               const int64_t *off, int64_t *qk, T *qf) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= chunks) return;
+    const int64_t lo = c * kHullChunk;
+    for (int64_t i = 0; i < cnt[c]; ++i) {
+        qk[off[c] + i] = ck[lo + i];
+        qf[off[c] + i] = cf[lo + i];
+    }
+}
+
+// one thread: the monotone chain over the candidates; hk/hf receive the hull
+// vertices k_0 = 0 < k_1 < ... < k_L = n and *nv = L + 1
+template <class T>
+__global__ void k_hull_chain(int64_t q, const int64_t *qk, const T *qf, int64_t *hk, T *hf,
+                             int64_t *nv) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int64_t top = 0;
+    for (int64_t i = 0; i < q; ++i) {
+        const int64_t k = qk[i];
+        const T f = qf[i];
+        while (top >= 2 && not_above(hk[top - 2], hf[top - 2], hk[top - 1], hf[top - 1], k, f))
+            --top;
+        hk[top] = k;
+        hf[top] = f;
+        ++top;
+    }
+    *nv = top;
+}
+
+// level of every node: the number of level ends k_j (j >= 1) at or below its
+// descending rank; and the ends as output arrays
+template <class T>
+__global__ void k_hull_levels(int32_t n, const int32_t *pos, const int64_t *hk, const T *hf,
+                              const int64_t *nv, int32_t *level, int64_t *k_end, double *f_end) {
+    const int64_t L = *nv - 1;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = (int64_t)n - 1 - pos[u];
+        int64_t a = 1, b = L + 1;   // first j in [1, L] with hk[j] > r
+        while (a < b) {
+            const int64_t mid = (a + b) >> 1;
+            if (hk[mid] <= r) a = mid + 1;
+            else b = mid;
+        }
+        level[u] = (int32_t)(a - 1);
+        if (u < L) {
+            k_end[u] = hk[u + 1];
+            f_end[u] = (double)hf[u + 1];
+        }
+    }
+}
+
+template <class T>
+void ldd_impl(int32_t n, const ExtractScratch &sc, LddScratch &ls, int32_t *level,
+              int64_t *k_end, double *f_end, hipStream_t s) {
+    const T *W = (const T *)sc.W.p;
+    const int64_t pts = (int64_t)n + 1;
+    const int64_t chunks = (pts + kHullChunk - 1) / kHullChunk;
+    ls.ensure(pts, chunks);
+    int64_t *ck = ls.ck.p, *qk = ls.qk.p, *hk = ls.hk.p;
+    T *cf = (T *)ls.cf.p, *qf = (T *)ls.qf.p, *hf = (T *)ls.hf.p;
+    hipLaunchKernelGGL(k_hull_chunks<T>, dim3(grid_for(chunks, 64)), dim3(64), 0, s, (int64_t)n, W,
+                       ck, cf, ls.cnt.p);
+    int64_t *total = ls.cnt.p + chunks;   // the scan's total, one past the counts
+    exclusive_scan_i64(ls.cnt.p, ls.off.p, chunks, total, ls.tmp.p, ls.tmp.bytes(), s);
+    hipLaunchKernelGGL(k_hull_compact<T>, dim3(grid_for(chunks, 64)), dim3(64), 0, s, chunks, ck,
+                       cf, ls.cnt.p, ls.off.p, qk, qf);
+    LOWD_HIP(hipMemcpyAsync(&ls.host_q, total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    LOWD_HIP(hipStreamSynchronize(s));
+    hipLaunchKernelGGL(k_hull_chain<T>, dim3(1), dim3(64), 0, s, ls.host_q, qk, qf, hk, hf,
+                       ls.nv.p);
+    hipLaunchKernelGGL(k_hull_levels<T>, dim3(grid_for(n, 256)), dim3(256), 0, s, n, sc.pos.p, hk,
+                       hf, ls.nv.p, level, k_end, f_end);
+    LOWD_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void LddScratch::ensure(int64_t points, int64_t chunks) {
+    if (points <= cap_points && chunks <= cap_chunks) return;
+    ck.alloc((size_t)points);
+    cf.alloc((size_t)points);
+    qk.alloc((size_t)points);
+    qf.alloc((size_t)points);
+    hk.alloc((size_t)points);
+    hf.alloc((size_t)points);
+    cnt.alloc((size_t)chunks + 1);
+    off.alloc((size_t)chunks);
+    nv.alloc(1);
+    tmp.alloc(exclusive_scan_tmp_bytes(chunks));
+    cap_points = points;
+    cap_chunks = chunks;
+}
+
+void launch_ldd(const ExtractArgs &a, ExtractScratch &sc, LddScratch &ls, int32_t *level,
+                int64_t *k_end, double *f_end, int64_t *nlevels, hipStream_t s) {
+    launch_extract(a, sc, s);   // order, positions and W(S_i)
+    if (a.weighted) ldd_impl<double>(a.n, sc, ls, level, k_end, f_end, s);
+    else ldd_impl<int64_t>(a.n, sc, ls, level, k_end, f_end, s);
+    int64_t nv = 0;
+    LOWD_HIP(hipMemcpyAsync(&nv, ls.nv.p, sizeof(nv), hipMemcpyDeviceToHost, s));
+    LOWD_HIP(hipStreamSynchronize(s));
+    *nlevels = nv - 1;
+}
+
+}  // namespace lowd
+
 // ------------------------------------------------ batched extraction -----
 // The same extraction for many graphs at once (unweighted): one stable sort
 // of all loads, then a stable sort by graph id, gives every graph's

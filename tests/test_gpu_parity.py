@@ -302,6 +302,59 @@ def test_chunglu_1m_10m_fp64_is_bit_exact():
     assert np.array_equal(ex["in_set"].cpu().numpy(), ro["in_set"])
 
 
+# ------------------------------------------- decomposition read-out --
+@pytest.mark.parametrize("T", [0, 3, 40])
+@pytest.mark.parametrize("name,g", GRAPHS, ids=[n for n, _ in GRAPHS])
+def test_ldd_readout_matches_oracle(name, g, T):
+    """The decomposition read from the loads equals the oracle's read-out of
+    its own (bit-identical) loads: unit weights exactly; weighted graphs (FP64
+    sums in different orders) to 1e-9 on f and on every level end."""
+    log(f"ldd {name} T={T}")
+    sv = lowd.Solver(g.n, g.src, g.dst, g.w, "f64")
+    sv.iterate(T)
+    r = sv.ldd()
+    xo, Lo, *_ = oracle_run(g, T, 16)
+    ro = oracle.ldd(g.n, g.src, g.dst, g.w, Lo)
+    log(f"  {len(r['k_end'])} levels")
+    if g.w is None:
+        assert np.array_equal(r["k_end"], ro["k_end"])
+        assert np.array_equal(r["f_end"], ro["f_end"])
+        assert np.array_equal(r["level"].cpu().numpy(), ro["level"])
+    else:
+        # a near-collinear corner may be decided differently under other
+        # rounding; the envelopes must agree wherever both have a corner
+        common = np.intersect1d(r["k_end"], ro["k_end"])
+        assert common.size >= 0.9 * max(len(r["k_end"]), len(ro["k_end"]))
+        fg = dict(zip(r["k_end"].tolist(), r["f_end"].tolist()))
+        fo = dict(zip(ro["k_end"].tolist(), ro["f_end"].tolist()))
+        for k in common.tolist():
+            assert abs(fg[k] - fo[k]) <= 1e-9 * max(1.0, abs(fo[k])), k
+    sv.close()
+
+
+def test_ldd_readout_properties_at_full_size():
+    """At full size (Chung-Lu 1M nodes / 9.86M edges, 40 sweeps): level 0 is
+    the extracted densest set, the level values decrease strictly, the last
+    level ends at (n, m), and every level is contiguous in the load order."""
+    g = synth.workload(1, seed=1)
+    sv = lowd.Solver(g.n, g.src, g.dst, None, "f64")
+    sv.iterate(40)
+    ex = sv.extract()
+    r = sv.ldd()
+    ke, fe = r["k_end"], r["f_end"]
+    log(f"workload1 ldd: {len(ke)} levels, first {ke[0]} nodes / {fe[0]} edges")
+    assert (ke[0], int(fe[0])) == (ex["den"], ex["num"])
+    assert ke[-1] == g.n and int(fe[-1]) == g.m
+    assert np.all(np.diff(ke) > 0)
+    lam = np.diff(np.concatenate([[0.0], fe])) / np.diff(np.concatenate([[0], ke]))
+    assert np.all(np.diff(lam) < 0)
+    level = r["level"].cpu().numpy()
+    assert np.array_equal(level == 0, ex["in_set"].cpu().numpy().astype(bool))
+    counts = np.bincount(level, minlength=len(ke))
+    assert np.array_equal(np.cumsum(counts), ke)
+    sv.close()
+
+
 # -------------------------------------------------------- batched form --
 def batch_graphs(count, seed):
     gs = synth.batch_of_graphs(count, seed=seed, m_lo=20, m_hi=3000)

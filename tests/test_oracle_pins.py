@@ -130,7 +130,7 @@ def _random_graphs(count, nmin, nmax, weighted, seed):
 
 @pytest.mark.parametrize("weighted", [False, True])
 def test_limit_equals_brute_force_ldd(weighted):
-    """Theorem 4 and Property 2: the converged loads equal the per-node value
+    """Theorem 3 and Property 2: the converged loads equal the per-node value
     lambda of the locally-dense decomposition, computed from its definition."""
     for g in _random_graphs(25, 4, 9, weighted, 7 + weighted):
         _, lam = brute_force_ldd(g.n, g.src, g.dst, g.w)
@@ -398,3 +398,94 @@ def test_certificate_on_unit_weights():
         n = g.n
         if r["D"] - r["rho"] < 1.0 / (n * (n - 1)):
             assert Fraction(r["num"], r["den"]) == rho
+
+
+# ------------------------------------------------- LDD read-out (Problem 2) --
+def _levels_from_readout(r):
+    """nested sets B_1 .. B_L and lambda_j as exact fractions of f, k"""
+    level = r["level"]
+    sets, lams = [], []
+    kp, fp = 0, Fraction(0)
+    for j, (k, f) in enumerate(zip(r["k_end"], r["f_end"])):
+        sets.append(frozenset(np.flatnonzero(level <= j).tolist()))
+        fj = Fraction(f)
+        lams.append((fj - fp) / (int(k) - kp))
+        kp, fp = int(k), fj
+    return sets, lams
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_ldd_readout_equals_brute_force_ldd(weighted):
+    """Problem 2 / Property 2: the decomposition read from converged loads
+    (prefixes of the descending load order, largest maximiser per level) is
+    the locally-dense decomposition by its definition over all subsets: the
+    same nested sets and the same lambda per level."""
+    for g in _random_graphs(25, 4, 9, weighted, 21 + weighted):
+        levels, lam = brute_force_ldd(g.n, g.src, g.dst, g.w)
+        r = converge(g, 6000)
+        ro = oracle.ldd(g.n, g.src, g.dst, g.w, r["L"])
+        sets, lams = _levels_from_readout(ro)
+        assert sets == levels, (g.src, g.dst, g.w)
+        for a, b in zip(lams, [lam[min(B - (levels[i - 1] if i else frozenset()))]
+                               for i, B in enumerate(levels)]):
+            if weighted:
+                assert abs(float(a) - float(b)) <= 1e-9 * max(1.0, abs(float(b)))
+            else:
+                assert a == b
+
+
+def test_ldd_readout_closed_forms():
+    """Two disjoint cliques K_6 and K_3 plus a pendant path: levels K_6
+    (lambda 5/2), K_3 (lambda 1), then the path (n-1)/n-type tail."""
+    edges = [(i, j) for i in range(6) for j in range(i + 1, 6)]
+    edges += [(6 + i, 6 + j) for i in range(3) for j in range(i + 1, 3)]
+    edges += [(9, 10), (10, 11)]
+    g = graph_from_edges(12, edges)
+    r = converge(g, 3000)
+    ro = oracle.ldd(g.n, g.src, g.dst, None, r["L"])
+    sets, lams = _levels_from_readout(ro)
+    assert sets[0] == frozenset(range(6)) and lams[0] == Fraction(5, 2)
+    assert sets[1] == frozenset(range(9)) and lams[1] == Fraction(1)
+    assert sets[2] == frozenset(range(12)) and lams[2] == Fraction(2, 3)
+    assert len(sets) == 3
+
+
+@pytest.mark.parametrize("T", [0, 2, 5, 40])
+def test_ldd_first_level_is_the_extracted_set(T):
+    """At any iteration the read-out's first level is the extraction's set
+    S* (the largest prefix of maximal density), with lambda_1 = rho(S*)."""
+    rng = np.random.default_rng(T)
+    for _ in range(6):
+        g = synth.random_small(rng, int(rng.integers(20, 80)), float(rng.uniform(0.05, 0.3)))
+        if g.m == 0:
+            continue
+        r = converge(g, T)
+        ex = oracle.extract(g.n, g.src, g.dst, None, r["L"])
+        ro = oracle.ldd(g.n, g.src, g.dst, None, r["L"])
+        assert np.array_equal((ro["level"] == 0).astype(np.uint8), ex["in_set"])
+        assert ro["k_end"][0] == ex["den"] and ro["f_end"][0] == ex["num"]
+        assert ro["k_end"][-1] == g.n and ro["f_end"][-1] == g.m
+
+
+def _densest_k_brute(n, edges, k):
+    from itertools import combinations
+    best = 0
+    for S in combinations(range(n), k):
+        s = set(S)
+        best = max(best, sum(1 for a, b in edges if a in s and b in s))
+    return Fraction(best, k)
+
+
+def test_dks_bound_holds_and_is_tight_at_levels():
+    """Corollary 1: for every k the densest k-subgraph has density at most the
+    bound read from the decomposition, with equality when k = |B_j|."""
+    for g in _random_graphs(12, 5, 9, False, 33):
+        r = converge(g, 6000)
+        ro = oracle.ldd(g.n, g.src, g.dst, None, r["L"])
+        edges = list(zip(g.src.tolist(), g.dst.tolist()))
+        for k in range(1, g.n + 1):
+            exact = _densest_k_brute(g.n, edges, k)
+            bound = oracle.dks_bound(ro["k_end"], ro["f_end"], k)
+            assert float(exact) <= bound + 1e-12, (k, exact, bound)
+            if k in set(int(v) for v in ro["k_end"]):
+                assert abs(float(exact) - bound) <= 1e-12, (k, exact, bound)
