@@ -58,8 +58,8 @@ const char *lowd_last_error(void);
  * counting-sort bucket scheme of Section III-D: starting from H = G, each
  * round removes every node whose degree in H is below the density
  * rho(H) = |E(H)| / |V(H)| (decided exactly as deg * |V(H)| < |E(H)|), then
- * recomputes rho(H); it stops when a round removes nothing.  By Theorem 3 no
- * node of a densest subgraph is removed.
+ * recomputes rho(H); it stops when a round removes nothing.  By the degree
+ * bound of Theorem 4 no node of a densest subgraph is removed.
  *
  *   n, m          nodes and edges of G (n >= 1, m >= 0)
  *   src, dst      [device] int32[m] edge list of G
@@ -73,13 +73,34 @@ const char *lowd_last_error(void);
  *   edge_map      [device] int64[m] out: original index of each H edge; may
  *                 be NULL
  *   rounds, n_h, m_h  [host] out: removal rounds, |V(H)|, |E(H)|
- * Synchronises `stream`.  Weighted pruning is not provided: weights are not
- * an argument.
+ * Synchronises `stream`.  Weighted graphs: lowd_prune_weighted.
  */
 lowd_status lowd_prune(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
                        uint8_t *node_keep, int32_t *relabel, int32_t *h_src, int32_t *h_dst,
                        int64_t *edge_map, int32_t *rounds, int32_t *n_h, int64_t *m_h,
                        void *stream);
+
+/*
+ * lowd_prune_weighted -- Algorithm 2 on a weighted graph (Section III-D: each
+ * round scans the nodes still in H): every round removes each node whose
+ * weighted degree in H is below rho(H) = w(E(H)) / |V(H)|, until a round
+ * removes nothing.  The test is exact: the float32 weights are integer
+ * multiples of 2^q for the smallest q among them, so degrees and w(E(H))
+ * are summed exactly in 128-bit integers and compared exactly (weights
+ * whose binary exponents span more than 40 give LOWD_E_UNSUPPORTED).
+ *
+ *   w      [device] float32[m] positive finite weights of G
+ *   h_w    [device] float32[m] out: weights of H's edges (first *m_h); may
+ *          be NULL
+ *   w_h    [host] out: w(E(H)) rounded once to FP64; may be NULL
+ *   other arguments as for lowd_prune
+ * Synchronises `stream`.
+ */
+lowd_status lowd_prune_weighted(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                                const float *w, uint8_t *node_keep, int32_t *relabel,
+                                int32_t *h_src, int32_t *h_dst, float *h_w, int64_t *edge_map,
+                                int32_t *rounds, int32_t *n_h, int64_t *m_h, double *w_h,
+                                void *stream);
 
 /*
  * lowd_init_loads -- Algorithm 1, initialisation: every edge gives half its
@@ -179,6 +200,36 @@ lowd_status lowd_extract_densest(lowd_solver *s, uint8_t *in_set, int64_t *num_u
  */
 lowd_status lowd_ldd_readout(lowd_solver *s, int32_t *level, int64_t *k_end, double *f_end,
                              int64_t *nlevels, void *stream);
+
+/*
+ * lowd_dks_bound -- Corollary 1: from a decomposition read-out, an upper
+ * bound on the density of any k-node subgraph (the densest-k-subgraph and
+ * at-least-k problems): the envelope (f_end[j-1] + (k - k_end[j-1]) *
+ * lambda_j) / k for k_end[j-1] < k <= k_end[j].  At k = k_end[j] and the
+ * limit of the iteration it is the density of B_{j+1} itself.  Host only.
+ *   k_end, f_end  [host] the read-out's first nlevels entries
+ *   bound         [host] out
+ */
+lowd_status lowd_dks_bound(const int64_t *k_end, const double *f_end, int64_t nlevels, int64_t k,
+                           double *bound);
+
+/*
+ * lowd_convergence_trace -- continues the iteration for `sweeps` sweeps and
+ * records, before the first and after every `every` sweeps (and at the
+ * end), the quantities behind the paper's convergence curves (Section IV):
+ * the dual bound D = max load (Section III-B), the density rho of the
+ * extracted set, the QP objective sum of squared loads (Section III-C) and
+ * the relative gap (D - rho) / rho.  The relative error (rho* - rho) / rho*
+ * and the QP error sum_sq - sum_sq* follow from a reference rho*, sum_sq*
+ * (for instance lambda_1 and sum_j lambda_j^2 |level j| of a converged
+ * decomposition).
+ *   out     [host] double[5 * (ceil(sweeps / every) + 1)] out, rows of
+ *           (sweeps done, D, rho, sum_sq, gap)
+ *   points  [host] out: rows written
+ * Synchronises `stream` at every record.
+ */
+lowd_status lowd_convergence_trace(lowd_solver *s, int32_t sweeps, int32_t every, double *out,
+                                   int64_t *points, void *stream);
 
 /*
  * lowd_read_state -- copies the current fractions and loads out, in the

@@ -146,6 +146,39 @@ def extract(n: int, src: np.ndarray, dst: np.ndarray, w: Optional[np.ndarray], L
                 den=int(den.value))
 
 
+def prune_weighted(n: int, src: np.ndarray, dst: np.ndarray, w: np.ndarray):
+    """Algorithm 2 on a weighted graph, in exact rational arithmetic (plain
+    Python; small graphs only).  H <- G; each round computes every node's
+    weighted degree in H and the density rho(H) = w(E(H)) / |V(H)|, and
+    removes every node with degree < rho(H) (decided exactly on the given
+    float32 weights); it stops when a round removes nothing.  Isolated nodes
+    count in |V(H)|.  Returns (node_keep uint8[n], rounds, n_h, m_h, w(E(H)))."""
+    from fractions import Fraction
+    wf = [Fraction(float(x)) for x in np.asarray(w, dtype=np.float32)]
+    s = [int(a) for a in src]
+    d = [int(b) for b in dst]
+    alive = [True] * n
+    rounds = 0
+    while True:
+        N = sum(alive)
+        deg = [Fraction(0)] * n
+        W = Fraction(0)
+        for e in range(len(s)):
+            if alive[s[e]] and alive[d[e]]:
+                deg[s[e]] += wf[e]
+                deg[d[e]] += wf[e]
+                W += wf[e]
+        gone = [u for u in range(n) if alive[u] and deg[u] * N < W]
+        if not gone:
+            break
+        for u in gone:
+            alive[u] = False
+        rounds += 1
+    keep = np.array(alive, dtype=np.uint8)
+    m_h = sum(1 for e in range(len(s)) if alive[s[e]] and alive[d[e]])
+    return keep, rounds, int(keep.sum()), m_h, W
+
+
 def ldd(n: int, src: np.ndarray, dst: np.ndarray, w: Optional[np.ndarray], L: np.ndarray):
     """Locally-dense decomposition read from loads L (prefixes of the
     descending load order) -> dict(level int32[n], k_end int64[L], f_end

@@ -43,6 +43,8 @@ def lib() -> C.CDLL:
         L.lowd_version.restype = C.c_char_p
         L.lowd_last_error.restype = C.c_char_p
         L.lowd_prune.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp, vp, P(i32), P(i32), P(i64), vp]
+        L.lowd_prune_weighted.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, P(i32),
+                                          P(i32), P(i64), P(C.c_double), vp]
         L.lowd_init_loads.argtypes = [i32, i64, vp, vp, vp, i32, i32, P(vp), vp]
         L.lowd_iterate.argtypes = [vp, i32, vp]
         L.lowd_reset_loads.argtypes = [vp, vp]
@@ -51,6 +53,8 @@ def lib() -> C.CDLL:
                                            P(C.c_double), P(C.c_double), vp]
         L.lowd_read_state.argtypes = [vp, vp, vp, vp]
         L.lowd_ldd_readout.argtypes = [vp, vp, vp, vp, P(i64), vp]
+        L.lowd_convergence_trace.argtypes = [vp, i32, i32, vp, P(i64), vp]
+        L.lowd_dks_bound.argtypes = [vp, vp, i64, i64, P(C.c_double)]
         L.lowd_schedule_export.argtypes = [vp, vp, vp, P(i32)]
         L.lowd_solver_info.argtypes = [vp, vp]
         L.lowd_schedule_build.argtypes = [i32, i64, vp, vp, i32, vp, vp, P(i32)]
@@ -65,9 +69,9 @@ def lib() -> C.CDLL:
         L.lowd_batch_retire.argtypes = [vp, vp, vp, vp, C.c_double, P(i32), P(i64), vp]
         L.lowd_batch_free.argtypes = [vp]
         L.lowd_batch_free.restype = None
-        for f in (L.lowd_prune, L.lowd_init_loads, L.lowd_iterate, L.lowd_check,
+        for f in (L.lowd_prune, L.lowd_prune_weighted, L.lowd_init_loads, L.lowd_iterate, L.lowd_check,
                   L.lowd_extract_densest, L.lowd_read_state, L.lowd_schedule_export,
-                  L.lowd_ldd_readout,
+                  L.lowd_ldd_readout, L.lowd_convergence_trace, L.lowd_dks_bound,
                   L.lowd_solver_info, L.lowd_batch_solve, L.lowd_schedule_build, L.lowd_reset_loads,
                   L.lowd_batch_prepare, L.lowd_batch_reset, L.lowd_batch_iterate,
                   L.lowd_batch_extract, L.lowd_batch_info, L.lowd_batch_retire):
@@ -130,6 +134,30 @@ def prune(n: int, src, dst, stream=None) -> dict:
     mh = int(mh.value)
     return dict(node_keep=keep, relabel=relabel, src=hs[:mh], dst=hd[:mh], edge_map=emap[:mh],
                 rounds=int(r.value), n_h=int(nh.value), m_h=mh)
+
+
+def prune_weighted(n: int, src, dst, w, stream=None) -> dict:
+    """Algorithm 2 on a weighted graph, decided exactly (lowd_prune_weighted):
+    like prune(), plus H's edge weights and its total weight w_h."""
+    torch = _torch()
+    s = _dev(src, torch.int32, "src")
+    d = _dev(dst, torch.int32, "dst")
+    ww = _dev(w, torch.float32, "w")
+    m = s.numel()
+    keep = torch.empty(n, dtype=torch.uint8, device=s.device)
+    relabel = torch.empty(n, dtype=torch.int32, device=s.device)
+    hs = torch.empty(max(m, 1), dtype=torch.int32, device=s.device)
+    hd = torch.empty(max(m, 1), dtype=torch.int32, device=s.device)
+    hw = torch.empty(max(m, 1), dtype=torch.float32, device=s.device)
+    emap = torch.empty(max(m, 1), dtype=torch.int64, device=s.device)
+    r, nh, mh, wh = C.c_int32(0), C.c_int32(0), C.c_int64(0), C.c_double(0)
+    _check(lib().lowd_prune_weighted(n, m, _ptr(s), _ptr(d), _ptr(ww), _ptr(keep), _ptr(relabel),
+                                     _ptr(hs), _ptr(hd), _ptr(hw), _ptr(emap), C.byref(r),
+                                     C.byref(nh), C.byref(mh), C.byref(wh), _stream(stream)))
+    mh = int(mh.value)
+    return dict(node_keep=keep, relabel=relabel, src=hs[:mh], dst=hd[:mh], w=hw[:mh],
+                edge_map=emap[:mh], rounds=int(r.value), n_h=int(nh.value), m_h=mh,
+                w_h=float(wh.value))
 
 
 class Solver:
@@ -196,6 +224,17 @@ class Solver:
                                       C.byref(nl), _stream(stream)))
         L = int(nl.value)
         return dict(level=level, k_end=k_end[:L].cpu().numpy(), f_end=f_end[:L].cpu().numpy())
+
+    def trace(self, sweeps: int, every: int = 1, stream=None) -> np.ndarray:
+        """Continues `sweeps` sweeps, recording (sweeps, D, rho, sum_sq, gap)
+        before the first and every `every` sweeps (lowd_convergence_trace)."""
+        rows = (sweeps + every - 1) // every + 1
+        out = np.zeros((rows, 5), dtype=np.float64)
+        pts = C.c_int64()
+        _check(lib().lowd_convergence_trace(self._h, sweeps, every,
+                                            out.ctypes.data_as(C.c_void_p), C.byref(pts),
+                                            _stream(stream)))
+        return out[:pts.value]
 
     def read_state(self, stream=None):
         torch = _torch()
@@ -264,6 +303,17 @@ def batch_solve(graphs, sweeps: int, state: str = "f64", star_max: int = 16, str
                                   _ptr(den), _ptr(load), _stream(stream)))
     return dict(num=num.cpu().numpy(), den=den.cpu().numpy(), in_set=in_set, load=load,
                 node_ptr=node_ptr, edge_ptr=edge_ptr)
+
+
+def dks_bound(k_end: np.ndarray, f_end: np.ndarray, k: int) -> float:
+    """Corollary 1 (lowd_dks_bound): upper bound on the density of any
+    k-node subgraph from a decomposition read-out (Solver.ldd())."""
+    ke = np.ascontiguousarray(k_end, dtype=np.int64)
+    fe = np.ascontiguousarray(f_end, dtype=np.float64)
+    b = C.c_double()
+    _check(lib().lowd_dks_bound(ke.ctypes.data_as(C.c_void_p), fe.ctypes.data_as(C.c_void_p),
+                                ke.size, int(k), C.byref(b)))
+    return b.value
 
 
 def _batch_arrays(graphs):

@@ -336,6 +336,62 @@ lowd_status lowd_extract_densest(lowd_solver *sv, uint8_t *in_set, int64_t *num_
     });
 }
 
+lowd_status lowd_convergence_trace(lowd_solver *sv, int32_t sweeps, int32_t every, double *out,
+                                   int64_t *points, void *stream) {
+    return guarded([&] {
+        if (!sv) fail(LOWD_E_ARG, "solver is NULL");
+        if (sweeps < 0 || every < 1) fail(LOWD_E_ARG, "need sweeps >= 0 and every >= 1");
+        if (!out || !points) fail(LOWD_E_ARG, "NULL output");
+        hipStream_t s = (hipStream_t)stream;
+        if (sv->ldd_in_set.n < (size_t)sv->n) sv->ldd_in_set.alloc((size_t)sv->n);
+        int64_t p = 0;
+        int32_t done = 0;
+        for (;;) {
+            double D = 0.0, rho = 0.0, gap = 0.0;
+            int64_t num = 0, den = 0;
+            double numw = 0.0;
+            lowd_status st = lowd_extract_densest(sv, sv->ldd_in_set.p, &num, &numw, &den, &D,
+                                                  &gap, stream);
+            if (st != LOWD_OK) fail(st, g_last_error);
+            double o[3];
+            stats(sv, o, s);   // loads are current from the extraction
+            rho = numw / (double)den;
+            double *row = out + p * 5;
+            row[0] = (double)done;
+            row[1] = D;
+            row[2] = rho;
+            row[3] = o[2];
+            row[4] = gap;
+            ++p;
+            if (done >= sweeps) break;
+            const int32_t k = std::min(every, sweeps - done);
+            if (sv->exec)
+                for (int32_t t = 0; t < k; ++t) LOWD_HIP(hipGraphLaunch(sv->exec, s));
+            done += k;
+        }
+        *points = p;
+    });
+}
+
+lowd_status lowd_dks_bound(const int64_t *k_end, const double *f_end, int64_t nlevels, int64_t k,
+                           double *bound) {
+    return guarded([&] {
+        if (!k_end || !f_end || !bound || nlevels < 1) fail(LOWD_E_ARG, "empty decomposition");
+        if (k < 1 || k > k_end[nlevels - 1]) fail(LOWD_E_ARG, "k must be in [1, n]");
+        int64_t kp = 0;
+        double fp = 0.0;
+        for (int64_t j = 0; j < nlevels; ++j) {
+            if (k <= k_end[j]) {
+                const double lam = (f_end[j] - fp) / (double)(k_end[j] - kp);
+                *bound = (fp + (double)(k - kp) * lam) / (double)k;
+                return;
+            }
+            kp = k_end[j];
+            fp = f_end[j];
+        }
+    });
+}
+
 lowd_status lowd_ldd_readout(lowd_solver *sv, int32_t *level, int64_t *k_end, double *f_end,
                              int64_t *nlevels, void *stream) {
     return guarded([&] {
@@ -435,6 +491,27 @@ lowd_status lowd_prune(int32_t n, int64_t m, const int32_t *src, const int32_t *
         hipStream_t s = (hipStream_t)stream;
         validate_graph(n, m, src, dst, nullptr, s);
         PruneResult r = run_prune(n, m, src, dst, node_keep, relabel, h_src, h_dst, edge_map, s);
+        if (rounds) *rounds = r.rounds;
+        if (n_h) *n_h = r.n_h;
+        if (m_h) *m_h = r.m_h;
+    });
+}
+
+lowd_status lowd_prune_weighted(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                                const float *w, uint8_t *node_keep, int32_t *relabel,
+                                int32_t *h_src, int32_t *h_dst, float *h_w, int64_t *edge_map,
+                                int32_t *rounds, int32_t *n_h, int64_t *m_h, double *w_h,
+                                void *stream) {
+    return guarded([&] {
+        if (n < 1) fail(LOWD_E_ARG, "n must be >= 1");
+        if (m < 0 || m >= ((int64_t)1 << 31)) fail(LOWD_E_ARG, "m must be in [0, 2^31)");
+        if (m > 0 && (!src || !dst || !w)) fail(LOWD_E_ARG, "src/dst/w is NULL");
+        if (!node_keep) fail(LOWD_E_ARG, "node_keep is NULL");
+        if ((h_src == nullptr) != (h_dst == nullptr)) fail(LOWD_E_ARG, "h_src/h_dst: both or none");
+        hipStream_t s = (hipStream_t)stream;
+        validate_graph(n, m, src, dst, w, s);
+        PruneResult r = run_prune_weighted(n, m, src, dst, w, node_keep, relabel, h_src, h_dst,
+                                           h_w, edge_map, w_h, s);
         if (rounds) *rounds = r.rounds;
         if (n_h) *n_h = r.n_h;
         if (m_h) *m_h = r.m_h;

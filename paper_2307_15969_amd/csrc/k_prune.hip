@@ -19,6 +19,7 @@
 // The alive list shrinks quickly (the number of removed nodes decays
 // exponentially, as the paper observes), so the rounds after the first cost
 // little.
+#include <cmath>
 #include <vector>
 
 #include "lowd_internal.h"
@@ -136,8 +137,9 @@ __global__ void k_edge_flags(int64_t m, const int32_t *src, const int32_t *dst,
 }
 
 __global__ void k_edge_compact(int64_t m, const int32_t *src, const int32_t *dst,
-                               const int64_t *flag, const int64_t *pos, const int64_t *npos,
-                               int32_t *h_src, int32_t *h_dst, int64_t *edge_map) {
+                               const float *w, const int64_t *flag, const int64_t *pos,
+                               const int64_t *npos, int32_t *h_src, int32_t *h_dst, float *h_w,
+                               int64_t *edge_map) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
          e += (int64_t)gridDim.x * blockDim.x) {
         if (!flag[e]) continue;
@@ -146,7 +148,131 @@ __global__ void k_edge_compact(int64_t m, const int32_t *src, const int32_t *dst
             h_src[at] = (int32_t)npos[src[e]];
             h_dst[at] = (int32_t)npos[dst[e]];
         }
+        if (h_w) h_w[at] = w[e];
         if (edge_map) edge_map[at] = e;
+    }
+}
+
+// ------------------------------------------------------ weighted graphs --
+// Algorithm 2 with weighted degrees (Section III-D: every round scans the
+// nodes still alive).  The test deg_w(u) < rho(H) = w(E(H)) / |V(H)| is
+// decided exactly.  Every float32 weight is m * 2^q with an integer m <
+// 2^24; with q_min the smallest such q over the edges, w / 2^q_min is an
+// integer, below 2^64 when the exponents span at most 40 binades.  Degrees
+// and 2 w(E(H)) = sum of degrees are then exact 128-bit sums in any order,
+// and 2 deg(u) |V(H)| < 2 w(E(H)) an exact 128-bit comparison.
+typedef unsigned __int128 u128;
+constexpr int32_t kMaxExpSpan = 40;
+
+__device__ __forceinline__ int32_t ulp_exponent(float x) {
+    const uint32_t b = __builtin_bit_cast(uint32_t, x);
+    const int32_t e = (int32_t)((b >> 23) & 0xFFu);
+    return e == 0 ? -149 : e - 150;
+}
+__device__ __forceinline__ uint64_t significand(float x) {
+    const uint32_t b = __builtin_bit_cast(uint32_t, x);
+    const uint32_t f = b & 0x7FFFFFu;
+    return ((b >> 23) & 0xFFu) == 0 ? (uint64_t)f : (uint64_t)(f | 0x800000u);
+}
+
+__global__ void k_exponent_range(int64_t m, const float *w, int32_t *range) {
+    int32_t lo = 1 << 30, hi = -(1 << 30);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t q = ulp_exponent(w[e]);
+        lo = q < lo ? q : lo;
+        hi = q > hi ? q : hi;
+    }
+    atomicMin(&range[0], lo);
+    atomicMax(&range[1], hi);
+}
+
+__global__ void k_fixed_weights(int64_t m, const float *w, int32_t qmin, uint64_t *wi) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x)
+        wi[e] = significand(w[e]) << (ulp_exponent(w[e]) - qmin);
+}
+
+__global__ void k_iota(int32_t n, int32_t *a) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = (int32_t)i;
+}
+
+__device__ __forceinline__ u128 shfl_down_u128(u128 v, int d) {
+    const uint64_t lo = __shfl_down((uint64_t)v, d, kWave);
+    const uint64_t hi = __shfl_down((uint64_t)(v >> 64), d, kWave);
+    return ((u128)hi << 64) | lo;
+}
+
+// weighted degree in H of every alive node (one wavefront per node); the
+// degree of list entry i goes to (dlo[i], dhi[i])
+__global__ void __launch_bounds__(256) k_weighted_degrees(int64_t k, const int32_t *alive,
+                                                          const int64_t *row_ptr,
+                                                          const uint32_t *inc, const int32_t *src,
+                                                          const int32_t *dst, const int32_t *stamp,
+                                                          const uint64_t *wi, uint64_t *dlo,
+                                                          uint64_t *dhi) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; i < k;
+         i += waves) {
+        const int32_t u = alive[i];
+        u128 acc = 0;
+        for (int64_t j = row_ptr[u] + lane; j < row_ptr[u + 1]; j += kWave) {
+            const uint32_t ent = inc[j];
+            const int64_t e = ent >> 1;
+            const int32_t v = (ent & 1) ? src[e] : dst[e];
+            if (stamp[v] == 0) acc += (u128)wi[e];
+        }
+        for (int d = kWave / 2; d > 0; d >>= 1) acc += shfl_down_u128(acc, d);
+        if (lane == 0) {
+            dlo[i] = (uint64_t)acc;
+            dhi[i] = (uint64_t)(acc >> 64);
+        }
+    }
+}
+
+// sum of the k degrees (exact; blocks write partials, then one block adds them)
+constexpr int kSumBlock = 256;
+__global__ void __launch_bounds__(kSumBlock) k_sum_u128(int64_t k, const uint64_t *lo,
+                                                        const uint64_t *hi, uint64_t *out_lo,
+                                                        uint64_t *out_hi) {
+    __shared__ uint64_t sl[kSumBlock], sh[kSumBlock];
+    u128 acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
+         i += (int64_t)gridDim.x * blockDim.x)
+        acc += ((u128)hi[i] << 64) | lo[i];
+    sl[threadIdx.x] = (uint64_t)acc;
+    sh[threadIdx.x] = (uint64_t)(acc >> 64);
+    __syncthreads();
+    for (int d = kSumBlock / 2; d > 0; d >>= 1) {
+        if ((int)threadIdx.x < d) {
+            const u128 a = ((u128)sh[threadIdx.x] << 64) | sl[threadIdx.x];
+            const u128 b = ((u128)sh[threadIdx.x + d] << 64) | sl[threadIdx.x + d];
+            const u128 c = a + b;
+            sl[threadIdx.x] = (uint64_t)c;
+            sh[threadIdx.x] = (uint64_t)(c >> 64);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out_lo[blockIdx.x] = sl[0];
+        out_hi[blockIdx.x] = sh[0];
+    }
+}
+
+// removal test of every alive node: 2 deg(u) N < sum of degrees (= 2 w(E(H)))
+__global__ void k_weighted_test(int64_t k, const uint64_t *dlo, const uint64_t *dhi, int64_t N,
+                                const uint64_t *total_lo, const uint64_t *total_hi, int64_t *rm,
+                                int64_t *keep) {
+    const u128 W2 = ((u128)total_hi[0] << 64) | total_lo[0];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const u128 d = ((u128)dhi[i] << 64) | dlo[i];
+        const bool r = d * (u128)(2 * N) < W2;
+        rm[i] = r ? 1 : 0;
+        keep[i] = r ? 0 : 1;
     }
 }
 
@@ -241,7 +367,7 @@ PruneResult run_prune(int32_t n, int64_t m, const int32_t *src, const int32_t *d
                            stamp.p, ef.p);
         exclusive_scan_i64(ef.p, ep.p, m, nullptr, scan_tmp.p, scan_tmp.bytes(), s);
         hipLaunchKernelGGL(k_edge_compact, dim3(grid_for(m, 256)), dim3(256), 0, s, m, src, dst,
-                           ef.p, ep.p, p_keep.p, h_src, h_dst, edge_map);
+                           nullptr, ef.p, ep.p, p_keep.p, h_src, h_dst, nullptr, edge_map);
         LOWD_HIP(hipGetLastError());
         LOWD_HIP(hipStreamSynchronize(s));
     }
@@ -249,6 +375,116 @@ PruneResult run_prune(int32_t n, int64_t m, const int32_t *src, const int32_t *d
     LOWD_HIP(hipStreamSynchronize(s));
     res.n_h = (int32_t)N;
     res.m_h = M;
+    return res;
+}
+
+// total = (lo, hi) of the sum of k 128-bit degrees, in two passes
+static void sum_degrees(int64_t k, const uint64_t *dlo, const uint64_t *dhi, uint64_t *part_lo,
+                        uint64_t *part_hi, uint64_t *total, hipStream_t s) {
+    const int32_t nb = (int32_t)grid_for(k, kSumBlock, 1024);
+    hipLaunchKernelGGL(k_sum_u128, dim3((unsigned)nb), dim3(kSumBlock), 0, s, k, dlo, dhi, part_lo,
+                       part_hi);
+    hipLaunchKernelGGL(k_sum_u128, dim3(1), dim3(kSumBlock), 0, s, (int64_t)nb, part_lo, part_hi,
+                       total, total + 1);
+}
+
+PruneResult run_prune_weighted(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                               const float *w, uint8_t *node_keep, int32_t *relabel,
+                               int32_t *h_src, int32_t *h_dst, float *h_w, int64_t *edge_map,
+                               double *w_h, hipStream_t s) {
+    PruneResult res;
+    const unsigned gn = grid_for(n, 256);
+    Csr csr;
+    build_incidence(n, m, src, dst, csr, s);
+    DBuf<int32_t> stamp((size_t)n), list_a((size_t)n), list_b((size_t)n), removed((size_t)n),
+        range(2);
+    DBuf<uint64_t> wi((size_t)(m > 0 ? m : 1)), dlo((size_t)n), dhi((size_t)n), part_lo(1024),
+        part_hi(1024), total(2);
+    DBuf<int64_t> f_rm((size_t)n), f_keep((size_t)n), p_rm((size_t)n), p_keep((size_t)n), tot(2);
+    int64_t big = n > m ? (int64_t)n : m;
+    DBuf<char> scan_tmp(exclusive_scan_tmp_bytes(big));
+    LOWD_HIP(hipMemsetAsync(stamp.p, 0, (size_t)n * sizeof(int32_t), s));
+    int32_t qmin = 0;
+    if (m > 0) {
+        const int32_t init[2] = {1 << 30, -(1 << 30)};
+        LOWD_HIP(hipMemcpyAsync(range.p, init, sizeof(init), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_exponent_range, dim3(grid_for(m, 256, 1024)), dim3(256), 0, s, m, w,
+                           range.p);
+        int32_t r[2];
+        LOWD_HIP(hipMemcpyAsync(r, range.p, sizeof(r), hipMemcpyDeviceToHost, s));
+        LOWD_HIP(hipStreamSynchronize(s));
+        if (r[1] - r[0] > kMaxExpSpan)
+            fail(-5, "weights span more than 2^40 in scale; exact weighted pruning needs them "
+                     "closer");
+        qmin = r[0];
+        hipLaunchKernelGGL(k_fixed_weights, dim3(grid_for(m, 256)), dim3(256), 0, s, m, w, qmin,
+                           wi.p);
+    }
+    hipLaunchKernelGGL(k_iota, dim3(gn), dim3(256), 0, s, n, list_a.p);
+    int32_t *alive = list_a.p;
+    int64_t nalive = n;
+    for (int32_t round = 1; nalive > 0 && m > 0; ++round) {
+        hipLaunchKernelGGL(k_weighted_degrees, dim3(grid_for(nalive * kWave, 256)), dim3(256), 0,
+                           s, nalive, alive, csr.row_ptr.p, csr.inc.p, src, dst, stamp.p, wi.p,
+                           dlo.p, dhi.p);
+        sum_degrees(nalive, dlo.p, dhi.p, part_lo.p, part_hi.p, total.p, s);
+        const unsigned gc = grid_for(nalive, 256);
+        hipLaunchKernelGGL(k_weighted_test, dim3(gc), dim3(256), 0, s, nalive, dlo.p, dhi.p,
+                           nalive, total.p, total.p + 1, f_rm.p, f_keep.p);
+        exclusive_scan_i64(f_rm.p, p_rm.p, nalive, tot.p, scan_tmp.p, scan_tmp.bytes(), s);
+        exclusive_scan_i64(f_keep.p, p_keep.p, nalive, tot.p + 1, scan_tmp.p, scan_tmp.bytes(), s);
+        int32_t *out = (alive == list_a.p) ? list_b.p : list_a.p;
+        hipLaunchKernelGGL(k_split, dim3(gc), dim3(256), 0, s, nalive, alive, f_rm.p, p_rm.p,
+                           p_keep.p, removed.p, out);
+        int64_t t[2];
+        LOWD_HIP(hipMemcpyAsync(t, tot.p, sizeof(t), hipMemcpyDeviceToHost, s));
+        LOWD_HIP(hipStreamSynchronize(s));
+        if (t[0] == 0) break;
+        hipLaunchKernelGGL(k_stamp, dim3(grid_for(t[0], 256)), dim3(256), 0, s, t[0], removed.p,
+                           stamp.p, round);
+        alive = out;
+        nalive = t[1];
+        res.rounds = round;
+    }
+    // outputs: mask, renumbering, compacted edge list with weights
+    hipLaunchKernelGGL(k_keep_flags, dim3(gn), dim3(256), 0, s, n, stamp.p, node_keep, f_keep.p);
+    exclusive_scan_i64(f_keep.p, p_keep.p, n, tot.p, scan_tmp.p, scan_tmp.bytes(), s);
+    if (relabel)
+        hipLaunchKernelGGL(k_relabel, dim3(gn), dim3(256), 0, s, n, f_keep.p, p_keep.p, relabel);
+    int64_t mh = 0;
+    if (m > 0) {
+        DBuf<int64_t> ef((size_t)m), ep((size_t)m), etot(1);
+        hipLaunchKernelGGL(k_edge_flags, dim3(grid_for(m, 256)), dim3(256), 0, s, m, src, dst,
+                           stamp.p, ef.p);
+        exclusive_scan_i64(ef.p, ep.p, m, etot.p, scan_tmp.p, scan_tmp.bytes(), s);
+        if (h_src || h_w || edge_map)
+            hipLaunchKernelGGL(k_edge_compact, dim3(grid_for(m, 256)), dim3(256), 0, s, m, src,
+                               dst, w, ef.p, ep.p, p_keep.p, h_src, h_dst, h_w, edge_map);
+        LOWD_HIP(hipMemcpyAsync(&mh, etot.p, sizeof(mh), hipMemcpyDeviceToHost, s));
+        LOWD_HIP(hipStreamSynchronize(s));
+    }
+    int64_t nh = 0;
+    LOWD_HIP(hipMemcpyAsync(&nh, tot.p, sizeof(nh), hipMemcpyDeviceToHost, s));
+    LOWD_HIP(hipStreamSynchronize(s));
+    if (w_h) {
+        // w(E(H)) = (sum of the kept degrees) / 2, times 2^q_min, rounded once
+        double v = 0.0;
+        if (m > 0 && nalive > 0) {
+            hipLaunchKernelGGL(k_weighted_degrees, dim3(grid_for(nalive * kWave, 256)), dim3(256),
+                               0, s, nalive, alive, csr.row_ptr.p, csr.inc.p, src, dst, stamp.p,
+                               wi.p, dlo.p, dhi.p);
+            sum_degrees(nalive, dlo.p, dhi.p, part_lo.p, part_hi.p, total.p, s);
+            uint64_t tw[2];
+            LOWD_HIP(hipMemcpyAsync(tw, total.p, sizeof(tw), hipMemcpyDeviceToHost, s));
+            LOWD_HIP(hipStreamSynchronize(s));
+            const u128 W2 = ((u128)tw[1] << 64) | tw[0];
+            v = ldexp((double)(W2 >> 1), qmin);
+        }
+        *w_h = v;
+    }
+    LOWD_HIP(hipGetLastError());
+    res.n_h = (int32_t)nh;
+    res.m_h = mh;
     return res;
 }
 

@@ -17,4 +17,12 @@ PruneResult run_prune(int32_t n, int64_t m, const int32_t *src, const int32_t *d
                       uint8_t *node_keep, int32_t *relabel, int32_t *h_src, int32_t *h_dst,
                       int64_t *edge_map, hipStream_t s);
 
+// Algorithm 2 on a weighted graph, deciding every removal exactly (see
+// k_prune.hip); h_w receives the kept edges' weights, w_h the kept graph's
+// total weight (rounded once to FP64).
+PruneResult run_prune_weighted(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                               const float *w, uint8_t *node_keep, int32_t *relabel,
+                               int32_t *h_src, int32_t *h_dst, float *h_w, int64_t *edge_map,
+                               double *w_h, hipStream_t s);
+
 }  // namespace lowd

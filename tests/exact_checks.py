@@ -154,3 +154,30 @@ def greedy_peel(n: int, src, dst) -> Tuple[List[Tuple[int, int]], List[int]]:
         if alive:
             sizes.append((M, len(alive)))
     return sizes, order
+
+
+def greedy_peel_weighted(n: int, src, dst, w) -> Tuple[List[Tuple[Fraction, int]], List[int]]:
+    """Greedy peeling on a weighted graph in exact arithmetic: repeatedly
+    remove a node of minimum weighted degree (smallest id on ties).  Returns
+    (w(E), |V|) of every remaining graph, starting with G, and the order."""
+    wf = [Fraction(float(x)) for x in np.asarray(w, dtype=np.float32)]
+    adj = [dict() for _ in range(n)]
+    for e, (a, b) in enumerate(zip(src, dst)):
+        adj[int(a)][int(b)] = wf[e]
+        adj[int(b)][int(a)] = wf[e]
+    deg = [sum(adj[u].values(), Fraction(0)) for u in range(n)]
+    alive = set(range(n))
+    W = sum(wf, Fraction(0))
+    sizes = [(W, n)]
+    order = []
+    while alive:
+        u = min(alive, key=lambda v: (deg[v], v))
+        alive.remove(u)
+        order.append(u)
+        W -= deg[u]
+        for v, x in adj[u].items():
+            if v in alive:
+                deg[v] -= x
+        if alive:
+            sizes.append((W, len(alive)))
+    return sizes, order

@@ -92,3 +92,18 @@ def test_host_schedule_equals_oracle_schedule(smax):
 def test_host_schedule_empty_graph():
     p, c, P = lowd.schedule_build(3, np.zeros(0, np.int32), np.zeros(0, np.int32))
     assert P == 0 and p.size == 0
+
+
+def test_dks_bound_host_function_equals_oracle():
+    """lowd_dks_bound (host only) evaluates Corollary 1's envelope like the
+    oracle's helper, on random decompositions; argument errors are caught."""
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        L = int(rng.integers(1, 8))
+        ke = np.cumsum(rng.integers(1, 20, size=L)).astype(np.int64)
+        slopes = np.sort(rng.uniform(0.1, 10.0, size=L))[::-1]
+        fe = np.cumsum(slopes * np.diff(np.concatenate([[0], ke])))
+        for k in range(1, int(ke[-1]) + 1):
+            assert abs(lowd.dks_bound(ke, fe, k) - oracle.dks_bound(ke, fe, k)) <= 1e-12
+    with pytest.raises(lowd.LowdError):
+        lowd.dks_bound(np.array([3], np.int64), np.array([2.0]), 4)

@@ -302,6 +302,68 @@ def test_chunglu_1m_10m_fp64_is_bit_exact():
     assert np.array_equal(ex["in_set"].cpu().numpy(), ro["in_set"])
 
 
+# ------------------------------------------------- weighted pruning --
+def _weighted_prune_graphs():
+    rng = np.random.default_rng(17)
+    out = []
+    for i in range(6):
+        g = synth.random_small(rng, int(rng.integers(30, 300)), float(rng.uniform(0.02, 0.2)))
+        g.w = rng.lognormal(0.0, 1.0, size=g.m).astype(np.float32)
+        out.append((f"gnp{i}", g))
+    out.append(("chunglu15k_w", synth.chung_lu(15000, 120000, 2.1, seed=4, weights="lognormal")))
+    return out
+
+
+@pytest.mark.parametrize("name,g", _weighted_prune_graphs(), ids=lambda v: v if isinstance(v, str) else "")
+def test_weighted_prune_matches_exact_oracle(name, g):
+    """Algorithm 2 with weighted degrees: mask, rounds, sizes and the
+    relabelled H (with weights) equal the exact rational oracle; w(E(H)) is
+    the exact value rounded once."""
+    log(f"weighted prune {name} n={g.n} m={g.m}")
+    r = lowd.prune_weighted(g.n, g.src, g.dst, g.w)
+    keep, rounds, nh, mh, WH = oracle.prune_weighted(g.n, g.src, g.dst, g.w)
+    log(f"  rounds {r['rounds']} H {r['n_h']}/{r['m_h']}")
+    assert np.array_equal(r["node_keep"].cpu().numpy(), keep)
+    assert (r["rounds"], r["n_h"], r["m_h"]) == (rounds, nh, mh)
+    assert r["w_h"] == float(WH)
+    kept = np.flatnonzero(keep[g.src] & keep[g.dst])
+    newid = np.cumsum(keep) - 1
+    assert np.array_equal(r["edge_map"].cpu().numpy(), kept)
+    assert np.array_equal(r["src"].cpu().numpy(), newid[g.src[kept]])
+    assert np.array_equal(r["dst"].cpu().numpy(), newid[g.dst[kept]])
+    assert np.array_equal(r["w"].cpu().numpy(), g.w[kept])
+
+
+def test_weighted_prune_equal_weights_is_unweighted_prune():
+    g = synth.chung_lu(20000, 200000, 2.1, seed=3, planted=60, p_planted=0.3)
+    r = lowd.prune_weighted(g.n, g.src, g.dst, np.full(g.m, 0.75, np.float32))
+    u = lowd.prune(g.n, g.src, g.dst)
+    assert np.array_equal(r["node_keep"].cpu().numpy(), u["node_keep"].cpu().numpy())
+    assert (r["rounds"], r["n_h"], r["m_h"]) == (u["rounds"], u["n_h"], u["m_h"])
+    assert r["w_h"] == 0.75 * u["m_h"]
+
+
+def test_weighted_prune_rejects_too_wide_a_weight_range():
+    g = synth.canonical(4, np.array([0, 1, 2]), np.array([1, 2, 3]),
+                        np.array([1.0, 2.0 ** -30, 2.0 ** 20], np.float32))
+    with pytest.raises(lowd.LowdError) as ei:
+        lowd.prune_weighted(g.n, g.src, g.dst, g.w)
+    assert ei.value.status == -5
+
+
+def test_weighted_prune_then_solve_keeps_the_optimum():
+    """The densest set of G (weighted) lies in H: solving H and G to a 1e-7
+    gap gives overlapping certified intervals [rho, D]."""
+    g = synth.chung_lu(15000, 120000, 2.1, seed=4, weights="lognormal")
+    r = lowd.prune_weighted(g.n, g.src, g.dst, g.w)
+    eh = lowd.solve(r["n_h"], r["src"], r["dst"], r["w"], "f64", tol=1e-7)
+    eg = lowd.solve(g.n, g.src, g.dst, g.w, "f64", tol=1e-7)
+    rh = eh["num_w"] / eh["den"]
+    rg = eg["num_w"] / eg["den"]
+    log(f"  H: rho {rh} D {eh['D']}  G: rho {rg} D {eg['D']}")
+    assert max(rh, rg) <= min(eh["D"], eg["D"]) * (1 + 1e-12)
+
+
 # ------------------------------------------- decomposition read-out --
 @pytest.mark.parametrize("T", [0, 3, 40])
 @pytest.mark.parametrize("name,g", GRAPHS, ids=[n for n, _ in GRAPHS])
@@ -329,6 +391,29 @@ def test_ldd_readout_matches_oracle(name, g, T):
         fo = dict(zip(ro["k_end"].tolist(), ro["f_end"].tolist()))
         for k in common.tolist():
             assert abs(fg[k] - fo[k]) <= 1e-9 * max(1.0, abs(fo[k])), k
+    sv.close()
+
+
+@pytest.mark.parametrize("name,g", GRAPHS[:2], ids=[n for n, _ in GRAPHS[:2]])
+def test_convergence_trace_matches_oracle(name, g):
+    """lowd_convergence_trace records (sweeps, D, rho, sum of squares, gap)
+    every 3 sweeps; each row equals the oracle's state after as many
+    sweeps (D exactly, rho exactly for unit weights, sums to 1e-12)."""
+    sv = lowd.Solver(g.n, g.src, g.dst, g.w, "f64")
+    tr = sv.trace(12, 3)
+    assert tr.shape == (5, 5)
+    for row in tr:
+        T = int(row[0])
+        xo, Lo, *_ = oracle_run(g, T, 16)
+        ro = oracle.extract(g.n, g.src, g.dst, g.w, Lo)
+        Do, _, s2o = oracle.stats(Lo)
+        rho = (ro["num"] if g.w is None else ro["num_w"]) / ro["den"]
+        assert row[1] == Do
+        if g.w is None:
+            assert row[2] == rho and row[4] == (Do - rho) / rho
+        else:
+            assert abs(row[2] - rho) <= 1e-12 * rho
+        assert abs(row[3] - s2o) <= 1e-12 * s2o
     sv.close()
 
 

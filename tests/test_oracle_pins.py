@@ -15,7 +15,7 @@ import pytest
 import oracle
 import synth
 from exact_checks import (brute_force_densest, brute_force_ldd, goldberg_check, greedy_peel,
-                          peel_densities)
+                          greedy_peel_weighted, peel_densities)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -489,3 +489,83 @@ def test_dks_bound_holds_and_is_tight_at_levels():
             assert float(exact) <= bound + 1e-12, (k, exact, bound)
             if k in set(int(v) for v in ro["k_end"]):
                 assert abs(float(exact) - bound) <= 1e-12, (k, exact, bound)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_qp_optimum_is_the_decomposition_value(weighted):
+    """Section III-C / Property 2: the QP objective converges to
+    sum_u lambda_u^2 of the locally-dense decomposition (brute force), the
+    reference for the QP-error curve; the read-out's levels give the same
+    value, sum_j lambda_j^2 |level j|."""
+    for g in _random_graphs(15, 4, 9, weighted, 41 + weighted):
+        _, lam = brute_force_ldd(g.n, g.src, g.dst, g.w)
+        qstar = float(sum(v * v for v in lam))
+        r = converge(g, 6000)
+        assert abs(r["sumL2"] - qstar) <= 1e-7 * max(1.0, qstar)
+        ro = oracle.ldd(g.n, g.src, g.dst, g.w, r["L"])
+        ke = np.concatenate([[0], ro["k_end"]])
+        fe = np.concatenate([[0.0], ro["f_end"]])
+        lam_j = np.diff(fe) / np.diff(ke)
+        assert abs(float(np.sum(lam_j ** 2 * np.diff(ke))) - qstar) <= 1e-9 * max(1.0, qstar)
+
+
+# ------------------------------------------- weighted pruning (Algorithm 2) --
+def _weighted_graphs(count, seed, nmin=8, nmax=40):
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        g = synth.random_small(rng, int(rng.integers(nmin, nmax + 1)),
+                               float(rng.uniform(0.08, 0.35)))
+        if g.m == 0:
+            continue
+        g.w = rng.lognormal(0.0, 1.0, size=g.m).astype(np.float32)
+        out.append(g)
+    return out
+
+
+@pytest.mark.parametrize("c", [1.0, 2.5, 0.375])
+def test_weighted_prune_with_equal_weights_is_the_unweighted_prune(c):
+    """Scaling every weight by the same c changes no comparison deg < rho:
+    the weighted rounds keep exactly the unweighted mask."""
+    rng = np.random.default_rng(int(c * 8))
+    for _ in range(15):
+        g = synth.random_small(rng, int(rng.integers(10, 60)), float(rng.uniform(0.05, 0.3)))
+        keep_u, rounds_u, nh_u, mh_u = oracle.prune(g.n, g.src, g.dst)
+        keep_w, rounds_w, nh_w, mh_w, _ = oracle.prune_weighted(
+            g.n, g.src, g.dst, np.full(g.m, c, np.float32))
+        assert np.array_equal(keep_u, keep_w) and (rounds_u, nh_u, mh_u) == (rounds_w, nh_w, mh_w)
+
+
+def test_weighted_prune_keeps_the_densest_subgraph():
+    """Theorem 4's argument with weighted degrees: every node of the maximal
+    densest subgraph (brute force) has weighted degree >= rho* >= rho(H) in
+    H, so it survives; rho(H) >= rho(G); every node of H has degree >= rho(H)."""
+    for g in _weighted_graphs(20, 5, 6, 12):
+        keep, rounds, nh, mh, WH = oracle.prune_weighted(g.n, g.src, g.dst, g.w)
+        rho, S = brute_force_densest(g.n, g.src, g.dst, g.w)
+        assert all(keep[u] for u in S)
+        wf = [Fraction(float(x)) for x in g.w]
+        assert WH / nh >= sum(wf, Fraction(0)) / g.n
+        deg = [Fraction(0)] * g.n
+        for e in range(g.m):
+            if keep[g.src[e]] and keep[g.dst[e]]:
+                deg[g.src[e]] += wf[e]
+                deg[g.dst[e]] += wf[e]
+        assert all(deg[u] * nh >= WH for u in range(g.n) if keep[u])
+
+
+def test_weighted_prune_matches_weighted_greedy():
+    """Theorem 5 with weighted degrees: greedy peeling (minimum weighted
+    degree first) passes through H, its density does not decrease before,
+    and the first decrease comes at H or later."""
+    checked = 0
+    for g in _weighted_graphs(30, 8):
+        keep, _, nh, mh, WH = oracle.prune_weighted(g.n, g.src, g.dst, g.w)
+        sizes, order = greedy_peel_weighted(g.n, g.src, g.dst, g.w)
+        k = g.n - nh
+        assert sizes[k] == (WH, nh)
+        assert set(order[k:]) == set(np.flatnonzero(keep))
+        dens = [W / N for W, N in sizes]
+        assert all(dens[i + 1] >= dens[i] for i in range(k))
+        checked += 1
+    assert checked == 30
