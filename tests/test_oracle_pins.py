@@ -359,9 +359,25 @@ def test_schedule_phases_are_star_forests():
             assert P >= deg.max()
 
 
+def _splitmix64(k):
+    """the k-th output (k = 1, 2, ...) of SplitMix64 seeded with 0"""
+    M = (1 << 64) - 1
+    z = (k * 0x9E3779B97F4A7C15) & M
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+    return z ^ (z >> 31)
+
+
+def test_splitmix64_known_answers():
+    """The first outputs of SplitMix64 seeded with 0, as its reference
+    implementation (Steele, Lea, Flood 2014; Vigna's splitmix64.c) prints."""
+    assert [_splitmix64(k) for k in (1, 2, 3)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4,
+                                                   0x06C45D188009454F]
+
+
 def test_schedule_first_fit_is_minimal():
     """Each edge sits in the first phase that admits it when the edges are
-    visited by descending leaf demand (ties by index): moving it to any
+    visited by ascending SplitMix64 key (ties by index): moving it to any
     earlier phase would break the star-forest rule or the size limit."""
     rng = np.random.default_rng(2)
     g = synth.random_small(rng, 40, 0.3)
@@ -372,9 +388,7 @@ def test_schedule_first_fit_is_minimal():
     exp_c = np.where((deg[g.src] > deg[g.dst]) | ((deg[g.src] == deg[g.dst]) & (g.src < g.dst)),
                      g.src, g.dst)
     assert np.array_equal(center, exp_c)
-    leaf = np.where(center == g.src, g.dst, g.src)
-    demand = np.bincount(leaf, minlength=g.n)
-    visit = sorted(range(g.m), key=lambda e: (-demand[leaf[e]], e))
+    visit = sorted(range(g.m), key=lambda e: (_splitmix64(e + 1), e))
     role = {}
     for e in visit:
         c = int(center[e])
