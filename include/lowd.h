@@ -103,6 +103,26 @@ lowd_status lowd_prune_weighted(int32_t n, int64_t m, const int32_t *src, const 
                                 void *stream);
 
 /*
+ * lowd_greedy_peel -- greedy peeling (the appendix's Algorithm 3), the second
+ * solver Algorithm 2's pruning can feed: from S = V and S* = V, repeatedly
+ * remove a node of minimum degree in S (ties: the smallest id) with its
+ * edges, replacing S* by S whenever rho(S) > rho(S*).  Exactly the
+ * sequential definition; one workgroup runs the removals over bucket
+ * bitsets in device memory ((largest degree + 1) * n / 8 bytes: graphs that
+ * would need more than 32 GiB give LOWD_E_UNSUPPORTED -- prune them first).
+ * By Theorem 5 the first n - n_h removals are exactly the nodes lowd_prune
+ * removes, so greedy on the pruned graph continues greedy on G.
+ *   order   [device] int32[n] out: removal order
+ *   rem_m   [device] int64[n] out: |E(S)| after each removal
+ *   in_set  [device] uint8[n] out: S*; may be NULL
+ *   num, den [host] out: |E(S*)|, |S*|; may be NULL
+ * Unweighted graphs.  Synchronises `stream`.
+ */
+lowd_status lowd_greedy_peel(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                             int32_t *order, int64_t *rem_m, uint8_t *in_set, int64_t *num,
+                             int64_t *den, void *stream);
+
+/*
  * lowd_init_loads -- Algorithm 1, initialisation: every edge gives half its
  * weight to each endpoint (f_e(u) = f_e(v) = w_e / 2) and the load of a node
  * is the sum of the halves it receives, summed in ascending edge index.

@@ -56,8 +56,9 @@ def _load():
                                        C.POINTER(i64), C.POINTER(C.c_double), C.POINTER(i64)]
         lib.oracle_ldd.argtypes = [i64, i64, _i32p, _i32p, fptr, _f64p, _i32p, _i64p, _f64p,
                                    C.POINTER(i64)]
+        lib.oracle_greedy.argtypes = [i64, i64, _i32p, _i32p, _i32p, _i64p, C.POINTER(i64)]
         for f in (lib.oracle_prune, lib.oracle_schedule, lib.oracle_init, lib.oracle_sweep,
-                  lib.oracle_stats, lib.oracle_extract, lib.oracle_ldd):
+                  lib.oracle_stats, lib.oracle_extract, lib.oracle_ldd, lib.oracle_greedy):
             f.restype = C.c_int
         _lib = lib
     return _lib
@@ -144,6 +145,24 @@ def extract(n: int, src: np.ndarray, dst: np.ndarray, w: Optional[np.ndarray], L
                               C.byref(nw), C.byref(den)), "oracle_extract")
     return dict(in_set=in_set, best_i=int(bi.value), num=int(nu.value), num_w=float(nw.value),
                 den=int(den.value))
+
+
+def greedy(n: int, src: np.ndarray, dst: np.ndarray):
+    """Greedy peeling (Algorithm 3) -> dict(order int32[n], rem_m int64[n],
+    best_i, num, den, in_set uint8[n]): S* = V minus the first best_i
+    removed nodes, with num = |E(S*)| and den = |S*|."""
+    lib = _load()
+    order = np.zeros(n, dtype=np.int32)
+    rem_m = np.zeros(n, dtype=np.int64)
+    bi = C.c_int64(0)
+    _check(lib.oracle_greedy(n, src.size, np.ascontiguousarray(src, np.int32),
+                             np.ascontiguousarray(dst, np.int32), order, rem_m, C.byref(bi)),
+           "oracle_greedy")
+    b = int(bi.value)
+    in_set = np.ones(n, dtype=np.uint8)
+    in_set[order[:b]] = 0
+    num = int(src.size) if b == 0 else int(rem_m[b - 1])
+    return dict(order=order, rem_m=rem_m, best_i=b, num=num, den=n - b, in_set=in_set)
 
 
 def prune_weighted(n: int, src: np.ndarray, dst: np.ndarray, w: np.ndarray):

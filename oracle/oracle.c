@@ -417,3 +417,55 @@ int oracle_ldd(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, con
     free(asc); free(rank); free(fi); free(fd);
     return ORACLE_OK;
 }
+
+/* ------------------------------------------------------------------------ *
+ * Greedy peeling (Appendix, Algorithm 3) on an unweighted graph: starting
+ * from S = V and S* = V, repeatedly remove a node of minimum degree in S
+ * (ties: the smallest id) with its edges; after each removal, if
+ * rho(S) > rho(S*) then S* = S.  Plain: every step scans all nodes.
+ *   order  [n]  out: the removal order
+ *   rem_m  [n]  out: |E(S)| after each removal
+ *   *best_i     out: the number of removals before S* (0 = V)
+ * ------------------------------------------------------------------------ */
+int oracle_greedy(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, int32_t *order,
+                  int64_t *rem_m, int64_t *best_i)
+{
+    if (n <= 0 || !order || !rem_m || !best_i) return ORACLE_E_ARG;
+    int64_t *deg = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    uint8_t *alive = (uint8_t *)malloc((size_t)n);
+    int64_t *rp = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t *adj = (int32_t *)malloc((size_t)(m > 0 ? 2 * m : 1) * sizeof(int32_t));
+    if (!deg || !alive || !rp || !adj) { free(deg); free(alive); free(rp); free(adj); return ORACLE_E_NOMEM; }
+    for (int64_t e = 0; e < m; ++e) { ++rp[src[e] + 1]; ++rp[dst[e] + 1]; }
+    for (int64_t u = 0; u < n; ++u) rp[u + 1] += rp[u];
+    {
+        int64_t *fill = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+        if (!fill) { free(deg); free(alive); free(rp); free(adj); return ORACLE_E_NOMEM; }
+        for (int64_t u = 0; u < n; ++u) fill[u] = rp[u];
+        for (int64_t e = 0; e < m; ++e) { adj[fill[src[e]]++] = dst[e]; adj[fill[dst[e]]++] = src[e]; }
+        free(fill);
+    }
+    for (int64_t u = 0; u < n; ++u) { deg[u] = rp[u + 1] - rp[u]; alive[u] = 1; }
+    int64_t M = m, N = n, bestM = m, bestN = n;
+    *best_i = 0;
+    for (int64_t step = 0; step < n; ++step) {
+        int64_t u = -1;
+        for (int64_t v = 0; v < n; ++v)
+            if (alive[v] && (u < 0 || deg[v] < deg[u])) u = v;
+        order[step] = (int32_t)u;
+        alive[u] = 0;
+        M -= deg[u];
+        N -= 1;
+        for (int64_t j = rp[u]; j < rp[u + 1]; ++j)
+            if (alive[adj[j]]) --deg[adj[j]];
+        rem_m[step] = M;
+        /* M / N > bestM / bestN, exactly */
+        if (N > 0 && (__int128)M * bestN > (__int128)bestM * N) {
+            bestM = M;
+            bestN = N;
+            *best_i = step + 1;
+        }
+    }
+    free(deg); free(alive); free(rp); free(adj);
+    return ORACLE_OK;
+}

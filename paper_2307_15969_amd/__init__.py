@@ -46,6 +46,7 @@ def lib() -> C.CDLL:
         L.lowd_prune.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp, vp, P(i32), P(i32), P(i64), vp]
         L.lowd_prune_weighted.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, P(i32),
                                           P(i32), P(i64), P(C.c_double), vp]
+        L.lowd_greedy_peel.argtypes = [i32, i64, vp, vp, vp, vp, vp, P(i64), P(i64), vp]
         L.lowd_init_loads.argtypes = [i32, i64, vp, vp, vp, i32, i32, P(vp), vp]
         L.lowd_iterate.argtypes = [vp, i32, vp]
         L.lowd_reset_loads.argtypes = [vp, vp]
@@ -70,7 +71,7 @@ def lib() -> C.CDLL:
         L.lowd_batch_retire.argtypes = [vp, vp, vp, vp, C.c_double, P(i32), P(i64), vp]
         L.lowd_batch_free.argtypes = [vp]
         L.lowd_batch_free.restype = None
-        for f in (L.lowd_prune, L.lowd_prune_weighted, L.lowd_init_loads, L.lowd_iterate, L.lowd_check,
+        for f in (L.lowd_prune, L.lowd_prune_weighted, L.lowd_greedy_peel, L.lowd_init_loads, L.lowd_iterate, L.lowd_check,
                   L.lowd_extract_densest, L.lowd_read_state, L.lowd_schedule_export,
                   L.lowd_ldd_readout, L.lowd_convergence_trace, L.lowd_dks_bound,
                   L.lowd_solver_info, L.lowd_batch_solve, L.lowd_schedule_build, L.lowd_reset_loads,
@@ -159,6 +160,46 @@ def prune_weighted(n: int, src, dst, w, stream=None) -> dict:
     return dict(node_keep=keep, relabel=relabel, src=hs[:mh], dst=hd[:mh], w=hw[:mh],
                 edge_map=emap[:mh], rounds=int(r.value), n_h=int(nh.value), m_h=mh,
                 w_h=float(wh.value))
+
+
+def greedy_peel(n: int, src, dst, stream=None) -> dict:
+    """Greedy peeling (Algorithm 3) on the GPU (lowd_greedy_peel): removal
+    order, |E(S)| after each removal, S* and its density num/den."""
+    torch = _torch()
+    s = _dev(src, torch.int32, "src")
+    d = _dev(dst, torch.int32, "dst")
+    order = torch.empty(n, dtype=torch.int32, device=s.device)
+    rem_m = torch.empty(n, dtype=torch.int64, device=s.device)
+    in_set = torch.empty(n, dtype=torch.uint8, device=s.device)
+    num, den = C.c_int64(0), C.c_int64(0)
+    _check(lib().lowd_greedy_peel(n, s.numel(), _ptr(s), _ptr(d), _ptr(order), _ptr(rem_m),
+                                  _ptr(in_set), C.byref(num), C.byref(den), _stream(stream)))
+    return dict(order=order, rem_m=rem_m, in_set=in_set, num=int(num.value), den=int(den.value))
+
+
+def densest_after_prune(n: int, src, dst, solver: str = "lowd", stream=None, **kw) -> dict:
+    """Algorithm 2 with a plug-in DSPSolver: prune G, solve the pruned graph
+    H with `solver` ("lowd" to a gap, or "greedy"), and map the set back to
+    G's node ids.  Returns num/den (|E(S)|, |S|) and in_set over G."""
+    torch = _torch()
+    pr = prune(n, src, dst, stream)
+    if pr["n_h"] == 0:
+        raise LowdError(-2, "the pruned graph is empty")
+    if solver == "lowd":
+        r = solve(pr["n_h"], pr["src"].clone(), pr["dst"].clone(), None, stream=stream, **kw)
+        sub = r["in_set"]
+        out = dict(num=r["num"], den=r["den"], gap=r["gap"], sweeps=r["sweeps"])
+    elif solver == "greedy":
+        r = greedy_peel(pr["n_h"], pr["src"].clone(), pr["dst"].clone(), stream)
+        sub = r["in_set"]
+        out = dict(num=r["num"], den=r["den"])
+    else:
+        raise ValueError(solver)
+    keep = pr["node_keep"].bool()
+    in_set = torch.zeros(n, dtype=torch.uint8, device=keep.device)
+    in_set[keep] = sub
+    out.update(in_set=in_set, n_h=pr["n_h"], m_h=pr["m_h"], rounds=pr["rounds"])
+    return out
 
 
 class Solver:

@@ -518,6 +518,26 @@ lowd_status lowd_prune_weighted(int32_t n, int64_t m, const int32_t *src, const 
     });
 }
 
+lowd_status lowd_greedy_peel(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                             int32_t *order, int64_t *rem_m, uint8_t *in_set, int64_t *num,
+                             int64_t *den, void *stream) {
+    return guarded([&] {
+        if (n < 1) fail(LOWD_E_ARG, "n must be >= 1");
+        if (m < 0 || m >= ((int64_t)1 << 31)) fail(LOWD_E_ARG, "m must be in [0, 2^31)");
+        if (m > 0 && (!src || !dst)) fail(LOWD_E_ARG, "src/dst is NULL");
+        if (!order || !rem_m) fail(LOWD_E_ARG, "order/rem_m is NULL");
+        hipStream_t s = (hipStream_t)stream;
+        validate_graph(n, m, src, dst, nullptr, s);
+        const int64_t bi = greedy_peel(n, m, src, dst, order, rem_m, in_set,
+                                       (int64_t)32 << 30, s);
+        int64_t mm = m;
+        if (bi > 0)
+            LOWD_HIP(hipMemcpy(&mm, rem_m + (bi - 1), sizeof(mm), hipMemcpyDeviceToHost));
+        if (num) *num = mm;
+        if (den) *den = (int64_t)n - bi;
+    });
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------- batches --

@@ -25,4 +25,11 @@ PruneResult run_prune_weighted(int32_t n, int64_t m, const int32_t *src, const i
                                int32_t *h_src, int32_t *h_dst, float *h_w, int64_t *edge_map,
                                double *w_h, hipStream_t s);
 
+// Greedy peeling (Algorithm 3) of an unweighted graph, exactly: the removal
+// order, |E(S)| after each removal, and S* (in_set, may be nullptr); returns
+// the number of removals before S*.  Fails (LOWD_E_UNSUPPORTED) when the
+// bucket bitsets would exceed max_bytes.
+int64_t greedy_peel(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, int32_t *order,
+                    int64_t *rem_m, uint8_t *in_set, int64_t max_bytes, hipStream_t s);
+
 }  // namespace lowd

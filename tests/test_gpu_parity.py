@@ -364,6 +364,63 @@ def test_weighted_prune_then_solve_keeps_the_optimum():
     assert max(rh, rg) <= min(eh["D"], eg["D"]) * (1 + 1e-12)
 
 
+# ---------------------------------------- greedy peeling plug-in (Alg. 3) --
+def _greedy_graphs():
+    rng = np.random.default_rng(23)
+    out = [("workload0", synth.workload(0))]
+    for i in range(4):
+        out.append((f"gnp{i}", synth.random_small(rng, int(rng.integers(2, 400)),
+                                                  float(rng.uniform(0.01, 0.3)))))
+    out.append(("chunglu20k", synth.chung_lu(20000, 200000, 2.1, seed=3, planted=60,
+                                             p_planted=0.3)))
+    return out
+
+
+@pytest.mark.parametrize("name,g", _greedy_graphs(), ids=lambda v: v if isinstance(v, str) else "")
+def test_greedy_peel_matches_oracle(name, g):
+    """Algorithm 3 on the GPU equals the oracle's sequential greedy: the
+    removal order, |E(S)| after every removal, S* and its density."""
+    log(f"greedy {name} n={g.n} m={g.m}")
+    r = lowd.greedy_peel(g.n, g.src, g.dst)
+    ro = oracle.greedy(g.n, g.src, g.dst)
+    assert np.array_equal(r["order"].cpu().numpy(), ro["order"])
+    assert np.array_equal(r["rem_m"].cpu().numpy(), ro["rem_m"])
+    assert (r["num"], r["den"]) == (ro["num"], ro["den"])
+    assert np.array_equal(r["in_set"].cpu().numpy(), ro["in_set"])
+
+
+@pytest.mark.parametrize("name,g", _greedy_graphs()[::5], ids=lambda v: v if isinstance(v, str) else "")
+def test_greedy_continues_on_the_pruned_graph(name, g):
+    """Theorem 5: greedy on G first removes exactly the nodes Algorithm 2
+    removes, and then continues as greedy on the pruned graph H (same
+    removal order through the renumbering)."""
+    pr = lowd.prune(g.n, g.src, g.dst)
+    rg = lowd.greedy_peel(g.n, g.src, g.dst)
+    rh = lowd.greedy_peel(pr["n_h"], pr["src"].clone(), pr["dst"].clone())
+    order_g = rg["order"].cpu().numpy()
+    keep = pr["node_keep"].cpu().numpy()
+    k = g.n - pr["n_h"]
+    assert set(order_g[:k].tolist()) == set(np.flatnonzero(keep == 0).tolist())
+    kept_ids = np.flatnonzero(keep)
+    assert np.array_equal(order_g[k:], kept_ids[rh["order"].cpu().numpy()])
+
+
+def test_prune_then_plugin_solvers():
+    """Algorithm 2 with a plug-in DSPSolver on workload 0: LOWD on H reaches
+    the max-flow optimum 435/30; greedy on H gives a set of density at least
+    half of it (Charikar), both mapped back to G's ids."""
+    g = synth.workload(0)
+    a = lowd.densest_after_prune(g.n, g.src, g.dst, "lowd", tol=1e-9)
+    b = lowd.densest_after_prune(g.n, g.src, g.dst, "greedy")
+    assert a["num"] * 30 == 435 * a["den"]
+    assert 2 * b["num"] * 30 >= 435 * b["den"]
+    for r in (a, b):
+        ins = r["in_set"].cpu().numpy().astype(bool)
+        assert ins.sum() == r["den"]
+        inside = ins[g.src] & ins[g.dst]
+        assert inside.sum() == r["num"]
+
+
 # ------------------------------------------- decomposition read-out --
 @pytest.mark.parametrize("T", [0, 3, 40])
 @pytest.mark.parametrize("name,g", GRAPHS, ids=[n for n, _ in GRAPHS])

@@ -583,3 +583,45 @@ def test_weighted_prune_matches_weighted_greedy():
         assert all(dens[i + 1] >= dens[i] for i in range(k))
         checked += 1
     assert checked == 30
+
+
+# ------------------------------------------------ greedy peeling (Algorithm 3) --
+def test_greedy_order_equals_an_independent_heap_greedy():
+    """The oracle's plain greedy (a full scan per step) removes the same nodes
+    in the same order as a heap-based implementation, with the same |E(S)|
+    after every removal."""
+    rng = np.random.default_rng(71)
+    for _ in range(25):
+        g = synth.random_small(rng, int(rng.integers(2, 120)), float(rng.uniform(0.02, 0.4)))
+        r = oracle.greedy(g.n, g.src, g.dst)
+        sizes, order = greedy_peel(g.n, g.src, g.dst)
+        assert r["order"].tolist() == order
+        assert [int(v) for v in r["rem_m"][:-1]] == [M for M, _ in sizes[1:]]
+
+
+def test_greedy_is_a_half_approximation_and_keeps_the_first_maximum():
+    """Charikar: the greedy set has density at least rho*/2 (brute force);
+    S* is the first (largest) remaining set of maximal density."""
+    for g in _random_graphs(30, 4, 12, False, 73):
+        r = oracle.greedy(g.n, g.src, g.dst)
+        rho_star, _ = brute_force_densest(g.n, g.src, g.dst)
+        rho = Fraction(r["num"], r["den"])
+        assert 2 * rho >= rho_star
+        dens = [Fraction(g.m, g.n)] + [Fraction(int(r["rem_m"][k]), g.n - k - 1)
+                                       for k in range(g.n - 1)]
+        assert rho == max(dens) and r["best_i"] == dens.index(max(dens))
+
+
+def test_greedy_passes_through_the_pruned_graph():
+    """Theorem 5 with the oracle's own greedy and prune: the first n - n_h
+    removals are exactly the nodes Algorithm 2 removes."""
+    rng = np.random.default_rng(79)
+    for _ in range(30):
+        g = synth.random_small(rng, int(rng.integers(8, 80)), float(rng.uniform(0.05, 0.3)))
+        if g.m == 0:
+            continue
+        keep, _, nh, mh = oracle.prune(g.n, g.src, g.dst)
+        r = oracle.greedy(g.n, g.src, g.dst)
+        k = g.n - nh
+        assert set(r["order"][:k].tolist()) == set(np.flatnonzero(keep == 0).tolist())
+        assert (int(r["rem_m"][k - 1]) if k > 0 else g.m) == mh
