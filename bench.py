@@ -319,6 +319,18 @@ def run_rmat24(args, torch, lowd, synth):
         "roofline": roofline(sweep_bytes(pr["n_h"], pr["m_h"], xb, 0, 8), r["per_sweep_s"],
                              "one sweep of H (HIP graph)"),
     })
+    sv.close()
+    # Algorithm 2's other plug-in: greedy peeling (Algorithm 3) of H
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gr = lowd.greedy_peel(pr["n_h"], hs, hd, stream)
+    torch.cuda.synchronize()
+    t_greedy = time.perf_counter() - t0
+    out["greedy_on_h"] = {"ms": t_greedy * 1e3, "density": f"{gr['num']}/{gr['den']}",
+                          "vs_lowd_density": (gr["num"] / gr["den"]) /
+                                             (r["ex"]["num"] / r["ex"]["den"])}
+    print(f"[bench] greedy on H: {t_greedy * 1e3:.1f} ms, density {gr['num']}/{gr['den']}",
+          flush=True)
     return out
 
 
