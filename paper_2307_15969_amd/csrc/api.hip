@@ -109,7 +109,7 @@ struct lowd_solver {
     DBuf<float> e_w;
     Csr csr;
     // schedule layout
-    DBuf<int32_t> tile_center, tail_nodes;
+    DBuf<int32_t> tile_center;
     DBuf<PhaseDesc> tail_desc, mid_desc;
     DBuf<int64_t> slot_edge, edge_slot;
     DBuf<uint32_t> slot_leaf, slot_next, center_next, tail_next, home;
@@ -206,7 +206,6 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
         upload(sv->tail_desc, tdesc, s);
         std::vector<PhaseDesc> mdesc(sc.desc.begin() + sc.P1, sc.desc.begin() + sc.P0);
         upload(sv->mid_desc, mdesc, s);
-        upload(sv->tail_nodes, sc.tail_nodes, s);
         upload(sv->slot_next, sc.slot_next, s);
         upload(sv->center_next, sc.center_next, s);
         upload(sv->tail_next, sc.tail_next, s);
