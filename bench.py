@@ -31,9 +31,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 PROFILE = os.path.join(ROOT, "profiles", "sweep_chunglu_1M_10M_f64.md")
+# the sources that decide the sweep's kernels and memory layout
 SWEEP_SOURCES = ["paper_2307_15969_amd/csrc/k_sweep.hip", "paper_2307_15969_amd/csrc/sweep_state.h",
-                 "paper_2307_15969_amd/csrc/schedule.cpp", "paper_2307_15969_amd/csrc/lowd_internal.h",
-                 "paper_2307_15969_amd/csrc/api.hip"]
+                 "paper_2307_15969_amd/csrc/schedule.cpp", "paper_2307_15969_amd/csrc/lowd_internal.h"]
 
 
 def profiled_traffic():
