@@ -36,6 +36,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <memory>
 #include <numeric>
 #include <utility>
 #include <vector>
@@ -69,6 +70,40 @@ inline uint64_t visit_key(int64_t e) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
+}
+
+// Edge indices 0..m-1 in ascending (visit_key, index) order: a stable LSD
+// radix sort on the 64-bit keys (11-bit digits), so equal keys keep
+// ascending index.
+std::vector<int64_t> sort_by_visit_key(int64_t m) {
+    std::vector<uint64_t> key((size_t)m), key2((size_t)m);
+    std::vector<int64_t> idx((size_t)m), idx2((size_t)m);
+    for (int64_t e = 0; e < m; ++e) {
+        key[(size_t)e] = visit_key(e);
+        idx[(size_t)e] = e;
+    }
+    constexpr int kDigit = 11;
+    constexpr size_t kBuckets = (size_t)1 << kDigit;
+    std::vector<int64_t> cnt(kBuckets);
+    for (int shift = 0; shift < 64; shift += kDigit) {
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (int64_t i = 0; i < m; ++i) ++cnt[(size_t)(key[(size_t)i] >> shift) & (kBuckets - 1)];
+        int64_t sum = 0;
+        for (size_t b = 0; b < kBuckets; ++b) {
+            const int64_t c = cnt[b];
+            cnt[b] = sum;
+            sum += c;
+        }
+        for (int64_t i = 0; i < m; ++i) {
+            const size_t b = (size_t)(key[(size_t)i] >> shift) & (kBuckets - 1);
+            const int64_t at = cnt[b]++;
+            key2[(size_t)at] = key[(size_t)i];
+            idx2[(size_t)at] = idx[(size_t)i];
+        }
+        key.swap(key2);
+        idx.swap(idx2);
+    }
+    return idx;
 }
 
 struct CostModel {
@@ -120,41 +155,89 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
             lf[(size_t)e] = a;
         }
     }
-    std::vector<std::pair<uint64_t, int64_t>> keyed((size_t)m);
-    for (int64_t e = 0; e < m; ++e) keyed[(size_t)e] = {visit_key(e), e};
-    std::sort(keyed.begin(), keyed.end());
-    std::vector<int64_t> visit((size_t)m);
-    for (int64_t i = 0; i < m; ++i) visit[(size_t)i] = keyed[(size_t)i].second;
-    std::vector<std::pair<uint64_t, int64_t>>().swap(keyed);
-    std::vector<Bits> used((size_t)n), noc((size_t)n);
-    std::vector<std::vector<uint8_t>> cnt((size_t)n);
+    const std::vector<int64_t> visit = sort_by_visit_key(m);
+    // the edges' centers and leaves in visiting order: the loop below then
+    // streams through them and can prefetch the node state ahead
+    std::vector<int32_t> cv((size_t)m), lv((size_t)m);
+    for (int64_t i = 0; i < m; ++i) {
+        cv[(size_t)i] = ctr[(size_t)visit[(size_t)i]];
+        lv[(size_t)i] = lf[(size_t)visit[(size_t)i]];
+    }
+    std::vector<int32_t> pv((size_t)m);
+    // The first 64 phases of every node live in flat arrays (one word per
+    // node, one byte per (node, phase) for star sizes); later phases, which
+    // only high-degree nodes reach, in per-node overflow storage.  The
+    // visiting order touches nodes at random, so the next edges' node state
+    // is prefetched.
+    std::vector<uint64_t> used0((size_t)n, 0), noc0((size_t)n, 0);
+    std::vector<uint8_t> cnt0((size_t)n * 64, 0);
+    struct Overflow {
+        Bits used, noc;
+        std::vector<uint8_t> cnt;   // star sizes of phases 64, 65, ...
+    };
+    std::vector<std::unique_ptr<Overflow>> ov((size_t)n);
+    auto used_word = [&](int32_t u, size_t wi) -> uint64_t {
+        if (wi == 0) return used0[(size_t)u];
+        const Overflow *o = ov[(size_t)u].get();
+        return o ? o->used.word(wi - 1) : 0ull;
+    };
+    auto noc_word = [&](int32_t u, size_t wi) -> uint64_t {
+        if (wi == 0) return noc0[(size_t)u];
+        const Overflow *o = ov[(size_t)u].get();
+        return o ? o->noc.word(wi - 1) : 0ull;
+    };
+    auto over = [&](int32_t u) -> Overflow & {
+        if (!ov[(size_t)u]) ov[(size_t)u].reset(new Overflow());
+        return *ov[(size_t)u];
+    };
+    constexpr int64_t kAhead = 8;
     int32_t P = 0;
     for (int64_t i = 0; i < m; ++i) {
-        const int64_t e = visit[(size_t)i];
-        const int32_t c = ctr[(size_t)e], l = lf[(size_t)e];
-        const Bits &bc = noc[(size_t)c];
-        const Bits &bl = used[(size_t)l];
+        if (i + kAhead < m) {
+            const int32_t ca = cv[(size_t)(i + kAhead)], la = lv[(size_t)(i + kAhead)];
+            __builtin_prefetch(&noc0[(size_t)ca]);
+            __builtin_prefetch(&used0[(size_t)ca]);
+            __builtin_prefetch(&used0[(size_t)la]);
+            __builtin_prefetch(&noc0[(size_t)la]);
+            __builtin_prefetch(&cnt0[(size_t)ca * 64]);
+        }
+        const int32_t c = cv[(size_t)i], l = lv[(size_t)i];
         int32_t p = 0;
         for (size_t wi = 0;; ++wi) {
-            uint64_t busy = bc.word(wi) | bl.word(wi);
+            const uint64_t busy = noc_word(c, wi) | used_word(l, wi);
             if (~busy) {
                 p = (int32_t)(wi * 64 + (size_t)__builtin_ctzll(~busy));
                 break;
             }
         }
-        used[(size_t)c].set(p);
-        used[(size_t)l].set(p);
-        noc[(size_t)l].set(p);
-        std::vector<uint8_t> &cc = cnt[(size_t)c];
-        if ((size_t)p >= cc.size()) cc.resize((size_t)p + 1 + ((size_t)p >> 1), 0);
-        if (++cc[(size_t)p] >= smax) noc[(size_t)c].set(p);
-        out.phase[(size_t)e] = p;
-        out.center[(size_t)e] = c;
+        uint8_t *cc;
+        if (p < 64) {
+            const uint64_t bit = 1ull << p;
+            used0[(size_t)c] |= bit;
+            used0[(size_t)l] |= bit;
+            noc0[(size_t)l] |= bit;
+            cc = &cnt0[(size_t)c * 64 + (size_t)p];
+            if (++*cc >= smax) noc0[(size_t)c] |= bit;
+        } else {
+            const int32_t q = p - 64;
+            Overflow &oc = over(c);
+            oc.used.set(q);
+            Overflow &ol = over(l);
+            ol.used.set(q);
+            ol.noc.set(q);
+            if ((size_t)q >= oc.cnt.size()) oc.cnt.resize((size_t)q + 1 + ((size_t)q >> 1), 0);
+            if (++oc.cnt[(size_t)q] >= smax) oc.noc.set(q);
+        }
+        pv[(size_t)i] = p;
         if (p + 1 > P) P = p + 1;
     }
     out.P = P;
-    { std::vector<Bits>().swap(used); std::vector<Bits>().swap(noc); }
-    std::vector<std::vector<uint8_t>>().swap(cnt);
+    for (int64_t i = 0; i < m; ++i) out.phase[(size_t)visit[(size_t)i]] = pv[(size_t)i];
+    out.center = std::move(ctr);
+    std::vector<uint64_t>().swap(used0);
+    std::vector<uint64_t>().swap(noc0);
+    std::vector<uint8_t>().swap(cnt0);
+    std::vector<std::unique_ptr<Overflow>>().swap(ov);
 
     if (force_p0 == -2) return;   // phase assignment only
 
@@ -162,20 +245,26 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
     std::vector<int64_t> pstart((size_t)P + 1, 0);
     for (int64_t e = 0; e < m; ++e) ++pstart[(size_t)out.phase[(size_t)e] + 1];
     for (int32_t p = 0; p < P; ++p) pstart[(size_t)p + 1] += pstart[(size_t)p];
+    // two stable counting sorts: by center, then by phase, so a phase's
+    // edges come grouped by center (ascending) in ascending edge index
     std::vector<int64_t> byphase((size_t)m);
     {
+        std::vector<int64_t> cstart((size_t)n + 1, 0);
+        for (int64_t e = 0; e < m; ++e) ++cstart[(size_t)out.center[(size_t)e] + 1];
+        for (int32_t u = 0; u < n; ++u) cstart[(size_t)u + 1] += cstart[(size_t)u];
+        std::vector<int64_t> bycenter((size_t)m);
+        for (int64_t e = 0; e < m; ++e) bycenter[(size_t)cstart[(size_t)out.center[(size_t)e]]++] = e;
         std::vector<int64_t> cur(pstart.begin(), pstart.end() - 1);
-        for (int64_t e = 0; e < m; ++e) byphase[(size_t)cur[(size_t)out.phase[(size_t)e]]++] = e;
+        for (int64_t i = 0; i < m; ++i) {
+            const int64_t e = bycenter[(size_t)i];
+            byphase[(size_t)cur[(size_t)out.phase[(size_t)e]]++] = e;
+        }
     }
     std::vector<int64_t> ecount((size_t)P, 0), maxstar((size_t)P, 0);
-    // stars per phase: (begin, len) into byphase after sorting by center
+    // stars per phase: (begin, len) into byphase
     struct Star { int64_t begin; int32_t len; int32_t center; };
     std::vector<std::vector<Star>> stars((size_t)P);
     for (int32_t p = 0; p < P; ++p) {
-        auto b = byphase.begin() + pstart[(size_t)p], en = byphase.begin() + pstart[(size_t)p + 1];
-        std::stable_sort(b, en, [&](int64_t x, int64_t y) {
-            return out.center[(size_t)x] < out.center[(size_t)y];
-        });
         ecount[(size_t)p] = pstart[(size_t)p + 1] - pstart[(size_t)p];
         std::vector<Star> &st = stars[(size_t)p];
         for (int64_t i = pstart[(size_t)p]; i < pstart[(size_t)p + 1];) {
