@@ -254,6 +254,63 @@ def test_single_node():
     assert ex["den"] == 1
 
 
+def test_degenerate_graphs_for_every_entry_point():
+    """No edges, one node, one edge: the decomposition read-out, the trace,
+    greedy peeling and both prunes give the definitions' answers."""
+    empty = synth.canonical(5, np.zeros(0, np.int64), np.zeros(0, np.int64))
+    one = synth.canonical(1, np.zeros(0, np.int64), np.zeros(0, np.int64))
+    edge = synth.canonical(6, np.array([4]), np.array([1]))
+    for g in (empty, one, edge):
+        sv = lowd.Solver(g.n, g.src, g.dst, None, "f64")
+        r = sv.ldd()
+        ro = oracle.ldd(g.n, g.src, g.dst, None, oracle_run(g, 0, 16)[1])
+        assert np.array_equal(r["k_end"], ro["k_end"]) and np.array_equal(r["f_end"], ro["f_end"])
+        assert np.array_equal(r["level"].cpu().numpy(), ro["level"])
+        tr = sv.trace(0, 3)
+        assert tr.shape == (1, 5) and tr[0, 0] == 0
+        gr = lowd.greedy_peel(g.n, g.src, g.dst)
+        go = oracle.greedy(g.n, g.src, g.dst)
+        assert np.array_equal(gr["order"].cpu().numpy(), go["order"])
+        assert (gr["num"], gr["den"]) == (go["num"], go["den"])
+        pu = lowd.prune(g.n, g.src, g.dst)
+        pw = lowd.prune_weighted(g.n, g.src, g.dst, np.ones(g.m, np.float32))
+        ko, rounds, nh, mh = oracle.prune(g.n, g.src, g.dst)
+        for p_ in (pu, pw):
+            assert np.array_equal(p_["node_keep"].cpu().numpy(), ko)
+            assert (p_["n_h"], p_["m_h"]) == (nh, mh)
+        sv.close()
+    # the single edge: one level of density 1/2, then the isolated nodes at 0
+    sv = lowd.Solver(edge.n, edge.src, edge.dst, None, "f64")
+    sv.iterate(2)
+    r = sv.ldd()
+    assert r["k_end"].tolist() == [2, 6] and r["f_end"].tolist() == [1.0, 1.0]
+    assert lowd.dks_bound(r["k_end"], r["f_end"], 1) == 0.5
+
+
+def test_batch_degenerate_graphs_and_tiny_batches():
+    """A batch of one graph; graphs without edges retire at once; an
+    all-converged batch iterates nothing."""
+    gs = [synth.canonical(3, np.zeros(0, np.int64), np.zeros(0, np.int64)),
+          synth.canonical(2, np.array([0]), np.array([1]))]
+    b = lowd.Batch(gs, "f64")
+    b.iterate(3)
+    b.extract(loads=True)
+    assert b.load.cpu().numpy().tolist() == [0, 0, 0, 0.5, 0.5]
+    assert b.num.cpu().numpy().tolist() == [0, 1] and b.den.cpu().numpy().tolist() == [3, 2]
+    active, edges = b.retire(0.0)
+    assert (active, edges) == (0, 0)
+    b.iterate(5)            # nothing left to sweep
+    b.extract(loads=True)
+    assert b.load.cpu().numpy().tolist() == [0, 0, 0, 0.5, 0.5]
+    b.close()
+    single = lowd.Batch([synth.workload(0)], "f64", tune=True)
+    single.iterate(4)
+    single.extract(loads=True)
+    xo, Lo, *_ = oracle_run(synth.workload(0), 4, 16)
+    assert np.array_equal(single.load.cpu().numpy(), Lo)
+    single.close()
+
+
 @pytest.mark.parametrize("src,dst,w,what", [
     ([0, 2], [1, 2], None, "self-loop"),
     ([0, 1], [1, 9], None, "out of range"),
