@@ -3,7 +3,10 @@
  * the LOWD densest-subgraph method: Locally Optimal Weight Distribution
  * (Algorithm 1) and its pruning pre-process (Algorithm 2) from Zhu, Liu, Feng,
  * Cheng, "Fast Searching The Densest Subgraph And Decomposition With Local
- * Optimality" (arXiv 2307.15969).
+ * Optimality" (arXiv 2307.15969).  Besides the solver: the locally-dense
+ * decomposition read-out (Problem 2) and Corollary 1's bounds, convergence
+ * traces, greedy peeling (the appendix's Algorithm 3) as Algorithm 2's
+ * plug-in solver, and a batched form for many small graphs.
  *
  * Conventions for every entry point
  *  - Graphs are COO edge lists, one entry per undirected edge (Section II,

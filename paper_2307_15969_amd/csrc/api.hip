@@ -13,7 +13,6 @@
 #include <string>
 #include <vector>
 
-#include "../../include/lowd.h"
 #include "extract.h"
 #include "lowd_internal.h"
 #include "prune.h"

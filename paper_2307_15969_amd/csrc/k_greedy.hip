@@ -190,7 +190,7 @@ int64_t greedy_peel(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
     const int64_t W = ((int64_t)n + 63) / 64, S = (W + 63) / 64;
     const int64_t bytes = (maxd + 1) * (W + S) * 8;
     if (bytes > max_bytes)
-        fail(-5, "greedy peeling needs " + std::to_string(bytes >> 20) +
+        fail(LOWD_E_UNSUPPORTED, "greedy peeling needs " + std::to_string(bytes >> 20) +
                      " MiB of bucket bitsets (degree range x nodes); prune the graph first");
     DBuf<uint64_t> words((size_t)((maxd + 1) * W)), summ((size_t)((maxd + 1) * S));
     DBuf<int32_t> deg((size_t)n), count((size_t)maxd + 1);
@@ -206,7 +206,7 @@ int64_t greedy_peel(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
     int64_t bi = 0;
     LOWD_HIP(hipMemcpyAsync(&bi, best.p, sizeof(bi), hipMemcpyDeviceToHost, s));
     LOWD_HIP(hipStreamSynchronize(s));
-    if (bi < 0) fail(-4, "greedy peeling lost track of a degree bucket");
+    if (bi < 0) fail(LOWD_E_HIP, "greedy peeling lost track of a degree bucket");
     if (in_set)
         hipLaunchKernelGGL(k_greedy_in_set, dim3(grid_for(n, 256)), dim3(256), 0, s, n, order, bi,
                            in_set);

@@ -414,7 +414,7 @@ PruneResult run_prune_weighted(int32_t n, int64_t m, const int32_t *src, const i
         LOWD_HIP(hipMemcpyAsync(r, range.p, sizeof(r), hipMemcpyDeviceToHost, s));
         LOWD_HIP(hipStreamSynchronize(s));
         if (r[1] - r[0] > kMaxExpSpan)
-            fail(-5, "weights span more than 2^40 in scale; exact weighted pruning needs them "
+            fail(LOWD_E_UNSUPPORTED, "weights span more than 2^40 in scale; exact weighted pruning needs them "
                      "closer");
         qmin = r[0];
         hipLaunchKernelGGL(k_fixed_weights, dim3(grid_for(m, 256)), dim3(256), 0, s, m, w, qmin,

@@ -201,7 +201,7 @@ void radix_sort_impl(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, i
     if (n <= 1 || bits <= 0) return;
     int64_t nb = cdiv(n, kRadixChunk);
     int64_t nh = nb * kDigits;
-    if (tmp_bytes < radix_sort_tmp_bytes(n)) fail(-1, "radix sort scratch too small");
+    if (tmp_bytes < radix_sort_tmp_bytes(n)) fail(LOWD_E_ARG, "radix sort scratch too small");
     int64_t *hist = (int64_t *)tmp;
     int64_t *scan_tmp = hist + nh;
     size_t scan_bytes = tmp_bytes - (size_t)nh * sizeof(int64_t);
@@ -235,7 +235,7 @@ void exclusive_scan_impl(const T *in, T *out, int64_t n, T *total_dev, void *tmp
                          size_t tmp_bytes, hipStream_t s) {
     if (n <= 0) return;
     int64_t nb = cdiv(n, kScanTile);
-    if (tmp_bytes < exclusive_scan_tmp_bytes(n)) fail(-1, "scan scratch too small");
+    if (tmp_bytes < exclusive_scan_tmp_bytes(n)) fail(LOWD_E_ARG, "scan scratch too small");
     T *partial = (T *)tmp;
     hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, n,
                        partial);

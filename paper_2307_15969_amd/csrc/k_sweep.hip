@@ -794,7 +794,7 @@ static void sweep_launchers(SweepLaunch &fn) {
             LOWD_BATCH_CASE(4, 1)
             LOWD_BATCH_CASE(8, 0)
             LOWD_BATCH_CASE(8, 1)
-            default: fail(-1, "unsupported batch workgroup shape");
+            default: fail(LOWD_E_ARG, "unsupported batch workgroup shape");
         }
 #undef LOWD_BATCH_CASE
     };
@@ -804,7 +804,7 @@ static void sweep_launchers(SweepLaunch &fn) {
                         : shape == 16 ? (const void *)k_batch<St, 8, false>
                         : shape == 17 ? (const void *)k_batch<St, 8, true>
                                       : nullptr;
-        if (!k) fail(-1, "unsupported batch workgroup shape");
+        if (!k) fail(LOWD_E_ARG, "unsupported batch workgroup shape");
         LOWD_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     };
     fn.batch_init_loads = [](int64_t N, const int32_t *deg, void *Lstate, hipStream_t s) {

@@ -8,6 +8,8 @@
 #include <string>
 #include <vector>
 
+#include "../../include/lowd.h"
+
 namespace lowd {
 
 // ---------------------------------------------------------------- errors --

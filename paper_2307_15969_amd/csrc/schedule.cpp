@@ -126,7 +126,7 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
     if (smax > kMaxStar && force_p0 != -2) {
         // the device layout holds stars of up to kMaxStar leaves; callers that
         // only want the phase assignment pass force_p0 = -2
-        fail(-1, "star_max must be at most 16 for the sweep kernels");
+        fail(LOWD_E_ARG, "star_max must be at most 16 for the sweep kernels");
     }
     out.n = n;
     out.m = m;
@@ -466,7 +466,7 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
         out.home[(size_t)v] = (uint32_t)first[(size_t)v];
     }
     if (entries >= (int64_t)kNoStation)
-        fail(-5, "graph too large for 31-bit station indices");
+        fail(LOWD_E_UNSUPPORTED, "graph too large for 31-bit station indices");
     out.entries = entries;
     // the orientation bit rides on the leaf slot's next station
     for (int64_t sl = 0; sl < (P0 < P ? out.desc[(size_t)P0].slot_base : nslots); ++sl)
