@@ -122,6 +122,7 @@ struct lowd_solver {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int32_t ntail = 0;
+    int64_t nslots = 0;
     ~lowd_solver() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -129,7 +130,7 @@ struct lowd_solver {
 };
 
 static void reset_state(lowd_solver *sv, hipStream_t s) {
-    const int64_t nslots = (int64_t)sv->sch.slot_leaf.size();
+    const int64_t nslots = sv->nslots;
     if (nslots > 0)
         sv->fn.init_slots(nslots, sv->slot_edge.p, sv->weighted ? sv->e_w.p : nullptr,
                           sv->slot_x.p, sv->weighted ? sv->slot_w.p : nullptr, s);
@@ -213,6 +214,7 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
 
         // state
         const int64_t nslots = (int64_t)sc.slot_leaf.size();
+        sv->nslots = nslots;
         sv->slot_x.alloc((size_t)nslots * sv->fn.x_bytes);
         if (sv->weighted) sv->slot_w.alloc((size_t)nslots);
         sv->E.alloc((size_t)sc.entries * sv->fn.l_bytes);
@@ -250,6 +252,20 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
             LOWD_HIP(hipGraphInstantiate(&sv->exec, sv->graph, nullptr, nullptr, 0));
         }
         LOWD_HIP(hipStreamSynchronize(s));
+        // the layout lives on the device now; keep only what later calls read
+        // (phases and centers for lowd_schedule_export, counts for info)
+        {
+            Schedule &k = sv->sch;
+            std::vector<int32_t>().swap(k.tile_center);
+            std::vector<uint32_t>().swap(k.slot_leaf);
+            std::vector<int64_t>().swap(k.slot_edge);
+            std::vector<int64_t>().swap(k.edge_slot);
+            std::vector<int32_t>().swap(k.tail_nodes);
+            std::vector<uint32_t>().swap(k.slot_next);
+            std::vector<uint32_t>().swap(k.center_next);
+            std::vector<uint32_t>().swap(k.tail_next);
+            std::vector<uint32_t>().swap(k.home);
+        }
         *out = guard.release();
     });
 }
