@@ -93,6 +93,8 @@ WORKLOADS = {
     "rmat24": "R-MAT scale 24, edge factor 16, (.57,.19,.19,.05), pruned by Algorithm 2",
     "batch4096": "4096 Chung-Lu graphs (beta 2.3), edges log-uniform in [100, 50000], "
                  "planted blocks of 5-40 nodes",
+    "uniform": "diagnostic: 2^28 uniform random pairs on 2^25 nodes (max degree ~45, few wide "
+               "phases); sweeps only",
 }
 
 
@@ -334,6 +336,47 @@ def run_rmat24(args, torch, lowd, synth):
     return out
 
 
+def run_uniform(args, torch, lowd, synth):
+    """The sweep where phases are wide: a uniform random graph has a small
+    maximum degree, so a sweep is a few dozen phases of millions of edges
+    each, and the kernels run at memory speed.  Times sweeps only."""
+    t0 = time.perf_counter()
+    g = synth.uniform_pairs(25, 28, seed=args.seed)
+    print(f"[bench] workload {g.name}: n={g.n} m={g.m} generated in "
+          f"{time.perf_counter() - t0:.1f}s", flush=True)
+    src = torch.from_numpy(g.src).cuda()
+    dst = torch.from_numpy(g.dst).cuda()
+    del g.src, g.dst
+    stream = torch.cuda.current_stream()
+    state = args.state or "f32k"
+    t0 = time.perf_counter()
+    sv = lowd.Solver(g.n, src, dst, None, state, star_max=16)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    info = sv.info()
+    print(f"[bench] setup {t_setup:.1f}s info {info}", flush=True)
+    ev_a = torch.cuda.Event(enable_timing=True)
+    ev_b = torch.cuda.Event(enable_timing=True)
+    sv.iterate(max(args.warmup, 1), stream)
+    sweeps = 10 * args.steps
+    ev_a.record(stream)
+    sv.iterate(sweeps, stream)
+    ev_b.record(stream)
+    ev_b.synchronize()
+    per = ev_a.elapsed_time(ev_b) / 1e3 / sweeps
+    m = info["m"]
+    xb = 4 if state == "f32k" else 8
+    out = base_line(args, m / per, per * 1e3, state,
+                    {"workload": WORKLOADS["uniform"], "n": g.n, "m": m, "star_max": 16,
+                     "seed": args.seed})
+    out.update({"sweep_ms": per * 1e3, "sweeps_timed": sweeps, "setup_s": t_setup,
+                "schedule": info,
+                "roofline": roofline(sweep_bytes(g.n, m, xb, 0, 8), per,
+                                     "one sweep (HIP graph); wide phases")})
+    sv.close()
+    return out
+
+
 def run_batch4096(args, torch, lowd, synth):
     t0 = time.perf_counter()
     gs = synth.workload(4, seed=args.seed)
@@ -499,7 +542,7 @@ def main():
         print(f"[bench] copy calibration: one copy of {nbytes} bytes", flush=True)
         del a, b
     run = {"chunglu1m": run_chunglu1m, "chunglu4m": run_chunglu4m, "rmat24": run_rmat24,
-           "batch4096": run_batch4096}[args.workload]
+           "batch4096": run_batch4096, "uniform": run_uniform}[args.workload]
     out = run(args, torch, lowd, synth)
     print(json.dumps(out), flush=True)
 

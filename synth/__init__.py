@@ -215,6 +215,18 @@ def batch_of_graphs(count: int = 4096, seed: int = 1, m_lo: int = 100, m_hi: int
     return out
 
 
+def uniform_pairs(log_n: int = 25, log_m: int = 28, seed: int = 1) -> Graph:
+    """2^log_m uniform random pairs on 2^log_n nodes, self-loops and repeats
+    dropped (a handful at these sizes): a graph of small maximum degree,
+    whose sweep phases are few and wide (a diagnostic of the sweep's memory
+    bandwidth, not one of the paper's workloads)."""
+    rng = np.random.default_rng(seed)
+    n, m = 1 << log_n, 1 << log_m
+    a = rng.integers(0, n, size=m, dtype=np.int64)
+    b = rng.integers(0, n, size=m, dtype=np.int64)
+    return canonical(n, a, b, None, f"uniform_2^{log_n}_2^{log_m}")
+
+
 def random_small(rng: np.random.Generator, n: int, p: float, weighted: bool = False) -> Graph:
     """G(n, p) for brute-force checks; optional weights in {1..4}/2 (exact in
     binary floating point) or lognormal."""
