@@ -132,11 +132,19 @@ lowd_status lowd_greedy_peel(int32_t n, int64_t m, const int32_t *src, const int
  * Also validates the graph and builds, once, the edge schedule the sweeps
  * follow: the edges are split into phases, each phase a set of vertex-
  * disjoint stars of at most `star_max` leaves (the center of an edge is its
- * endpoint of larger degree, ties to the smaller id; edge e, in ascending
- * index, joins the first phase where its center is not a leaf and has fewer
- * than star_max leaves and its leaf is unused).  A sweep processes the phases
- * in order; the result equals processing the edges one by one in ascending
- * (phase, edge index).
+ * endpoint of larger degree, ties to the smaller id; the edges are visited in
+ * ascending order of the e-th output of SplitMix64 seeded with 0, ties by
+ * index, and edge e joins the first phase where its center is not a leaf and
+ * has fewer than star_max leaves and its leaf is unused).  A sweep processes
+ * the phases in order; the result equals processing the edges one by one in
+ * ascending (phase, edge index).
+ *
+ * How a sweep runs (none of this changes the result): the wide phases as one
+ * launch each, the next narrower ones inside one workgroup with the loads in
+ * global memory, and the last, narrowest ones inside one workgroup with
+ * their nodes' loads in LDS.  A cost model places the two splits;
+ * LOWD_MID_SPLIT and LOWD_TAIL_SPLIT in the environment (read by this call)
+ * override them.
  *
  *   n, m          nodes and edges (n >= 1, m >= 0, m < 2^31)
  *   src, dst      [device] int32[m]; read during this call only

@@ -120,7 +120,7 @@ struct Schedule {
     std::vector<int32_t> phase_depth;     // [P] deepest star
 };
 
-// Builds the phase schedule (first fit over edges in ascending index) and
+// Builds the phase schedule (first fit over the edges in visiting order) and
 // the tile layout.
 // lds_bytes bounds the single-workgroup tiers' LDS (descriptors, and node
 // loads of l_bytes each for the last tier; 0 = whole-GPU launches only);

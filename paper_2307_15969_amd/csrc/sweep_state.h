@@ -52,25 +52,31 @@ struct StateF64 {
     // -diff_c (center is v; exact negation by the sign bit), so the move goes
     // from u to v exactly when s > 0, its size is d = min(|s| * 0.5, cap),
     // and the center loses d exactly when that direction and the center's
-    // role agree.  Only exact rewrites of step() are used: x - y == x + (-y);
-    // min picks one of its operands (none is NaN or -0 here); negation flips
-    // the sign bit.  So the bits agree with step().
+    // role agree.  Both directions' moves are formed (d_dn = min(half, a),
+    // d_up = min(half, b)) and applied, and the direction selects among the
+    // results: the comparison then runs beside the arithmetic instead of
+    // ahead of it, which shortens the dependent path from one step's center
+    // load to the next's.  Only exact rewrites of step() are used: x - y ==
+    // x + (-y); min picks one of its operands (none is NaN or -0 here);
+    // negation flips the sign bit.  So the bits agree with step().
     __device__ static inline void step_center(L &lc, L &ll, uint32_t flip, X &x, float wf) {
         const double w = (double)wf;
         const double a = x;
         const double b = w - a;
         const double diff = lc - ll;
-        const double s = flip_sign(diff, flip);
-        const bool down = s > 0.0;
         const double half = __builtin_fabs(diff) * 0.5;
-        const double cap = down ? a : b;
-        const double d = min_f64(half, cap);
-        const uint32_t sx = down ? 0x80000000u : 0u;      // x loses d when moving down
-        const double dc = flip_sign(d, sx ^ flip);         // the center loses d iff sx ^ flip
-        lc = lc + dc;
-        ll = ll - dc;
-        const double xs = a + flip_sign(d, sx);
-        x = (!down && d == b) ? w : xs;
+        const bool down = flip_sign(diff, flip) > 0.0;
+        const double d_dn = min_f64(half, a);
+        const double d_up = min_f64(half, b);
+        // the center's change: down, it loses d_dn unless it is v; else it
+        // gains d_up unless it is v
+        const double c_dn = flip_sign(d_dn, 0x80000000u ^ flip);
+        const double c_up = flip_sign(d_up, flip);
+        const double lc_dn = lc + c_dn, lc_up = lc + c_up;
+        const double ll_dn = ll - c_dn, ll_up = ll - c_up;
+        lc = down ? lc_dn : lc_up;
+        ll = down ? ll_dn : ll_up;
+        x = down ? a - d_dn : ((d_up == b) ? w : a + d_up);
     }
     __device__ static inline double flip_sign(double v, uint32_t bit) {
         uint64_t u = __builtin_bit_cast(uint64_t, v) ^ ((uint64_t)bit << 32);

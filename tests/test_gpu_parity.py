@@ -114,6 +114,26 @@ def test_sweeps_are_bit_exact(name, g, smax, tier, split):
     assert abs(s - so) <= 1e-12 * abs(so) and abs(s2 - s2o) <= 1e-12 * abs(s2o)
 
 
+@pytest.mark.parametrize("tier", ["auto", "no_lds", "all_mid"])
+def test_reset_restores_the_initial_state(tier, split):
+    """A reset after some sweeps gives back Algorithm 1's initial state (the
+    loads at every node's first station, the fractions), and the sweeps after
+    it follow the oracle from there."""
+    split(tier)
+    g = GRAPHS[2][1]
+    sv = lowd.Solver(g.n, g.src, g.dst, g.w, "f64")
+    sv.iterate(3)
+    sv.check()
+    sv.reset()
+    x, L = gpu_state(sv)
+    xo, Lo = oracle.init(g.n, g.src, g.dst, g.w)
+    assert np.array_equal(L, Lo) and np.array_equal(x, xo)
+    sv.iterate(4)
+    x, L = gpu_state(sv)
+    xo, Lo, *_ = oracle_run(g, 4, 16)
+    assert np.array_equal(L, Lo) and np.array_equal(x, xo)
+
+
 @pytest.mark.parametrize("name,g", GRAPHS, ids=[n for n, _ in GRAPHS])
 def test_schedule_export_equals_oracle(name, g):
     sv = lowd.Solver(g.n, g.src, g.dst, g.w, "f64", star_max=16)
