@@ -102,14 +102,16 @@ def single_solve(sv, stream, tol, check_every, ev_a, ev_b):
     """reset, then sweep/check until the gap tolerance; returns (sweeps,
     seconds spent in sweeps measured with events on the sweep stream, final
     extraction).  The sweeps between checks follow lowd.next_check: at most
-    check_every, fewer when the gap's decay predicts the tolerance sooner."""
+    check_every, fewer when the gap's decay predicts the tolerance sooner;
+    as in lowd.solve, the first check comes after the first check_every
+    sweeps."""
     import paper_2307_15969_amd as lowd
     sv.reset(stream)
     sweeps = 0
     sweep_s = 0.0
-    ex = sv.extract(stream)
-    hist = [(0, ex["gap"])]
-    while ex["gap"] > tol:
+    ex = None
+    hist = []
+    while ex is None or ex["gap"] > tol:
         k = lowd.next_check(hist, tol, check_every)
         ev_a.record(stream)
         sv.iterate(k, stream)

@@ -320,17 +320,22 @@ def solve(n: int, src, dst, w=None, state: str = "f64", star_max: int = 16, tol:
     """Sweeps until the density gap (D - rho) / rho is at most `tol` (D is
     the dual objective, an upper bound on the optimum; rho the density of the
     extracted set, a lower bound), checking at most every `check_every`
-    sweeps (sooner when the gap's decay predicts the tolerance, next_check)."""
+    sweeps (sooner when the gap's decay predicts the tolerance, next_check).
+    The first check comes after the first sweeps, not at the initial state:
+    its gap only feeds the decay estimate, and the decay of the first sweeps
+    is much faster than the later one it would be used to predict."""
     sv = Solver(n, src, dst, w, state, star_max, stream)
     sweeps = 0
-    ex = sv.extract(stream)
-    hist = [(0, ex["gap"])]
-    while ex["gap"] > tol and sweeps < max_sweeps:
+    ex = None
+    hist = []
+    while sweeps < max_sweeps and (ex is None or ex["gap"] > tol):
         k = min(next_check(hist, tol, check_every), max_sweeps - sweeps)
         sv.iterate(k, stream)
         sweeps += k
         ex = sv.extract(stream)
         hist.append((sweeps, ex["gap"]))
+    if ex is None:   # max_sweeps == 0
+        ex = sv.extract(stream)
     ex["sweeps"] = sweeps
     ex["solver"] = sv
     return ex
