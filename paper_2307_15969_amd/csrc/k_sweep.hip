@@ -228,6 +228,8 @@ __device__ __forceinline__ void run_station_tile(StationTile<St, kWeighted> &tl,
 // phase is spread instead: a tile is shared by 2^spread waves, each running
 // 64 >> spread of its lanes (lanes outside the wave's share exit at once).
 constexpr int kPhaseBlock = 64;
+// s_waitcnt immediate: vector memory count 0, the other counters not waited
+constexpr int kWaitLoads = 0x0F70;
 static_assert(kWave == 64, "lane shares assume 64-wide waves");
 constexpr int kMaxSpreadLog2 = 3;    // at least 8 lanes per wave
 constexpr int32_t kSpreadWaves = 256;  // spread until about one wave per CU
@@ -245,6 +247,10 @@ k_phase(PhaseDesc d, int32_t spread, int64_t center_base, const uint32_t *__rest
     StationTile<St, kWeighted> tl;
     load_static(tl, d, t, lane, center_base, center_next, slot_next, slot_x, slot_w);
     load_loads(tl, lane, E);
+    // Every load of the tile is needed before the chain.  Waiting for all of
+    // them here, on every path, keeps the compiler's per-path wait tracking
+    // from placing a wait for the previous store before each store.
+    __builtin_amdgcn_s_waitcnt(kWaitLoads);
     run_station_tile(tl, lane, slot_x, E);
 }
 
@@ -379,10 +385,14 @@ __device__ __forceinline__ void mid_phase(StationTile<St, kWeighted> &tl, const 
                                           const float *__restrict__ slot_w, typename St::L *E) {
     if (wave >= d.T[0]) return;
     load_loads(tl, lane, E);
+    // all loads first, on every path (see k_phase); this also completes the
+    // next phase's prefetch, which the loads overtake in any case
+    __builtin_amdgcn_s_waitcnt(kWaitLoads);
     run_station_tile(tl, lane, slot_x, E);
     for (int32_t t = wave + kTailWaves; t < d.T[0]; t += kTailWaves) {
         load_static(tl, d, t, lane, center_base, center_next, slot_next, slot_x, slot_w);
         load_loads(tl, lane, E);
+        __builtin_amdgcn_s_waitcnt(kWaitLoads);
         run_station_tile(tl, lane, slot_x, E);
     }
 }
