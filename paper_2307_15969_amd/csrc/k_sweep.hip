@@ -149,7 +149,8 @@ struct StationTile {
     int32_t depth;        // wave-uniform
     int64_t base;         // wave-uniform: first slot of the tile
     int64_t lane_entry;   // the lane's center station
-    uint32_t cnext;
+    uint32_t cnext;       // next station of the center, or the sink
+    uint32_t sink;
     uint32_t nx[kMaxStar];
     typename St::X x[kMaxStar];
     float w[kMaxStar];
@@ -178,9 +179,19 @@ __device__ __forceinline__ void load_static(StationTile<St, kWeighted> &tl, cons
     const int64_t li = (int64_t)(d.tile0 + t) * kWave + lane;
     tl.lane_entry = center_base + li;
     tl.cnext = center_next[li];
+    tl.sink = (uint32_t)d.sink;
     const uint32_t *pn = slot_next + base + lane;
     const typename St::X *px = slot_x + base + lane;
     const float *pw = kWeighted ? slot_w + base + lane : nullptr;
+    if (tl.depth == kMaxStar) {   // a full tile: no per-row guard
+#pragma unroll
+        for (int k = 0; k < kMaxStar; ++k) {
+            tl.nx[k] = pn[k * kWave];
+            tl.x[k] = px[k * kWave];
+            tl.w[k] = kWeighted ? pw[k * kWave] : 1.0f;
+        }
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < kMaxStar; ++k) {
         if (k < tl.depth) {
@@ -197,28 +208,49 @@ __device__ __forceinline__ void load_loads(StationTile<St, kWeighted> &tl, int l
                                            const typename St::L *E) {
     tl.lc = E[tl.lane_entry];
     const typename St::L *pl = E + tl.base + lane;
+    if (tl.depth == kMaxStar) {
+#pragma unroll
+        for (int k = 0; k < kMaxStar; ++k) tl.ll[k] = pl[k * kWave];
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < kMaxStar; ++k)
         if (k < tl.depth) tl.ll[k] = pl[k * kWave];
 }
 
+// A row without a next station (padding, or a lane without a star) stores
+// into the sink entry, so the stores need no per-lane branch; a full tile
+// needs no per-row guard either, and its rows form one straight block.
 template <class St, bool kWeighted>
 __device__ __forceinline__ void run_station_tile(StationTile<St, kWeighted> &tl, int lane,
                                                  typename St::X *__restrict__ slot_x,
                                                  typename St::L *E) {
-#pragma unroll
-    for (int k = 0; k < kMaxStar; ++k)
-        if (k < tl.depth) St::step_center(tl.lc, tl.ll[k], tl.nx[k] & kCenterIsDst, tl.x[k], tl.w[k]);
     typename St::X *px = slot_x + tl.base + lane;
+    if (tl.depth == kMaxStar) {
 #pragma unroll
-    for (int k = 0; k < kMaxStar; ++k) {
-        if (k < tl.depth) {
+        for (int k = 0; k < kMaxStar; ++k)
+            St::step_center(tl.lc, tl.ll[k], tl.nx[k] & kCenterIsDst, tl.x[k], tl.w[k]);
+#pragma unroll
+        for (int k = 0; k < kMaxStar; ++k) {
             px[k * kWave] = tl.x[k];
             const uint32_t nx = tl.nx[k] & ~kCenterIsDst;
-            if (nx != kNoStation) E[nx] = tl.ll[k];
+            E[nx != kNoStation ? nx : tl.sink] = tl.ll[k];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kMaxStar; ++k)
+            if (k < tl.depth)
+                St::step_center(tl.lc, tl.ll[k], tl.nx[k] & kCenterIsDst, tl.x[k], tl.w[k]);
+#pragma unroll
+        for (int k = 0; k < kMaxStar; ++k) {
+            if (k < tl.depth) {
+                px[k * kWave] = tl.x[k];
+                const uint32_t nx = tl.nx[k] & ~kCenterIsDst;
+                E[nx != kNoStation ? nx : tl.sink] = tl.ll[k];
+            }
         }
     }
-    if (tl.cnext != kNoStation) E[tl.cnext] = tl.lc;
+    E[tl.cnext != kNoStation ? tl.cnext : tl.sink] = tl.lc;
 }
 
 // --------------------------------------------------- whole-GPU phase -----
@@ -296,7 +328,7 @@ __device__ __forceinline__ PhaseDesc desc_from_lds(const PhaseDesc *sd, int32_t 
     d.tile0 = __builtin_amdgcn_readlane(v, 2);
 #pragma unroll
     for (int k = 0; k < kMaxStar; ++k) d.T[k] = __builtin_amdgcn_readlane(v, 3 + k);
-    d.pad = 0;
+    d.sink = __builtin_amdgcn_readlane(v, 3 + kMaxStar);
     return d;
 }
 

@@ -76,7 +76,8 @@ struct PhaseDesc {
     int64_t slot_base;                // first slot of the phase
     int32_t tile0;                    // first tile (index into tile_center / 64)
     int32_t T[kMaxStar];              // T[k] = tiles of depth > k; T[0] = tiles
-    int32_t pad;
+    int32_t sink;                     // entry that takes the stores of stations without a
+                                      // next one (the last entry; unused by the LDS tiers)
 };
 
 // LDS bytes the tail workgroup spends on its phase descriptors.

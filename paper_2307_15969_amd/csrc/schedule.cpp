@@ -380,7 +380,7 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
         PhaseDesc &d = out.desc[(size_t)p];
         d.slot_base = nslots;
         d.tile0 = (int32_t)ntiles;
-        d.pad = 0;
+        d.sink = 0;
         int32_t t = (int32_t)((st.size() + kWave - 1) / kWave);
         for (int k = 0; k < kMaxStar; ++k) {
             int32_t cnt = 0;   // tiles whose first (deepest) star is longer than k
@@ -465,9 +465,12 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
         else first[(size_t)v] = entries++;
         out.home[(size_t)v] = (uint32_t)first[(size_t)v];
     }
-    if (entries >= (int64_t)kNoStation)
+    // one more entry, the sink: stores of padding rows and empty lanes go
+    // there, so the kernels store without a branch
+    if (entries + 1 >= (int64_t)kNoStation)
         fail(LOWD_E_UNSUPPORTED, "graph too large for 31-bit station indices");
-    out.entries = entries;
+    for (PhaseDesc &d : out.desc) d.sink = (int32_t)entries;
+    out.entries = entries + 1;
     // the orientation bit rides on the leaf slot's next station
     for (int64_t sl = 0; sl < (P0 < P ? out.desc[(size_t)P0].slot_base : nslots); ++sl)
         if (out.slot_next[(size_t)sl] != kNoStation)
