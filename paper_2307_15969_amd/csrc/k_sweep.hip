@@ -102,6 +102,15 @@ __device__ __forceinline__ void load_tile(Tile<St, kWeighted> &tl, const PhaseDe
     const uint32_t *pl = slot_leaf + base + lane;
     const typename St::X *px = slot_x + base + lane;
     const float *pw = kWeighted ? slot_w + base + lane : nullptr;
+    if (tl.depth == kMaxStar) {   // a full tile: no per-row guard
+#pragma unroll
+        for (int k = 0; k < kMaxStar; ++k) {
+            tl.enc[k] = pl[k * kWave];
+            tl.x[k] = px[k * kWave];
+            tl.w[k] = kWeighted ? pw[k * kWave] : 1.0f;
+        }
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < kMaxStar; ++k) {
         if (k < tl.depth) {
@@ -121,13 +130,27 @@ __device__ __forceinline__ void run_tile(Tile<St, kWeighted> &tl, int lane,
                                          typename St::X *__restrict__ slot_x, LPtr L) {
     typename St::L Lc = L[tl.c];
     typename St::L Ll[kMaxStar];
+    typename St::X *px = slot_x + tl.base + lane;
+    if (tl.depth == kMaxStar) {   // a full tile: one straight block
+#pragma unroll
+        for (int k = 0; k < kMaxStar; ++k) Ll[k] = L[tl.enc[k] & ~kCenterIsDst];
+#pragma unroll
+        for (int k = 0; k < kMaxStar; ++k)
+            St::step_center(Lc, Ll[k], tl.enc[k] & kCenterIsDst, tl.x[k], tl.w[k]);
+#pragma unroll
+        for (int k = 0; k < kMaxStar; ++k) {
+            px[k * kWave] = tl.x[k];
+            L[tl.enc[k] & ~kCenterIsDst] = Ll[k];
+        }
+        L[tl.c] = Lc;
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < kMaxStar; ++k)
         if (k < tl.depth) Ll[k] = L[tl.enc[k] & ~kCenterIsDst];
 #pragma unroll
     for (int k = 0; k < kMaxStar; ++k)
         if (k < tl.depth) St::step_center(Lc, Ll[k], tl.enc[k] & kCenterIsDst, tl.x[k], tl.w[k]);
-    typename St::X *px = slot_x + tl.base + lane;
 #pragma unroll
     for (int k = 0; k < kMaxStar; ++k) {
         if (k < tl.depth) {
