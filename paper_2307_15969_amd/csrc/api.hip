@@ -561,6 +561,7 @@ struct lowd_batch {
     int32_t state = 0;
     SweepLaunch fn{};
     std::vector<int64_t> node_ptr_h, edge_ptr_h;
+    int64_t max_nodes = 0;   // nodes of the largest graph
     int64_t total_phases = 0, max_phases = 0;
     DBuf<int64_t> node_ptr, edge_ptr, desc_ptr, slot_edge;
     DBuf<int32_t> gsrc, gdst, node_graph, order_all, order, active, tile_center, deg;
@@ -694,6 +695,8 @@ lowd_status lowd_batch_prepare(int32_t G, const int64_t *node_ptr, const int64_t
         get_sweep_launchers(state, false, b->fn);
         b->node_ptr_h.assign(node_ptr, node_ptr + G + 1);
         b->edge_ptr_h.assign(edge_ptr, edge_ptr + G + 1);
+        for (int32_t g = 0; g < G; ++g)
+            b->max_nodes = std::max<int64_t>(b->max_nodes, node_ptr[g + 1] - node_ptr[g]);
 
         std::vector<int32_t> hs((size_t)M), hd((size_t)M);
         if (M > 0) {
@@ -863,6 +866,8 @@ lowd_status lowd_batch_extract(lowd_batch *b, uint8_t *in_set, int64_t *num, int
         a.N = b->N;
         a.M = b->M;
         a.node_ptr = b->node_ptr.p;
+        a.edge_ptr = b->edge_ptr.p;
+        a.max_nodes = b->max_nodes;
         a.node_graph = b->node_graph.p;
         a.gsrc = b->gsrc.p;
         a.gdst = b->gdst.p;

@@ -69,6 +69,8 @@ struct BatchExtractArgs {
     int64_t N = 0;                     // total nodes
     int64_t M = 0;                     // total edges
     const int64_t *node_ptr = nullptr; // [G+1] device
+    const int64_t *edge_ptr = nullptr; // [G+1] device: graph g's edges, in graph order
+    int64_t max_nodes = 0;             // nodes of the largest graph
     const int32_t *node_graph = nullptr; // [N] graph of each node
     const int32_t *gsrc = nullptr;     // [M] global node ids
     const int32_t *gdst = nullptr;

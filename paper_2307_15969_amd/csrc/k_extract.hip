@@ -402,23 +402,23 @@ __global__ void k_graph_keys(int64_t N, const uint32_t *vals, const int32_t *nod
         keys2[k] = (uint32_t)node_graph[vals[k]];
 }
 
-__global__ void k_local_positions(int64_t N, const uint32_t *asc, const int32_t *node_graph,
-                                  const int64_t *node_ptr, int32_t *pos) {
+// Positions in the batch's sorted order, which keeps each graph's nodes
+// together (graph g at node_ptr[g] .. node_ptr[g+1]-1): node u's position
+// within its graph is pos[u] - node_ptr[g].
+__global__ void k_batch_positions(int64_t N, const uint32_t *asc, int32_t *pos) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < N;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t u = asc[k];
-        pos[u] = (int32_t)(k - node_ptr[node_graph[u]]);
-    }
+         k += (int64_t)gridDim.x * blockDim.x)
+        pos[asc[k]] = (int32_t)k;
 }
 
+// Both ends of an edge are in one graph, so the smaller batch position is
+// the graph's offset plus the smaller position within the graph.
 __global__ void k_edge_min_pos_batch(int64_t M, const int32_t *gsrc, const int32_t *gdst,
-                                     const int32_t *node_graph, const int64_t *node_ptr,
                                      const int32_t *pos, unsigned long long *hist) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < M;
          e += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t u = gsrc[e], v = gdst[e];
-        const int32_t a = pos[u], b = pos[v];
-        atomicAdd(&hist[node_ptr[node_graph[u]] + (a < b ? a : b)], 1ull);
+        const int32_t a = pos[gsrc[e]], b = pos[gdst[e]];
+        atomicAdd(&hist[a < b ? a : b], 1ull);
     }
 }
 
@@ -474,11 +474,37 @@ __global__ void __launch_bounds__(kArgBlock) k_best_batch(int32_t G, const int64
     }
 }
 
+// One workgroup per graph: each edge's smaller position is counted in LDS
+// (a graph's nodes fit one workgroup's LDS), then the graph's bins are
+// written out.  Counts are integers, so the order of the additions does not
+// matter.  Writes every bin of hist.
+constexpr int kGraphHistBlock = 256;
+constexpr size_t kGraphHistLds = 160 * 1024;   // a CU's LDS
+__global__ void __launch_bounds__(kGraphHistBlock)
+k_edge_min_pos_graph(const int64_t *node_ptr, const int64_t *edge_ptr, const int32_t *gsrc,
+                     const int32_t *gdst, const int32_t *pos, unsigned long long *hist) {
+    extern __shared__ uint32_t hbin[];
+    const int32_t g = (int32_t)blockIdx.x;
+    const int64_t base = node_ptr[g];
+    const int32_t n = (int32_t)(node_ptr[g + 1] - base);
+    for (int32_t i = threadIdx.x; i < n; i += kGraphHistBlock) hbin[i] = 0u;
+    __syncthreads();
+    const int64_t e1 = edge_ptr[g + 1];
+    for (int64_t e = edge_ptr[g] + threadIdx.x; e < e1; e += kGraphHistBlock) {
+        const int32_t a = pos[gsrc[e]], b = pos[gdst[e]];
+        atomicAdd(&hbin[(a < b ? a : b) - base], 1u);
+    }
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < n; i += kGraphHistBlock) hist[base + i] = hbin[i];
+}
+
 __global__ void k_in_set_batch(int64_t N, const int32_t *pos, const int32_t *node_graph,
-                               const int64_t *best, uint8_t *in_set) {
+                               const int64_t *node_ptr, const int64_t *best, uint8_t *in_set) {
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < N;
-         u += (int64_t)gridDim.x * blockDim.x)
-        in_set[u] = pos[u] >= best[node_graph[u]] ? 1 : 0;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t g = node_graph[u];
+        in_set[u] = (int64_t)pos[u] - node_ptr[g] >= best[g] ? 1 : 0;
+    }
 }
 
 }  // namespace
@@ -518,13 +544,22 @@ void launch_extract_batch(const BatchExtractArgs &a, BatchExtractScratch &sc, hi
     bool alt2 = false;
     radix_sort_u32(sc.g0.p, vals, sc.g1.p, vals_alt, N, gbits, sc.tmp.p, sc.tmp.bytes(), &alt2, s);
     const uint32_t *asc = alt2 ? vals_alt : vals;
-    hipLaunchKernelGGL(k_local_positions, dim3(gn), dim3(256), 0, s, N, asc, a.node_graph,
-                       a.node_ptr, sc.pos.p);
-    hipLaunchKernelGGL(k_fill_i64, dim3(gn), dim3(256), 0, s, N, sc.hist.p);
-    if (a.M > 0)
-        hipLaunchKernelGGL(k_edge_min_pos_batch, dim3(grid_for(a.M, 256)), dim3(256), 0, s, a.M,
-                           a.gsrc, a.gdst, a.node_graph, a.node_ptr, sc.pos.p,
+    hipLaunchKernelGGL(k_batch_positions, dim3(gn), dim3(256), 0, s, N, asc, sc.pos.p);
+    const size_t hist_lds = (size_t)a.max_nodes * sizeof(uint32_t);
+    if (a.edge_ptr && a.max_nodes > 0 && hist_lds <= kGraphHistLds) {
+        if (hist_lds > 64 * 1024)
+            LOWD_HIP(hipFuncSetAttribute((const void *)k_edge_min_pos_graph,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)hist_lds));
+        hipLaunchKernelGGL(k_edge_min_pos_graph, dim3((unsigned)a.G), dim3(kGraphHistBlock),
+                           hist_lds, s, a.node_ptr, a.edge_ptr, a.gsrc, a.gdst, sc.pos.p,
                            (unsigned long long *)sc.hist.p);
+    } else {
+        hipLaunchKernelGGL(k_fill_i64, dim3(gn), dim3(256), 0, s, N, sc.hist.p);
+        if (a.M > 0)
+            hipLaunchKernelGGL(k_edge_min_pos_batch, dim3(grid_for(a.M, 256)), dim3(256), 0, s,
+                               a.M, a.gsrc, a.gdst, sc.pos.p, (unsigned long long *)sc.hist.p);
+    }
     hipLaunchKernelGGL(k_reverse<int64_t>, dim3(gn), dim3(256), 0, s, N, sc.hist.p, sc.rev.p);
     exclusive_scan_i64(sc.rev.p, sc.rev.p, N, nullptr, sc.tmp.p, sc.tmp.bytes(), s);
     hipLaunchKernelGGL(k_suffix<int64_t>, dim3(gn), dim3(256), 0, s, N, sc.rev.p, sc.hist.p,
@@ -532,7 +567,7 @@ void launch_extract_batch(const BatchExtractArgs &a, BatchExtractScratch &sc, hi
     hipLaunchKernelGGL(k_best_batch, dim3((unsigned)a.G), dim3(kArgBlock), 0, s, a.G, a.node_ptr,
                        N, sc.W.p, a.L64, sc.best.p, a.num, a.den, a.D);
     hipLaunchKernelGGL(k_in_set_batch, dim3(gn), dim3(256), 0, s, N, sc.pos.p, a.node_graph,
-                       sc.best.p, a.in_set);
+                       a.node_ptr, sc.best.p, a.in_set);
     LOWD_HIP(hipGetLastError());
 }
 
