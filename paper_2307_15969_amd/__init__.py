@@ -315,6 +315,34 @@ def next_check(history, tol: float, check_every: int) -> int:
     return check_every
 
 
+def _density(ex: dict) -> float:
+    return (ex["num_w"] if ex.get("weighted") else ex["num"]) / ex["den"] if ex["den"] else 0.0
+
+
+def certify(sv: "Solver", best, tol: float, stream=None):
+    """One convergence check.  D, the largest load, bounds the optimum from
+    above at every sweep and any extracted set bounds it from below, so the
+    best set extracted so far is certified once (D - rho_best) / rho_best is
+    at most tol.  D alone is cheap; the extraction (a sort of all nodes) runs
+    only when D does not certify the best set already.  Returns (best, gap):
+    best is the densest extraction so far (its "D" and "gap" updated to this
+    check)."""
+    if best is not None:
+        D = sv.check(stream)[0]
+        rho = _density(best)
+        gap = (D - rho) / rho if rho > 0 else (0.0 if D <= 0 else math.inf)
+        if gap <= tol:
+            return dict(best, D=D, gap=gap), gap
+    ex = sv.extract(stream)
+    ex["weighted"] = sv.weighted
+    if best is None or _density(ex) >= _density(best):
+        best = ex
+    rho = _density(best)
+    D = ex["D"]
+    gap = (D - rho) / rho if rho > 0 else (0.0 if D <= 0 else math.inf)
+    return dict(best, D=D, gap=gap), gap
+
+
 def solve(n: int, src, dst, w=None, state: str = "f64", star_max: int = 16, tol: float = 1e-6,
           check_every: int = 10, max_sweeps: int = 10000, stream=None) -> dict:
     """Sweeps until the density gap (D - rho) / rho is at most `tol` (D is
@@ -327,15 +355,16 @@ def solve(n: int, src, dst, w=None, state: str = "f64", star_max: int = 16, tol:
     sv = Solver(n, src, dst, w, state, star_max, stream)
     sweeps = 0
     ex = None
+    gap = math.inf
     hist = []
-    while sweeps < max_sweeps and (ex is None or ex["gap"] > tol):
+    while sweeps < max_sweeps and gap > tol:
         k = min(next_check(hist, tol, check_every), max_sweeps - sweeps)
         sv.iterate(k, stream)
         sweeps += k
-        ex = sv.extract(stream)
-        hist.append((sweeps, ex["gap"]))
+        ex, gap = certify(sv, ex, tol, stream)
+        hist.append((sweeps, gap))
     if ex is None:   # max_sweeps == 0
-        ex = sv.extract(stream)
+        ex, gap = certify(sv, None, tol, stream)
     ex["sweeps"] = sweeps
     ex["solver"] = sv
     return ex
