@@ -107,9 +107,9 @@ std::vector<int64_t> sort_by_visit_key(int64_t m) {
 }
 
 struct CostModel {
-    double grid_fixed_us = 6.5;                  // boundary + dependent memory round trips
+    double grid_fixed_us = 3.9;                  // launch, one round trip, chain, stores
     double grid_us_per_edge = 48.0 / 4.0e6;      // ~48 B per edge at ~4 TB/s
-    double mid_fixed_us = 2.0;                   // barrier + gathers through one CU
+    double mid_fixed_us = 3.8;                   // barrier + gathers through one CU
     double mid_us_per_round = 1.2;               // each further tile per wave (no prefetch)
     double mid_us_per_edge = 0.0018;             // ~4 random cache lines per edge, one CU
     double tail_fixed_us = 1.0;                  // barrier + LDS gathers
