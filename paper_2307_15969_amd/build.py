@@ -23,6 +23,10 @@ ARCH = os.environ.get("LOWD_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall",
           "-I" + os.path.join(HERE, "..", "include")]
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# The sweep kernels take their first 16 argument dwords preloaded into scalar
+# registers (gfx950 kernel-argument preloading; the code keeps a prologue
+# that loads them from memory where the firmware does not preload).
+PER_FILE = {"k_sweep.hip": ["-mllvm", "-amdgpu-kernarg-preload-count=16"]}
 
 
 def _hipcc() -> str:
@@ -37,6 +41,7 @@ def _compile(src: str) -> str:
     cmd = [_hipcc(), "-c", src, "-o", obj] + COMMON
     if src.endswith(".hip"):
         cmd += DEVICE
+    cmd += PER_FILE.get(os.path.basename(src), [])
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     out = "\n".join(l for l in r.stdout.splitlines()
                     if "packed-fp32-ops" not in l and "--hip-link" not in l)

@@ -181,28 +181,35 @@ struct StationTile {
     typename St::L ll[kMaxStar];
 };
 
-// the parts that do not depend on the previous phase
-template <class St, bool kWeighted>
-__device__ __forceinline__ void load_static(StationTile<St, kWeighted> &tl, const PhaseDesc &d,
-                                            int32_t t, int lane, int64_t center_base,
-                                            const uint32_t *__restrict__ center_next,
-                                            const uint32_t *__restrict__ slot_next,
-                                            const typename St::X *__restrict__ slot_x,
-                                            const float *__restrict__ slot_w) {
-    int32_t depth = 0;
+// A tile's depth and first slot.  Tile t of a phase has depth
+// #{k : T[k] > t} and follows sum_k min(T[k], t) full rows of the phase.
+__device__ __forceinline__ void tile_geometry(const PhaseDesc &d, int32_t t, int32_t &depth,
+                                              int64_t &base) {
+    int32_t dp = 0;
     int64_t rows = 0;
 #pragma unroll
     for (int k = 0; k < kMaxStar; ++k) {
-        depth += (d.T[k] > t) ? 1 : 0;
+        dp += (d.T[k] > t) ? 1 : 0;
         rows += (int64_t)(d.T[k] < t ? d.T[k] : t);
     }
-    tl.depth = __builtin_amdgcn_readfirstlane(depth);
-    const int64_t base = d.slot_base + rows * kWave;
+    depth = __builtin_amdgcn_readfirstlane(dp);
+    base = d.slot_base + rows * kWave;
+}
+
+// the parts that do not depend on the previous phase, for a tile of the
+// given depth whose rows start at slot `base`; li = the lane's index among
+// all tile lanes
+template <class St, bool kWeighted>
+__device__ __forceinline__ void load_static_at(StationTile<St, kWeighted> &tl, int32_t depth,
+                                               int64_t base, int64_t li, int lane,
+                                               int64_t center_base,
+                                               const uint32_t *__restrict__ center_next,
+                                               const uint32_t *__restrict__ slot_next,
+                                               const typename St::X *__restrict__ slot_x,
+                                               const float *__restrict__ slot_w) {
+    tl.depth = depth;
     tl.base = base;
-    const int64_t li = (int64_t)(d.tile0 + t) * kWave + lane;
     tl.lane_entry = center_base + li;
-    tl.cnext = center_next[li];
-    tl.sink = (uint32_t)d.sink;
     const uint32_t *pn = slot_next + base + lane;
     const typename St::X *px = slot_x + base + lane;
     const float *pw = kWeighted ? slot_w + base + lane : nullptr;
@@ -213,16 +220,33 @@ __device__ __forceinline__ void load_static(StationTile<St, kWeighted> &tl, cons
             tl.x[k] = px[k * kWave];
             tl.w[k] = kWeighted ? pw[k * kWave] : 1.0f;
         }
-        return;
-    }
+    } else {
 #pragma unroll
-    for (int k = 0; k < kMaxStar; ++k) {
-        if (k < tl.depth) {
-            tl.nx[k] = pn[k * kWave];
-            tl.x[k] = px[k * kWave];
-            tl.w[k] = kWeighted ? pw[k * kWave] : 1.0f;
+        for (int k = 0; k < kMaxStar; ++k) {
+            if (k < tl.depth) {
+                tl.nx[k] = pn[k * kWave];
+                tl.x[k] = px[k * kWave];
+                tl.w[k] = kWeighted ? pw[k * kWave] : 1.0f;
+            }
         }
     }
+    // last: in k_phase center_next is the first argument not preloaded
+    tl.cnext = center_next[li];
+}
+
+template <class St, bool kWeighted>
+__device__ __forceinline__ void load_static(StationTile<St, kWeighted> &tl, const PhaseDesc &d,
+                                            int32_t t, int lane, int64_t center_base,
+                                            const uint32_t *__restrict__ center_next,
+                                            const uint32_t *__restrict__ slot_next,
+                                            const typename St::X *__restrict__ slot_x,
+                                            const float *__restrict__ slot_w) {
+    int32_t depth;
+    int64_t base;
+    tile_geometry(d, t, depth, base);
+    load_static_at(tl, depth, base, (int64_t)(d.tile0 + t) * kWave + lane, lane, center_base,
+                   center_next, slot_next, slot_x, slot_w);
+    tl.sink = (uint32_t)d.sink;
 }
 
 // the loads, written by earlier phases
@@ -289,19 +313,30 @@ static_assert(kWave == 64, "lane shares assume 64-wide waves");
 constexpr int kMaxSpreadLog2 = 3;    // at least 8 lanes per wave
 constexpr int32_t kSpreadWaves = 256;  // spread until about one wave per CU
 
+// The first 16 dwords of the arguments (through center_next) are all a full
+// tile needs before its first loads; they are preloaded into scalar
+// registers at wave launch, so a full tile's loads do not wait for the
+// argument fetch (the descriptor and slot_w follow).  full_tiles = T[15]:
+// tiles t < full_tiles have depth 16 and start at slot_base + 16 * 64 * t.
 template <class St, bool kWeighted>
 __global__ void __launch_bounds__(kPhaseBlock)
-k_phase(PhaseDesc d, int32_t spread, int64_t center_base, const uint32_t *__restrict__ center_next,
+k_phase(int64_t slot_base, int32_t tile0, int32_t tiles, int32_t full_tiles, int32_t spread,
+        int64_t center_base, typename St::L *__restrict__ E,
         const uint32_t *__restrict__ slot_next, typename St::X *__restrict__ slot_x,
-        const float *__restrict__ slot_w, typename St::L *__restrict__ E) {
+        const uint32_t *__restrict__ center_next, PhaseDesc d, const float *__restrict__ slot_w) {
     const int lane = threadIdx.x & (kWave - 1);
     const int32_t t = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x >> spread));
-    if (t >= d.T[0]) return;
+    if (t >= tiles) return;
     const int32_t share = (int32_t)(blockIdx.x & ((1u << spread) - 1));
     if ((lane >> (6 - spread)) != share) return;
+    int32_t depth = kMaxStar;
+    int64_t base = slot_base + (int64_t)t * (kMaxStar * kWave);
+    if (t >= full_tiles) tile_geometry(d, t, depth, base);
     StationTile<St, kWeighted> tl;
-    load_static(tl, d, t, lane, center_base, center_next, slot_next, slot_x, slot_w);
+    load_static_at(tl, depth, base, (int64_t)(tile0 + t) * kWave + lane, lane, center_base,
+                   center_next, slot_next, slot_x, slot_w);
     load_loads(tl, lane, E);
+    tl.sink = (uint32_t)d.sink;
     // Every load of the tile is needed before the chain.  Waiting for all of
     // them here, on every path, keeps the compiler's per-path wait tracking
     // from placing a wait for the previous store before each store.
@@ -793,9 +828,10 @@ static void sweep_launchers(SweepLaunch &fn) {
         while (spread < kMaxSpreadLog2 && ((int64_t)tiles << (spread + 1)) <= kSpreadWaves)
             ++spread;
         const unsigned blocks = (unsigned)((int64_t)tiles << spread);
-        hipLaunchKernelGGL((k_phase<St, kW>), dim3(blocks), dim3(kPhaseBlock), 0, s, d, spread,
-                           center_base, center_next, slot_next, (typename St::X *)slot_x, slot_w,
-                           (typename St::L *)E);
+        hipLaunchKernelGGL((k_phase<St, kW>), dim3(blocks), dim3(kPhaseBlock), 0, s, d.slot_base,
+                           d.tile0, d.T[0], d.T[kMaxStar - 1], spread, center_base,
+                           (typename St::L *)E, slot_next, (typename St::X *)slot_x, center_next,
+                           d, slot_w);
     };
     fn.tail = [](int32_t nph, const PhaseDesc *descs, const int32_t *tile_center,
                  const uint32_t *slot_leaf, void *slot_x, const float *slot_w, int64_t tail_base,
