@@ -119,6 +119,10 @@ struct lowd_solver {
     ExtractScratch ex;
     LddScratch ldd;
     DBuf<uint8_t> ldd_in_set;
+    // unit weights: the other end of each incidence entry, and the nodes of
+    // degree >= kBigDegree, for the extraction's atomic-free count
+    DBuf<int32_t> adj, big;
+    int32_t nbig = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int32_t ntail = 0;
@@ -196,6 +200,19 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
                     hipMemcpyAsync(sv->e_w.p, w, (size_t)m * 4, hipMemcpyDeviceToDevice, s));
         }
         build_incidence(n, m, sv->e_src.p, sv->e_dst.p, sv->csr, s);
+        if (!sv->weighted) {
+            sv->adj.alloc((size_t)(2 * m));
+            build_adjacency(m, sv->csr, sv->e_src.p, sv->e_dst.p, sv->adj.p, s);
+            std::vector<int32_t> deg((size_t)n, 0), big;
+            for (int64_t e = 0; e < m; ++e) {
+                ++deg[(size_t)hs[(size_t)e]];
+                ++deg[(size_t)hd[(size_t)e]];
+            }
+            for (int32_t u = 0; u < n; ++u)
+                if (deg[(size_t)u] >= kBigDegree) big.push_back(u);
+            upload(sv->big, big, s);
+            sv->nbig = (int32_t)big.size();
+        }
 
         // schedule layout
         upload(sv->tile_center, sc.tile_center, s);
@@ -331,6 +348,11 @@ lowd_status lowd_extract_densest(lowd_solver *sv, uint8_t *in_set, int64_t *num_
         a.src = sv->e_src.p;
         a.dst = sv->e_dst.p;
         a.w = sv->weighted ? sv->e_w.p : nullptr;
+        if (!sv->weighted && sv->m > 0) {
+            a.adj = sv->adj.p;
+            a.big = sv->big.p;
+            a.nbig = sv->nbig;
+        }
         a.in_set = in_set;
         launch_extract(a, sv->ex, s);
         int64_t best[2];
@@ -424,6 +446,11 @@ lowd_status lowd_ldd_readout(lowd_solver *sv, int32_t *level, int64_t *k_end, do
         a.src = sv->e_src.p;
         a.dst = sv->e_dst.p;
         a.w = sv->weighted ? sv->e_w.p : nullptr;
+        if (!sv->weighted && sv->m > 0) {
+            a.adj = sv->adj.p;
+            a.big = sv->big.p;
+            a.nbig = sv->nbig;
+        }
         a.in_set = sv->ldd_in_set.p;
         launch_ldd(a, sv->ex, sv->ldd, level, k_end, f_end, nlevels, s);
     });

@@ -52,6 +52,52 @@ __global__ void k_edge_min_pos(int64_t m, const int32_t *src, const int32_t *dst
     }
 }
 
+// Unweighted, without atomics: node u's bin is the number of its neighbours
+// at higher positions (positions are distinct, so every edge is counted once,
+// at its lower end).  Groups of 8 lanes per node of degree below kBigDegree;
+// the others are left to k_towards_higher_big.  Writes every such bin.
+constexpr int kRowLanes = 8;
+__global__ void __launch_bounds__(256) k_towards_higher_small(int32_t n, const int64_t *row_ptr,
+                                                              const int32_t *adj,
+                                                              const int32_t *pos,
+                                                              unsigned long long *hist) {
+    const int sub = threadIdx.x & (kRowLanes - 1);
+    const int64_t groups = (int64_t)gridDim.x * (blockDim.x / kRowLanes);
+    for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / kRowLanes) + threadIdx.x / kRowLanes;
+         u < n; u += groups) {
+        const int64_t b = row_ptr[u], e = row_ptr[u + 1];
+        if (e - b >= kBigDegree) continue;   // the whole group skips it
+        const int32_t pu = pos[u];
+        uint32_t c = 0;
+        for (int64_t j = b + sub; j < e; j += kRowLanes) c += pos[adj[j]] > pu ? 1u : 0u;
+        for (int d = kRowLanes / 2; d > 0; d >>= 1) c += __shfl_down(c, d, kRowLanes);
+        if (sub == 0) hist[pu] = c;
+    }
+}
+
+// One workgroup per node of degree >= kBigDegree (the list big[]).
+constexpr int kBigBlock = 256;
+__global__ void __launch_bounds__(kBigBlock) k_towards_higher_big(const int32_t *big,
+                                                                  const int64_t *row_ptr,
+                                                                  const int32_t *adj,
+                                                                  const int32_t *pos,
+                                                                  unsigned long long *hist) {
+    __shared__ uint32_t part[kBigBlock / kWave];
+    const int32_t u = big[blockIdx.x];
+    const int32_t pu = pos[u];
+    uint32_t c = 0;
+    for (int64_t j = row_ptr[u] + threadIdx.x; j < row_ptr[u + 1]; j += kBigBlock)
+        c += pos[adj[j]] > pu ? 1u : 0u;
+    for (int d = kWave / 2; d > 0; d >>= 1) c += __shfl_down(c, d, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int k = 0; k < kBigBlock / kWave; ++k) t += part[k];
+        hist[pu] = t;
+    }
+}
+
 // Weighted: the weight from node u towards nodes at higher positions, stored
 // at pos[u]; one wavefront per node, lanes stride over the row, fixed-order
 // reduction (deterministic).
@@ -171,6 +217,13 @@ void extract_impl(const ExtractArgs &a, ExtractScratch &sc, hipStream_t s) {
     if constexpr (kWeighted) {
         hipLaunchKernelGGL(k_towards_higher_w, dim3(grid_for((int64_t)n * kWave, 256)), dim3(256),
                            0, s, n, a.row_ptr, a.inc, a.src, a.dst, a.w, sc.pos.p, hist);
+    } else if (a.adj) {
+        hipLaunchKernelGGL(k_towards_higher_small, dim3(grid_for((int64_t)n * kRowLanes, 256)),
+                           dim3(256), 0, s, n, a.row_ptr, a.adj, sc.pos.p,
+                           (unsigned long long *)hist);
+        if (a.nbig > 0)
+            hipLaunchKernelGGL(k_towards_higher_big, dim3((unsigned)a.nbig), dim3(kBigBlock), 0, s,
+                               a.big, a.row_ptr, a.adj, sc.pos.p, (unsigned long long *)hist);
     } else {
         hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n, 256)), dim3(256), 0, s, (int64_t)n, hist);
         if (a.m > 0)

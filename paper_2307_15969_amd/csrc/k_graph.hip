@@ -60,6 +60,27 @@ void launch_validate(int32_t n, int64_t m, const int32_t *src, const int32_t *ds
     LOWD_HIP(hipStreamSynchronize(s));   // `init` must outlive the copy
 }
 
+namespace {
+// adj[j] = the other end of incidence entry j (entry = edge << 1 | side, side
+// 1 when the row's node is the edge's dst)
+__global__ void k_adjacency(int64_t len, const uint32_t *inc, const int32_t *src,
+                            const int32_t *dst, int32_t *adj) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < len;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t ent = inc[j];
+        adj[j] = (ent & 1u) ? src[ent >> 1] : dst[ent >> 1];
+    }
+}
+}  // namespace
+
+void build_adjacency(int64_t m, const Csr &csr, const int32_t *src, const int32_t *dst,
+                     int32_t *adj, hipStream_t s) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_adjacency, dim3(grid_for(2 * m, 256)), dim3(256), 0, s, 2 * m,
+                       csr.inc.p, src, dst, adj);
+    LOWD_HIP(hipGetLastError());
+}
+
 void build_incidence(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, Csr &csr,
                      hipStream_t s) {
     int64_t len = 2 * m;

@@ -164,6 +164,9 @@ struct Csr {
 };
 void build_incidence(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, Csr &csr,
                      hipStream_t s);
+// adj[j] = the other end of the edge of incidence entry j ([2m])
+void build_adjacency(int64_t m, const Csr &csr, const int32_t *src, const int32_t *dst,
+                     int32_t *adj, hipStream_t s);
 inline unsigned grid_for(int64_t work, int block, int64_t cap = 65536) {
     int64_t g = (work + block - 1) / block;
     if (g < 1) g = 1;
