@@ -211,6 +211,24 @@ lowd_status lowd_extract_densest(lowd_solver *s, uint8_t *in_set, int64_t *num_u
                                  void *stream);
 
 /*
+ * lowd_check_kept, lowd_extract_densest_kept -- lowd_check and
+ * lowd_extract_densest on the loads the solver keeps, with the same
+ * arguments: for LOWD_STATE_F32K each node's compensated FP32 pair rounded
+ * to FP64, without the recomputation from the fractions; for
+ * LOWD_STATE_F64 identical to the plain calls.  The kept FP32K loads follow
+ * the fractions' sums up to the rounding of the FP32 fractions (Section
+ * III-B's bound needs the loads of the fractions as stored), so D here
+ * estimates the dual objective: it steers the iteration between checks, and
+ * a certificate takes D from lowd_check.  The extracted set is a set of the
+ * graph, its density exact as for lowd_extract_densest.
+ */
+lowd_status lowd_check_kept(lowd_solver *s, double *D, double *sum_loads, double *sum_sq_loads,
+                            void *stream);
+lowd_status lowd_extract_densest_kept(lowd_solver *s, uint8_t *in_set, int64_t *num_unit,
+                                      double *num_w, int64_t *den, double *D, double *gap,
+                                      void *stream);
+
+/*
  * lowd_ldd_readout -- the locally-dense decomposition (Problem 2, Property
  * 2) read from the current loads: with the nodes ranked by descending load
  * (the reverse of lowd_extract_densest's order) and f(k) the weight of the

@@ -53,6 +53,8 @@ def lib() -> C.CDLL:
         L.lowd_check.argtypes = [vp, P(C.c_double), P(C.c_double), P(C.c_double), vp]
         L.lowd_extract_densest.argtypes = [vp, vp, P(i64), P(C.c_double), P(i64),
                                            P(C.c_double), P(C.c_double), vp]
+        L.lowd_check_kept.argtypes = L.lowd_check.argtypes
+        L.lowd_extract_densest_kept.argtypes = L.lowd_extract_densest.argtypes
         L.lowd_read_state.argtypes = [vp, vp, vp, vp]
         L.lowd_ldd_readout.argtypes = [vp, vp, vp, vp, P(i64), vp]
         L.lowd_convergence_trace.argtypes = [vp, i32, i32, vp, P(i64), vp]
@@ -239,18 +241,24 @@ class Solver:
     def iterate(self, sweeps: int = 1, stream=None):
         _check(lib().lowd_iterate(self._h, int(sweeps), _stream(stream)))
 
-    def check(self, stream=None):
+    def check(self, stream=None, kept: bool = False):
+        """(D, sum of loads, sum of squared loads).  kept: from the loads as
+        the solver keeps them (FP32K: an estimate of D, no recomputation from
+        the fractions); otherwise exact."""
         D, s, s2 = C.c_double(), C.c_double(), C.c_double()
-        _check(lib().lowd_check(self._h, C.byref(D), C.byref(s), C.byref(s2), _stream(stream)))
+        f = lib().lowd_check_kept if kept else lib().lowd_check
+        _check(f(self._h, C.byref(D), C.byref(s), C.byref(s2), _stream(stream)))
         return D.value, s.value, s2.value
 
-    def extract(self, stream=None) -> dict:
+    def extract(self, stream=None, kept: bool = False) -> dict:
+        """The densest prefix of the descending-load order; kept as for
+        check (the set's density is exact either way)."""
         torch = _torch()
         in_set = torch.empty(self.n, dtype=torch.uint8, device=self.device)
         nu, nw, den, D, gap = C.c_int64(), C.c_double(), C.c_int64(), C.c_double(), C.c_double()
-        _check(lib().lowd_extract_densest(self._h, _ptr(in_set), C.byref(nu), C.byref(nw),
-                                          C.byref(den), C.byref(D), C.byref(gap),
-                                          _stream(stream)))
+        f = lib().lowd_extract_densest_kept if kept else lib().lowd_extract_densest
+        _check(f(self._h, _ptr(in_set), C.byref(nu), C.byref(nw), C.byref(den), C.byref(D),
+                 C.byref(gap), _stream(stream)))
         return dict(in_set=in_set, num=int(nu.value), num_w=float(nw.value), den=int(den.value),
                     D=float(D.value), gap=float(gap.value))
 
@@ -319,28 +327,41 @@ def _density(ex: dict) -> float:
     return (ex["num_w"] if ex.get("weighted") else ex["num"]) / ex["den"] if ex["den"] else 0.0
 
 
+def _gap(D: float, rho: float) -> float:
+    return (D - rho) / rho if rho > 0 else (0.0 if D <= 0 else math.inf)
+
+
 def certify(sv: "Solver", best, tol: float, stream=None):
     """One convergence check.  D, the largest load, bounds the optimum from
     above at every sweep and any extracted set bounds it from below, so the
     best set extracted so far is certified once (D - rho_best) / rho_best is
     at most tol.  D alone is cheap; the extraction (a sort of all nodes) runs
-    only when D does not certify the best set already.  Returns (best, gap):
-    best is the densest extraction so far (its "D" and "gap" updated to this
-    check)."""
+    only when D does not certify the best set already.  Both read the loads
+    as kept; for FP32K these only estimate the loads of the stored fractions,
+    so a gap within tol is confirmed with the exact D (recomputed from the
+    fractions) before it is returned, and a gap above tol only steers the
+    next check.  Returns (best, gap): best is the densest extraction so far
+    (its "D" and "gap" updated to this check)."""
+    exact = sv.state == "f64"   # the kept loads are the loads
+
+    def confirm(best, D, gap):
+        if gap <= tol and not exact:
+            D = sv.check(stream)[0]
+            gap = _gap(D, _density(best))
+        return dict(best, D=D, gap=gap), gap
+
     if best is not None:
-        D = sv.check(stream)[0]
-        rho = _density(best)
-        gap = (D - rho) / rho if rho > 0 else (0.0 if D <= 0 else math.inf)
+        D = sv.check(stream, kept=True)[0]
+        gap = _gap(D, _density(best))
         if gap <= tol:
-            return dict(best, D=D, gap=gap), gap
-    ex = sv.extract(stream)
+            best, gap = confirm(best, D, gap)
+            if gap <= tol:
+                return best, gap
+    ex = sv.extract(stream, kept=True)
     ex["weighted"] = sv.weighted
     if best is None or _density(ex) >= _density(best):
         best = ex
-    rho = _density(best)
-    D = ex["D"]
-    gap = (D - rho) / rho if rho > 0 else (0.0 if D <= 0 else math.inf)
-    return dict(best, D=D, gap=gap), gap
+    return confirm(best, ex["D"], _gap(ex["D"], _density(best)))
 
 
 def solve(n: int, src, dst, w=None, state: str = "f64", star_max: int = 16, tol: float = 1e-6,
@@ -365,6 +386,9 @@ def solve(n: int, src, dst, w=None, state: str = "f64", star_max: int = 16, tol:
         hist.append((sweeps, gap))
     if ex is None:   # max_sweeps == 0
         ex, gap = certify(sv, None, tol, stream)
+    if gap > tol and state != "f64":   # stopped at max_sweeps: report the exact D
+        D = sv.check(stream)[0]
+        ex = dict(ex, D=D, gap=_gap(D, _density(ex)))
     ex["sweeps"] = sweeps
     ex["solver"] = sv
     return ex

@@ -119,8 +119,8 @@ struct lowd_solver {
     ExtractScratch ex;
     LddScratch ldd;
     DBuf<uint8_t> ldd_in_set;
-    // unit weights: the other end of each incidence entry, and the nodes of
-    // degree >= kBigDegree, for the extraction's atomic-free count
+    // the other end of each incidence entry, and the nodes of degree >=
+    // kBigRow, for the per-node kernels (initial loads, recompute, extraction)
     DBuf<int32_t> adj, big;
     int32_t nbig = 0;
     hipGraph_t graph = nullptr;
@@ -139,7 +139,8 @@ static void reset_state(lowd_solver *sv, hipStream_t s) {
         sv->fn.init_slots(nslots, sv->slot_edge.p, sv->weighted ? sv->e_w.p : nullptr,
                           sv->slot_x.p, sv->weighted ? sv->slot_w.p : nullptr, s);
     sv->fn.init_loads(sv->n, sv->csr.row_ptr.p, sv->csr.inc.p, sv->weighted ? sv->e_w.p : nullptr,
-                      sv->home.p, sv->sch.entries, sv->sch.center_base, sv->E.p, s);
+                      sv->home.p, sv->big.p, sv->nbig, sv->sch.entries, sv->sch.center_base,
+                      sv->E.p, s);
     LOWD_HIP(hipGetLastError());
 }
 
@@ -200,7 +201,7 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
                     hipMemcpyAsync(sv->e_w.p, w, (size_t)m * 4, hipMemcpyDeviceToDevice, s));
         }
         build_incidence(n, m, sv->e_src.p, sv->e_dst.p, sv->csr, s);
-        if (!sv->weighted) {
+        {
             sv->adj.alloc((size_t)(2 * m));
             build_adjacency(m, sv->csr, sv->e_src.p, sv->e_dst.p, sv->adj.p, s);
             std::vector<int32_t> deg((size_t)n, 0), big;
@@ -209,7 +210,7 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
                 ++deg[(size_t)hd[(size_t)e]];
             }
             for (int32_t u = 0; u < n; ++u)
-                if (deg[(size_t)u] >= kBigDegree) big.push_back(u);
+                if (deg[(size_t)u] >= kBigRow) big.push_back(u);
             upload(sv->big, big, s);
             sv->nbig = (int32_t)big.size();
         }
@@ -303,9 +304,16 @@ lowd_status lowd_iterate(lowd_solver *sv, int32_t sweeps, void *stream) {
     });
 }
 
-static void loads_f64(lowd_solver *sv, hipStream_t s) {
+// FP64 loads into L64: for LOWD_STATE_F32K recomputed from the fractions
+// (exact), or the kept compensated pairs rounded to FP64 (kept)
+static void loads_f64(lowd_solver *sv, hipStream_t s, bool kept = false) {
+    if (kept) {
+        sv->fn.read_loads(sv->n, sv->home.p, sv->E.p, sv->L64.p, s);
+        return;
+    }
     sv->fn.loads_f64(sv->n, sv->csr.row_ptr.p, sv->csr.inc.p, sv->edge_slot.p, sv->slot_x.p,
-                     sv->weighted ? sv->e_w.p : nullptr, sv->home.p, sv->E.p, sv->L64.p, s);
+                     sv->weighted ? sv->e_w.p : nullptr, sv->home.p, sv->big.p, sv->nbig, sv->E.p,
+                     sv->L64.p, s);
 }
 
 static void stats(lowd_solver *sv, double out[3], hipStream_t s) {
@@ -316,59 +324,78 @@ static void stats(lowd_solver *sv, double out[3], hipStream_t s) {
     LOWD_HIP(hipStreamSynchronize(s));
 }
 
+static void check_impl(lowd_solver *sv, bool kept, double *D, double *sum_loads,
+                       double *sum_sq_loads, hipStream_t s) {
+    if (!sv) fail(LOWD_E_ARG, "solver is NULL");
+    loads_f64(sv, s, kept);
+    double o[3];
+    stats(sv, o, s);
+    if (D) *D = o[0];
+    if (sum_loads) *sum_loads = o[1];
+    if (sum_sq_loads) *sum_sq_loads = o[2];
+}
+
+static void extract_api(lowd_solver *sv, bool kept, uint8_t *in_set, int64_t *num_unit,
+                        double *num_w, int64_t *den, double *D, double *gap, hipStream_t s) {
+    if (!sv) fail(LOWD_E_ARG, "solver is NULL");
+    if (!in_set) fail(LOWD_E_ARG, "in_set is NULL");
+    loads_f64(sv, s, kept);
+    ExtractArgs a;
+    a.n = sv->n;
+    a.m = sv->m;
+    a.weighted = sv->weighted;
+    a.L64 = sv->L64.p;
+    a.row_ptr = sv->csr.row_ptr.p;
+    a.inc = sv->csr.inc.p;
+    a.src = sv->e_src.p;
+    a.dst = sv->e_dst.p;
+    a.w = sv->weighted ? sv->e_w.p : nullptr;
+    if (sv->m > 0) {
+        a.adj = sv->adj.p;
+        a.big = sv->big.p;
+        a.nbig = sv->nbig;
+    }
+    a.in_set = in_set;
+    launch_extract(a, sv->ex, s);
+    int64_t best[2];
+    LOWD_HIP(hipMemcpyAsync(best, sv->ex.best.p, sizeof(best), hipMemcpyDeviceToHost, s));
+    double o[3];
+    stats(sv, o, s);   // synchronises
+    int64_t dn = (int64_t)sv->n - best[0];
+    double wnum;
+    if (sv->weighted) memcpy(&wnum, &best[1], sizeof(double));
+    else wnum = (double)best[1];
+    if (num_unit) *num_unit = sv->weighted ? 0 : best[1];
+    if (num_w) *num_w = wnum;
+    if (den) *den = dn;
+    if (D) *D = o[0];
+    double rho = wnum / (double)dn;
+    if (gap) *gap = rho > 0.0 ? (o[0] - rho) / rho : (o[0] > 0.0 ? 1.0e300 : 0.0);
+}
+
 lowd_status lowd_check(lowd_solver *sv, double *D, double *sum_loads, double *sum_sq_loads,
                        void *stream) {
-    return guarded([&] {
-        if (!sv) fail(LOWD_E_ARG, "solver is NULL");
-        hipStream_t s = (hipStream_t)stream;
-        loads_f64(sv, s);
-        double o[3];
-        stats(sv, o, s);
-        if (D) *D = o[0];
-        if (sum_loads) *sum_loads = o[1];
-        if (sum_sq_loads) *sum_sq_loads = o[2];
-    });
+    return guarded([&] { check_impl(sv, false, D, sum_loads, sum_sq_loads, (hipStream_t)stream); });
+}
+
+lowd_status lowd_check_kept(lowd_solver *sv, double *D, double *sum_loads, double *sum_sq_loads,
+                            void *stream) {
+    return guarded([&] { check_impl(sv, true, D, sum_loads, sum_sq_loads, (hipStream_t)stream); });
 }
 
 lowd_status lowd_extract_densest(lowd_solver *sv, uint8_t *in_set, int64_t *num_unit,
                                  double *num_w, int64_t *den, double *D, double *gap,
                                  void *stream) {
     return guarded([&] {
-        if (!sv) fail(LOWD_E_ARG, "solver is NULL");
-        if (!in_set) fail(LOWD_E_ARG, "in_set is NULL");
-        hipStream_t s = (hipStream_t)stream;
-        loads_f64(sv, s);
-        ExtractArgs a;
-        a.n = sv->n;
-        a.m = sv->m;
-        a.weighted = sv->weighted;
-        a.L64 = sv->L64.p;
-        a.row_ptr = sv->csr.row_ptr.p;
-        a.inc = sv->csr.inc.p;
-        a.src = sv->e_src.p;
-        a.dst = sv->e_dst.p;
-        a.w = sv->weighted ? sv->e_w.p : nullptr;
-        if (!sv->weighted && sv->m > 0) {
-            a.adj = sv->adj.p;
-            a.big = sv->big.p;
-            a.nbig = sv->nbig;
-        }
-        a.in_set = in_set;
-        launch_extract(a, sv->ex, s);
-        int64_t best[2];
-        LOWD_HIP(hipMemcpyAsync(best, sv->ex.best.p, sizeof(best), hipMemcpyDeviceToHost, s));
-        double o[3];
-        stats(sv, o, s);   // synchronises
-        int64_t dn = (int64_t)sv->n - best[0];
-        double wnum;
-        if (sv->weighted) memcpy(&wnum, &best[1], sizeof(double));
-        else wnum = (double)best[1];
-        if (num_unit) *num_unit = sv->weighted ? 0 : best[1];
-        if (num_w) *num_w = wnum;
-        if (den) *den = dn;
-        if (D) *D = o[0];
-        double rho = wnum / (double)dn;
-        if (gap) *gap = rho > 0.0 ? (o[0] - rho) / rho : (o[0] > 0.0 ? 1.0e300 : 0.0);
+        extract_api(sv, false, in_set, num_unit, num_w, den, D, gap, (hipStream_t)stream);
+    });
+}
+
+lowd_status lowd_extract_densest_kept(lowd_solver *sv, uint8_t *in_set, int64_t *num_unit,
+                                      double *num_w, int64_t *den, double *D, double *gap,
+                                      void *stream) {
+    return guarded([&] {
+        extract_api(sv, true, in_set, num_unit, num_w, den, D, gap, (hipStream_t)stream);
     });
 }
 
@@ -446,7 +473,7 @@ lowd_status lowd_ldd_readout(lowd_solver *sv, int32_t *level, int64_t *k_end, do
         a.src = sv->e_src.p;
         a.dst = sv->e_dst.p;
         a.w = sv->weighted ? sv->e_w.p : nullptr;
-        if (!sv->weighted && sv->m > 0) {
+        if (sv->m > 0) {
             a.adj = sv->adj.p;
             a.big = sv->big.p;
             a.nbig = sv->nbig;

@@ -18,17 +18,14 @@ struct ExtractArgs {
     const int32_t *src = nullptr;     // [m] edge list
     const int32_t *dst = nullptr;
     const float *w = nullptr;         // [m] or nullptr
-    // optional, unweighted graphs: the other end of each incidence entry and
-    // the nodes of degree >= kBigDegree (counted a workgroup each)
+    // optional: the other end of each incidence entry and the nodes of
+    // degree >= kBigRow (counted a workgroup each)
     const int32_t *adj = nullptr;     // [2m]
     const int32_t *big = nullptr;     // [nbig]
     int32_t nbig = 0;
     uint8_t *in_set = nullptr;        // [n] out
 };
 
-// Nodes of at least this degree are counted by a workgroup each in the
-// extraction; the others by groups of 8 lanes.
-constexpr int32_t kBigDegree = 256;
 
 struct ExtractScratch {
     int64_t cap = -1;

@@ -54,7 +54,7 @@ __global__ void k_edge_min_pos(int64_t m, const int32_t *src, const int32_t *dst
 
 // Unweighted, without atomics: node u's bin is the number of its neighbours
 // at higher positions (positions are distinct, so every edge is counted once,
-// at its lower end).  Groups of 8 lanes per node of degree below kBigDegree;
+// at its lower end).  Groups of 8 lanes per node of degree below kBigRow;
 // the others are left to k_towards_higher_big.  Writes every such bin.
 constexpr int kRowLanes = 8;
 __global__ void __launch_bounds__(256) k_towards_higher_small(int32_t n, const int64_t *row_ptr,
@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(256) k_towards_higher_small(int32_t n, const i
     for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / kRowLanes) + threadIdx.x / kRowLanes;
          u < n; u += groups) {
         const int64_t b = row_ptr[u], e = row_ptr[u + 1];
-        if (e - b >= kBigDegree) continue;   // the whole group skips it
+        if (e - b >= kBigRow) continue;   // the whole group skips it
         const int32_t pu = pos[u];
         uint32_t c = 0;
         for (int64_t j = b + sub; j < e; j += kRowLanes) c += pos[adj[j]] > pu ? 1u : 0u;
@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(256) k_towards_higher_small(int32_t n, const i
     }
 }
 
-// One workgroup per node of degree >= kBigDegree (the list big[]).
+// One workgroup per node of degree >= kBigRow (the list big[]).
 constexpr int kBigBlock = 256;
 __global__ void __launch_bounds__(kBigBlock) k_towards_higher_big(const int32_t *big,
                                                                   const int64_t *row_ptr,
@@ -99,26 +99,44 @@ __global__ void __launch_bounds__(kBigBlock) k_towards_higher_big(const int32_t 
 }
 
 // Weighted: the weight from node u towards nodes at higher positions, stored
-// at pos[u]; one wavefront per node, lanes stride over the row, fixed-order
-// reduction (deterministic).
+// at pos[u].  Groups of 8 lanes per node of degree below kBigRow (the others:
+// k_towards_higher_w_big), each a fixed-order FP64 reduction (deterministic).
 __global__ void __launch_bounds__(256) k_towards_higher_w(int32_t n, const int64_t *row_ptr,
-                                                          const uint32_t *inc, const int32_t *src,
-                                                          const int32_t *dst, const float *w,
-                                                          const int32_t *pos, double *hist) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
-    for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; u < n;
-         u += waves) {
+                                                          const uint32_t *inc, const int32_t *adj,
+                                                          const float *w, const int32_t *pos,
+                                                          double *hist) {
+    const int sub = threadIdx.x & (kRowLanes - 1);
+    const int64_t groups = (int64_t)gridDim.x * (blockDim.x / kRowLanes);
+    for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / kRowLanes) + threadIdx.x / kRowLanes;
+         u < n; u += groups) {
+        const int64_t b = row_ptr[u], e = row_ptr[u + 1];
+        if (e - b >= kBigRow) continue;
         const int32_t pu = pos[u];
         double acc = 0.0;
-        for (int64_t j = row_ptr[u] + lane; j < row_ptr[u + 1]; j += kWave) {
-            uint32_t ent = inc[j];
-            int64_t e = ent >> 1;
-            int32_t other = (ent & 1) ? src[e] : dst[e];
-            if (pos[other] > pu) acc = acc + (double)w[e];
-        }
-        for (int d = kWave / 2; d > 0; d >>= 1) acc = acc + __shfl_down(acc, d, kWave);
-        if (lane == 0) hist[pu] = acc;
+        for (int64_t j = b + sub; j < e; j += kRowLanes)
+            if (pos[adj[j]] > pu) acc = acc + (double)w[inc[j] >> 1];
+        for (int d = kRowLanes / 2; d > 0; d >>= 1) acc = acc + __shfl_down(acc, d, kRowLanes);
+        if (sub == 0) hist[pu] = acc;
+    }
+}
+
+// the same for one node of degree >= kBigRow per workgroup
+__global__ void __launch_bounds__(kBigBlock) k_towards_higher_w_big(
+    const int32_t *big, const int64_t *row_ptr, const uint32_t *inc, const int32_t *adj,
+    const float *w, const int32_t *pos, double *hist) {
+    __shared__ double part[kBigBlock / kWave];
+    const int32_t u = big[blockIdx.x];
+    const int32_t pu = pos[u];
+    double acc = 0.0;
+    for (int64_t j = row_ptr[u] + threadIdx.x; j < row_ptr[u + 1]; j += kBigBlock)
+        if (pos[adj[j]] > pu) acc = acc + (double)w[inc[j] >> 1];
+    for (int d = kWave / 2; d > 0; d >>= 1) acc = acc + __shfl_down(acc, d, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < kBigBlock / kWave; ++k) t = t + part[k];
+        hist[pu] = t;
     }
 }
 
@@ -215,8 +233,17 @@ void extract_impl(const ExtractArgs &a, ExtractScratch &sc, hipStream_t s) {
     T *rev = (T *)sc.rev.p;
     T *W = (T *)sc.W.p;
     if constexpr (kWeighted) {
-        hipLaunchKernelGGL(k_towards_higher_w, dim3(grid_for((int64_t)n * kWave, 256)), dim3(256),
-                           0, s, n, a.row_ptr, a.inc, a.src, a.dst, a.w, sc.pos.p, hist);
+        if (a.m == 0) {   // no edges: every bin is zero (+0.0)
+            hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n, 256)), dim3(256), 0, s, (int64_t)n,
+                               (int64_t *)hist);
+        } else {
+            if (!a.adj) fail(LOWD_E_ARG, "weighted extraction needs the adjacency");
+            hipLaunchKernelGGL(k_towards_higher_w, dim3(grid_for((int64_t)n * kRowLanes, 256)),
+                               dim3(256), 0, s, n, a.row_ptr, a.inc, a.adj, a.w, sc.pos.p, hist);
+        }
+        if (a.m > 0 && a.nbig > 0)
+            hipLaunchKernelGGL(k_towards_higher_w_big, dim3((unsigned)a.nbig), dim3(kBigBlock), 0,
+                               s, a.big, a.row_ptr, a.inc, a.adj, a.w, sc.pos.p, hist);
     } else if (a.adj) {
         hipLaunchKernelGGL(k_towards_higher_small, dim3(grid_for((int64_t)n * kRowLanes, 256)),
                            dim3(256), 0, s, n, a.row_ptr, a.adj, sc.pos.p,

@@ -46,7 +46,8 @@ __global__ void k_fill_entries(int64_t entries, int64_t center_base, typename St
 }
 
 // l_u = sum of w_e / 2 over the edges at u, in ascending edge index, placed
-// at u's first station
+// at u's first station.  Weighted rows of kBigRow entries or more are left to
+// k_init_loads_big.
 template <class St, bool kWeighted>
 __global__ void k_init_loads(int32_t n, const int64_t *row_ptr, const uint32_t *inc,
                              const float *w, const uint32_t *home, typename St::L *E) {
@@ -54,6 +55,7 @@ __global__ void k_init_loads(int32_t n, const int64_t *row_ptr, const uint32_t *
          u += (int64_t)gridDim.x * blockDim.x) {
         double acc = 0.0;
         if (kWeighted) {
+            if (row_ptr[u + 1] - row_ptr[u] >= kBigRow) continue;
             for (int64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j)
                 acc = acc + (double)w[inc[j] >> 1] / 2.0;
         } else {
@@ -62,6 +64,35 @@ __global__ void k_init_loads(int32_t n, const int64_t *row_ptr, const uint32_t *
         }
         E[home[u]] = St::from_f64(acc);
     }
+}
+
+// The same ascending-order sum for one long weighted row per wave: the wave
+// loads 64 consecutive halves at a time and every lane adds them in order
+// (lanes past the row's end contribute +0, which leaves a sum of
+// non-negative terms unchanged), so the bits equal the sequential sum.
+template <class St>
+__global__ void __launch_bounds__(kWave) k_init_loads_big(const int32_t *big,
+                                                          const int64_t *row_ptr,
+                                                          const uint32_t *inc, const float *w,
+                                                          const uint32_t *home,
+                                                          typename St::L *E) {
+    const int32_t u = big[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int64_t end = row_ptr[u + 1];
+    double acc = 0.0;
+    for (int64_t j0 = row_ptr[u]; j0 < end; j0 += kWave) {
+        const int64_t j = j0 + lane;
+        const double h = j < end ? (double)w[inc[j] >> 1] / 2.0 : 0.0;
+        const uint64_t hb = __builtin_bit_cast(uint64_t, h);
+        const uint32_t lo = (uint32_t)hb, hi = (uint32_t)(hb >> 32);
+#pragma unroll
+        for (int k = 0; k < kWave; ++k) {
+            const uint64_t v = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(hi, k) << 32) |
+                               (uint32_t)__builtin_amdgcn_readlane(lo, k);
+            acc = acc + __builtin_bit_cast(double, v);
+        }
+    }
+    if (lane == 0) E[home[u]] = St::from_f64(acc);
 }
 
 // ------------------------------------------------------------ one tile ---
@@ -699,27 +730,55 @@ __global__ void k_zero_u32(unsigned *p) { *p = 0u; }
 // ------------------------------------------------------------ statistics --
 constexpr int kRedBlock = 256;
 
-// FP64 loads recomputed from the fractions (f_e(src) = x, f_e(dst) = w - x);
-// one wavefront per node, lanes stride over the row, fixed-order reduction
+// FP64 loads recomputed from the fractions (f_e(src) = x, f_e(dst) = w - x):
+// a group of 8 lanes per node of degree below kBigRow, lanes striding over
+// the row, fixed-order reduction; longer rows: k_recompute_big.
+constexpr int kRowLanes = 8;
+template <class St, bool kWeighted>
+__device__ __forceinline__ double recompute_term(uint32_t ent, const int64_t *edge_slot,
+                                                 const typename St::X *slot_x, const float *w) {
+    const int64_t e = ent >> 1;
+    const double x = (double)slot_x[edge_slot[e]];
+    const double we = kWeighted ? (double)w[e] : 1.0;
+    return (ent & 1) ? we - x : x;
+}
+
 template <class St, bool kWeighted>
 __global__ void __launch_bounds__(256) k_recompute(int32_t n, const int64_t *row_ptr,
                                                    const uint32_t *inc, const int64_t *edge_slot,
                                                    const typename St::X *slot_x, const float *w,
                                                    double *L64) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
-    for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; u < n;
-         u += waves) {
+    const int sub = threadIdx.x & (kRowLanes - 1);
+    const int64_t groups = (int64_t)gridDim.x * (blockDim.x / kRowLanes);
+    for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / kRowLanes) + threadIdx.x / kRowLanes;
+         u < n; u += groups) {
+        const int64_t b = row_ptr[u], e = row_ptr[u + 1];
+        if (e - b >= kBigRow) continue;
         double acc = 0.0;
-        for (int64_t j = row_ptr[u] + lane; j < row_ptr[u + 1]; j += kWave) {
-            uint32_t ent = inc[j];
-            int64_t e = ent >> 1;
-            double x = (double)slot_x[edge_slot[e]];
-            double we = kWeighted ? (double)w[e] : 1.0;
-            acc = acc + ((ent & 1) ? we - x : x);
-        }
-        for (int d = kWave / 2; d > 0; d >>= 1) acc = acc + __shfl_down(acc, d, kWave);
-        if (lane == 0) L64[u] = acc;
+        for (int64_t j = b + sub; j < e; j += kRowLanes)
+            acc = acc + recompute_term<St, kWeighted>(inc[j], edge_slot, slot_x, w);
+        for (int d = kRowLanes / 2; d > 0; d >>= 1) acc = acc + __shfl_down(acc, d, kRowLanes);
+        if (sub == 0) L64[u] = acc;
+    }
+}
+
+constexpr int kBigRowBlock = 256;
+template <class St, bool kWeighted>
+__global__ void __launch_bounds__(kBigRowBlock) k_recompute_big(
+    const int32_t *big, const int64_t *row_ptr, const uint32_t *inc, const int64_t *edge_slot,
+    const typename St::X *slot_x, const float *w, double *L64) {
+    __shared__ double part[kBigRowBlock / kWave];
+    const int32_t u = big[blockIdx.x];
+    double acc = 0.0;
+    for (int64_t j = row_ptr[u] + threadIdx.x; j < row_ptr[u + 1]; j += kBigRowBlock)
+        acc = acc + recompute_term<St, kWeighted>(inc[j], edge_slot, slot_x, w);
+    for (int d = kWave / 2; d > 0; d >>= 1) acc = acc + __shfl_down(acc, d, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < kBigRowBlock / kWave; ++k) t = t + part[k];
+        L64[u] = t;
     }
 }
 
@@ -813,12 +872,15 @@ static void sweep_launchers(SweepLaunch &fn) {
                            nslots, slot_edge, w, (typename St::X *)slot_x, slot_w);
     };
     fn.init_loads = [](int32_t n, const int64_t *row_ptr, const uint32_t *inc, const float *w,
-                       const uint32_t *home, int64_t entries, int64_t center_base, void *E,
-                       hipStream_t s) {
+                       const uint32_t *home, const int32_t *big, int32_t nbig, int64_t entries,
+                       int64_t center_base, void *E, hipStream_t s) {
         hipLaunchKernelGGL((k_fill_entries<St>), dim3(grid_for(entries, 256)), dim3(256), 0, s,
                            entries, center_base, (typename St::L *)E);
         hipLaunchKernelGGL((k_init_loads<St, kW>), dim3(grid_for((int64_t)n, 256)), dim3(256), 0, s,
                            n, row_ptr, inc, w, home, (typename St::L *)E);
+        if (kW && nbig > 0)
+            hipLaunchKernelGGL((k_init_loads_big<St>), dim3((unsigned)nbig), dim3(kWave), 0, s, big,
+                               row_ptr, inc, w, home, (typename St::L *)E);
     };
     fn.phase = [](const PhaseDesc &d, int64_t center_base, const uint32_t *center_next,
                   const uint32_t *slot_next, void *slot_x, const float *slot_w, void *E,
@@ -859,12 +921,17 @@ static void sweep_launchers(SweepLaunch &fn) {
     };
     fn.loads_f64 = [](int32_t n, const int64_t *row_ptr, const uint32_t *inc,
                       const int64_t *edge_slot, const void *slot_x, const float *w,
-                      const uint32_t *home, const void *E, double *L64, hipStream_t s) {
-        if (St::kRecompute)
-            hipLaunchKernelGGL((k_recompute<St, kW>), dim3(grid_for((int64_t)n * kWave, 256)),
+                      const uint32_t *home, const int32_t *big, int32_t nbig, const void *E,
+                      double *L64, hipStream_t s) {
+        if (St::kRecompute) {
+            hipLaunchKernelGGL((k_recompute<St, kW>), dim3(grid_for((int64_t)n * kRowLanes, 256)),
                                dim3(256), 0, s, n, row_ptr, inc, edge_slot,
                                (const typename St::X *)slot_x, w, L64);
-        else
+            if (nbig > 0)
+                hipLaunchKernelGGL((k_recompute_big<St, kW>), dim3((unsigned)nbig),
+                                   dim3(kBigRowBlock), 0, s, big, row_ptr, inc, edge_slot,
+                                   (const typename St::X *)slot_x, w, L64);
+        } else
             hipLaunchKernelGGL((k_loads_to_f64<St>), dim3(grid_for(n, 256)), dim3(256), 0, s, n,
                                home, (const typename St::L *)E, L64);
     };

@@ -158,6 +158,11 @@ int64_t find_duplicate_pair(int32_t n, int64_t m, const int32_t *src, const int3
                             hipStream_t s);
 // Incidence CSR, rows in ascending edge index: entry j = 2*e + side
 // (side 0: the row node is src[e]; side 1: dst[e]).  row_ptr has n+1 entries.
+// Rows (incidence rows, i.e. node degrees) of at least this length are
+// handled by a wave or a workgroup each in the per-node kernels; shorter rows
+// by one thread or a group of 8 lanes.
+constexpr int32_t kBigRow = 256;
+
 struct Csr {
     DBuf<int64_t> row_ptr;   // [n+1]
     DBuf<uint32_t> inc;      // [2m]

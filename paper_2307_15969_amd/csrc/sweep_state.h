@@ -152,9 +152,10 @@ struct StateF32K {
 struct SweepLaunch {
     void (*init_slots)(int64_t nslots, const int64_t *slot_edge, const float *w, void *slot_x,
                        float *slot_w, hipStream_t s);
+    // big[nbig]: the nodes of degree >= kBigRow (a wave or workgroup each)
     void (*init_loads)(int32_t n, const int64_t *row_ptr, const uint32_t *inc, const float *w,
-                       const uint32_t *home, int64_t entries, int64_t center_base, void *E,
-                       hipStream_t s);
+                       const uint32_t *home, const int32_t *big, int32_t nbig, int64_t entries,
+                       int64_t center_base, void *E, hipStream_t s);
     void (*phase)(const PhaseDesc &d, int64_t center_base, const uint32_t *center_next,
                   const uint32_t *slot_next, void *slot_x, const float *slot_w, void *E,
                   hipStream_t s);
@@ -168,7 +169,8 @@ struct SweepLaunch {
     void (*set_mid_lds)(size_t bytes);
     void (*loads_f64)(int32_t n, const int64_t *row_ptr, const uint32_t *inc,
                       const int64_t *edge_slot, const void *slot_x, const float *w,
-                      const uint32_t *home, const void *E, double *L64, hipStream_t s);
+                      const uint32_t *home, const int32_t *big, int32_t nbig, const void *E,
+                      double *L64, hipStream_t s);
     void (*read_x)(int64_t m, const int64_t *edge_slot, const void *slot_x, double *x,
                    hipStream_t s);
     void (*read_loads)(int32_t n, const uint32_t *home, const void *E, double *out,

@@ -201,6 +201,60 @@ def test_f32_compensated_within_tolerance(name, g):
     assert abs(s - wsum) <= 1e-9 * wsum
 
 
+def _induced(g, in_set):
+    """(W(S), |S|) of a node mask, counted on the CPU in FP64."""
+    keep = in_set.astype(bool)
+    both = keep[g.src] & keep[g.dst]
+    num = float(np.sum(g.w.astype(np.float64)[both])) if g.w is not None else float(both.sum())
+    return num, int(keep.sum())
+
+
+@pytest.mark.parametrize("state", ["f64", "f32k"])
+@pytest.mark.parametrize("name,g", GRAPHS, ids=[n for n, _ in GRAPHS])
+def test_kept_check_and_extract(name, g, state):
+    """The kept-load variants: for FP64 identical to the exact calls; for
+    FP32K D within the FP32 load bound of the oracle's, and the extracted
+    set's density exact for that set."""
+    T = 25
+    log(f"kept {name} {state}")
+    sv = lowd.Solver(g.n, g.src, g.dst, g.w, state)
+    sv.iterate(T)
+    Dk, sk, s2k = sv.check(kept=True)
+    D, s, s2 = sv.check()
+    ek = sv.extract(kept=True)
+    e = sv.extract()
+    _, Lo, *_ = oracle_run(g, T, 16)
+    Do, _, _ = oracle.stats(Lo)
+    if state == "f64":
+        assert (Dk, sk, s2k) == (D, s, s2)
+        assert np.array_equal(ek["in_set"].cpu().numpy(), e["in_set"].cpu().numpy())
+        assert (ek["num"], ek["num_w"], ek["den"], ek["D"]) == (e["num"], e["num_w"], e["den"], e["D"])
+    else:
+        assert abs(Dk - Do) <= 1e-5 * Do
+        assert abs(ek["D"] - Do) <= 1e-5 * Do
+    num, den = _induced(g, ek["in_set"].cpu().numpy())
+    assert den == ek["den"]
+    got = ek["num"] if g.w is None else ek["num_w"]
+    assert abs(got - num) <= 1e-12 * max(num, 1.0)
+
+
+def test_f32k_solve_certifies_with_the_exact_bound():
+    """solve() screens with the kept FP32K loads but returns a gap taken
+    from the exact D (recomputed from the fractions), and its set is as
+    dense as the FP64 solve's within the tolerance."""
+    g = GRAPHS[2][1]
+    tol = 1e-6
+    r32 = lowd.solve(g.n, g.src, g.dst, g.w, "f32k", tol=tol)
+    r64 = lowd.solve(g.n, g.src, g.dst, g.w, "f64", tol=tol)
+    D = r32["solver"].check()[0]
+    assert r32["D"] == D
+    rho32 = r32["num"] / r32["den"]
+    rho64 = r64["num"] / r64["den"]
+    assert (D - rho32) / rho32 <= tol and r32["gap"] <= tol
+    assert abs(rho32 - rho64) <= 2 * tol * rho64
+    log(f"  f32k {r32['sweeps']} sweeps, f64 {r64['sweeps']} sweeps")
+
+
 def test_unit_graph_f32k_finds_the_same_densest_set():
     g = synth.workload(0)
     sv = lowd.Solver(g.n, g.src, g.dst, None, "f32k")
