@@ -51,14 +51,38 @@ __global__ void __launch_bounds__(256) k_degree_hist(int32_t n, const int32_t *d
         if (h[b]) atomicAdd(&hist[b], (unsigned long long)h[b]);
 }
 
-__global__ void k_bucket_scatter(int32_t n, const int32_t *deg, const int64_t *bin_start,
-                                 unsigned long long *cursor, int32_t *by_deg) {
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
-         u += (int64_t)gridDim.x * blockDim.x) {
-        int32_t d = deg[u];
-        int b = d < kBins - 1 ? d : kBins - 1;
-        int64_t at = bin_start[b] + (int64_t)atomicAdd(&cursor[b], 1ull);
-        by_deg[at] = (int32_t)u;
+// The counting sort's scatter.  Block b places the nodes of its chunk
+// [b * kScatterChunk, (b + 1) * kScatterChunk): it counts them per bin in
+// LDS, reserves each non-empty bin's range with one global atomic, then
+// ranks the nodes inside the range with LDS atomics.  (A global atomic per
+// node serialises on the few bins that hold most nodes.)  The order inside
+// a bin is arbitrary; nothing downstream depends on it.
+constexpr int kScatterBlock = 256;
+constexpr int64_t kScatterChunk = 16 * kScatterBlock;
+__global__ void __launch_bounds__(kScatterBlock)
+k_bucket_scatter(int32_t n, const int32_t *deg, const int64_t *bin_start,
+                 unsigned long long *cursor, int32_t *by_deg) {
+    __shared__ uint32_t cnt[kBins];
+    __shared__ int64_t base[kBins];
+    for (int b = threadIdx.x; b < kBins; b += kScatterBlock) cnt[b] = 0;
+    __syncthreads();
+    const int64_t lo = (int64_t)blockIdx.x * kScatterChunk;
+    const int64_t hi = lo + kScatterChunk < n ? lo + kScatterChunk : (int64_t)n;
+    for (int64_t u = lo + threadIdx.x; u < hi; u += kScatterBlock) {
+        const int32_t d = deg[u];
+        atomicAdd(&cnt[d < kBins - 1 ? d : kBins - 1], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < kBins; b += kScatterBlock) {
+        const uint32_t c = cnt[b];
+        base[b] = c ? bin_start[b] + (int64_t)atomicAdd(&cursor[b], (unsigned long long)c) : 0;
+        cnt[b] = 0;
+    }
+    __syncthreads();
+    for (int64_t u = lo + threadIdx.x; u < hi; u += kScatterBlock) {
+        const int32_t d = deg[u];
+        const int b = d < kBins - 1 ? d : kBins - 1;
+        by_deg[base[b] + (int64_t)atomicAdd(&cnt[b], 1u)] = (int32_t)u;
     }
 }
 
@@ -89,16 +113,30 @@ __global__ void k_stamp(int64_t k, const int32_t *list, int32_t *stamp, int32_t 
 }
 
 // for each removed node: lower alive neighbours' degrees; count each removed
-// edge once (an edge between two nodes removed this round by its smaller end)
-__global__ void k_remove_edges(int64_t k, const int32_t *removed, const int64_t *row_ptr,
-                               const uint32_t *inc, const int32_t *src, const int32_t *dst,
-                               const int32_t *stamp, int32_t round, int32_t *deg,
-                               unsigned long long *gone) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
-         i += (int64_t)gridDim.x * blockDim.x) {
+// edge once (an edge between two nodes removed this round by its smaller
+// end).  G lanes walk one removed node's row (G = 1 for the many short rows
+// of the first round; a wave or the whole workgroup for the later rounds,
+// whose few removed nodes can have long rows).  The counts are summed per
+// wave after the loop, where the whole wave has reconverged, and added with
+// one atomic per wave.
+constexpr int kRemoveBlock = 256;
+template <int G>
+__global__ void __launch_bounds__(kRemoveBlock) k_remove_edges(int64_t k, const int32_t *removed,
+                                                               const int64_t *row_ptr,
+                                                               const uint32_t *inc,
+                                                               const int32_t *src,
+                                                               const int32_t *dst,
+                                                               const int32_t *stamp,
+                                                               int32_t round, int32_t *deg,
+                                                               unsigned long long *gone) {
+    constexpr int kGroups = kRemoveBlock / G;
+    const int grp = threadIdx.x / G, lane = threadIdx.x % G;
+    unsigned long long cnt = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kGroups + grp; i < k;
+         i += (int64_t)gridDim.x * kGroups) {
         const int32_t u = removed[i];
-        unsigned long long cnt = 0;
-        for (int64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j) {
+        const int64_t end = row_ptr[u + 1];
+        for (int64_t j = row_ptr[u] + lane; j < end; j += G) {
             uint32_t ent = inc[j];
             int64_t e = ent >> 1;
             int32_t v = (ent & 1) ? src[e] : dst[e];
@@ -110,8 +148,9 @@ __global__ void k_remove_edges(int64_t k, const int32_t *removed, const int64_t 
                 ++cnt;
             }
         }
-        if (cnt) atomicAdd(gone, cnt);
     }
+    for (int o = kWave / 2; o > 0; o >>= 1) cnt += __shfl_down(cnt, o, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0 && cnt) atomicAdd(gone, cnt);
 }
 
 __global__ void k_keep_flags(int32_t n, const int32_t *stamp, uint8_t *node_keep, int64_t *flag) {
@@ -302,8 +341,9 @@ PruneResult run_prune(int32_t n, int64_t m, const int32_t *src, const int32_t *d
                        hist.p);
     exclusive_scan_i64((const int64_t *)hist.p, bin_start.p, kBins, nullptr, scan_tmp.p,
                        scan_tmp.bytes(), s);
-    hipLaunchKernelGGL(k_bucket_scatter, dim3(gn), dim3(256), 0, s, n, deg.p, bin_start.p,
-                       cursor.p, by_deg.p);
+    if (n > 0)
+        hipLaunchKernelGGL(k_bucket_scatter, dim3((unsigned)((n + kScatterChunk - 1) / kScatterChunk)),
+                           dim3(kScatterBlock), 0, s, n, deg.p, bin_start.p, cursor.p, by_deg.p);
     std::vector<int64_t> hstart(kBins);
     LOWD_HIP(hipMemcpyAsync(hstart.data(), bin_start.p, kBins * sizeof(int64_t),
                             hipMemcpyDeviceToHost, s));
@@ -345,8 +385,18 @@ PruneResult run_prune(int32_t n, int64_t m, const int32_t *src, const int32_t *d
         LOWD_HIP(hipMemsetAsync(gone.p, 0, sizeof(unsigned long long), s));
         const unsigned gr = grid_for(nrm, 256);
         hipLaunchKernelGGL(k_stamp, dim3(gr), dim3(256), 0, s, nrm, rm_list, stamp.p, round);
-        hipLaunchKernelGGL(k_remove_edges, dim3(gr), dim3(256), 0, s, nrm, rm_list, csr.row_ptr.p,
-                           csr.inc.p, src, dst, stamp.p, round, deg.p, gone.p);
+        if (nrm >= (1 << 18))
+            hipLaunchKernelGGL(k_remove_edges<1>, dim3(grid_for(nrm, kRemoveBlock)),
+                               dim3(kRemoveBlock), 0, s, nrm, rm_list, csr.row_ptr.p, csr.inc.p,
+                               src, dst, stamp.p, round, deg.p, gone.p);
+        else if (nrm >= (1 << 12))
+            hipLaunchKernelGGL(k_remove_edges<kWave>, dim3(grid_for(nrm, kRemoveBlock / kWave)),
+                               dim3(kRemoveBlock), 0, s, nrm, rm_list, csr.row_ptr.p, csr.inc.p,
+                               src, dst, stamp.p, round, deg.p, gone.p);
+        else
+            hipLaunchKernelGGL(k_remove_edges<kRemoveBlock>, dim3(grid_for(nrm, 1)),
+                               dim3(kRemoveBlock), 0, s, nrm, rm_list, csr.row_ptr.p, csr.inc.p,
+                               src, dst, stamp.p, round, deg.p, gone.p);
         LOWD_HIP(hipGetLastError());
         unsigned long long g = 0;
         LOWD_HIP(hipMemcpyAsync(&g, gone.p, sizeof(g), hipMemcpyDeviceToHost, s));
