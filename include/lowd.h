@@ -369,7 +369,11 @@ typedef struct lowd_batch lowd_batch;
  * state.  With tune = 1 it also times each supported launch shape (waves
  * per workgroup, prefetching tile buffers or not, workgroups per CU) on a
  * short run of this batch and keeps the fastest; the shape never changes a
- * result.  tune = 0 keeps the default shape.  Arguments as for
+ * result.  tune = 0 keeps the default shape.  For LOWD_STATE_F32K, launches
+ * made once at most two graphs per CU still iterate (as of the last
+ * lowd_batch_retire) use 16 waves per workgroup, one workgroup per CU; the
+ * environment variable LOWD_BATCH_SHAPE=waves,prefetch,per_cu forces one
+ * shape for every launch instead.  Arguments as for
  * lowd_batch_solve; the device arrays are copied, not kept.
  *   out  [host] out: the prepared batch; free with lowd_batch_free
  * Synchronises `stream`.

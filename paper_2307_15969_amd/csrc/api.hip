@@ -631,7 +631,16 @@ struct lowd_batch {
     int32_t prefetch = 1;  // double-buffered tiles or not,
     int32_t blocks = 1;    // workgroups
     int32_t shape() const { return waves * 2 + prefetch; }
-    int32_t graph_sweeps = -1;
+    // Once few graphs still iterate, each runs alone on a CU and its widest
+    // phases (more tiles than waves) bound the launch: then 16 waves per
+    // workgroup (no tile prefetch, to stay within 128 registers) deal those
+    // tiles out faster.  FP32K only (the FP64 kernel would spill at 16
+    // waves); off when the shape is forced.
+    bool tail_shape = false;
+    int32_t cus = 1;
+    int32_t last_active = 0;   // graphs iterating after the last retire
+    static constexpr int32_t kTailShape = 16 * 2 + 0;
+    int32_t graph_sweeps = -1, graph_shape = -1;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     void drop_graph() {
@@ -640,6 +649,7 @@ struct lowd_batch {
         exec = nullptr;
         graph = nullptr;
         graph_sweeps = -1;
+        graph_shape = -1;
     }
     ~lowd_batch() { drop_graph(); }
 };
@@ -651,26 +661,33 @@ static void batch_reset(lowd_batch *b, hipStream_t s) {
     launch_activate_all(b->G, b->order_all.p, b->edge_ptr.p, b->order.p, b->active.p,
                         b->active_edges.p, s);
     LOWD_HIP(hipGetLastError());
+    b->last_active = b->G;
 }
 
 // One launch of the persistent kernel for `sweeps` sweeps, as a HIP graph
 // (captured once per distinct sweep count and launch shape).
 static void batch_launch(lowd_batch *b, int32_t sweeps, hipStream_t s) {
-    if (b->graph_sweeps != sweeps || !b->exec) {
+    int32_t shape = b->shape(), blocks = b->blocks;
+    if (b->tail_shape && b->last_active <= 2 * b->cus) {
+        shape = lowd_batch::kTailShape;
+        blocks = std::min(b->cus, b->G);
+    }
+    if (b->graph_sweeps != sweeps || b->graph_shape != shape || !b->exec) {
         b->drop_graph();
         hipStream_t cs;
         LOWD_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
         hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (err == hipSuccess) {
-            b->fn.batch(b->shape(), b->active.p, b->order.p, b->queue.p, b->node_ptr.p, b->desc_ptr.p,
+            b->fn.batch(shape, b->active.p, b->order.p, b->queue.p, b->node_ptr.p, b->desc_ptr.p,
                         b->descs.p, b->tile_center.p, b->slot_leaf.p, b->slot_x.p, sweeps,
-                        b->Lstate.p, b->lds, b->blocks, cs);
+                        b->Lstate.p, b->lds, blocks, cs);
             err = hipStreamEndCapture(cs, &b->graph);
         }
         (void)hipStreamDestroy(cs);
         LOWD_HIP(err);
         LOWD_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
         b->graph_sweeps = sweeps;
+        b->graph_shape = shape;
     }
     LOWD_HIP(hipGraphLaunch(b->exec, s));
 }
@@ -876,16 +893,22 @@ lowd_status lowd_batch_prepare(int32_t G, const int64_t *node_ptr, const int64_t
         int32_t per_cu = 1;
         if (const char *e = getenv("LOWD_BATCH_SHAPE")) {   // "waves,prefetch,per_cu"
             int w = 0, pf = 0, pc = 0;
-            if (sscanf(e, "%d,%d,%d", &w, &pf, &pc) != 3 || (w != 4 && w != 8) ||
-                (pf != 0 && pf != 1) || pc < 1 || pc > 4)
-                fail(LOWD_E_ARG, "LOWD_BATCH_SHAPE must be waves(4|8),prefetch(0|1),per_cu(1-4)");
+            if (sscanf(e, "%d,%d,%d", &w, &pf, &pc) != 3 || (w != 4 && w != 8 && w != 16) ||
+                (pf != 0 && pf != 1) || (w == 16 && pf != 0) || pc < 1 || pc > 4)
+                fail(LOWD_E_ARG, "LOWD_BATCH_SHAPE must be waves(4|8),prefetch(0|1),per_cu(1-4) "
+                                 "or 16,0,per_cu");
             b->waves = w;
             b->prefetch = pf;
             per_cu = pc;
         }
         b->blocks = (int32_t)std::min<int64_t>((int64_t)cus * per_cu, G);
+        b->cus = cus;
         b->fn.set_batch_lds(b->shape(), b->lds);
         if (tune) batch_tune(b, cus, s);
+        if (state == LOWD_STATE_F32K && !getenv("LOWD_BATCH_SHAPE")) {
+            b->fn.set_batch_lds(lowd_batch::kTailShape, b->lds);
+            b->tail_shape = true;
+        }
         batch_reset(b, s);
         LOWD_HIP(hipStreamSynchronize(s));
         *out = guard.release();
@@ -955,6 +978,7 @@ lowd_status lowd_batch_retire(lowd_batch *b, const int64_t *num, const int64_t *
         LOWD_HIP(hipStreamSynchronize(s));
         if (active) *active = a;
         if (active_edges) *active_edges = ae;
+        b->last_active = a;
     });
 }
 

@@ -222,8 +222,15 @@ __global__ void k_exponent_range(int64_t m, const float *w, int32_t *range) {
         lo = q < lo ? q : lo;
         hi = q > hi ? q : hi;
     }
-    atomicMin(&range[0], lo);
-    atomicMax(&range[1], hi);
+    for (int o = kWave / 2; o > 0; o >>= 1) {   // one atomic pair per wave
+        const int32_t a = __shfl_down(lo, o, kWave), b = __shfl_down(hi, o, kWave);
+        lo = a < lo ? a : lo;
+        hi = b > hi ? b : hi;
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        atomicMin(&range[0], lo);
+        atomicMax(&range[1], hi);
+    }
 }
 
 __global__ void k_fixed_weights(int64_t m, const float *w, int32_t qmin, uint64_t *wi) {

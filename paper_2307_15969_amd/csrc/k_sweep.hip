@@ -962,6 +962,7 @@ static void sweep_launchers(SweepLaunch &fn) {
             LOWD_BATCH_CASE(4, 1)
             LOWD_BATCH_CASE(8, 0)
             LOWD_BATCH_CASE(8, 1)
+            LOWD_BATCH_CASE(16, 0)
             default: fail(LOWD_E_ARG, "unsupported batch workgroup shape");
         }
 #undef LOWD_BATCH_CASE
@@ -971,6 +972,7 @@ static void sweep_launchers(SweepLaunch &fn) {
                         : shape == 9 ? (const void *)k_batch<St, 4, true>
                         : shape == 16 ? (const void *)k_batch<St, 8, false>
                         : shape == 17 ? (const void *)k_batch<St, 8, true>
+                        : shape == 32 ? (const void *)k_batch<St, 16, false>
                                       : nullptr;
         if (!k) fail(LOWD_E_ARG, "unsupported batch workgroup shape");
         LOWD_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));

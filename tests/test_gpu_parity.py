@@ -739,7 +739,7 @@ def test_batch_retire_freezes_converged_graphs():
     b.close()
 
 
-@pytest.mark.parametrize("shape", ["8,1,1", "8,0,2", "4,1,2", "4,0,4"])
+@pytest.mark.parametrize("shape", ["8,1,1", "8,0,2", "4,1,2", "4,0,4", "16,0,1"])
 def test_batch_every_launch_shape_is_bit_exact(shape, monkeypatch):
     monkeypatch.setenv("LOWD_BATCH_SHAPE", shape)
     gs = batch_graphs(30, 11)
@@ -765,3 +765,29 @@ def test_batch_rejects_bad_graphs():
     with pytest.raises(lowd.LowdError) as ei:
         lowd.batch_solve([g, bad], 1)
     assert ei.value.status == -2
+
+
+def test_batch_f32k_tail_shape_matches_a_fixed_shape(monkeypatch):
+    """FP32K batches switch to 16-wave workgroups once few graphs iterate
+    (here from the start: 30 graphs); the loads equal, bit for bit, those of
+    a forced 8-wave shape, across a retire and further sweeps."""
+    gs = batch_graphs(30, 17)
+    T1, T2, tol = 6, 4, 1e-3
+
+    def run():
+        b = lowd.Batch(gs, "f32k")
+        b.iterate(T1)
+        b.extract()
+        act = b.retire(tol)
+        b.iterate(T2)
+        b.extract(loads=True)
+        out = (b.load.cpu().numpy().copy(), b.num.cpu().numpy().copy(), act)
+        b.close()
+        return out
+
+    La, na, aa = run()
+    monkeypatch.setenv("LOWD_BATCH_SHAPE", "8,1,1")
+    Lb, nb, ab = run()
+    log(f"active after retire: {aa}")
+    assert aa == ab
+    assert np.array_equal(La, Lb) and np.array_equal(na, nb)
