@@ -224,6 +224,18 @@ lowd_status lowd_extract_densest(lowd_solver *s, uint8_t *in_set, int64_t *num_u
  */
 lowd_status lowd_check_kept(lowd_solver *s, double *D, double *sum_loads, double *sum_sq_loads,
                             void *stream);
+
+/*
+ * lowd_resync_loads -- LOWD_STATE_F32K: sets every node's carried
+ * compensated load to the FP64 load recomputed from the stored fractions
+ * (as lowd_check computes it), rounded to the (s, c) pair.  A step moves
+ * the carried loads by its exact amount while the FP32 fraction takes the
+ * rounded one, so over many sweeps the carried loads can drift from the
+ * loads of the stored fractions, which alone make the dual bound; this
+ * restarts them from those.  No-op for LOWD_STATE_F64 (its loads are the
+ * loads of its fractions) and for a graph without edges.  Asynchronous.
+ */
+lowd_status lowd_resync_loads(lowd_solver *s, void *stream);
 lowd_status lowd_extract_densest_kept(lowd_solver *s, uint8_t *in_set, int64_t *num_unit,
                                       double *num_w, int64_t *den, double *D, double *gap,
                                       void *stream);
@@ -395,12 +407,15 @@ lowd_status lowd_batch_iterate(lowd_batch *b, int32_t sweeps, void *stream);
 /*
  * lowd_batch_extract -- every graph's densest set from its current loads
  * (Algorithm 1's extraction), and its largest load D_g, the dual bound of
- * Section III-B (rho_g <= rho*_g <= D_g).
+ * Section III-B (rho_g <= rho*_g <= D_g).  The loads are FP64: for
+ * LOWD_STATE_F32K they are recomputed from the stored fractions (summed in
+ * incidence order), so that D_g is the bound of the fractions as stored,
+ * not of the compensated loads the sweeps carry.
  *   in_set  [device] uint8[total nodes] out
  *   num     [device] int64[G] out
  *   den     [device] int64[G] out
  *   D       [device] double[G] out, or NULL
- *   load    [device] double[total nodes] out, or NULL
+ *   load    [device] double[total nodes] out (the FP64 loads above), or NULL
  * Asynchronous.
  */
 lowd_status lowd_batch_extract(lowd_batch *b, uint8_t *in_set, int64_t *num, int64_t *den,

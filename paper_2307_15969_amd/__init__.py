@@ -54,6 +54,7 @@ def lib() -> C.CDLL:
         L.lowd_extract_densest.argtypes = [vp, vp, P(i64), P(C.c_double), P(i64),
                                            P(C.c_double), P(C.c_double), vp]
         L.lowd_check_kept.argtypes = L.lowd_check.argtypes
+        L.lowd_resync_loads.argtypes = [vp, vp]
         L.lowd_extract_densest_kept.argtypes = L.lowd_extract_densest.argtypes
         L.lowd_read_state.argtypes = [vp, vp, vp, vp]
         L.lowd_ldd_readout.argtypes = [vp, vp, vp, vp, P(i64), vp]
@@ -78,7 +79,8 @@ def lib() -> C.CDLL:
                   L.lowd_ldd_readout, L.lowd_convergence_trace, L.lowd_dks_bound,
                   L.lowd_solver_info, L.lowd_batch_solve, L.lowd_schedule_build, L.lowd_reset_loads,
                   L.lowd_batch_prepare, L.lowd_batch_reset, L.lowd_batch_iterate,
-                  L.lowd_batch_extract, L.lowd_batch_info, L.lowd_batch_retire):
+                  L.lowd_batch_extract, L.lowd_batch_info, L.lowd_batch_retire,
+                  L.lowd_check_kept, L.lowd_extract_densest_kept, L.lowd_resync_loads):
             f.restype = C.c_int32
         _lib = L
     return _lib
@@ -250,6 +252,11 @@ class Solver:
         _check(f(self._h, C.byref(D), C.byref(s), C.byref(s2), _stream(stream)))
         return D.value, s.value, s2.value
 
+    def resync(self, stream=None):
+        """F32K: restart the carried loads from the FP64 loads of the stored
+        fractions (lowd_resync_loads); no-op for F64."""
+        _check(lib().lowd_resync_loads(self._h, _stream(stream)))
+
     def extract(self, stream=None, kept: bool = False) -> dict:
         """The densest prefix of the descending-load order; kept as for
         check (the set's density is exact either way)."""
@@ -348,6 +355,8 @@ def certify(sv: "Solver", best, tol: float, stream=None):
         if gap <= tol and not exact:
             D = sv.check(stream)[0]
             gap = _gap(D, _density(best))
+            if gap > tol:   # the carried loads drifted from the fractions' loads
+                sv.resync(stream)
         return dict(best, D=D, gap=gap), gap
 
     if best is not None:

@@ -378,6 +378,17 @@ lowd_status lowd_check(lowd_solver *sv, double *D, double *sum_loads, double *su
     return guarded([&] { check_impl(sv, false, D, sum_loads, sum_sq_loads, (hipStream_t)stream); });
 }
 
+lowd_status lowd_resync_loads(lowd_solver *sv, void *stream) {
+    return guarded([&] {
+        if (!sv) fail(LOWD_E_ARG, "solver is NULL");
+        if (sv->state != LOWD_STATE_F32K || sv->m == 0) return;
+        hipStream_t s = (hipStream_t)stream;
+        loads_f64(sv, s, false);
+        sv->fn.write_loads(sv->n, sv->home.p, sv->L64.p, sv->E.p, s);
+        LOWD_HIP(hipGetLastError());
+    });
+}
+
 lowd_status lowd_check_kept(lowd_solver *sv, double *D, double *sum_loads, double *sum_sq_loads,
                             void *stream) {
     return guarded([&] { check_impl(sv, true, D, sum_loads, sum_sq_loads, (hipStream_t)stream); });
@@ -625,6 +636,13 @@ struct lowd_batch {
     DBuf<char> slot_x, Lstate;
     DBuf<double> L64;
     DBuf<unsigned> queue;
+    // FP32K: the incidence of the concatenated graphs, each edge's slot and
+    // the nodes of degree >= kBigRow, to recompute FP64 loads from the
+    // fractions (the dual bound must be the loads of the stored fractions)
+    Csr csr;
+    DBuf<int64_t> edge_slot;
+    DBuf<int32_t> big;
+    int32_t nbig = 0;
     BatchExtractScratch ex;
     size_t lds = 0;        // bytes of LDS per workgroup
     int32_t waves = 8;     // launch shape: waves per workgroup,
@@ -836,6 +854,8 @@ lowd_status lowd_batch_prepare(int32_t G, const int64_t *node_ptr, const int64_t
         std::vector<int32_t> tile_center;
         std::vector<uint32_t> slot_leaf;
         std::vector<int64_t> slot_edge, desc_ptr((size_t)G + 1, 0);
+        const bool recompute = state == LOWD_STATE_F32K && M > 0;
+        std::vector<int64_t> edge_slot(recompute ? (size_t)M : 0);
         size_t lds_need = 0;
         for (int32_t g = 0; g < G; ++g) {
             const Schedule &sc = sch[(size_t)g];
@@ -859,6 +879,22 @@ lowd_status lowd_batch_prepare(int32_t G, const int64_t *node_ptr, const int64_t
             tile_center.insert(tile_center.end(), sc.tile_center.begin(), sc.tile_center.end());
             slot_leaf.insert(slot_leaf.end(), sc.slot_leaf.begin(), sc.slot_leaf.end());
             for (int64_t e : sc.slot_edge) slot_edge.push_back(e >= 0 ? e + edge_ptr[g] : -1);
+            if (recompute)
+                for (size_t e = 0; e < sc.edge_slot.size(); ++e)
+                    edge_slot[(size_t)edge_ptr[g] + e] = slot0 + sc.edge_slot[e];
+        }
+        if (recompute) {
+            upload(b->edge_slot, edge_slot, s);
+            build_incidence((int32_t)N, M, b->gsrc.p, b->gdst.p, b->csr, s);
+            std::vector<int32_t> deg((size_t)N, 0), big;
+            for (int64_t e = 0; e < M; ++e) {
+                ++deg[(size_t)gsrc[(size_t)e]];
+                ++deg[(size_t)gdst[(size_t)e]];
+            }
+            for (int64_t u = 0; u < N; ++u)
+                if (deg[(size_t)u] >= kBigRow) big.push_back((int32_t)u);
+            upload(b->big, big, s);
+            b->nbig = (int32_t)big.size();
         }
         std::vector<int32_t> order((size_t)G);
         for (int32_t g = 0; g < G; ++g) order[(size_t)g] = g;
@@ -937,7 +973,16 @@ lowd_status lowd_batch_extract(lowd_batch *b, uint8_t *in_set, int64_t *num, int
         if (!b) fail(LOWD_E_ARG, "batch is NULL");
         if (!in_set || !num || !den) fail(LOWD_E_ARG, "in_set/num/den is NULL");
         hipStream_t s = (hipStream_t)stream;
-        b->fn.batch_loads_f64(b->N, b->Lstate.p, b->L64.p, s);
+        if (b->state == LOWD_STATE_F32K && b->M > 0) {
+            // FP64 loads of the stored fractions; the carried loads restart
+            // from them, so the rounding of the fractions cannot make the two
+            // drift apart for more than one check interval
+            b->fn.loads_f64((int32_t)b->N, b->csr.row_ptr.p, b->csr.inc.p, b->edge_slot.p,
+                            b->slot_x.p, nullptr, nullptr, b->big.p, b->nbig, nullptr, b->L64.p,
+                            s);
+            b->fn.batch_loads_from_f64(b->N, b->L64.p, b->Lstate.p, s);
+        } else
+            b->fn.batch_loads_f64(b->N, b->Lstate.p, b->L64.p, s);
         BatchExtractArgs a;
         a.G = b->G;
         a.N = b->N;

@@ -725,6 +725,15 @@ __global__ void k_batch_loads_f64(int64_t N, const typename St::L *Lstate, doubl
         L64[u] = St::to_f64(Lstate[u]);
 }
 
+// The carried loads set to FP64 values (the loads recomputed from the
+// fractions), rounded to the state's load type.
+template <class St>
+__global__ void k_batch_loads_from_f64(int64_t N, const double *L64, typename St::L *Lstate) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < N;
+         u += (int64_t)gridDim.x * blockDim.x)
+        Lstate[u] = St::from_f64(L64[u]);
+}
+
 __global__ void k_zero_u32(unsigned *p) { *p = 0u; }
 
 // ------------------------------------------------------------ statistics --
@@ -789,6 +798,15 @@ __global__ void k_loads_to_f64(int32_t n, const uint32_t *home, const typename S
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
          u += (int64_t)gridDim.x * blockDim.x)
         L64[u] = St::to_f64(E[home[u]]);
+}
+
+// The inverse: node u's carried load set from an FP64 value.
+template <class St>
+__global__ void k_loads_from_f64(int32_t n, const uint32_t *home, const double *L64,
+                                 typename St::L *E) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+         u += (int64_t)gridDim.x * blockDim.x)
+        E[home[u]] = St::from_f64(L64[u]);
 }
 
 __device__ inline void red3(double &mx, double &s, double &s2, double *lds) {
@@ -935,6 +953,11 @@ static void sweep_launchers(SweepLaunch &fn) {
             hipLaunchKernelGGL((k_loads_to_f64<St>), dim3(grid_for(n, 256)), dim3(256), 0, s, n,
                                home, (const typename St::L *)E, L64);
     };
+    fn.write_loads = [](int32_t n, const uint32_t *home, const double *L64, void *E,
+                        hipStream_t s) {
+        hipLaunchKernelGGL((k_loads_from_f64<St>), dim3(grid_for(n, 256)), dim3(256), 0, s, n,
+                           home, L64, (typename St::L *)E);
+    };
     fn.read_x = [](int64_t m, const int64_t *edge_slot, const void *slot_x, double *x,
                    hipStream_t s) {
         hipLaunchKernelGGL((k_read_x<St>), dim3(grid_for(m, 256)), dim3(256), 0, s, m, edge_slot,
@@ -984,6 +1007,10 @@ static void sweep_launchers(SweepLaunch &fn) {
     fn.batch_loads_f64 = [](int64_t N, const void *Lstate, double *L64, hipStream_t s) {
         hipLaunchKernelGGL((k_batch_loads_f64<St>), dim3(grid_for(N, 256)), dim3(256), 0, s, N,
                            (const typename St::L *)Lstate, L64);
+    };
+    fn.batch_loads_from_f64 = [](int64_t N, const double *L64, void *Lstate, hipStream_t s) {
+        hipLaunchKernelGGL((k_batch_loads_from_f64<St>), dim3(grid_for(N, 256)), dim3(256), 0, s,
+                           N, L64, (typename St::L *)Lstate);
     };
     fn.x_bytes = sizeof(typename St::X);
     fn.l_bytes = sizeof(typename St::L);

@@ -171,6 +171,8 @@ struct SweepLaunch {
                       const int64_t *edge_slot, const void *slot_x, const float *w,
                       const uint32_t *home, const int32_t *big, int32_t nbig, const void *E,
                       double *L64, hipStream_t s);
+    void (*write_loads)(int32_t n, const uint32_t *home, const double *L64, void *E,
+                        hipStream_t s);
     void (*read_x)(int64_t m, const int64_t *edge_slot, const void *slot_x, double *x,
                    hipStream_t s);
     void (*read_loads)(int32_t n, const uint32_t *home, const void *E, double *out,
@@ -183,6 +185,7 @@ struct SweepLaunch {
     void (*set_batch_lds)(int32_t shape, size_t bytes);
     void (*batch_init_loads)(int64_t N, const int32_t *deg, void *Lstate, hipStream_t s);
     void (*batch_loads_f64)(int64_t N, const void *Lstate, double *L64, hipStream_t s);
+    void (*batch_loads_from_f64)(int64_t N, const double *L64, void *Lstate, hipStream_t s);
     size_t x_bytes;
     size_t l_bytes;
 };

@@ -48,6 +48,7 @@ def test_argument_errors_need_no_device():
     assert L.lowd_iterate(None, 1, None) == -1
     assert L.lowd_check(None, None, None, None, None) == -1
     assert L.lowd_check_kept(None, None, None, None, None) == -1
+    assert L.lowd_resync_loads(None, None) == -1
     assert L.lowd_extract_densest_kept(None, None, None, None, None, None, None, None) == -1
     assert L.lowd_iterate(None, -1, None) == -1
     L.lowd_solver_free(None)

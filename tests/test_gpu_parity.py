@@ -238,6 +238,34 @@ def test_kept_check_and_extract(name, g, state):
     assert abs(got - num) <= 1e-12 * max(num, 1.0)
 
 
+@pytest.mark.parametrize("name,g", GRAPHS, ids=[n for n, _ in GRAPHS])
+def test_f32k_resync_restarts_from_the_fractions_loads(name, g):
+    """After a resync the carried FP32K loads are the loads recomputed from
+    the fractions (to the precision of the (s, c) pair), the fractions are
+    untouched, and further sweeps stay within the FP32 tolerance of the
+    oracle; for FP64 a resync changes nothing."""
+    T = 15
+    for state in ("f32k", "f64"):
+        sv = lowd.Solver(g.n, g.src, g.dst, g.w, state)
+        sv.iterate(T)
+        x0, L0 = (t.cpu().numpy() for t in sv.read_state())
+        D = sv.check()[0]
+        sv.resync()
+        x1, L1 = (t.cpu().numpy() for t in sv.read_state())
+        assert np.array_equal(x0, x1)
+        Dk = sv.check(kept=True)[0]
+        if state == "f64":
+            assert np.array_equal(L0, L1) and Dk == D
+        else:
+            assert abs(Dk - D) <= 1e-13 * max(D, 1.0)
+            sv.iterate(T)
+            _, Lo, *_ = oracle_run(g, 2 * T, 16)
+            _, L2 = sv.read_state()
+            L2 = L2.cpu().numpy()
+            assert np.max(np.abs(L2 - Lo)) <= 1e-5 * np.max(np.abs(Lo))
+        sv.close()
+
+
 def test_f32k_solve_certifies_with_the_exact_bound():
     """solve() screens with the kept FP32K loads but returns a gap taken
     from the exact D (recomputed from the fractions), and its set is as
@@ -791,3 +819,33 @@ def test_batch_f32k_tail_shape_matches_a_fixed_shape(monkeypatch):
     log(f"active after retire: {aa}")
     assert aa == ab
     assert np.array_equal(La, Lb) and np.array_equal(na, nb)
+
+
+def test_batch_f32k_bound_is_recomputed_from_the_fractions():
+    """FP32K batches report loads (and D_g) recomputed in FP64 from the
+    stored FP32 fractions: they match the FP64 sums, on the CPU, of the
+    fractions a single-graph FP32K solver holds after the same sweeps (the
+    two run the same steps in the same order), and D_g is their maximum."""
+    gs = batch_graphs(12, 23)
+    T = 20
+    b = lowd.Batch(gs, "f32k")
+    b.iterate(T)
+    b.extract(loads=True)
+    L = b.load.cpu().numpy()
+    D = b.D.cpu().numpy()
+    for i, g in enumerate(gs):
+        a, c = b.node_ptr[i], b.node_ptr[i + 1]
+        if g.m == 0:
+            continue
+        sv = lowd.Solver(g.n, g.src, g.dst, None, "f32k")
+        sv.iterate(T)
+        x, _ = sv.read_state()
+        x = x.cpu().numpy()
+        ref = np.zeros(g.n)
+        np.add.at(ref, g.src, x)
+        np.add.at(ref, g.dst, 1.0 - x)
+        assert np.max(np.abs(L[a:c] - ref)) <= 1e-12 * np.max(ref), i
+        assert D[i] == np.max(L[a:c]), i
+        assert abs(D[i] - sv.check()[0]) <= 1e-12 * D[i], i
+        sv.close()
+    b.close()
