@@ -381,31 +381,25 @@ def run_uniform(args, torch, lowd, synth):
     return out
 
 
-def run_batch4096(args, torch, lowd, synth):
-    t0 = time.perf_counter()
-    gs = synth.workload(4, seed=args.seed)
+def batch_solves(gs, state, args, torch, lowd, stream):
+    """Prepares (and tunes) the batch in one state, then times args.steps
+    solves after args.warmup untimed ones.  Each solve: reset; then sweep the
+    graphs still above the tolerance, k sweeps a launch, extract and retire,
+    until every graph is within it.  Once fewer than an eighth of the graphs
+    remain, k doubles after each check (up to 16 K): the few slow graphs then
+    cost a check far more than a sweep."""
     M = sum(g.m for g in gs)
-    N = sum(g.n for g in gs)
-    print(f"[bench] {len(gs)} graphs, N={N} M={M}, generated in {time.perf_counter() - t0:.1f}s",
-          flush=True)
-    state = args.state or "f32k"
-    stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
     b = lowd.Batch(gs, state, tune=True, stream=stream)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     info = b.info()
-    print(f"[bench] prepare + tune {t_setup:.1f}s info {info}", flush=True)
+    print(f"[bench] {state} prepare + tune {t_setup:.1f}s info {info}", flush=True)
     ev_a = torch.cuda.Event(enable_timing=True)
     ev_b = torch.cuda.Event(enable_timing=True)
     K = args.check_every
 
     def one_solve():
-        """reset; then sweep the graphs still above the tolerance, k sweeps a
-        launch, extract and retire, until every graph is within it.  Once
-        fewer than an eighth of the graphs remain, k doubles after each check
-        (up to 16 K): the few slow graphs then cost a check far more than a
-        sweep."""
         b.reset(stream)
         updates, launches, sweeps, launch_s, launch_bytes = 0, 0, 0, 0.0, 0
         active, aedges = len(gs), M
@@ -430,47 +424,67 @@ def run_batch4096(args, torch, lowd, synth):
 
     for i in range(args.warmup):
         u, l, s_, _, _ = one_solve()
-        print(f"[bench] warmup {i}: {s_} sweeps in {l} launches, {u} edge updates", flush=True)
+        print(f"[bench] {state} warmup {i}: {s_} sweeps in {l} launches, {u} edge updates",
+              flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    tot_u = tot_l = 0
-    tot_s = 0.0
-    tot_bytes = 0
-    last = None
+    r = dict(updates=0, launches=0, launch_s=0.0, bytes=0, last=None, setup_s=t_setup, info=info)
     for i in range(args.steps):
         u, l, s_, ls, lb = one_solve()
-        tot_u += u
-        tot_l += l
-        tot_s += ls
-        tot_bytes += lb
-        last = (u, l, s_)
-        print(f"[bench] step {i}: {s_} sweeps in {l} launches", flush=True)
+        r["updates"] += u
+        r["launches"] += l
+        r["launch_s"] += ls
+        r["bytes"] += lb
+        r["last"] = (u, l, s_)
+        print(f"[bench] {state} step {i}: {s_} sweeps in {l} launches", flush=True)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    r["elapsed"] = time.perf_counter() - t0
     b.extract(stream)
-    gaps = b.gaps()
-    num = b.num.cpu().numpy()
-    den = b.den.cpu().numpy()
-    out = base_line(args, tot_u / elapsed, elapsed / args.steps * 1e3, state,
+    r["gaps"] = b.gaps()
+    r["num"] = b.num.cpu().numpy()
+    r["den"] = b.den.cpu().numpy()
+    b.close()
+    return r
+
+
+def run_batch4096(args, torch, lowd, synth):
+    t0 = time.perf_counter()
+    gs = synth.workload(4, seed=args.seed)
+    M = sum(g.m for g in gs)
+    N = sum(g.n for g in gs)
+    print(f"[bench] {len(gs)} graphs, N={N} M={M}, generated in {time.perf_counter() - t0:.1f}s",
+          flush=True)
+    state = args.state or "f32k"
+    stream = torch.cuda.current_stream()
+    r = batch_solves(gs, state, args, torch, lowd, stream)
+    last = r["last"]
+    out = base_line(args, r["updates"] / r["elapsed"], r["elapsed"] / args.steps * 1e3, state,
                     {"workload": WORKLOADS["batch4096"] + ", " + state.upper() +
                      ", every graph to a 1e-6 gap, converged graphs retired",
-                     "graphs": len(gs), "N": N, "M": M, "star_max": 16, "check_every": K,
-                     "seed": args.seed})
+                     "graphs": len(gs), "N": N, "M": M, "star_max": 16,
+                     "check_every": args.check_every, "seed": args.seed})
     out.update({
-        "time_to_1e-6_ms": elapsed / args.steps * 1e3,
+        "time_to_1e-6_ms": r["elapsed"] / args.steps * 1e3,
         "sweeps_to_1e-6": last[2],
         "launches": last[1],
         "edge_updates_per_solve": last[0],
-        "max_gap": float(np.max(gaps)),
-        "densities_sum": f"{int(num.sum())}/{int(den.sum())}",
-        "setup_s": t_setup,
-        "batch": info,
-        "roofline": roofline(tot_bytes / max(tot_l, 1), tot_s / max(tot_l, 1),
+        "max_gap": float(np.max(r["gaps"])),
+        "densities_sum": f"{int(r['num'].sum())}/{int(r['den'].sum())}",
+        "setup_s": r["setup_s"],
+        "batch": r["info"],
+        "roofline": roofline(r["bytes"] / max(r["launches"], 1),
+                             r["launch_s"] / max(r["launches"], 1),
                              "one persistent launch of k sweeps over the graphs still "
                              "iterating (LDS-resident; HBM carries ids, fractions and the "
                              "loads in and out)"),
     })
-    b.close()
+    # the same batch in the other state, for comparison
+    other = "f64" if state == "f32k" else "f32k"
+    r2 = batch_solves(gs, other, args, torch, lowd, stream)
+    out[other] = {"time_to_1e-6_ms": r2["elapsed"] / args.steps * 1e3,
+                  "sweeps_to_1e-6": r2["last"][2], "launches": r2["last"][1],
+                  "max_gap": float(np.max(r2["gaps"])),
+                  "densities_sum": f"{int(r2['num'].sum())}/{int(r2['den'].sum())}"}
     if args.per_graph_sample > 0:
         out["per_graph_f64"] = per_graph_baseline(gs, args, torch, lowd, stream)
     return out
