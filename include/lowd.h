@@ -408,9 +408,11 @@ lowd_status lowd_batch_iterate(lowd_batch *b, int32_t sweeps, void *stream);
  * lowd_batch_extract -- every graph's densest set from its current loads
  * (Algorithm 1's extraction), and its largest load D_g, the dual bound of
  * Section III-B (rho_g <= rho*_g <= D_g).  The loads are FP64: for
- * LOWD_STATE_F32K they are recomputed from the stored fractions (summed in
- * incidence order), so that D_g is the bound of the fractions as stored,
- * not of the compensated loads the sweeps carry.
+ * LOWD_STATE_F32K, those of the graphs still iterating are recomputed from
+ * the stored fractions, so that D_g is the bound of the fractions as stored
+ * and not of the compensated loads the sweeps carry, and the carried loads
+ * restart from them (a retired graph's fractions no longer change, and its
+ * loads stay those of its last extraction).
  *   in_set  [device] uint8[total nodes] out
  *   num     [device] int64[G] out
  *   den     [device] int64[G] out

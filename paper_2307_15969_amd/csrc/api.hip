@@ -636,13 +636,12 @@ struct lowd_batch {
     DBuf<char> slot_x, Lstate;
     DBuf<double> L64;
     DBuf<unsigned> queue;
-    // FP32K: the incidence of the concatenated graphs, each edge's slot and
-    // the nodes of degree >= kBigRow, to recompute FP64 loads from the
-    // fractions (the dual bound must be the loads of the stored fractions)
+    // FP32K: the incidence of the concatenated graphs and each edge's slot,
+    // to recompute FP64 loads from the fractions (the dual bound must be the
+    // loads of the stored fractions)
     Csr csr;
     DBuf<int64_t> edge_slot;
-    DBuf<int32_t> big;
-    int32_t nbig = 0;
+    DBuf<uint8_t> active_flag;   // [G]
     BatchExtractScratch ex;
     size_t lds = 0;        // bytes of LDS per workgroup
     int32_t waves = 8;     // launch shape: waves per workgroup,
@@ -886,15 +885,7 @@ lowd_status lowd_batch_prepare(int32_t G, const int64_t *node_ptr, const int64_t
         if (recompute) {
             upload(b->edge_slot, edge_slot, s);
             build_incidence((int32_t)N, M, b->gsrc.p, b->gdst.p, b->csr, s);
-            std::vector<int32_t> deg((size_t)N, 0), big;
-            for (int64_t e = 0; e < M; ++e) {
-                ++deg[(size_t)gsrc[(size_t)e]];
-                ++deg[(size_t)gdst[(size_t)e]];
-            }
-            for (int64_t u = 0; u < N; ++u)
-                if (deg[(size_t)u] >= kBigRow) big.push_back((int32_t)u);
-            upload(b->big, big, s);
-            b->nbig = (int32_t)big.size();
+            b->active_flag.alloc((size_t)G);
         }
         std::vector<int32_t> order((size_t)G);
         for (int32_t g = 0; g < G; ++g) order[(size_t)g] = g;
@@ -974,13 +965,13 @@ lowd_status lowd_batch_extract(lowd_batch *b, uint8_t *in_set, int64_t *num, int
         if (!in_set || !num || !den) fail(LOWD_E_ARG, "in_set/num/den is NULL");
         hipStream_t s = (hipStream_t)stream;
         if (b->state == LOWD_STATE_F32K && b->M > 0) {
-            // FP64 loads of the stored fractions; the carried loads restart
-            // from them, so the rounding of the fractions cannot make the two
-            // drift apart for more than one check interval
-            b->fn.loads_f64((int32_t)b->N, b->csr.row_ptr.p, b->csr.inc.p, b->edge_slot.p,
-                            b->slot_x.p, nullptr, nullptr, b->big.p, b->nbig, nullptr, b->L64.p,
-                            s);
-            b->fn.batch_loads_from_f64(b->N, b->L64.p, b->Lstate.p, s);
+            // FP64 loads of the stored fractions of the graphs still
+            // iterating; the carried loads restart from them, so the rounding
+            // of the fractions cannot make the two drift apart for more than
+            // one check interval
+            b->fn.batch_recompute(b->G, b->N, b->active.p, b->order.p, b->node_graph.p,
+                                  b->active_flag.p, b->csr.row_ptr.p, b->csr.inc.p,
+                                  b->edge_slot.p, b->slot_x.p, b->L64.p, b->Lstate.p, s);
         } else
             b->fn.batch_loads_f64(b->N, b->Lstate.p, b->L64.p, s);
         BatchExtractArgs a;

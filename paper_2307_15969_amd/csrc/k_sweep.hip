@@ -725,15 +725,6 @@ __global__ void k_batch_loads_f64(int64_t N, const typename St::L *Lstate, doubl
         L64[u] = St::to_f64(Lstate[u]);
 }
 
-// The carried loads set to FP64 values (the loads recomputed from the
-// fractions), rounded to the state's load type.
-template <class St>
-__global__ void k_batch_loads_from_f64(int64_t N, const double *L64, typename St::L *Lstate) {
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < N;
-         u += (int64_t)gridDim.x * blockDim.x)
-        Lstate[u] = St::from_f64(L64[u]);
-}
-
 __global__ void k_zero_u32(unsigned *p) { *p = 0u; }
 
 // ------------------------------------------------------------ statistics --
@@ -769,6 +760,44 @@ __global__ void __launch_bounds__(256) k_recompute(int32_t n, const int64_t *row
         for (int d = kRowLanes / 2; d > 0; d >>= 1) acc = acc + __shfl_down(acc, d, kRowLanes);
         if (sub == 0) L64[u] = acc;
     }
+}
+
+// Batches (unit weights): the same sums for the nodes of the graphs still
+// iterating (flag[node_graph[u]] set, see k_mark_active), 8 lanes per node
+// over all nodes; written to L64 and, rounded to the state's load type, as
+// the carried loads.  Retired graphs keep both from their last pass: their
+// fractions no longer change.
+template <class St>
+__global__ void __launch_bounds__(256)
+k_batch_recompute(int64_t N, const int32_t *node_graph, const uint8_t *flag,
+                  const int64_t *row_ptr, const uint32_t *inc, const int64_t *edge_slot,
+                  const typename St::X *slot_x, double *L64, typename St::L *Lstate) {
+    const int sub = threadIdx.x & (kRowLanes - 1);
+    const int64_t groups = (int64_t)gridDim.x * (blockDim.x / kRowLanes);
+    for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / kRowLanes) + threadIdx.x / kRowLanes;
+         u < N; u += groups) {
+        if (!flag[node_graph[u]]) continue;   // the whole 8-lane group skips together
+        const int64_t b = row_ptr[u], e = row_ptr[u + 1];
+        double acc = 0.0;
+        for (int64_t j = b + sub; j < e; j += kRowLanes)
+            acc = acc + recompute_term<St, false>(inc[j], edge_slot, slot_x, nullptr);
+        for (int d = kRowLanes / 2; d > 0; d >>= 1) acc = acc + __shfl_down(acc, d, kRowLanes);
+        if (sub == 0) {
+            L64[u] = acc;
+            Lstate[u] = St::from_f64(acc);
+        }
+    }
+}
+
+// flag[g] = 1 for the graphs order[0..*active), 0 for the others.  One
+// workgroup.
+constexpr int kMarkBlock = 1024;
+__global__ void __launch_bounds__(kMarkBlock)
+k_mark_active(int32_t G, const int32_t *active, const int32_t *order, uint8_t *flag) {
+    for (int32_t g = threadIdx.x; g < G; g += kMarkBlock) flag[g] = 0;
+    __syncthreads();
+    const int32_t A = *active;
+    for (int32_t i = threadIdx.x; i < A; i += kMarkBlock) flag[order[i]] = 1;
 }
 
 constexpr int kBigRowBlock = 256;
@@ -1008,9 +1037,14 @@ static void sweep_launchers(SweepLaunch &fn) {
         hipLaunchKernelGGL((k_batch_loads_f64<St>), dim3(grid_for(N, 256)), dim3(256), 0, s, N,
                            (const typename St::L *)Lstate, L64);
     };
-    fn.batch_loads_from_f64 = [](int64_t N, const double *L64, void *Lstate, hipStream_t s) {
-        hipLaunchKernelGGL((k_batch_loads_from_f64<St>), dim3(grid_for(N, 256)), dim3(256), 0, s,
-                           N, L64, (typename St::L *)Lstate);
+    fn.batch_recompute = [](int32_t G, int64_t N, const int32_t *active, const int32_t *order,
+                            const int32_t *node_graph, uint8_t *flag, const int64_t *row_ptr,
+                            const uint32_t *inc, const int64_t *edge_slot, const void *slot_x,
+                            double *L64, void *Lstate, hipStream_t s) {
+        hipLaunchKernelGGL(k_mark_active, dim3(1), dim3(kMarkBlock), 0, s, G, active, order, flag);
+        hipLaunchKernelGGL((k_batch_recompute<St>), dim3(grid_for(N * kRowLanes, 256)), dim3(256),
+                           0, s, N, node_graph, flag, row_ptr, inc, edge_slot,
+                           (const typename St::X *)slot_x, L64, (typename St::L *)Lstate);
     };
     fn.x_bytes = sizeof(typename St::X);
     fn.l_bytes = sizeof(typename St::L);

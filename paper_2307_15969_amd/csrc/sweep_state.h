@@ -185,7 +185,10 @@ struct SweepLaunch {
     void (*set_batch_lds)(int32_t shape, size_t bytes);
     void (*batch_init_loads)(int64_t N, const int32_t *deg, void *Lstate, hipStream_t s);
     void (*batch_loads_f64)(int64_t N, const void *Lstate, double *L64, hipStream_t s);
-    void (*batch_loads_from_f64)(int64_t N, const double *L64, void *Lstate, hipStream_t s);
+    void (*batch_recompute)(int32_t G, int64_t N, const int32_t *active, const int32_t *order,
+                            const int32_t *node_graph, uint8_t *flag, const int64_t *row_ptr,
+                            const uint32_t *inc, const int64_t *edge_slot, const void *slot_x,
+                            double *L64, void *Lstate, hipStream_t s);
     size_t x_bytes;
     size_t l_bytes;
 };
