@@ -412,7 +412,9 @@ lowd_status lowd_batch_iterate(lowd_batch *b, int32_t sweeps, void *stream);
  * the stored fractions, so that D_g is the bound of the fractions as stored
  * and not of the compensated loads the sweeps carry, and the carried loads
  * restart from them (a retired graph's fractions no longer change, and its
- * loads stay those of its last extraction).
+ * loads stay those of its last extraction).  Only the graphs still
+ * iterating are extracted again; every array is written for all graphs, a
+ * retired graph's entries being those of its last extraction.
  *   in_set  [device] uint8[total nodes] out
  *   num     [device] int64[G] out
  *   den     [device] int64[G] out

@@ -642,6 +642,20 @@ struct lowd_batch {
     Csr csr;
     DBuf<int64_t> edge_slot;
     DBuf<uint8_t> active_flag;   // [G]
+    // the graphs still iterating as the host last saw them (after a reset or
+    // a retire): count, each graph's index in that list (-1 if retired) and
+    // the compact node offsets of the listed graphs, for the extraction
+    std::vector<int32_t> order_all_h;
+    int32_t act_count = 0;
+    int64_t act_nodes = 0;
+    std::vector<int32_t> rank_h;
+    std::vector<int64_t> seg_h;
+    DBuf<int32_t> act_rank;
+    DBuf<int64_t> act_seg;
+    // every graph's latest extraction (retired graphs keep theirs)
+    DBuf<int64_t> r_num, r_den;
+    DBuf<double> r_D;
+    DBuf<uint8_t> r_in_set;
     BatchExtractScratch ex;
     size_t lds = 0;        // bytes of LDS per workgroup
     int32_t waves = 8;     // launch shape: waves per workgroup,
@@ -671,6 +685,28 @@ struct lowd_batch {
     ~lowd_batch() { drop_graph(); }
 };
 
+// The extraction's view of the graphs still iterating: act[0..A) as listed
+// on the device (b->order), their ranks and compact node offsets.
+static void set_active_list(lowd_batch *b, const int32_t *act, int32_t A, hipStream_t s) {
+    b->rank_h.assign((size_t)b->G, -1);
+    b->seg_h.assign((size_t)A + 1, 0);
+    for (int32_t k = 0; k < A; ++k) {
+        const int32_t g = act[k];
+        b->rank_h[(size_t)g] = k;
+        b->seg_h[(size_t)k + 1] = b->seg_h[(size_t)k] + (b->node_ptr_h[(size_t)g + 1] -
+                                                         b->node_ptr_h[(size_t)g]);
+    }
+    b->act_count = A;
+    b->act_nodes = b->seg_h[(size_t)A];
+    LOWD_HIP(hipMemcpyAsync(b->act_rank.p, b->rank_h.data(), b->rank_h.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s));
+    LOWD_HIP(hipMemcpyAsync(b->act_seg.p, b->seg_h.data(), b->seg_h.size() * sizeof(int64_t),
+                            hipMemcpyHostToDevice, s));
+    // the host vectors may change at the next reset or retire: let the
+    // copies finish first
+    LOWD_HIP(hipStreamSynchronize(s));
+}
+
 static void batch_reset(lowd_batch *b, hipStream_t s) {
     const int64_t nslots = (int64_t)(b->slot_leaf.n);
     if (b->M > 0) b->fn.init_slots(nslots, b->slot_edge.p, nullptr, b->slot_x.p, nullptr, s);
@@ -679,6 +715,7 @@ static void batch_reset(lowd_batch *b, hipStream_t s) {
                         b->active_edges.p, s);
     LOWD_HIP(hipGetLastError());
     b->last_active = b->G;
+    set_active_list(b, b->order_all_h.data(), b->G, s);
 }
 
 // One launch of the persistent kernel for `sweeps` sweeps, as a HIP graph
@@ -897,6 +934,17 @@ lowd_status lowd_batch_prepare(int32_t G, const int64_t *node_ptr, const int64_t
         upload(b->desc_ptr, desc_ptr, s);
         upload(b->slot_edge, slot_edge, s);
         upload(b->order_all, order, s);
+        b->order_all_h = order;
+        b->act_rank.alloc((size_t)G);
+        b->act_seg.alloc((size_t)G + 1);
+        b->r_num.alloc((size_t)G);
+        b->r_den.alloc((size_t)G);
+        b->r_D.alloc((size_t)G);
+        b->r_in_set.alloc((size_t)N);
+        LOWD_HIP(hipMemsetAsync(b->r_num.p, 0, b->r_num.bytes(), s));
+        LOWD_HIP(hipMemsetAsync(b->r_den.p, 0, b->r_den.bytes(), s));
+        LOWD_HIP(hipMemsetAsync(b->r_D.p, 0, b->r_D.bytes(), s));
+        LOWD_HIP(hipMemsetAsync(b->r_in_set.p, 0, b->r_in_set.bytes(), s));
         b->order.alloc((size_t)G);
         b->active.alloc(1);
         b->active_edges.alloc(1);
@@ -985,11 +1033,21 @@ lowd_status lowd_batch_extract(lowd_batch *b, uint8_t *in_set, int64_t *num, int
         a.gsrc = b->gsrc.p;
         a.gdst = b->gdst.p;
         a.L64 = b->L64.p;
-        a.in_set = in_set;
-        a.num = num;
-        a.den = den;
-        a.D = D;
+        a.A = b->act_count;
+        a.act = b->order.p;
+        a.seg = b->act_seg.p;
+        a.rank = b->act_rank.p;
+        a.Na = b->act_nodes;
+        a.in_set = b->r_in_set.p;
+        a.num = b->r_num.p;
+        a.den = b->r_den.p;
+        a.D = b->r_D.p;
         launch_extract_batch(a, b->ex, s);
+        const size_t gb = (size_t)b->G * 8;
+        LOWD_HIP(hipMemcpyAsync(num, b->r_num.p, gb, hipMemcpyDeviceToDevice, s));
+        LOWD_HIP(hipMemcpyAsync(den, b->r_den.p, gb, hipMemcpyDeviceToDevice, s));
+        if (D) LOWD_HIP(hipMemcpyAsync(D, b->r_D.p, gb, hipMemcpyDeviceToDevice, s));
+        LOWD_HIP(hipMemcpyAsync(in_set, b->r_in_set.p, (size_t)b->N, hipMemcpyDeviceToDevice, s));
         if (load)
             LOWD_HIP(hipMemcpyAsync(load, b->L64.p, (size_t)b->N * sizeof(double),
                                     hipMemcpyDeviceToDevice, s));
@@ -1015,6 +1073,11 @@ lowd_status lowd_batch_retire(lowd_batch *b, const int64_t *num, const int64_t *
         if (active) *active = a;
         if (active_edges) *active_edges = ae;
         b->last_active = a;
+        std::vector<int32_t> act((size_t)a);
+        if (a > 0)
+            LOWD_HIP(hipMemcpy(act.data(), b->order.p, (size_t)a * sizeof(int32_t),
+                               hipMemcpyDeviceToHost));
+        set_active_list(b, act.data(), a, s);
     });
 }
 

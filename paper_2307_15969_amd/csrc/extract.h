@@ -58,8 +58,9 @@ void launch_ldd(const ExtractArgs &a, ExtractScratch &sc, LddScratch &ls, int32_
                 int64_t *k_end, double *f_end, int64_t *nlevels, hipStream_t s);
 
 // Extraction for many unweighted graphs whose nodes and edges are
-// concatenated (global node ids); enqueued on the stream, scratch owned by
-// the caller.
+// concatenated (global node ids), over the A graphs act[0..A) (the graphs
+// still iterating; a retired graph's results do not change); enqueued on the
+// stream, scratch owned by the caller.
 struct BatchExtractScratch {
     int64_t cap_n = -1;
     int32_t cap_g = -1;
@@ -81,10 +82,15 @@ struct BatchExtractArgs {
     const int32_t *gsrc = nullptr;     // [M] global node ids
     const int32_t *gdst = nullptr;
     const double *L64 = nullptr;       // [N]
-    uint8_t *in_set = nullptr;         // [N] out
-    int64_t *num = nullptr;            // [G] out
+    int32_t A = 0;                     // graphs extracted
+    const int32_t *act = nullptr;      // [A] device: their ids
+    const int64_t *seg = nullptr;      // [A+1] device: compact node offsets (prefix of sizes)
+    const int32_t *rank = nullptr;     // [G] device: index in act, or -1
+    int64_t Na = 0;                    // seg[A]
+    uint8_t *in_set = nullptr;         // [N] out (the listed graphs' nodes)
+    int64_t *num = nullptr;            // [G] out (the listed graphs)
     int64_t *den = nullptr;            // [G] out
-    double *D = nullptr;               // [G] out: largest load per graph, or nullptr
+    double *D = nullptr;               // [G] out: largest load per graph
 };
 void launch_extract_batch(const BatchExtractArgs &a, BatchExtractScratch &sc, hipStream_t s);
 

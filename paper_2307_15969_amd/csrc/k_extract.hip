@@ -468,61 +468,83 @@ void launch_ldd(const ExtractArgs &a, ExtractScratch &sc, LddScratch &ls, int32_
 }  // namespace lowd
 
 // ------------------------------------------------ batched extraction -----
-// The same extraction for many graphs at once (unweighted): one stable sort
-// of all loads, then a stable sort by graph id, gives every graph's
-// ascending order as one contiguous segment; positions, the W(S_i) suffix
-// sums and the densest prefix are then taken per segment.
+// The same extraction for many graphs at once (unweighted), over the graphs
+// still iterating: act[k] (k < A) is the k-th of them, and its nodes take
+// the compact range seg[k] .. seg[k+1]-1.  One stable sort of their loads,
+// then a stable sort by k, gives every graph's ascending order as its
+// compact range; positions, the W(S_i) suffix sums and the densest prefix
+// are then taken per range.
 namespace lowd {
 namespace {
 
-__global__ void k_graph_keys(int64_t N, const uint32_t *vals, const int32_t *node_graph,
-                             uint32_t *keys2) {
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < N;
-         k += (int64_t)gridDim.x * blockDim.x)
-        keys2[k] = (uint32_t)node_graph[vals[k]];
+// one block per listed graph: its nodes' sort keys and ids, in compact order
+__global__ void k_keys_batch(int32_t A, const int32_t *act, const int64_t *seg,
+                             const int64_t *node_ptr, const double *L, uint64_t *keys,
+                             uint32_t *vals) {
+    for (int32_t k = blockIdx.x; k < A; k += gridDim.x) {
+        const int32_t g = act[k];
+        const int64_t u0 = node_ptr[g], c0 = seg[k];
+        const int64_t n = node_ptr[g + 1] - u0;
+        for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+            keys[c0 + j] = sortable(L[u0 + j]);
+            vals[c0 + j] = (uint32_t)(u0 + j);
+        }
+    }
 }
 
-// Positions in the batch's sorted order, which keeps each graph's nodes
-// together (graph g at node_ptr[g] .. node_ptr[g+1]-1): node u's position
-// within its graph is pos[u] - node_ptr[g].
-__global__ void k_batch_positions(int64_t N, const uint32_t *asc, int32_t *pos) {
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < N;
+__global__ void k_graph_keys(int64_t Na, const uint32_t *vals, const int32_t *node_graph,
+                             const int32_t *rank, uint32_t *keys2) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < Na;
+         k += (int64_t)gridDim.x * blockDim.x)
+        keys2[k] = (uint32_t)rank[node_graph[vals[k]]];
+}
+
+// Compact positions in the sorted order, which keeps each graph's nodes
+// together (the k-th listed graph at seg[k] .. seg[k+1]-1): node u's
+// position within its graph is pos[u] - seg[k].
+__global__ void k_batch_positions(int64_t Na, const uint32_t *asc, int32_t *pos) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < Na;
          k += (int64_t)gridDim.x * blockDim.x)
         pos[asc[k]] = (int32_t)k;
 }
 
-// Both ends of an edge are in one graph, so the smaller batch position is
-// the graph's offset plus the smaller position within the graph.
+// Both ends of an edge are in one graph, so the smaller compact position is
+// the graph's offset plus the smaller position within the graph.  Edges of
+// graphs not listed are skipped.
 __global__ void k_edge_min_pos_batch(int64_t M, const int32_t *gsrc, const int32_t *gdst,
+                                     const int32_t *node_graph, const int32_t *rank,
                                      const int32_t *pos, unsigned long long *hist) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < M;
          e += (int64_t)gridDim.x * blockDim.x) {
+        if (rank[node_graph[gsrc[e]]] < 0) continue;
         const int32_t a = pos[gsrc[e]], b = pos[gdst[e]];
         atomicAdd(&hist[a < b ? a : b], 1ull);
     }
 }
 
-// one block per graph: first index of maximal density W_g[i] / (n_g - i),
+// one block per listed graph: first index of maximal density W_g[i] / (n_g - i),
 // and the graph's largest load D_g (the dual bound of Section III-B)
-__global__ void __launch_bounds__(kArgBlock) k_best_batch(int32_t G, const int64_t *node_ptr,
-                                                          int64_t N, const int64_t *W,
-                                                          const double *L64, int64_t *best,
-                                                          int64_t *num, int64_t *den,
-                                                          double *D) {
+__global__ void __launch_bounds__(kArgBlock) k_best_batch(int32_t A, const int32_t *act,
+                                                          const int64_t *seg,
+                                                          const int64_t *node_ptr, int64_t Na,
+                                                          const int64_t *W, const double *L64,
+                                                          int64_t *best, int64_t *num,
+                                                          int64_t *den, double *D) {
     __shared__ int64_t lds_i[kArgBlock];
     __shared__ int64_t lds_w[kArgBlock];
     __shared__ double lds_d[kArgBlock];
-    const int32_t g = blockIdx.x;
-    const int64_t start = node_ptr[g], end = node_ptr[g + 1];
-    const int64_t n = end - start;
-    const int64_t tail = end < N ? W[end] : 0;
+    const int32_t k = blockIdx.x;
+    const int32_t g = act[k];
+    const int64_t start = seg[k], end = seg[k + 1];
+    const int64_t n = end - start, u0 = node_ptr[g];
+    const int64_t tail = end < Na ? W[end] : 0;
     int64_t bi = -1, bw = 0;
     double dmax = -1.0e308;
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
         const int64_t wi = W[start + i] - tail;
         // wi / (n - i) > bw / (n - bi), exact in int64
         if (bi < 0 || wi * (n - bi) > bw * (n - i)) { bi = i; bw = wi; }
-        const double l = L64[start + i];
+        const double l = L64[u0 + i];
         dmax = l > dmax ? l : dmax;
     }
     lds_i[threadIdx.x] = bi;
@@ -547,26 +569,28 @@ __global__ void __launch_bounds__(kArgBlock) k_best_batch(int32_t G, const int64
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        best[g] = lds_i[0];
+        best[k] = lds_i[0];
         num[g] = lds_w[0];
         den[g] = n - lds_i[0];
-        if (D) D[g] = lds_d[0];
+        D[g] = lds_d[0];
     }
 }
 
-// One workgroup per graph: each edge's smaller position is counted in LDS
-// (a graph's nodes fit one workgroup's LDS), then the graph's bins are
+// One workgroup per listed graph: each edge's smaller position is counted in
+// LDS (a graph's nodes fit one workgroup's LDS), then the graph's bins are
 // written out.  Counts are integers, so the order of the additions does not
-// matter.  Writes every bin of hist.
+// matter.  Writes every bin of hist[0 .. seg[A]).
 constexpr int kGraphHistBlock = 256;
 constexpr size_t kGraphHistLds = 160 * 1024;   // a CU's LDS
 __global__ void __launch_bounds__(kGraphHistBlock)
-k_edge_min_pos_graph(const int64_t *node_ptr, const int64_t *edge_ptr, const int32_t *gsrc,
-                     const int32_t *gdst, const int32_t *pos, unsigned long long *hist) {
+k_edge_min_pos_graph(const int32_t *act, const int64_t *seg, const int64_t *edge_ptr,
+                     const int32_t *gsrc, const int32_t *gdst, const int32_t *pos,
+                     unsigned long long *hist) {
     extern __shared__ uint32_t hbin[];
-    const int32_t g = (int32_t)blockIdx.x;
-    const int64_t base = node_ptr[g];
-    const int32_t n = (int32_t)(node_ptr[g + 1] - base);
+    const int32_t k = (int32_t)blockIdx.x;
+    const int32_t g = act[k];
+    const int64_t base = seg[k];
+    const int32_t n = (int32_t)(seg[k + 1] - base);
     for (int32_t i = threadIdx.x; i < n; i += kGraphHistBlock) hbin[i] = 0u;
     __syncthreads();
     const int64_t e1 = edge_ptr[g + 1];
@@ -578,12 +602,15 @@ k_edge_min_pos_graph(const int64_t *node_ptr, const int64_t *edge_ptr, const int
     for (int32_t i = threadIdx.x; i < n; i += kGraphHistBlock) hist[base + i] = hbin[i];
 }
 
-__global__ void k_in_set_batch(int64_t N, const int32_t *pos, const int32_t *node_graph,
-                               const int64_t *node_ptr, const int64_t *best, uint8_t *in_set) {
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < N;
-         u += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t g = node_graph[u];
-        in_set[u] = (int64_t)pos[u] - node_ptr[g] >= best[g] ? 1 : 0;
+// one block per listed graph: its nodes' membership in its densest prefix
+__global__ void k_in_set_batch(int32_t A, const int32_t *act, const int64_t *seg,
+                               const int64_t *node_ptr, const int32_t *pos, const int64_t *best,
+                               uint8_t *in_set) {
+    for (int32_t k = blockIdx.x; k < A; k += gridDim.x) {
+        const int32_t g = act[k];
+        const int64_t u0 = node_ptr[g], n = node_ptr[g + 1] - u0, c0 = seg[k], bk = best[k];
+        for (int64_t j = threadIdx.x; j < n; j += blockDim.x)
+            in_set[u0 + j] = (int64_t)pos[u0 + j] - c0 >= bk ? 1 : 0;
     }
 }
 
@@ -610,44 +637,49 @@ void BatchExtractScratch::ensure(int64_t N, int32_t G) {
 }
 
 void launch_extract_batch(const BatchExtractArgs &a, BatchExtractScratch &sc, hipStream_t s) {
-    const int64_t N = a.N;
+    const int64_t Na = a.Na;
+    if (a.A <= 0 || Na <= 0) return;
     int gbits = 1;
-    while (gbits < 31 && ((int64_t)1 << gbits) < (int64_t)a.G) ++gbits;
-    sc.ensure(N, a.G);
-    const unsigned gn = grid_for(N, 256);
-    hipLaunchKernelGGL(k_keys, dim3(gn), dim3(256), 0, s, (int32_t)N, a.L64, sc.k0.p, sc.v0.p);
+    while (gbits < 31 && ((int64_t)1 << gbits) < (int64_t)a.A) ++gbits;
+    sc.ensure(a.N, a.G);
+    const unsigned gn = grid_for(Na, 256);
+    const unsigned ga = (unsigned)(a.A < 65535 ? a.A : 65535);
+    hipLaunchKernelGGL(k_keys_batch, dim3(ga), dim3(256), 0, s, a.A, a.act, a.seg, a.node_ptr,
+                       a.L64, sc.k0.p, sc.v0.p);
     bool alt = false;
-    radix_sort_u64(sc.k0.p, sc.v0.p, sc.k1.p, sc.v1.p, N, 64, sc.tmp.p, sc.tmp.bytes(), &alt, s);
+    radix_sort_u64(sc.k0.p, sc.v0.p, sc.k1.p, sc.v1.p, Na, 64, sc.tmp.p, sc.tmp.bytes(), &alt, s);
     uint32_t *vals = alt ? sc.v1.p : sc.v0.p;
     uint32_t *vals_alt = alt ? sc.v0.p : sc.v1.p;
-    hipLaunchKernelGGL(k_graph_keys, dim3(gn), dim3(256), 0, s, N, vals, a.node_graph, sc.g0.p);
+    hipLaunchKernelGGL(k_graph_keys, dim3(gn), dim3(256), 0, s, Na, vals, a.node_graph, a.rank,
+                       sc.g0.p);
     bool alt2 = false;
-    radix_sort_u32(sc.g0.p, vals, sc.g1.p, vals_alt, N, gbits, sc.tmp.p, sc.tmp.bytes(), &alt2, s);
+    radix_sort_u32(sc.g0.p, vals, sc.g1.p, vals_alt, Na, gbits, sc.tmp.p, sc.tmp.bytes(), &alt2, s);
     const uint32_t *asc = alt2 ? vals_alt : vals;
-    hipLaunchKernelGGL(k_batch_positions, dim3(gn), dim3(256), 0, s, N, asc, sc.pos.p);
+    hipLaunchKernelGGL(k_batch_positions, dim3(gn), dim3(256), 0, s, Na, asc, sc.pos.p);
     const size_t hist_lds = (size_t)a.max_nodes * sizeof(uint32_t);
     if (a.edge_ptr && a.max_nodes > 0 && hist_lds <= kGraphHistLds) {
         if (hist_lds > 64 * 1024)
             LOWD_HIP(hipFuncSetAttribute((const void *)k_edge_min_pos_graph,
                                          hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)hist_lds));
-        hipLaunchKernelGGL(k_edge_min_pos_graph, dim3((unsigned)a.G), dim3(kGraphHistBlock),
-                           hist_lds, s, a.node_ptr, a.edge_ptr, a.gsrc, a.gdst, sc.pos.p,
+        hipLaunchKernelGGL(k_edge_min_pos_graph, dim3((unsigned)a.A), dim3(kGraphHistBlock),
+                           hist_lds, s, a.act, a.seg, a.edge_ptr, a.gsrc, a.gdst, sc.pos.p,
                            (unsigned long long *)sc.hist.p);
     } else {
-        hipLaunchKernelGGL(k_fill_i64, dim3(gn), dim3(256), 0, s, N, sc.hist.p);
+        hipLaunchKernelGGL(k_fill_i64, dim3(gn), dim3(256), 0, s, Na, sc.hist.p);
         if (a.M > 0)
             hipLaunchKernelGGL(k_edge_min_pos_batch, dim3(grid_for(a.M, 256)), dim3(256), 0, s,
-                               a.M, a.gsrc, a.gdst, sc.pos.p, (unsigned long long *)sc.hist.p);
+                               a.M, a.gsrc, a.gdst, a.node_graph, a.rank, sc.pos.p,
+                               (unsigned long long *)sc.hist.p);
     }
-    hipLaunchKernelGGL(k_reverse<int64_t>, dim3(gn), dim3(256), 0, s, N, sc.hist.p, sc.rev.p);
-    exclusive_scan_i64(sc.rev.p, sc.rev.p, N, nullptr, sc.tmp.p, sc.tmp.bytes(), s);
-    hipLaunchKernelGGL(k_suffix<int64_t>, dim3(gn), dim3(256), 0, s, N, sc.rev.p, sc.hist.p,
+    hipLaunchKernelGGL(k_reverse<int64_t>, dim3(gn), dim3(256), 0, s, Na, sc.hist.p, sc.rev.p);
+    exclusive_scan_i64(sc.rev.p, sc.rev.p, Na, nullptr, sc.tmp.p, sc.tmp.bytes(), s);
+    hipLaunchKernelGGL(k_suffix<int64_t>, dim3(gn), dim3(256), 0, s, Na, sc.rev.p, sc.hist.p,
                        sc.W.p);
-    hipLaunchKernelGGL(k_best_batch, dim3((unsigned)a.G), dim3(kArgBlock), 0, s, a.G, a.node_ptr,
-                       N, sc.W.p, a.L64, sc.best.p, a.num, a.den, a.D);
-    hipLaunchKernelGGL(k_in_set_batch, dim3(gn), dim3(256), 0, s, N, sc.pos.p, a.node_graph,
-                       a.node_ptr, sc.best.p, a.in_set);
+    hipLaunchKernelGGL(k_best_batch, dim3((unsigned)a.A), dim3(kArgBlock), 0, s, a.A, a.act,
+                       a.seg, a.node_ptr, Na, sc.W.p, a.L64, sc.best.p, a.num, a.den, a.D);
+    hipLaunchKernelGGL(k_in_set_batch, dim3(ga), dim3(256), 0, s, a.A, a.act, a.seg, a.node_ptr,
+                       sc.pos.p, sc.best.p, a.in_set);
     LOWD_HIP(hipGetLastError());
 }
 
