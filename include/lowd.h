@@ -394,7 +394,8 @@ lowd_status lowd_batch_prepare(int32_t G, const int64_t *node_ptr, const int64_t
                                const int32_t *src, const int32_t *dst, int32_t state,
                                int32_t star_max, int32_t tune, lowd_batch **out, void *stream);
 
-/* lowd_batch_reset -- back to Algorithm 1's initial state.  Asynchronous. */
+/* lowd_batch_reset -- back to Algorithm 1's initial state, every graph
+ * iterating again.  Synchronises `stream`. */
 lowd_status lowd_batch_reset(lowd_batch *b, void *stream);
 
 /*

@@ -762,10 +762,11 @@ __global__ void __launch_bounds__(256) k_recompute(int32_t n, const int64_t *row
     }
 }
 
-// Batches (unit weights): the same sums for the nodes of the graphs still
-// iterating (flag[node_graph[u]] set, see k_mark_active), 8 lanes per node
-// over all nodes; written to L64 and, rounded to the state's load type, as
-// the carried loads.  Retired graphs keep both from their last pass: their
+// Batches (unit weights): the same per-node sums for the nodes of the
+// graphs still iterating (flag[node_graph[u]] set, see k_mark_active), 8
+// lanes per node for every row (a batch's graphs have no long rows to speak
+// of); written to L64 and, rounded to the state's load type, as the carried
+// loads.  Retired graphs keep both from their last pass: their
 // fractions no longer change.
 template <class St>
 __global__ void __launch_bounds__(256)
