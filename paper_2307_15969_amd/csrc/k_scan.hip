@@ -116,19 +116,29 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_apply(const T *in, T *out, 
 
 
 // ------------------------------------------------------------ radix sort --
+// A block sorts a chunk of `tiles` tiles of 256 keys per pass.  The chunk
+// is sized to the input so that about kRadixTargetBlocks blocks share it
+// (a fixed 64-tile chunk left 1M keys to 64 blocks on 256 CUs), at most
+// kRadixMaxTiles tiles: larger inputs get more blocks instead.
 constexpr int kRadixBlock = 256;
-constexpr int kRadixTiles = 64;                       // tiles of 256 keys per block
-constexpr int64_t kRadixChunk = (int64_t)kRadixBlock * kRadixTiles;
+constexpr int64_t kRadixMaxTiles = 64;
+constexpr int64_t kRadixTargetBlocks = 1024;
 constexpr int kDigits = 256;
+inline int64_t radix_tiles(int64_t n) {
+    const int64_t per = kRadixTargetBlocks * kRadixBlock;
+    const int64_t t = (n + per - 1) / per;
+    return t < 1 ? 1 : (t > kRadixMaxTiles ? kRadixMaxTiles : t);
+}
 
 template <class K>
 __global__ void __launch_bounds__(kRadixBlock) k_radix_hist(const K *keys, int64_t n, int shift,
-                                                            int64_t *blockhist, int64_t nb) {
+                                                            int64_t *blockhist, int64_t nb,
+                                                            int64_t chunk) {
     __shared__ uint32_t h[kDigits];
     h[threadIdx.x] = 0;
     __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * kRadixChunk;
-    int64_t end = base + kRadixChunk < n ? base + kRadixChunk : n;
+    int64_t base = (int64_t)blockIdx.x * chunk;
+    int64_t end = base + chunk < n ? base + chunk : n;
     for (int64_t i = base + threadIdx.x; i < end; i += kRadixBlock) {
         uint32_t d = (uint32_t)(keys[i] >> shift) & (kDigits - 1);
         atomicAdd(&h[d], 1u);
@@ -142,7 +152,7 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter(const K *keys, co
                                                                K *keys_out, uint32_t *vals_out,
                                                                int64_t n, int shift,
                                                                const int64_t *offsets,
-                                                               int64_t nb) {
+                                                               int64_t nb, int64_t tiles) {
     constexpr int kWaves = kRadixBlock / kWave;
     __shared__ int64_t running[kDigits];
     __shared__ int32_t wave_cnt[kWaves][kDigits];
@@ -151,8 +161,8 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter(const K *keys, co
     const int wave = threadIdx.x / kWave;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     running[threadIdx.x] = offsets[(int64_t)threadIdx.x * nb + blockIdx.x];
-    int64_t base = (int64_t)blockIdx.x * kRadixChunk;
-    for (int t = 0; t < kRadixTiles; ++t) {
+    int64_t base = (int64_t)blockIdx.x * tiles * kRadixBlock;
+    for (int64_t t = 0; t < tiles; ++t) {
         int64_t tile0 = base + (int64_t)t * kRadixBlock;
         if (tile0 >= n) break;                       // uniform across the block
         int64_t i = tile0 + threadIdx.x;
@@ -199,7 +209,8 @@ void radix_sort_impl(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, i
                      void *tmp, size_t tmp_bytes, bool *result_in_alt, hipStream_t s) {
     *result_in_alt = false;
     if (n <= 1 || bits <= 0) return;
-    int64_t nb = cdiv(n, kRadixChunk);
+    const int64_t tiles = radix_tiles(n), chunk = tiles * kRadixBlock;
+    int64_t nb = cdiv(n, chunk);
     int64_t nh = nb * kDigits;
     if (tmp_bytes < radix_sort_tmp_bytes(n)) fail(LOWD_E_ARG, "radix sort scratch too small");
     int64_t *hist = (int64_t *)tmp;
@@ -210,10 +221,10 @@ void radix_sort_impl(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, i
     bool in_alt = false;
     for (int shift = 0; shift < bits; shift += 8) {
         hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)nb), dim3(kRadixBlock), 0, s, kin, n,
-                           shift, hist, nb);
+                           shift, hist, nb, chunk);
         exclusive_scan_i64(hist, hist, nh, nullptr, scan_tmp, scan_bytes, s);
         hipLaunchKernelGGL(k_radix_scatter<K>, dim3((unsigned)nb), dim3(kRadixBlock), 0, s, kin,
-                           vin, kout, vout, n, shift, hist, nb);
+                           vin, kout, vout, n, shift, hist, nb, tiles);
         LOWD_HIP(hipGetLastError());
         std::swap(kin, kout);
         std::swap(vin, vout);
@@ -258,7 +269,13 @@ void exclusive_scan_f64(const double *in, double *out, int64_t n, double *total_
 }
 
 size_t radix_sort_tmp_bytes(int64_t n) {
-    int64_t nb = cdiv(n > 0 ? n : 1, kRadixChunk);
+    // enough for every n' <= n: below the tile cap a sort uses at most
+    // min(kRadixTargetBlocks, n' / 256) blocks, at the cap n' / (64 * 256)
+    const int64_t m = n > 0 ? n : 1;
+    const int64_t small = cdiv(m, kRadixBlock) < kRadixTargetBlocks ? cdiv(m, kRadixBlock)
+                                                                    : kRadixTargetBlocks;
+    const int64_t big = cdiv(m, kRadixMaxTiles * kRadixBlock);
+    const int64_t nb = small > big ? small : big;
     int64_t nh = nb * kDigits;
     return (size_t)nh * sizeof(int64_t) + exclusive_scan_tmp_bytes(nh);
 }
