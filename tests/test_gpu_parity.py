@@ -170,6 +170,24 @@ def test_extraction_matches_oracle(name, g, T):
             assert abs(ex["num_w"] - ro["num_w"]) <= 1e-12 * ro["num_w"]
 
 
+@pytest.mark.parametrize("T", [0, 2])
+def test_extraction_with_several_sort_tiles_per_block(T):
+    """300,001 nodes: the radix sort's blocks take two tiles each and the
+    last block is partial; at T = 0 the loads are degree / 2, so many keys
+    tie and the order among them is by node id.  Set and exact density equal
+    the oracle's."""
+    g = synth.chung_lu(300001, 1200000, 2.3, seed=9)
+    log(f"n={g.n} m={g.m} T={T}")
+    sv = lowd.Solver(g.n, g.src, g.dst, None, "f64")
+    sv.iterate(T)
+    ex = sv.extract()
+    _, Lo, *_ = oracle_run(g, T, 16)
+    ro = oracle.extract(g.n, g.src, g.dst, None, Lo)
+    assert (ex["num"], ex["den"]) == (ro["num"], ro["den"])
+    assert np.array_equal(ex["in_set"].cpu().numpy(), ro["in_set"])
+    sv.close()
+
+
 def test_workload0_reaches_the_maxflow_optimum():
     """200 sweeps on ER(1000, 5000) + K_30: the densest set and its exact
     density equal the oracle's, which max-flow certifies in the CPU pins."""
@@ -694,6 +712,48 @@ def test_batch_f32k_within_tolerance():
         xo, Lo, *_ = oracle_run(g, T, 16)
         if g.m:
             assert np.max(np.abs(L[a:b] - Lo)) <= 1e-5 * np.max(np.abs(Lo)), i
+
+
+def test_batch_with_several_sort_tiles_per_block():
+    """About 275k nodes over 300 graphs: the batched extraction's sorts take
+    two tiles per block.  Every graph's densest set and exact density equal
+    its own oracle run; after a retire, the next extraction leaves the
+    retired graphs' results as they were and gives the others' at 2T."""
+    gs = synth.batch_of_graphs(300, seed=29, m_lo=2000, m_hi=6000)
+    N = sum(g.n for g in gs)
+    log(f"{len(gs)} graphs, N={N}")
+    assert N > 1024 * 256
+    T, tol = 4, 1e-2
+    b = lowd.Batch(gs, "f64")
+    b.iterate(T)
+    b.extract()
+    num, den = b.num.cpu().numpy().copy(), b.den.cpu().numpy().copy()
+    ins = b.in_set.cpu().numpy().copy()
+    for i, g in enumerate(gs):
+        a, c = b.node_ptr[i], b.node_ptr[i + 1]
+        _, Lo, *_ = oracle_run(g, T, 16)
+        ro = oracle.extract(g.n, g.src, g.dst, None, Lo)
+        assert (num[i], den[i]) == (ro["num"], ro["den"]), i
+        assert np.array_equal(ins[a:c], ro["in_set"]), i
+    retired = b.gaps() <= tol
+    active, _ = b.retire(tol)
+    log(f"retired {int(retired.sum())}, active {active}")
+    assert active == int((~retired).sum()) and 0 < active < len(gs)
+    b.iterate(T)
+    b.extract()
+    num2, den2 = b.num.cpu().numpy(), b.den.cpu().numpy()
+    ins2 = b.in_set.cpu().numpy()
+    for i, g in enumerate(gs):
+        a, c = b.node_ptr[i], b.node_ptr[i + 1]
+        if retired[i]:
+            assert (num2[i], den2[i]) == (num[i], den[i]), i
+            assert np.array_equal(ins2[a:c], ins[a:c]), i
+        else:
+            _, Lo, *_ = oracle_run(g, 2 * T, 16)
+            ro = oracle.extract(g.n, g.src, g.dst, None, Lo)
+            assert (num2[i], den2[i]) == (ro["num"], ro["den"]), i
+            assert np.array_equal(ins2[a:c], ro["in_set"]), i
+    b.close()
 
 
 def test_prepared_batch_in_steps_equals_oracle():
