@@ -6,7 +6,8 @@
 // Radix sort: 8-bit digits; per block an LDS digit histogram, one global
 // exclusive scan of the digit-major block histograms, then a stable scatter
 // in which every wavefront ranks its keys among equal digits with eight
-// ballots (the lanes whose digit matches in all eight bits).
+// ballots (the lanes whose digit matches in all eight bits).  Large inputs
+// stage the ranked keys in LDS and write each digit's run contiguously.
 #include <utility>
 
 #include "lowd_internal.h"
@@ -147,8 +148,115 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_hist(const K *keys, int64
     blockhist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
+// The scatter stages rounds of kRadixRound keys in LDS in digit order, then
+// writes every digit's run of the round to consecutive addresses: a tile's
+// 256 keys written straight out land on up to 256 scattered lines, a round's
+// runs average 16 keys per digit.  Ranks are taken tile by tile in key order
+// (wave ballots for equal digits, waves in order), so the permutation is the
+// stable one.
+constexpr int kRadixRoundTiles = 16;
+constexpr int kRadixRound = kRadixRoundTiles * kRadixBlock;   // keys staged at a time
+
 template <class K>
-__global__ void __launch_bounds__(kRadixBlock) k_radix_scatter(const K *keys, const uint32_t *vals,
+__global__ void __launch_bounds__(kRadixBlock) k_radix_scatter_staged(const K *keys, const uint32_t *vals,
+                                                               K *keys_out, uint32_t *vals_out,
+                                                               int64_t n, int shift,
+                                                               const int64_t *offsets,
+                                                               int64_t nb, int64_t tiles) {
+    constexpr int kWaves = kRadixBlock / kWave;
+    __shared__ int64_t running[kDigits];         // next global position of each digit
+    __shared__ int64_t scan_lds[kWave + 1];
+    __shared__ uint32_t cnt[kDigits];            // this round's keys per digit
+    __shared__ uint32_t start[kDigits];          // their first local position
+    __shared__ uint32_t next[kDigits];           // next free local position
+    __shared__ uint32_t wave_cnt[kWaves][kDigits];
+    __shared__ uint32_t wave_off[kWaves][kDigits];
+    __shared__ K skey[kRadixRound];
+    __shared__ uint32_t sval[kRadixRound];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid / kWave;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    running[tid] = offsets[(int64_t)tid * nb + blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * tiles * kRadixBlock;
+    const int64_t end = base + tiles * kRadixBlock < n ? base + tiles * kRadixBlock : n;
+    for (int64_t r0 = base; r0 < end; r0 += kRadixRound) {   // uniform across the block
+        const int64_t r1 = r0 + kRadixRound < end ? r0 + kRadixRound : end;
+        // the round's keys, one per thread per tile, and its digit counts
+        K kreg[kRadixRoundTiles];
+        uint32_t vreg[kRadixRoundTiles];
+        cnt[tid] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < kRadixRoundTiles; ++t) {
+            const int64_t i = r0 + (int64_t)t * kRadixBlock + tid;
+            kreg[t] = i < r1 ? keys[i] : (K)0;
+            vreg[t] = i < r1 ? vals[i] : 0u;
+            if (i < r1) atomicAdd(&cnt[(uint32_t)(kreg[t] >> shift) & (kDigits - 1)], 1u);
+        }
+        __syncthreads();
+        {
+            int64_t tot;
+            const int64_t st = block_exclusive_scan<int64_t>((int64_t)cnt[tid], scan_lds, &tot);
+            start[tid] = (uint32_t)st;
+            next[tid] = (uint32_t)st;
+        }
+        __syncthreads();
+        // local positions in digit order, tile by tile
+#pragma unroll
+        for (int t = 0; t < kRadixRoundTiles; ++t) {
+            const int64_t i = r0 + (int64_t)t * kRadixBlock + tid;
+            if (r0 + (int64_t)t * kRadixBlock >= r1) break;   // uniform across the block
+            const bool valid = i < r1;
+            const uint32_t d = (uint32_t)(kreg[t] >> shift) & (kDigits - 1);
+            for (int k = 0; k < kWaves; ++k) wave_cnt[k][tid] = 0;
+            uint64_t same = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t ones = __ballot(valid && bit);
+                same &= bit ? ones : ~ones;
+            }
+            const int rank = __popcll(same & lt_mask);
+            __syncthreads();
+            if (valid && rank == 0) wave_cnt[wave][d] = __popcll(same);
+            __syncthreads();
+            {   // one thread per digit: each wave's first position, in wave order
+                uint32_t r = next[tid];
+                for (int k = 0; k < kWaves; ++k) {
+                    wave_off[k][tid] = r;
+                    r += wave_cnt[k][tid];
+                }
+                next[tid] = r;
+            }
+            __syncthreads();
+            if (valid) {
+                const uint32_t p = wave_off[wave][d] + (uint32_t)rank;
+                skey[p] = kreg[t];
+                sval[p] = vreg[t];
+            }
+        }
+        __syncthreads();
+        // every digit's run to consecutive global positions
+        const int64_t m = r1 - r0;
+        for (int64_t j = tid; j < m; j += kRadixBlock) {
+            const K key = skey[j];
+            const uint32_t d = (uint32_t)(key >> shift) & (kDigits - 1);
+            const int64_t dst = running[d] + (j - (int64_t)start[d]);
+            keys_out[dst] = key;
+            vals_out[dst] = sval[j];
+        }
+        __syncthreads();
+        running[tid] += cnt[tid];
+        __syncthreads();
+    }
+}
+
+// Per-tile scatter: every tile's keys go straight to their places.  Used
+// below kRadixStagedTiles tiles per block, where the staged kernel's LDS
+// (two blocks per CU) costs more than its coalescing gains.
+template <class K>
+__global__ void __launch_bounds__(kRadixBlock) k_radix_scatter_tiles(const K *keys, const uint32_t *vals,
                                                                K *keys_out, uint32_t *vals_out,
                                                                int64_t n, int shift,
                                                                const int64_t *offsets,
@@ -202,6 +310,8 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter(const K *keys, co
     }
 }
 
+constexpr int64_t kRadixStagedTiles = 32;
+
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 template <class K>
@@ -223,8 +333,12 @@ void radix_sort_impl(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, i
         hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)nb), dim3(kRadixBlock), 0, s, kin, n,
                            shift, hist, nb, chunk);
         exclusive_scan_i64(hist, hist, nh, nullptr, scan_tmp, scan_bytes, s);
-        hipLaunchKernelGGL(k_radix_scatter<K>, dim3((unsigned)nb), dim3(kRadixBlock), 0, s, kin,
-                           vin, kout, vout, n, shift, hist, nb, tiles);
+        if (tiles >= kRadixStagedTiles)
+            hipLaunchKernelGGL(k_radix_scatter_staged<K>, dim3((unsigned)nb), dim3(kRadixBlock), 0,
+                               s, kin, vin, kout, vout, n, shift, hist, nb, tiles);
+        else
+            hipLaunchKernelGGL(k_radix_scatter_tiles<K>, dim3((unsigned)nb), dim3(kRadixBlock), 0,
+                               s, kin, vin, kout, vout, n, shift, hist, nb, tiles);
         LOWD_HIP(hipGetLastError());
         std::swap(kin, kout);
         std::swap(vin, vout);

@@ -333,6 +333,21 @@ def test_prune_matches_oracle(name, g):
     assert np.array_equal(r["dst"].cpu().numpy(), relabel[g.dst[ek]])
 
 
+def test_prune_with_sorts_large_enough_to_stage():
+    """R-MAT scale 19 (about 7M edges): the incidence sort (14M keys) takes
+    the radix sort's LDS-staged scatter, the pair sort of the validation the
+    per-tile one; the pruned graph equals the oracle's."""
+    g = synth.rmat(19, 16, seed=5)
+    log(f"n={g.n} m={g.m}")
+    assert 2 * g.m > 32 * 1024 * 256
+    r = lowd.prune(g.n, g.src, g.dst)
+    keep, rounds, nh, mh = oracle.prune(g.n, g.src, g.dst)
+    assert np.array_equal(r["node_keep"].cpu().numpy(), keep)
+    assert (r["rounds"], r["n_h"], r["m_h"]) == (rounds, nh, mh)
+    ek = (keep[g.src] == 1) & (keep[g.dst] == 1)
+    assert np.array_equal(r["edge_map"].cpu().numpy(), np.flatnonzero(ek))
+
+
 def test_prune_then_solve_finds_the_densest_set_of_g():
     g = synth.workload(0)
     r = lowd.prune(g.n, g.src, g.dst)
