@@ -414,6 +414,19 @@ def test_degenerate_graphs_for_every_entry_point():
             assert np.array_equal(p_["node_keep"].cpu().numpy(), ko)
             assert (p_["n_h"], p_["m_h"]) == (nh, mh)
         sv.close()
+    # the kept-load calls and the resync, in both states
+    for g in (empty, one, edge):
+        for state in ("f64", "f32k"):
+            sv = lowd.Solver(g.n, g.src, g.dst, None, state)
+            sv.iterate(3)
+            assert sv.check(kept=True) == sv.check()
+            ek, e = sv.extract(kept=True), sv.extract()
+            assert (ek["num"], ek["den"], ek["D"]) == (e["num"], e["den"], e["D"])
+            sv.resync()
+            assert sv.check() == sv.check(kept=True)
+            r = lowd.solve(g.n, g.src, g.dst, None, state)
+            assert r["gap"] <= 1e-6 and (r["num"], r["den"]) == (e["num"], e["den"])
+            sv.close()
     # the single edge: one level of density 1/2, then the isolated nodes at 0
     sv = lowd.Solver(edge.n, edge.src, edge.dst, None, "f64")
     sv.iterate(2)
