@@ -386,8 +386,10 @@ def batch_solves(gs, state, args, torch, lowd, stream):
     solves after args.warmup untimed ones.  Each solve: reset; then sweep the
     graphs still above the tolerance, k sweeps a launch, extract and retire,
     until every graph is within it.  Once fewer than an eighth of the graphs
-    remain, k doubles after each check (up to 16 K): the few slow graphs then
-    cost a check far more than a sweep."""
+    remain, k doubles after each check, up to 8 K (FP64) or 4 K (FP32K): the
+    few slow graphs then cost a check more than a sweep, but a longer launch
+    overshoots their convergence, and for FP32K lets the carried loads drift
+    further from the fractions' loads between two restarts."""
     M = sum(g.m for g in gs)
     t0 = time.perf_counter()
     b = lowd.Batch(gs, state, tune=True, stream=stream)
@@ -406,7 +408,7 @@ def batch_solves(gs, state, args, torch, lowd, stream):
         k = K
         while active > 0:
             if active * 8 < len(gs):
-                k = min(2 * k, 16 * K)
+                k = min(2 * k, (4 if state == "f32k" else 8) * K)
             ev_a.record(stream)
             b.iterate(k, stream)
             ev_b.record(stream)
