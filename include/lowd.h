@@ -40,7 +40,7 @@ typedef int32_t lowd_status;
 #define LOWD_E_ARG (-1)         /* bad pointer, size or option */
 #define LOWD_E_GRAPH (-2)       /* id out of range, self-loop, repeated pair, bad weight */
 #define LOWD_E_HIP (-4)         /* a HIP runtime call failed */
-#define LOWD_E_UNSUPPORTED (-5) /* valid request this build does not implement */
+#define LOWD_E_UNSUPPORTED (-5) /* valid request beyond a documented limit (e.g. a batch graph larger than one workgroup's LDS) */
 #define LOWD_E_NOMEM (-6)       /* host or device allocation failed */
 
 /* Precision of the solver state (edge fractions and node loads). */
