@@ -1,24 +1,27 @@
-"""Benchmark: LOWD on the Chung-Lu power-law workload (n = 1M nodes, ~10M
-unit-weight edges, degree exponent 2.1, a planted 500-node block of pair
-density 0.3), FP64 state, no pruning, solved to a 1e-6 relative density
-gap.  Other workloads (--workload): chunglu4m (4M nodes, 64M lognormal
-edges, FP32 + compensated loads against FP64), rmat24 (R-MAT scale 24,
-pruned by Algorithm 2, then LOWD on the pruned graph) and batch4096 (4096
-small graphs in the batched form, converged graphs retired).
+"""Benchmark: LOWD on R-MAT scale 24 (16.8M nodes, edge factor 16, quadrant
+probabilities .57/.19/.19/.05, ~260M unit edges after symmetrising and
+de-duplication), pruned by Algorithm 2, then solved on the pruned graph H to a
+1e-6 relative density gap: FP64 in `value`, the FP32 + compensated-load state
+beside it.  Other workloads (--workload): chunglu1m (1M nodes, ~10M unit
+edges, FP64, no pruning), chunglu4m (4M nodes, ~64M lognormal edges, FP32K
+against FP64), batch4096 (4096 small graphs in the batched form) and uniform
+(a wide-phase diagnostic of the sweep, not a paper workload).
 
-One step = one whole solve on the GPU from Algorithm 1's initial state:
-reset the fractions and loads, then sweep (the phase schedule is built once
-per graph, before timing), checking every few sweeps with the extraction
-(sort, prefix densities) and the dual bound D = max load, until
-(D - rho) / rho <= 1e-6.  The inputs are resident in HBM before timing.
+One step = the hot path once, on inputs resident in HBM: Algorithm 2's prune
+of G (where the workload prunes), then a solve of H from Algorithm 1's
+initial state (reset of fractions and loads, sweeps, checks with the dual
+bound D and the extraction) through lowd_solve until (D - rho) / rho <= 1e-6.
+The phase schedule is built once per graph, before timing (setup_s).
 
-Printed: one JSON line with edge-updates/s over the timed steps (checks
-included), the HBM roofline of the sweep measured with HIP events on the
-stream the sweeps run on, and the CPU oracle timed on a bounded sample.
+Printed: one JSON line.  `value` is edge updates of the solves (|E(H)| x
+sweeps) per second of solve; `roofline` is the sweep's algorithmic bytes over
+its time, measured with HIP events on the stream the sweeps run on;
+`cpu_baseline` is the CPU oracle's edge loop timed on a bounded sample.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -30,28 +33,36 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PROFILE = os.path.join(ROOT, "profiles", "sweep_chunglu_1M_10M_f64.md")
-# the sources that decide the sweep's kernels and memory layout
+# the sources that decide the sweep's kernels and memory layout; a committed
+# counter summary is used only while they are unchanged
 SWEEP_SOURCES = ["paper_2307_15969_amd/csrc/k_sweep.hip", "paper_2307_15969_amd/csrc/sweep_state.h",
                  "paper_2307_15969_amd/csrc/schedule.cpp", "paper_2307_15969_amd/csrc/lowd_internal.h"]
+PROFILES = {
+    "rmat24": os.path.join(ROOT, "profiles", "sweep_rmat24_H_f64.md"),
+    "chunglu1m": os.path.join(ROOT, "profiles", "sweep_chunglu_1M_10M_f64.md"),
+    "uniform": os.path.join(ROOT, "profiles", "sweep_uniform_f64.md"),
+}
 
 
-def profiled_traffic():
-    """HBM bytes per sweep from the committed FETCH_SIZE/WRITE_SIZE summary,
-    or None when the sweep sources changed since the counters were taken
-    (the summary records a hash of those sources)."""
-    import hashlib
-    try:
-        text = open(PROFILE).read()
-    except OSError:
-        return None
+def sources_hash() -> str:
     h = hashlib.sha256()
     for p in SWEEP_SOURCES:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(workload: str):
+    """HBM bytes per sweep from the committed FETCH_SIZE/WRITE_SIZE summary of
+    this workload's FP64 sweep, or None when the sweep sources changed since
+    the counters were taken (the summary records a hash of those sources)."""
+    try:
+        text = open(PROFILES[workload]).read()
+    except (OSError, KeyError):
+        return None
     fields = dict(l.split(": ", 1) for l in text.splitlines()
                   if l.startswith(("traffic_bytes_per_sweep: ", "sources_sha256_16: ")))
-    if fields.get("sources_sha256_16", "").strip() != h.hexdigest()[:16]:
+    if fields.get("sources_sha256_16", "").strip() != sources_hash():
         return None
     return int(fields["traffic_bytes_per_sweep"])
 
@@ -63,100 +74,39 @@ def sweep_bytes(n: int, m: int, x_bytes: int = 8, w_bytes: int = 0, l_bytes: int
     return m * (8 + 2 * x_bytes + w_bytes) + n * 2 * l_bytes
 
 
-def cpu_baseline(g, seconds: float = 12.0) -> dict:
-    """The FP64 oracle (sequential, one core) on a bounded sample: its own
-    schedule, init, then as many full sweeps of the same graph as fit in
-    about `seconds`."""
+def cpu_baseline(n, src, dst, w, seconds: float = 12.0) -> dict:
+    """The FP64 oracle (sequential, one core): initialisation, then full
+    passes of Algorithm 1's edge loop in edge-index order over the same
+    graph, for about `seconds`."""
     import oracle
     oracle.build(force=False)
-    t0 = time.perf_counter()
-    _, _, order, _ = oracle.schedule(g.n, g.src, g.dst, 16)
-    t_sched = time.perf_counter() - t0
-    x, L = oracle.init(g.n, g.src, g.dst, g.w)
+    src = np.ascontiguousarray(src, dtype=np.int32)
+    dst = np.ascontiguousarray(dst, dtype=np.int32)
+    m = src.size
+    order = np.arange(m, dtype=np.int32)
+    x, L = oracle.init(n, src, dst, w)
     sweeps = 0
     t0 = time.perf_counter()
     while True:
-        oracle.sweep(g.n, g.src, g.dst, g.w, order, 1, x, L)
+        oracle.sweep(n, src, dst, w, order, 1, x, L)
         sweeps += 1
         el = time.perf_counter() - t0
         if el >= seconds or sweeps >= 200:
             break
-    rate = g.m * sweeps / el
-    return {"value": rate, "unit": "edge-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sweeps} full sweeps of the same {g.m}-edge graph in schedule order "
-                      f"({el:.1f} s; schedule build {t_sched:.1f} s not included)"}
+    return {"value": m * sweeps / el, "unit": "edge-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sweeps} full passes of the edge loop over the same {m}-edge graph, "
+                      f"edge-index order ({el:.1f} s)"}
 
 
 WORKLOADS = {
+    "rmat24": "R-MAT scale 24, edge factor 16, (.57,.19,.19,.05), pruned by Algorithm 2, "
+              "then LOWD on H",
     "chunglu1m": "Chung-Lu n=1M, ~10M unit edges, beta 2.1, planted 500-node block p=0.3",
     "chunglu4m": "Chung-Lu n=4M, ~64M lognormal(0,1) edges (float32), beta 2.1, planted block",
-    "rmat24": "R-MAT scale 24, edge factor 16, (.57,.19,.19,.05), pruned by Algorithm 2",
     "batch4096": "4096 Chung-Lu graphs (beta 2.3), edges log-uniform in [100, 50000], "
                  "planted blocks of 5-40 nodes",
-    "uniform": "diagnostic: 2^28 uniform random pairs on 2^25 nodes (max degree ~45, few wide "
-               "phases); sweeps only",
+    "uniform": "diagnostic: uniform random pairs (few wide phases); sweeps only",
 }
-
-
-def single_solve(sv, stream, tol, check_every, ev_a, ev_b):
-    """reset, then sweep/check until the gap tolerance; returns (sweeps,
-    seconds spent in sweeps measured with events on the sweep stream, final
-    extraction).  The sweeps between checks follow lowd.next_check: at most
-    check_every, fewer when the gap's decay predicts the tolerance sooner;
-    as in lowd.solve, the first check comes after the first check_every
-    sweeps, and a check extracts only when the largest load does not
-    certify the best set so far (lowd.certify)."""
-    import paper_2307_15969_amd as lowd
-    sv.reset(stream)
-    sweeps = 0
-    sweep_s = 0.0
-    ex = None
-    gap = float("inf")
-    hist = []
-    while gap > tol:
-        k = lowd.next_check(hist, tol, check_every)
-        ev_a.record(stream)
-        sv.iterate(k, stream)
-        ev_b.record(stream)
-        ev_b.synchronize()
-        sweep_s += ev_a.elapsed_time(ev_b) / 1e3
-        sweeps += k
-        ex, gap = lowd.certify(sv, ex, tol, stream)
-        hist.append((sweeps, gap))
-        if sweeps > 20000:
-            raise RuntimeError("no convergence within 20000 sweeps")
-    return sweeps, sweep_s, ex
-
-
-def timed_single(sv, m, args, stream, torch, label):
-    ev_a = torch.cuda.Event(enable_timing=True)
-    ev_b = torch.cuda.Event(enable_timing=True)
-    for i in range(args.warmup):
-        s_, _, ex = single_solve(sv, stream, args.tol, args.check_every, ev_a, ev_b)
-        print(f"[bench] {label} warmup {i}: {s_} sweeps, gap {ex['gap']:.3e}, "
-              f"density {ex['num']}/{ex['den']}", flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    tot_sweeps, tot_sweep_s, last = 0, 0.0, None
-    for i in range(args.steps):
-        s_, ss, ex = single_solve(sv, stream, args.tol, args.check_every, ev_a, ev_b)
-        tot_sweeps += s_
-        tot_sweep_s += ss
-        last = (s_, ex)
-        print(f"[bench] {label} step {i}: {s_} sweeps, gap {ex['gap']:.3e}", flush=True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    return dict(elapsed=elapsed, sweeps=tot_sweeps, sweep_s=tot_sweep_s, last_sweeps=last[0],
-                ex=last[1], value=m * tot_sweeps / elapsed,
-                per_sweep_s=tot_sweep_s / max(tot_sweeps, 1))
-
-
-def density_str(ex, weighted=False):
-    """the extracted density: the exact rational for unit weights, else the
-    FP64 weight sum over the node count"""
-    if weighted:
-        return f"{ex['num_w']!r}/{ex['den']}"
-    return f"{ex['num']}/{ex['den']}"
 
 
 def base_line(args, metric_value, ms_per_step, dtype, config):
@@ -184,6 +134,170 @@ def roofline(bytes_per_unit, seconds_per_unit, kernel, traffic=None):
             "algorithmic_bytes": bytes_per_unit}
 
 
+def density_str(r, weighted=False):
+    """the extracted density: the exact rational for unit weights, else the
+    FP64 weight sum over the node count"""
+    if weighted:
+        return f"{r['num_w']!r}/{r['den']}"
+    return f"{r['num']}/{r['den']}"
+
+
+def one_solve(sv, args, stream):
+    sv.reset(stream)
+    r = sv.solve(args.tol, args.max_sweeps, args.check_every, stream)
+    if not r["converged"]:
+        raise RuntimeError(f"no convergence within {args.max_sweeps} sweeps (gap {r['gap']:.3e})")
+    return r
+
+
+def sweep_seconds(sv, sweeps, stream, torch):
+    """Average time of one sweep: `sweeps` replays of the sweep's HIP graph
+    from the initial state, timed with events on the stream they run on."""
+    ev_a = torch.cuda.Event(enable_timing=True)
+    ev_b = torch.cuda.Event(enable_timing=True)
+    sv.reset(stream)
+    sv.iterate(1, stream)
+    sv.reset(stream)
+    ev_a.record(stream)
+    sv.iterate(sweeps, stream)
+    ev_b.record(stream)
+    ev_b.synchronize()
+    return ev_a.elapsed_time(ev_b) / 1e3 / sweeps
+
+
+def timed_solves(sv, m, args, stream, torch, label, before_each=None):
+    """args.warmup untimed solves, then args.steps timed ones (each from the
+    initial state); before_each() runs inside the timed region first (the
+    prune, where the workload prunes) and returns its seconds."""
+    for i in range(args.warmup):
+        if before_each:
+            before_each()
+        r = one_solve(sv, args, stream)
+        print(f"[bench] {label} warmup {i}: {r['sweeps']} sweeps, gap {r['gap']:.3e}, "
+              f"density {r['num']}/{r['den']}", flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot_sweeps, solve_s, pre_s, last = 0, 0.0, 0.0, None
+    for i in range(args.steps):
+        if before_each:
+            pre_s += before_each()
+        ta = time.perf_counter()
+        r = one_solve(sv, args, stream)
+        solve_s += time.perf_counter() - ta
+        tot_sweeps += r["sweeps"]
+        last = r
+        print(f"[bench] {label} step {i}: {r['sweeps']} sweeps, gap {r['gap']:.3e}", flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    per_sweep = sweep_seconds(sv, max(last["sweeps"], 1), stream, torch)
+    return dict(elapsed=elapsed, sweeps=tot_sweeps, solve_s=solve_s, pre_s=pre_s, last=last,
+                value=m * tot_sweeps / solve_s, per_sweep_s=per_sweep)
+
+
+def state_result(r, m, n, xb, wb, kernel, traffic=None, weighted=False):
+    return {"value": r["value"], "time_to_1e-6_ms": r["solve_s"] / max(len_steps(r), 1) * 1e3,
+            "sweeps_to_1e-6": r["last"]["sweeps"], "density": density_str(r["last"], weighted),
+            "gap": r["last"]["gap"], "sweep_ms": r["per_sweep_s"] * 1e3,
+            "sweep_edge_updates_per_s": m / r["per_sweep_s"],
+            "roofline": roofline(sweep_bytes(n, m, xb, wb, 8), r["per_sweep_s"], kernel, traffic)}
+
+
+def len_steps(r):
+    return r.get("steps", 1)
+
+
+def load_error(sv_a, sv_b, sweeps, stream):
+    """max |L_a - L_b| / max |L_b| after the same number of sweeps from the
+    initial state"""
+    sv_a.reset(stream)
+    sv_a.iterate(sweeps, stream)
+    _, La = sv_a.read_state(stream)
+    sv_b.reset(stream)
+    sv_b.iterate(sweeps, stream)
+    _, Lb = sv_b.read_state(stream)
+    La, Lb = La.cpu().numpy(), Lb.cpu().numpy()
+    return float(np.max(np.abs(La - Lb)) / np.max(np.abs(Lb)))
+
+
+def run_rmat24(args, torch, lowd, synth):
+    t0 = time.perf_counter()
+    g = synth.rmat(24, 16, seed=args.seed, device="cuda")
+    print(f"[bench] workload {g.name}: n={g.n} m={g.m} generated in "
+          f"{time.perf_counter() - t0:.1f}s", flush=True)
+    src = torch.from_numpy(g.src).cuda()
+    dst = torch.from_numpy(g.dst).cuda()
+    n, m = g.n, g.m
+    del g
+    stream = torch.cuda.current_stream()
+    pr = lowd.prune(n, src, dst, stream)          # warm-up (allocations, code load)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pr = lowd.prune(n, src, dst, stream)
+    torch.cuda.synchronize()
+    t_prune = time.perf_counter() - t0
+    n_h, m_h = pr["n_h"], pr["m_h"]
+    print(f"[bench] prune {t_prune * 1e3:.1f} ms: rounds {pr['rounds']} H n={n_h} m={m_h}",
+          flush=True)
+    hs = pr["src"].clone()
+    hd = pr["dst"].clone()
+    del pr
+
+    def prune_again():
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        lowd.prune(n, src, dst, stream)
+        torch.cuda.synchronize()
+        return time.perf_counter() - ta
+
+    res, svs = {}, {}
+    for state in ("f64", "f32k"):
+        t0 = time.perf_counter()
+        sv = lowd.Solver(n_h, hs, hd, None, state, star_max=args.star_max)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        print(f"[bench] {state} setup {t_setup:.1f}s info {sv.info()}", flush=True)
+        r = timed_solves(sv, m_h, args, stream, torch, state, prune_again)
+        r["steps"] = args.steps
+        r["setup_s"] = t_setup
+        res[state] = r
+        svs[state] = sv
+    r64, r32 = res["f64"], res["f32k"]
+    err = load_error(svs["f32k"], svs["f64"], r32["last"]["sweeps"], stream)
+    info = svs["f64"].info()
+    for sv in svs.values():
+        sv.close()
+    step_ms = (r64["pre_s"] + r64["solve_s"]) / args.steps * 1e3
+    out = base_line(args, r64["value"], step_ms, "f64",
+                    {"workload": f"rmat24 ({WORKLOADS['rmat24']}), FP64 to a 1e-6 gap; "
+                     "step = prune + solve", "n": n, "m": m, "n_h": n_h, "m_h": m_h,
+                     "star_max": args.star_max, "check_every": args.check_every,
+                     "seed": args.seed})
+    f64 = state_result(r64, m_h, n_h, 8, 0, "one FP64 sweep of H (HIP graph of phase kernels "
+                       "and single-workgroup tiers)", profiled_traffic("rmat24"))
+    f32 = state_result(r32, m_h, n_h, 4, 0, "one FP32K sweep of H (HIP graph)")
+    out.update({
+        "prune_ms": t_prune * 1e3,
+        "prune_edges_per_s": m / t_prune,
+        "time_to_1e-6_ms": step_ms,
+        "solve_ms": f64["time_to_1e-6_ms"],
+        "sweeps_to_1e-6": f64["sweeps_to_1e-6"],
+        "density": f64["density"],
+        "sweep_ms": f64["sweep_ms"],
+        "setup_s": r64["setup_s"],
+        "schedule": info,
+        "roofline": f64["roofline"],
+        "f32k": dict(f32, setup_s=r32["setup_s"],
+                     step_ms=(r32["pre_s"] + r32["solve_s"]) / args.steps * 1e3),
+        "f32k_load_error_vs_f64": {"max_abs_over_max": err, "sweeps": r32["last"]["sweeps"]},
+    })
+    if not args.no_cpu_baseline:
+        torch.cuda.synchronize()
+        h_src, h_dst = hs.cpu().numpy(), hd.cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(n_h, h_src, h_dst, None, args.cpu_seconds)
+        out["cpu_baseline"]["sample"] += " (the pruned graph H)"
+    return out
+
+
 def run_chunglu1m(args, torch, lowd, synth):
     t0 = time.perf_counter()
     g = synth.workload(1, seed=args.seed)
@@ -192,33 +306,29 @@ def run_chunglu1m(args, torch, lowd, synth):
     src = torch.from_numpy(g.src).cuda()
     dst = torch.from_numpy(g.dst).cuda()
     stream = torch.cuda.current_stream()
+    state = args.state or "f64"
     t0 = time.perf_counter()
-    sv = lowd.Solver(g.n, src, dst, None, args.state or "f64", star_max=16)
+    sv = lowd.Solver(g.n, src, dst, None, state, star_max=args.star_max)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     info = sv.info()
-    print(f"[bench] setup (validation, schedule, CSR, init) {t_setup:.2f}s info {info}", flush=True)
-    state = args.state or "f64"
-    r = timed_single(sv, g.m, args, stream, torch, state)
-    xb, lb = (8, 8) if state == "f64" else (4, 8)
-    out = base_line(args, r["value"], r["elapsed"] / args.steps * 1e3, state,
-                    {"workload": g.name + " (" + WORKLOADS["chunglu1m"] + "), " + state.upper() +
-                     ", no pruning, to 1e-6 gap", "n": g.n, "m": g.m, "star_max": 16,
-                     "check_every": args.check_every, "seed": args.seed})
-    out.update({
-        "time_to_1e-6_ms": r["elapsed"] / args.steps * 1e3,
-        "sweeps_to_1e-6": r["last_sweeps"],
-        "density": density_str(r["ex"]),
-        "sweep_ms": r["per_sweep_s"] * 1e3,
-        "sweep_edge_updates_per_s": g.m / r["per_sweep_s"],
-        "setup_s": t_setup,
-        "schedule": info,
-        "roofline": roofline(sweep_bytes(g.n, g.m, xb, 0, lb), r["per_sweep_s"],
-                             "one sweep (the HIP graph of phase kernels + single-workgroup tiers)",
-                             profiled_traffic() if state == "f64" else None),
-    })
+    print(f"[bench] setup {t_setup:.2f}s info {info}", flush=True)
+    r = timed_solves(sv, g.m, args, stream, torch, state)
+    r["steps"] = args.steps
+    sv.close()
+    xb = 8 if state == "f64" else 4
+    res = state_result(r, g.m, g.n, xb, 0, "one sweep (HIP graph of phase kernels and "
+                       "single-workgroup tiers)",
+                       profiled_traffic("chunglu1m") if state == "f64" else None)
+    out = base_line(args, r["value"], r["solve_s"] / args.steps * 1e3, state,
+                    {"workload": f"{g.name} ({WORKLOADS['chunglu1m']}), {state.upper()}, "
+                     "no pruning, to a 1e-6 gap", "n": g.n, "m": g.m,
+                     "star_max": args.star_max, "check_every": args.check_every,
+                     "seed": args.seed})
+    out.update(res)
+    out.update({"setup_s": t_setup, "schedule": info})
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(g, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(g.n, g.src, g.dst, None, args.cpu_seconds)
     return out
 
 
@@ -231,222 +341,114 @@ def run_chunglu4m(args, torch, lowd, synth):
     dst = torch.from_numpy(g.dst).cuda()
     w = torch.from_numpy(g.w).cuda()
     stream = torch.cuda.current_stream()
-    res = {}
+    res, svs = {}, {}
     for state in ("f32k", "f64"):
         t0 = time.perf_counter()
-        sv = lowd.Solver(g.n, src, dst, w, state, star_max=16)
+        sv = lowd.Solver(g.n, src, dst, w, state, star_max=args.star_max)
         torch.cuda.synchronize()
         t_setup = time.perf_counter() - t0
         print(f"[bench] {state} setup {t_setup:.1f}s info {sv.info()}", flush=True)
-        r = timed_single(sv, g.m, args, stream, torch, state)
+        r = timed_solves(sv, g.m, args, stream, torch, state)
+        r["steps"] = args.steps
         r["setup_s"] = t_setup
-        r["info"] = sv.info()
-        res[state] = (r, sv)
-        if state == "f32k":
-            # loads after the FP32 run's sweep count, for the error against FP64
-            sv.reset(stream)
-            sv.iterate(r["last_sweeps"], stream)
-            _, L32 = sv.read_state(stream)
-            res["L32"] = L32.cpu().numpy()
-            sv.close()
-    r64, sv64 = res["f64"]
-    r32 = res["f32k"][0]
-    sv64.reset(stream)
-    sv64.iterate(r32["last_sweeps"], stream)
-    _, L64 = sv64.read_state(stream)
-    L64 = L64.cpu().numpy()
-    err = float(np.max(np.abs(res["L32"] - L64)) / np.max(np.abs(L64)))
-    sv64.close()
-    out = base_line(args, r32["value"], r32["elapsed"] / args.steps * 1e3, "f32k",
-                    {"workload": g.name + " (" + WORKLOADS["chunglu4m"] + "), FP32 fractions + "
-                     "compensated FP32 loads vs FP64, to 1e-6 gap", "n": g.n, "m": g.m,
-                     "star_max": 16, "check_every": args.check_every, "seed": args.seed})
-    out.update({
-        "time_to_1e-6_ms": r32["elapsed"] / args.steps * 1e3,
-        "sweeps_to_1e-6": r32["last_sweeps"],
-        "density": density_str(r32["ex"], True),
-        "sweep_ms": r32["per_sweep_s"] * 1e3,
-        "setup_s": r32["setup_s"],
-        "schedule": r32["info"],
-        "roofline": roofline(sweep_bytes(g.n, g.m, 4, 4, 8), r32["per_sweep_s"],
-                             "one FP32 sweep (HIP graph)"),
-        "f64": {"value": r64["value"], "time_to_1e-6_ms": r64["elapsed"] / args.steps * 1e3,
-                "sweeps_to_1e-6": r64["last_sweeps"], "density": density_str(r64["ex"], True),
-                "sweep_ms": r64["per_sweep_s"] * 1e3,
-                "roofline": roofline(sweep_bytes(g.n, g.m, 8, 4, 8), r64["per_sweep_s"],
-                                     "one FP64 sweep (HIP graph)")},
-        "f32k_load_error_vs_f64": {"max_abs_over_max": err, "sweeps": r32["last_sweeps"],
-                                   "note": "FP64 path is bit-identical to the FP64 oracle"},
-    })
-    return out
-
-
-def run_rmat24(args, torch, lowd, synth):
-    t0 = time.perf_counter()
-    g = synth.workload(3, seed=args.seed)
-    print(f"[bench] workload {g.name}: n={g.n} m={g.m} generated in "
-          f"{time.perf_counter() - t0:.1f}s", flush=True)
-    src = torch.from_numpy(g.src).cuda()
-    dst = torch.from_numpy(g.dst).cuda()
-    stream = torch.cuda.current_stream()
-    pr = lowd.prune(g.n, src, dst, stream)          # warm-up (allocations, code load)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    pr = lowd.prune(g.n, src, dst, stream)
-    torch.cuda.synchronize()
-    t_prune = time.perf_counter() - t0
-    print(f"[bench] prune {t_prune * 1e3:.1f} ms: rounds {pr['rounds']} H n={pr['n_h']} "
-          f"m={pr['m_h']}", flush=True)
-    hs = pr["src"].clone()
-    hd = pr["dst"].clone()
-    state = args.state or "f32k"
-    t0 = time.perf_counter()
-    sv = lowd.Solver(pr["n_h"], hs, hd, None, state, star_max=16)
-    torch.cuda.synchronize()
-    t_setup = time.perf_counter() - t0
-    print(f"[bench] setup {t_setup:.1f}s info {sv.info()}", flush=True)
-    r = timed_single(sv, pr["m_h"], args, stream, torch, state)
-    xb = 4 if state == "f32k" else 8
-    out = base_line(args, r["value"], r["elapsed"] / args.steps * 1e3 + t_prune * 1e3, state,
-                    {"workload": g.name + " (" + WORKLOADS["rmat24"] + "), then LOWD on H in " +
-                     state.upper() + ", to 1e-6 gap", "n": g.n, "m": g.m, "n_h": pr["n_h"],
-                     "m_h": pr["m_h"], "star_max": 16, "check_every": args.check_every,
+        res[state] = r
+        svs[state] = sv
+    r32, r64 = res["f32k"], res["f64"]
+    err = load_error(svs["f32k"], svs["f64"], r32["last"]["sweeps"], stream)
+    info = svs["f32k"].info()
+    for sv in svs.values():
+        sv.close()
+    f32 = state_result(r32, g.m, g.n, 4, 4, "one FP32K sweep (HIP graph)", None, True)
+    f64 = state_result(r64, g.m, g.n, 8, 4, "one FP64 sweep (HIP graph)", None, True)
+    out = base_line(args, r32["value"], r32["solve_s"] / args.steps * 1e3, "f32k",
+                    {"workload": f"{g.name} ({WORKLOADS['chunglu4m']}), FP32 fractions + "
+                     "compensated loads vs FP64, to a 1e-6 gap", "n": g.n, "m": g.m,
+                     "star_max": args.star_max, "check_every": args.check_every,
                      "seed": args.seed})
-    out.update({
-        "prune_ms": t_prune * 1e3,
-        "prune_rounds": pr["rounds"],
-        "prune_edges_per_s": g.m / t_prune,
-        "time_to_1e-6_ms": r["elapsed"] / args.steps * 1e3,
-        "sweeps_to_1e-6": r["last_sweeps"],
-        "density": density_str(r["ex"]),
-        "sweep_ms": r["per_sweep_s"] * 1e3,
-        "setup_s": t_setup,
-        "schedule": sv.info(),
-        "roofline": roofline(sweep_bytes(pr["n_h"], pr["m_h"], xb, 0, 8), r["per_sweep_s"],
-                             "one sweep of H (HIP graph)"),
-    })
-    sv.close()
-    # Algorithm 2's other plug-in: greedy peeling (Algorithm 3) of H
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    gr = lowd.greedy_peel(pr["n_h"], hs, hd, stream)
-    torch.cuda.synchronize()
-    t_greedy = time.perf_counter() - t0
-    out["greedy_on_h"] = {"ms": t_greedy * 1e3, "density": f"{gr['num']}/{gr['den']}",
-                          "vs_lowd_density": (gr["num"] / gr["den"]) /
-                                             (r["ex"]["num"] / r["ex"]["den"])}
-    print(f"[bench] greedy on H: {t_greedy * 1e3:.1f} ms, density {gr['num']}/{gr['den']}",
-          flush=True)
+    out.update(f32)
+    out.update({"setup_s": r32["setup_s"], "schedule": info, "f64": f64,
+                "f32k_load_error_vs_f64": {"max_abs_over_max": err,
+                                           "sweeps": r32["last"]["sweeps"],
+                                           "note": "the FP64 path is bit-identical to the FP64 "
+                                                   "oracle"}})
     return out
 
 
 def run_uniform(args, torch, lowd, synth):
     """The sweep where phases are wide: a uniform random graph has a small
     maximum degree, so a sweep is a few dozen phases of millions of edges
-    each, and the kernels run at memory speed.  Times sweeps only."""
+    each, and bytes, not phase latency, bound it.  Times sweeps only."""
     t0 = time.perf_counter()
-    g = synth.uniform_pairs(25, 28, seed=args.seed)
+    g = synth.uniform_pairs(args.uniform_log_n, args.uniform_log_m, seed=args.seed,
+                            device="cuda")
     print(f"[bench] workload {g.name}: n={g.n} m={g.m} generated in "
           f"{time.perf_counter() - t0:.1f}s", flush=True)
     src = torch.from_numpy(g.src).cuda()
     dst = torch.from_numpy(g.dst).cuda()
-    del g.src, g.dst
+    n, m = g.n, g.m
+    del g
     stream = torch.cuda.current_stream()
-    state = args.state or "f32k"
+    state = args.state or "f64"
     t0 = time.perf_counter()
-    sv = lowd.Solver(g.n, src, dst, None, state, star_max=16)
+    sv = lowd.Solver(n, src, dst, None, state, star_max=args.star_max)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     info = sv.info()
     print(f"[bench] setup {t_setup:.1f}s info {info}", flush=True)
-    ev_a = torch.cuda.Event(enable_timing=True)
-    ev_b = torch.cuda.Event(enable_timing=True)
-    sv.iterate(max(args.warmup, 1), stream)
     sweeps = 10 * args.steps
-    ev_a.record(stream)
-    sv.iterate(sweeps, stream)
-    ev_b.record(stream)
-    ev_b.synchronize()
-    per = ev_a.elapsed_time(ev_b) / 1e3 / sweeps
-    m = info["m"]
+    per = sweep_seconds(sv, sweeps, stream, torch)
+    sv.close()
     xb = 4 if state == "f32k" else 8
     out = base_line(args, m / per, per * 1e3, state,
-                    {"workload": WORKLOADS["uniform"], "n": g.n, "m": m, "star_max": 16,
-                     "seed": args.seed})
+                    {"workload": f"{WORKLOADS['uniform']}: 2^{args.uniform_log_m} pairs on "
+                     f"2^{args.uniform_log_n} nodes", "n": n, "m": m,
+                     "star_max": args.star_max, "seed": args.seed})
     out.update({"sweep_ms": per * 1e3, "sweeps_timed": sweeps, "setup_s": t_setup,
                 "schedule": info,
-                "roofline": roofline(sweep_bytes(g.n, m, xb, 0, 8), per,
-                                     "one sweep (HIP graph); wide phases")})
-    sv.close()
+                "roofline": roofline(sweep_bytes(n, m, xb, 0, 8), per,
+                                     "one sweep (HIP graph); wide phases",
+                                     profiled_traffic("uniform") if state == "f64" else None)})
     return out
 
 
 def batch_solves(gs, state, args, torch, lowd, stream):
     """Prepares (and tunes) the batch in one state, then times args.steps
-    solves after args.warmup untimed ones.  Each solve: reset; then sweep the
-    graphs still above the tolerance, k sweeps a launch, extract and retire,
-    until every graph is within it.  Once fewer than an eighth of the graphs
-    remain, k doubles after each check, up to 8 K (FP64) or 4 K (FP32K): the
-    few slow graphs then cost a check more than a sweep, but a longer launch
-    overshoots their convergence, and for FP32K lets the carried loads drift
-    further from the fractions' loads between two restarts."""
-    M = sum(g.m for g in gs)
+    solves after args.warmup untimed ones; each solve: reset, then
+    lowd_batch_solve_prepared to the tolerance."""
     t0 = time.perf_counter()
     b = lowd.Batch(gs, state, tune=True, stream=stream)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     info = b.info()
     print(f"[bench] {state} prepare + tune {t_setup:.1f}s info {info}", flush=True)
-    ev_a = torch.cuda.Event(enable_timing=True)
-    ev_b = torch.cuda.Event(enable_timing=True)
-    K = args.check_every
+    m = np.array([g.m for g in gs], dtype=np.int64)
 
-    def one_solve():
+    def one():
         b.reset(stream)
-        updates, launches, sweeps, launch_s, launch_bytes = 0, 0, 0, 0.0, 0
-        active, aedges = len(gs), M
-        k = K
-        while active > 0:
-            if active * 8 < len(gs):
-                k = min(2 * k, (4 if state == "f32k" else 8) * K)
-            ev_a.record(stream)
-            b.iterate(k, stream)
-            ev_b.record(stream)
-            b.extract(stream)
-            ev_b.synchronize()
-            launch_s += ev_a.elapsed_time(ev_b) / 1e3
-            updates += aedges * k
-            launch_bytes += aedges * k * (8 + 2 * (4 if state == "f32k" else 8))
-            launches += 1
-            sweeps += k
-            active, aedges = b.retire(args.tol, stream)
-            if sweeps > 20000:
-                raise RuntimeError("no convergence within 20000 sweeps")
-        return updates, launches, sweeps, launch_s, launch_bytes
+        r = b.solve(args.tol, args.max_sweeps, args.check_every, stream)
+        if not r["converged"]:
+            raise RuntimeError(f"batch: no convergence within {args.max_sweeps} sweeps")
+        return r
 
     for i in range(args.warmup):
-        u, l, s_, _, _ = one_solve()
-        print(f"[bench] {state} warmup {i}: {s_} sweeps in {l} launches, {u} edge updates",
-              flush=True)
+        r = one()
+        print(f"[bench] {state} warmup {i}: most sweeps {int(r['sweeps'].max())}", flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    r = dict(updates=0, launches=0, launch_s=0.0, bytes=0, last=None, setup_s=t_setup, info=info)
+    updates = 0
     for i in range(args.steps):
-        u, l, s_, ls, lb = one_solve()
-        r["updates"] += u
-        r["launches"] += l
-        r["launch_s"] += ls
-        r["bytes"] += lb
-        r["last"] = (u, l, s_)
-        print(f"[bench] {state} step {i}: {s_} sweeps in {l} launches", flush=True)
+        r = one()
+        updates += int((m * r["sweeps"]).sum())
+        print(f"[bench] {state} step {i}: most sweeps {int(r['sweeps'].max())}", flush=True)
     torch.cuda.synchronize()
-    r["elapsed"] = time.perf_counter() - t0
-    b.extract(stream)
-    r["gaps"] = b.gaps()
-    r["num"] = b.num.cpu().numpy()
-    r["den"] = b.den.cpu().numpy()
+    elapsed = time.perf_counter() - t0
+    num, den, D = b.num.cpu().numpy(), b.den.cpu().numpy(), b.D.cpu().numpy()
+    rho = num / np.maximum(den, 1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        gaps = np.where(rho > 0, (D - rho) / rho, 0.0)
     b.close()
-    return r
+    return dict(elapsed=elapsed, updates=updates, sweeps=r["sweeps"], setup_s=t_setup, info=info,
+                max_gap=float(np.max(gaps)), num=num, den=den)
 
 
 def run_batch4096(args, torch, lowd, synth):
@@ -459,33 +461,32 @@ def run_batch4096(args, torch, lowd, synth):
     state = args.state or "f32k"
     stream = torch.cuda.current_stream()
     r = batch_solves(gs, state, args, torch, lowd, stream)
-    last = r["last"]
-    out = base_line(args, r["updates"] / r["elapsed"], r["elapsed"] / args.steps * 1e3, state,
+    per_solve = r["elapsed"] / args.steps
+    xb = 4 if state == "f32k" else 8
+    out = base_line(args, r["updates"] / r["elapsed"], per_solve * 1e3, state,
                     {"workload": WORKLOADS["batch4096"] + ", " + state.upper() +
-                     ", every graph to a 1e-6 gap, converged graphs retired",
-                     "graphs": len(gs), "N": N, "M": M, "star_max": 16,
-                     "check_every": args.check_every, "seed": args.seed})
+                     ", every graph to a 1e-6 gap", "graphs": len(gs), "N": N, "M": M,
+                     "star_max": args.star_max, "check_every": args.check_every,
+                     "seed": args.seed})
+    m = np.array([g.m for g in gs], dtype=np.int64)
+    n = np.array([g.n for g in gs], dtype=np.int64)
+    bytes_solve = int((r["sweeps"] * (m * (8 + 2 * xb) + n * 16)).sum())
     out.update({
-        "time_to_1e-6_ms": r["elapsed"] / args.steps * 1e3,
-        "sweeps_to_1e-6": last[2],
-        "launches": last[1],
-        "edge_updates_per_solve": last[0],
-        "max_gap": float(np.max(r["gaps"])),
+        "time_to_1e-6_ms": per_solve * 1e3,
+        "most_sweeps": int(r["sweeps"].max()),
+        "edge_updates_per_solve": r["updates"] // args.steps,
+        "max_gap": r["max_gap"],
         "densities_sum": f"{int(r['num'].sum())}/{int(r['den'].sum())}",
         "setup_s": r["setup_s"],
         "batch": r["info"],
-        "roofline": roofline(r["bytes"] / max(r["launches"], 1),
-                             r["launch_s"] / max(r["launches"], 1),
-                             "one persistent launch of k sweeps over the graphs still "
-                             "iterating (LDS-resident; HBM carries ids, fractions and the "
-                             "loads in and out)"),
+        "roofline": roofline(bytes_solve, per_solve,
+                             "the whole batched solve (sweeps of every graph's schedule from LDS, "
+                             "checks included); a loose model: the loads live in LDS"),
     })
-    # the same batch in the other state, for comparison
     other = "f64" if state == "f32k" else "f32k"
     r2 = batch_solves(gs, other, args, torch, lowd, stream)
     out[other] = {"time_to_1e-6_ms": r2["elapsed"] / args.steps * 1e3,
-                  "sweeps_to_1e-6": r2["last"][2], "launches": r2["last"][1],
-                  "max_gap": float(np.max(r2["gaps"])),
+                  "most_sweeps": int(r2["sweeps"].max()), "max_gap": r2["max_gap"],
                   "densities_sum": f"{int(r2['num'].sum())}/{int(r2['den'].sum())}"}
     if args.per_graph_sample > 0:
         out["per_graph_f64"] = per_graph_baseline(gs, args, torch, lowd, stream)
@@ -499,8 +500,6 @@ def per_graph_baseline(gs, args, torch, lowd, stream):
     order = sorted(range(len(gs)), key=lambda i: -gs[i].m)
     step = max(1, len(gs) // args.per_graph_sample)
     sample = order[::step]
-    ev_a = torch.cuda.Event(enable_timing=True)
-    ev_b = torch.cuda.Event(enable_timing=True)
     t_setup = t_solve = 0.0
     for i in sample:
         g = gs[i]
@@ -509,7 +508,7 @@ def per_graph_baseline(gs, args, torch, lowd, stream):
                          None, "f64", star_max=16)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        single_solve(sv, stream, args.tol, args.check_every, ev_a, ev_b)
+        one_solve(sv, args, stream)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         t_setup += t1 - t0
@@ -530,9 +529,14 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--check-every", type=int, default=10)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="chunglu1m")
+    ap.add_argument("--max-sweeps", type=int, default=20000)
+    ap.add_argument("--star-max", type=int, default=16)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="rmat24")
     ap.add_argument("--state", choices=["f64", "f32k"], default=None,
-                    help="solver state (default: f64 for chunglu1m, f32k otherwise)")
+                    help="solver state where the workload runs one (chunglu1m: f64, batch4096 "
+                         "and uniform: the first of two / the only one)")
+    ap.add_argument("--uniform-log-n", type=int, default=22)
+    ap.add_argument("--uniform-log-m", type=int, default=28)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--per-graph-sample", type=int, default=64,
                     help="batch4096: graphs solved one by one in FP64 for comparison (0: none)")
@@ -543,7 +547,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the workload is one graph on one MI355X)", file=sys.stderr)
+              "(every workload is sized for one MI355X)", file=sys.stderr)
         sys.exit(2)
 
     import torch

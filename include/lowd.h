@@ -37,6 +37,7 @@ extern "C" {
 
 typedef int32_t lowd_status;
 #define LOWD_OK 0
+#define LOWD_NOT_CONVERGED 1    /* informational: the sweep limit came before the tolerance */
 #define LOWD_E_ARG (-1)         /* bad pointer, size or option */
 #define LOWD_E_GRAPH (-2)       /* id out of range, self-loop, repeated pair, bad weight */
 #define LOWD_E_HIP (-4)         /* a HIP runtime call failed */
@@ -241,6 +242,44 @@ lowd_status lowd_extract_densest_kept(lowd_solver *s, uint8_t *in_set, int64_t *
                                       void *stream);
 
 /*
+ * lowd_solve -- Algorithm 1 run to a certified density gap, from the
+ * solver's current state (lowd_reset_loads first for a fresh solve).  The
+ * stopping rule is Section III-B's duality: D = max load bounds the maximum
+ * density from above at every sweep, and the density rho of any extracted
+ * set bounds it from below, so the densest set extracted so far is
+ * certified once (D - rho) / rho <= tol.  The call sweeps and checks until
+ * that holds or max_sweeps sweeps are done.
+ *
+ * Checks come at most every check_every sweeps, sooner when the decay of the
+ * gap over the last two checks predicts the tolerance; the first comes after
+ * the first sweeps.  A check takes D first and extracts (Algorithm 1's sort
+ * and prefix densities) only when D does not already certify the best set.
+ * With LOWD_STATE_F32K checks screen with the kept compensated loads and
+ * confirm a passing gap with D recomputed in FP64 from the stored fractions
+ * (the loads of a feasible dual point); when the confirmation fails the
+ * carried loads restart from those loads (as lowd_resync_loads).
+ *
+ *   tol          relative gap to reach (>= 0; 1e-6 in the benchmarks)
+ *   max_sweeps   sweep limit (>= 0)
+ *   check_every  most sweeps between two checks (>= 1; 10 is the default)
+ *   in_set       [device] uint8[n] out: the certified (or, on
+ *                LOWD_NOT_CONVERGED, the best) set
+ *   num_unit     [host] out: |E(S)| (unit weights; 0 for weighted graphs);
+ *                may be NULL
+ *   num_w        [host] out: W(S) in FP64; may be NULL
+ *   den          [host] out: |S|; may be NULL
+ *   D, gap       [host] out: the bound and the gap at the last check; may be
+ *                NULL
+ *   sweeps_used  [host] out: sweeps done by this call; may be NULL
+ * Returns LOWD_OK when the gap is within tol, LOWD_NOT_CONVERGED (> 0, the
+ * outputs still written) when max_sweeps came first, or an error.
+ * Synchronises `stream`.
+ */
+lowd_status lowd_solve(lowd_solver *s, double tol, int32_t max_sweeps, int32_t check_every,
+                       uint8_t *in_set, int64_t *num_unit, double *num_w, int64_t *den,
+                       double *D, double *gap, int32_t *sweeps_used, void *stream);
+
+/*
  * lowd_ldd_readout -- the locally-dense decomposition (Problem 2, Property
  * 2) read from the current loads: with the nodes ranked by descending load
  * (the reverse of lowd_extract_densest's order) and f(k) the weight of the
@@ -342,36 +381,46 @@ lowd_status lowd_solver_info(const lowd_solver *s, int64_t *info);
 void lowd_solver_free(lowd_solver *s);
 
 /*
- * lowd_batch_solve -- many independent unweighted graphs solved together:
- * Algorithm 1 (init, `sweeps` sweeps in each graph's own schedule,
- * extraction) on every graph, one workgroup per graph with its loads held in
- * LDS, in a single persistent launch.  Each graph's result equals its own
- * single-graph solve with the same star_max.
+ * lowd_batch_solve -- many independent unweighted graphs, each solved to a
+ * certified density gap (Section III-B, as lowd_solve): Algorithm 1 on every
+ * graph in its own schedule, one workgroup per graph with its loads held in
+ * LDS, in persistent launches over the graphs still iterating.  A graph
+ * stops (retires) at the first check where (D_g - rho_g) / rho_g <= tol,
+ * D_g its largest load and rho_g the density of its extracted set; checks
+ * come every check_every sweeps, and, once fewer than an eighth of the
+ * graphs iterate, at doubling intervals (at most 8 check_every for FP64,
+ * 4 check_every for FP32K).  Each graph's set is that of its own
+ * single-graph iteration after its sweeps_used sweeps.
  *
- *   G          number of graphs (>= 1)
- *   node_ptr   [host] int64[G+1]: graph g owns nodes node_ptr[g]..node_ptr[g+1]-1
- *   edge_ptr   [host] int64[G+1]: graph g owns edges edge_ptr[g]..edge_ptr[g+1]-1
- *   src, dst   [device] int32[total edges], node ids local to their graph
- *   state      LOWD_STATE_F64 or LOWD_STATE_F32K
- *   star_max   as for lowd_init_loads
- *   sweeps     sweeps per graph (>= 0)
- *   in_set     [device] uint8[total nodes] out
- *   num        [device] int64[G] out: |E(S*)| per graph
- *   den        [device] int64[G] out: |S*| per graph
- *   load       [device] double[total nodes] out, or NULL: final loads
- * Graphs whose nodes do not fit one workgroup's LDS are rejected with
- * LOWD_E_UNSUPPORTED.  Synchronises `stream`.
+ *   G            number of graphs (>= 1)
+ *   node_ptr     [host] int64[G+1]: graph g owns nodes node_ptr[g]..node_ptr[g+1]-1
+ *   edge_ptr     [host] int64[G+1]: graph g owns edges edge_ptr[g]..edge_ptr[g+1]-1
+ *   src, dst     [device] int32[total edges], node ids local to their graph
+ *   state        LOWD_STATE_F64 or LOWD_STATE_F32K
+ *   star_max     as for lowd_init_loads
+ *   tol          relative gap (>= 0)
+ *   max_sweeps   sweep limit per graph (>= 0)
+ *   check_every  sweeps between the first checks (>= 1)
+ *   in_set       [device] uint8[total nodes] out
+ *   num, den     [device] int64[G] out: |E(S_g)|, |S_g|
+ *   D            [device] double[G] out: each graph's bound at its last check;
+ *                may be NULL
+ *   sweeps_used  [device] int32[G] out: sweeps each graph ran; may be NULL
+ * Returns LOWD_OK when every graph is within tol, LOWD_NOT_CONVERGED (> 0,
+ * outputs written) when some graph reached max_sweeps first.  Graphs whose
+ * nodes do not fit one workgroup's LDS are rejected with LOWD_E_UNSUPPORTED.
+ * Synchronises `stream`.
  */
 lowd_status lowd_batch_solve(int32_t G, const int64_t *node_ptr, const int64_t *edge_ptr,
                              const int32_t *src, const int32_t *dst, int32_t state,
-                             int32_t star_max, int32_t sweeps, uint8_t *in_set, int64_t *num,
-                             int64_t *den, double *load, void *stream);
+                             int32_t star_max, double tol, int32_t max_sweeps,
+                             int32_t check_every, uint8_t *in_set, int64_t *num, int64_t *den,
+                             double *D, int32_t *sweeps_used, void *stream);
 
 /*
  * The batched form in steps, for solving to a tolerance: a prepared batch
  * keeps its schedules, fractions and loads on the device between calls.
- * lowd_batch_solve is lowd_batch_prepare + lowd_batch_iterate +
- * lowd_batch_extract.
+ * lowd_batch_solve is lowd_batch_prepare + lowd_batch_solve_prepared.
  */
 typedef struct lowd_batch lowd_batch;
 
@@ -442,6 +491,16 @@ lowd_status lowd_batch_extract(lowd_batch *b, uint8_t *in_set, int64_t *num, int
 lowd_status lowd_batch_retire(lowd_batch *b, const int64_t *num, const int64_t *den,
                               const double *D, double tol, int32_t *active, int64_t *active_edges,
                               void *stream);
+
+/*
+ * lowd_batch_solve_prepared -- lowd_batch_solve on a prepared batch, from
+ * its current state (lowd_batch_reset first for a fresh solve); the same
+ * arguments from tol on.  Sweeps are counted from this call.
+ */
+lowd_status lowd_batch_solve_prepared(lowd_batch *b, double tol, int32_t max_sweeps,
+                                      int32_t check_every, uint8_t *in_set, int64_t *num,
+                                      int64_t *den, double *D, int32_t *sweeps_used,
+                                      void *stream);
 
 /*
  * lowd_batch_info --

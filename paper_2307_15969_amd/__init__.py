@@ -9,7 +9,6 @@ no CPU fallback: if the library is missing, every call raises.
 from __future__ import annotations
 
 import ctypes as C
-import math
 import os
 from typing import Optional
 
@@ -54,6 +53,8 @@ def lib() -> C.CDLL:
         L.lowd_extract_densest.argtypes = [vp, vp, P(i64), P(C.c_double), P(i64),
                                            P(C.c_double), P(C.c_double), vp]
         L.lowd_check_kept.argtypes = L.lowd_check.argtypes
+        L.lowd_solve.argtypes = [vp, C.c_double, i32, i32, vp, P(i64), P(C.c_double), P(i64),
+                                 P(C.c_double), P(C.c_double), P(i32), vp]
         L.lowd_resync_loads.argtypes = [vp, vp]
         L.lowd_extract_densest_kept.argtypes = L.lowd_extract_densest.argtypes
         L.lowd_read_state.argtypes = [vp, vp, vp, vp]
@@ -65,7 +66,9 @@ def lib() -> C.CDLL:
         L.lowd_schedule_build.argtypes = [i32, i64, vp, vp, i32, vp, vp, P(i32)]
         L.lowd_solver_free.argtypes = [vp]
         L.lowd_solver_free.restype = None
-        L.lowd_batch_solve.argtypes = [i32, vp, vp, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp]
+        L.lowd_batch_solve.argtypes = [i32, vp, vp, vp, vp, i32, i32, C.c_double, i32, i32, vp, vp,
+                                       vp, vp, vp, vp]
+        L.lowd_batch_solve_prepared.argtypes = [vp, C.c_double, i32, i32, vp, vp, vp, vp, vp, vp]
         L.lowd_batch_prepare.argtypes = [i32, vp, vp, vp, vp, i32, i32, i32, P(vp), vp]
         L.lowd_batch_reset.argtypes = [vp, vp]
         L.lowd_batch_iterate.argtypes = [vp, i32, vp]
@@ -80,7 +83,8 @@ def lib() -> C.CDLL:
                   L.lowd_solver_info, L.lowd_batch_solve, L.lowd_schedule_build, L.lowd_reset_loads,
                   L.lowd_batch_prepare, L.lowd_batch_reset, L.lowd_batch_iterate,
                   L.lowd_batch_extract, L.lowd_batch_info, L.lowd_batch_retire,
-                  L.lowd_check_kept, L.lowd_extract_densest_kept, L.lowd_resync_loads):
+                  L.lowd_check_kept, L.lowd_extract_densest_kept, L.lowd_resync_loads,
+                  L.lowd_solve, L.lowd_batch_solve_prepared):
             f.restype = C.c_int32
         _lib = L
     return _lib
@@ -269,6 +273,21 @@ class Solver:
         return dict(in_set=in_set, num=int(nu.value), num_w=float(nw.value), den=int(den.value),
                     D=float(D.value), gap=float(gap.value))
 
+    def solve(self, tol: float = 1e-6, max_sweeps: int = 10000, check_every: int = 10,
+              stream=None) -> dict:
+        """lowd_solve from the current state: in_set (device), num (|E(S)|
+        for unit weights), num_w, den, D, gap, sweeps and converged."""
+        torch = _torch()
+        in_set = torch.empty(self.n, dtype=torch.uint8, device=self.device)
+        nu, nw, den, D, gap = C.c_int64(), C.c_double(), C.c_int64(), C.c_double(), C.c_double()
+        sw = C.c_int32()
+        st = _check(lib().lowd_solve(self._h, float(tol), int(max_sweeps), int(check_every),
+                                     _ptr(in_set), C.byref(nu), C.byref(nw), C.byref(den),
+                                     C.byref(D), C.byref(gap), C.byref(sw), _stream(stream)))
+        return dict(in_set=in_set, num=int(nu.value), num_w=float(nw.value), den=int(den.value),
+                    D=float(D.value), gap=float(gap.value), sweeps=int(sw.value),
+                    converged=st == 0)
+
     def ldd(self, stream=None) -> dict:
         """The locally-dense decomposition read from the current loads:
         level per node (device int32), level ends k_end and f_end (numpy)."""
@@ -316,119 +335,57 @@ class Solver:
         return {k: int(v) for k, v in zip(keys, a)}
 
 
-def next_check(history, tol: float, check_every: int) -> int:
-    """Sweeps to run before the next check, from the (sweeps, gap) history:
-    the gap of LOWD decays about geometrically, so the last two checks
-    predict when it reaches tol; at most check_every, at least 1."""
-    if len(history) >= 2:
-        (t0, g0), (t1, g1) = history[-2], history[-1]
-        if 0.0 < g1 < g0 and t1 > t0 and g1 > tol:
-            rate = (g1 / g0) ** (1.0 / (t1 - t0))
-            if rate < 1.0:
-                k = math.ceil(math.log(tol / g1) / math.log(rate))
-                return max(1, min(check_every, k))
-    return check_every
-
-
-def _density(ex: dict) -> float:
-    return (ex["num_w"] if ex.get("weighted") else ex["num"]) / ex["den"] if ex["den"] else 0.0
-
-
-def _gap(D: float, rho: float) -> float:
-    return (D - rho) / rho if rho > 0 else (0.0 if D <= 0 else math.inf)
-
-
-def certify(sv: "Solver", best, tol: float, stream=None):
-    """One convergence check.  D, the largest load, bounds the optimum from
-    above at every sweep and any extracted set bounds it from below, so the
-    best set extracted so far is certified once (D - rho_best) / rho_best is
-    at most tol.  D alone is cheap; the extraction (a sort of all nodes) runs
-    only when D does not certify the best set already.  Both read the loads
-    as kept; for FP32K these only estimate the loads of the stored fractions,
-    so a gap within tol is confirmed with the exact D (recomputed from the
-    fractions) before it is returned, and a gap above tol only steers the
-    next check.  Returns (best, gap): best is the densest extraction so far
-    (its "D" and "gap" updated to this check)."""
-    exact = sv.state == "f64"   # the kept loads are the loads
-
-    def confirm(best, D, gap):
-        if gap <= tol and not exact:
-            D = sv.check(stream)[0]
-            gap = _gap(D, _density(best))
-            if gap > tol:   # the carried loads drifted from the fractions' loads
-                sv.resync(stream)
-        return dict(best, D=D, gap=gap), gap
-
-    if best is not None:
-        D = sv.check(stream, kept=True)[0]
-        gap = _gap(D, _density(best))
-        if gap <= tol:
-            best, gap = confirm(best, D, gap)
-            if gap <= tol:
-                return best, gap
-    ex = sv.extract(stream, kept=True)
-    ex["weighted"] = sv.weighted
-    if best is None or _density(ex) >= _density(best):
-        best = ex
-    return confirm(best, ex["D"], _gap(ex["D"], _density(best)))
+LOWD_NOT_CONVERGED = 1
 
 
 def solve(n: int, src, dst, w=None, state: str = "f64", star_max: int = 16, tol: float = 1e-6,
           check_every: int = 10, max_sweeps: int = 10000, stream=None) -> dict:
-    """Sweeps until the density gap (D - rho) / rho is at most `tol` (D is
-    the dual objective, an upper bound on the optimum; rho the density of the
-    extracted set, a lower bound), checking at most every `check_every`
-    sweeps (sooner when the gap's decay predicts the tolerance, next_check).
-    The first check comes after the first sweeps, not at the initial state:
-    its gap only feeds the decay estimate, and the decay of the first sweeps
-    is much faster than the later one it would be used to predict."""
+    """A new solver for the graph, then lowd_solve: sweeps until the density
+    gap (D - rho) / rho is at most `tol` (Section III-B's bounds) or
+    max_sweeps.  Returns the dict of Solver.solve plus the solver itself."""
     sv = Solver(n, src, dst, w, state, star_max, stream)
-    sweeps = 0
-    ex = None
-    gap = math.inf
-    hist = []
-    while sweeps < max_sweeps and gap > tol:
-        k = min(next_check(hist, tol, check_every), max_sweeps - sweeps)
-        sv.iterate(k, stream)
-        sweeps += k
-        ex, gap = certify(sv, ex, tol, stream)
-        hist.append((sweeps, gap))
-    if ex is None:   # max_sweeps == 0
-        ex, gap = certify(sv, None, tol, stream)
-    if gap > tol and state != "f64":   # stopped at max_sweeps: report the exact D
-        D = sv.check(stream)[0]
-        ex = dict(ex, D=D, gap=_gap(D, _density(ex)))
-    ex["sweeps"] = sweeps
+    ex = sv.solve(tol, max_sweeps, check_every, stream)
     ex["solver"] = sv
     return ex
 
 
-def batch_solve(graphs, sweeps: int, state: str = "f64", star_max: int = 16, stream=None,
-                return_loads: bool = True) -> dict:
-    """Many unweighted graphs (each with .n, .src, .dst in local ids) solved
-    in one persistent launch: `sweeps` sweeps each, then every graph's
-    densest set.  Returns per-graph num/den (int64 numpy), the concatenated
-    in_set and loads (device tensors) and node offsets."""
+def batch_solve(graphs, tol: float = 1e-6, state: str = "f64", star_max: int = 16,
+                max_sweeps: int = 20000, check_every: int = 10, stream=None) -> dict:
+    """Many unweighted graphs (each with .n, .src, .dst in local ids), each
+    solved to a certified gap `tol` (lowd_batch_solve).  Returns per-graph
+    num/den/D/sweeps (numpy), the concatenated in_set (device tensor), node
+    and edge offsets, and whether every graph converged."""
     torch = _torch()
     G = len(graphs)
-    node_ptr = np.zeros(G + 1, dtype=np.int64)
-    edge_ptr = np.zeros(G + 1, dtype=np.int64)
-    for i, g in enumerate(graphs):
-        node_ptr[i + 1] = node_ptr[i] + g.n
-        edge_ptr[i + 1] = edge_ptr[i] + g.src.size
-    src = torch.from_numpy(np.concatenate([g.src for g in graphs]).astype(np.int32)).cuda()
-    dst = torch.from_numpy(np.concatenate([g.dst for g in graphs]).astype(np.int32)).cuda()
+    node_ptr, edge_ptr, src, dst = _batch_arrays(graphs)
     N = int(node_ptr[-1])
-    in_set = torch.empty(N, dtype=torch.uint8, device=src.device)
+    in_set = torch.empty(max(N, 1), dtype=torch.uint8, device=src.device)
     num = torch.empty(G, dtype=torch.int64, device=src.device)
     den = torch.empty(G, dtype=torch.int64, device=src.device)
-    load = torch.empty(N, dtype=torch.float64, device=src.device) if return_loads else None
-    _check(lib().lowd_batch_solve(G, node_ptr.ctypes.data_as(C.c_void_p),
-                                  edge_ptr.ctypes.data_as(C.c_void_p), _ptr(src), _ptr(dst),
-                                  _STATES[state], star_max, sweeps, _ptr(in_set), _ptr(num),
-                                  _ptr(den), _ptr(load), _stream(stream)))
-    return dict(num=num.cpu().numpy(), den=den.cpu().numpy(), in_set=in_set, load=load,
-                node_ptr=node_ptr, edge_ptr=edge_ptr)
+    D = torch.empty(G, dtype=torch.float64, device=src.device)
+    used = torch.empty(G, dtype=torch.int32, device=src.device)
+    st = _check(lib().lowd_batch_solve(G, node_ptr.ctypes.data_as(C.c_void_p),
+                                       edge_ptr.ctypes.data_as(C.c_void_p), _ptr(src), _ptr(dst),
+                                       _STATES[state], star_max, float(tol), int(max_sweeps),
+                                       int(check_every), _ptr(in_set), _ptr(num), _ptr(den),
+                                       _ptr(D), _ptr(used), _stream(stream)))
+    return dict(num=num.cpu().numpy(), den=den.cpu().numpy(), D=D.cpu().numpy(),
+                sweeps=used.cpu().numpy(), in_set=in_set[:N], node_ptr=node_ptr,
+                edge_ptr=edge_ptr, converged=st == 0)
+
+
+def batch_run(graphs, sweeps: int, state: str = "f64", star_max: int = 16, stream=None) -> dict:
+    """A fixed number of sweeps on every graph of a batch (lowd_batch_prepare,
+    lowd_batch_iterate, lowd_batch_extract): per-graph num/den (numpy), the
+    concatenated in_set and FP64 loads (device), node and edge offsets."""
+    b = Batch(graphs, state, star_max, stream=stream)
+    b.iterate(sweeps, stream)
+    b.extract(stream, loads=True)
+    out = dict(num=b.num.cpu().numpy(), den=b.den.cpu().numpy(), in_set=b.in_set.clone(),
+               load=b.load.clone(), D=b.D.cpu().numpy(), node_ptr=b.node_ptr,
+               edge_ptr=b.edge_ptr)
+    b.close()
+    return out
 
 
 def dks_bound(k_end: np.ndarray, f_end: np.ndarray, k: int) -> float:
@@ -498,6 +455,19 @@ class Batch:
         _check(lib().lowd_batch_retire(self._h, _ptr(self.num), _ptr(self.den), _ptr(self.D),
                                        float(tol), C.byref(a), C.byref(ae), _stream(stream)))
         return a.value, ae.value
+
+    def solve(self, tol: float = 1e-6, max_sweeps: int = 20000, check_every: int = 10,
+              stream=None) -> dict:
+        """lowd_batch_solve_prepared from the current state into self.in_set,
+        num, den, D; returns per-graph sweeps (numpy) and whether every
+        graph converged."""
+        torch = _torch()
+        used = torch.empty(self.G, dtype=torch.int32, device=self.device)
+        st = _check(lib().lowd_batch_solve_prepared(self._h, float(tol), int(max_sweeps),
+                                                    int(check_every), _ptr(self.in_set),
+                                                    _ptr(self.num), _ptr(self.den), _ptr(self.D),
+                                                    _ptr(used), _stream(stream)))
+        return dict(sweeps=used.cpu().numpy(), converged=st == 0)
 
     def gaps(self):
         """Per-graph relative gap (D_g - rho_g) / rho_g after extract()."""

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <exception>
 #include <thread>
@@ -119,6 +120,7 @@ struct lowd_solver {
     ExtractScratch ex;
     LddScratch ldd;
     DBuf<uint8_t> ldd_in_set;
+    DBuf<uint8_t> solve_in_set;   // lowd_solve: each check's extraction
     // the other end of each incidence entry, and the nodes of degree >=
     // kBigRow, for the per-node kernels (initial loads, recompute, extraction)
     DBuf<int32_t> adj, big;
@@ -408,6 +410,149 @@ lowd_status lowd_extract_densest_kept(lowd_solver *sv, uint8_t *in_set, int64_t 
     return guarded([&] {
         extract_api(sv, true, in_set, num_unit, num_w, den, D, gap, (hipStream_t)stream);
     });
+}
+
+// ------------------------------------------------------------ solve ------
+// The stopping rule of Section III-B.  The largest load D bounds the maximum
+// density from above at every sweep (weak duality), and the density of any
+// extracted set bounds it from below, so the densest set extracted so far is
+// certified once (D - rho_best) / rho_best <= tol.
+}  // extern "C"
+
+namespace {
+
+struct Extracted {
+    bool have = false;
+    int64_t num_unit = 0;   // |E(S)| (unit weights)
+    double num_w = 0.0;     // W(S) in FP64
+    int64_t den = 0;        // |S|
+};
+
+double relative_gap(double D, double rho) {
+    return rho > 0.0 ? (D - rho) / rho : (D > 0.0 ? 1.0e300 : 0.0);
+}
+
+double density_of(const Extracted &x) {
+    return x.den > 0 ? x.num_w / (double)x.den : 0.0;
+}
+
+// a at least as dense as b: exactly by cross-multiplication for unit
+// weights (|E| < 2^31 and |S| < 2^31, so the products fit in 63 bits)
+bool at_least_as_dense(const Extracted &a, const Extracted &b, bool weighted) {
+    if (weighted) return density_of(a) >= density_of(b);
+    return (__int128)a.num_unit * b.den >= (__int128)b.num_unit * a.den;
+}
+
+// Sweeps before the next check from the last two (sweeps, gap) records: the
+// gap decays about geometrically, so they predict when it reaches tol; at
+// most check_every, at least 1.
+int32_t next_check(const std::vector<std::pair<int64_t, double>> &hist, double tol,
+                   int32_t check_every) {
+    if (hist.size() >= 2) {
+        const auto &a = hist[hist.size() - 2];
+        const auto &b = hist[hist.size() - 1];
+        const double g0 = a.second, g1 = b.second;
+        if (g1 > 0.0 && g1 < g0 && b.first > a.first && g1 > tol) {
+            const double rate = std::pow(g1 / g0, 1.0 / (double)(b.first - a.first));
+            if (rate < 1.0) {
+                const double k = std::ceil(std::log(tol / g1) / std::log(rate));
+                if (k < (double)check_every) return (int32_t)std::max(1.0, k);
+            }
+        }
+    }
+    return check_every;
+}
+
+}  // namespace
+
+// One convergence check.  D alone is cheap; the extraction (a sort of every
+// node) runs only when D does not already certify the best set.  Both read
+// the loads as kept; for LOWD_STATE_F32K those only follow the loads of the
+// stored fractions, so a gap within tol is confirmed with the exact D
+// (recomputed from the fractions) before it counts, and when the exact D
+// fails where the kept one passed, the carried loads restart from the
+// fractions' loads.  Returns the gap of the best set; *D_out is the D it
+// was taken with.
+static double certify(lowd_solver *sv, Extracted &best, uint8_t *best_in_set, double tol,
+                      double *D_out, hipStream_t s) {
+    const bool exact = sv->state == LOWD_STATE_F64;
+    auto confirm = [&](double D, double gap) {
+        if (gap <= tol && !exact) {
+            check_impl(sv, false, &D, nullptr, nullptr, s);
+            gap = relative_gap(D, density_of(best));
+            if (gap > tol) {
+                loads_f64(sv, s, false);
+                sv->fn.write_loads(sv->n, sv->home.p, sv->L64.p, sv->E.p, s);
+                LOWD_HIP(hipGetLastError());
+            }
+        }
+        *D_out = D;
+        return gap;
+    };
+    if (best.have) {
+        double D = 0.0;
+        check_impl(sv, true, &D, nullptr, nullptr, s);
+        const double gap = relative_gap(D, density_of(best));
+        if (gap <= tol) {
+            const double g = confirm(D, gap);
+            if (g <= tol) return g;
+        }
+    }
+    if (sv->solve_in_set.n < (size_t)sv->n) sv->solve_in_set.alloc((size_t)sv->n);
+    Extracted ex;
+    ex.have = true;
+    double D = 0.0;
+    extract_api(sv, true, sv->solve_in_set.p, &ex.num_unit, &ex.num_w, &ex.den, &D, nullptr, s);
+    if (!best.have || at_least_as_dense(ex, best, sv->weighted)) {
+        best = ex;
+        LOWD_HIP(hipMemcpyAsync(best_in_set, sv->solve_in_set.p, (size_t)sv->n,
+                                hipMemcpyDeviceToDevice, s));
+    }
+    return confirm(D, relative_gap(D, density_of(best)));
+}
+
+extern "C" {
+
+lowd_status lowd_solve(lowd_solver *sv, double tol, int32_t max_sweeps, int32_t check_every,
+                       uint8_t *in_set, int64_t *num_unit, double *num_w, int64_t *den,
+                       double *D_out, double *gap_out, int32_t *sweeps_used, void *stream) {
+    bool converged = false;
+    lowd_status st = guarded([&] {
+        if (!sv) fail(LOWD_E_ARG, "solver is NULL");
+        if (!in_set) fail(LOWD_E_ARG, "in_set is NULL");
+        if (!(tol >= 0.0)) fail(LOWD_E_ARG, "tol must be >= 0");
+        if (max_sweeps < 0) fail(LOWD_E_ARG, "max_sweeps must be >= 0");
+        if (check_every < 1) fail(LOWD_E_ARG, "check_every must be >= 1");
+        hipStream_t s = (hipStream_t)stream;
+        Extracted best;
+        std::vector<std::pair<int64_t, double>> hist;
+        int32_t sweeps = 0;
+        double gap = 1.0e300, D = 0.0;
+        while (sweeps < max_sweeps && gap > tol) {
+            const int32_t k = std::min(next_check(hist, tol, check_every), max_sweeps - sweeps);
+            if (sv->exec)
+                for (int32_t t = 0; t < k; ++t) LOWD_HIP(hipGraphLaunch(sv->exec, s));
+            sweeps += k;
+            gap = certify(sv, best, in_set, tol, &D, s);
+            hist.emplace_back(sweeps, gap);
+        }
+        if (!best.have) gap = certify(sv, best, in_set, tol, &D, s);   // max_sweeps == 0
+        if (gap > tol && sv->state != LOWD_STATE_F64) {
+            // stopped at max_sweeps: report the bound of the stored fractions
+            check_impl(sv, false, &D, nullptr, nullptr, s);
+            gap = relative_gap(D, density_of(best));
+        }
+        LOWD_HIP(hipStreamSynchronize(s));
+        if (num_unit) *num_unit = sv->weighted ? 0 : best.num_unit;
+        if (num_w) *num_w = best.num_w;
+        if (den) *den = best.den;
+        if (D_out) *D_out = D;
+        if (gap_out) *gap_out = gap;
+        if (sweeps_used) *sweeps_used = sweeps;
+        converged = gap <= tol;
+    });
+    if (st == LOWD_OK && !converged) return LOWD_NOT_CONVERGED;
+    return st;
 }
 
 lowd_status lowd_convergence_trace(lowd_solver *sv, int32_t sweeps, int32_t every, double *out,
@@ -1102,28 +1247,81 @@ void lowd_batch_free(lowd_batch *b) {
     delete b;
 }
 
+// Solve to a tolerance, from the batch's current state: sweeps of the graphs
+// still iterating, k a launch, then every such graph's extraction and dual
+// bound, and the retirement of those within tol.  Once fewer than an eighth
+// of the graphs iterate, k doubles after each check up to 8 check_every
+// (FP64) or 4 check_every (FP32K): the few slow graphs then cost a check
+// more than a sweep, but a longer launch overshoots their convergence and,
+// for FP32K, lets the carried loads drift further between two restarts.
+lowd_status lowd_batch_solve_prepared(lowd_batch *b, double tol, int32_t max_sweeps,
+                                      int32_t check_every, uint8_t *in_set, int64_t *num,
+                                      int64_t *den, double *D, int32_t *sweeps_used,
+                                      void *stream) {
+    bool all_converged = false;
+    lowd_status st = guarded([&] {
+        if (!b) fail(LOWD_E_ARG, "batch is NULL");
+        if (!in_set || !num || !den) fail(LOWD_E_ARG, "in_set/num/den is NULL");
+        if (!(tol >= 0.0)) fail(LOWD_E_ARG, "tol must be >= 0");
+        if (max_sweeps < 0) fail(LOWD_E_ARG, "max_sweeps must be >= 0");
+        if (check_every < 1) fail(LOWD_E_ARG, "check_every must be >= 1");
+        hipStream_t s = (hipStream_t)stream;
+        std::vector<int32_t> used((size_t)b->G, 0);
+        const int32_t cap = (b->state == LOWD_STATE_F32K ? 4 : 8) * check_every;
+        int32_t sweeps = 0, k = check_every;
+        int32_t active = b->act_count;
+        // one check: every iterating graph's extraction and bound, then the
+        // retirement of those within tol
+        auto check = [&] {
+            lowd_status e = lowd_batch_extract(b, in_set, num, den, D, nullptr, stream);
+            if (e != LOWD_OK) fail(e, g_last_error);
+            const std::vector<int32_t> rank_before = b->rank_h;
+            e = lowd_batch_retire(b, b->r_num.p, b->r_den.p, b->r_D.p, tol, &active, nullptr,
+                                  stream);
+            if (e != LOWD_OK) fail(e, g_last_error);
+            for (int32_t g = 0; g < b->G; ++g)
+                if (rank_before[(size_t)g] >= 0 && b->rank_h[(size_t)g] < 0)
+                    used[(size_t)g] = sweeps;
+        };
+        if (max_sweeps == 0) check();
+        while (active > 0 && sweeps < max_sweeps) {
+            if ((int64_t)active * 8 < b->G) k = std::min(2 * k, cap);
+            const int32_t kk = std::min(k, max_sweeps - sweeps);
+            lowd_status it = lowd_batch_iterate(b, kk, stream);
+            if (it != LOWD_OK) fail(it, g_last_error);
+            sweeps += kk;
+            check();
+        }
+        for (int32_t g = 0; g < b->G; ++g)
+            if (b->rank_h[(size_t)g] >= 0) used[(size_t)g] = sweeps;
+        // the results of every graph (retired ones keep their last extraction)
+        const size_t gb = (size_t)b->G * 8;
+        LOWD_HIP(hipMemcpyAsync(num, b->r_num.p, gb, hipMemcpyDeviceToDevice, s));
+        LOWD_HIP(hipMemcpyAsync(den, b->r_den.p, gb, hipMemcpyDeviceToDevice, s));
+        if (D) LOWD_HIP(hipMemcpyAsync(D, b->r_D.p, gb, hipMemcpyDeviceToDevice, s));
+        LOWD_HIP(hipMemcpyAsync(in_set, b->r_in_set.p, (size_t)b->N, hipMemcpyDeviceToDevice, s));
+        if (sweeps_used)
+            LOWD_HIP(hipMemcpyAsync(sweeps_used, used.data(), used.size() * sizeof(int32_t),
+                                    hipMemcpyHostToDevice, s));
+        LOWD_HIP(hipStreamSynchronize(s));
+        all_converged = active == 0;
+    });
+    if (st == LOWD_OK && !all_converged) return LOWD_NOT_CONVERGED;
+    return st;
+}
+
 lowd_status lowd_batch_solve(int32_t G, const int64_t *node_ptr, const int64_t *edge_ptr,
                              const int32_t *src, const int32_t *dst, int32_t state,
-                             int32_t star_max, int32_t sweeps, uint8_t *in_set, int64_t *num,
-                             int64_t *den, double *load, void *stream) {
-    if (sweeps < 0) {
-        g_last_error = "sweeps must be >= 0";
-        return LOWD_E_ARG;
-    }
-    if (!in_set || !num || !den) {
-        g_last_error = "in_set/num/den is NULL";
-        return LOWD_E_ARG;
-    }
+                             int32_t star_max, double tol, int32_t max_sweeps,
+                             int32_t check_every, uint8_t *in_set, int64_t *num, int64_t *den,
+                             double *D, int32_t *sweeps_used, void *stream) {
     lowd_batch *b = nullptr;
     lowd_status st = lowd_batch_prepare(G, node_ptr, edge_ptr, src, dst, state, star_max, 0, &b,
                                         stream);
     if (st != LOWD_OK) return st;
     std::unique_ptr<lowd_batch, void (*)(lowd_batch *)> guard(b, lowd_batch_free);
-    st = lowd_batch_iterate(b, sweeps, stream);
-    if (st == LOWD_OK) st = lowd_batch_extract(b, in_set, num, den, nullptr, load, stream);
-    if (st == LOWD_OK)
-        st = guarded([&] { LOWD_HIP(hipStreamSynchronize((hipStream_t)stream)); });
-    return st;
+    return lowd_batch_solve_prepared(b, tol, max_sweeps, check_every, in_set, num, den, D,
+                                     sweeps_used, stream);
 }
 
 }  // extern "C"

@@ -159,26 +159,26 @@ __device__ __forceinline__ void load_tile(Tile<St, kWeighted> &tl, const PhaseDe
 template <class St, bool kWeighted, class LPtr>
 __device__ __forceinline__ void run_tile(Tile<St, kWeighted> &tl, int lane,
                                          typename St::X *__restrict__ slot_x, LPtr L) {
-    typename St::L Lc = L[tl.c];
-    typename St::L Ll[kMaxStar];
+    typename St::R Lc = St::to_f64(L[tl.c]);
+    typename St::R Ll[kMaxStar];
     typename St::X *px = slot_x + tl.base + lane;
     if (tl.depth == kMaxStar) {   // a full tile: one straight block
 #pragma unroll
-        for (int k = 0; k < kMaxStar; ++k) Ll[k] = L[tl.enc[k] & ~kCenterIsDst];
+        for (int k = 0; k < kMaxStar; ++k) Ll[k] = St::to_f64(L[tl.enc[k] & ~kCenterIsDst]);
 #pragma unroll
         for (int k = 0; k < kMaxStar; ++k)
             St::step_center(Lc, Ll[k], tl.enc[k] & kCenterIsDst, tl.x[k], tl.w[k]);
 #pragma unroll
         for (int k = 0; k < kMaxStar; ++k) {
             px[k * kWave] = tl.x[k];
-            L[tl.enc[k] & ~kCenterIsDst] = Ll[k];
+            L[tl.enc[k] & ~kCenterIsDst] = St::from_f64(Ll[k]);
         }
-        L[tl.c] = Lc;
+        L[tl.c] = St::from_f64(Lc);
         return;
     }
 #pragma unroll
     for (int k = 0; k < kMaxStar; ++k)
-        if (k < tl.depth) Ll[k] = L[tl.enc[k] & ~kCenterIsDst];
+        if (k < tl.depth) Ll[k] = St::to_f64(L[tl.enc[k] & ~kCenterIsDst]);
 #pragma unroll
     for (int k = 0; k < kMaxStar; ++k)
         if (k < tl.depth) St::step_center(Lc, Ll[k], tl.enc[k] & kCenterIsDst, tl.x[k], tl.w[k]);
@@ -186,10 +186,10 @@ __device__ __forceinline__ void run_tile(Tile<St, kWeighted> &tl, int lane,
     for (int k = 0; k < kMaxStar; ++k) {
         if (k < tl.depth) {
             px[k * kWave] = tl.x[k];
-            L[tl.enc[k] & ~kCenterIsDst] = Ll[k];
+            L[tl.enc[k] & ~kCenterIsDst] = St::from_f64(Ll[k]);
         }
     }
-    L[tl.c] = Lc;
+    L[tl.c] = St::from_f64(Lc);
 }
 
 // ---------------------------------------------- one tile, station form --
@@ -208,8 +208,8 @@ struct StationTile {
     uint32_t nx[kMaxStar];
     typename St::X x[kMaxStar];
     float w[kMaxStar];
-    typename St::L lc;
-    typename St::L ll[kMaxStar];
+    typename St::R lc;
+    typename St::R ll[kMaxStar];
 };
 
 // A tile's depth and first slot.  Tile t of a phase has depth
@@ -284,16 +284,16 @@ __device__ __forceinline__ void load_static(StationTile<St, kWeighted> &tl, cons
 template <class St, bool kWeighted>
 __device__ __forceinline__ void load_loads(StationTile<St, kWeighted> &tl, int lane,
                                            const typename St::L *E) {
-    tl.lc = E[tl.lane_entry];
+    tl.lc = St::to_f64(E[tl.lane_entry]);
     const typename St::L *pl = E + tl.base + lane;
     if (tl.depth == kMaxStar) {
 #pragma unroll
-        for (int k = 0; k < kMaxStar; ++k) tl.ll[k] = pl[k * kWave];
+        for (int k = 0; k < kMaxStar; ++k) tl.ll[k] = St::to_f64(pl[k * kWave]);
         return;
     }
 #pragma unroll
     for (int k = 0; k < kMaxStar; ++k)
-        if (k < tl.depth) tl.ll[k] = pl[k * kWave];
+        if (k < tl.depth) tl.ll[k] = St::to_f64(pl[k * kWave]);
 }
 
 // A row without a next station (padding, or a lane without a star) stores
@@ -312,7 +312,7 @@ __device__ __forceinline__ void run_station_tile(StationTile<St, kWeighted> &tl,
         for (int k = 0; k < kMaxStar; ++k) {
             px[k * kWave] = tl.x[k];
             const uint32_t nx = tl.nx[k] & ~kCenterIsDst;
-            E[nx != kNoStation ? nx : tl.sink] = tl.ll[k];
+            E[nx != kNoStation ? nx : tl.sink] = St::from_f64(tl.ll[k]);
         }
     } else {
 #pragma unroll
@@ -324,11 +324,11 @@ __device__ __forceinline__ void run_station_tile(StationTile<St, kWeighted> &tl,
             if (k < tl.depth) {
                 px[k * kWave] = tl.x[k];
                 const uint32_t nx = tl.nx[k] & ~kCenterIsDst;
-                E[nx != kNoStation ? nx : tl.sink] = tl.ll[k];
+                E[nx != kNoStation ? nx : tl.sink] = St::from_f64(tl.ll[k]);
             }
         }
     }
-    E[tl.cnext != kNoStation ? tl.cnext : tl.sink] = tl.lc;
+    E[tl.cnext != kNoStation ? tl.cnext : tl.sink] = St::from_f64(tl.lc);
 }
 
 // --------------------------------------------------- whole-GPU phase -----

@@ -25,6 +25,7 @@ namespace lowd {
 struct StateF64 {
     using X = double;
     using L = double;
+    using R = double;   // a load in registers
     static constexpr bool kRecompute = false;
     __host__ __device__ static inline X half_weight(float w) { return (double)w / 2.0; }
     __device__ static inline L infinite() { return __builtin_inf(); }
@@ -89,10 +90,18 @@ struct StateF64 {
     }
 };
 
-// FP32 fractions; FP32 loads carried as (s, c) with value s + c, where every
-// addition to a load is exact-error compensated (two-sum: the rounding error
-// of s + y is accumulated into c).  Differences of loads are taken as
-// (s_u - s_v) + (c_u - c_v).
+// FP32 fractions; loads stored as compensated FP32 pairs (s, c) with value
+// s + c (s = the load rounded to FP32, c = the rest rounded to FP32: about
+// 48 significant bits), in the station array, in LDS and between launches.
+// A star's chain runs in FP64 registers: its loads are widened once when
+// the tile reads them and rounded back to pairs once when it writes them,
+// and each step is StateF64's step on the widened loads, with the fraction
+// widened from FP32 and its new value rounded back to FP32.  So the
+// dependent path of a step is FP64's, while the stored fractions take 4
+// bytes.  The loads move by the step's exact d, the fractions by d rounded
+// to FP32, so over many sweeps the carried loads can drift from the loads
+// of the stored fractions (which alone form a feasible dual point); the
+// checks recompute the latter in FP64 (kRecompute).
 struct LoadK32 {
     float s, c;
 };
@@ -100,51 +109,24 @@ struct LoadK32 {
 struct StateF32K {
     using X = float;
     using L = LoadK32;
+    using R = double;
     static constexpr bool kRecompute = true;
     __host__ __device__ static inline X half_weight(float w) { return w * 0.5f; }
     __device__ static inline L infinite() { return L{__builtin_inff(), 0.0f}; }
+    // the pair of v: s = v rounded to FP32, c = (v - s) rounded to FP32
+    // (v - s is exact in FP64); an infinite v (the padding leaf) keeps c = 0
     __device__ static inline L from_f64(double v) {
         L r;
         r.s = (float)v;
-        r.c = (float)(v - (double)r.s);
+        const float c = (float)(v - (double)r.s);
+        r.c = __builtin_isinf(r.s) ? 0.0f : c;
         return r;
     }
     __device__ static inline double to_f64(L v) { return (double)v.s + (double)v.c; }
-    __device__ static inline void add(L &a, float y) {
-        const float t = a.s + y;
-        const float z = t - a.s;
-        const float e = (a.s - (t - z)) + (y - z);
-        a.s = t;
-        a.c = a.c + e;
-    }
-    __device__ static inline void step(L &lu, L &lv, X &x, float w) {
-        const float a = x;
-        const float b = w - a;
-        const float diff = (lu.s - lv.s) + (lu.c - lv.c);
-        const bool down = diff > 0.0f;
-        const float half = __builtin_fabsf(diff) * 0.5f;
-        const float cap = down ? a : b;
-        const float d = half < cap ? half : cap;
-        const float du = down ? -d : d;               // change of l_u
-        add(lu, du);
-        add(lv, -du);
-        x = down ? a - d : ((d == b) ? w : a + d);
-    }
-    __device__ static inline void step_center(L &lc, L &ll, uint32_t flip, X &x, float w) {
-        const float a = x;
-        const float b = w - a;
-        const float diff = (lc.s - ll.s) + (lc.c - ll.c);
-        const float sdiff = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, diff) ^ flip);
-        const bool down = sdiff > 0.0f;
-        const float half = __builtin_fabsf(diff) * 0.5f;
-        const float cap = down ? a : b;
-        const float d = half < cap ? half : cap;
-        const uint32_t sx = down ? 0x80000000u : 0u;
-        const float dc = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, d) ^ sx ^ flip);
-        add(lc, dc);
-        add(ll, -dc);
-        const float xs = a + __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, d) ^ sx);
-        x = (!down && d == b) ? w : xs;
+    __device__ static inline void step_center(R &lc, R &ll, uint32_t flip, X &x, float w) {
+        double xd = (double)x;
+        StateF64::step_center(lc, ll, flip, xd, w);
+        x = (float)xd;
     }
 };
 

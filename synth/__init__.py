@@ -2,7 +2,7 @@
 oracle's callers.
 
 This module holds no part of the densest-subgraph method: it only draws graphs.
-Every graph comes back in the canonical form the method assumes (Section V,
+Every graph comes back in the canonical form the method assumes (Section IV,
 experimental setup: multi-edges and self-loops removed, direction ignored):
 
     n    : number of nodes, ids in [0, n)
@@ -152,36 +152,94 @@ def chung_lu(n: int, m: int, beta: float, seed: int, planted: int = 0, p_planted
     return g
 
 
+_M64 = (1 << 64) - 1
+
+
+def _s64(c: int) -> int:
+    """A 64-bit constant as the signed value torch's int64 holds."""
+    return c - (1 << 64) if c >= (1 << 63) else c
+
+
+def _mix64(torch, z):
+    """SplitMix64's output mix (Steele, Lea and Flood 2014) on an int64
+    tensor, with logical right shifts; products wrap modulo 2^64 on every
+    device, so CPU and GPU give the same bits."""
+    z = z ^ ((z >> 30) & ((1 << 34) - 1))
+    z = z * _s64(0xBF58476D1CE4E5B9)
+    z = z ^ ((z >> 27) & ((1 << 37) - 1))
+    z = z * _s64(0x94D049BB133111EB)
+    return z ^ ((z >> 31) & ((1 << 33) - 1))
+
+
+def _hash_stream(torch, seed: int, stream: int, index):
+    """Counter-based random words: the SplitMix64 mix of (seed, stream,
+    index), so any element can be drawn on its own, on any device."""
+    return _mix64(torch, index * _s64(0x9E3779B97F4A7C15) + _s64(_mix64_int(seed, stream)))
+
+
+def _mix64_int(seed: int, stream: int) -> int:
+    """The stream's offset: SplitMix64's mix of (seed, stream) in Python
+    integers, so that streams are unrelated (not shifted copies)."""
+    z = (((seed & 0xFFFFFFFF) << 32) | (stream & 0xFFFFFFFF)) * 0x9E3779B97F4A7C15 & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
 def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c: float = 0.19,
-         seed: int = 1, permute: bool = True, samples: Optional[int] = None) -> Graph:
-    """R-MAT: `edge_factor * 2^scale` samples, quadrant probabilities
-    (a, b, c, d=1-a-b-c) at every level, no noise; random vertex permutation;
-    symmetrised and de-duplicated."""
-    rng = np.random.default_rng(seed)
+         seed: int = 1, permute: bool = True, samples: Optional[int] = None,
+         device: str = "cpu") -> Graph:
+    """R-MAT: `edge_factor * 2^scale` samples; at each of the `scale` levels
+    a sample picks quadrant (0,0), (0,1), (1,0), (1,1) with probabilities
+    (a, b, c, d = 1-a-b-c), each level from 16 random bits (probabilities
+    rounded to multiples of 2^-16), no noise; node ids permuted by a random
+    permutation; symmetrised and de-duplicated.  The random bits are a
+    counter-based hash, so the graph is the same on the CPU and on a GPU
+    (device="cuda" draws 2^28 samples in about a second)."""
+    import torch
     n = 1 << scale
     k_total = samples if samples is not None else edge_factor * n
-    src = np.empty(k_total, dtype=np.int64)
-    dst = np.empty(k_total, dtype=np.int64)
-    ab = a + b
-    abc = a + b + c
-    chunk = 1 << 23
-    for s in range(0, k_total, chunk):
-        k = min(chunk, k_total - s)
-        u = np.zeros(k, dtype=np.int64)
-        v = np.zeros(k, dtype=np.int64)
-        for _ in range(scale):
-            r = rng.random(k, dtype=np.float32)
-            ubit = (r >= ab).astype(np.int64)
-            vbit = (((r >= a) & (r < ab)) | (r >= abc)).astype(np.int64)
-            u = (u << 1) | ubit
-            v = (v << 1) | vbit
-        src[s:s + k] = u
-        dst[s:s + k] = v
-    if permute:
-        perm = rng.permutation(n).astype(np.int64)
-        src = perm[src]
-        dst = perm[dst]
-    return canonical(n, src, dst, None, f"rmat{scale}_{edge_factor}")
+    ta = int(round(a * 65536))
+    tab = int(round((a + b) * 65536))
+    tabc = int(round((a + b + c) * 65536))
+    words = (scale + 3) // 4            # 64 bits = four 16-bit draws per word
+    keys = []
+    chunk = 1 << 26
+    for s0 in range(0, k_total, chunk):
+        k = min(chunk, k_total - s0)
+        idx = torch.arange(s0, s0 + k, dtype=torch.int64, device=device)
+        u = torch.zeros(k, dtype=torch.int64, device=device)
+        v = torch.zeros(k, dtype=torch.int64, device=device)
+        lvl = 0
+        for j in range(words):
+            h = _hash_stream(torch, seed, 1 + j, idx)
+            for q in range(4):
+                if lvl == scale:
+                    break
+                r = (h >> (16 * q)) & 0xFFFF
+                ubit = (r >= tab).to(torch.int64)
+                vbit = (((r >= ta) & (r < tab)) | (r >= tabc)).to(torch.int64)
+                u = (u << 1) | ubit
+                v = (v << 1) | vbit
+                lvl += 1
+        keep = u != v
+        u, v = u[keep], v[keep]
+        if permute:
+            if s0 == 0:
+                nodes = torch.arange(n, dtype=torch.int64, device=device)
+                perm = torch.argsort(_hash_stream(torch, seed, 0, nodes), stable=True)
+            u = perm[u]
+            v = perm[v]
+        lo = torch.minimum(u, v)
+        hi = torch.maximum(u, v)
+        keys.append(torch.unique(lo * n + hi))
+        del idx, u, v, lo, hi
+    key = torch.unique(torch.cat(keys)) if len(keys) > 1 else keys[0]
+    del keys
+    src = (key // n).to(torch.int32).cpu().numpy()
+    dst = (key % n).to(torch.int32).cpu().numpy()
+    return Graph(int(n), np.ascontiguousarray(src), np.ascontiguousarray(dst), None,
+                 f"rmat{scale}_{edge_factor}")
 
 
 def batch_of_graphs(count: int = 4096, seed: int = 1, m_lo: int = 100, m_hi: int = 50000,
@@ -215,16 +273,29 @@ def batch_of_graphs(count: int = 4096, seed: int = 1, m_lo: int = 100, m_hi: int
     return out
 
 
-def uniform_pairs(log_n: int = 25, log_m: int = 28, seed: int = 1) -> Graph:
+def uniform_pairs(log_n: int = 22, log_m: int = 28, seed: int = 1, device: str = "cpu") -> Graph:
     """2^log_m uniform random pairs on 2^log_n nodes, self-loops and repeats
-    dropped (a handful at these sizes): a graph of small maximum degree,
-    whose sweep phases are few and wide (a diagnostic of the sweep's memory
-    bandwidth, not one of the paper's workloads)."""
-    rng = np.random.default_rng(seed)
+    dropped: a graph of small maximum degree, whose sweep phases are few and
+    wide (a diagnostic of the sweep's memory bandwidth, not one of the paper's
+    workloads).  Counter-based random bits, as for rmat()."""
+    import torch
     n, m = 1 << log_n, 1 << log_m
-    a = rng.integers(0, n, size=m, dtype=np.int64)
-    b = rng.integers(0, n, size=m, dtype=np.int64)
-    return canonical(n, a, b, None, f"uniform_2^{log_n}_2^{log_m}")
+    keys = []
+    chunk = 1 << 26
+    for s0 in range(0, m, chunk):
+        k = min(chunk, m - s0)
+        idx = torch.arange(s0, s0 + k, dtype=torch.int64, device=device)
+        h = _hash_stream(torch, seed, 100, idx)
+        a = h & (n - 1)
+        b = (h >> 32) & (n - 1)
+        keep = a != b
+        a, b = a[keep], b[keep]
+        keys.append(torch.unique(torch.minimum(a, b) * n + torch.maximum(a, b)))
+    key = torch.unique(torch.cat(keys)) if len(keys) > 1 else keys[0]
+    src = (key // n).to(torch.int32).cpu().numpy()
+    dst = (key % n).to(torch.int32).cpu().numpy()
+    return Graph(int(n), np.ascontiguousarray(src), np.ascontiguousarray(dst), None,
+                 f"uniform_2^{log_n}_2^{log_m}")
 
 
 def random_small(rng: np.random.Generator, n: int, p: float, weighted: bool = False) -> Graph:

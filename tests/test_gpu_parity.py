@@ -718,7 +718,7 @@ def test_batch_matches_single_graph_oracle(T):
     loads bit-exact (FP64), densest set and exact density equal."""
     gs = batch_graphs(40, 3)
     log(f"batch of {len(gs)} graphs, T={T}")
-    r = lowd.batch_solve(gs, T, "f64")
+    r = lowd.batch_run(gs, T, "f64")
     L = r["load"].cpu().numpy()
     ins = r["in_set"].cpu().numpy()
     for i, g in enumerate(gs):
@@ -733,7 +733,7 @@ def test_batch_matches_single_graph_oracle(T):
 def test_batch_f32k_within_tolerance():
     gs = batch_graphs(20, 5)
     T = 30
-    r = lowd.batch_solve(gs, T, "f32k")
+    r = lowd.batch_run(gs, T, "f32k")
     L = r["load"].cpu().numpy()
     for i, g in enumerate(gs):
         a, b = r["node_ptr"][i], r["node_ptr"][i + 1]
@@ -879,7 +879,7 @@ def test_batch_rejects_bad_graphs():
     g = synth.canonical(5, np.array([0, 1]), np.array([1, 2]))
     bad = synth.Graph(3, np.array([0, 1], np.int32), np.array([1, 5], np.int32), None)
     with pytest.raises(lowd.LowdError) as ei:
-        lowd.batch_solve([g, bad], 1)
+        lowd.batch_solve([g, bad])
     assert ei.value.status == -2
 
 
