@@ -382,15 +382,23 @@ void lowd_solver_free(lowd_solver *s);
 
 /*
  * lowd_batch_solve -- many independent unweighted graphs, each solved to a
- * certified density gap (Section III-B, as lowd_solve): Algorithm 1 on every
- * graph in its own schedule, one workgroup per graph with its loads held in
- * LDS, in persistent launches over the graphs still iterating.  A graph
- * stops (retires) at the first check where (D_g - rho_g) / rho_g <= tol,
- * D_g its largest load and rho_g the density of its extracted set; checks
- * come every check_every sweeps, and, once fewer than an eighth of the
- * graphs iterate, at doubling intervals (at most 8 check_every for FP64,
- * 4 check_every for FP32K).  Each graph's set is that of its own
- * single-graph iteration after its sweeps_used sweeps.
+ * certified density gap (Section III-B, as lowd_solve), in one persistent
+ * launch (captured in a HIP graph): a workgroup takes the next graph (the
+ * largest first) and solves it alone, with its loads in LDS: sweeps of
+ * Algorithm 1 in the graph's own schedule and, every few sweeps, a check
+ * inside the workgroup: the loads' maximum D_g, then, unless D_g already
+ * certifies the densest set found so far, Algorithm 1's extraction (sort by
+ * load, densest removal prefix).  The graph stops at the first check where
+ * (D_g - rho_g) / rho_g <= tol, rho_g the density of its densest set so
+ * far, or at max_sweeps.  For LOWD_STATE_F32K the checks read the kept
+ * compensated loads, and a gap within tol is confirmed with D_g recomputed
+ * in FP64 from the stored fractions (the loads of a feasible dual point);
+ * the carried loads then restart from those loads, so a failed
+ * confirmation leaves no drift behind.
+ * Checks come every check_every sweeps, sooner when the gap's decay over
+ * the last two checks predicts the tolerance.  The set of each graph is
+ * Algorithm 1's extraction after set_sweeps[g] sweeps of its single-graph
+ * iteration (with the same star_max).
  *
  *   G            number of graphs (>= 1)
  *   node_ptr     [host] int64[G+1]: graph g owns nodes node_ptr[g]..node_ptr[g+1]-1
@@ -400,22 +408,27 @@ void lowd_solver_free(lowd_solver *s);
  *   star_max     as for lowd_init_loads
  *   tol          relative gap (>= 0)
  *   max_sweeps   sweep limit per graph (>= 0)
- *   check_every  sweeps between the first checks (>= 1)
+ *   check_every  most sweeps between two checks (>= 1)
  *   in_set       [device] uint8[total nodes] out
  *   num, den     [device] int64[G] out: |E(S_g)|, |S_g|
  *   D            [device] double[G] out: each graph's bound at its last check;
  *                may be NULL
  *   sweeps_used  [device] int32[G] out: sweeps each graph ran; may be NULL
+ *   set_sweeps   [device] int32[G] out: the sweep count at which each
+ *                graph's set was extracted; may be NULL
  * Returns LOWD_OK when every graph is within tol, LOWD_NOT_CONVERGED (> 0,
- * outputs written) when some graph reached max_sweeps first.  Graphs whose
- * nodes do not fit one workgroup's LDS are rejected with LOWD_E_UNSUPPORTED.
- * Synchronises `stream`.
+ * outputs written) when some graph reached max_sweeps first.  Every graph's
+ * phase descriptors and node loads must fit one workgroup's LDS beside the
+ * checks' own (about 18 KB): 80 bytes per phase plus 8 per node within
+ * 160 KB - 18 KB; larger graphs give LOWD_E_UNSUPPORTED.  Synchronises
+ * `stream`.
  */
 lowd_status lowd_batch_solve(int32_t G, const int64_t *node_ptr, const int64_t *edge_ptr,
                              const int32_t *src, const int32_t *dst, int32_t state,
                              int32_t star_max, double tol, int32_t max_sweeps,
                              int32_t check_every, uint8_t *in_set, int64_t *num, int64_t *den,
-                             double *D, int32_t *sweeps_used, void *stream);
+                             double *D, int32_t *sweeps_used, int32_t *set_sweeps,
+                             void *stream);
 
 /*
  * The batched form in steps, for solving to a tolerance: a prepared batch
@@ -500,7 +513,7 @@ lowd_status lowd_batch_retire(lowd_batch *b, const int64_t *num, const int64_t *
 lowd_status lowd_batch_solve_prepared(lowd_batch *b, double tol, int32_t max_sweeps,
                                       int32_t check_every, uint8_t *in_set, int64_t *num,
                                       int64_t *den, double *D, int32_t *sweeps_used,
-                                      void *stream);
+                                      int32_t *set_sweeps, void *stream);
 
 /*
  * lowd_batch_info --

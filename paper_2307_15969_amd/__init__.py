@@ -67,8 +67,9 @@ def lib() -> C.CDLL:
         L.lowd_solver_free.argtypes = [vp]
         L.lowd_solver_free.restype = None
         L.lowd_batch_solve.argtypes = [i32, vp, vp, vp, vp, i32, i32, C.c_double, i32, i32, vp, vp,
-                                       vp, vp, vp, vp]
-        L.lowd_batch_solve_prepared.argtypes = [vp, C.c_double, i32, i32, vp, vp, vp, vp, vp, vp]
+                                       vp, vp, vp, vp, vp]
+        L.lowd_batch_solve_prepared.argtypes = [vp, C.c_double, i32, i32, vp, vp, vp, vp, vp, vp,
+                                                vp]
         L.lowd_batch_prepare.argtypes = [i32, vp, vp, vp, vp, i32, i32, i32, P(vp), vp]
         L.lowd_batch_reset.argtypes = [vp, vp]
         L.lowd_batch_iterate.argtypes = [vp, i32, vp]
@@ -364,14 +365,15 @@ def batch_solve(graphs, tol: float = 1e-6, state: str = "f64", star_max: int = 1
     den = torch.empty(G, dtype=torch.int64, device=src.device)
     D = torch.empty(G, dtype=torch.float64, device=src.device)
     used = torch.empty(G, dtype=torch.int32, device=src.device)
+    at = torch.empty(G, dtype=torch.int32, device=src.device)
     st = _check(lib().lowd_batch_solve(G, node_ptr.ctypes.data_as(C.c_void_p),
                                        edge_ptr.ctypes.data_as(C.c_void_p), _ptr(src), _ptr(dst),
                                        _STATES[state], star_max, float(tol), int(max_sweeps),
                                        int(check_every), _ptr(in_set), _ptr(num), _ptr(den),
-                                       _ptr(D), _ptr(used), _stream(stream)))
+                                       _ptr(D), _ptr(used), _ptr(at), _stream(stream)))
     return dict(num=num.cpu().numpy(), den=den.cpu().numpy(), D=D.cpu().numpy(),
-                sweeps=used.cpu().numpy(), in_set=in_set[:N], node_ptr=node_ptr,
-                edge_ptr=edge_ptr, converged=st == 0)
+                sweeps=used.cpu().numpy(), set_sweeps=at.cpu().numpy(), in_set=in_set[:N],
+                node_ptr=node_ptr, edge_ptr=edge_ptr, converged=st == 0)
 
 
 def batch_run(graphs, sweeps: int, state: str = "f64", star_max: int = 16, stream=None) -> dict:
@@ -459,15 +461,16 @@ class Batch:
     def solve(self, tol: float = 1e-6, max_sweeps: int = 20000, check_every: int = 10,
               stream=None) -> dict:
         """lowd_batch_solve_prepared from the current state into self.in_set,
-        num, den, D; returns per-graph sweeps (numpy) and whether every
-        graph converged."""
+        num, den, D; returns per-graph sweeps, the sweep count of each set's
+        extraction (numpy) and whether every graph converged."""
         torch = _torch()
         used = torch.empty(self.G, dtype=torch.int32, device=self.device)
+        at = torch.empty(self.G, dtype=torch.int32, device=self.device)
         st = _check(lib().lowd_batch_solve_prepared(self._h, float(tol), int(max_sweeps),
                                                     int(check_every), _ptr(self.in_set),
                                                     _ptr(self.num), _ptr(self.den), _ptr(self.D),
-                                                    _ptr(used), _stream(stream)))
-        return dict(sweeps=used.cpu().numpy(), converged=st == 0)
+                                                    _ptr(used), _ptr(at), _stream(stream)))
+        return dict(sweeps=used.cpu().numpy(), set_sweeps=at.cpu().numpy(), converged=st == 0)
 
     def gaps(self):
         """Per-graph relative gap (D_g - rho_g) / rho_g after extract()."""

@@ -18,6 +18,7 @@
 #include "lowd_internal.h"
 #include "prune.h"
 #include "sweep_state.h"
+#include "wg_check.h"
 
 namespace lowd {
 
@@ -819,6 +820,26 @@ struct lowd_batch {
     int32_t graph_sweeps = -1, graph_shape = -1;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    int32_t per_cu = 1;   // workgroups per CU of the tuned shape
+    // the batched solve in one launch: the batch's adjacency (the other end
+    // of each incidence entry), per-node scratch of the in-kernel checks,
+    // the per-graph sweep counts, and the captured launch with its settings
+    DBuf<int32_t> adj;
+    DBuf<uint32_t> inc_slot;   // FP32K: slot << 1 | side of each incidence entry
+    DBuf<uint64_t> sk0, sk1;
+    DBuf<uint32_t> si0, si1;
+    DBuf<int32_t> spos, shist, r_sweeps, r_set;
+    hipGraph_t solve_graph = nullptr;
+    hipGraphExec_t solve_exec = nullptr;
+    int32_t solve_shape = -1, solve_blocks = -1, solve_max = -1, solve_every = -1;
+    double solve_tol = -1.0;
+    void drop_solve_graph() {
+        if (solve_exec) (void)hipGraphExecDestroy(solve_exec);
+        if (solve_graph) (void)hipGraphDestroy(solve_graph);
+        solve_exec = nullptr;
+        solve_graph = nullptr;
+        solve_shape = -1;
+    }
     void drop_graph() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -827,7 +848,10 @@ struct lowd_batch {
         graph_sweeps = -1;
         graph_shape = -1;
     }
-    ~lowd_batch() { drop_graph(); }
+    ~lowd_batch() {
+        drop_graph();
+        drop_solve_graph();
+    }
 };
 
 // The extraction's view of the graphs still iterating: act[0..A) as listed
@@ -931,6 +955,7 @@ static void batch_tune(lowd_batch *b, int32_t cus, hipStream_t s) {
     b->waves = pick.waves;
     b->prefetch = pick.prefetch;
     b->blocks = (int32_t)std::min<int64_t>((int64_t)cus * pick.per_cu, b->G);
+    b->per_cu = pick.per_cu;
     b->drop_graph();
     b->fn.set_batch_lds(b->shape(), b->lds);
 }
@@ -997,7 +1022,7 @@ lowd_status lowd_batch_prepare(int32_t G, const int64_t *node_ptr, const int64_t
         }
 
         // per-graph schedules (every phase from LDS), built in parallel
-        const int64_t lds_cap = (int64_t)lds_capacity_bytes() - 64;
+        const int64_t lds_cap = (int64_t)lds_capacity_bytes() - (int64_t)kWgCheckLdsMax;
         std::vector<Schedule> sch((size_t)G);
         {
             std::atomic<int32_t> next(0);
@@ -1064,10 +1089,17 @@ lowd_status lowd_batch_prepare(int32_t G, const int64_t *node_ptr, const int64_t
                 for (size_t e = 0; e < sc.edge_slot.size(); ++e)
                     edge_slot[(size_t)edge_ptr[g] + e] = slot0 + sc.edge_slot[e];
         }
+        // the incidence of the concatenated graphs and the other end of each
+        // entry: the in-kernel checks count each node's neighbours at higher
+        // positions, and FP32K recomputes the fractions' loads along it
+        build_incidence((int32_t)N, M, b->gsrc.p, b->gdst.p, b->csr, s);
+        b->adj.alloc((size_t)(2 * M > 0 ? 2 * M : 1));
+        if (M > 0) build_adjacency(M, b->csr, b->gsrc.p, b->gdst.p, b->adj.p, s);
         if (recompute) {
             upload(b->edge_slot, edge_slot, s);
-            build_incidence((int32_t)N, M, b->gsrc.p, b->gdst.p, b->csr, s);
             b->active_flag.alloc((size_t)G);
+            b->inc_slot.alloc((size_t)(2 * M));
+            launch_inc_slots(2 * M, b->csr.inc.p, b->edge_slot.p, b->inc_slot.p, s);
         }
         std::vector<int32_t> order((size_t)G);
         for (int32_t g = 0; g < G; ++g) order[(size_t)g] = g;
@@ -1102,7 +1134,7 @@ lowd_status lowd_batch_prepare(int32_t G, const int64_t *node_ptr, const int64_t
         b->L64.alloc((size_t)(N > 0 ? N : 1));
         b->deg.alloc((size_t)(N > 0 ? N : 1));
         launch_batch_degrees(N, M, b->gsrc.p, b->gdst.p, b->deg.p, s);
-        b->queue.alloc(1);
+        b->queue.alloc(2);
         b->lds = lds_need;
 
         int dev = 0, cus = 0;
@@ -1122,6 +1154,7 @@ lowd_status lowd_batch_prepare(int32_t G, const int64_t *node_ptr, const int64_t
             per_cu = pc;
         }
         b->blocks = (int32_t)std::min<int64_t>((int64_t)cus * per_cu, G);
+        b->per_cu = per_cu;
         b->cus = cus;
         b->fn.set_batch_lds(b->shape(), b->lds);
         if (tune) batch_tune(b, cus, s);
@@ -1247,18 +1280,15 @@ void lowd_batch_free(lowd_batch *b) {
     delete b;
 }
 
-// Solve to a tolerance, from the batch's current state: sweeps of the graphs
-// still iterating, k a launch, then every such graph's extraction and dual
-// bound, and the retirement of those within tol.  Once fewer than an eighth
-// of the graphs iterate, k doubles after each check up to 8 check_every
-// (FP64) or 4 check_every (FP32K): the few slow graphs then cost a check
-// more than a sweep, but a longer launch overshoots their convergence and,
-// for FP32K, lets the carried loads drift further between two restarts.
+// Solve to a tolerance, from the batch's current state, in one persistent
+// launch (k_batch_solve, captured as a HIP graph once per launch settings):
+// every graph still listed as iterating is swept and checked inside its
+// workgroup until its own certified gap is within tol or max_sweeps.
 lowd_status lowd_batch_solve_prepared(lowd_batch *b, double tol, int32_t max_sweeps,
                                       int32_t check_every, uint8_t *in_set, int64_t *num,
                                       int64_t *den, double *D, int32_t *sweeps_used,
-                                      void *stream) {
-    bool all_converged = false;
+                                      int32_t *set_sweeps, void *stream) {
+    unsigned unconverged = 0;
     lowd_status st = guarded([&] {
         if (!b) fail(LOWD_E_ARG, "batch is NULL");
         if (!in_set || !num || !den) fail(LOWD_E_ARG, "in_set/num/den is NULL");
@@ -1266,47 +1296,91 @@ lowd_status lowd_batch_solve_prepared(lowd_batch *b, double tol, int32_t max_swe
         if (max_sweeps < 0) fail(LOWD_E_ARG, "max_sweeps must be >= 0");
         if (check_every < 1) fail(LOWD_E_ARG, "check_every must be >= 1");
         hipStream_t s = (hipStream_t)stream;
-        std::vector<int32_t> used((size_t)b->G, 0);
-        const int32_t cap = (b->state == LOWD_STATE_F32K ? 4 : 8) * check_every;
-        int32_t sweeps = 0, k = check_every;
-        int32_t active = b->act_count;
-        // one check: every iterating graph's extraction and bound, then the
-        // retirement of those within tol
-        auto check = [&] {
-            lowd_status e = lowd_batch_extract(b, in_set, num, den, D, nullptr, stream);
-            if (e != LOWD_OK) fail(e, g_last_error);
-            const std::vector<int32_t> rank_before = b->rank_h;
-            e = lowd_batch_retire(b, b->r_num.p, b->r_den.p, b->r_D.p, tol, &active, nullptr,
-                                  stream);
-            if (e != LOWD_OK) fail(e, g_last_error);
-            for (int32_t g = 0; g < b->G; ++g)
-                if (rank_before[(size_t)g] >= 0 && b->rank_h[(size_t)g] < 0)
-                    used[(size_t)g] = sweeps;
-        };
-        if (max_sweeps == 0) check();
-        while (active > 0 && sweeps < max_sweeps) {
-            if ((int64_t)active * 8 < b->G) k = std::min(2 * k, cap);
-            const int32_t kk = std::min(k, max_sweeps - sweeps);
-            lowd_status it = lowd_batch_iterate(b, kk, stream);
-            if (it != LOWD_OK) fail(it, g_last_error);
-            sweeps += kk;
-            check();
+        const size_t N = (size_t)(b->N > 0 ? b->N : 1);
+        if (b->sk0.n < N) {
+            b->sk0.alloc(N);
+            b->sk1.alloc(N);
+            b->si0.alloc(N);
+            b->si1.alloc(N);
+            b->spos.alloc(N);
+            b->shist.alloc(N);
+            b->r_sweeps.alloc((size_t)b->G);
+            b->r_set.alloc((size_t)b->G);
         }
-        for (int32_t g = 0; g < b->G; ++g)
-            if (b->rank_h[(size_t)g] >= 0) used[(size_t)g] = sweeps;
-        // the results of every graph (retired ones keep their last extraction)
-        const size_t gb = (size_t)b->G * 8;
+        // the tuned shape, where its sweeps and checks fit the registers
+        // together without spilling (4 waves, or 8 without the prefetching
+        // tile buffer); else 8 waves without it
+        const int32_t shape = b->waves == 4 ? b->shape() : 8 * 2 + 0;
+        // workgroups: the tuned count per CU, as far as the checks' static LDS
+        // leaves room
+        const int64_t per_wg = (int64_t)b->lds + (int64_t)kWgCheckLdsMax;
+        const int32_t fit = (int32_t)std::max<int64_t>(1, (160 * 1024) / per_wg);
+        const int32_t blocks =
+            (int32_t)std::min<int64_t>((int64_t)b->cus * std::min(b->per_cu, fit), b->G);
+        if (!b->solve_exec || b->solve_shape != shape || b->solve_blocks != blocks ||
+            b->solve_tol != tol || b->solve_max != max_sweeps || b->solve_every != check_every) {
+            b->drop_solve_graph();
+            b->fn.set_batch_solve_lds(shape, b->lds);
+            BatchSolveArgs a;
+            a.active = b->active.p;
+            a.order = b->order.p;
+            a.queue = b->queue.p;
+            a.node_ptr = b->node_ptr.p;
+            a.desc_ptr = b->desc_ptr.p;
+            a.descs = b->descs.p;
+            a.tile_center = b->tile_center.p;
+            a.slot_leaf = b->slot_leaf.p;
+            a.slot_x = b->slot_x.p;
+            a.Lstate = b->Lstate.p;
+            a.row_ptr = b->csr.row_ptr.p;
+            a.adj = b->adj.p;
+            a.inc_slot = b->inc_slot.p;
+            a.k0 = b->sk0.p;
+            a.k1 = b->sk1.p;
+            a.i0 = b->si0.p;
+            a.i1 = b->si1.p;
+            a.pos = b->spos.p;
+            a.hist = b->shist.p;
+            a.tol = tol;
+            a.max_sweeps = max_sweeps;
+            a.check_every = check_every;
+            a.in_set = b->r_in_set.p;
+            a.num = b->r_num.p;
+            a.den = b->r_den.p;
+            a.D = b->r_D.p;
+            a.sweeps_used = b->r_sweeps.p;
+            a.set_sweeps = b->r_set.p;
+            hipStream_t cs;
+            LOWD_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (err == hipSuccess) {
+                b->fn.batch_solve(shape, a, b->lds, blocks, cs);
+                err = hipStreamEndCapture(cs, &b->solve_graph);
+            }
+            (void)hipStreamDestroy(cs);
+            LOWD_HIP(err);
+            LOWD_HIP(hipGraphInstantiate(&b->solve_exec, b->solve_graph, nullptr, nullptr, 0));
+            b->solve_shape = shape;
+            b->solve_blocks = blocks;
+            b->solve_tol = tol;
+            b->solve_max = max_sweeps;
+            b->solve_every = check_every;
+        }
+        LOWD_HIP(hipGraphLaunch(b->solve_exec, s));
+        const size_t gb = (size_t)b->G * 8, g4 = (size_t)b->G * 4;
         LOWD_HIP(hipMemcpyAsync(num, b->r_num.p, gb, hipMemcpyDeviceToDevice, s));
         LOWD_HIP(hipMemcpyAsync(den, b->r_den.p, gb, hipMemcpyDeviceToDevice, s));
         if (D) LOWD_HIP(hipMemcpyAsync(D, b->r_D.p, gb, hipMemcpyDeviceToDevice, s));
         LOWD_HIP(hipMemcpyAsync(in_set, b->r_in_set.p, (size_t)b->N, hipMemcpyDeviceToDevice, s));
         if (sweeps_used)
-            LOWD_HIP(hipMemcpyAsync(sweeps_used, used.data(), used.size() * sizeof(int32_t),
-                                    hipMemcpyHostToDevice, s));
+            LOWD_HIP(hipMemcpyAsync(sweeps_used, b->r_sweeps.p, g4, hipMemcpyDeviceToDevice, s));
+        if (set_sweeps)
+            LOWD_HIP(hipMemcpyAsync(set_sweeps, b->r_set.p, g4, hipMemcpyDeviceToDevice, s));
+        LOWD_HIP(hipMemcpyAsync(&unconverged, b->queue.p + 1, sizeof(unsigned),
+                                hipMemcpyDeviceToHost, s));
         LOWD_HIP(hipStreamSynchronize(s));
-        all_converged = active == 0;
     });
-    if (st == LOWD_OK && !all_converged) return LOWD_NOT_CONVERGED;
+    if (st == LOWD_OK && unconverged > 0) return LOWD_NOT_CONVERGED;
     return st;
 }
 
@@ -1314,14 +1388,15 @@ lowd_status lowd_batch_solve(int32_t G, const int64_t *node_ptr, const int64_t *
                              const int32_t *src, const int32_t *dst, int32_t state,
                              int32_t star_max, double tol, int32_t max_sweeps,
                              int32_t check_every, uint8_t *in_set, int64_t *num, int64_t *den,
-                             double *D, int32_t *sweeps_used, void *stream) {
+                             double *D, int32_t *sweeps_used, int32_t *set_sweeps,
+                             void *stream) {
     lowd_batch *b = nullptr;
     lowd_status st = lowd_batch_prepare(G, node_ptr, edge_ptr, src, dst, state, star_max, 0, &b,
                                         stream);
     if (st != LOWD_OK) return st;
     std::unique_ptr<lowd_batch, void (*)(lowd_batch *)> guard(b, lowd_batch_free);
     return lowd_batch_solve_prepared(b, tol, max_sweeps, check_every, in_set, num, den, D,
-                                     sweeps_used, stream);
+                                     sweeps_used, set_sweeps, stream);
 }
 
 }  // extern "C"

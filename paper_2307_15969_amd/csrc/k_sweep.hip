@@ -16,6 +16,7 @@
 // node's next station, so no read of a phase waits for an address.
 #include "lowd_internal.h"
 #include "sweep_state.h"
+#include "wg_check.h"
 
 namespace lowd {
 namespace {
@@ -159,26 +160,38 @@ __device__ __forceinline__ void load_tile(Tile<St, kWeighted> &tl, const PhaseDe
 template <class St, bool kWeighted, class LPtr>
 __device__ __forceinline__ void run_tile(Tile<St, kWeighted> &tl, int lane,
                                          typename St::X *__restrict__ slot_x, LPtr L) {
-    typename St::R Lc = St::to_f64(L[tl.c]);
+    using T = typename std::remove_cv<typename std::remove_reference<decltype(L[0])>::type>::type;
+    const T lc_raw = L[tl.c];
+    T raw[kMaxStar];
     typename St::R Ll[kMaxStar];
     typename St::X *px = slot_x + tl.base + lane;
     if (tl.depth == kMaxStar) {   // a full tile: one straight block
 #pragma unroll
-        for (int k = 0; k < kMaxStar; ++k) Ll[k] = St::to_f64(L[tl.enc[k] & ~kCenterIsDst]);
+        for (int k = 0; k < kMaxStar; ++k) raw[k] = L[tl.enc[k] & ~kCenterIsDst];
+        typename St::R Lc = widen(lc_raw);
+#pragma unroll
+        for (int k = 0; k < kMaxStar; ++k) Ll[k] = widen(raw[k]);
 #pragma unroll
         for (int k = 0; k < kMaxStar; ++k)
             St::step_center(Lc, Ll[k], tl.enc[k] & kCenterIsDst, tl.x[k], tl.w[k]);
 #pragma unroll
         for (int k = 0; k < kMaxStar; ++k) {
             px[k * kWave] = tl.x[k];
-            L[tl.enc[k] & ~kCenterIsDst] = St::from_f64(Ll[k]);
+            L[tl.enc[k] & ~kCenterIsDst] = narrow<T>(Ll[k]);
         }
-        L[tl.c] = St::from_f64(Lc);
+        L[tl.c] = narrow<T>(Lc);
         return;
     }
 #pragma unroll
-    for (int k = 0; k < kMaxStar; ++k)
-        if (k < tl.depth) Ll[k] = St::to_f64(L[tl.enc[k] & ~kCenterIsDst]);
+    for (int k = 0; k < kMaxStar; ++k) {
+        if (k < tl.depth) raw[k] = L[tl.enc[k] & ~kCenterIsDst];
+        else raw[k] = narrow<T>(__builtin_inf());
+    }
+    // widened after all the loads are issued (a conversion next to a guarded
+    // load makes the compiler wait for that load before issuing the next)
+    typename St::R Lc = widen(lc_raw);
+#pragma unroll
+    for (int k = 0; k < kMaxStar; ++k) Ll[k] = widen(raw[k]);
 #pragma unroll
     for (int k = 0; k < kMaxStar; ++k)
         if (k < tl.depth) St::step_center(Lc, Ll[k], tl.enc[k] & kCenterIsDst, tl.x[k], tl.w[k]);
@@ -186,10 +199,10 @@ __device__ __forceinline__ void run_tile(Tile<St, kWeighted> &tl, int lane,
     for (int k = 0; k < kMaxStar; ++k) {
         if (k < tl.depth) {
             px[k * kWave] = tl.x[k];
-            L[tl.enc[k] & ~kCenterIsDst] = St::from_f64(Ll[k]);
+            L[tl.enc[k] & ~kCenterIsDst] = narrow<T>(Ll[k]);
         }
     }
-    L[tl.c] = St::from_f64(Lc);
+    L[tl.c] = narrow<T>(Lc);
 }
 
 // ---------------------------------------------- one tile, station form --
@@ -208,6 +221,8 @@ struct StationTile {
     uint32_t nx[kMaxStar];
     typename St::X x[kMaxStar];
     float w[kMaxStar];
+    typename St::L lc_raw;             // the loads as stored, widened after the
+    typename St::L ll_raw[kMaxStar];   // tile's single wait (see run_station_tile)
     typename St::R lc;
     typename St::R ll[kMaxStar];
 };
@@ -284,16 +299,18 @@ __device__ __forceinline__ void load_static(StationTile<St, kWeighted> &tl, cons
 template <class St, bool kWeighted>
 __device__ __forceinline__ void load_loads(StationTile<St, kWeighted> &tl, int lane,
                                            const typename St::L *E) {
-    tl.lc = St::to_f64(E[tl.lane_entry]);
+    tl.lc_raw = E[tl.lane_entry];
     const typename St::L *pl = E + tl.base + lane;
     if (tl.depth == kMaxStar) {
 #pragma unroll
-        for (int k = 0; k < kMaxStar; ++k) tl.ll[k] = St::to_f64(pl[k * kWave]);
+        for (int k = 0; k < kMaxStar; ++k) tl.ll_raw[k] = pl[k * kWave];
         return;
     }
 #pragma unroll
-    for (int k = 0; k < kMaxStar; ++k)
-        if (k < tl.depth) tl.ll[k] = St::to_f64(pl[k * kWave]);
+    for (int k = 0; k < kMaxStar; ++k) {
+        if (k < tl.depth) tl.ll_raw[k] = pl[k * kWave];
+        else tl.ll_raw[k] = St::infinite();
+    }
 }
 
 // A row without a next station (padding, or a lane without a star) stores
@@ -304,6 +321,11 @@ __device__ __forceinline__ void run_station_tile(StationTile<St, kWeighted> &tl,
                                                  typename St::X *__restrict__ slot_x,
                                                  typename St::L *E) {
     typename St::X *px = slot_x + tl.base + lane;
+    // widen the loads here, after the wait: a conversion next to a guarded
+    // load makes the compiler wait for each load before issuing the next
+    tl.lc = St::to_f64(tl.lc_raw);
+#pragma unroll
+    for (int k = 0; k < kMaxStar; ++k) tl.ll[k] = St::to_f64(tl.ll_raw[k]);
     if (tl.depth == kMaxStar) {
 #pragma unroll
         for (int k = 0; k < kMaxStar; ++k)
@@ -393,6 +415,8 @@ k_phase(int64_t slot_base, int32_t tile0, int32_t tiles, int32_t full_tiles, int
 // register copy forces the prefetch to complete.  Phase descriptors are
 // staged in LDS.
 constexpr int kTailBlock = 512;
+// lanes that share one node's incidence row in the per-node sums
+constexpr int kRowLanes = 8;
 static_assert(kTailBlock / kWave == kTailWaves, "tail width");
 
 // Barrier that orders LDS only: every wave's LDS writes are complete before
@@ -565,20 +589,20 @@ k_tail(int32_t nph, const PhaseDesc *__restrict__ descs, const int32_t *__restri
        int32_t ntail, typename St::L *__restrict__ E) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     PhaseDesc *sd = reinterpret_cast<PhaseDesc *>(lds_raw);
-    typename St::L *sL = reinterpret_cast<typename St::L *>(lds_raw + tail_desc_bytes(nph));
+    typename St::R *sL = reinterpret_cast<typename St::R *>(lds_raw + tail_desc_bytes(nph));
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     stage_descs(nph, descs, sd);
-    for (int32_t i = threadIdx.x; i < ntail; i += kTailBlock) sL[i] = E[tail_base + i];
+    for (int32_t i = threadIdx.x; i < ntail; i += kTailBlock) sL[i] = St::to_f64(E[tail_base + i]);
     if (threadIdx.x == 0) {
-        sL[ntail] = St::from_f64(0.0);      // dummy center of empty lanes
-        sL[ntail + 1] = St::infinite();     // dummy leaf of padding rows
+        sL[ntail] = 0.0;                    // dummy center of empty lanes
+        sL[ntail + 1] = __builtin_inf();    // dummy leaf of padding rows
     }
     __syncthreads();
     run_phases<kTailWaves, St, kWeighted>(nph, sd, wave, lane, tile_center, slot_leaf, slot_x,
                                           slot_w, sL);
     __syncthreads();
-    for (int32_t i = threadIdx.x; i < ntail; i += kTailBlock) E[tail_next[i]] = sL[i];
+    for (int32_t i = threadIdx.x; i < ntail; i += kTailBlock) E[tail_next[i]] = St::from_f64(sL[i]);
 }
 
 // ------------------------------------------------------- batched graphs --
@@ -615,12 +639,12 @@ k_batch(const int32_t *__restrict__ active, const int32_t *__restrict__ order,
         const int32_t n = (int32_t)(node_ptr[g + 1] - n0);
         const int32_t nph = (int32_t)(desc_ptr[g + 1] - desc_ptr[g]);
         PhaseDesc *sd = reinterpret_cast<PhaseDesc *>(lds_raw);
-        typename St::L *sL = reinterpret_cast<typename St::L *>(lds_raw + tail_desc_bytes(nph));
+        typename St::R *sL = reinterpret_cast<typename St::R *>(lds_raw + tail_desc_bytes(nph));
         stage_descs(nph, descs + desc_ptr[g], sd);
-        for (int32_t u = threadIdx.x; u < n; u += W * kWave) sL[u] = Lstate[n0 + u];
+        for (int32_t u = threadIdx.x; u < n; u += W * kWave) sL[u] = St::to_f64(Lstate[n0 + u]);
         if (threadIdx.x == 0) {
-            sL[n] = St::from_f64(0.0);
-            sL[n + 1] = St::infinite();
+            sL[n] = 0.0;
+            sL[n + 1] = __builtin_inf();
         }
         __syncthreads();
         for (int32_t t = 0; t < sweeps; ++t) {
@@ -632,7 +656,160 @@ k_batch(const int32_t *__restrict__ active, const int32_t *__restrict__ order,
                                                 slot_x, nullptr, sL);
         }
         __syncthreads();
-        for (int32_t u = threadIdx.x; u < n; u += W * kWave) Lstate[n0 + u] = sL[u];
+        for (int32_t u = threadIdx.x; u < n; u += W * kWave) Lstate[n0 + u] = St::from_f64(sL[u]);
+        __syncthreads();   // LDS reuse by the next graph
+    }
+}
+
+// ------------------------------------------- batched solve in one launch --
+// Each workgroup takes the next graph from the queue and solves it to the
+// tolerance on its own: sweeps from LDS (as k_batch), then, every few
+// sweeps, the check of Section III-B inside the workgroup (wg_check.h): the
+// loads' maximum D, the dual bound; when D does not already certify the
+// densest set found so far, Algorithm 1's extraction (a stable radix sort
+// of the loads, each node's count of neighbours at higher positions, the
+// densest removal prefix); the graph stops once (D - rho_best) / rho_best
+// <= tol or at max_sweeps.  FP32K screens with the kept loads and confirms
+// a passing gap with D of the loads recomputed from the stored fractions.  Between
+// checks the cadence follows the decay of the gap (wg_next_check).  No
+// kernel boundary or host round trip falls inside a solve, so a graph stops
+// at its own check and not at a launch boundary.
+template <class St, int W, bool kPrefetch>
+__global__ void __launch_bounds__(W * kWave) k_batch_solve(BatchSolveArgs a) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ int32_t s_graph;
+    __shared__ WgCheckLds<W> ls;
+    using X = typename St::X;
+    using L = typename St::L;
+    X *slot_x = (X *)a.slot_x;
+    L *Lstate = (L *)a.Lstate;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const unsigned G = (unsigned)*a.active;
+    for (;;) {
+        if (tid == 0) {
+            const unsigned k = atomicAdd(a.queue, 1u);
+            s_graph = k < G ? a.order[k] : -1;
+        }
+        __syncthreads();
+        const int32_t g = s_graph;
+        if (g < 0) break;
+        const int64_t n0 = a.node_ptr[g];
+        const int32_t n = (int32_t)(a.node_ptr[g + 1] - n0);
+        const int32_t nph = (int32_t)(a.desc_ptr[g + 1] - a.desc_ptr[g]);
+        PhaseDesc *sd = reinterpret_cast<PhaseDesc *>(lds_raw);
+        typename St::R *sL = reinterpret_cast<typename St::R *>(lds_raw + tail_desc_bytes(nph));
+        stage_descs(nph, a.descs + a.desc_ptr[g], sd);
+        for (int32_t u = tid; u < n; u += W * kWave) sL[u] = St::to_f64(Lstate[n0 + u]);
+        if (tid == 0) {
+            sL[n] = 0.0;
+            sL[n + 1] = __builtin_inf();
+        }
+        __syncthreads();
+        uint64_t *k0 = a.k0 + n0, *k1 = a.k1 + n0;
+        uint32_t *i0 = a.i0 + n0, *i1 = a.i1 + n0;
+        int32_t *pos = a.pos + n0, *hist = a.hist + n0;
+        int32_t sweeps = 0, k = a.check_every, t0 = -1, t1 = -1, set_at = 0;
+        double g0 = 0.0, g1 = 0.0, gap = 1.0e300, D = 0.0;
+        int64_t bnum = 0, bden = 0;
+        bool have = false;
+        for (;;) {
+            const int32_t kk = k < a.max_sweeps - sweeps ? k : a.max_sweeps - sweeps;
+            for (int32_t t = 0; t < kk; ++t) {
+                if (kPrefetch)
+                    run_phases<W, St, false>(nph, sd, wave, lane, a.tile_center, a.slot_leaf,
+                                             slot_x, nullptr, sL);
+                else
+                    run_phases_single<W, St, false>(nph, sd, wave, lane, a.tile_center,
+                                                    a.slot_leaf, slot_x, nullptr, sL);
+            }
+            sweeps += kk;
+            // every wave's fraction stores are complete and visible before the
+            // fractions are read back
+            __syncthreads();
+            // FP64 loads as sort keys, and their maximum D (for FP32K the
+            // loads as kept: they screen; a passing gap is confirmed below)
+            double vmax = -1.0e308;
+            for (int32_t u = tid; u < n; u += W * kWave) {
+                const double v = sL[u];
+                k0[u] = wg_sortable(v);
+                i0[u] = (uint32_t)u;
+                vmax = v > vmax ? v : vmax;
+            }
+            D = wg_max<W>(vmax, ls);
+            bool certified = false;
+            if (have) {
+                gap = batch_rel_gap(D, bnum, bden);
+                certified = gap <= a.tol;
+            }
+            if (!certified) {
+                const bool in1 = wg_radix_sort<W>(k0, i0, k1, i1, n, ls);
+                const uint32_t *ids = in1 ? i1 : i0;
+                for (int32_t i = tid; i < n; i += W * kWave) pos[ids[i]] = i;
+                __syncthreads();
+                for (int32_t u = tid; u < n; u += W * kWave) {
+                    const int32_t p = pos[u];
+                    int32_t c = 0;
+                    for (int64_t j = a.row_ptr[n0 + u]; j < a.row_ptr[n0 + u + 1]; ++j)
+                        c += pos[a.adj[j] - n0] > p ? 1 : 0;
+                    hist[p] = c;
+                }
+                __syncthreads();
+                int64_t bi, bw;
+                wg_best_prefix<W>(hist, n, ls, &bi, &bw);
+                const int64_t en = bw, ed = (int64_t)n - bi;
+                if (!have || (__int128)en * bden >= (__int128)bnum * ed) {
+                    have = true;
+                    bnum = en;
+                    bden = ed;
+                    set_at = sweeps;
+                    for (int32_t u = tid; u < n; u += W * kWave)
+                        a.in_set[n0 + u] = pos[u] >= bi ? 1 : 0;
+                }
+                gap = batch_rel_gap(D, bnum, bden);
+            }
+            if (St::kRecompute && gap <= a.tol) {
+                // only the loads of the stored fractions make a feasible dual
+                // point: D from those (FP64 sums along each node's incidence,
+                // 8 lanes a node, fixed order), and the carried loads restart
+                // from them, so a failed confirmation leaves no drift behind
+                double emax = -1.0e308;
+                const int sub = tid & (kRowLanes - 1);
+                for (int32_t u0 = tid / kRowLanes; u0 < n; u0 += W * kWave / kRowLanes) {
+                    const int64_t b = a.row_ptr[n0 + u0], e = a.row_ptr[n0 + u0 + 1];
+                    double v = 0.0;
+                    for (int64_t j = b + sub; j < e; j += kRowLanes) {
+                        const uint32_t ent = a.inc_slot[j];
+                        const double x = (double)slot_x[ent >> 1];
+                        v = v + ((ent & 1u) ? 1.0 - x : x);
+                    }
+                    for (int d = kRowLanes / 2; d > 0; d >>= 1) v = v + __shfl_down(v, d, kRowLanes);
+                    if (sub == 0) {
+                        sL[u0] = v;
+                        emax = v > emax ? v : emax;
+                    }
+                }
+                D = wg_max<W>(emax, ls);
+                gap = batch_rel_gap(D, bnum, bden);
+            }
+            if (gap <= a.tol || sweeps >= a.max_sweeps) break;
+            t0 = t1;
+            g0 = g1;
+            t1 = sweeps;
+            g1 = gap;
+            k = wg_next_check(t0, g0, t1, g1, a.tol, a.check_every);
+        }
+        __syncthreads();
+        for (int32_t u = tid; u < n; u += W * kWave) Lstate[n0 + u] = St::from_f64(sL[u]);
+        if (tid == 0) {
+            a.num[g] = bnum;
+            a.den[g] = bden;
+            a.D[g] = D;
+            a.sweeps_used[g] = sweeps;
+            a.set_sweeps[g] = set_at;
+            if (gap > a.tol) atomicAdd(a.queue + 1, 1u);
+        }
         __syncthreads();   // LDS reuse by the next graph
     }
 }
@@ -726,14 +903,17 @@ __global__ void k_batch_loads_f64(int64_t N, const typename St::L *Lstate, doubl
 }
 
 __global__ void k_zero_u32(unsigned *p) { *p = 0u; }
+__global__ void k_zero_u32x2(unsigned *p) {
+    p[0] = 0u;
+    p[1] = 0u;
+}
 
 // ------------------------------------------------------------ statistics --
 constexpr int kRedBlock = 256;
 
 // FP64 loads recomputed from the fractions (f_e(src) = x, f_e(dst) = w - x):
-// a group of 8 lanes per node of degree below kBigRow, lanes striding over
-// the row, fixed-order reduction; longer rows: k_recompute_big.
-constexpr int kRowLanes = 8;
+// a group of kRowLanes lanes per node of degree below kBigRow, lanes striding
+// over the row, fixed-order reduction; longer rows: k_recompute_big.
 template <class St, bool kWeighted>
 __device__ __forceinline__ double recompute_term(uint32_t ent, const int64_t *edge_slot,
                                                  const typename St::X *slot_x, const float *w) {
@@ -787,6 +967,17 @@ k_batch_recompute(int64_t N, const int32_t *node_graph, const uint8_t *flag,
             L64[u] = acc;
             Lstate[u] = St::from_f64(acc);
         }
+    }
+}
+
+// Each incidence entry's slot: (slot of its edge) << 1 | side, so the sums of
+// the fractions along a row take one gather per entry.
+__global__ void k_inc_slots(int64_t entries, const uint32_t *inc, const int64_t *edge_slot,
+                            uint32_t *inc_slot) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < entries;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t ent = inc[j];
+        inc_slot[j] = ((uint32_t)edge_slot[ent >> 1] << 1) | (ent & 1u);
     }
 }
 
@@ -946,7 +1137,7 @@ static void sweep_launchers(SweepLaunch &fn) {
     fn.tail = [](int32_t nph, const PhaseDesc *descs, const int32_t *tile_center,
                  const uint32_t *slot_leaf, void *slot_x, const float *slot_w, int64_t tail_base,
                  const uint32_t *tail_next, int32_t ntail, void *E, hipStream_t s) {
-        size_t lds = tail_desc_bytes(nph) + (size_t)(ntail + 2) * sizeof(typename St::L);
+        size_t lds = tail_desc_bytes(nph) + (size_t)(ntail + 2) * sizeof(typename St::R);
         hipLaunchKernelGGL((k_tail<St, kW>), dim3(1), dim3(kTailBlock), lds, s, nph, descs,
                            tile_center, slot_leaf, (typename St::X *)slot_x, slot_w, tail_base,
                            tail_next, ntail, (typename St::L *)E);
@@ -1030,6 +1221,30 @@ static void sweep_launchers(SweepLaunch &fn) {
         if (!k) fail(LOWD_E_ARG, "unsupported batch workgroup shape");
         LOWD_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     };
+    fn.batch_solve = [](int32_t shape, const BatchSolveArgs &a, size_t lds, int32_t blocks,
+                        hipStream_t s) {
+        hipLaunchKernelGGL(k_zero_u32x2, dim3(1), dim3(1), 0, s, a.queue);
+#define LOWD_SOLVE_CASE(W, PF)                                                                 \
+    case W * 2 + PF:                                                                           \
+        hipLaunchKernelGGL((k_batch_solve<St, W, PF>), dim3((unsigned)blocks), dim3(W * kWave),  \
+                           lds, s, a);                                                         \
+        break;
+        switch (shape) {   // the shapes whose sweeps and checks fit 256 registers
+            LOWD_SOLVE_CASE(4, 0)
+            LOWD_SOLVE_CASE(4, 1)
+            LOWD_SOLVE_CASE(8, 0)
+            default: fail(LOWD_E_ARG, "unsupported batch workgroup shape for the solve");
+        }
+#undef LOWD_SOLVE_CASE
+    };
+    fn.set_batch_solve_lds = [](int32_t shape, size_t bytes) {
+        const void *k = shape == 8 ? (const void *)k_batch_solve<St, 4, false>
+                        : shape == 9 ? (const void *)k_batch_solve<St, 4, true>
+                        : shape == 16 ? (const void *)k_batch_solve<St, 8, false>
+                                      : nullptr;
+        if (!k) fail(LOWD_E_ARG, "unsupported batch workgroup shape for the solve");
+        LOWD_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    };
     fn.batch_init_loads = [](int64_t N, const int32_t *deg, void *Lstate, hipStream_t s) {
         hipLaunchKernelGGL((k_batch_init_loads<St>), dim3(grid_for(N, 256)), dim3(256), 0, s, N,
                            deg, (typename St::L *)Lstate);
@@ -1048,6 +1263,8 @@ static void sweep_launchers(SweepLaunch &fn) {
                            (const typename St::X *)slot_x, L64, (typename St::L *)Lstate);
     };
     fn.x_bytes = sizeof(typename St::X);
+    // a load takes as many bytes at rest as in LDS: l_bytes sizes both
+    static_assert(sizeof(typename St::L) == sizeof(typename St::R), "load sizes");
     fn.l_bytes = sizeof(typename St::L);
 }
 
@@ -1059,6 +1276,13 @@ void get_sweep_launchers(int32_t state, bool weighted, SweepLaunch &fn) {
         if (weighted) sweep_launchers<StateF32K, true>(fn);
         else sweep_launchers<StateF32K, false>(fn);
     }
+}
+
+void launch_inc_slots(int64_t entries, const uint32_t *inc, const int64_t *edge_slot,
+                      uint32_t *inc_slot, hipStream_t s) {
+    if (entries > 0)
+        hipLaunchKernelGGL(k_inc_slots, dim3(grid_for(entries, 256)), dim3(256), 0, s, entries,
+                           inc, edge_slot, inc_slot);
 }
 
 void launch_retire(int32_t G, const int32_t *all, const int64_t *edge_ptr, const int64_t *num,

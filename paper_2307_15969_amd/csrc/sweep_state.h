@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "lowd_internal.h"
 
 namespace lowd {
@@ -92,7 +94,8 @@ struct StateF64 {
 
 // FP32 fractions; loads stored as compensated FP32 pairs (s, c) with value
 // s + c (s = the load rounded to FP32, c = the rest rounded to FP32: about
-// 48 significant bits), in the station array, in LDS and between launches.
+// 48 significant bits) wherever they rest in HBM: the station array and the
+// batch's loads between launches (the LDS tiers keep them in FP64).
 // A star's chain runs in FP64 registers: its loads are widened once when
 // the tile reads them and rounded back to pairs once when it writes them,
 // and each step is StateF64's step on the widened loads, with the fraction
@@ -130,6 +133,54 @@ struct StateF32K {
     }
 };
 
+// Arguments of the batched solve in one launch (k_batch_solve): the graphs,
+// their layouts and state, the batch's incidence for the checks, per-node
+// scratch of the checks (each graph owns its nodes' slice), the tolerance
+// and the per-graph results.
+struct BatchSolveArgs {
+    const int32_t *active;        // [1] graphs listed in order
+    const int32_t *order;         // [G] graph ids, largest first
+    unsigned *queue;              // [2] next list index; graphs that reached max_sweeps
+    const int64_t *node_ptr;      // [G+1]
+    const int64_t *desc_ptr;      // [G+1]
+    const PhaseDesc *descs;
+    const int32_t *tile_center;
+    const uint32_t *slot_leaf;
+    void *slot_x;
+    void *Lstate;                 // [N] carried loads, read at the start, written at the end
+    const int64_t *row_ptr;       // [N+1] incidence rows (ascending edge index)
+    const int32_t *adj;           // [2M] the other end of each entry (batch node id)
+    const uint32_t *inc_slot;     // [2M] slot << 1 | side of each entry (FP32K)
+    uint64_t *k0, *k1;            // [N] sort keys
+    uint32_t *i0, *i1;            // [N] sort ids
+    int32_t *pos, *hist;          // [N] positions, edge counts by position
+    double tol;
+    int32_t max_sweeps, check_every;
+    uint8_t *in_set;              // [N] out
+    int64_t *num, *den;           // [G] out
+    double *D;                    // [G] out
+    int32_t *sweeps_used;         // [G] out
+    int32_t *set_sweeps;          // [G] out: the sweep count of the set's extraction
+};
+
+// (D - rho) / rho for rho = num / den (a graph without edges: 0)
+__host__ __device__ inline double batch_rel_gap(double D, int64_t num, int64_t den) {
+    const double rho = den > 0 ? (double)num / (double)den : 0.0;
+    return rho > 0.0 ? (D - rho) / rho : (D > 0.0 ? 1.0e300 : 0.0);
+}
+
+// A load in FP64 from its stored form, and back: the LDS tiers hold FP64
+// loads for either state (LDS is private to the run: the pair form is kept
+// only where loads rest in HBM between phases and launches).
+__device__ inline double widen(double v) { return v; }
+__device__ inline double widen(LoadK32 v) { return StateF32K::to_f64(v); }
+template <class T>
+__device__ inline T narrow(double v);
+template <>
+__device__ inline double narrow<double>(double v) { return v; }
+template <>
+__device__ inline LoadK32 narrow<LoadK32>(double v) { return StateF32K::from_f64(v); }
+
 // Host-callable launchers for one (state, weighted) combination.
 struct SweepLaunch {
     void (*init_slots)(int64_t nslots, const int64_t *slot_edge, const float *w, void *slot_x,
@@ -165,6 +216,10 @@ struct SweepLaunch {
                   const int32_t *tile_center, const uint32_t *slot_leaf, void *slot_x,
                   int32_t sweeps, void *Lstate, size_t lds, int32_t blocks, hipStream_t s);
     void (*set_batch_lds)(int32_t shape, size_t bytes);
+    // the batched solve in one launch (same shapes as batch)
+    void (*batch_solve)(int32_t shape, const BatchSolveArgs &a, size_t lds, int32_t blocks,
+                        hipStream_t s);
+    void (*set_batch_solve_lds)(int32_t shape, size_t bytes);
     void (*batch_init_loads)(int64_t N, const int32_t *deg, void *Lstate, hipStream_t s);
     void (*batch_loads_f64)(int64_t N, const void *Lstate, double *L64, hipStream_t s);
     void (*batch_recompute)(int32_t G, int64_t N, const int32_t *active, const int32_t *order,
@@ -185,6 +240,9 @@ void launch_batch_degrees(int64_t N, int64_t M, const int32_t *gsrc, const int32
 void launch_retire(int32_t G, const int32_t *all, const int64_t *edge_ptr, const int64_t *num,
                    const int64_t *den, const double *D, double tol, int32_t *order,
                    int32_t *active, int64_t *active_edges, hipStream_t s);
+// inc_slot[j] = edge_slot[inc[j] >> 1] << 1 | (inc[j] & 1)
+void launch_inc_slots(int64_t entries, const uint32_t *inc, const int64_t *edge_slot,
+                      uint32_t *inc_slot, hipStream_t s);
 void launch_activate_all(int32_t G, const int32_t *all, const int64_t *edge_ptr, int32_t *order,
                          int32_t *active, int64_t *active_edges, hipStream_t s);
 

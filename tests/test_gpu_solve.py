@@ -4,10 +4,12 @@
   bound D it returns equals the oracle's largest load after as many sweeps
   (bit for bit in FP64), the returned set is a set of the graph with the
   stated exact density, and the certified gap holds with the oracle's D.
-- lowd_batch_solve on a batch shaped like the 4096-graph workload (edge
+- lowd_batch_solve (one persistent launch; every graph checked and stopped
+  inside its workgroup) on a batch shaped like the 4096-graph workload (edge
   targets log-uniform up to 50,000, planted blocks), both states: every
-  graph's set, exact density and D equal the FP64 oracle's after that
-  graph's own sweep count.
+  graph's set and exact density equal the FP64 oracle's extraction after the
+  sweeps the set was taken at, and its D the oracle's largest load after all
+  of the graph's sweeps (bit for bit in FP64, within 1e-5 in FP32K).
 - The pruned graph of an R-MAT graph (the shape of the scale-24 workload: a
   hub adjacent to nearly every node, hundreds of phases, the LDS tier):
   FP64 bit-exact on every tier split, FP32K within 1e-5, the same set.
@@ -278,13 +280,17 @@ def test_batch_solve_at_the_workload_shape(state):
     ins = b.in_set.cpu().numpy()
     for i, g in enumerate(gs):
         a, c = b.node_ptr[i], b.node_ptr[i + 1]
-        T = int(r["sweeps"][i])
-        _, Lo, _ = oracle_state(g, T)
-        ro = oracle.extract(g.n, g.src, g.dst, None, Lo)
-        assert (num[i], den[i]) == (ro["num"], ro["den"]), (i, g.m, T)
-        assert np.array_equal(ins[a:c], ro["in_set"]), (i, g.m, T)
+        T, Ts = int(r["sweeps"][i]), int(r["set_sweeps"][i])
+        assert 0 < Ts <= T
+        # the set: the oracle's extraction after the sweeps it was taken at
+        _, Ls, _ = oracle_state(g, Ts)
+        ro = oracle.extract(g.n, g.src, g.dst, None, Ls)
+        assert (num[i], den[i]) == (ro["num"], ro["den"]), (i, g.m, Ts)
+        assert np.array_equal(ins[a:c], ro["in_set"]), (i, g.m, Ts)
         if g.m == 0:
             continue
+        # the bound: the oracle's largest load after all the graph's sweeps
+        _, Lo, _ = oracle_state(g, T)
         Do = float(Lo.max())
         if state == "f64":
             assert D[i] == Do, i
@@ -297,7 +303,23 @@ def test_batch_solve_at_the_workload_shape(state):
     r2 = b.solve(TOL)
     assert np.array_equal(r2["sweeps"], r["sweeps"])
     assert np.array_equal(b.num.cpu().numpy(), num)
+    assert np.array_equal(b.in_set.cpu().numpy(), ins)
     b.close()
+
+
+@pytest.mark.parametrize("shape", ["4,0,2", "4,1,1", "8,0,1"])
+def test_batch_solve_every_launch_shape_agrees(shape, monkeypatch):
+    """The launch shape changes only which workgroup runs which graph: the
+    sweep counts and sets are the same for every shape."""
+    gs = synth.batch_of_graphs(40, seed=21, m_lo=100, m_hi=8000)
+    ref = lowd.batch_solve(gs, TOL, "f64")
+    monkeypatch.setenv("LOWD_BATCH_SHAPE", shape)
+    r = lowd.batch_solve(gs, TOL, "f64")
+    assert np.array_equal(r["sweeps"], ref["sweeps"])
+    assert np.array_equal(r["set_sweeps"], ref["set_sweeps"])
+    assert np.array_equal(r["num"], ref["num"]) and np.array_equal(r["den"], ref["den"])
+    assert np.array_equal(r["in_set"].cpu().numpy(), ref["in_set"].cpu().numpy())
+    assert np.array_equal(r["D"], ref["D"])
 
 
 def test_batch_solve_reports_not_converged():
