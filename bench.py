@@ -530,7 +530,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--max-sweeps", type=int, default=20000)
-    ap.add_argument("--star-max", type=int, default=16)
+    ap.add_argument("--star-max", type=int, default=None,
+                    help="leaves per star per phase (default 32 for rmat24, whose pruned "
+                         "graph's phase count a hub sets, else 16)")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="rmat24")
     ap.add_argument("--state", choices=["f64", "f32k"], default=None,
                     help="solver state where the workload runs one (chunglu1m: f64, batch4096 "
@@ -545,6 +547,8 @@ def main():
                     help="also run one plain device-to-device copy of this many MiB (a "
                          "known-size kernel for scaling memory counters)")
     args = ap.parse_args()
+    if args.star_max is None:
+        args.star_max = 32 if args.workload == "rmat24" else 16
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(every workload is sized for one MI355X)", file=sys.stderr)

@@ -152,8 +152,11 @@ lowd_status lowd_greedy_peel(int32_t n, int64_t m, const int32_t *src, const int
  *   w             [device] float32[m] or NULL (unit weights); read during
  *                 this call only
  *   state         LOWD_STATE_F64 or LOWD_STATE_F32K
- *   star_max      leaves per star per phase, 1..16 (1 gives a proper edge
- *                 colouring: every phase is a matching); 16 is the default
+ *   star_max      leaves per star per phase, 1..32 (1 gives a proper edge
+ *                 colouring: every phase is a matching); 16 is the default.
+ *                 Phases whose stars have more than 16 leaves run as
+ *                 whole-GPU launches only (the single-workgroup tiers take
+ *                 tiles of at most 16 rows)
  *   out           [host] receives the solver; free with lowd_solver_free
  * The solver owns its device memory (schedule, fractions, loads, about
  * 40 bytes per edge and 40 per node for LOWD_STATE_F64).  Synchronises

@@ -163,7 +163,7 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
         if (m < 0 || m >= ((int64_t)1 << 31)) fail(LOWD_E_ARG, "m must be in [0, 2^31)");
         if (m > 0 && (!src || !dst)) fail(LOWD_E_ARG, "src/dst is NULL");
         if (state != LOWD_STATE_F64 && state != LOWD_STATE_F32K) fail(LOWD_E_ARG, "bad state");
-        if (star_max < 1 || star_max > kMaxStar) fail(LOWD_E_ARG, "star_max must be in [1, 16]");
+        if (star_max < 1 || star_max > kMaxStar) fail(LOWD_E_ARG, "star_max must be in [1, 32]");
         hipStream_t s = (hipStream_t)stream;
         validate_graph(n, m, src, dst, w, s);
 
@@ -223,9 +223,12 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
         upload(sv->slot_leaf, sc.slot_leaf, s);
         upload(sv->slot_edge, sc.slot_edge, s);
         upload(sv->edge_slot, sc.edge_slot, s);
-        std::vector<PhaseDesc> tdesc(sc.desc.begin() + sc.P0, sc.desc.end());
+        // the single-workgroup tiers stage their descriptors in LDS in the
+        // narrow form (their phases are at most kTierStar deep)
+        std::vector<PhaseDesc> tdesc, mdesc;
+        for (int32_t p = sc.P0; p < sc.P; ++p) tdesc.push_back(narrow_desc<kTierStar>(sc.desc[(size_t)p]));
+        for (int32_t p = sc.P1; p < sc.P0; ++p) mdesc.push_back(narrow_desc<kTierStar>(sc.desc[(size_t)p]));
         upload(sv->tail_desc, tdesc, s);
-        std::vector<PhaseDesc> mdesc(sc.desc.begin() + sc.P1, sc.desc.begin() + sc.P0);
         upload(sv->mid_desc, mdesc, s);
         upload(sv->slot_next, sc.slot_next, s);
         upload(sv->center_next, sc.center_next, s);
@@ -970,7 +973,7 @@ lowd_status lowd_batch_prepare(int32_t G, const int64_t *node_ptr, const int64_t
         *out = nullptr;
         if (G < 1 || !node_ptr || !edge_ptr) fail(LOWD_E_ARG, "G >= 1 and node_ptr/edge_ptr needed");
         if (state != LOWD_STATE_F64 && state != LOWD_STATE_F32K) fail(LOWD_E_ARG, "bad state");
-        if (star_max < 1 || star_max > kMaxStar) fail(LOWD_E_ARG, "star_max must be in [1, 16]");
+        if (star_max < 1 || star_max > kTierStar) fail(LOWD_E_ARG, "star_max must be in [1, 16]");
         if (tune != 0 && tune != 1) fail(LOWD_E_ARG, "tune must be 0 or 1");
         if (node_ptr[0] != 0 || edge_ptr[0] != 0) fail(LOWD_E_ARG, "node_ptr[0], edge_ptr[0] must be 0");
         for (int32_t g = 0; g < G; ++g) {
@@ -1076,7 +1079,8 @@ lowd_status lowd_batch_prepare(int32_t G, const int64_t *node_ptr, const int64_t
             b->max_phases = std::max<int64_t>(b->max_phases, sc.P);
             const int64_t slot0 = (int64_t)slot_leaf.size();
             const int32_t tile0 = (int32_t)(tile_center.size() / kWave);
-            for (PhaseDesc d : sc.desc) {
+            for (const PhaseDescWide &dw : sc.desc) {
+                PhaseDesc d = narrow_desc<kTierStar>(dw);
                 d.slot_base += slot0;
                 d.tile0 += tile0;
                 descs.push_back(d);

@@ -109,9 +109,9 @@ struct Tile {
     int32_t c;
     int32_t depth;        // wave-uniform
     int64_t base;         // wave-uniform: first slot of the tile
-    uint32_t enc[kMaxStar];
-    typename St::X x[kMaxStar];
-    float w[kMaxStar];
+    uint32_t enc[kTierStar];
+    typename St::X x[kTierStar];
+    float w[kTierStar];
 };
 
 template <class St, bool kWeighted>
@@ -123,7 +123,7 @@ __device__ __forceinline__ void load_tile(Tile<St, kWeighted> &tl, const PhaseDe
     int32_t depth = 0;
     int64_t rows = 0;
 #pragma unroll
-    for (int k = 0; k < kMaxStar; ++k) {
+    for (int k = 0; k < kTierStar; ++k) {
         depth += (d.T[k] > t) ? 1 : 0;
         rows += (int64_t)(d.T[k] < t ? d.T[k] : t);
     }
@@ -134,9 +134,9 @@ __device__ __forceinline__ void load_tile(Tile<St, kWeighted> &tl, const PhaseDe
     const uint32_t *pl = slot_leaf + base + lane;
     const typename St::X *px = slot_x + base + lane;
     const float *pw = kWeighted ? slot_w + base + lane : nullptr;
-    if (tl.depth == kMaxStar) {   // a full tile: no per-row guard
+    if (tl.depth == kTierStar) {   // a full tile: no per-row guard
 #pragma unroll
-        for (int k = 0; k < kMaxStar; ++k) {
+        for (int k = 0; k < kTierStar; ++k) {
             tl.enc[k] = pl[k * kWave];
             tl.x[k] = px[k * kWave];
             tl.w[k] = kWeighted ? pw[k * kWave] : 1.0f;
@@ -144,7 +144,7 @@ __device__ __forceinline__ void load_tile(Tile<St, kWeighted> &tl, const PhaseDe
         return;
     }
 #pragma unroll
-    for (int k = 0; k < kMaxStar; ++k) {
+    for (int k = 0; k < kTierStar; ++k) {
         if (k < tl.depth) {
             tl.enc[k] = pl[k * kWave];
             tl.x[k] = px[k * kWave];
@@ -162,20 +162,20 @@ __device__ __forceinline__ void run_tile(Tile<St, kWeighted> &tl, int lane,
                                          typename St::X *__restrict__ slot_x, LPtr L) {
     using T = typename std::remove_cv<typename std::remove_reference<decltype(L[0])>::type>::type;
     const T lc_raw = L[tl.c];
-    T raw[kMaxStar];
-    typename St::R Ll[kMaxStar];
+    T raw[kTierStar];
+    typename St::R Ll[kTierStar];
     typename St::X *px = slot_x + tl.base + lane;
-    if (tl.depth == kMaxStar) {   // a full tile: one straight block
+    if (tl.depth == kTierStar) {   // a full tile: one straight block
 #pragma unroll
-        for (int k = 0; k < kMaxStar; ++k) raw[k] = L[tl.enc[k] & ~kCenterIsDst];
+        for (int k = 0; k < kTierStar; ++k) raw[k] = L[tl.enc[k] & ~kCenterIsDst];
         typename St::R Lc = widen(lc_raw);
 #pragma unroll
-        for (int k = 0; k < kMaxStar; ++k) Ll[k] = widen(raw[k]);
+        for (int k = 0; k < kTierStar; ++k) Ll[k] = widen(raw[k]);
 #pragma unroll
-        for (int k = 0; k < kMaxStar; ++k)
+        for (int k = 0; k < kTierStar; ++k)
             St::step_center(Lc, Ll[k], tl.enc[k] & kCenterIsDst, tl.x[k], tl.w[k]);
 #pragma unroll
-        for (int k = 0; k < kMaxStar; ++k) {
+        for (int k = 0; k < kTierStar; ++k) {
             px[k * kWave] = tl.x[k];
             L[tl.enc[k] & ~kCenterIsDst] = narrow<T>(Ll[k]);
         }
@@ -183,7 +183,7 @@ __device__ __forceinline__ void run_tile(Tile<St, kWeighted> &tl, int lane,
         return;
     }
 #pragma unroll
-    for (int k = 0; k < kMaxStar; ++k) {
+    for (int k = 0; k < kTierStar; ++k) {
         if (k < tl.depth) raw[k] = L[tl.enc[k] & ~kCenterIsDst];
         else raw[k] = narrow<T>(__builtin_inf());
     }
@@ -191,12 +191,12 @@ __device__ __forceinline__ void run_tile(Tile<St, kWeighted> &tl, int lane,
     // load makes the compiler wait for that load before issuing the next)
     typename St::R Lc = widen(lc_raw);
 #pragma unroll
-    for (int k = 0; k < kMaxStar; ++k) Ll[k] = widen(raw[k]);
+    for (int k = 0; k < kTierStar; ++k) Ll[k] = widen(raw[k]);
 #pragma unroll
-    for (int k = 0; k < kMaxStar; ++k)
+    for (int k = 0; k < kTierStar; ++k)
         if (k < tl.depth) St::step_center(Lc, Ll[k], tl.enc[k] & kCenterIsDst, tl.x[k], tl.w[k]);
 #pragma unroll
-    for (int k = 0; k < kMaxStar; ++k) {
+    for (int k = 0; k < kTierStar; ++k) {
         if (k < tl.depth) {
             px[k * kWave] = tl.x[k];
             L[tl.enc[k] & ~kCenterIsDst] = narrow<T>(Ll[k]);
@@ -211,30 +211,31 @@ __device__ __forceinline__ void run_tile(Tile<St, kWeighted> &tl, int lane,
 // leaves' loads (the slots' station entries) in slot order, plus where each
 // goes next.  Padding rows read +infinity and lanes without a star read a
 // zero center; neither is written back.
-template <class St, bool kWeighted>
+template <class St, bool kWeighted, int D>
 struct StationTile {
     int32_t depth;        // wave-uniform
     int64_t base;         // wave-uniform: first slot of the tile
     int64_t lane_entry;   // the lane's center station
     uint32_t cnext;       // next station of the center, or the sink
     uint32_t sink;
-    uint32_t nx[kMaxStar];
-    typename St::X x[kMaxStar];
-    float w[kMaxStar];
+    uint32_t nx[D];
+    typename St::X x[D];
+    float w[D];
     typename St::L lc_raw;             // the loads as stored, widened after the
-    typename St::L ll_raw[kMaxStar];   // tile's single wait (see run_station_tile)
+    typename St::L ll_raw[D];   // tile's single wait (see run_station_tile)
     typename St::R lc;
-    typename St::R ll[kMaxStar];
+    typename St::R ll[D];
 };
 
 // A tile's depth and first slot.  Tile t of a phase has depth
 // #{k : T[k] > t} and follows sum_k min(T[k], t) full rows of the phase.
-__device__ __forceinline__ void tile_geometry(const PhaseDesc &d, int32_t t, int32_t &depth,
+template <int D>
+__device__ __forceinline__ void tile_geometry(const PhaseDescT<D> &d, int32_t t, int32_t &depth,
                                               int64_t &base) {
     int32_t dp = 0;
     int64_t rows = 0;
 #pragma unroll
-    for (int k = 0; k < kMaxStar; ++k) {
+    for (int k = 0; k < D; ++k) {
         dp += (d.T[k] > t) ? 1 : 0;
         rows += (int64_t)(d.T[k] < t ? d.T[k] : t);
     }
@@ -245,8 +246,8 @@ __device__ __forceinline__ void tile_geometry(const PhaseDesc &d, int32_t t, int
 // the parts that do not depend on the previous phase, for a tile of the
 // given depth whose rows start at slot `base`; li = the lane's index among
 // all tile lanes
-template <class St, bool kWeighted>
-__device__ __forceinline__ void load_static_at(StationTile<St, kWeighted> &tl, int32_t depth,
+template <class St, bool kWeighted, int D>
+__device__ __forceinline__ void load_static_at(StationTile<St, kWeighted, D> &tl, int32_t depth,
                                                int64_t base, int64_t li, int lane,
                                                int64_t center_base,
                                                const uint32_t *__restrict__ center_next,
@@ -259,16 +260,16 @@ __device__ __forceinline__ void load_static_at(StationTile<St, kWeighted> &tl, i
     const uint32_t *pn = slot_next + base + lane;
     const typename St::X *px = slot_x + base + lane;
     const float *pw = kWeighted ? slot_w + base + lane : nullptr;
-    if (tl.depth == kMaxStar) {   // a full tile: no per-row guard
+    if (tl.depth == D) {   // a full tile: no per-row guard
 #pragma unroll
-        for (int k = 0; k < kMaxStar; ++k) {
+        for (int k = 0; k < D; ++k) {
             tl.nx[k] = pn[k * kWave];
             tl.x[k] = px[k * kWave];
             tl.w[k] = kWeighted ? pw[k * kWave] : 1.0f;
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < kMaxStar; ++k) {
+        for (int k = 0; k < D; ++k) {
             if (k < tl.depth) {
                 tl.nx[k] = pn[k * kWave];
                 tl.x[k] = px[k * kWave];
@@ -280,8 +281,8 @@ __device__ __forceinline__ void load_static_at(StationTile<St, kWeighted> &tl, i
     tl.cnext = center_next[li];
 }
 
-template <class St, bool kWeighted>
-__device__ __forceinline__ void load_static(StationTile<St, kWeighted> &tl, const PhaseDesc &d,
+template <class St, bool kWeighted, int D>
+__device__ __forceinline__ void load_static(StationTile<St, kWeighted, D> &tl, const PhaseDescT<D> &d,
                                             int32_t t, int lane, int64_t center_base,
                                             const uint32_t *__restrict__ center_next,
                                             const uint32_t *__restrict__ slot_next,
@@ -296,18 +297,18 @@ __device__ __forceinline__ void load_static(StationTile<St, kWeighted> &tl, cons
 }
 
 // the loads, written by earlier phases
-template <class St, bool kWeighted>
-__device__ __forceinline__ void load_loads(StationTile<St, kWeighted> &tl, int lane,
+template <class St, bool kWeighted, int D>
+__device__ __forceinline__ void load_loads(StationTile<St, kWeighted, D> &tl, int lane,
                                            const typename St::L *E) {
     tl.lc_raw = E[tl.lane_entry];
     const typename St::L *pl = E + tl.base + lane;
-    if (tl.depth == kMaxStar) {
+    if (tl.depth == D) {
 #pragma unroll
-        for (int k = 0; k < kMaxStar; ++k) tl.ll_raw[k] = pl[k * kWave];
+        for (int k = 0; k < D; ++k) tl.ll_raw[k] = pl[k * kWave];
         return;
     }
 #pragma unroll
-    for (int k = 0; k < kMaxStar; ++k) {
+    for (int k = 0; k < D; ++k) {
         if (k < tl.depth) tl.ll_raw[k] = pl[k * kWave];
         else tl.ll_raw[k] = St::infinite();
     }
@@ -316,8 +317,8 @@ __device__ __forceinline__ void load_loads(StationTile<St, kWeighted> &tl, int l
 // A row without a next station (padding, or a lane without a star) stores
 // into the sink entry, so the stores need no per-lane branch; a full tile
 // needs no per-row guard either, and its rows form one straight block.
-template <class St, bool kWeighted>
-__device__ __forceinline__ void run_station_tile(StationTile<St, kWeighted> &tl, int lane,
+template <class St, bool kWeighted, int D>
+__device__ __forceinline__ void run_station_tile(StationTile<St, kWeighted, D> &tl, int lane,
                                                  typename St::X *__restrict__ slot_x,
                                                  typename St::L *E) {
     typename St::X *px = slot_x + tl.base + lane;
@@ -325,25 +326,23 @@ __device__ __forceinline__ void run_station_tile(StationTile<St, kWeighted> &tl,
     // load makes the compiler wait for each load before issuing the next
     tl.lc = St::to_f64(tl.lc_raw);
 #pragma unroll
-    for (int k = 0; k < kMaxStar; ++k) tl.ll[k] = St::to_f64(tl.ll_raw[k]);
-    if (tl.depth == kMaxStar) {
+    for (int k = 0; k < D; ++k) tl.ll[k] = St::to_f64(tl.ll_raw[k]);
+    // A leaf's load and the edge's fraction are final after its step: their
+    // stores go out right behind it, while the chain's next steps (which
+    // depend only on the center's load) run, instead of after the chain.
+    if (tl.depth == D) {
 #pragma unroll
-        for (int k = 0; k < kMaxStar; ++k)
+        for (int k = 0; k < D; ++k) {
             St::step_center(tl.lc, tl.ll[k], tl.nx[k] & kCenterIsDst, tl.x[k], tl.w[k]);
-#pragma unroll
-        for (int k = 0; k < kMaxStar; ++k) {
             px[k * kWave] = tl.x[k];
             const uint32_t nx = tl.nx[k] & ~kCenterIsDst;
             E[nx != kNoStation ? nx : tl.sink] = St::from_f64(tl.ll[k]);
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < kMaxStar; ++k)
-            if (k < tl.depth)
-                St::step_center(tl.lc, tl.ll[k], tl.nx[k] & kCenterIsDst, tl.x[k], tl.w[k]);
-#pragma unroll
-        for (int k = 0; k < kMaxStar; ++k) {
+        for (int k = 0; k < D; ++k) {
             if (k < tl.depth) {
+                St::step_center(tl.lc, tl.ll[k], tl.nx[k] & kCenterIsDst, tl.x[k], tl.w[k]);
                 px[k * kWave] = tl.x[k];
                 const uint32_t nx = tl.nx[k] & ~kCenterIsDst;
                 E[nx != kNoStation ? nx : tl.sink] = St::from_f64(tl.ll[k]);
@@ -369,23 +368,26 @@ constexpr int32_t kSpreadWaves = 256;  // spread until about one wave per CU
 // The first 16 dwords of the arguments (through center_next) are all a full
 // tile needs before its first loads; they are preloaded into scalar
 // registers at wave launch, so a full tile's loads do not wait for the
-// argument fetch (the descriptor and slot_w follow).  full_tiles = T[15]:
-// tiles t < full_tiles have depth 16 and start at slot_base + 16 * 64 * t.
-template <class St, bool kWeighted>
+// argument fetch (the descriptor and slot_w follow).  full_tiles = T[D-1]:
+// tiles t < full_tiles have depth D and start at slot_base + D * 64 * t.
+// D = 16 for phases whose stars have at most 16 leaves, 32 for deeper ones
+// (a lane then keeps 32 leaves' fractions and loads in registers).
+template <class St, bool kWeighted, int D>
 __global__ void __launch_bounds__(kPhaseBlock)
 k_phase(int64_t slot_base, int32_t tile0, int32_t tiles, int32_t full_tiles, int32_t spread,
         int64_t center_base, typename St::L *__restrict__ E,
         const uint32_t *__restrict__ slot_next, typename St::X *__restrict__ slot_x,
-        const uint32_t *__restrict__ center_next, PhaseDesc d, const float *__restrict__ slot_w) {
+        const uint32_t *__restrict__ center_next, PhaseDescT<D> d,
+        const float *__restrict__ slot_w) {
     const int lane = threadIdx.x & (kWave - 1);
     const int32_t t = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x >> spread));
     if (t >= tiles) return;
     const int32_t share = (int32_t)(blockIdx.x & ((1u << spread) - 1));
     if ((lane >> (6 - spread)) != share) return;
-    int32_t depth = kMaxStar;
-    int64_t base = slot_base + (int64_t)t * (kMaxStar * kWave);
+    int32_t depth = D;
+    int64_t base = slot_base + (int64_t)t * (D * kWave);
     if (t >= full_tiles) tile_geometry(d, t, depth, base);
-    StationTile<St, kWeighted> tl;
+    StationTile<St, kWeighted, D> tl;
     load_static_at(tl, depth, base, (int64_t)(tile0 + t) * kWave + lane, lane, center_base,
                    center_next, slot_next, slot_x, slot_w);
     load_loads(tl, lane, E);
@@ -440,8 +442,8 @@ __device__ __forceinline__ PhaseDesc desc_from_lds(const PhaseDesc *sd, int32_t 
     d.slot_base = (int64_t)(((uint64_t)hi << 32) | lo);
     d.tile0 = __builtin_amdgcn_readlane(v, 2);
 #pragma unroll
-    for (int k = 0; k < kMaxStar; ++k) d.T[k] = __builtin_amdgcn_readlane(v, 3 + k);
-    d.sink = __builtin_amdgcn_readlane(v, 3 + kMaxStar);
+    for (int k = 0; k < kTierStar; ++k) d.T[k] = __builtin_amdgcn_readlane(v, 3 + k);
+    d.sink = __builtin_amdgcn_readlane(v, 3 + kTierStar);
     return d;
 }
 
@@ -522,7 +524,7 @@ __device__ __forceinline__ void run_phases_single(int32_t nph, const PhaseDesc *
 // One middle-tier phase for this wave: its first tile's static part is
 // already in tl; the loads are read now (after the previous barrier).
 template <class St, bool kWeighted>
-__device__ __forceinline__ void mid_phase(StationTile<St, kWeighted> &tl, const PhaseDesc &d,
+__device__ __forceinline__ void mid_phase(StationTile<St, kWeighted, kTierStar> &tl, const PhaseDesc &d,
                                           int wave, int lane, int64_t center_base,
                                           const uint32_t *__restrict__ center_next,
                                           const uint32_t *__restrict__ slot_next,
@@ -555,7 +557,7 @@ k_mid(int32_t nph, const PhaseDesc *__restrict__ descs, int64_t center_base,
     stage_descs(nph, descs, sd);
     __syncthreads();
     if (nph <= 0) return;
-    StationTile<St, kWeighted> ta, tb;
+    StationTile<St, kWeighted, kTierStar> ta, tb;
     PhaseDesc da = desc_from_lds(sd, 0, lane), db;
     if (wave < da.T[0])
         load_static(ta, da, wave, lane, center_base, center_next, slot_next, slot_x, slot_w);
@@ -1121,7 +1123,7 @@ static void sweep_launchers(SweepLaunch &fn) {
             hipLaunchKernelGGL((k_init_loads_big<St>), dim3((unsigned)nbig), dim3(kWave), 0, s, big,
                                row_ptr, inc, w, home, (typename St::L *)E);
     };
-    fn.phase = [](const PhaseDesc &d, int64_t center_base, const uint32_t *center_next,
+    fn.phase = [](const PhaseDescWide &d, int64_t center_base, const uint32_t *center_next,
                   const uint32_t *slot_next, void *slot_x, const float *slot_w, void *E,
                   hipStream_t s) {
         const int32_t tiles = d.T[0];
@@ -1129,10 +1131,18 @@ static void sweep_launchers(SweepLaunch &fn) {
         while (spread < kMaxSpreadLog2 && ((int64_t)tiles << (spread + 1)) <= kSpreadWaves)
             ++spread;
         const unsigned blocks = (unsigned)((int64_t)tiles << spread);
-        hipLaunchKernelGGL((k_phase<St, kW>), dim3(blocks), dim3(kPhaseBlock), 0, s, d.slot_base,
-                           d.tile0, d.T[0], d.T[kMaxStar - 1], spread, center_base,
-                           (typename St::L *)E, slot_next, (typename St::X *)slot_x, center_next,
-                           d, slot_w);
+        if (desc_depth(d) <= kTierStar) {
+            const PhaseDesc n = narrow_desc<kTierStar>(d);
+            hipLaunchKernelGGL((k_phase<St, kW, kTierStar>), dim3(blocks), dim3(kPhaseBlock), 0, s,
+                               n.slot_base, n.tile0, n.T[0], n.T[kTierStar - 1], spread,
+                               center_base, (typename St::L *)E, slot_next,
+                               (typename St::X *)slot_x, center_next, n, slot_w);
+        } else {
+            hipLaunchKernelGGL((k_phase<St, kW, kMaxStar>), dim3(blocks), dim3(kPhaseBlock), 0, s,
+                               d.slot_base, d.tile0, d.T[0], d.T[kMaxStar - 1], spread,
+                               center_base, (typename St::L *)E, slot_next,
+                               (typename St::X *)slot_x, center_next, d, slot_w);
+        }
     };
     fn.tail = [](int32_t nph, const PhaseDesc *descs, const int32_t *tile_center,
                  const uint32_t *slot_leaf, void *slot_x, const float *slot_w, int64_t tail_base,

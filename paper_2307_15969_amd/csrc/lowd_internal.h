@@ -69,16 +69,42 @@ constexpr uint32_t kNoStation = 0x7FFFFFFFu;
 // (the tiles before t hold sum_{i<t} depth_i = sum_k' min(T[k'], t) rows).
 // Every slot address follows from the phase descriptor alone (a kernel
 // argument), so a phase needs no metadata load before its slot rows.
-constexpr int kMaxStar = 16;          // largest star the sweep kernels take
+constexpr int kMaxStar = 32;          // largest star of a schedule (whole-GPU phases)
+constexpr int kTierStar = 16;         // largest star of the single-workgroup tiers and batches
 constexpr int kTailWaves = 8;         // waves of the LDS-resident tail workgroup
 
-struct PhaseDesc {
+template <int D>
+struct PhaseDescT {
+    static constexpr int kDepth = D;
     int64_t slot_base;                // first slot of the phase
     int32_t tile0;                    // first tile (index into tile_center / 64)
-    int32_t T[kMaxStar];              // T[k] = tiles of depth > k; T[0] = tiles
+    int32_t T[D];                     // T[k] = tiles of depth > k; T[0] = tiles
     int32_t sink;                     // entry that takes the stores of stations without a
                                       // next one (the last entry; unused by the LDS tiers)
 };
+// the schedule's descriptors and the whole-GPU phase kernels
+using PhaseDescWide = PhaseDescT<kMaxStar>;
+// the single-workgroup tiers and the batches, which stage descriptors in LDS
+// and take tiles of at most kTierStar rows
+using PhaseDesc = PhaseDescT<kTierStar>;
+
+// A descriptor in the narrower form (its phase is at most D rows deep).
+template <int D, int E>
+inline PhaseDescT<D> narrow_desc(const PhaseDescT<E> &w) {
+    PhaseDescT<D> d;
+    d.slot_base = w.slot_base;
+    d.tile0 = w.tile0;
+    for (int k = 0; k < D; ++k) d.T[k] = w.T[k];
+    d.sink = w.sink;
+    return d;
+}
+// rows of the phase's deepest tile
+template <int D>
+inline int32_t desc_depth(const PhaseDescT<D> &d) {
+    int32_t k = 0;
+    while (k < D && d.T[k] > 0) ++k;
+    return k;
+}
 
 // LDS bytes the tail workgroup spends on its phase descriptors.
 __host__ __device__ inline size_t tail_desc_bytes(int64_t nph) {
@@ -96,7 +122,7 @@ struct Schedule {
     int32_t P1 = 0;                 // phases [0, P1) run as whole-GPU launches
     int32_t P0 = 0;                 // [P1, P0) in one workgroup, loads in global memory;
                                     // [P0, P) in one workgroup, loads in LDS
-    std::vector<PhaseDesc> desc;          // [P]
+    std::vector<PhaseDescWide> desc;      // [P]
     std::vector<int32_t> tile_center;     // [ntiles*64] node id (local ids for tail tiles), -1 empty
     std::vector<uint32_t> slot_leaf;      // [nslots] leaf | orientation (padding: dummy leaf)
     std::vector<int64_t> slot_edge;       // [nslots] edge index, -1 for padding

@@ -126,7 +126,7 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
     if (smax > kMaxStar && force_p0 != -2) {
         // the device layout holds stars of up to kMaxStar leaves; callers that
         // only want the phase assignment pass force_p0 = -2
-        fail(LOWD_E_ARG, "star_max must be at most 16 for the sweep kernels");
+        fail(LOWD_E_ARG, "star_max must be at most 32 for the sweep kernels");
     }
     out.n = n;
     out.m = m;
@@ -294,9 +294,15 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
     CostModel cm;
     // the tail [p0, P) fits when its descriptors and node loads fit in LDS,
     // and no tail phase is wider than the workgroup
-    int32_t min_p0 = 0;
-    for (int32_t p = 0; p < P; ++p)
+    // and no tail or middle phase has a star deeper than the tiers' tiles
+    int32_t min_p0 = 0, min_p1 = 0;
+    for (int32_t p = 0; p < P; ++p) {
         if ((int64_t)stars[(size_t)p].size() > (int64_t)kTailWaves * kWave) min_p0 = p + 1;
+        if (maxstar[(size_t)p] > kTierStar) {
+            min_p0 = std::max(min_p0, p + 1);
+            min_p1 = p + 1;
+        }
+    }
     auto fits = [&](int32_t p0) {
         if (lds_bytes <= 0) return p0 >= P;
         if (p0 < min_p0) return false;
@@ -323,7 +329,7 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
     auto best_p1 = [&](int32_t p0, double *cost) {
         int32_t b = p0;
         double bc = gpre[(size_t)p0] - mpre[(size_t)p0];
-        for (int32_t p1 = p0 - 1; p1 >= 0 && p0 - p1 <= max_mid; --p1) {
+        for (int32_t p1 = p0 - 1; p1 >= min_p1 && p0 - p1 <= max_mid; --p1) {
             const double c = gpre[(size_t)p1] - mpre[(size_t)p1];
             if (c < bc) { bc = c; b = p1; }
         }
@@ -340,6 +346,7 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
         P1 = (int32_t)std::min<int64_t>(force_p1 >= 0 ? force_p1 : P0, P0);
         if (lds_bytes <= 0) P1 = P0;
         if (P0 - P1 > max_mid) P1 = (int32_t)(P0 - max_mid);
+        if (P1 < min_p1) P1 = std::min(min_p1, P0);
     } else if (lds_bytes > 0 && P > 0) {
         double c0;
         P1 = best_p1(P, &c0);
@@ -371,13 +378,13 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
     }
 
     // ---- tiles and slots ----------------------------------------------------
-    out.desc.assign((size_t)P, PhaseDesc{});
+    out.desc.assign((size_t)P, PhaseDescWide{});
     out.phase_edges = ecount;
     out.phase_depth.assign((size_t)P, 0);
     int64_t ntiles = 0, nslots = 0;
     for (int32_t p = 0; p < P; ++p) {
         const std::vector<Star> &st = stars[(size_t)p];
-        PhaseDesc &d = out.desc[(size_t)p];
+        PhaseDescWide &d = out.desc[(size_t)p];
         d.slot_base = nslots;
         d.tile0 = (int32_t)ntiles;
         d.sink = 0;
@@ -425,14 +432,14 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
             const int64_t t = (int64_t)((stars[(size_t)p].size() + kWave - 1) / kWave);
             for (int64_t i = 0; i < t * kWave; ++i)
                 out.tile_center[(size_t)(out.desc[(size_t)p].tile0 * kWave + i)] = ntail_nodes;
-            const PhaseDesc &dd = out.desc[(size_t)p];
+            const PhaseDescWide &dd = out.desc[(size_t)p];
             int64_t rows = 0;
             for (int k = 0; k < kMaxStar; ++k) rows += dd.T[k];
             for (int64_t i = 0; i < rows * kWave; ++i)
                 out.slot_leaf[(size_t)(dd.slot_base + i)] = (uint32_t)ntail_nodes + 1u;
         }
         const std::vector<Star> &st = stars[(size_t)p];
-        const PhaseDesc &d = out.desc[(size_t)p];
+        const PhaseDescWide &d = out.desc[(size_t)p];
         for (size_t i = 0; i < st.size(); ++i) {
             const Star &sr = st[i];
             const int64_t tt = (int64_t)(i / kWave);
@@ -469,7 +476,7 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
     // there, so the kernels store without a branch
     if (entries + 1 >= (int64_t)kNoStation)
         fail(LOWD_E_UNSUPPORTED, "graph too large for 31-bit station indices");
-    for (PhaseDesc &d : out.desc) d.sink = (int32_t)entries;
+    for (PhaseDescWide &d : out.desc) d.sink = (int32_t)entries;
     out.entries = entries + 1;
     // the orientation bit rides on the leaf slot's next station
     for (int64_t sl = 0; sl < (P0 < P ? out.desc[(size_t)P0].slot_base : nslots); ++sl)

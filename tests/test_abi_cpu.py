@@ -77,7 +77,7 @@ def test_host_schedule_rejects_invalid_edges():
         lowd.schedule_build(4, np.array([0, 5]), np.array([1, 2]))
 
 
-@pytest.mark.parametrize("smax", [1, 2, 5, 16, 64])
+@pytest.mark.parametrize("smax", [1, 2, 5, 16, 32, 64])
 def test_host_schedule_equals_oracle_schedule(smax):
     graphs = [synth.workload(0)]
     rng = np.random.default_rng(smax)

@@ -84,7 +84,7 @@ def test_init_is_bit_exact(name, g):
 
 
 @pytest.mark.parametrize("tier", list(SPLITS))
-@pytest.mark.parametrize("smax", [1, 16])
+@pytest.mark.parametrize("smax", [1, 16, 32])
 @pytest.mark.parametrize("name,g", GRAPHS, ids=[n for n, _ in GRAPHS])
 def test_sweeps_are_bit_exact(name, g, smax, tier, split):
     split(tier)
@@ -95,7 +95,9 @@ def test_sweeps_are_bit_exact(name, g, smax, tier, split):
     if tier == "no_lds":
         assert info["lds_phases"] == 0 and info["mid_phases"] == 0
     if tier == "all_mid":
-        assert info["grid_phases"] == 0 and info["lds_phases"] == 0
+        # phases with stars deeper than 16 leaves run as whole-GPU launches
+        assert info["lds_phases"] == 0
+        assert info["grid_phases"] == 0 or smax > 16
     T = 7
     # several launches of the sweep graph with eager work in between
     sv.iterate(1)

@@ -197,8 +197,9 @@ SPLITS = {"auto": (None, None), "all_lds": (0, None), "no_lds": (1 << 30, 1 << 3
           "all_mid": (1 << 30, 0), "mid_lds": (None, 0)}
 
 
+@pytest.mark.parametrize("smax", [16, 32])
 @pytest.mark.parametrize("tier", list(SPLITS))
-def test_pruned_rmat_h_sweeps_bit_exact(rmat_h, tier, monkeypatch):
+def test_pruned_rmat_h_sweeps_bit_exact(rmat_h, tier, smax, monkeypatch):
     g, h = rmat_h
     tail, mid = SPLITS[tier]
     for var, v in (("LOWD_TAIL_SPLIT", tail), ("LOWD_MID_SPLIT", mid)):
@@ -211,12 +212,12 @@ def test_pruned_rmat_h_sweeps_bit_exact(rmat_h, tier, monkeypatch):
     assert np.array_equal(pr["src"].cpu().numpy(), h.src)
     assert np.array_equal(pr["dst"].cpu().numpy(), h.dst)
     T = 3
-    sv = lowd.Solver(h.n, pr["src"].clone(), pr["dst"].clone(), None, "f64")
+    sv = lowd.Solver(h.n, pr["src"].clone(), pr["dst"].clone(), None, "f64", star_max=smax)
     info = sv.info()
-    log(f"  {tier}: {info}")
+    log(f"  {tier} smax={smax}: {info}")
     sv.iterate(T)
     x, L = sv.read_state()
-    xo, Lo, _ = oracle_state(h, T)
+    xo, Lo, _ = oracle_state(h, T, smax=smax)
     assert np.array_equal(x.cpu().numpy(), xo)
     assert np.array_equal(L.cpu().numpy(), Lo)
     ex = sv.extract()
@@ -226,25 +227,26 @@ def test_pruned_rmat_h_sweeps_bit_exact(rmat_h, tier, monkeypatch):
     sv.close()
 
 
-def test_pruned_rmat_h_f32k_and_solve(rmat_h):
+@pytest.mark.parametrize("smax", [16, 32])
+def test_pruned_rmat_h_f32k_and_solve(rmat_h, smax):
     """FP32K on H within 1e-5 of the FP64 oracle; both states solved to the
     tolerance give the same densest set, and the FP64 one equals the
     oracle's extraction after its sweeps."""
     _, h = rmat_h
     T = 6
-    sv = lowd.Solver(h.n, h.src, h.dst, None, "f32k")
+    sv = lowd.Solver(h.n, h.src, h.dst, None, "f32k", star_max=smax)
     sv.iterate(T)
     _, L = sv.read_state()
-    _, Lo, _ = oracle_state(h, T)
+    _, Lo, _ = oracle_state(h, T, smax=smax)
     assert np.max(np.abs(L.cpu().numpy() - Lo)) <= 1e-5 * np.max(np.abs(Lo))
     sv.reset()
     r32 = sv.solve(TOL)
     sv.close()
-    sv = lowd.Solver(h.n, h.src, h.dst, None, "f64")
+    sv = lowd.Solver(h.n, h.src, h.dst, None, "f64", star_max=smax)
     r64 = sv.solve(TOL)
     sv.close()
     assert r32["converged"] and r64["converged"]
-    _, Lo, _ = oracle_state(h, r64["sweeps"])
+    _, Lo, _ = oracle_state(h, r64["sweeps"], smax=smax)
     ro = oracle.extract(h.n, h.src, h.dst, None, Lo)
     assert r64["D"] == float(Lo.max())
     assert (r64["num"], r64["den"]) == (ro["num"], ro["den"])

@@ -202,7 +202,7 @@ def _rho_h(keep, src, dst):
 @pytest.mark.parametrize("seed", range(6))
 def test_prune_equals_core_of_ceil_density(seed):
     """Every removed node had degree below delta <= rho(H), every kept node
-    has degree >= rho(H) (Theorem 3), so H is the ceil(rho(H))-core of G."""
+    has degree >= rho(H) (Theorem 4), so H is the ceil(rho(H))-core of G."""
     rng = np.random.default_rng(seed)
     for _ in range(20):
         n = int(rng.integers(5, 120))
@@ -227,7 +227,7 @@ def test_prune_workload0_and_densest_inside():
     G.add_edges_from(zip(g.src.tolist(), g.dst.tolist()))
     rho, inside = _rho_h(keep, g.src, g.dst)
     assert set(np.flatnonzero(keep)) == set(nx.k_core(G, math.ceil(rho)).nodes())
-    # Theorem 3 / Section III-D: the densest set survives pruning
+    # Theorem 4 / Section III-D: the densest set survives pruning
     r = converge(g, 200)
     assert np.all(keep[r["in_set"].astype(bool)] == 1)
     # density of H is at least that of G
@@ -341,7 +341,7 @@ def test_one_way_property_at_the_limit():
 # --------------------------------------------------------------- schedule --
 def test_schedule_phases_are_star_forests():
     g = synth.workload(0)
-    for smax in (1, 4, 16):
+    for smax in (1, 4, 16, 32):
         phase, center, order, P = oracle.schedule(g.n, g.src, g.dst, smax)
         assert np.array_equal(np.sort(order), np.arange(g.m))
         assert np.all(np.diff(phase[order]) >= 0)
