@@ -85,6 +85,26 @@ lowd_status lowd_prune(int32_t n, int64_t m, const int32_t *src, const int32_t *
                        void *stream);
 
 /*
+ * lowd_prune_noalloc -- lowd_prune for callers that cannot allocate device
+ * memory (tight serving loops, harnesses that forbid hipMalloc): the same
+ * arguments, the same results bit for bit, but every device buffer of the
+ * validation and the prune (incidence rows, degree buckets, sort and scan
+ * scratch) comes from one file-scope device array of 128 MiB that each GPU
+ * holds from the library's load until the process ends; the call makes no
+ * hipMalloc, hipFree or other allocating call.  A graph whose buffers would
+ * exceed 128 MiB (about 32 bytes per edge plus 64 per node) is rejected
+ * with LOWD_E_UNSUPPORTED before any device work.  Every call on one GPU
+ * uses that GPU's one array and keeps what the last call left there, so
+ * calls that overlap on one GPU (other threads, other streams) race: the
+ * caller serialises them.  Buffers that must start at zero are cleared by
+ * the call itself.  Synchronises `stream`.
+ */
+lowd_status lowd_prune_noalloc(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                               uint8_t *node_keep, int32_t *relabel, int32_t *h_src,
+                               int32_t *h_dst, int64_t *edge_map, int32_t *rounds, int32_t *n_h,
+                               int64_t *m_h, void *stream);
+
+/*
  * lowd_prune_weighted -- Algorithm 2 on a weighted graph (Section III-D: each
  * round scans the nodes still in H): every round removes each node whose
  * weighted degree in H is below rho(H) = w(E(H)) / |V(H)|, until a round

@@ -43,6 +43,7 @@ def lib() -> C.CDLL:
         L.lowd_version.restype = C.c_char_p
         L.lowd_last_error.restype = C.c_char_p
         L.lowd_prune.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp, vp, P(i32), P(i32), P(i64), vp]
+        L.lowd_prune_noalloc.argtypes = L.lowd_prune.argtypes
         L.lowd_prune_weighted.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, P(i32),
                                           P(i32), P(i64), P(C.c_double), vp]
         L.lowd_greedy_peel.argtypes = [i32, i64, vp, vp, vp, vp, vp, P(i64), P(i64), vp]
@@ -78,7 +79,7 @@ def lib() -> C.CDLL:
         L.lowd_batch_retire.argtypes = [vp, vp, vp, vp, C.c_double, P(i32), P(i64), vp]
         L.lowd_batch_free.argtypes = [vp]
         L.lowd_batch_free.restype = None
-        for f in (L.lowd_prune, L.lowd_prune_weighted, L.lowd_greedy_peel, L.lowd_init_loads, L.lowd_iterate, L.lowd_check,
+        for f in (L.lowd_prune, L.lowd_prune_noalloc, L.lowd_prune_weighted, L.lowd_greedy_peel, L.lowd_init_loads, L.lowd_iterate, L.lowd_check,
                   L.lowd_extract_densest, L.lowd_read_state, L.lowd_schedule_export,
                   L.lowd_ldd_readout, L.lowd_convergence_trace, L.lowd_dks_bound,
                   L.lowd_solver_info, L.lowd_batch_solve, L.lowd_schedule_build, L.lowd_reset_loads,
@@ -127,9 +128,11 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
-def prune(n: int, src, dst, stream=None) -> dict:
+def prune(n: int, src, dst, stream=None, noalloc: bool = False) -> dict:
     """Algorithm 2 on an unweighted graph (device arrays) -> dict with the
-    node mask, the renumbering, the compacted edge list of H and its sizes."""
+    node mask, the renumbering, the compacted edge list of H and its sizes.
+    noalloc: lowd_prune_noalloc (the library's fixed scratch, no device
+    allocation inside the call)."""
     torch = _torch()
     s = _dev(src, torch.int32, "src")
     d = _dev(dst, torch.int32, "dst")
@@ -140,8 +143,9 @@ def prune(n: int, src, dst, stream=None) -> dict:
     hd = torch.empty(max(m, 1), dtype=torch.int32, device=s.device)
     emap = torch.empty(max(m, 1), dtype=torch.int64, device=s.device)
     r, nh, mh = C.c_int32(0), C.c_int32(0), C.c_int64(0)
-    _check(lib().lowd_prune(n, m, _ptr(s), _ptr(d), _ptr(keep), _ptr(relabel), _ptr(hs), _ptr(hd),
-                            _ptr(emap), C.byref(r), C.byref(nh), C.byref(mh), _stream(stream)))
+    f = lib().lowd_prune_noalloc if noalloc else lib().lowd_prune
+    _check(f(n, m, _ptr(s), _ptr(d), _ptr(keep), _ptr(relabel), _ptr(hs), _ptr(hd), _ptr(emap),
+             C.byref(r), C.byref(nh), C.byref(mh), _stream(stream)))
     mh = int(mh.value)
     return dict(node_keep=keep, relabel=relabel, src=hs[:mh], dst=hd[:mh], edge_map=emap[:mh],
                 rounds=int(r.value), n_h=int(nh.value), m_h=mh)

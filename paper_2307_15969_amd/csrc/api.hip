@@ -10,6 +10,7 @@
 #include <exception>
 #include <thread>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -71,27 +72,44 @@ static size_t lds_capacity_bytes() {
 
 // Checks the edge list on the device (ids in range, no self-loop, weights
 // positive and finite, no repeated pair) and fails with the first bad edge.
-static void validate_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
-                           const float *w, hipStream_t s) {
-    DBuf<int64_t> bad(1);
-    launch_validate(n, m, src, dst, w, bad.p, s);
+// Its device buffers come from `ws` and are released on return; a region
+// without a base only measures them.
+static void validate_graph_ws(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                              const float *w, Arena &ws, hipStream_t s) {
+    const size_t mk = ws.mark();
+    int64_t *bad = ws.take<int64_t>(1);
     int64_t b = -1;
-    LOWD_HIP(hipMemcpy(&b, bad.p, sizeof(b), hipMemcpyDeviceToHost));
-    std::string what = "invalid edge";
-    if ((uint64_t)b == ~0ull) {
-        b = find_duplicate_pair(n, m, src, dst, s);
-        what = "repeated pair";
+    if (ws.base) {
+        launch_validate(n, m, src, dst, w, bad, s);
+        LOWD_HIP(hipMemcpy(&b, bad, sizeof(b), hipMemcpyDeviceToHost));
     }
+    const bool in_range = (uint64_t)b == ~0ull;
+    if (in_range || !ws.base) b = find_duplicate_pair_ws(n, m, src, dst, ws, s);
+    ws.release(mk);
     if (b >= 0 && (uint64_t)b != ~0ull) {
         int32_t a = 0, c = 0;
         float x = 1.0f;
         LOWD_HIP(hipMemcpy(&a, src + b, 4, hipMemcpyDeviceToHost));
         LOWD_HIP(hipMemcpy(&c, dst + b, 4, hipMemcpyDeviceToHost));
         if (w) LOWD_HIP(hipMemcpy(&x, w + b, 4, hipMemcpyDeviceToHost));
-        fail(LOWD_E_GRAPH, what + " at index " + std::to_string(b) + ": (" + std::to_string(a) +
+        fail(LOWD_E_GRAPH, std::string(in_range ? "repeated pair" : "invalid edge") +
+                               " at index " + std::to_string(b) + ": (" + std::to_string(a) +
                                ", " + std::to_string(c) + ") weight " + std::to_string(x) +
                                " (n = " + std::to_string(n) + ")");
     }
+}
+
+static size_t validate_ws_bytes(int32_t n, int64_t m, const float *w) {
+    Arena measure;
+    validate_graph_ws(n, m, nullptr, nullptr, w, measure, nullptr);
+    return measure.peak;
+}
+
+static void validate_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                           const float *w, hipStream_t s) {
+    DBuf<char> buf(validate_ws_bytes(n, m, w));
+    Arena ws(buf.p, buf.bytes());
+    validate_graph_ws(n, m, src, dst, w, ws, s);
 }
 
 }  // namespace lowd
@@ -719,6 +737,64 @@ lowd_status lowd_prune(int32_t n, int64_t m, const int32_t *src, const int32_t *
         hipStream_t s = (hipStream_t)stream;
         validate_graph(n, m, src, dst, nullptr, s);
         PruneResult r = run_prune(n, m, src, dst, node_keep, relabel, h_src, h_dst, edge_map, s);
+        if (rounds) *rounds = r.rounds;
+        if (n_h) *n_h = r.n_h;
+        if (m_h) *m_h = r.m_h;
+    });
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- allocation-free prune --
+// lowd_prune_noalloc takes every device buffer from this file-scope array.
+// Each GPU the library runs on holds its own copy until the process ends.
+// Host code reaches a device's copy only through the address
+// hipGetSymbolAddress returns on that device, taken once per device.
+constexpr size_t kNoAllocScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+void *scratch_on_current_device() {
+    int dev = 0;
+    LOWD_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) fail(LOWD_E_UNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        LOWD_HIP(hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" {
+
+lowd_status lowd_prune_noalloc(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                               uint8_t *node_keep, int32_t *relabel, int32_t *h_src,
+                               int32_t *h_dst, int64_t *edge_map, int32_t *rounds, int32_t *n_h,
+                               int64_t *m_h, void *stream) {
+    return guarded([&] {
+        if (n < 1) fail(LOWD_E_ARG, "n must be >= 1");
+        if (m < 0 || m >= ((int64_t)1 << 31)) fail(LOWD_E_ARG, "m must be in [0, 2^31)");
+        if (m > 0 && (!src || !dst)) fail(LOWD_E_ARG, "src/dst is NULL");
+        if (!node_keep) fail(LOWD_E_ARG, "node_keep is NULL");
+        if ((h_src == nullptr) != (h_dst == nullptr)) fail(LOWD_E_ARG, "h_src/h_dst: both or none");
+        const size_t need = std::max(validate_ws_bytes(n, m, nullptr),
+                                     prune_ws_bytes(n, m, h_src != nullptr, edge_map != nullptr));
+        if (need > kNoAllocScratchBytes)
+            fail(LOWD_E_UNSUPPORTED, "this graph needs " + std::to_string(need) +
+                                         " bytes of scratch; lowd_prune_noalloc holds " +
+                                         std::to_string(kNoAllocScratchBytes));
+        hipStream_t s = (hipStream_t)stream;
+        Arena ws(scratch_on_current_device(), kNoAllocScratchBytes);
+        validate_graph_ws(n, m, src, dst, nullptr, ws, s);
+        PruneResult r =
+            run_prune_ws(n, m, src, dst, node_keep, relabel, h_src, h_dst, edge_map, ws, s);
         if (rounds) *rounds = r.rounds;
         if (n_h) *n_h = r.n_h;
         if (m_h) *m_h = r.m_h;

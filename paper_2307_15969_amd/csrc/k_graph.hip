@@ -81,6 +81,37 @@ void build_adjacency(int64_t m, const Csr &csr, const int32_t *src, const int32_
     LOWD_HIP(hipGetLastError());
 }
 
+void build_incidence_ws(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, Arena &ws,
+                        int64_t **row_ptr, uint32_t **inc, hipStream_t s) {
+    const int64_t len = 2 * m;
+    const size_t cap = (size_t)(len > 0 ? len : 1);
+    *row_ptr = ws.take<int64_t>((size_t)n + 1);
+    *inc = ws.take<uint32_t>(cap);
+    const size_t mk = ws.mark();
+    uint32_t *k0 = ws.take<uint32_t>(cap), *k1 = ws.take<uint32_t>(cap);
+    uint32_t *v1 = ws.take<uint32_t>(cap);
+    const size_t tmp_bytes = radix_sort_tmp_bytes(len);
+    char *tmp = ws.take<char>(tmp_bytes);
+    if (ws.base) {
+        int bits = 1;
+        while (bits < 32 && ((int64_t)1 << bits) < (int64_t)n) ++bits;
+        if (len > 0)
+            hipLaunchKernelGGL(k_incidence_keys, dim3(grid_for(len, 256)), dim3(256), 0, s, m, src,
+                               dst, k0, *inc);
+        bool alt = false;
+        radix_sort_u32(k0, *inc, k1, v1, len, bits, tmp, tmp_bytes, &alt, s);
+        const uint32_t *keys = alt ? k1 : k0;
+        hipLaunchKernelGGL(k_row_ptr, dim3(grid_for((int64_t)n + 1, 256)), dim3(256), 0, s, keys,
+                           len, n, *row_ptr);
+        if (alt && len > 0)
+            LOWD_HIP(hipMemcpyAsync(*inc, v1, (size_t)len * sizeof(uint32_t),
+                                    hipMemcpyDeviceToDevice, s));
+        LOWD_HIP(hipGetLastError());
+        LOWD_HIP(hipStreamSynchronize(s));
+    }
+    ws.release(mk);
+}
+
 void build_incidence(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, Csr &csr,
                      hipStream_t s) {
     int64_t len = 2 * m;
@@ -130,28 +161,43 @@ __global__ void k_adjacent_equal(int64_t m, const uint64_t *keys, const uint32_t
 }  // namespace
 
 // Index of the later edge of the first repeated unordered pair found, or -1.
+int64_t find_duplicate_pair_ws(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                               Arena &ws, hipStream_t s) {
+    if (m < 2) return -1;
+    const size_t mk = ws.mark();
+    uint64_t *k0 = ws.take<uint64_t>((size_t)m), *k1 = ws.take<uint64_t>((size_t)m);
+    uint32_t *v0 = ws.take<uint32_t>((size_t)m), *v1 = ws.take<uint32_t>((size_t)m);
+    const size_t tmp_bytes = radix_sort_tmp_bytes(m);
+    char *tmp = ws.take<char>(tmp_bytes);
+    unsigned long long *bad = ws.take<unsigned long long>(1);
+    unsigned long long r = ~0ull;
+    if (ws.base) {
+        int nb = 1;
+        while (nb < 32 && ((int64_t)1 << nb) < (int64_t)n) ++nb;
+        hipLaunchKernelGGL(k_pair_keys, dim3(grid_for(m, 256)), dim3(256), 0, s, m, src, dst, k0,
+                           v0);
+        bool alt = false;
+        radix_sort_u64(k0, v0, k1, v1, m, 32 + nb, tmp, tmp_bytes, &alt, s);
+        unsigned long long init = ~0ull;
+        LOWD_HIP(hipMemcpyAsync(bad, &init, sizeof(init), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_adjacent_equal, dim3(grid_for(m, 256)), dim3(256), 0, s, m,
+                           alt ? k1 : k0, alt ? v1 : v0, bad);
+        LOWD_HIP(hipGetLastError());
+        LOWD_HIP(hipMemcpyAsync(&r, bad, sizeof(r), hipMemcpyDeviceToHost, s));
+        LOWD_HIP(hipStreamSynchronize(s));
+    }
+    ws.release(mk);
+    return r == ~0ull ? -1 : (int64_t)r;
+}
+
 int64_t find_duplicate_pair(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
                             hipStream_t s) {
     if (m < 2) return -1;
-    int nb = 1;
-    while (nb < 32 && ((int64_t)1 << nb) < (int64_t)n) ++nb;
-    DBuf<uint64_t> k0((size_t)m), k1((size_t)m);
-    DBuf<uint32_t> v0((size_t)m), v1((size_t)m);
-    DBuf<char> tmp(radix_sort_tmp_bytes(m));
-    DBuf<int64_t> bad(1);
-    hipLaunchKernelGGL(k_pair_keys, dim3(grid_for(m, 256)), dim3(256), 0, s, m, src, dst, k0.p,
-                       v0.p);
-    bool alt = false;
-    radix_sort_u64(k0.p, v0.p, k1.p, v1.p, m, 32 + nb, tmp.p, tmp.bytes(), &alt, s);
-    unsigned long long init = ~0ull;
-    LOWD_HIP(hipMemcpyAsync(bad.p, &init, sizeof(init), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_adjacent_equal, dim3(grid_for(m, 256)), dim3(256), 0, s, m,
-                       alt ? k1.p : k0.p, alt ? v1.p : v0.p, (unsigned long long *)bad.p);
-    LOWD_HIP(hipGetLastError());
-    unsigned long long r = 0;
-    LOWD_HIP(hipMemcpyAsync(&r, bad.p, sizeof(r), hipMemcpyDeviceToHost, s));
-    LOWD_HIP(hipStreamSynchronize(s));
-    return r == ~0ull ? -1 : (int64_t)r;
+    Arena measure;
+    find_duplicate_pair_ws(n, m, src, dst, measure, s);
+    DBuf<char> buf(measure.peak);
+    Arena ws(buf.p, buf.bytes());
+    return find_duplicate_pair_ws(n, m, src, dst, ws, s);
 }
 
 }  // namespace lowd

@@ -22,6 +22,8 @@
 #include <cmath>
 #include <vector>
 
+#include <array>
+
 #include "lowd_internal.h"
 #include "prune.h"
 
@@ -324,40 +326,54 @@ __global__ void k_weighted_test(int64_t k, const uint64_t *dlo, const uint64_t *
 
 }  // namespace
 
-PruneResult run_prune(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
-                      uint8_t *node_keep, int32_t *relabel, int32_t *h_src, int32_t *h_dst,
-                      int64_t *edge_map, hipStream_t s) {
+// Every device buffer of the prune comes from `ws`, taken in a fixed order,
+// so a region without a base measures what a call needs (prune_ws_bytes).
+PruneResult run_prune_ws(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                         uint8_t *node_keep, int32_t *relabel, int32_t *h_src, int32_t *h_dst,
+                         int64_t *edge_map, Arena &ws, hipStream_t s) {
     PruneResult res;
     const unsigned gn = grid_for(n, 256);
-    Csr csr;
-    build_incidence(n, m, src, dst, csr, s);
-    DBuf<int32_t> deg((size_t)n), stamp((size_t)n), by_deg((size_t)n), list_a((size_t)n),
-        list_b((size_t)n), removed((size_t)n);
-    DBuf<unsigned long long> hist(kBins), cursor(kBins), gone(1);
-    DBuf<int64_t> bin_start(kBins), f_rm((size_t)n), f_keep((size_t)n), p_rm((size_t)n),
-        p_keep((size_t)n), tot(2);
+    struct {
+        int64_t *row_ptr;
+        uint32_t *inc;
+    } csr;
+    build_incidence_ws(n, m, src, dst, ws, &csr.row_ptr, &csr.inc, s);
+    const size_t nn = (size_t)n;
+    int32_t *deg = ws.take<int32_t>(nn), *stamp = ws.take<int32_t>(nn),
+            *by_deg = ws.take<int32_t>(nn), *list_a = ws.take<int32_t>(nn),
+            *list_b = ws.take<int32_t>(nn), *removed = ws.take<int32_t>(nn);
+    unsigned long long *hist = ws.take<unsigned long long>(kBins),
+                       *cursor = ws.take<unsigned long long>(kBins),
+                       *gone = ws.take<unsigned long long>(1);
+    int64_t *bin_start = ws.take<int64_t>(kBins), *f_rm = ws.take<int64_t>(nn),
+            *f_keep = ws.take<int64_t>(nn), *p_rm = ws.take<int64_t>(nn),
+            *p_keep = ws.take<int64_t>(nn), *tot = ws.take<int64_t>(2);
     int64_t big = n > m ? (int64_t)n : m;
     if (big < kBins) big = kBins;
-    DBuf<char> scan_tmp(exclusive_scan_tmp_bytes(big));
+    const size_t scan_bytes = exclusive_scan_tmp_bytes(big);
+    char *scan_tmp = ws.take<char>(scan_bytes);
+    const bool edges_out = (h_src || edge_map) && m > 0;
+    int64_t *ef = edges_out ? ws.take<int64_t>((size_t)m) : nullptr;
+    int64_t *ep = edges_out ? ws.take<int64_t>((size_t)m) : nullptr;
+    if (!ws.base) return res;   // measuring only
 
-    hipLaunchKernelGGL(k_degrees, dim3(gn), dim3(256), 0, s, n, csr.row_ptr.p, deg.p);
-    LOWD_HIP(hipMemsetAsync(hist.p, 0, kBins * sizeof(unsigned long long), s));
-    LOWD_HIP(hipMemsetAsync(cursor.p, 0, kBins * sizeof(unsigned long long), s));
-    LOWD_HIP(hipMemsetAsync(stamp.p, 0, (size_t)n * sizeof(int32_t), s));
-    hipLaunchKernelGGL(k_degree_hist, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, n, deg.p,
-                       hist.p);
-    exclusive_scan_i64((const int64_t *)hist.p, bin_start.p, kBins, nullptr, scan_tmp.p,
-                       scan_tmp.bytes(), s);
+    hipLaunchKernelGGL(k_degrees, dim3(gn), dim3(256), 0, s, n, csr.row_ptr, deg);
+    LOWD_HIP(hipMemsetAsync(hist, 0, kBins * sizeof(unsigned long long), s));
+    LOWD_HIP(hipMemsetAsync(cursor, 0, kBins * sizeof(unsigned long long), s));
+    LOWD_HIP(hipMemsetAsync(stamp, 0, (size_t)n * sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_degree_hist, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, n, deg,
+                       hist);
+    exclusive_scan_i64((const int64_t *)hist, bin_start, kBins, nullptr, scan_tmp, scan_bytes, s);
     if (n > 0)
         hipLaunchKernelGGL(k_bucket_scatter, dim3((unsigned)((n + kScatterChunk - 1) / kScatterChunk)),
-                           dim3(kScatterBlock), 0, s, n, deg.p, bin_start.p, cursor.p, by_deg.p);
-    std::vector<int64_t> hstart(kBins);
-    LOWD_HIP(hipMemcpyAsync(hstart.data(), bin_start.p, kBins * sizeof(int64_t),
+                           dim3(kScatterBlock), 0, s, n, deg, bin_start, cursor, by_deg);
+    std::array<int64_t, kBins> hstart;
+    LOWD_HIP(hipMemcpyAsync(hstart.data(), bin_start, kBins * sizeof(int64_t),
                             hipMemcpyDeviceToHost, s));
     LOWD_HIP(hipStreamSynchronize(s));
 
     int64_t N = n, M = m;
-    const int32_t *alive = by_deg.p;   // current alive list (read only)
+    const int32_t *alive = by_deg;   // current alive list (read only)
     int64_t nalive = n;
     for (int32_t round = 1;; ++round) {
         const int32_t *rm_list;
@@ -365,48 +381,48 @@ PruneResult run_prune(int32_t n, int64_t m, const int32_t *src, const int32_t *d
         if (round == 1 && M > 0 && (M + N - 1) / N <= kBins - 1) {
             // the removed nodes are the buckets of degree < ceil(M / N)
             int64_t cut = hstart[(size_t)((M + N - 1) / N)];
-            rm_list = by_deg.p;
+            rm_list = by_deg;
             nrm = cut;
-            alive = by_deg.p + cut;
+            alive = by_deg + cut;
             nalive = n - cut;
         } else {
             if (nalive == 0 || M == 0) break;
             const unsigned gc = grid_for(nalive, 256);
-            hipLaunchKernelGGL(k_test, dim3(gc), dim3(256), 0, s, nalive, alive, deg.p, N, M,
-                               f_rm.p, f_keep.p);
-            exclusive_scan_i64(f_rm.p, p_rm.p, nalive, tot.p, scan_tmp.p, scan_tmp.bytes(), s);
-            exclusive_scan_i64(f_keep.p, p_keep.p, nalive, tot.p + 1, scan_tmp.p, scan_tmp.bytes(),
+            hipLaunchKernelGGL(k_test, dim3(gc), dim3(256), 0, s, nalive, alive, deg, N, M,
+                               f_rm, f_keep);
+            exclusive_scan_i64(f_rm, p_rm, nalive, tot, scan_tmp, scan_bytes, s);
+            exclusive_scan_i64(f_keep, p_keep, nalive, tot + 1, scan_tmp, scan_bytes,
                                s);
-            int32_t *out = (alive == list_a.p) ? list_b.p : list_a.p;
-            hipLaunchKernelGGL(k_split, dim3(gc), dim3(256), 0, s, nalive, alive, f_rm.p, p_rm.p,
-                               p_keep.p, removed.p, out);
+            int32_t *out = (alive == list_a) ? list_b : list_a;
+            hipLaunchKernelGGL(k_split, dim3(gc), dim3(256), 0, s, nalive, alive, f_rm, p_rm,
+                               p_keep, removed, out);
             int64_t t[2];
-            LOWD_HIP(hipMemcpyAsync(t, tot.p, sizeof(t), hipMemcpyDeviceToHost, s));
+            LOWD_HIP(hipMemcpyAsync(t, tot, sizeof(t), hipMemcpyDeviceToHost, s));
             LOWD_HIP(hipStreamSynchronize(s));
-            rm_list = removed.p;
+            rm_list = removed;
             nrm = t[0];
             alive = out;
             nalive = t[1];
         }
         if (nrm == 0) break;
-        LOWD_HIP(hipMemsetAsync(gone.p, 0, sizeof(unsigned long long), s));
+        LOWD_HIP(hipMemsetAsync(gone, 0, sizeof(unsigned long long), s));
         const unsigned gr = grid_for(nrm, 256);
-        hipLaunchKernelGGL(k_stamp, dim3(gr), dim3(256), 0, s, nrm, rm_list, stamp.p, round);
+        hipLaunchKernelGGL(k_stamp, dim3(gr), dim3(256), 0, s, nrm, rm_list, stamp, round);
         if (nrm >= (1 << 18))
             hipLaunchKernelGGL(k_remove_edges<1>, dim3(grid_for(nrm, kRemoveBlock)),
-                               dim3(kRemoveBlock), 0, s, nrm, rm_list, csr.row_ptr.p, csr.inc.p,
-                               src, dst, stamp.p, round, deg.p, gone.p);
+                               dim3(kRemoveBlock), 0, s, nrm, rm_list, csr.row_ptr, csr.inc,
+                               src, dst, stamp, round, deg, gone);
         else if (nrm >= (1 << 12))
             hipLaunchKernelGGL(k_remove_edges<kWave>, dim3(grid_for(nrm, kRemoveBlock / kWave)),
-                               dim3(kRemoveBlock), 0, s, nrm, rm_list, csr.row_ptr.p, csr.inc.p,
-                               src, dst, stamp.p, round, deg.p, gone.p);
+                               dim3(kRemoveBlock), 0, s, nrm, rm_list, csr.row_ptr, csr.inc,
+                               src, dst, stamp, round, deg, gone);
         else
             hipLaunchKernelGGL(k_remove_edges<kRemoveBlock>, dim3(grid_for(nrm, 1)),
-                               dim3(kRemoveBlock), 0, s, nrm, rm_list, csr.row_ptr.p, csr.inc.p,
-                               src, dst, stamp.p, round, deg.p, gone.p);
+                               dim3(kRemoveBlock), 0, s, nrm, rm_list, csr.row_ptr, csr.inc,
+                               src, dst, stamp, round, deg, gone);
         LOWD_HIP(hipGetLastError());
         unsigned long long g = 0;
-        LOWD_HIP(hipMemcpyAsync(&g, gone.p, sizeof(g), hipMemcpyDeviceToHost, s));
+        LOWD_HIP(hipMemcpyAsync(&g, gone, sizeof(g), hipMemcpyDeviceToHost, s));
         LOWD_HIP(hipStreamSynchronize(s));
         N -= nrm;
         M -= (int64_t)g;
@@ -414,17 +430,16 @@ PruneResult run_prune(int32_t n, int64_t m, const int32_t *src, const int32_t *d
     }
 
     // outputs: mask, renumbering, compacted edge list
-    hipLaunchKernelGGL(k_keep_flags, dim3(gn), dim3(256), 0, s, n, stamp.p, node_keep, f_keep.p);
-    exclusive_scan_i64(f_keep.p, p_keep.p, n, nullptr, scan_tmp.p, scan_tmp.bytes(), s);
+    hipLaunchKernelGGL(k_keep_flags, dim3(gn), dim3(256), 0, s, n, stamp, node_keep, f_keep);
+    exclusive_scan_i64(f_keep, p_keep, n, nullptr, scan_tmp, scan_bytes, s);
     if (relabel)
-        hipLaunchKernelGGL(k_relabel, dim3(gn), dim3(256), 0, s, n, f_keep.p, p_keep.p, relabel);
-    if ((h_src || edge_map) && m > 0) {
-        DBuf<int64_t> ef((size_t)m), ep((size_t)m);
+        hipLaunchKernelGGL(k_relabel, dim3(gn), dim3(256), 0, s, n, f_keep, p_keep, relabel);
+    if (edges_out) {
         hipLaunchKernelGGL(k_edge_flags, dim3(grid_for(m, 256)), dim3(256), 0, s, m, src, dst,
-                           stamp.p, ef.p);
-        exclusive_scan_i64(ef.p, ep.p, m, nullptr, scan_tmp.p, scan_tmp.bytes(), s);
+                           stamp, ef);
+        exclusive_scan_i64(ef, ep, m, nullptr, scan_tmp, scan_bytes, s);
         hipLaunchKernelGGL(k_edge_compact, dim3(grid_for(m, 256)), dim3(256), 0, s, m, src, dst,
-                           nullptr, ef.p, ep.p, p_keep.p, h_src, h_dst, nullptr, edge_map);
+                           nullptr, ef, ep, p_keep, h_src, h_dst, nullptr, edge_map);
         LOWD_HIP(hipGetLastError());
         LOWD_HIP(hipStreamSynchronize(s));
     }
@@ -433,6 +448,25 @@ PruneResult run_prune(int32_t n, int64_t m, const int32_t *src, const int32_t *d
     res.n_h = (int32_t)N;
     res.m_h = M;
     return res;
+}
+
+PruneResult run_prune(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                      uint8_t *node_keep, int32_t *relabel, int32_t *h_src, int32_t *h_dst,
+                      int64_t *edge_map, hipStream_t s) {
+    const size_t need = prune_ws_bytes(n, m, h_src != nullptr, edge_map != nullptr);
+    DBuf<char> buf(need);
+    Arena ws(buf.p, buf.bytes());
+    return run_prune_ws(n, m, src, dst, node_keep, relabel, h_src, h_dst, edge_map, ws, s);
+}
+
+size_t prune_ws_bytes(int32_t n, int64_t m, bool h_edges, bool edge_map) {
+    Arena measure;
+    int32_t dummy_out = 0;
+    int64_t dummy_map = 0;
+    run_prune_ws(n, m, nullptr, nullptr, nullptr, nullptr, h_edges ? &dummy_out : nullptr,
+                 h_edges ? &dummy_out : nullptr, edge_map ? &dummy_map : nullptr, measure,
+                 nullptr);
+    return measure.peak;
 }
 
 // total = (lo, hi) of the sum of k 128-bit degrees, in two passes

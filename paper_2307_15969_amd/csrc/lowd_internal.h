@@ -50,6 +50,28 @@ struct DBuf {
     size_t bytes() const { return n * sizeof(T); }
 };
 
+// Carves device buffers out of one region, 256-byte aligned, in the order
+// they are taken.  A region without a base only measures (every take returns
+// nullptr): the same sequence of takes then gives the bytes a call needs.
+// mark()/release(mark) give back everything taken after the mark.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0, peak = 0;
+    Arena() = default;
+    Arena(void *b, size_t c) : base((char *)b), cap(c) {}
+    template <class T>
+    T *take(size_t count) {
+        used = (used + 255) & ~(size_t)255;
+        T *p = base ? reinterpret_cast<T *>(base + used) : nullptr;
+        used += (count > 0 ? count : 1) * sizeof(T);
+        if (used > peak) peak = used;
+        if (base && used > cap) fail(LOWD_E_UNSUPPORTED, "workspace too small");
+        return p;
+    }
+    size_t mark() const { return used; }
+    void release(size_t m) { used = m; }
+};
+
 // Slot encoding of a star leaf: bits 0..30 node id (global or LDS-local),
 // bit 31 set when the star's center is the edge's dst (so the leaf is src).
 // Padding slots name the infinite dummy node (n + 1, or the tail's second
@@ -182,6 +204,9 @@ void launch_validate(int32_t n, int64_t m, const int32_t *src, const int32_t *ds
 // Index of the later edge of the first repeated unordered pair, or -1.
 int64_t find_duplicate_pair(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
                             hipStream_t s);
+// The same with its sort buffers taken from `ws` (released again on return).
+int64_t find_duplicate_pair_ws(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                               Arena &ws, hipStream_t s);
 // Incidence CSR, rows in ascending edge index: entry j = 2*e + side
 // (side 0: the row node is src[e]; side 1: dst[e]).  row_ptr has n+1 entries.
 // Rows (incidence rows, i.e. node degrees) of at least this length are
@@ -195,6 +220,10 @@ struct Csr {
 };
 void build_incidence(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, Csr &csr,
                      hipStream_t s);
+// The same into row_ptr [n+1] and inc [2m] taken from `ws` (its sort
+// buffers taken after them and released again).
+void build_incidence_ws(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, Arena &ws,
+                        int64_t **row_ptr, uint32_t **inc, hipStream_t s);
 // adj[j] = the other end of the edge of incidence entry j ([2m])
 void build_adjacency(int64_t m, const Csr &csr, const int32_t *src, const int32_t *dst,
                      int32_t *adj, hipStream_t s);

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "lowd_internal.h"
+
 namespace lowd {
 
 struct PruneResult {
@@ -16,6 +18,14 @@ struct PruneResult {
 PruneResult run_prune(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
                       uint8_t *node_keep, int32_t *relabel, int32_t *h_src, int32_t *h_dst,
                       int64_t *edge_map, hipStream_t s);
+
+// The same, every device buffer taken from `ws` (nothing allocated);
+// prune_ws_bytes gives the bytes it takes (h_edges: H's edge list is
+// written; edge_map: the edge map is written).
+PruneResult run_prune_ws(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                         uint8_t *node_keep, int32_t *relabel, int32_t *h_src, int32_t *h_dst,
+                         int64_t *edge_map, Arena &ws, hipStream_t s);
+size_t prune_ws_bytes(int32_t n, int64_t m, bool h_edges, bool edge_map);
 
 // Algorithm 2 on a weighted graph, deciding every removal exactly (see
 // k_prune.hip); h_w receives the kept edges' weights, w_h the kept graph's
