@@ -172,6 +172,9 @@ lowd_status lowd_greedy_peel(int32_t n, int64_t m, const int32_t *src, const int
  *   w             [device] float32[m] or NULL (unit weights); read during
  *                 this call only
  *   state         LOWD_STATE_F64 or LOWD_STATE_F32K
+ *                 (weighted graphs whose weights' binary exponents span more
+ *                 than 40 give LOWD_E_UNSUPPORTED: the extraction's exact
+ *                 integer sums need them closer)
  *   star_max      leaves per star per phase, 1..32 (1 gives a proper edge
  *                 colouring: every phase is a matching); 16 is the default.
  *                 Phases whose stars have more than 16 leaves run as
@@ -218,9 +221,12 @@ lowd_status lowd_check(lowd_solver *s, double *D, double *sum_loads, double *sum
  * ascending (stable on node id), remove them one by one and keep the
  * remaining set of largest density, the first (largest) one on ties; the
  * empty set is never a candidate.  Densities use the graph's own weights
- * (Problem 1): unweighted graphs give an exact rational num_unit / den;
- * weighted graphs give num_w / den with num_w in FP64.  Loads are FP64 (for
- * LOWD_STATE_F32K the FP64 recomputation from the fractions).
+ * (Problem 1) and are compared exactly: unweighted graphs give an exact
+ * rational num_unit / den; for weighted graphs every float32 weight is an
+ * exact integer multiple of the smallest weight's unit in the last place,
+ * so W(S) is an exact integer sum, returned as num_w rounded once to FP64.
+ * Loads are FP64 (for LOWD_STATE_F32K the FP64 recomputation from the
+ * fractions).
  *
  *   in_set    [device] uint8[n] out: 1 if the node is in the extracted set
  *   num_unit  [host] out: |E(S*)| for an unweighted graph, else 0; may be NULL
@@ -310,8 +316,9 @@ lowd_status lowd_solve(lowd_solver *s, double tol, int32_t max_sweeps, int32_t c
  * (f(k) - f(k_{j-1})) / (k - k_{j-1}) (k_0 = 0), until k = n.  Level 0 is
  * the set lowd_extract_densest returns; at the limit of the iteration the
  * levels are the decomposition B_1 < B_2 < ... and lambda_j = (f_end[j] -
- * f_end[j-1]) / (k_end[j] - k_end[j-1]) its level values.  Unit weights are
- * decided exactly; weighted graphs in FP64.  Corollary 1 then bounds the
+ * f_end[j-1]) / (k_end[j] - k_end[j-1]) its level values.  Every level end
+ * is decided exactly (integer weight sums, as for lowd_extract_densest);
+ * f_end is f rounded once to FP64.  Corollary 1 then bounds the
  * density of any k-node subgraph by the envelope of (k_end, f_end) at k,
  * over k.
  *   level    [device] int32[n] out: level of each node (0 = densest)

@@ -32,11 +32,17 @@
  *    never a candidate; the largest prefix of maximal density is kept
  *    (S* starts as V and is replaced only on a strict increase);
  *  - pruning removes, each round, every node whose degree is below the
- *    current density, then recomputes the density (Algorithm 2).
+ *    current density, then recomputes the density (Algorithm 2);
+ *  - densities W(S)/|S| (Problem 1) are compared exactly, also for
+ *    weighted graphs: the float32 weights are exact binary fractions, so
+ *    their sums are taken as exact integers in a common unit.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+typedef unsigned __int128 oracle_u128;
 
 #define ORACLE_OK 0
 #define ORACLE_E_ARG (-1)
@@ -287,18 +293,53 @@ int oracle_stats(int64_t n, const double *L, double *D, double *sumL, double *su
 }
 
 /* ------------------------------------------------------------------------ *
+ * Exact weights.  A positive finite float32 w is M * 2^E for an odd integer
+ * M < 2^24 (frexpf gives w = f * 2^e with f in [0.5, 1); M = f * 2^24 is an
+ * integer, then trailing zero bits move into E).  With q = the smallest E
+ * over the edges, w / 2^q = M * 2^(E - q) is an integer.  Sums of such
+ * integers are exact; W / 2^q values are returned as FP64 once, by
+ * ldexp((double) W, q).  Fails (ORACLE_E_ARG) if an integer would not fit
+ * 64 bits.  *wi is malloc'ed (m entries).
+ * ------------------------------------------------------------------------ */
+static int exact_weights(int64_t m, const float *w, uint64_t **wi_out, int *q_out)
+{
+    int64_t *E = (int64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    uint64_t *M = (uint64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(uint64_t));
+    if (!E || !M) { free(E); free(M); return ORACLE_E_NOMEM; }
+    int q = 0;
+    for (int64_t e = 0; e < m; ++e) {
+        int ex = 0;
+        float f = frexpf(w[e], &ex);
+        uint64_t mm = (uint64_t)ldexpf(f, 24);
+        int64_t ee = (int64_t)ex - 24;
+        while (mm != 0 && (mm & 1) == 0) { mm >>= 1; ++ee; }
+        M[e] = mm;
+        E[e] = ee;
+        if (e == 0 || ee < q) q = (int)ee;
+    }
+    for (int64_t e = 0; e < m; ++e) {
+        int64_t sh = E[e] - q;
+        if (sh > 40) { free(E); free(M); return ORACLE_E_ARG; }
+        M[e] <<= sh;
+    }
+    free(E);
+    *wi_out = M;
+    *q_out = q;
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------ *
  * Algorithm 1, extraction: V_s = nodes sorted by load, non-decreasing
  * (stable: equal loads by ascending id); S_i = V minus its first i nodes;
  * S* = the S_i (0 <= i < n) of largest density, first (largest) on ties.
  *
  * W(S_i) = total weight of edges with both ends in S_i: an edge is inside
  * S_i exactly when min(pos_u, pos_v) >= i, so W is the suffix sum of the
- * weights binned at min(pos_u, pos_v).
- * Unit weights: W is an integer and densities are compared exactly by
- * cross-multiplication.  Weights: W in FP64, densities compared as
- * W[i] / (n - i) in FP64.
+ * weights binned at min(pos_u, pos_v).  W is an exact integer (unit
+ * weights: an edge count; weighted: in units of 2^q, see exact_weights),
+ * and densities are compared exactly by cross-multiplication.
  * Outputs: in_set[n] (1 = in S*), *best_i, *num_unit (W for unit weights),
- * *num_w (W as FP64), *den (|S*|).
+ * *num_w (W as FP64, rounded once), *den (|S*|).
  * ------------------------------------------------------------------------ */
 static const double *g_sort_L;
 static int cmp_load_then_id(const void *pa, const void *pb)
@@ -314,37 +355,34 @@ int oracle_extract(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
                    double *num_w, int64_t *den)
 {
     if (n <= 0) return ORACLE_E_ARG;
+    uint64_t *wi = NULL;
+    int q = 0;
+    if (w) {
+        int rc = exact_weights(m, w, &wi, &q);
+        if (rc != ORACLE_OK) return rc;
+    }
     int32_t *asc = (int32_t *)malloc((size_t)n * sizeof(int32_t));
     int64_t *pos = (int64_t *)malloc((size_t)n * sizeof(int64_t));
-    int64_t *Wi = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
-    double *Wd = (double *)calloc((size_t)n + 1, sizeof(double));
-    if (!asc || !pos || !Wi || !Wd) { free(asc); free(pos); free(Wi); free(Wd); return ORACLE_E_NOMEM; }
+    oracle_u128 *W = (oracle_u128 *)calloc((size_t)n + 1, sizeof(oracle_u128));
+    if (!asc || !pos || !W) { free(asc); free(pos); free(W); free(wi); return ORACLE_E_NOMEM; }
     for (int64_t u = 0; u < n; ++u) asc[u] = (int32_t)u;
     g_sort_L = L;
     qsort(asc, (size_t)n, sizeof(int32_t), cmp_load_then_id);
     for (int64_t i = 0; i < n; ++i) pos[asc[i]] = i;
     for (int64_t e = 0; e < m; ++e) {
         int64_t t = pos[src[e]] < pos[dst[e]] ? pos[src[e]] : pos[dst[e]];
-        if (w) Wd[t] = Wd[t] + (double)w[e];
-        else Wi[t] += 1;
+        W[t] += w ? (oracle_u128)wi[e] : 1;
     }
-    for (int64_t i = n - 1; i >= 0; --i) {
-        Wi[i] += Wi[i + 1];
-        Wd[i] = Wd[i] + Wd[i + 1];
-    }
+    for (int64_t i = n - 1; i >= 0; --i) W[i] += W[i + 1];
     int64_t best = 0;
-    for (int64_t i = 1; i < n; ++i) {
-        int better;
-        if (w) better = (Wd[best] / (double)(n - best)) < (Wd[i] / (double)(n - i));
-        else better = Wi[best] * (n - i) < Wi[i] * (n - best);
-        if (better) best = i;
-    }
+    for (int64_t i = 1; i < n; ++i)
+        if (W[best] * (oracle_u128)(n - i) < W[i] * (oracle_u128)(n - best)) best = i;
     for (int64_t u = 0; u < n; ++u) in_set[u] = pos[u] >= best ? 1 : 0;
     if (best_i_out) *best_i_out = best;
-    if (num_unit) *num_unit = w ? 0 : Wi[best];
-    if (num_w) *num_w = w ? Wd[best] : (double)Wi[best];
+    if (num_unit) *num_unit = w ? 0 : (int64_t)W[best];
+    if (num_w) *num_w = ldexp((double)W[best], q);
     if (den) *den = n - best;
-    free(asc); free(pos); free(Wi); free(Wd);
+    free(asc); free(pos); free(W); free(wi);
     return ORACLE_OK;
 }
 
@@ -360,8 +398,9 @@ int oracle_extract(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
  * until k_j = n.  Level j-1 holds the nodes of rank k_{j-1} .. k_j - 1, and
  * lambda_j is that maximal ratio.  At the limit of the iteration the
  * ranking is consistent with the decomposition and this is the exact LDD.
- * Unit weights compare the ratios exactly by cross-multiplication in
- * integers; weighted graphs compare FP64 quotients.
+ * The ratios are compared exactly by cross-multiplication of integers (edge
+ * counts, or weights in units of 2^q, see exact_weights); f_end holds f
+ * rounded once to FP64.
  *   level  [n]  out: level of each node (0 = densest)
  *   k_end  [n]  out: k_1 .. k_L (L levels)
  *   f_end  [n]  out: f(k_1) .. f(k_L)
@@ -370,11 +409,16 @@ int oracle_ldd(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, con
                const double *L, int32_t *level, int64_t *k_end, double *f_end, int64_t *nlevels)
 {
     if (n <= 0 || !level || !k_end || !f_end || !nlevels) return ORACLE_E_ARG;
+    uint64_t *wi = NULL;
+    int q = 0;
+    if (w) {
+        int rc = exact_weights(m, w, &wi, &q);
+        if (rc != ORACLE_OK) return rc;
+    }
     int32_t *asc = (int32_t *)malloc((size_t)n * sizeof(int32_t));
     int64_t *rank = (int64_t *)malloc((size_t)n * sizeof(int64_t));
-    int64_t *fi = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
-    double *fd = (double *)calloc((size_t)n + 1, sizeof(double));
-    if (!asc || !rank || !fi || !fd) { free(asc); free(rank); free(fi); free(fd); return ORACLE_E_NOMEM; }
+    oracle_u128 *f = (oracle_u128 *)calloc((size_t)n + 1, sizeof(oracle_u128));
+    if (!asc || !rank || !f) { free(asc); free(rank); free(f); free(wi); return ORACLE_E_NOMEM; }
     for (int64_t u = 0; u < n; ++u) asc[u] = (int32_t)u;
     g_sort_L = L;
     qsort(asc, (size_t)n, sizeof(int32_t), cmp_load_then_id);
@@ -382,39 +426,27 @@ int oracle_ldd(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, con
     /* an edge is inside the top k exactly when k > the larger rank of its ends */
     for (int64_t e = 0; e < m; ++e) {
         int64_t r = rank[src[e]] > rank[dst[e]] ? rank[src[e]] : rank[dst[e]];
-        if (w) fd[r + 1] = fd[r + 1] + (double)w[e];
-        else fi[r + 1] += 1;
+        f[r + 1] += w ? (oracle_u128)wi[e] : 1;
     }
-    for (int64_t k = 1; k <= n; ++k) {
-        fi[k] += fi[k - 1];
-        fd[k] = fd[k] + fd[k - 1];
-    }
+    for (int64_t k = 1; k <= n; ++k) f[k] += f[k - 1];
     int64_t L_count = 0, kp = 0;
     while (kp < n) {
         int64_t best = kp + 1;
         for (int64_t k = kp + 2; k <= n; ++k) {
-            int at_least;
-            if (w) {
-                double a = (fd[k] - fd[kp]) / (double)(k - kp);
-                double b = (fd[best] - fd[kp]) / (double)(best - kp);
-                at_least = a >= b;
-            } else {
-                /* (f(k)-f(kp))/(k-kp) >= (f(best)-f(kp))/(best-kp), exactly */
-                __int128 a = (__int128)(fi[k] - fi[kp]) * (best - kp);
-                __int128 b = (__int128)(fi[best] - fi[kp]) * (k - kp);
-                at_least = a >= b;
-            }
-            if (at_least) best = k;
+            /* (f(k)-f(kp))/(k-kp) >= (f(best)-f(kp))/(best-kp), exactly */
+            oracle_u128 a = (f[k] - f[kp]) * (oracle_u128)(best - kp);
+            oracle_u128 b = (f[best] - f[kp]) * (oracle_u128)(k - kp);
+            if (a >= b) best = k;
         }
         k_end[L_count] = best;
-        f_end[L_count] = w ? fd[best] : (double)fi[best];
+        f_end[L_count] = ldexp((double)f[best], q);
         for (int64_t i = 0; i < n; ++i)
             if (rank[i] >= kp && rank[i] < best) level[i] = (int32_t)L_count;
         ++L_count;
         kp = best;
     }
     *nlevels = L_count;
-    free(asc); free(rank); free(fi); free(fd);
+    free(asc); free(rank); free(f); free(wi);
     return ORACLE_OK;
 }
 

@@ -126,6 +126,10 @@ struct lowd_solver {
     // device copies of the graph (for extraction and read-out)
     DBuf<int32_t> e_src, e_dst;
     DBuf<float> e_w;
+    // weighted: each weight over 2^wq as an exact integer (the extraction's
+    // densities are decided exactly)
+    DBuf<uint64_t> e_wi;
+    int32_t wq = 0;
     Csr csr;
     // schedule layout
     DBuf<int32_t> tile_center;
@@ -220,6 +224,9 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
             if (m > 0)
                 LOWD_HIP(
                     hipMemcpyAsync(sv->e_w.p, w, (size_t)m * 4, hipMemcpyDeviceToDevice, s));
+            sv->e_wi.alloc((size_t)m);
+            DBuf<int32_t> range(2);
+            fixed_point_weights(m, sv->e_w.p, sv->e_wi.p, &sv->wq, range.p, s);
         }
         build_incidence(n, m, sv->e_src.p, sv->e_dst.p, sv->csr, s);
         {
@@ -360,7 +367,8 @@ static void check_impl(lowd_solver *sv, bool kept, double *D, double *sum_loads,
 }
 
 static void extract_api(lowd_solver *sv, bool kept, uint8_t *in_set, int64_t *num_unit,
-                        double *num_w, int64_t *den, double *D, double *gap, hipStream_t s) {
+                        double *num_w, int64_t *den, double *D, double *gap, hipStream_t s,
+                        u128 *w_exact = nullptr) {
     if (!sv) fail(LOWD_E_ARG, "solver is NULL");
     if (!in_set) fail(LOWD_E_ARG, "in_set is NULL");
     loads_f64(sv, s, kept);
@@ -374,6 +382,8 @@ static void extract_api(lowd_solver *sv, bool kept, uint8_t *in_set, int64_t *nu
     a.src = sv->e_src.p;
     a.dst = sv->e_dst.p;
     a.w = sv->weighted ? sv->e_w.p : nullptr;
+    a.wi = sv->weighted ? sv->e_wi.p : nullptr;
+    a.wq = sv->wq;
     if (sv->m > 0) {
         a.adj = sv->adj.p;
         a.big = sv->big.p;
@@ -381,14 +391,21 @@ static void extract_api(lowd_solver *sv, bool kept, uint8_t *in_set, int64_t *nu
     }
     a.in_set = in_set;
     launch_extract(a, sv->ex, s);
-    int64_t best[2];
+    int64_t best[3];
     LOWD_HIP(hipMemcpyAsync(best, sv->ex.best.p, sizeof(best), hipMemcpyDeviceToHost, s));
     double o[3];
     stats(sv, o, s);   // synchronises
     int64_t dn = (int64_t)sv->n - best[0];
     double wnum;
-    if (sv->weighted) memcpy(&wnum, &best[1], sizeof(double));
-    else wnum = (double)best[1];
+    if (sv->weighted) {
+        u128 wi;
+        memcpy(&wi, &best[1], sizeof(wi));
+        if (w_exact) *w_exact = wi;
+        wnum = std::ldexp(u128_to_double(wi), sv->wq);   // rounded once
+    } else {
+        wnum = (double)best[1];
+        if (w_exact) *w_exact = (u128)best[1];
+    }
     if (num_unit) *num_unit = sv->weighted ? 0 : best[1];
     if (num_w) *num_w = wnum;
     if (den) *den = dn;
@@ -447,6 +464,7 @@ struct Extracted {
     bool have = false;
     int64_t num_unit = 0;   // |E(S)| (unit weights)
     double num_w = 0.0;     // W(S) in FP64
+    u128 w_exact = 0;       // W(S) exactly (weighted: in units of 2^wq)
     int64_t den = 0;        // |S|
 };
 
@@ -458,11 +476,10 @@ double density_of(const Extracted &x) {
     return x.den > 0 ? x.num_w / (double)x.den : 0.0;
 }
 
-// a at least as dense as b: exactly by cross-multiplication for unit
-// weights (|E| < 2^31 and |S| < 2^31, so the products fit in 63 bits)
-bool at_least_as_dense(const Extracted &a, const Extracted &b, bool weighted) {
-    if (weighted) return density_of(a) >= density_of(b);
-    return (__int128)a.num_unit * b.den >= (__int128)b.num_unit * a.den;
+// a at least as dense as b, exactly by cross-multiplication (W < 2^95 in
+// units of 2^wq, |S| < 2^31: the products stay below 2^126)
+bool at_least_as_dense(const Extracted &a, const Extracted &b) {
+    return a.w_exact * (u128)b.den >= b.w_exact * (u128)a.den;
 }
 
 // Sweeps before the next check from the last two (sweeps, gap) records: the
@@ -524,8 +541,9 @@ static double certify(lowd_solver *sv, Extracted &best, uint8_t *best_in_set, do
     Extracted ex;
     ex.have = true;
     double D = 0.0;
-    extract_api(sv, true, sv->solve_in_set.p, &ex.num_unit, &ex.num_w, &ex.den, &D, nullptr, s);
-    if (!best.have || at_least_as_dense(ex, best, sv->weighted)) {
+    extract_api(sv, true, sv->solve_in_set.p, &ex.num_unit, &ex.num_w, &ex.den, &D, nullptr, s,
+                &ex.w_exact);
+    if (!best.have || at_least_as_dense(ex, best)) {
         best = ex;
         LOWD_HIP(hipMemcpyAsync(best_in_set, sv->solve_in_set.p, (size_t)sv->n,
                                 hipMemcpyDeviceToDevice, s));
@@ -651,6 +669,8 @@ lowd_status lowd_ldd_readout(lowd_solver *sv, int32_t *level, int64_t *k_end, do
         a.src = sv->e_src.p;
         a.dst = sv->e_dst.p;
         a.w = sv->weighted ? sv->e_w.p : nullptr;
+        a.wi = sv->weighted ? sv->e_wi.p : nullptr;
+        a.wq = sv->wq;
         if (sv->m > 0) {
             a.adj = sv->adj.p;
             a.big = sv->big.p;

@@ -18,6 +18,8 @@ struct ExtractArgs {
     const int32_t *src = nullptr;     // [m] edge list
     const int32_t *dst = nullptr;
     const float *w = nullptr;         // [m] or nullptr
+    const uint64_t *wi = nullptr;     // [m] weighted: w / 2^wq as exact integers
+    int32_t wq = 0;
     // optional: the other end of each incidence entry and the nodes of
     // degree >= kBigRow (counted a workgroup each)
     const int32_t *adj = nullptr;     // [2m]
@@ -40,7 +42,8 @@ struct ExtractScratch {
 
 // Enqueues the extraction; after the stream completes, best.p[0] holds the
 // number of removed nodes i* and best.p[1] holds W(S_{i*}) (int64 for
-// unweighted graphs, FP64 bits otherwise).
+// unweighted graphs; weighted: best.p[1..2] hold W(S_{i*}) / 2^wq as an
+// exact 128-bit integer).
 void launch_extract(const ExtractArgs &a, ExtractScratch &sc, hipStream_t s);
 
 // Locally-dense decomposition read from the loads: the extraction, then the

@@ -99,12 +99,24 @@ __global__ void __launch_bounds__(kBigBlock) k_towards_higher_big(const int32_t 
 }
 
 // Weighted: the weight from node u towards nodes at higher positions, stored
-// at pos[u].  Groups of 8 lanes per node of degree below kBigRow (the others:
-// k_towards_higher_w_big), each a fixed-order FP64 reduction (deterministic).
+// at pos[u], summed exactly: each weight is the integer wi[e] (the weight
+// over 2^q, see fixed_point_weights), so the sums are exact 128-bit integers
+// in any order.  Groups of 8 lanes per node of degree below kBigRow (the
+// others: k_towards_higher_w_big).
+__device__ __forceinline__ u128 shfl_down_u128(u128 v, int d, int width) {
+    struct Words {
+        int w[4];
+    };
+    Words x = __builtin_bit_cast(Words, v);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x.w[k] = __shfl_down(x.w[k], d, width);
+    return __builtin_bit_cast(u128, x);
+}
+
 __global__ void __launch_bounds__(256) k_towards_higher_w(int32_t n, const int64_t *row_ptr,
                                                           const uint32_t *inc, const int32_t *adj,
-                                                          const float *w, const int32_t *pos,
-                                                          double *hist) {
+                                                          const uint64_t *wi, const int32_t *pos,
+                                                          u128 *hist) {
     const int sub = threadIdx.x & (kRowLanes - 1);
     const int64_t groups = (int64_t)gridDim.x * (blockDim.x / kRowLanes);
     for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / kRowLanes) + threadIdx.x / kRowLanes;
@@ -112,10 +124,10 @@ __global__ void __launch_bounds__(256) k_towards_higher_w(int32_t n, const int64
         const int64_t b = row_ptr[u], e = row_ptr[u + 1];
         if (e - b >= kBigRow) continue;
         const int32_t pu = pos[u];
-        double acc = 0.0;
+        u128 acc = 0;
         for (int64_t j = b + sub; j < e; j += kRowLanes)
-            if (pos[adj[j]] > pu) acc = acc + (double)w[inc[j] >> 1];
-        for (int d = kRowLanes / 2; d > 0; d >>= 1) acc = acc + __shfl_down(acc, d, kRowLanes);
+            if (pos[adj[j]] > pu) acc += (u128)wi[inc[j] >> 1];
+        for (int d = kRowLanes / 2; d > 0; d >>= 1) acc += shfl_down_u128(acc, d, kRowLanes);
         if (sub == 0) hist[pu] = acc;
     }
 }
@@ -123,19 +135,19 @@ __global__ void __launch_bounds__(256) k_towards_higher_w(int32_t n, const int64
 // the same for one node of degree >= kBigRow per workgroup
 __global__ void __launch_bounds__(kBigBlock) k_towards_higher_w_big(
     const int32_t *big, const int64_t *row_ptr, const uint32_t *inc, const int32_t *adj,
-    const float *w, const int32_t *pos, double *hist) {
-    __shared__ double part[kBigBlock / kWave];
+    const uint64_t *wi, const int32_t *pos, u128 *hist) {
+    __shared__ u128 part[kBigBlock / kWave];
     const int32_t u = big[blockIdx.x];
     const int32_t pu = pos[u];
-    double acc = 0.0;
+    u128 acc = 0;
     for (int64_t j = row_ptr[u] + threadIdx.x; j < row_ptr[u + 1]; j += kBigBlock)
-        if (pos[adj[j]] > pu) acc = acc + (double)w[inc[j] >> 1];
-    for (int d = kWave / 2; d > 0; d >>= 1) acc = acc + __shfl_down(acc, d, kWave);
+        if (pos[adj[j]] > pu) acc += (u128)wi[inc[j] >> 1];
+    for (int d = kWave / 2; d > 0; d >>= 1) acc += shfl_down_u128(acc, d, kWave);
     if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int k = 0; k < kBigBlock / kWave; ++k) t = t + part[k];
+        u128 t = 0;
+        for (int k = 0; k < kBigBlock / kWave; ++k) t += part[k];
         hist[pu] = t;
     }
 }
@@ -164,10 +176,12 @@ __device__ inline bool better(int64_t i, int64_t j, const int64_t *W, int64_t n)
     int64_t a = W[i] * (n - j), b = W[j] * (n - i);
     return a > b || (a == b && i < j);
 }
-__device__ inline bool better(int64_t i, int64_t j, const double *W, int64_t n) {
+// weighted, exact: W < 2^95 (integer weights below 2^64, fewer than 2^31
+// edges) and n < 2^31, so the cross products stay below 2^126
+__device__ inline bool better(int64_t i, int64_t j, const u128 *W, int64_t n) {
     if (j < 0) return i >= 0;
     if (i < 0) return false;
-    double a = W[i] / (double)(n - i), b = W[j] / (double)(n - j);
+    const u128 a = W[i] * (u128)(n - j), b = W[j] * (u128)(n - i);
     return a > b || (a == b && i < j);
 }
 
@@ -233,17 +247,17 @@ void extract_impl(const ExtractArgs &a, ExtractScratch &sc, hipStream_t s) {
     T *rev = (T *)sc.rev.p;
     T *W = (T *)sc.W.p;
     if constexpr (kWeighted) {
-        if (a.m == 0) {   // no edges: every bin is zero (+0.0)
-            hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n, 256)), dim3(256), 0, s, (int64_t)n,
-                               (int64_t *)hist);
+        if (a.m == 0) {   // no edges: every bin is zero
+            hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(2 * (int64_t)n, 256)), dim3(256), 0, s,
+                               2 * (int64_t)n, (int64_t *)hist);
         } else {
-            if (!a.adj) fail(LOWD_E_ARG, "weighted extraction needs the adjacency");
+            if (!a.adj || !a.wi) fail(LOWD_E_ARG, "weighted extraction needs the adjacency");
             hipLaunchKernelGGL(k_towards_higher_w, dim3(grid_for((int64_t)n * kRowLanes, 256)),
-                               dim3(256), 0, s, n, a.row_ptr, a.inc, a.adj, a.w, sc.pos.p, hist);
+                               dim3(256), 0, s, n, a.row_ptr, a.inc, a.adj, a.wi, sc.pos.p, hist);
         }
         if (a.m > 0 && a.nbig > 0)
             hipLaunchKernelGGL(k_towards_higher_w_big, dim3((unsigned)a.nbig), dim3(kBigBlock), 0,
-                               s, a.big, a.row_ptr, a.inc, a.adj, a.w, sc.pos.p, hist);
+                               s, a.big, a.row_ptr, a.inc, a.adj, a.wi, sc.pos.p, hist);
     } else if (a.adj) {
         hipLaunchKernelGGL(k_towards_higher_small, dim3(grid_for((int64_t)n * kRowLanes, 256)),
                            dim3(256), 0, s, n, a.row_ptr, a.adj, sc.pos.p,
@@ -260,7 +274,7 @@ void extract_impl(const ExtractArgs &a, ExtractScratch &sc, hipStream_t s) {
     hipLaunchKernelGGL(k_reverse<T>, dim3(grid_for(n, 256)), dim3(256), 0, s, (int64_t)n, hist,
                        rev);
     if constexpr (kWeighted)
-        exclusive_scan_f64(rev, rev, n, nullptr, sc.tmp.p, sc.tmp.bytes(), s);
+        exclusive_scan_u128(rev, rev, n, nullptr, sc.tmp.p, sc.tmp.bytes(), s);
     else
         exclusive_scan_i64(rev, rev, n, nullptr, sc.tmp.p, sc.tmp.bytes(), s);
     hipLaunchKernelGGL(k_suffix<T>, dim3(grid_for(n, 256)), dim3(256), 0, s, (int64_t)n, rev, hist,
@@ -285,11 +299,11 @@ void ExtractScratch::ensure(int64_t n) {
     vals.alloc((size_t)c);
     vals_alt.alloc((size_t)c);
     pos.alloc((size_t)c);
-    hist.alloc((size_t)c);
-    rev.alloc((size_t)c);
-    W.alloc((size_t)c);
+    hist.alloc(2 * (size_t)c);   // room for 128-bit weighted sums
+    rev.alloc(2 * (size_t)c);
+    W.alloc(2 * (size_t)c);
     part.alloc(1024);
-    best.alloc(2);
+    best.alloc(3);
     size_t t = radix_sort_tmp_bytes(c);
     size_t t2 = exclusive_scan_tmp_bytes(c);
     tmp.alloc(t > t2 ? t : t2);
@@ -298,7 +312,7 @@ void ExtractScratch::ensure(int64_t n) {
 
 void launch_extract(const ExtractArgs &a, ExtractScratch &sc, hipStream_t s) {
     sc.ensure(a.n);
-    if (a.weighted) extract_impl<double, true>(a, sc, s);
+    if (a.weighted) extract_impl<u128, true>(a, sc, s);
     else extract_impl<int64_t, false>(a, sc, s);
 }
 
@@ -333,10 +347,19 @@ __device__ __forceinline__ bool not_above(int64_t ok, int64_t of, int64_t ak, in
     const __int128 r = (__int128)(af - of) * (__int128)(bk - ok);
     return l >= r;
 }
-__device__ __forceinline__ bool not_above(int64_t ok, double of, int64_t ak, double af,
-                                          int64_t bk, double bf) {
-    return (double)(ak - ok) * (bf - of) >= (af - of) * (double)(bk - ok);
+// weighted, exact: f is non-decreasing in k, so the differences are
+// non-negative; f < 2^95 and k < 2^31 keep the products below 2^126
+__device__ __forceinline__ bool not_above(int64_t ok, u128 of, int64_t ak, u128 af, int64_t bk,
+                                          u128 bf) {
+    const u128 l = (u128)(ak - ok) * (bf - of);
+    const u128 r = (af - of) * (u128)(bk - ok);
+    return l >= r;
 }
+
+// f(k) as FP64: exact integers for unit weights; the weighted integer sum
+// (in units of 2^q) rounded once and scaled
+__device__ __forceinline__ double f_value(int64_t v, int32_t) { return (double)v; }
+__device__ __forceinline__ double f_value(u128 v, int32_t q) { return ldexp(u128_to_double(v), q); }
 
 template <class T>
 __global__ void k_hull_chunks(int64_t n, const T *W, int64_t *ck, T *cf, int64_t *cnt) {
@@ -393,7 +416,8 @@ __global__ void k_hull_chain(int64_t q, const int64_t *qk, const T *qf, int64_t 
 // descending rank; and the ends as output arrays
 template <class T>
 __global__ void k_hull_levels(int32_t n, const int32_t *pos, const int64_t *hk, const T *hf,
-                              const int64_t *nv, int32_t *level, int64_t *k_end, double *f_end) {
+                              const int64_t *nv, int32_t q, int32_t *level, int64_t *k_end,
+                              double *f_end) {
     const int64_t L = *nv - 1;
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
          u += (int64_t)gridDim.x * blockDim.x) {
@@ -407,13 +431,13 @@ __global__ void k_hull_levels(int32_t n, const int32_t *pos, const int64_t *hk, 
         level[u] = (int32_t)(a - 1);
         if (u < L) {
             k_end[u] = hk[u + 1];
-            f_end[u] = (double)hf[u + 1];
+            f_end[u] = f_value(hf[u + 1], q);
         }
     }
 }
 
 template <class T>
-void ldd_impl(int32_t n, const ExtractScratch &sc, LddScratch &ls, int32_t *level,
+void ldd_impl(int32_t n, int32_t q, const ExtractScratch &sc, LddScratch &ls, int32_t *level,
               int64_t *k_end, double *f_end, hipStream_t s) {
     const T *W = (const T *)sc.W.p;
     const int64_t pts = (int64_t)n + 1;
@@ -432,7 +456,7 @@ void ldd_impl(int32_t n, const ExtractScratch &sc, LddScratch &ls, int32_t *leve
     hipLaunchKernelGGL(k_hull_chain<T>, dim3(1), dim3(64), 0, s, ls.host_q, qk, qf, hk, hf,
                        ls.nv.p);
     hipLaunchKernelGGL(k_hull_levels<T>, dim3(grid_for(n, 256)), dim3(256), 0, s, n, sc.pos.p, hk,
-                       hf, ls.nv.p, level, k_end, f_end);
+                       hf, ls.nv.p, q, level, k_end, f_end);
     LOWD_HIP(hipGetLastError());
 }
 
@@ -441,11 +465,11 @@ void ldd_impl(int32_t n, const ExtractScratch &sc, LddScratch &ls, int32_t *leve
 void LddScratch::ensure(int64_t points, int64_t chunks) {
     if (points <= cap_points && chunks <= cap_chunks) return;
     ck.alloc((size_t)points);
-    cf.alloc((size_t)points);
+    cf.alloc(2 * (size_t)points);   // room for 128-bit weighted values
     qk.alloc((size_t)points);
-    qf.alloc((size_t)points);
+    qf.alloc(2 * (size_t)points);
     hk.alloc((size_t)points);
-    hf.alloc((size_t)points);
+    hf.alloc(2 * (size_t)points);
     cnt.alloc((size_t)chunks + 1);
     off.alloc((size_t)chunks);
     nv.alloc(1);
@@ -457,8 +481,8 @@ void LddScratch::ensure(int64_t points, int64_t chunks) {
 void launch_ldd(const ExtractArgs &a, ExtractScratch &sc, LddScratch &ls, int32_t *level,
                 int64_t *k_end, double *f_end, int64_t *nlevels, hipStream_t s) {
     launch_extract(a, sc, s);   // order, positions and W(S_i)
-    if (a.weighted) ldd_impl<double>(a.n, sc, ls, level, k_end, f_end, s);
-    else ldd_impl<int64_t>(a.n, sc, ls, level, k_end, f_end, s);
+    if (a.weighted) ldd_impl<u128>(a.n, a.wq, sc, ls, level, k_end, f_end, s);
+    else ldd_impl<int64_t>(a.n, 0, sc, ls, level, k_end, f_end, s);
     int64_t nv = 0;
     LOWD_HIP(hipMemcpyAsync(&nv, ls.nv.p, sizeof(nv), hipMemcpyDeviceToHost, s));
     LOWD_HIP(hipStreamSynchronize(s));

@@ -202,8 +202,6 @@ __global__ void k_edge_compact(int64_t m, const int32_t *src, const int32_t *dst
 // integer, below 2^64 when the exponents span at most 40 binades.  Degrees
 // and 2 w(E(H)) = sum of degrees are then exact 128-bit sums in any order,
 // and 2 deg(u) |V(H)| < 2 w(E(H)) an exact 128-bit comparison.
-typedef unsigned __int128 u128;
-constexpr int32_t kMaxExpSpan = 40;
 
 __device__ __forceinline__ int32_t ulp_exponent(float x) {
     const uint32_t b = __builtin_bit_cast(uint32_t, x);
@@ -325,6 +323,25 @@ __global__ void k_weighted_test(int64_t k, const uint64_t *dlo, const uint64_t *
 }
 
 }  // namespace
+
+void fixed_point_weights(int64_t m, const float *w, uint64_t *wi, int32_t *q_out,
+                         int32_t *range_dev, hipStream_t s) {
+    *q_out = 0;
+    if (m <= 0) return;
+    const int32_t init[2] = {1 << 30, -(1 << 30)};
+    LOWD_HIP(hipMemcpyAsync(range_dev, init, sizeof(init), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_exponent_range, dim3(grid_for(m, 256, 1024)), dim3(256), 0, s, m, w,
+                       range_dev);
+    int32_t r[2];
+    LOWD_HIP(hipMemcpyAsync(r, range_dev, sizeof(r), hipMemcpyDeviceToHost, s));
+    LOWD_HIP(hipStreamSynchronize(s));
+    if (r[1] - r[0] > kMaxExpSpan)
+        fail(LOWD_E_UNSUPPORTED, "weights span more than 2^40 in scale; exact weighted sums need "
+                                 "them closer");
+    *q_out = r[0];
+    hipLaunchKernelGGL(k_fixed_weights, dim3(grid_for(m, 256)), dim3(256), 0, s, m, w, r[0], wi);
+    LOWD_HIP(hipGetLastError());
+}
 
 // Every device buffer of the prune comes from `ws`, taken in a fixed order,
 // so a region without a base measures what a call needs (prune_ws_bytes).
@@ -496,21 +513,7 @@ PruneResult run_prune_weighted(int32_t n, int64_t m, const int32_t *src, const i
     DBuf<char> scan_tmp(exclusive_scan_tmp_bytes(big));
     LOWD_HIP(hipMemsetAsync(stamp.p, 0, (size_t)n * sizeof(int32_t), s));
     int32_t qmin = 0;
-    if (m > 0) {
-        const int32_t init[2] = {1 << 30, -(1 << 30)};
-        LOWD_HIP(hipMemcpyAsync(range.p, init, sizeof(init), hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_exponent_range, dim3(grid_for(m, 256, 1024)), dim3(256), 0, s, m, w,
-                           range.p);
-        int32_t r[2];
-        LOWD_HIP(hipMemcpyAsync(r, range.p, sizeof(r), hipMemcpyDeviceToHost, s));
-        LOWD_HIP(hipStreamSynchronize(s));
-        if (r[1] - r[0] > kMaxExpSpan)
-            fail(LOWD_E_UNSUPPORTED, "weights span more than 2^40 in scale; exact weighted pruning needs them "
-                     "closer");
-        qmin = r[0];
-        hipLaunchKernelGGL(k_fixed_weights, dim3(grid_for(m, 256)), dim3(256), 0, s, m, w, qmin,
-                           wi.p);
-    }
+    fixed_point_weights(m, w, wi.p, &qmin, range.p, s);
     hipLaunchKernelGGL(k_iota, dim3(gn), dim3(256), 0, s, n, list_a.p);
     int32_t *alive = list_a.p;
     int64_t nalive = n;

@@ -19,14 +19,17 @@ constexpr int kScanBlock = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanBlock * kScanItems;
 
+// shuffle of an 8- or 16-byte value, 32 bits at a time
 template <class T>
 __device__ inline T shfl_up_64(T v, int d) {
-    uint64_t u = __builtin_bit_cast(uint64_t, v);
-    int lo = (int)(uint32_t)u;
-    int hi = (int)(uint32_t)(u >> 32);
-    lo = __shfl_up(lo, d, kWave);
-    hi = __shfl_up(hi, d, kWave);
-    return __builtin_bit_cast(T, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+    static_assert(sizeof(T) == 8 || sizeof(T) == 16, "8- or 16-byte values");
+    struct Words {
+        int w[sizeof(T) / 4];
+    };
+    Words x = __builtin_bit_cast(Words, v);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) x.w[k] = __shfl_up(x.w[k], d, kWave);
+    return __builtin_bit_cast(T, x);
 }
 
 // inclusive scan over the 64 lanes of a wavefront
@@ -349,9 +352,10 @@ void radix_sort_impl(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, i
 
 }  // namespace
 
+// scratch of a scan of up to n values of up to 16 bytes
 size_t exclusive_scan_tmp_bytes(int64_t n) {
     int64_t nb = cdiv(n > 0 ? n : 1, kScanTile);
-    return (size_t)(nb + 1) * sizeof(int64_t);
+    return (size_t)(nb + 1) * 16;
 }
 
 namespace {
@@ -380,6 +384,11 @@ void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tot
 void exclusive_scan_f64(const double *in, double *out, int64_t n, double *total_dev, void *tmp,
                         size_t tmp_bytes, hipStream_t s) {
     exclusive_scan_impl<double>(in, out, n, total_dev, tmp, tmp_bytes, s);
+}
+
+void exclusive_scan_u128(const u128 *in, u128 *out, int64_t n, u128 *total_dev, void *tmp,
+                         size_t tmp_bytes, hipStream_t s) {
+    exclusive_scan_impl<u128>(in, out, n, total_dev, tmp, tmp_bytes, s);
 }
 
 size_t radix_sort_tmp_bytes(int64_t n) {

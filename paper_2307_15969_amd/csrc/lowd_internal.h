@@ -183,12 +183,44 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
                     Schedule &out, bool whole_in_lds = false);
 
 // --------------------------------------------------------------- kernels --
+typedef unsigned __int128 u128;
+
 // Device-wide primitives (k_scan.hip)
 void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total_dev,
                         void *tmp, size_t tmp_bytes, hipStream_t s);
 void exclusive_scan_f64(const double *in, double *out, int64_t n, double *total_dev, void *tmp,
                         size_t tmp_bytes, hipStream_t s);
+void exclusive_scan_u128(const u128 *in, u128 *out, int64_t n, u128 *total_dev, void *tmp,
+                         size_t tmp_bytes, hipStream_t s);
 size_t exclusive_scan_tmp_bytes(int64_t n);
+
+// Weights as exact integers (k_prune.hip): every float32 weight is M * 2^E
+// with an integer M < 2^24 (E its ulp exponent); with q the smallest E over
+// the edges, wi[e] = w[e] / 2^q is an integer, below 2^64 when the
+// exponents span at most 40 binades (else LOWD_E_UNSUPPORTED).  range_dev:
+// 2 ints of device scratch.  Synchronises the stream.
+constexpr int32_t kMaxExpSpan = 40;
+void fixed_point_weights(int64_t m, const float *w, uint64_t *wi, int32_t *q_out,
+                         int32_t *range_dev, hipStream_t s);
+// x rounded once to FP64 (round to nearest even), on either side
+__host__ __device__ inline double u128_to_double(u128 x) {
+    const uint64_t hi = (uint64_t)(x >> 64);
+    if (hi == 0) return (double)(uint64_t)x;
+    // keep the top 64 bits and fold every lower bit into a sticky bit, so the
+    // one rounding of the 64-bit value is the rounding of x
+    int shift = 64;
+    uint64_t h = hi;
+    while (h) {
+        h >>= 1;
+        --shift;
+    }
+    shift = 64 - shift;   // bits of hi
+    const uint64_t top = (uint64_t)(x >> shift);
+    const bool sticky = (x & ((((u128)1) << shift) - 1)) != 0;
+    double r = (double)(top | (sticky ? 1u : 0u));
+    for (int k = 0; k < shift; ++k) r *= 2.0;
+    return r;
+}
 // Stable LSD radix sort of (key, value) pairs on bits [0, bits) of the key.
 void radix_sort_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
                     int64_t n, int bits, void *tmp, size_t tmp_bytes, bool *result_in_alt,

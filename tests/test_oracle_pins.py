@@ -152,6 +152,46 @@ def test_extracted_set_is_maximal_densest_by_brute_force(weighted):
         assert num / r["den"] == rho
 
 
+def test_weighted_peel_densities_match_exact_evaluation():
+    """Weighted graphs (float32 lognormal weights, no dyadic niceness): the
+    oracle's choice of prefix is the first maximum of the exact rational
+    densities (Problem 1), and its W is that exact rational rounded once."""
+    rng = np.random.default_rng(17)
+    for _ in range(20):
+        n = int(rng.integers(3, 12))
+        g = synth.random_small(rng, n, float(rng.uniform(0.3, 0.8)), False)
+        if g.m == 0:
+            continue
+        w = rng.lognormal(0.0, 1.0, size=g.m).astype(np.float32)
+        L = rng.integers(0, 3, size=g.n).astype(np.float64)       # many ties
+        r = oracle.extract(g.n, g.src, g.dst, w, L)
+        order = sorted(range(g.n), key=lambda u: (L[u], u))
+        dens = peel_densities(g.n, g.src, g.dst, w, order)
+        best = max(range(g.n), key=lambda i: (dens[i], -i))
+        assert r["best_i"] == best
+        assert r["num_w"] == float(dens[best] * (g.n - best))
+        assert r["den"] == g.n - best
+
+
+def test_weighted_exact_tie_keeps_the_larger_set():
+    """Two disjoint triangles carry the same three float32 weights in
+    different edge orders, so each has density 2 exactly and so does their
+    union; among equally dense prefixes the largest is kept (S* is replaced
+    only on a strict increase, O9), with the weights compared exactly."""
+    src = np.array([0, 0, 1, 3, 3, 4, 6], dtype=np.int32)
+    dst = np.array([1, 2, 2, 4, 5, 5, 7], dtype=np.int32)
+    w = np.array([1.5, 2.0, 2.5, 2.5, 1.5, 2.0, 0.01], dtype=np.float32)
+    n = 8
+    L = np.array([1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 0.0, 0.0])   # nodes 6, 7 go first
+    r = oracle.extract(n, src, dst, w, L)
+    assert list(np.flatnonzero(r["in_set"])) == [0, 1, 2, 3, 4, 5]
+    assert r["num_w"] == 12.0 and r["den"] == 6
+    # the prefix {3, 4, 5} ties with it and is not taken
+    order = sorted(range(n), key=lambda u: (L[u], u))
+    dens = peel_densities(n, src, dst, w, order)
+    assert dens[2] == dens[5] == 2
+
+
 def test_peel_densities_match_direct_evaluation():
     """The suffix-sum computation of rho(S_i) equals evaluating every S_i
     directly, for arbitrary (not converged) loads, including ties."""
