@@ -165,7 +165,11 @@ lowd_status lowd_greedy_peel(int32_t n, int64_t m, const int32_t *src, const int
  * global memory, and the last, narrowest ones inside one workgroup with
  * their nodes' loads in LDS.  A cost model places the two splits;
  * LOWD_MID_SPLIT and LOWD_TAIL_SPLIT in the environment (read by this call)
- * override them.
+ * override them.  Between phases a node's load waits where the sweep reads
+ * it next (its next leaf slot or star).  LOWD_LAYOUT=node in the
+ * environment keeps the loads in one node-indexed array instead, gathered
+ * and scattered by id, every phase a launch of its own (measured slower on
+ * every graph tried; the results are the same bits).
  *
  *   n, m          nodes and edges (n >= 1, m >= 0, m < 2^31)
  *   src, dst      [device] int32[m]; read during this call only
@@ -398,11 +402,12 @@ lowd_status lowd_schedule_build(int32_t n, int64_t m, const int32_t *src, const 
 
 /*
  * lowd_solver_info -- sizes of the solver, for reports.
- *   info [host] int64[10] out: n, m, phases, phases run by whole-GPU
+ *   info [host] int64[11] out: n, m, phases, phases run by whole-GPU
  *        launches, phases run inside one workgroup with loads in global
  *        memory, phases run inside one workgroup with loads in LDS, nodes
  *        held in LDS, edges of the LDS phases, edges of the global-memory
- *        single-workgroup phases, state type.
+ *        single-workgroup phases, state type, load layout (0: stations, 1:
+ *        a node-indexed array).
  */
 lowd_status lowd_solver_info(const lowd_solver *s, int64_t *info);
 

@@ -112,6 +112,23 @@ static void validate_graph(int32_t n, int64_t m, const int32_t *src, const int32
     validate_graph_ws(n, m, src, dst, w, ws, s);
 }
 
+// Where a node's load waits between phases: at its next station (the
+// default), or in one node-indexed array (LOWD_LAYOUT=node).  The array is
+// small enough for the on-die caches, but a tile then reads its leaf ids
+// before it can gather their loads (two dependent round trips instead of
+// one), and the gathers are random: on uniform random graphs with wide
+// phases (2^22 nodes and 2^28 edges; 2^19 and 2^27, whose array fits each
+// L2) a sweep took 1.5 times as long as with stations, so stations are the
+// default everywhere.
+static bool choose_node_layout() {
+    if (const char *e = getenv("LOWD_LAYOUT")) {
+        if (!strcmp(e, "node")) return true;
+        if (!strcmp(e, "station")) return false;
+        fail(LOWD_E_ARG, "LOWD_LAYOUT must be node or station");
+    }
+    return false;
+}
+
 }  // namespace lowd
 
 using namespace lowd;
@@ -152,6 +169,8 @@ struct lowd_solver {
     hipGraphExec_t exec = nullptr;
     int32_t ntail = 0;
     int64_t nslots = 0;
+    // loads in a node-indexed array (wide phases) instead of at stations
+    bool node_layout = false;
     ~lowd_solver() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -163,9 +182,10 @@ static void reset_state(lowd_solver *sv, hipStream_t s) {
     if (nslots > 0)
         sv->fn.init_slots(nslots, sv->slot_edge.p, sv->weighted ? sv->e_w.p : nullptr,
                           sv->slot_x.p, sv->weighted ? sv->slot_w.p : nullptr, s);
+    if (sv->node_layout) sv->fn.fill_nodes(sv->n, sv->E.p, s);
     sv->fn.init_loads(sv->n, sv->csr.row_ptr.p, sv->csr.inc.p, sv->weighted ? sv->e_w.p : nullptr,
-                      sv->home.p, sv->big.p, sv->nbig, sv->sch.entries, sv->sch.center_base,
-                      sv->E.p, s);
+                      sv->home.p, sv->big.p, sv->nbig, sv->node_layout ? 0 : sv->sch.entries,
+                      sv->sch.center_base, sv->E.p, s);
     LOWD_HIP(hipGetLastError());
 }
 
@@ -204,10 +224,13 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
             LOWD_HIP(hipMemcpyAsync(hd.data(), dst, (size_t)m * 4, hipMemcpyDeviceToHost, s));
             LOWD_HIP(hipStreamSynchronize(s));
         }
-        const int64_t lds = (int64_t)lds_capacity_bytes();
+        sv->node_layout = choose_node_layout();
+        const int64_t lds = sv->node_layout ? 0 : (int64_t)lds_capacity_bytes();
         int64_t force0 = -1, force1 = -1;
-        if (const char *e = getenv("LOWD_TAIL_SPLIT")) force0 = atoll(e);
-        if (const char *e = getenv("LOWD_MID_SPLIT")) force1 = atoll(e);
+        if (!sv->node_layout) {
+            if (const char *e = getenv("LOWD_TAIL_SPLIT")) force0 = atoll(e);
+            if (const char *e = getenv("LOWD_MID_SPLIT")) force1 = atoll(e);
+        }
         build_schedule(n, m, hs.data(), hd.data(), star_max, lds, (int64_t)sv->fn.l_bytes, force0,
                        force1, sv->sch);
         const Schedule &sc = sv->sch;
@@ -255,10 +278,17 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
         for (int32_t p = sc.P1; p < sc.P0; ++p) mdesc.push_back(narrow_desc<kTierStar>(sc.desc[(size_t)p]));
         upload(sv->tail_desc, tdesc, s);
         upload(sv->mid_desc, mdesc, s);
-        upload(sv->slot_next, sc.slot_next, s);
-        upload(sv->center_next, sc.center_next, s);
-        upload(sv->tail_next, sc.tail_next, s);
-        upload(sv->home, sc.home, s);
+        if (sv->node_layout) {
+            // a node's load lives at its own index
+            std::vector<uint32_t> home((size_t)n);
+            for (int32_t u = 0; u < n; ++u) home[(size_t)u] = (uint32_t)u;
+            upload(sv->home, home, s);
+        } else {
+            upload(sv->slot_next, sc.slot_next, s);
+            upload(sv->center_next, sc.center_next, s);
+            upload(sv->tail_next, sc.tail_next, s);
+            upload(sv->home, sc.home, s);
+        }
         sv->ntail = (int32_t)sc.tail_nodes.size();
 
         // state
@@ -266,7 +296,7 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
         sv->nslots = nslots;
         sv->slot_x.alloc((size_t)nslots * sv->fn.x_bytes);
         if (sv->weighted) sv->slot_w.alloc((size_t)nslots);
-        sv->E.alloc((size_t)sc.entries * sv->fn.l_bytes);
+        sv->E.alloc((size_t)(sv->node_layout ? (int64_t)n + 2 : sc.entries) * sv->fn.l_bytes);
         sv->L64.alloc((size_t)n);
         sv->stats_partial.alloc(3 * 1024);
         sv->stats_out.alloc(3);
@@ -284,9 +314,14 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
             hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             if (err == hipSuccess) {
                 const float *sw = sv->weighted ? sv->slot_w.p : nullptr;
-                for (int32_t p = 0; p < sc.P1; ++p)
-                    sv->fn.phase(sc.desc[(size_t)p], sc.center_base, sv->center_next.p,
-                                 sv->slot_next.p, sv->slot_x.p, sw, sv->E.p, cs);
+                for (int32_t p = 0; p < sc.P1; ++p) {
+                    if (sv->node_layout)
+                        sv->fn.phase_node(sc.desc[(size_t)p], sv->tile_center.p, sv->slot_leaf.p,
+                                          sv->slot_x.p, sw, sv->E.p, cs);
+                    else
+                        sv->fn.phase(sc.desc[(size_t)p], sc.center_base, sv->center_next.p,
+                                     sv->slot_next.p, sv->slot_x.p, sw, sv->E.p, cs);
+                }
                 if (sc.P1 < sc.P0)
                     sv->fn.mid(sc.P0 - sc.P1, sv->mid_desc.p, sc.center_base, sv->center_next.p,
                                sv->slot_next.p, sv->slot_x.p, sw, sv->E.p, cs);
@@ -735,6 +770,7 @@ lowd_status lowd_solver_info(const lowd_solver *sv, int64_t *info) {
         info[7] = sv->sch.tail_edges;
         info[8] = mid_edges;
         info[9] = sv->state;
+        info[10] = sv->node_layout ? 1 : 0;
     });
 }
 

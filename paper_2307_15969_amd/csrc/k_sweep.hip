@@ -399,6 +399,80 @@ k_phase(int64_t slot_base, int32_t tile0, int32_t tiles, int32_t full_tiles, int
     run_station_tile(tl, lane, slot_x, E);
 }
 
+// ------------------------------------------- whole-GPU phase, node form --
+// For graphs whose phases are wide (millions of edges each), the loads live
+// in one node-indexed array E[n + 2] (E[n] the zero center of empty lanes,
+// E[n+1] the infinite leaf of padding rows) instead of at stations: it is
+// small enough to stay in the on-die caches (the 256 MB Infinity Cache and
+// the L2s), while the station array of such a graph is as large as its edge
+// list and every scattered write to it goes to HBM.  A tile's leaf ids and
+// fractions stream in coalesced; its loads are gathered by id, the chain
+// runs as in k_phase, and each leaf's load is scattered back by id right
+// behind its step.  Leaves of one phase are distinct and no center is a
+// leaf, so no two lanes touch one entry.
+template <class St, bool kWeighted, int D>
+__global__ void __launch_bounds__(kPhaseBlock)
+k_phase_node(PhaseDescT<D> d, int32_t spread, const int32_t *__restrict__ tile_center,
+             const uint32_t *__restrict__ slot_leaf, typename St::X *__restrict__ slot_x,
+             const float *__restrict__ slot_w, typename St::L *__restrict__ E) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int32_t t = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x >> spread));
+    if (t >= d.T[0]) return;
+    const int32_t share = (int32_t)(blockIdx.x & ((1u << spread) - 1));
+    if ((lane >> (6 - spread)) != share) return;
+    int32_t depth;
+    int64_t base;
+    tile_geometry(d, t, depth, base);
+    const int32_t c = tile_center[(int64_t)(d.tile0 + t) * kWave + lane];
+    const uint32_t *pl = slot_leaf + base + lane;
+    typename St::X *px = slot_x + base + lane;
+    const float *pw = kWeighted ? slot_w + base + lane : nullptr;
+    uint32_t enc[D];
+    typename St::X x[D];
+    float w[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        if (k < depth) {
+            enc[k] = pl[k * kWave];
+            x[k] = px[k * kWave];
+            w[k] = kWeighted ? pw[k * kWave] : 1.0f;
+        } else {
+            enc[k] = 0u;
+        }
+    }
+    // the gathers, then one wait for all of them (see k_phase)
+    const typename St::L lc_raw = E[c];
+    typename St::L raw[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        if (k < depth) raw[k] = E[enc[k] & ~kCenterIsDst];
+        else raw[k] = St::infinite();
+    }
+    __builtin_amdgcn_s_waitcnt(kWaitLoads);
+    typename St::R lc = St::to_f64(lc_raw);
+    typename St::R ll[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) ll[k] = St::to_f64(raw[k]);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        if (k < depth) {
+            St::step_center(lc, ll[k], enc[k] & kCenterIsDst, x[k], w[k]);
+            px[k * kWave] = x[k];
+            E[enc[k] & ~kCenterIsDst] = St::from_f64(ll[k]);
+        }
+    }
+    E[c] = St::from_f64(lc);
+}
+
+// initial node-form entries: every node and the zero center 0, the
+// padding leaf +infinity (the initial loads follow, k_init_loads)
+template <class St>
+__global__ void k_fill_nodes(int32_t n, typename St::L *E) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)n + 2;
+         i += (int64_t)gridDim.x * blockDim.x)
+        E[i] = i == (int64_t)n + 1 ? St::infinite() : St::from_f64(0.0);
+}
+
 // ----------------------------------------- single-workgroup phases -------
 // The narrow phases after the whole-GPU ones run inside ONE workgroup, one
 // after another, separated by workgroup barriers instead of kernel
@@ -1143,6 +1217,27 @@ static void sweep_launchers(SweepLaunch &fn) {
                                center_base, (typename St::L *)E, slot_next,
                                (typename St::X *)slot_x, center_next, d, slot_w);
         }
+    };
+    fn.phase_node = [](const PhaseDescWide &d, const int32_t *tile_center,
+                       const uint32_t *slot_leaf, void *slot_x, const float *slot_w, void *E,
+                       hipStream_t s) {
+        const int32_t tiles = d.T[0];
+        int32_t spread = 0;
+        while (spread < kMaxSpreadLog2 && ((int64_t)tiles << (spread + 1)) <= kSpreadWaves)
+            ++spread;
+        const unsigned blocks = (unsigned)((int64_t)tiles << spread);
+        if (desc_depth(d) <= kTierStar)
+            hipLaunchKernelGGL((k_phase_node<St, kW, kTierStar>), dim3(blocks), dim3(kPhaseBlock),
+                               0, s, narrow_desc<kTierStar>(d), spread, tile_center, slot_leaf,
+                               (typename St::X *)slot_x, slot_w, (typename St::L *)E);
+        else
+            hipLaunchKernelGGL((k_phase_node<St, kW, kMaxStar>), dim3(blocks), dim3(kPhaseBlock), 0,
+                               s, d, spread, tile_center, slot_leaf, (typename St::X *)slot_x,
+                               slot_w, (typename St::L *)E);
+    };
+    fn.fill_nodes = [](int32_t n, void *E, hipStream_t s) {
+        hipLaunchKernelGGL((k_fill_nodes<St>), dim3(grid_for((int64_t)n + 2, 256)), dim3(256), 0, s,
+                           n, (typename St::L *)E);
     };
     fn.tail = [](int32_t nph, const PhaseDesc *descs, const int32_t *tile_center,
                  const uint32_t *slot_leaf, void *slot_x, const float *slot_w, int64_t tail_base,

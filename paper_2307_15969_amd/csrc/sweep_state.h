@@ -117,13 +117,13 @@ struct StateF32K {
     __host__ __device__ static inline X half_weight(float w) { return w * 0.5f; }
     __device__ static inline L infinite() { return L{__builtin_inff(), 0.0f}; }
     // the pair of v: s = v rounded to FP32, c = (v - s) rounded to FP32
-    // (v - s is exact in FP64).  Only finite loads are stored this way: the
-    // padding leaf's infinite load is written only to the sink entry, which
-    // is never read, and the initial entries use infinite() directly.
+    // (v - s is exact in FP64); an infinite v (the padding leaf, whose entry
+    // the node form writes back) keeps c = 0
     __device__ static inline L from_f64(double v) {
         L r;
         r.s = (float)v;
-        r.c = (float)(v - (double)r.s);
+        const float c = (float)(v - (double)r.s);
+        r.c = __builtin_isinf(r.s) ? 0.0f : c;
         return r;
     }
     __device__ static inline double to_f64(L v) { return (double)v.s + (double)v.c; }
@@ -193,6 +193,11 @@ struct SweepLaunch {
     void (*phase)(const PhaseDescWide &d, int64_t center_base, const uint32_t *center_next,
                   const uint32_t *slot_next, void *slot_x, const float *slot_w, void *E,
                   hipStream_t s);
+    // the node form (loads in a node-indexed array; whole-GPU phases only)
+    void (*phase_node)(const PhaseDescWide &d, const int32_t *tile_center,
+                       const uint32_t *slot_leaf, void *slot_x, const float *slot_w, void *E,
+                       hipStream_t s);
+    void (*fill_nodes)(int32_t n, void *E, hipStream_t s);
     void (*tail)(int32_t nph, const PhaseDesc *descs, const int32_t *tile_center,
                  const uint32_t *slot_leaf, void *slot_x, const float *slot_w, int64_t tail_base,
                  const uint32_t *tail_next, int32_t ntail, void *E, hipStream_t s);

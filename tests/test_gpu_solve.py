@@ -329,3 +329,59 @@ def test_batch_solve_reports_not_converged():
     r = lowd.batch_solve(gs, 1e-14, "f64", max_sweeps=4, check_every=2)
     assert not r["converged"]
     assert int(r["sweeps"].max()) == 4
+
+
+# ------------------------------------------- node-indexed load layout ----
+NODE_GRAPHS = SOLVE_GRAPHS + [("uniform_2^13_2^17", synth.uniform_pairs(13, 17, seed=3))]
+
+
+@pytest.mark.parametrize("smax", [1, 16, 32])
+@pytest.mark.parametrize("name,g", NODE_GRAPHS, ids=[n for n, _ in NODE_GRAPHS])
+def test_node_layout_sweeps_bit_exact(name, g, smax, monkeypatch):
+    """Loads in a node-indexed array (the layout for wide phases): the same
+    bits as the oracle's sequential loop, across launches with eager work in
+    between; D, the extraction and the initial state after a reset too."""
+    monkeypatch.setenv("LOWD_LAYOUT", "node")
+    sv = lowd.Solver(g.n, g.src, g.dst, g.w, "f64", star_max=smax)
+    info = sv.info()
+    assert info["node_layout"] == 1 and info["lds_phases"] == 0 and info["mid_phases"] == 0
+    T = 7
+    sv.iterate(1)
+    sv.check()
+    sv.iterate(2)
+    sv.extract()
+    sv.iterate(T - 3)
+    x, L = sv.read_state()
+    xo, Lo, _ = oracle_state(g, T, smax=smax)
+    assert np.array_equal(x.cpu().numpy(), xo)
+    assert np.array_equal(L.cpu().numpy(), Lo)
+    assert sv.check()[0] == float(Lo.max())
+    ex = sv.extract()
+    ro = oracle.extract(g.n, g.src, g.dst, g.w, Lo)
+    assert np.array_equal(ex["in_set"].cpu().numpy(), ro["in_set"])
+    assert ex["den"] == ro["den"] and ex["num_w"] == ro["num_w"]
+    sv.reset()
+    x0, L0 = sv.read_state()
+    xi, Li = oracle.init(g.n, g.src, g.dst, g.w)
+    assert np.array_equal(x0.cpu().numpy(), xi) and np.array_equal(L0.cpu().numpy(), Li)
+    sv.close()
+
+
+@pytest.mark.parametrize("name,g", NODE_GRAPHS, ids=[n for n, _ in NODE_GRAPHS])
+def test_node_layout_f32k_and_solve(name, g, monkeypatch):
+    monkeypatch.setenv("LOWD_LAYOUT", "node")
+    sv = lowd.Solver(g.n, g.src, g.dst, g.w, "f32k")
+    assert sv.info()["node_layout"] == 1
+    sv.iterate(6)
+    _, L = sv.read_state()
+    _, Lo, _ = oracle_state(g, 6)
+    assert np.max(np.abs(L.cpu().numpy() - Lo)) <= 1e-5 * np.max(np.abs(Lo))
+    sv.reset()
+    r = sv.solve(TOL)
+    assert r["converged"] and r["D"] == sv.check()[0]
+    sv.close()
+    sv = lowd.Solver(g.n, g.src, g.dst, g.w, "f64")
+    r64 = sv.solve(TOL)
+    _, Lo, _ = oracle_state(g, r64["sweeps"])
+    assert r64["D"] == float(Lo.max())
+    sv.close()
