@@ -38,9 +38,7 @@ def _hipcc() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [_hipcc(), "-c", src, "-o", obj] + COMMON
-    if src.endswith(".hip"):
-        cmd += DEVICE
+    cmd = [_hipcc(), "-c", src, "-o", obj] + COMMON + DEVICE
     cmd += PER_FILE.get(os.path.basename(src), [])
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     out = "\n".join(l for l in r.stdout.splitlines()
