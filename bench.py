@@ -64,6 +64,8 @@ def profiled_traffic(workload: str):
                   if l.startswith(("traffic_bytes_per_sweep: ", "sources_sha256_16: ")))
     if fields.get("sources_sha256_16", "").strip() != sources_hash():
         return None
+    if "traffic_bytes_per_sweep" not in fields:
+        return None
     return int(fields["traffic_bytes_per_sweep"])
 
 
@@ -250,7 +252,7 @@ def run_rmat24(args, torch, lowd, synth):
         return time.perf_counter() - ta
 
     res, svs = {}, {}
-    for state in ("f64", "f32k"):
+    for state in ((args.state,) if args.state else ("f64", "f32k")):
         t0 = time.perf_counter()
         sv = lowd.Solver(n_h, hs, hd, None, state, star_max=args.star_max)
         torch.cuda.synchronize()
@@ -261,20 +263,24 @@ def run_rmat24(args, torch, lowd, synth):
         r["setup_s"] = t_setup
         res[state] = r
         svs[state] = sv
-    r64, r32 = res["f64"], res["f32k"]
-    err = load_error(svs["f32k"], svs["f64"], r32["last"]["sweeps"], stream)
-    info = svs["f64"].info()
+    lead = "f64" if "f64" in res else "f32k"
+    r64, r32 = res[lead], res.get("f32k")
+    err = (load_error(svs["f32k"], svs["f64"], r32["last"]["sweeps"], stream)
+           if len(res) == 2 else None)
+    info = svs[lead].info()
     for sv in svs.values():
         sv.close()
     step_ms = (r64["pre_s"] + r64["solve_s"]) / args.steps * 1e3
-    out = base_line(args, r64["value"], step_ms, "f64",
-                    {"workload": f"rmat24 ({WORKLOADS['rmat24']}), FP64 to a 1e-6 gap; "
+    name = {"f64": "FP64", "f32k": "FP32K"}[lead]
+    out = base_line(args, r64["value"], step_ms, lead,
+                    {"workload": f"rmat24 ({WORKLOADS['rmat24']}), {name} to a 1e-6 gap; "
                      "step = prune + solve", "n": n, "m": m, "n_h": n_h, "m_h": m_h,
                      "star_max": args.star_max, "check_every": args.check_every,
                      "seed": args.seed})
-    f64 = state_result(r64, m_h, n_h, 8, 0, "one FP64 sweep of H (HIP graph of phase kernels "
-                       "and single-workgroup tiers)", profiled_traffic("rmat24"))
-    f32 = state_result(r32, m_h, n_h, 4, 0, "one FP32K sweep of H (HIP graph)")
+    f64 = state_result(r64, m_h, n_h, 8 if lead == "f64" else 4, 0,
+                       f"one {name} sweep of H (HIP graph of phase kernels and "
+                       "single-workgroup tiers)",
+                       profiled_traffic("rmat24") if lead == "f64" else None)
     out.update({
         "prune_ms": t_prune * 1e3,
         "prune_edges_per_s": m / t_prune,
@@ -286,10 +292,14 @@ def run_rmat24(args, torch, lowd, synth):
         "setup_s": r64["setup_s"],
         "schedule": info,
         "roofline": f64["roofline"],
-        "f32k": dict(f32, setup_s=r32["setup_s"],
-                     step_ms=(r32["pre_s"] + r32["solve_s"]) / args.steps * 1e3),
-        "f32k_load_error_vs_f64": {"max_abs_over_max": err, "sweeps": r32["last"]["sweeps"]},
     })
+    if err is not None:
+        f32 = state_result(r32, m_h, n_h, 4, 0, "one FP32K sweep of H (HIP graph)")
+        out.update({
+            "f32k": dict(f32, setup_s=r32["setup_s"],
+                         step_ms=(r32["pre_s"] + r32["solve_s"]) / args.steps * 1e3),
+            "f32k_load_error_vs_f64": {"max_abs_over_max": err, "sweeps": r32["last"]["sweeps"]},
+        })
     if not args.no_cpu_baseline:
         torch.cuda.synchronize()
         h_src, h_dst = hs.cpu().numpy(), hd.cpu().numpy()
@@ -535,8 +545,9 @@ def main():
                          "graph's phase count a hub sets, else 16)")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="rmat24")
     ap.add_argument("--state", choices=["f64", "f32k"], default=None,
-                    help="solver state where the workload runs one (chunglu1m: f64, batch4096 "
-                         "and uniform: the first of two / the only one)")
+                    help="solver state: rmat24 runs only this one (default: FP64, then "
+                         "FP32K beside it); chunglu1m: f64; batch4096 and uniform: the first "
+                         "of two / the only one")
     ap.add_argument("--uniform-log-n", type=int, default=22)
     ap.add_argument("--uniform-log-m", type=int, default=28)
     ap.add_argument("--no-cpu-baseline", action="store_true")
