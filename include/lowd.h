@@ -283,10 +283,13 @@ lowd_status lowd_extract_densest_kept(lowd_solver *s, uint8_t *in_set, int64_t *
  * certified once (D - rho) / rho <= tol.  The call sweeps and checks until
  * that holds or max_sweeps sweeps are done.
  *
- * Checks come at most every check_every sweeps, sooner when the decay of the
- * gap over the last two checks predicts the tolerance; the first comes after
- * the first sweeps.  A check takes D first and extracts (Algorithm 1's sort
- * and prefix densities) only when D does not already certify the best set.
+ * The first check comes after one sweep.  Later ones come where the decay
+ * of the gap over the last two checks predicts the tolerance (at most
+ * check_every sweeps on); without such a prediction the check points double,
+ * but stay far enough apart that a check (timed against a sweep on the
+ * stream) costs at most about a quarter of the sweeps between two checks.
+ * A check takes D first and extracts (Algorithm 1's sort and prefix
+ * densities) only when D does not already certify the best set.
  * With LOWD_STATE_F32K checks screen with the kept compensated loads and
  * confirm a passing gap with D recomputed in FP64 from the stored fractions
  * (the loads of a feasible dual point); when the confirmation fails the

@@ -517,11 +517,14 @@ bool at_least_as_dense(const Extracted &a, const Extracted &b) {
     return a.w_exact * (u128)b.den >= b.w_exact * (u128)a.den;
 }
 
-// Sweeps before the next check from the last two (sweeps, gap) records: the
-// gap decays about geometrically, so they predict when it reaches tol; at
-// most check_every, at least 1.
+// Sweeps before the next check.  From the last two (sweeps, gap) records:
+// the gap decays about geometrically, so they predict when it reaches tol
+// (at least 1, at most check_every).  Without such a prediction (the first
+// checks, or a gap that did not fall): the sweeps done so far, so that check
+// points double, but at least k_min and at most check_every; the first check
+// comes after one sweep.
 int32_t next_check(const std::vector<std::pair<int64_t, double>> &hist, double tol,
-                   int32_t check_every) {
+                   int32_t check_every, int32_t k_min) {
     if (hist.size() >= 2) {
         const auto &a = hist[hist.size() - 2];
         const auto &b = hist[hist.size() - 1];
@@ -530,11 +533,14 @@ int32_t next_check(const std::vector<std::pair<int64_t, double>> &hist, double t
             const double rate = std::pow(g1 / g0, 1.0 / (double)(b.first - a.first));
             if (rate < 1.0) {
                 const double k = std::ceil(std::log(tol / g1) / std::log(rate));
-                if (k < (double)check_every) return (int32_t)std::max(1.0, k);
+                return (int32_t)std::max(1.0, std::min(k, (double)check_every));
             }
         }
     }
-    return check_every;
+    if (hist.empty()) return 1;
+    const int64_t done = hist.back().first;
+    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(std::max<int64_t>(k_min, done),
+                                                           check_every));
 }
 
 }  // namespace
@@ -603,13 +609,41 @@ lowd_status lowd_solve(lowd_solver *sv, double tol, int32_t max_sweeps, int32_t 
         std::vector<std::pair<int64_t, double>> hist;
         int32_t sweeps = 0;
         double gap = 1.0e300, D = 0.0;
+        // The cost of a check against a sweep's, timed with events on the
+        // stream: checks without a predicted convergence point stay at
+        // least k_min sweeps apart, so that they cost at most about a
+        // quarter of the sweeps between them.
+        hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+        struct Events {
+            hipEvent_t *e;
+            ~Events() {
+                for (int i = 0; i < 3; ++i)
+                    if (e[i]) (void)hipEventDestroy(e[i]);
+            }
+        } ev_guard{ev};
+        for (int i = 0; i < 3; ++i) LOWD_HIP(hipEventCreate(&ev[i]));
+        int32_t k_min = 1;
         while (sweeps < max_sweeps && gap > tol) {
-            const int32_t k = std::min(next_check(hist, tol, check_every), max_sweeps - sweeps);
+            const int32_t k = std::min(next_check(hist, tol, check_every, k_min),
+                                       max_sweeps - sweeps);
+            LOWD_HIP(hipEventRecord(ev[0], s));
             if (sv->exec)
                 for (int32_t t = 0; t < k; ++t) LOWD_HIP(hipGraphLaunch(sv->exec, s));
+            LOWD_HIP(hipEventRecord(ev[1], s));
             sweeps += k;
             gap = certify(sv, best, in_set, tol, &D, s);
+            LOWD_HIP(hipEventRecord(ev[2], s));
             hist.emplace_back(sweeps, gap);
+            if (gap > tol && k > 0) {
+                LOWD_HIP(hipEventSynchronize(ev[2]));
+                float sweep_ms = 0.f, check_ms = 0.f;
+                LOWD_HIP(hipEventElapsedTime(&sweep_ms, ev[0], ev[1]));
+                LOWD_HIP(hipEventElapsedTime(&check_ms, ev[1], ev[2]));
+                const double per = (double)sweep_ms / (double)k;
+                k_min = per > 0.0 ? (int32_t)std::min<double>(
+                                        check_every, std::max(1.0, std::ceil(4.0 * check_ms / per)))
+                                  : check_every;
+            }
         }
         if (!best.have) gap = certify(sv, best, in_set, tol, &D, s);   // max_sweeps == 0
         if (gap > tol && sv->state != LOWD_STATE_F64) {

@@ -33,6 +33,18 @@ __global__ void k_incidence_keys(int64_t m, const int32_t *src, const int32_t *d
     }
 }
 
+// the same with each entry's value the edge's other end
+__global__ void k_incidence_neighbours(int64_t m, const int32_t *src, const int32_t *dst,
+                                       uint32_t *keys, uint32_t *vals) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < 2 * m;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = j >> 1;
+        const uint32_t a = (uint32_t)src[e], b = (uint32_t)dst[e];
+        keys[j] = (j & 1) ? b : a;
+        vals[j] = (j & 1) ? a : b;
+    }
+}
+
 // row_ptr[u] = first position of key u in the sorted keys (lower bound)
 __global__ void k_row_ptr(const uint32_t *sorted, int64_t len, int32_t n, int64_t *row_ptr) {
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u <= n;
@@ -82,29 +94,38 @@ void build_adjacency(int64_t m, const Csr &csr, const int32_t *src, const int32_
 }
 
 void build_incidence_ws(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, Arena &ws,
-                        int64_t **row_ptr, uint32_t **inc, hipStream_t s) {
+                        int64_t **row_ptr, uint32_t **inc, bool neighbours, hipStream_t s) {
     const int64_t len = 2 * m;
     const size_t cap = (size_t)(len > 0 ? len : 1);
     *row_ptr = ws.take<int64_t>((size_t)n + 1);
     *inc = ws.take<uint32_t>(cap);
     const size_t mk = ws.mark();
     uint32_t *k0 = ws.take<uint32_t>(cap), *k1 = ws.take<uint32_t>(cap);
-    uint32_t *v1 = ws.take<uint32_t>(cap);
+    uint32_t *vt = ws.take<uint32_t>(cap);
     const size_t tmp_bytes = radix_sort_tmp_bytes(len);
     char *tmp = ws.take<char>(tmp_bytes);
     if (ws.base) {
         int bits = 1;
         while (bits < 32 && ((int64_t)1 << bits) < (int64_t)n) ++bits;
-        if (len > 0)
-            hipLaunchKernelGGL(k_incidence_keys, dim3(grid_for(len, 256)), dim3(256), 0, s, m, src,
-                               dst, k0, *inc);
+        // the sort makes one pass per 8 bits and ends in its second buffers
+        // after an odd number of them: start the values where they end in inc
+        const bool odd = len > 1 && ((bits + 7) / 8) % 2 == 1;
+        uint32_t *v_in = odd ? vt : *inc, *v_alt = odd ? *inc : vt;
+        if (len > 0) {
+            if (neighbours)
+                hipLaunchKernelGGL(k_incidence_neighbours, dim3(grid_for(len, 256)), dim3(256), 0,
+                                   s, m, src, dst, k0, v_in);
+            else
+                hipLaunchKernelGGL(k_incidence_keys, dim3(grid_for(len, 256)), dim3(256), 0, s, m,
+                                   src, dst, k0, v_in);
+        }
         bool alt = false;
-        radix_sort_u32(k0, *inc, k1, v1, len, bits, tmp, tmp_bytes, &alt, s);
+        radix_sort_u32(k0, v_in, k1, v_alt, len, bits, tmp, tmp_bytes, &alt, s);
         const uint32_t *keys = alt ? k1 : k0;
         hipLaunchKernelGGL(k_row_ptr, dim3(grid_for((int64_t)n + 1, 256)), dim3(256), 0, s, keys,
                            len, n, *row_ptr);
-        if (alt && len > 0)
-            LOWD_HIP(hipMemcpyAsync(*inc, v1, (size_t)len * sizeof(uint32_t),
+        if ((alt ? v_alt : v_in) != *inc && len > 0)
+            LOWD_HIP(hipMemcpyAsync(*inc, alt ? v_alt : v_in, (size_t)len * sizeof(uint32_t),
                                     hipMemcpyDeviceToDevice, s));
         LOWD_HIP(hipGetLastError());
         LOWD_HIP(hipStreamSynchronize(s));
@@ -158,6 +179,22 @@ __global__ void k_adjacent_equal(int64_t m, const uint64_t *keys, const uint32_t
         if (keys[i] == keys[i - 1]) atomicMin(bad, (unsigned long long)vals[i]);
 }
 
+// the unordered pair as one key of 2 nb bits: (smaller id << nb) | larger id
+__global__ void k_packed_pair_keys(int64_t m, const int32_t *src, const int32_t *dst, int nb,
+                                   uint64_t *keys) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t a = (uint32_t)src[e], b = (uint32_t)dst[e];
+        keys[e] = a < b ? (a << nb) | b : (b << nb) | a;
+    }
+}
+
+__global__ void k_any_adjacent_equal(int64_t m, const uint64_t *keys, unsigned int *any) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + 1; i < m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (keys[i] == keys[i - 1]) *any = 1u;
+}
+
 }  // namespace
 
 // Index of the later edge of the first repeated unordered pair found, or -1.
@@ -170,13 +207,32 @@ int64_t find_duplicate_pair_ws(int32_t n, int64_t m, const int32_t *src, const i
     const size_t tmp_bytes = radix_sort_tmp_bytes(m);
     char *tmp = ws.take<char>(tmp_bytes);
     unsigned long long *bad = ws.take<unsigned long long>(1);
+    unsigned int *any = ws.take<unsigned int>(1);
     unsigned long long r = ~0ull;
     if (ws.base) {
         int nb = 1;
         while (nb < 32 && ((int64_t)1 << nb) < (int64_t)n) ++nb;
+        // Whether any pair repeats: the packed keys alone, sorted (2 nb bits).
+        // Only then is the indexed sort below run, to name the edge.
+        const unsigned int zero = 0u;
+        LOWD_HIP(hipMemcpyAsync(any, &zero, sizeof(zero), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_packed_pair_keys, dim3(grid_for(m, 256)), dim3(256), 0, s, m, src,
+                           dst, nb, k0);
+        bool alt = false;
+        radix_sort_u64(k0, nullptr, k1, nullptr, m, 2 * nb, tmp, tmp_bytes, &alt, s);
+        hipLaunchKernelGGL(k_any_adjacent_equal, dim3(grid_for(m, 256)), dim3(256), 0, s, m,
+                           alt ? k1 : k0, any);
+        LOWD_HIP(hipGetLastError());
+        unsigned int found = 0u;
+        LOWD_HIP(hipMemcpyAsync(&found, any, sizeof(found), hipMemcpyDeviceToHost, s));
+        LOWD_HIP(hipStreamSynchronize(s));
+        if (!found) {
+            ws.release(mk);
+            return -1;
+        }
         hipLaunchKernelGGL(k_pair_keys, dim3(grid_for(m, 256)), dim3(256), 0, s, m, src, dst, k0,
                            v0);
-        bool alt = false;
+        alt = false;
         radix_sort_u64(k0, v0, k1, v1, m, 32 + nb, tmp, tmp_bytes, &alt, s);
         unsigned long long init = ~0ull;
         LOWD_HIP(hipMemcpyAsync(bad, &init, sizeof(init), hipMemcpyHostToDevice, s));

@@ -114,9 +114,9 @@ __global__ void k_stamp(int64_t k, const int32_t *list, int32_t *stamp, int32_t 
         stamp[list[i]] = round;
 }
 
-// for each removed node: lower alive neighbours' degrees; count each removed
-// edge once (an edge between two nodes removed this round by its smaller
-// end).  G lanes walk one removed node's row (G = 1 for the many short rows
+// for each removed node (its row of neighbour ids): lower alive neighbours'
+// degrees; count each removed edge once (an edge between two nodes removed
+// this round by its smaller end).  G lanes walk one removed node's row (G = 1 for the many short rows
 // of the first round; a wave or the whole workgroup for the later rounds,
 // whose few removed nodes can have long rows).  The counts are summed per
 // wave after the loop, where the whole wave has reconverged, and added with
@@ -125,9 +125,7 @@ constexpr int kRemoveBlock = 256;
 template <int G>
 __global__ void __launch_bounds__(kRemoveBlock) k_remove_edges(int64_t k, const int32_t *removed,
                                                                const int64_t *row_ptr,
-                                                               const uint32_t *inc,
-                                                               const int32_t *src,
-                                                               const int32_t *dst,
+                                                               const uint32_t *nbr,
                                                                const int32_t *stamp,
                                                                int32_t round, int32_t *deg,
                                                                unsigned long long *gone) {
@@ -139,10 +137,8 @@ __global__ void __launch_bounds__(kRemoveBlock) k_remove_edges(int64_t k, const 
         const int32_t u = removed[i];
         const int64_t end = row_ptr[u + 1];
         for (int64_t j = row_ptr[u] + lane; j < end; j += G) {
-            uint32_t ent = inc[j];
-            int64_t e = ent >> 1;
-            int32_t v = (ent & 1) ? src[e] : dst[e];
-            int32_t sv = stamp[v];
+            const int32_t v = (int32_t)nbr[j];
+            const int32_t sv = stamp[v];
             if (sv == 0) {
                 atomicSub(&deg[v], 1);
                 ++cnt;
@@ -170,28 +166,109 @@ __global__ void k_relabel(int32_t n, const int64_t *flag, const int64_t *pos, in
         relabel[u] = flag[u] ? (int32_t)pos[u] : -1;
 }
 
-__global__ void k_edge_flags(int64_t m, const int32_t *src, const int32_t *dst,
-                             const int32_t *stamp, int64_t *flag) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
-         e += (int64_t)gridDim.x * blockDim.x)
-        flag[e] = (stamp[src[e]] == 0 && stamp[dst[e]] == 0) ? 1 : 0;
+// The edges of H (both ends kept), compacted in their original order, in
+// two passes over tiles of kCompactTile edges: the first marks each edge and
+// counts a tile's kept edges; after a scan of the tile counts, the second
+// writes a tile's kept edges from its offset, each thread its own run of
+// kCompactItems consecutive edges after the runs of the threads before it.
+constexpr int kCompactBlock = 256, kCompactItems = 16;
+constexpr int64_t kCompactTile = (int64_t)kCompactBlock * kCompactItems;
+
+// exclusive scan of one int per thread over a 256-thread block; *total =
+// the block's sum.  Two barriers.
+__device__ inline int block_scan_int(int v, int *lds, int *total) {
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    int inc = v;
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int y = __shfl_up(inc, d, kWave);
+        if (lane >= d) inc += y;
+    }
+    if (lane == kWave - 1) lds[wave] = inc;
+    __syncthreads();
+    int before = 0, all = 0;
+    for (int k = 0; k < kCompactBlock / kWave; ++k) {
+        before += k < wave ? lds[k] : 0;
+        all += lds[k];
+    }
+    __syncthreads();
+    *total = all;
+    return inc - v + before;
 }
 
-__global__ void k_edge_compact(int64_t m, const int32_t *src, const int32_t *dst,
-                               const float *w, const int64_t *flag, const int64_t *pos,
-                               const int64_t *npos, int32_t *h_src, int32_t *h_dst, float *h_w,
-                               int64_t *edge_map) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        if (!flag[e]) continue;
-        int64_t at = pos[e];
-        if (h_src) {
-            h_src[at] = (int32_t)npos[src[e]];
-            h_dst[at] = (int32_t)npos[dst[e]];
+__global__ void __launch_bounds__(kCompactBlock)
+    k_edge_keep_tiles(int64_t m, const int32_t *src, const int32_t *dst, const int32_t *stamp,
+                      uint8_t *keep, int64_t *tile_count) {
+    __shared__ int lds[kCompactBlock / kWave];
+    const int64_t ntiles = (m + kCompactTile - 1) / kCompactTile;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {   // uniform across the block
+        int c = 0;
+        for (int k = 0; k < kCompactItems; ++k) {
+            const int64_t e = t * kCompactTile + (int64_t)k * kCompactBlock + threadIdx.x;
+            if (e < m) {
+                const bool kp = stamp[src[e]] == 0 && stamp[dst[e]] == 0;
+                keep[e] = kp ? 1 : 0;
+                c += kp ? 1 : 0;
+            }
         }
-        if (h_w) h_w[at] = w[e];
-        if (edge_map) edge_map[at] = e;
+        int total;
+        block_scan_int(c, lds, &total);
+        if (threadIdx.x == 0) tile_count[t] = total;
     }
+}
+
+__global__ void __launch_bounds__(kCompactBlock)
+    k_edge_write_tiles(int64_t m, const int32_t *src, const int32_t *dst, const float *w,
+                       const uint8_t *keep, const int64_t *tile_offset, const int64_t *npos,
+                       int32_t *h_src, int32_t *h_dst, float *h_w, int64_t *edge_map) {
+    __shared__ int lds[kCompactBlock / kWave];
+    const int64_t ntiles = (m + kCompactTile - 1) / kCompactTile;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {   // uniform across the block
+        const int64_t e0 = t * kCompactTile + (int64_t)threadIdx.x * kCompactItems;
+        uint32_t bits = 0;
+        int c = 0;
+        for (int k = 0; k < kCompactItems; ++k) {
+            const int64_t e = e0 + k;
+            if (e < m && keep[e]) {
+                bits |= 1u << k;
+                ++c;
+            }
+        }
+        int total;
+        int64_t at = tile_offset[t] + block_scan_int(c, lds, &total);
+        for (int k = 0; k < kCompactItems; ++k) {
+            if (!((bits >> k) & 1u)) continue;
+            const int64_t e = e0 + k;
+            if (h_src) {
+                h_src[at] = (int32_t)npos[src[e]];
+                h_dst[at] = (int32_t)npos[dst[e]];
+            }
+            if (h_w) h_w[at] = w[e];
+            if (edge_map) edge_map[at] = e;
+            ++at;
+        }
+    }
+}
+
+// buffers of compact_edges for m edges
+inline int64_t compact_tiles(int64_t m) { return (m + kCompactTile - 1) / kCompactTile; }
+
+// H's edge list (renumbered by npos) from the kept flags of the nodes
+// (stamp == 0); *kept_dev (device) receives the number of H's edges.
+void compact_edges(int64_t m, const int32_t *src, const int32_t *dst, const float *w,
+                   const int32_t *stamp, const int64_t *npos, int32_t *h_src, int32_t *h_dst,
+                   float *h_w, int64_t *edge_map, uint8_t *keep, int64_t *tile_count,
+                   int64_t *tile_offset, int64_t *kept_dev, void *scan_tmp, size_t scan_bytes,
+                   hipStream_t s) {
+    if (m <= 0) return;
+    const int64_t nt = compact_tiles(m);
+    const unsigned g = (unsigned)std::min<int64_t>(nt, 65536);
+    hipLaunchKernelGGL(k_edge_keep_tiles, dim3(g), dim3(kCompactBlock), 0, s, m, src, dst, stamp,
+                       keep, tile_count);
+    exclusive_scan_i64(tile_count, tile_offset, nt, kept_dev, scan_tmp, scan_bytes, s);
+    if (h_src || h_w || edge_map)
+        hipLaunchKernelGGL(k_edge_write_tiles, dim3(g), dim3(kCompactBlock), 0, s, m, src, dst, w,
+                           keep, tile_offset, npos, h_src, h_dst, h_w, edge_map);
+    LOWD_HIP(hipGetLastError());
 }
 
 // ------------------------------------------------------ weighted graphs --
@@ -354,7 +431,7 @@ PruneResult run_prune_ws(int32_t n, int64_t m, const int32_t *src, const int32_t
         int64_t *row_ptr;
         uint32_t *inc;
     } csr;
-    build_incidence_ws(n, m, src, dst, ws, &csr.row_ptr, &csr.inc, s);
+    build_incidence_ws(n, m, src, dst, ws, &csr.row_ptr, &csr.inc, true, s);   // neighbour ids
     const size_t nn = (size_t)n;
     int32_t *deg = ws.take<int32_t>(nn), *stamp = ws.take<int32_t>(nn),
             *by_deg = ws.take<int32_t>(nn), *list_a = ws.take<int32_t>(nn),
@@ -365,13 +442,14 @@ PruneResult run_prune_ws(int32_t n, int64_t m, const int32_t *src, const int32_t
     int64_t *bin_start = ws.take<int64_t>(kBins), *f_rm = ws.take<int64_t>(nn),
             *f_keep = ws.take<int64_t>(nn), *p_rm = ws.take<int64_t>(nn),
             *p_keep = ws.take<int64_t>(nn), *tot = ws.take<int64_t>(2);
-    int64_t big = n > m ? (int64_t)n : m;
-    if (big < kBins) big = kBins;
+    int64_t big = std::max<int64_t>(std::max<int64_t>(n, compact_tiles(m)), kBins);
     const size_t scan_bytes = exclusive_scan_tmp_bytes(big);
     char *scan_tmp = ws.take<char>(scan_bytes);
     const bool edges_out = (h_src || edge_map) && m > 0;
-    int64_t *ef = edges_out ? ws.take<int64_t>((size_t)m) : nullptr;
-    int64_t *ep = edges_out ? ws.take<int64_t>((size_t)m) : nullptr;
+    const int64_t nt = compact_tiles(m);
+    uint8_t *ekeep = edges_out ? ws.take<uint8_t>((size_t)m) : nullptr;
+    int64_t *tcount = edges_out ? ws.take<int64_t>((size_t)nt) : nullptr;
+    int64_t *toff = edges_out ? ws.take<int64_t>((size_t)nt + 1) : nullptr;
     if (!ws.base) return res;   // measuring only
 
     hipLaunchKernelGGL(k_degrees, dim3(gn), dim3(256), 0, s, n, csr.row_ptr, deg);
@@ -428,15 +506,15 @@ PruneResult run_prune_ws(int32_t n, int64_t m, const int32_t *src, const int32_t
         if (nrm >= (1 << 18))
             hipLaunchKernelGGL(k_remove_edges<1>, dim3(grid_for(nrm, kRemoveBlock)),
                                dim3(kRemoveBlock), 0, s, nrm, rm_list, csr.row_ptr, csr.inc,
-                               src, dst, stamp, round, deg, gone);
+                               stamp, round, deg, gone);
         else if (nrm >= (1 << 12))
             hipLaunchKernelGGL(k_remove_edges<kWave>, dim3(grid_for(nrm, kRemoveBlock / kWave)),
                                dim3(kRemoveBlock), 0, s, nrm, rm_list, csr.row_ptr, csr.inc,
-                               src, dst, stamp, round, deg, gone);
+                               stamp, round, deg, gone);
         else
             hipLaunchKernelGGL(k_remove_edges<kRemoveBlock>, dim3(grid_for(nrm, 1)),
                                dim3(kRemoveBlock), 0, s, nrm, rm_list, csr.row_ptr, csr.inc,
-                               src, dst, stamp, round, deg, gone);
+                               stamp, round, deg, gone);
         LOWD_HIP(hipGetLastError());
         unsigned long long g = 0;
         LOWD_HIP(hipMemcpyAsync(&g, gone, sizeof(g), hipMemcpyDeviceToHost, s));
@@ -452,12 +530,8 @@ PruneResult run_prune_ws(int32_t n, int64_t m, const int32_t *src, const int32_t
     if (relabel)
         hipLaunchKernelGGL(k_relabel, dim3(gn), dim3(256), 0, s, n, f_keep, p_keep, relabel);
     if (edges_out) {
-        hipLaunchKernelGGL(k_edge_flags, dim3(grid_for(m, 256)), dim3(256), 0, s, m, src, dst,
-                           stamp, ef);
-        exclusive_scan_i64(ef, ep, m, nullptr, scan_tmp, scan_bytes, s);
-        hipLaunchKernelGGL(k_edge_compact, dim3(grid_for(m, 256)), dim3(256), 0, s, m, src, dst,
-                           nullptr, ef, ep, p_keep, h_src, h_dst, nullptr, edge_map);
-        LOWD_HIP(hipGetLastError());
+        compact_edges(m, src, dst, nullptr, stamp, p_keep, h_src, h_dst, nullptr, edge_map, ekeep,
+                      tcount, toff, toff + nt, scan_tmp, scan_bytes, s);
         LOWD_HIP(hipStreamSynchronize(s));
     }
     LOWD_HIP(hipGetLastError());
@@ -547,13 +621,11 @@ PruneResult run_prune_weighted(int32_t n, int64_t m, const int32_t *src, const i
         hipLaunchKernelGGL(k_relabel, dim3(gn), dim3(256), 0, s, n, f_keep.p, p_keep.p, relabel);
     int64_t mh = 0;
     if (m > 0) {
-        DBuf<int64_t> ef((size_t)m), ep((size_t)m), etot(1);
-        hipLaunchKernelGGL(k_edge_flags, dim3(grid_for(m, 256)), dim3(256), 0, s, m, src, dst,
-                           stamp.p, ef.p);
-        exclusive_scan_i64(ef.p, ep.p, m, etot.p, scan_tmp.p, scan_tmp.bytes(), s);
-        if (h_src || h_w || edge_map)
-            hipLaunchKernelGGL(k_edge_compact, dim3(grid_for(m, 256)), dim3(256), 0, s, m, src,
-                               dst, w, ef.p, ep.p, p_keep.p, h_src, h_dst, h_w, edge_map);
+        const int64_t nt = compact_tiles(m);
+        DBuf<uint8_t> ekeep((size_t)m);
+        DBuf<int64_t> tcount((size_t)nt), toff((size_t)nt), etot(1);
+        compact_edges(m, src, dst, w, stamp.p, p_keep.p, h_src, h_dst, h_w, edge_map, ekeep.p,
+                      tcount.p, toff.p, etot.p, scan_tmp.p, scan_tmp.bytes(), s);
         LOWD_HIP(hipMemcpyAsync(&mh, etot.p, sizeof(mh), hipMemcpyDeviceToHost, s));
         LOWD_HIP(hipStreamSynchronize(s));
     }

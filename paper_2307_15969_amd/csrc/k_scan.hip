@@ -151,22 +151,28 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_hist(const K *keys, int64
     blockhist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
-// The scatter stages rounds of kRadixRound keys in LDS in digit order, then
-// writes every digit's run of the round to consecutive addresses: a tile's
-// 256 keys written straight out land on up to 256 scattered lines, a round's
-// runs average 16 keys per digit.  Ranks are taken tile by tile in key order
-// (wave ballots for equal digits, waves in order), so the permutation is the
-// stable one.
-constexpr int kRadixRoundTiles = 16;
-constexpr int kRadixRound = kRadixRoundTiles * kRadixBlock;   // keys staged at a time
+// The scatter stages rounds of keys in LDS in digit order, then writes every
+// digit's run of the round to consecutive addresses: a tile's 256 keys
+// written straight out land on up to 256 scattered lines.  A round is 16
+// tiles (4,096 keys) of 12-byte pairs, 32 tiles of 8-byte ones (4-byte keys
+// with values, or 8-byte keys alone), so that a digit's run averages a full
+// 128-byte line or more (about 77 KB of LDS, two blocks per CU).  Ranks are
+// taken tile by tile in key order (wave ballots for equal digits, waves in
+// order), so the permutation is the stable one.
+template <class K, bool kVals>
+constexpr int radix_round_tiles() {
+    return sizeof(K) + (kVals ? sizeof(uint32_t) : 0) <= 8 ? 32 : 16;
+}
 
-template <class K>
+template <class K, bool kVals>
 __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter_staged(const K *keys, const uint32_t *vals,
                                                                K *keys_out, uint32_t *vals_out,
                                                                int64_t n, int shift,
                                                                const int64_t *offsets,
                                                                int64_t nb, int64_t tiles) {
     constexpr int kWaves = kRadixBlock / kWave;
+    constexpr int kTiles = radix_round_tiles<K, kVals>();
+    constexpr int kRound = kTiles * kRadixBlock;   // keys staged at a time
     __shared__ int64_t running[kDigits];         // next global position of each digit
     __shared__ int64_t scan_lds[kWave + 1];
     __shared__ uint32_t cnt[kDigits];            // this round's keys per digit
@@ -174,8 +180,8 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter_staged(const K *k
     __shared__ uint32_t next[kDigits];           // next free local position
     __shared__ uint32_t wave_cnt[kWaves][kDigits];
     __shared__ uint32_t wave_off[kWaves][kDigits];
-    __shared__ K skey[kRadixRound];
-    __shared__ uint32_t sval[kRadixRound];
+    __shared__ K skey[kRound];
+    __shared__ uint32_t sval[kVals ? kRound : 1];
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
@@ -183,18 +189,18 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter_staged(const K *k
     running[tid] = offsets[(int64_t)tid * nb + blockIdx.x];
     const int64_t base = (int64_t)blockIdx.x * tiles * kRadixBlock;
     const int64_t end = base + tiles * kRadixBlock < n ? base + tiles * kRadixBlock : n;
-    for (int64_t r0 = base; r0 < end; r0 += kRadixRound) {   // uniform across the block
-        const int64_t r1 = r0 + kRadixRound < end ? r0 + kRadixRound : end;
+    for (int64_t r0 = base; r0 < end; r0 += kRound) {   // uniform across the block
+        const int64_t r1 = r0 + kRound < end ? r0 + kRound : end;
         // the round's keys, one per thread per tile, and its digit counts
-        K kreg[kRadixRoundTiles];
-        uint32_t vreg[kRadixRoundTiles];
+        K kreg[kTiles];
+        uint32_t vreg[kTiles];
         cnt[tid] = 0;
         __syncthreads();
 #pragma unroll
-        for (int t = 0; t < kRadixRoundTiles; ++t) {
+        for (int t = 0; t < kTiles; ++t) {
             const int64_t i = r0 + (int64_t)t * kRadixBlock + tid;
             kreg[t] = i < r1 ? keys[i] : (K)0;
-            vreg[t] = i < r1 ? vals[i] : 0u;
+            vreg[t] = kVals && i < r1 ? vals[i] : 0u;
             if (i < r1) atomicAdd(&cnt[(uint32_t)(kreg[t] >> shift) & (kDigits - 1)], 1u);
         }
         __syncthreads();
@@ -207,7 +213,7 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter_staged(const K *k
         __syncthreads();
         // local positions in digit order, tile by tile
 #pragma unroll
-        for (int t = 0; t < kRadixRoundTiles; ++t) {
+        for (int t = 0; t < kTiles; ++t) {
             const int64_t i = r0 + (int64_t)t * kRadixBlock + tid;
             if (r0 + (int64_t)t * kRadixBlock >= r1) break;   // uniform across the block
             const bool valid = i < r1;
@@ -236,7 +242,7 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter_staged(const K *k
             if (valid) {
                 const uint32_t p = wave_off[wave][d] + (uint32_t)rank;
                 skey[p] = kreg[t];
-                sval[p] = vreg[t];
+                if (kVals) sval[p] = vreg[t];
             }
         }
         __syncthreads();
@@ -247,7 +253,7 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter_staged(const K *k
             const uint32_t d = (uint32_t)(key >> shift) & (kDigits - 1);
             const int64_t dst = running[d] + (j - (int64_t)start[d]);
             keys_out[dst] = key;
-            vals_out[dst] = sval[j];
+            if (kVals) vals_out[dst] = sval[j];
         }
         __syncthreads();
         running[tid] += cnt[tid];
@@ -258,7 +264,7 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter_staged(const K *k
 // Per-tile scatter: every tile's keys go straight to their places.  Used
 // below kRadixStagedTiles tiles per block, where the staged kernel's LDS
 // (two blocks per CU) costs more than its coalescing gains.
-template <class K>
+template <class K, bool kVals>
 __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter_tiles(const K *keys, const uint32_t *vals,
                                                                K *keys_out, uint32_t *vals_out,
                                                                int64_t n, int shift,
@@ -279,7 +285,7 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter_tiles(const K *ke
         int64_t i = tile0 + threadIdx.x;
         bool valid = i < n;
         K key = valid ? keys[i] : (K)0;
-        uint32_t val = valid ? vals[i] : 0u;
+        uint32_t val = kVals && valid ? vals[i] : 0u;
         uint32_t d = (uint32_t)(key >> shift) & (kDigits - 1);
         for (int k = 0; k < kWaves; ++k) wave_cnt[k][threadIdx.x] = 0;
         // lanes of this wave holding the same digit
@@ -307,7 +313,7 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter_tiles(const K *ke
         if (valid) {
             int64_t dst = wave_off[wave][d] + rank;
             keys_out[dst] = key;
-            vals_out[dst] = val;
+            if (kVals) vals_out[dst] = val;
         }
         __syncthreads();
     }
@@ -317,6 +323,7 @@ constexpr int64_t kRadixStagedTiles = 32;
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// vals (and vals_alt) may be NULL: the keys alone are sorted.
 template <class K>
 void radix_sort_impl(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, int64_t n, int bits,
                      void *tmp, size_t tmp_bytes, bool *result_in_alt, hipStream_t s) {
@@ -336,12 +343,25 @@ void radix_sort_impl(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, i
         hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)nb), dim3(kRadixBlock), 0, s, kin, n,
                            shift, hist, nb, chunk);
         exclusive_scan_i64(hist, hist, nh, nullptr, scan_tmp, scan_bytes, s);
-        if (tiles >= kRadixStagedTiles)
-            hipLaunchKernelGGL(k_radix_scatter_staged<K>, dim3((unsigned)nb), dim3(kRadixBlock), 0,
-                               s, kin, vin, kout, vout, n, shift, hist, nb, tiles);
-        else
-            hipLaunchKernelGGL(k_radix_scatter_tiles<K>, dim3((unsigned)nb), dim3(kRadixBlock), 0,
-                               s, kin, vin, kout, vout, n, shift, hist, nb, tiles);
+        if (tiles >= kRadixStagedTiles) {
+            if (vals)
+                hipLaunchKernelGGL((k_radix_scatter_staged<K, true>), dim3((unsigned)nb),
+                                   dim3(kRadixBlock), 0, s, kin, vin, kout, vout, n, shift, hist,
+                                   nb, tiles);
+            else
+                hipLaunchKernelGGL((k_radix_scatter_staged<K, false>), dim3((unsigned)nb),
+                                   dim3(kRadixBlock), 0, s, kin, vin, kout, vout, n, shift, hist,
+                                   nb, tiles);
+        } else {
+            if (vals)
+                hipLaunchKernelGGL((k_radix_scatter_tiles<K, true>), dim3((unsigned)nb),
+                                   dim3(kRadixBlock), 0, s, kin, vin, kout, vout, n, shift, hist,
+                                   nb, tiles);
+            else
+                hipLaunchKernelGGL((k_radix_scatter_tiles<K, false>), dim3((unsigned)nb),
+                                   dim3(kRadixBlock), 0, s, kin, vin, kout, vout, n, shift, hist,
+                                   nb, tiles);
+        }
         LOWD_HIP(hipGetLastError());
         std::swap(kin, kout);
         std::swap(vin, vout);

@@ -221,7 +221,8 @@ __host__ __device__ inline double u128_to_double(u128 x) {
     for (int k = 0; k < shift; ++k) r *= 2.0;
     return r;
 }
-// Stable LSD radix sort of (key, value) pairs on bits [0, bits) of the key.
+// Stable LSD radix sort of (key, value) pairs on bits [0, bits) of the key;
+// vals and vals_alt may both be NULL to sort the keys alone.
 void radix_sort_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
                     int64_t n, int bits, void *tmp, size_t tmp_bytes, bool *result_in_alt,
                     hipStream_t s);
@@ -253,9 +254,10 @@ struct Csr {
 void build_incidence(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, Csr &csr,
                      hipStream_t s);
 // The same into row_ptr [n+1] and inc [2m] taken from `ws` (its sort
-// buffers taken after them and released again).
+// buffers taken after them and released again); with `neighbours` each
+// entry holds the edge's other end instead of (edge << 1 | side).
 void build_incidence_ws(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, Arena &ws,
-                        int64_t **row_ptr, uint32_t **inc, hipStream_t s);
+                        int64_t **row_ptr, uint32_t **inc, bool neighbours, hipStream_t s);
 // adj[j] = the other end of the edge of incidence entry j ([2m])
 void build_adjacency(int64_t m, const Csr &csr, const int32_t *src, const int32_t *dst,
                      int32_t *adj, hipStream_t s);
