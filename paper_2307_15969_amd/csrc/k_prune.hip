@@ -167,42 +167,24 @@ __global__ void k_relabel(int32_t n, const int64_t *flag, const int64_t *pos, in
 }
 
 // The edges of H (both ends kept), compacted in their original order, in
-// two passes over tiles of kCompactTile edges: the first marks each edge and
+// two passes over tiles of kCompactTile edges, each a block of 256 threads
+// reading rows of 256 consecutive edges: the first marks each edge and
 // counts a tile's kept edges; after a scan of the tile counts, the second
-// writes a tile's kept edges from its offset, each thread its own run of
-// kCompactItems consecutive edges after the runs of the threads before it.
-constexpr int kCompactBlock = 256, kCompactItems = 16;
-constexpr int64_t kCompactTile = (int64_t)kCompactBlock * kCompactItems;
-
-// exclusive scan of one int per thread over a 256-thread block; *total =
-// the block's sum.  Two barriers.
-__device__ inline int block_scan_int(int v, int *lds, int *total) {
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    int inc = v;
-    for (int d = 1; d < kWave; d <<= 1) {
-        const int y = __shfl_up(inc, d, kWave);
-        if (lane >= d) inc += y;
-    }
-    if (lane == kWave - 1) lds[wave] = inc;
-    __syncthreads();
-    int before = 0, all = 0;
-    for (int k = 0; k < kCompactBlock / kWave; ++k) {
-        before += k < wave ? lds[k] : 0;
-        all += lds[k];
-    }
-    __syncthreads();
-    *total = all;
-    return inc - v + before;
-}
+// writes a tile's kept edges from its offset, ranked within each row by a
+// wave ballot (rows in order, waves in order within a row).
+constexpr int kCompactBlock = 256, kCompactRows = 16;
+constexpr int kCompactWaves = kCompactBlock / kWave;
+constexpr int64_t kCompactTile = (int64_t)kCompactBlock * kCompactRows;
 
 __global__ void __launch_bounds__(kCompactBlock)
     k_edge_keep_tiles(int64_t m, const int32_t *src, const int32_t *dst, const int32_t *stamp,
                       uint8_t *keep, int64_t *tile_count) {
-    __shared__ int lds[kCompactBlock / kWave];
+    __shared__ int lds[kCompactWaves];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int64_t ntiles = (m + kCompactTile - 1) / kCompactTile;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {   // uniform across the block
         int c = 0;
-        for (int k = 0; k < kCompactItems; ++k) {
+        for (int k = 0; k < kCompactRows; ++k) {
             const int64_t e = t * kCompactTile + (int64_t)k * kCompactBlock + threadIdx.x;
             if (e < m) {
                 const bool kp = stamp[src[e]] == 0 && stamp[dst[e]] == 0;
@@ -210,9 +192,15 @@ __global__ void __launch_bounds__(kCompactBlock)
                 c += kp ? 1 : 0;
             }
         }
-        int total;
-        block_scan_int(c, lds, &total);
-        if (threadIdx.x == 0) tile_count[t] = total;
+        for (int d = kWave / 2; d > 0; d >>= 1) c += __shfl_down(c, d, kWave);
+        if (lane == 0) lds[wave] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int total = 0;
+            for (int w = 0; w < kCompactWaves; ++w) total += lds[w];
+            tile_count[t] = total;
+        }
+        __syncthreads();
     }
 }
 
@@ -220,32 +208,38 @@ __global__ void __launch_bounds__(kCompactBlock)
     k_edge_write_tiles(int64_t m, const int32_t *src, const int32_t *dst, const float *w,
                        const uint8_t *keep, const int64_t *tile_offset, const int64_t *npos,
                        int32_t *h_src, int32_t *h_dst, float *h_w, int64_t *edge_map) {
-    __shared__ int lds[kCompactBlock / kWave];
+    __shared__ int cnt[kCompactRows][kCompactWaves];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
     const int64_t ntiles = (m + kCompactTile - 1) / kCompactTile;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {   // uniform across the block
-        const int64_t e0 = t * kCompactTile + (int64_t)threadIdx.x * kCompactItems;
-        uint32_t bits = 0;
-        int c = 0;
-        for (int k = 0; k < kCompactItems; ++k) {
-            const int64_t e = e0 + k;
-            if (e < m && keep[e]) {
-                bits |= 1u << k;
-                ++c;
-            }
+        uint64_t ball[kCompactRows];
+        for (int k = 0; k < kCompactRows; ++k) {
+            const int64_t e = t * kCompactTile + (int64_t)k * kCompactBlock + threadIdx.x;
+            ball[k] = __ballot(e < m && keep[e] != 0);
+            if (lane == 0) cnt[k][wave] = __popcll(ball[k]);
         }
-        int total;
-        int64_t at = tile_offset[t] + block_scan_int(c, lds, &total);
-        for (int k = 0; k < kCompactItems; ++k) {
-            if (!((bits >> k) & 1u)) continue;
-            const int64_t e = e0 + k;
-            if (h_src) {
-                h_src[at] = (int32_t)npos[src[e]];
-                h_dst[at] = (int32_t)npos[dst[e]];
+        __syncthreads();
+        int64_t base = tile_offset[t];
+        for (int k = 0; k < kCompactRows; ++k) {
+            int before = 0, row = 0;
+            for (int v = 0; v < kCompactWaves; ++v) {
+                before += v < wave ? cnt[k][v] : 0;
+                row += cnt[k][v];
             }
-            if (h_w) h_w[at] = w[e];
-            if (edge_map) edge_map[at] = e;
-            ++at;
+            if ((ball[k] >> lane) & 1ull) {
+                const int64_t e = t * kCompactTile + (int64_t)k * kCompactBlock + threadIdx.x;
+                const int64_t at = base + before + __popcll(ball[k] & lt);
+                if (h_src) {
+                    h_src[at] = (int32_t)npos[src[e]];
+                    h_dst[at] = (int32_t)npos[dst[e]];
+                }
+                if (h_w) h_w[at] = w[e];
+                if (edge_map) edge_map[at] = e;
+            }
+            base += row;
         }
+        __syncthreads();
     }
 }
 

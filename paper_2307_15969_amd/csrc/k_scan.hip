@@ -151,18 +151,15 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_hist(const K *keys, int64
     blockhist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
-// The scatter stages rounds of keys in LDS in digit order, then writes every
-// digit's run of the round to consecutive addresses: a tile's 256 keys
-// written straight out land on up to 256 scattered lines.  A round is 16
-// tiles (4,096 keys) of 12-byte pairs, 32 tiles of 8-byte ones (4-byte keys
-// with values, or 8-byte keys alone), so that a digit's run averages a full
-// 128-byte line or more (about 77 KB of LDS, two blocks per CU).  Ranks are
-// taken tile by tile in key order (wave ballots for equal digits, waves in
-// order), so the permutation is the stable one.
-template <class K, bool kVals>
-constexpr int radix_round_tiles() {
-    return sizeof(K) + (kVals ? sizeof(uint32_t) : 0) <= 8 ? 32 : 16;
-}
+// The scatter stages rounds of 16 tiles (4,096 keys) in LDS in digit
+// order, then writes every digit's run of the round to consecutive
+// addresses: a tile's 256 keys written straight out land on up to 256
+// scattered lines, a round's runs average 16 keys per digit.  (Rounds of 32
+// tiles, whose runs fill whole lines for 4-byte keys, measured slower: at
+// 77 KB of LDS only two blocks fit a CU.)  Ranks are taken tile by tile in
+// key order (wave ballots for equal digits, waves in order), so the
+// permutation is the stable one.
+constexpr int kRadixRoundTiles = 16;
 
 template <class K, bool kVals>
 __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter_staged(const K *keys, const uint32_t *vals,
@@ -171,7 +168,7 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter_staged(const K *k
                                                                const int64_t *offsets,
                                                                int64_t nb, int64_t tiles) {
     constexpr int kWaves = kRadixBlock / kWave;
-    constexpr int kTiles = radix_round_tiles<K, kVals>();
+    constexpr int kTiles = kRadixRoundTiles;
     constexpr int kRound = kTiles * kRadixBlock;   // keys staged at a time
     __shared__ int64_t running[kDigits];         // next global position of each digit
     __shared__ int64_t scan_lds[kWave + 1];
