@@ -108,6 +108,19 @@ __global__ void k_split(int64_t c, const int32_t *cand, const int64_t *rm, const
     }
 }
 
+// stamp[v]: 0 for an alive node, -(slot + 1) for an alive hub (below), r > 0
+// once removed in round r.
+// The kHubs highest-degree nodes (the tail of the degree-bucketed order) are
+// hubs: the removal kernel counts their lost edges per workgroup in LDS and
+// adds each count with one atomic, where the rounds' removed nodes would
+// otherwise send one atomic per edge to the same few degree counters.
+constexpr int kHubs = 4096;
+__global__ void k_mark_hubs(int32_t k, const int32_t *hubs, int32_t *stamp) {
+    for (int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x); i < k;
+         i += (int32_t)(gridDim.x * blockDim.x))
+        stamp[hubs[i]] = -(i + 1);
+}
+
 __global__ void k_stamp(int64_t k, const int32_t *list, int32_t *stamp, int32_t round) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -122,39 +135,62 @@ __global__ void k_stamp(int64_t k, const int32_t *list, int32_t *stamp, int32_t 
 // wave after the loop, where the whole wave has reconverged, and added with
 // one atomic per wave.
 constexpr int kRemoveBlock = 256;
+constexpr int64_t kRemoveGrid = 2048;
 template <int G>
 __global__ void __launch_bounds__(kRemoveBlock) k_remove_edges(int64_t k, const int32_t *removed,
                                                                const int64_t *row_ptr,
                                                                const uint32_t *nbr,
                                                                const int32_t *stamp,
                                                                int32_t round, int32_t *deg,
-                                                               unsigned long long *gone) {
+                                                               unsigned long long *gone,
+                                                               const int32_t *hubs,
+                                                               int32_t nhubs) {
     constexpr int kGroups = kRemoveBlock / G;
+    __shared__ int32_t hub_lost[kHubs];
+    for (int i = threadIdx.x; i < kHubs; i += kRemoveBlock) hub_lost[i] = 0;
+    __syncthreads();
     const int grp = threadIdx.x / G, lane = threadIdx.x % G;
     unsigned long long cnt = 0;
     for (int64_t i = (int64_t)blockIdx.x * kGroups + grp; i < k;
          i += (int64_t)gridDim.x * kGroups) {
         const int32_t u = removed[i];
         const int64_t end = row_ptr[u + 1];
-        for (int64_t j = row_ptr[u] + lane; j < end; j += G) {
-            const int32_t v = (int32_t)nbr[j];
-            const int32_t sv = stamp[v];
-            if (sv == 0) {
-                atomicSub(&deg[v], 1);
-                ++cnt;
-            } else if (sv == round && u < v) {
-                ++cnt;
+        // four entries a lane at a time: their loads, then their stamps,
+        // are independent and in flight together
+        constexpr int kU = 4;
+        for (int64_t j = row_ptr[u] + lane; j < end; j += kU * G) {
+            int32_t v[kU], sv[kU];
+#pragma unroll
+            for (int q = 0; q < kU; ++q) v[q] = j + q * G < end ? (int32_t)nbr[j + q * G] : -1;
+#pragma unroll
+            for (int q = 0; q < kU; ++q) sv[q] = v[q] >= 0 ? stamp[v[q]] : round + 1;
+#pragma unroll
+            for (int q = 0; q < kU; ++q) {
+                if (sv[q] == 0) {
+                    atomicSub(&deg[v[q]], 1);
+                    ++cnt;
+                } else if (sv[q] < 0) {
+                    atomicAdd(&hub_lost[-sv[q] - 1], 1);
+                    ++cnt;
+                } else if (sv[q] == round && u < v[q]) {
+                    ++cnt;
+                }
             }
         }
     }
     for (int o = kWave / 2; o > 0; o >>= 1) cnt += __shfl_down(cnt, o, kWave);
     if ((threadIdx.x & (kWave - 1)) == 0 && cnt) atomicAdd(gone, cnt);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nhubs; i += kRemoveBlock) {
+        const int32_t c = hub_lost[i];
+        if (c) atomicSub(&deg[hubs[i]], c);
+    }
 }
 
 __global__ void k_keep_flags(int32_t n, const int32_t *stamp, uint8_t *node_keep, int64_t *flag) {
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
          u += (int64_t)gridDim.x * blockDim.x) {
-        bool k = stamp[u] == 0;
+        bool k = stamp[u] <= 0;
         node_keep[u] = k ? 1 : 0;
         flag[u] = k ? 1 : 0;
     }
@@ -187,7 +223,7 @@ __global__ void __launch_bounds__(kCompactBlock)
         for (int k = 0; k < kCompactRows; ++k) {
             const int64_t e = t * kCompactTile + (int64_t)k * kCompactBlock + threadIdx.x;
             if (e < m) {
-                const bool kp = stamp[src[e]] == 0 && stamp[dst[e]] == 0;
+                const bool kp = stamp[src[e]] <= 0 && stamp[dst[e]] <= 0;
                 keep[e] = kp ? 1 : 0;
                 c += kp ? 1 : 0;
             }
@@ -456,6 +492,11 @@ PruneResult run_prune_ws(int32_t n, int64_t m, const int32_t *src, const int32_t
     if (n > 0)
         hipLaunchKernelGGL(k_bucket_scatter, dim3((unsigned)((n + kScatterChunk - 1) / kScatterChunk)),
                            dim3(kScatterBlock), 0, s, n, deg, bin_start, cursor, by_deg);
+    const int32_t nhubs = n < kHubs ? n : kHubs;
+    const int32_t *hubs = by_deg + (n - nhubs);   // the highest degrees
+    if (nhubs > 0)
+        hipLaunchKernelGGL(k_mark_hubs, dim3(grid_for(nhubs, 256)), dim3(256), 0, s, nhubs, hubs,
+                           stamp);
     std::array<int64_t, kBins> hstart;
     LOWD_HIP(hipMemcpyAsync(hstart.data(), bin_start, kBins * sizeof(int64_t),
                             hipMemcpyDeviceToHost, s));
@@ -497,18 +538,21 @@ PruneResult run_prune_ws(int32_t n, int64_t m, const int32_t *src, const int32_t
         LOWD_HIP(hipMemsetAsync(gone, 0, sizeof(unsigned long long), s));
         const unsigned gr = grid_for(nrm, 256);
         hipLaunchKernelGGL(k_stamp, dim3(gr), dim3(256), 0, s, nrm, rm_list, stamp, round);
+        // at most kRemoveGrid workgroups, each over many removed nodes, so
+        // that the hubs' LDS counts are added with few atomics
         if (nrm >= (1 << 18))
-            hipLaunchKernelGGL(k_remove_edges<1>, dim3(grid_for(nrm, kRemoveBlock)),
+            hipLaunchKernelGGL(k_remove_edges<1>, dim3(grid_for(nrm, kRemoveBlock, kRemoveGrid)),
                                dim3(kRemoveBlock), 0, s, nrm, rm_list, csr.row_ptr, csr.inc,
-                               stamp, round, deg, gone);
+                               stamp, round, deg, gone, hubs, nhubs);
         else if (nrm >= (1 << 12))
-            hipLaunchKernelGGL(k_remove_edges<kWave>, dim3(grid_for(nrm, kRemoveBlock / kWave)),
+            hipLaunchKernelGGL(k_remove_edges<kWave>,
+                               dim3(grid_for(nrm, kRemoveBlock / kWave, kRemoveGrid)),
                                dim3(kRemoveBlock), 0, s, nrm, rm_list, csr.row_ptr, csr.inc,
-                               stamp, round, deg, gone);
+                               stamp, round, deg, gone, hubs, nhubs);
         else
-            hipLaunchKernelGGL(k_remove_edges<kRemoveBlock>, dim3(grid_for(nrm, 1)),
+            hipLaunchKernelGGL(k_remove_edges<kRemoveBlock>, dim3(grid_for(nrm, 1, kRemoveGrid)),
                                dim3(kRemoveBlock), 0, s, nrm, rm_list, csr.row_ptr, csr.inc,
-                               stamp, round, deg, gone);
+                               stamp, round, deg, gone, hubs, nhubs);
         LOWD_HIP(hipGetLastError());
         unsigned long long g = 0;
         LOWD_HIP(hipMemcpyAsync(&g, gone, sizeof(g), hipMemcpyDeviceToHost, s));
