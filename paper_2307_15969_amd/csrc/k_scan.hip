@@ -134,16 +134,34 @@ inline int64_t radix_tiles(int64_t n) {
     return t < 1 ? 1 : (t > kRadixMaxTiles ? kRadixMaxTiles : t);
 }
 
+// A block counts the digits of its chunk (a multiple of 256 keys, so every
+// 16-byte group of keys is aligned): 16 bytes of keys a lane per load, two
+// loads in flight, the rest one key at a time.
 template <class K>
 __global__ void __launch_bounds__(kRadixBlock) k_radix_hist(const K *keys, int64_t n, int shift,
                                                             int64_t *blockhist, int64_t nb,
                                                             int64_t chunk) {
+    constexpr int kV = 16 / sizeof(K);   // keys per 16-byte load
+    struct alignas(16) Vec {
+        K k[kV];
+    };
     __shared__ uint32_t h[kDigits];
     h[threadIdx.x] = 0;
     __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * chunk;
-    int64_t end = base + chunk < n ? base + chunk : n;
-    for (int64_t i = base + threadIdx.x; i < end; i += kRadixBlock) {
+    const int64_t base = (int64_t)blockIdx.x * chunk;
+    const int64_t end = base + chunk < n ? base + chunk : n;
+    constexpr int64_t kStep = 2 * kV * kRadixBlock;
+    const int64_t vend = base + (end - base) / kStep * kStep;
+    for (int64_t i = base + (int64_t)threadIdx.x * kV; i < vend; i += kStep) {
+        const Vec a = *(const Vec *)(keys + i);
+        const Vec b = *(const Vec *)(keys + i + kV * kRadixBlock);
+#pragma unroll
+        for (int q = 0; q < kV; ++q) {
+            atomicAdd(&h[(uint32_t)(a.k[q] >> shift) & (kDigits - 1)], 1u);
+            atomicAdd(&h[(uint32_t)(b.k[q] >> shift) & (kDigits - 1)], 1u);
+        }
+    }
+    for (int64_t i = vend + threadIdx.x; i < end; i += kRadixBlock) {
         uint32_t d = (uint32_t)(keys[i] >> shift) & (kDigits - 1);
         atomicAdd(&h[d], 1u);
     }
