@@ -97,7 +97,22 @@ def cpu_baseline(n, src, dst, w, seconds: float = 12.0) -> dict:
             break
     return {"value": m * sweeps / el, "unit": "edge-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{sweeps} full passes of the edge loop over the same {m}-edge graph, "
-                      f"edge-index order ({el:.1f} s)"}
+                      f"edge-index order ({el:.1f} s)",
+            "sweep_s": el / sweeps, "host": host_cpu()}
+
+
+def host_cpu() -> str:
+    """The host's CPU model and logical core count (for the CPU baseline)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {os.cpu_count()} logical cores"
 
 
 WORKLOADS = {
@@ -305,6 +320,9 @@ def run_rmat24(args, torch, lowd, synth):
         h_src, h_dst = hs.cpu().numpy(), hd.cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(n_h, h_src, h_dst, None, args.cpu_seconds)
         out["cpu_baseline"]["sample"] += " (the pruned graph H)"
+        # as many oracle passes as the GPU solve made sweeps
+        out["cpu_baseline"]["solve_sweeps_s"] = (out["cpu_baseline"]["sweep_s"] *
+                                                f64["sweeps_to_1e-6"])
     return out
 
 
