@@ -195,44 +195,161 @@ __global__ void k_any_adjacent_equal(int64_t m, const uint64_t *keys, unsigned i
         if (keys[i] == keys[i - 1]) *any = 1u;
 }
 
+// ---- repeated pairs by hash buckets ----
+// The packed pair (2 nb <= 48 bits) goes to one of 2^bits buckets by a hash;
+// the keys (pair << bits | bucket) sorted on their low `bits` bits put every
+// bucket's pairs together (a repeated pair twice in one bucket), and one
+// workgroup per bucket inserts them into a hash set in LDS.  A bucket too
+// large for the set sends the check to the full sort instead.
+constexpr int kRepeatBlock = 256;
+constexpr int kRepeatCap = 5120;                 // pairs a bucket may hold
+constexpr int kRepeatSlots = 2 * kRepeatCap;     // LDS set, half full at most
+// 80 KB: two workgroups a CU
+constexpr size_t kRepeatLds = (size_t)kRepeatSlots * sizeof(unsigned long long);
+constexpr unsigned long long kRepeatEmpty = ~0ull;
+
+// SplitMix64's output mix (Steele, Lea and Flood, OOPSLA 2014) as the hash
+__device__ inline uint64_t pair_mix(uint64_t x) {
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+__global__ void k_bucketed_pair_keys(int64_t m, const int32_t *src, const int32_t *dst, int nb,
+                                     int bits, uint64_t *keys) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t a = (uint32_t)src[e], b = (uint32_t)dst[e];
+        const uint64_t pair = a < b ? (a << nb) | b : (b << nb) | a;
+        keys[e] = (pair << bits) | (pair_mix(pair) >> (64 - bits));
+    }
+}
+
+// start[b] = first position of bucket b in the keys sorted by bucket (b in
+// [0, 2^bits]; start[2^bits] = m)
+__global__ void k_bucket_starts(const uint64_t *keys, int64_t m, int bits, int64_t *start) {
+    const int64_t nbk = (int64_t)1 << bits;
+    const uint64_t mask = (uint64_t)nbk - 1;
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b <= nbk;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = 0, hi = m;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((int64_t)(keys[mid] & mask) < b) lo = mid + 1;
+            else hi = mid;
+        }
+        start[b] = lo;
+    }
+}
+
+// flags[0] = 1 if a pair repeats, flags[1] = 1 if a bucket exceeded the set
+__global__ void __launch_bounds__(kRepeatBlock)
+    k_bucket_repeats(const uint64_t *keys, const int64_t *start, int bits, unsigned int *flags) {
+    extern __shared__ unsigned long long set[];
+    const int64_t nbk = (int64_t)1 << bits;
+    for (int64_t b = blockIdx.x; b < nbk; b += gridDim.x) {   // uniform across the block
+        const int64_t s0 = start[b], s1 = start[b + 1];
+        if (s1 - s0 < 2) continue;
+        if (s1 - s0 > kRepeatCap) {
+            if (threadIdx.x == 0) flags[1] = 1u;
+            continue;
+        }
+        for (int i = threadIdx.x; i < kRepeatSlots; i += kRepeatBlock) set[i] = kRepeatEmpty;
+        __syncthreads();
+        for (int64_t i = s0 + threadIdx.x; i < s1; i += kRepeatBlock) {
+            const unsigned long long pair = keys[i] >> bits;
+            // a slot from the low hash bits (the bucket took the top ones)
+            uint32_t h = (uint32_t)(((uint64_t)(uint32_t)pair_mix(pair) * kRepeatSlots) >> 32);
+            // the set is at most half full, so a free slot is always found
+            for (;;) {
+                const unsigned long long old = atomicCAS(&set[h], kRepeatEmpty, pair);
+                if (old == kRepeatEmpty) break;
+                if (old == pair) {
+                    flags[0] = 1u;
+                    break;
+                }
+                h = h + 1 == (uint32_t)kRepeatSlots ? 0u : h + 1;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 // Index of the later edge of the first repeated unordered pair found, or -1.
+// Whether any pair repeats is decided first, by hash buckets (a radix sort
+// of 8 to 24 bucket bits) or, where the ids are too wide for them or a
+// bucket is too large, by a sort of the packed pairs; only when a pair
+// repeats does an indexed sort of the pairs name the edge.
 int64_t find_duplicate_pair_ws(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
                                Arena &ws, hipStream_t s) {
     if (m < 2) return -1;
+    int nb = 1;
+    while (nb < 32 && ((int64_t)1 << nb) < (int64_t)n) ++nb;
+    // bucket bits: buckets of at most about 2,048 pairs on average (well
+    // within the set's capacity), at least 8 bits, at most 24 and what the
+    // key leaves beside the pair
+    int bits = 8;
+    while (bits < 24 && ((int64_t)2048 << bits) < m) ++bits;
+    bits = std::min(bits, 64 - 2 * nb);
+    const bool bucketed = bits >= 8;
     const size_t mk = ws.mark();
     uint64_t *k0 = ws.take<uint64_t>((size_t)m), *k1 = ws.take<uint64_t>((size_t)m);
     uint32_t *v0 = ws.take<uint32_t>((size_t)m), *v1 = ws.take<uint32_t>((size_t)m);
     const size_t tmp_bytes = radix_sort_tmp_bytes(m);
     char *tmp = ws.take<char>(tmp_bytes);
     unsigned long long *bad = ws.take<unsigned long long>(1);
-    unsigned int *any = ws.take<unsigned int>(1);
+    unsigned int *flags = ws.take<unsigned int>(2);
+    int64_t *bstart = bucketed ? ws.take<int64_t>(((size_t)1 << bits) + 1) : nullptr;
     unsigned long long r = ~0ull;
     if (ws.base) {
-        int nb = 1;
-        while (nb < 32 && ((int64_t)1 << nb) < (int64_t)n) ++nb;
-        // Whether any pair repeats: the packed keys alone, sorted (2 nb bits).
-        // Only then is the indexed sort below run, to name the edge.
-        const unsigned int zero = 0u;
-        LOWD_HIP(hipMemcpyAsync(any, &zero, sizeof(zero), hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_packed_pair_keys, dim3(grid_for(m, 256)), dim3(256), 0, s, m, src,
-                           dst, nb, k0);
-        bool alt = false;
-        radix_sort_u64(k0, nullptr, k1, nullptr, m, 2 * nb, tmp, tmp_bytes, &alt, s);
-        hipLaunchKernelGGL(k_any_adjacent_equal, dim3(grid_for(m, 256)), dim3(256), 0, s, m,
-                           alt ? k1 : k0, any);
-        LOWD_HIP(hipGetLastError());
-        unsigned int found = 0u;
-        LOWD_HIP(hipMemcpyAsync(&found, any, sizeof(found), hipMemcpyDeviceToHost, s));
-        LOWD_HIP(hipStreamSynchronize(s));
-        if (!found) {
+        const unsigned int zero[2] = {0u, 0u};
+        unsigned int found[2] = {0u, 1u};
+        if (bucketed) {
+            static const bool lds_set = [] {
+                LOWD_HIP(hipFuncSetAttribute((const void *)k_bucket_repeats,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)kRepeatLds));
+                return true;
+            }();
+            (void)lds_set;
+            LOWD_HIP(hipMemcpyAsync(flags, zero, sizeof(zero), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_bucketed_pair_keys, dim3(grid_for(m, 256)), dim3(256), 0, s, m,
+                               src, dst, nb, bits, k0);
+            bool alt = false;
+            radix_sort_u64(k0, nullptr, k1, nullptr, m, bits, tmp, tmp_bytes, &alt, s);
+            const uint64_t *keys = alt ? k1 : k0;
+            const int64_t nbk = (int64_t)1 << bits;
+            hipLaunchKernelGGL(k_bucket_starts, dim3(grid_for(nbk + 1, 256)), dim3(256), 0, s,
+                               keys, m, bits, bstart);
+            hipLaunchKernelGGL(k_bucket_repeats, dim3(grid_for(nbk, 1, 8192)), dim3(kRepeatBlock),
+                               kRepeatLds, s, keys, bstart, bits, flags);
+            LOWD_HIP(hipGetLastError());
+            LOWD_HIP(hipMemcpyAsync(found, flags, sizeof(found), hipMemcpyDeviceToHost, s));
+            LOWD_HIP(hipStreamSynchronize(s));
+        }
+        if (found[1]) {
+            // the packed keys alone, sorted (2 nb bits)
+            LOWD_HIP(hipMemcpyAsync(flags, zero, sizeof(zero), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_packed_pair_keys, dim3(grid_for(m, 256)), dim3(256), 0, s, m,
+                               src, dst, nb, k0);
+            bool alt = false;
+            radix_sort_u64(k0, nullptr, k1, nullptr, m, 2 * nb, tmp, tmp_bytes, &alt, s);
+            hipLaunchKernelGGL(k_any_adjacent_equal, dim3(grid_for(m, 256)), dim3(256), 0, s, m,
+                               alt ? k1 : k0, flags);
+            LOWD_HIP(hipGetLastError());
+            LOWD_HIP(hipMemcpyAsync(found, flags, sizeof(unsigned int), hipMemcpyDeviceToHost,
+                                    s));
+            LOWD_HIP(hipStreamSynchronize(s));
+        }
+        if (!found[0]) {
             ws.release(mk);
             return -1;
         }
         hipLaunchKernelGGL(k_pair_keys, dim3(grid_for(m, 256)), dim3(256), 0, s, m, src, dst, k0,
                            v0);
-        alt = false;
+        bool alt = false;
         radix_sort_u64(k0, v0, k1, v1, m, 32 + nb, tmp, tmp_bytes, &alt, s);
         unsigned long long init = ~0ull;
         LOWD_HIP(hipMemcpyAsync(bad, &init, sizeof(init), hipMemcpyHostToDevice, s));

@@ -479,6 +479,41 @@ def test_repeated_pair_in_reverse_orientation_is_rejected():
     assert ei.value.status == -2
 
 
+@pytest.mark.parametrize("copies", [2, 9000])
+def test_repeated_pair_is_named_by_its_first_repeat(copies):
+    """A pair repeated among many distinct edges is rejected, and the message
+    names the first edge whose pair appeared before.  9,000 copies of one
+    pair overflow its hash bucket, so the check falls back to the full sort
+    of the pairs (a0: no repeated unordered pair)."""
+    rng = np.random.default_rng(copies)
+    n = 1 << 16
+    a = rng.integers(0, n, 600000)
+    b = rng.integers(0, n, 600000)
+    keep = a != b
+    lo, hi = np.minimum(a, b)[keep], np.maximum(a, b)[keep]
+    key = np.unique(lo.astype(np.int64) * n + hi)
+    src, dst = (key // n).astype(np.int32), (key % n).astype(np.int32)
+    perm = rng.permutation(src.size)
+    src, dst = src[perm], dst[perm]
+    rep = np.full(copies, 7, np.int32), np.full(copies, 11, np.int32)
+    pos = src.size // 3
+    src = np.concatenate([src[:pos], rep[0], src[pos:]]).astype(np.int32)
+    dst = np.concatenate([dst[:pos], rep[1], dst[pos:]]).astype(np.int32)
+    # flip the orientation of every other copy
+    dst[pos + 1:pos + copies:2], src[pos + 1:pos + copies:2] = 7, 11
+    pair = np.minimum(src, dst).astype(np.int64) * n + np.maximum(src, dst)
+    _, first = np.unique(pair, return_index=True)
+    seen = np.zeros(src.size, bool)
+    seen[first] = True
+    expect = int(np.flatnonzero(~seen)[0])
+    log(f"m={src.size} copies={copies} first repeat at {expect}")
+    for call in (lambda: lowd.Solver(n, src, dst), lambda: lowd.prune(n, src, dst)):
+        with pytest.raises(lowd.LowdError) as ei:
+            call()
+        assert ei.value.status == -2
+        assert f"at index {expect}:" in str(ei.value), str(ei.value)
+
+
 # ------------------------------------------------- full-size workload ----
 def test_chunglu_1m_10m_fp64_is_bit_exact():
     """The benchmark workload at full size (Chung-Lu n=1M, ~10M edges,
