@@ -174,9 +174,13 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_hist(const K *keys, int64
 // addresses: a tile's 256 keys written straight out land on up to 256
 // scattered lines, a round's runs average 16 keys per digit.  (Rounds of 32
 // tiles, whose runs fill whole lines for 4-byte keys, measured slower: at
-// 77 KB of LDS only two blocks fit a CU.)  Ranks are taken tile by tile in
-// key order (wave ballots for equal digits, waves in order), so the
-// permutation is the stable one.
+// 77 KB of LDS only two blocks fit a CU.)  Within a round wave w owns the
+// contiguous quarter [w R/4, (w+1) R/4) of the keys: it counts its digits
+// in a row of LDS counters of its own, one scan over (digit, wave) in that
+// order gives every wave the first position of each digit, and the wave
+// places its keys chunk by chunk in key order, ranking equal digits among
+// its lanes with eight ballots and moving its own counters on.  Keys keep
+// their order within a digit, so the permutation is the stable one.
 constexpr int kRadixRoundTiles = 16;
 
 template <class K, bool kVals>
@@ -186,15 +190,13 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter_staged(const K *k
                                                                const int64_t *offsets,
                                                                int64_t nb, int64_t tiles) {
     constexpr int kWaves = kRadixBlock / kWave;
-    constexpr int kTiles = kRadixRoundTiles;
-    constexpr int kRound = kTiles * kRadixBlock;   // keys staged at a time
+    constexpr int kRound = kRadixRoundTiles * kRadixBlock;   // keys staged at a time
+    constexpr int kChunks = kRound / kRadixBlock;             // 64-key chunks a wave owns
     __shared__ int64_t running[kDigits];         // next global position of each digit
     __shared__ int64_t scan_lds[kWave + 1];
     __shared__ uint32_t cnt[kDigits];            // this round's keys per digit
     __shared__ uint32_t start[kDigits];          // their first local position
-    __shared__ uint32_t next[kDigits];           // next free local position
-    __shared__ uint32_t wave_cnt[kWaves][kDigits];
-    __shared__ uint32_t wave_off[kWaves][kDigits];
+    __shared__ uint32_t wpos[kWaves][kDigits];   // a wave's digit counts, then its next positions
     __shared__ K skey[kRound];
     __shared__ uint32_t sval[kVals ? kRound : 1];
     const int tid = threadIdx.x;
@@ -206,34 +208,46 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter_staged(const K *k
     const int64_t end = base + tiles * kRadixBlock < n ? base + tiles * kRadixBlock : n;
     for (int64_t r0 = base; r0 < end; r0 += kRound) {   // uniform across the block
         const int64_t r1 = r0 + kRound < end ? r0 + kRound : end;
-        // the round's keys, one per thread per tile, and its digit counts
-        K kreg[kTiles];
-        uint32_t vreg[kTiles];
-        cnt[tid] = 0;
-        __syncthreads();
+        // this wave's quarter of the round, 64 keys a chunk in key order
+        const int64_t lo = r0 + (int64_t)wave * (kRound / kWaves);
+        const int64_t hi = lo + kRound / kWaves < r1 ? lo + kRound / kWaves : r1;
+        K kreg[kChunks];
+        uint32_t vreg[kChunks];
+        for (int d = lane; d < kDigits; d += kWave) wpos[wave][d] = 0u;
 #pragma unroll
-        for (int t = 0; t < kTiles; ++t) {
-            const int64_t i = r0 + (int64_t)t * kRadixBlock + tid;
-            kreg[t] = i < r1 ? keys[i] : (K)0;
-            vreg[t] = kVals && i < r1 ? vals[i] : 0u;
-            if (i < r1) atomicAdd(&cnt[(uint32_t)(kreg[t] >> shift) & (kDigits - 1)], 1u);
+        for (int c = 0; c < kChunks; ++c) {
+            const int64_t i = lo + (int64_t)c * kWave + lane;
+            kreg[c] = i < hi ? keys[i] : (K)0;
+            vreg[c] = kVals && i < hi ? vals[i] : 0u;
         }
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c)
+            if (lo + (int64_t)c * kWave + lane < hi)
+                atomicAdd(&wpos[wave][(uint32_t)(kreg[c] >> shift) & (kDigits - 1)], 1u);
         __syncthreads();
-        {
+        {   // digit totals, their scan, and each wave's first position per digit
+            uint32_t t = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) t += wpos[w][tid];
+            cnt[tid] = t;
             int64_t tot;
-            const int64_t st = block_exclusive_scan<int64_t>((int64_t)cnt[tid], scan_lds, &tot);
-            start[tid] = (uint32_t)st;
-            next[tid] = (uint32_t)st;
+            const uint32_t st = (uint32_t)block_exclusive_scan<int64_t>((int64_t)t, scan_lds, &tot);
+            start[tid] = st;
+            uint32_t run = st;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                const uint32_t c = wpos[w][tid];
+                wpos[w][tid] = run;
+                run += c;
+            }
         }
         __syncthreads();
-        // local positions in digit order, tile by tile
+        // each wave places its keys in order; its counters are its own
 #pragma unroll
-        for (int t = 0; t < kTiles; ++t) {
-            const int64_t i = r0 + (int64_t)t * kRadixBlock + tid;
-            if (r0 + (int64_t)t * kRadixBlock >= r1) break;   // uniform across the block
-            const bool valid = i < r1;
-            const uint32_t d = (uint32_t)(kreg[t] >> shift) & (kDigits - 1);
-            for (int k = 0; k < kWaves; ++k) wave_cnt[k][tid] = 0;
+        for (int c = 0; c < kChunks; ++c) {
+            if (lo + (int64_t)c * kWave >= hi) break;   // uniform across the wave
+            const bool valid = lo + (int64_t)c * kWave + lane < hi;
+            const uint32_t d = (uint32_t)(kreg[c] >> shift) & (kDigits - 1);
             uint64_t same = __ballot(valid);
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
@@ -241,24 +255,16 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter_staged(const K *k
                 const uint64_t ones = __ballot(valid && bit);
                 same &= bit ? ones : ~ones;
             }
-            const int rank = __popcll(same & lt_mask);
-            __syncthreads();
-            if (valid && rank == 0) wave_cnt[wave][d] = __popcll(same);
-            __syncthreads();
-            {   // one thread per digit: each wave's first position, in wave order
-                uint32_t r = next[tid];
-                for (int k = 0; k < kWaves; ++k) {
-                    wave_off[k][tid] = r;
-                    r += wave_cnt[k][tid];
-                }
-                next[tid] = r;
-            }
-            __syncthreads();
+            const uint32_t rank = (uint32_t)__popcll(same & lt_mask);
+            const uint32_t p = wpos[wave][d];
             if (valid) {
-                const uint32_t p = wave_off[wave][d] + (uint32_t)rank;
-                skey[p] = kreg[t];
-                if (kVals) sval[p] = vreg[t];
+                skey[p + rank] = kreg[c];
+                if (kVals) sval[p + rank] = vreg[c];
             }
+            // every lane has read its digit's position (one instruction for
+            // the wave, a wave's LDS accesses in order) before the first lane
+            // of each digit moves it on
+            if (valid && rank == 0) wpos[wave][d] = p + (uint32_t)__popcll(same);
         }
         __syncthreads();
         // every digit's run to consecutive global positions
