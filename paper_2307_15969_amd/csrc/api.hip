@@ -81,7 +81,8 @@ static void validate_graph_ws(int32_t n, int64_t m, const int32_t *src, const in
     int64_t b = -1;
     if (ws.base) {
         launch_validate(n, m, src, dst, w, bad, s);
-        LOWD_HIP(hipMemcpy(&b, bad, sizeof(b), hipMemcpyDeviceToHost));
+        LOWD_HIP(hipMemcpyAsync(&b, bad, sizeof(b), hipMemcpyDeviceToHost, s));
+        LOWD_HIP(hipStreamSynchronize(s));
     }
     const bool in_range = (uint64_t)b == ~0ull;
     if (in_range || !ws.base) b = find_duplicate_pair_ws(n, m, src, dst, ws, s);
@@ -89,9 +90,10 @@ static void validate_graph_ws(int32_t n, int64_t m, const int32_t *src, const in
     if (b >= 0 && (uint64_t)b != ~0ull) {
         int32_t a = 0, c = 0;
         float x = 1.0f;
-        LOWD_HIP(hipMemcpy(&a, src + b, 4, hipMemcpyDeviceToHost));
-        LOWD_HIP(hipMemcpy(&c, dst + b, 4, hipMemcpyDeviceToHost));
-        if (w) LOWD_HIP(hipMemcpy(&x, w + b, 4, hipMemcpyDeviceToHost));
+        LOWD_HIP(hipMemcpyAsync(&a, src + b, 4, hipMemcpyDeviceToHost, s));
+        LOWD_HIP(hipMemcpyAsync(&c, dst + b, 4, hipMemcpyDeviceToHost, s));
+        if (w) LOWD_HIP(hipMemcpyAsync(&x, w + b, 4, hipMemcpyDeviceToHost, s));
+        LOWD_HIP(hipStreamSynchronize(s));
         fail(LOWD_E_GRAPH, std::string(in_range ? "repeated pair" : "invalid edge") +
                                " at index " + std::to_string(b) + ": (" + std::to_string(a) +
                                ", " + std::to_string(c) + ") weight " + std::to_string(x) +
@@ -825,8 +827,14 @@ lowd_status lowd_prune(int32_t n, int64_t m, const int32_t *src, const int32_t *
         if (!node_keep) fail(LOWD_E_ARG, "node_keep is NULL");
         if ((h_src == nullptr) != (h_dst == nullptr)) fail(LOWD_E_ARG, "h_src/h_dst: both or none");
         hipStream_t s = (hipStream_t)stream;
-        validate_graph(n, m, src, dst, nullptr, s);
-        PruneResult r = run_prune(n, m, src, dst, node_keep, relabel, h_src, h_dst, edge_map, s);
+        // one allocation serves the check and then the prune
+        const size_t need = std::max(validate_ws_bytes(n, m, nullptr),
+                                     prune_ws_bytes(n, m, h_src != nullptr, edge_map != nullptr));
+        DBuf<char> buf(need);
+        Arena ws(buf.p, buf.bytes());
+        validate_graph_ws(n, m, src, dst, nullptr, ws, s);
+        PruneResult r =
+            run_prune_ws(n, m, src, dst, node_keep, relabel, h_src, h_dst, edge_map, ws, s);
         if (rounds) *rounds = r.rounds;
         if (n_h) *n_h = r.n_h;
         if (m_h) *m_h = r.m_h;
@@ -925,8 +933,10 @@ lowd_status lowd_greedy_peel(int32_t n, int64_t m, const int32_t *src, const int
         const int64_t bi = greedy_peel(n, m, src, dst, order, rem_m, in_set,
                                        (int64_t)32 << 30, s);
         int64_t mm = m;
-        if (bi > 0)
-            LOWD_HIP(hipMemcpy(&mm, rem_m + (bi - 1), sizeof(mm), hipMemcpyDeviceToHost));
+        if (bi > 0) {
+            LOWD_HIP(hipMemcpyAsync(&mm, rem_m + (bi - 1), sizeof(mm), hipMemcpyDeviceToHost, s));
+            LOWD_HIP(hipStreamSynchronize(s));
+        }
         if (num) *num = mm;
         if (den) *den = (int64_t)n - bi;
     });
@@ -1422,9 +1432,11 @@ lowd_status lowd_batch_retire(lowd_batch *b, const int64_t *num, const int64_t *
         if (active_edges) *active_edges = ae;
         b->last_active = a;
         std::vector<int32_t> act((size_t)a);
-        if (a > 0)
-            LOWD_HIP(hipMemcpy(act.data(), b->order.p, (size_t)a * sizeof(int32_t),
-                               hipMemcpyDeviceToHost));
+        if (a > 0) {
+            LOWD_HIP(hipMemcpyAsync(act.data(), b->order.p, (size_t)a * sizeof(int32_t),
+                                    hipMemcpyDeviceToHost, s));
+            LOWD_HIP(hipStreamSynchronize(s));
+        }
         set_active_list(b, act.data(), a, s);
     });
 }

@@ -355,6 +355,32 @@ def test_prune_then_solve_finds_the_densest_set_of_g():
     assert (ex["num"], ex["den"]) == (ro["num"], ro["den"])
 
 
+def test_entry_points_on_a_side_stream():
+    """Every call orders its copies on the caller's stream: on a torch side
+    stream (created non-blocking, so it does not wait for the null stream)
+    the prune, the check of the edge list, greedy and the solve give the
+    oracle's results, and a repeated pair is still named."""
+    g = PRUNE_GRAPHS[4][1]
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        r = lowd.prune(g.n, g.src, g.dst)
+        keep = r["node_keep"].cpu().numpy()
+        gr = lowd.greedy_peel(g.n, g.src, g.dst)
+        sv = lowd.solve(g.n, g.src, g.dst, None, state="f64", tol=1e-9)
+        src = np.concatenate([g.src, g.src[:1]])
+        dst = np.concatenate([g.dst, g.dst[:1]])
+        with pytest.raises(RuntimeError, match=f"at index {g.m}:"):
+            lowd.prune(g.n, src, dst)
+    side.synchronize()
+    ko, rounds, nh, mh = oracle.prune(g.n, g.src, g.dst)
+    assert np.array_equal(keep, ko)
+    assert (r["rounds"], r["n_h"], r["m_h"]) == (rounds, nh, mh)
+    go = oracle.greedy(g.n, g.src, g.dst)
+    assert np.array_equal(gr["order"].cpu().numpy(), go["order"])
+    assert (gr["num"], gr["den"]) == (go["num"], go["den"])
+    assert sv["gap"] <= 1e-9
+
+
 # ------------------------------------------------------------ edge cases --
 def test_graph_without_edges():
     g = synth.canonical(5, np.zeros(0, np.int64), np.zeros(0, np.int64))
