@@ -115,10 +115,44 @@ __global__ void k_split(int64_t c, const int32_t *cand, const int64_t *rm, const
 // adds each count with one atomic, where the rounds' removed nodes would
 // otherwise send one atomic per edge to the same few degree counters.
 constexpr int kHubs = 4096;
-__global__ void k_mark_hubs(int32_t k, const int32_t *hubs, int32_t *stamp) {
+
+// The removal kernel reads a neighbour's state from 2-bit marks, 16 nodes a
+// word (4 MB for 16M nodes, about an L2's size, where the stamps take 64 MB
+// and every read of one would go past the L2): dead, alive, removed in the
+// current round, alive hub.
+constexpr uint32_t kMarkDead = 0u, kMarkAlive = 1u, kMarkNow = 2u, kMarkHub = 3u;
+__device__ __forceinline__ uint32_t mark_of(const uint32_t *marks, int32_t v) {
+    return (marks[v >> 4] >> ((v & 15) * 2)) & 3u;
+}
+__device__ __forceinline__ void set_mark(uint32_t *marks, int32_t v, uint32_t mk) {
+    const uint32_t sh = (uint32_t)(v & 15) * 2;
+    atomicAnd(&marks[v >> 4], ~(3u << sh));
+    if (mk) atomicOr(&marks[v >> 4], mk << sh);
+}
+
+__global__ void k_mark_hubs(int32_t k, const int32_t *hubs, int32_t *stamp, uint32_t *marks) {
     for (int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x); i < k;
-         i += (int32_t)(gridDim.x * blockDim.x))
+         i += (int32_t)(gridDim.x * blockDim.x)) {
         stamp[hubs[i]] = -(i + 1);
+        set_mark(marks, hubs[i], kMarkHub);
+    }
+}
+
+// the round's removed nodes: stamped, and marked as removed in this round
+__global__ void k_stamp_marks(int64_t k, const int32_t *list, int32_t *stamp, uint32_t *marks,
+                              int32_t round) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        stamp[list[i]] = round;
+        set_mark(marks, list[i], kMarkNow);
+    }
+}
+
+// after the round: its removed nodes are dead
+__global__ void k_mark_dead(int64_t k, const int32_t *list, uint32_t *marks) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
+         i += (int64_t)gridDim.x * blockDim.x)
+        set_mark(marks, list[i], kMarkDead);
 }
 
 __global__ void k_stamp(int64_t k, const int32_t *list, int32_t *stamp, int32_t round) {
@@ -129,7 +163,8 @@ __global__ void k_stamp(int64_t k, const int32_t *list, int32_t *stamp, int32_t 
 
 // for each removed node (its row of neighbour ids): lower alive neighbours'
 // degrees; count each removed edge once (an edge between two nodes removed
-// this round by its smaller end).  G lanes walk one removed node's row (G = 1 for the many short rows
+// this round by its smaller end).  A neighbour's state comes from its mark;
+// only a hub's stamp is read, for its slot.  G lanes walk one removed node's row (G = 1 for the many short rows
 // of the first round; a wave or the whole workgroup for the later rounds,
 // whose few removed nodes can have long rows).  The counts are summed per
 // wave after the loop, where the whole wave has reconverged, and added with
@@ -141,7 +176,8 @@ __global__ void __launch_bounds__(kRemoveBlock) k_remove_edges(int64_t k, const 
                                                                const int64_t *row_ptr,
                                                                const uint32_t *nbr,
                                                                const int32_t *stamp,
-                                                               int32_t round, int32_t *deg,
+                                                               const uint32_t *marks,
+                                                               int32_t *deg,
                                                                unsigned long long *gone,
                                                                const int32_t *hubs,
                                                                int32_t nhubs) {
@@ -155,24 +191,25 @@ __global__ void __launch_bounds__(kRemoveBlock) k_remove_edges(int64_t k, const 
          i += (int64_t)gridDim.x * kGroups) {
         const int32_t u = removed[i];
         const int64_t end = row_ptr[u + 1];
-        // four entries a lane at a time: their loads, then their stamps,
+        // four entries a lane at a time: their loads, then their marks,
         // are independent and in flight together
         constexpr int kU = 4;
         for (int64_t j = row_ptr[u] + lane; j < end; j += kU * G) {
-            int32_t v[kU], sv[kU];
+            int32_t v[kU];
+            uint32_t mk[kU];
 #pragma unroll
             for (int q = 0; q < kU; ++q) v[q] = j + q * G < end ? (int32_t)nbr[j + q * G] : -1;
 #pragma unroll
-            for (int q = 0; q < kU; ++q) sv[q] = v[q] >= 0 ? stamp[v[q]] : round + 1;
+            for (int q = 0; q < kU; ++q) mk[q] = v[q] >= 0 ? mark_of(marks, v[q]) : kMarkDead;
 #pragma unroll
             for (int q = 0; q < kU; ++q) {
-                if (sv[q] == 0) {
+                if (mk[q] == kMarkAlive) {
                     atomicSub(&deg[v[q]], 1);
                     ++cnt;
-                } else if (sv[q] < 0) {
-                    atomicAdd(&hub_lost[-sv[q] - 1], 1);
+                } else if (mk[q] == kMarkHub) {
+                    atomicAdd(&hub_lost[-stamp[v[q]] - 1], 1);   // the hub's slot
                     ++cnt;
-                } else if (sv[q] == round && u < v[q]) {
+                } else if (mk[q] == kMarkNow && u < v[q]) {
                     ++cnt;
                 }
             }
@@ -463,6 +500,7 @@ PruneResult run_prune_ws(int32_t n, int64_t m, const int32_t *src, const int32_t
     } csr;
     build_incidence_ws(n, m, src, dst, ws, &csr.row_ptr, &csr.inc, true, s);   // neighbour ids
     const size_t nn = (size_t)n;
+    uint32_t *marks = ws.take<uint32_t>((nn + 15) / 16);
     int32_t *deg = ws.take<int32_t>(nn), *stamp = ws.take<int32_t>(nn),
             *by_deg = ws.take<int32_t>(nn), *list_a = ws.take<int32_t>(nn),
             *list_b = ws.take<int32_t>(nn), *removed = ws.take<int32_t>(nn);
@@ -486,6 +524,7 @@ PruneResult run_prune_ws(int32_t n, int64_t m, const int32_t *src, const int32_t
     LOWD_HIP(hipMemsetAsync(hist, 0, kBins * sizeof(unsigned long long), s));
     LOWD_HIP(hipMemsetAsync(cursor, 0, kBins * sizeof(unsigned long long), s));
     LOWD_HIP(hipMemsetAsync(stamp, 0, (size_t)n * sizeof(int32_t), s));
+    LOWD_HIP(hipMemsetAsync(marks, 0x55, (nn + 15) / 16 * sizeof(uint32_t), s));   // all alive
     hipLaunchKernelGGL(k_degree_hist, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, n, deg,
                        hist);
     exclusive_scan_i64((const int64_t *)hist, bin_start, kBins, nullptr, scan_tmp, scan_bytes, s);
@@ -496,7 +535,7 @@ PruneResult run_prune_ws(int32_t n, int64_t m, const int32_t *src, const int32_t
     const int32_t *hubs = by_deg + (n - nhubs);   // the highest degrees
     if (nhubs > 0)
         hipLaunchKernelGGL(k_mark_hubs, dim3(grid_for(nhubs, 256)), dim3(256), 0, s, nhubs, hubs,
-                           stamp);
+                           stamp, marks);
     std::array<int64_t, kBins> hstart;
     LOWD_HIP(hipMemcpyAsync(hstart.data(), bin_start, kBins * sizeof(int64_t),
                             hipMemcpyDeviceToHost, s));
@@ -537,22 +576,24 @@ PruneResult run_prune_ws(int32_t n, int64_t m, const int32_t *src, const int32_t
         if (nrm == 0) break;
         LOWD_HIP(hipMemsetAsync(gone, 0, sizeof(unsigned long long), s));
         const unsigned gr = grid_for(nrm, 256);
-        hipLaunchKernelGGL(k_stamp, dim3(gr), dim3(256), 0, s, nrm, rm_list, stamp, round);
+        hipLaunchKernelGGL(k_stamp_marks, dim3(gr), dim3(256), 0, s, nrm, rm_list, stamp, marks,
+                           round);
         // at most kRemoveGrid workgroups, each over many removed nodes, so
         // that the hubs' LDS counts are added with few atomics
         if (nrm >= (1 << 18))
             hipLaunchKernelGGL(k_remove_edges<1>, dim3(grid_for(nrm, kRemoveBlock, kRemoveGrid)),
                                dim3(kRemoveBlock), 0, s, nrm, rm_list, csr.row_ptr, csr.inc,
-                               stamp, round, deg, gone, hubs, nhubs);
+                               stamp, marks, deg, gone, hubs, nhubs);
         else if (nrm >= (1 << 12))
             hipLaunchKernelGGL(k_remove_edges<kWave>,
                                dim3(grid_for(nrm, kRemoveBlock / kWave, kRemoveGrid)),
                                dim3(kRemoveBlock), 0, s, nrm, rm_list, csr.row_ptr, csr.inc,
-                               stamp, round, deg, gone, hubs, nhubs);
+                               stamp, marks, deg, gone, hubs, nhubs);
         else
             hipLaunchKernelGGL(k_remove_edges<kRemoveBlock>, dim3(grid_for(nrm, 1, kRemoveGrid)),
                                dim3(kRemoveBlock), 0, s, nrm, rm_list, csr.row_ptr, csr.inc,
-                               stamp, round, deg, gone, hubs, nhubs);
+                               stamp, marks, deg, gone, hubs, nhubs);
+        hipLaunchKernelGGL(k_mark_dead, dim3(gr), dim3(256), 0, s, nrm, rm_list, marks);
         LOWD_HIP(hipGetLastError());
         unsigned long long g = 0;
         LOWD_HIP(hipMemcpyAsync(&g, gone, sizeof(g), hipMemcpyDeviceToHost, s));
