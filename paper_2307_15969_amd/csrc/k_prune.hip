@@ -124,41 +124,36 @@ constexpr uint32_t kMarkDead = 0u, kMarkAlive = 1u, kMarkNow = 2u, kMarkHub = 3u
 __device__ __forceinline__ uint32_t mark_of(const uint32_t *marks, int32_t v) {
     return (marks[v >> 4] >> ((v & 15) * 2)) & 3u;
 }
-__device__ __forceinline__ void set_mark(uint32_t *marks, int32_t v, uint32_t mk) {
-    const uint32_t sh = (uint32_t)(v & 15) * 2;
-    atomicAnd(&marks[v >> 4], ~(3u << sh));
-    if (mk) atomicOr(&marks[v >> 4], mk << sh);
-}
 
-__global__ void k_mark_hubs(int32_t k, const int32_t *hubs, int32_t *stamp, uint32_t *marks) {
+__global__ void k_mark_hubs(int32_t k, const int32_t *hubs, int32_t *stamp) {
     for (int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x); i < k;
-         i += (int32_t)(gridDim.x * blockDim.x)) {
+         i += (int32_t)(gridDim.x * blockDim.x))
         stamp[hubs[i]] = -(i + 1);
-        set_mark(marks, hubs[i], kMarkHub);
-    }
-}
-
-// the round's removed nodes: stamped, and marked as removed in this round
-__global__ void k_stamp_marks(int64_t k, const int32_t *list, int32_t *stamp, uint32_t *marks,
-                              int32_t round) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        stamp[list[i]] = round;
-        set_mark(marks, list[i], kMarkNow);
-    }
-}
-
-// after the round: its removed nodes are dead
-__global__ void k_mark_dead(int64_t k, const int32_t *list, uint32_t *marks) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
-         i += (int64_t)gridDim.x * blockDim.x)
-        set_mark(marks, list[i], kMarkDead);
 }
 
 __global__ void k_stamp(int64_t k, const int32_t *list, int32_t *stamp, int32_t round) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
          i += (int64_t)gridDim.x * blockDim.x)
         stamp[list[i]] = round;
+}
+
+// The marks from the stamps in one pass (round 0: alive, hubs and dead
+// only): each lane finds its node's mark and 16 lanes OR theirs into one
+// word.  Every lane of a wave runs the same iterations (the loop bound is
+// uniform), so the shuffles see whole waves.
+__global__ void k_marks(int32_t n, const int32_t *stamp, uint32_t *marks, int32_t round) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
+        const int64_t v = base + threadIdx.x;
+        uint32_t mk = kMarkDead;
+        if (v < n) {
+            const int32_t st = stamp[v];
+            mk = st == 0 ? kMarkAlive : st < 0 ? kMarkHub : st == round ? kMarkNow : kMarkDead;
+        }
+        uint32_t word = mk << ((uint32_t)(v & 15) * 2);
+        for (int o = 1; o < 16; o <<= 1) word |= __shfl_xor(word, o, kWave);
+        if ((v & 15) == 0 && v < n) marks[v >> 4] = word;
+    }
 }
 
 // for each removed node (its row of neighbour ids): lower alive neighbours'
@@ -251,18 +246,32 @@ constexpr int64_t kCompactTile = (int64_t)kCompactBlock * kCompactRows;
 
 __global__ void __launch_bounds__(kCompactBlock)
     k_edge_keep_tiles(int64_t m, const int32_t *src, const int32_t *dst, const int32_t *stamp,
-                      uint8_t *keep, int64_t *tile_count) {
+                      const uint32_t *marks, uint8_t *keep, int64_t *tile_count) {
     __shared__ int lds[kCompactWaves];
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int64_t ntiles = (m + kCompactTile - 1) / kCompactTile;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {   // uniform across the block
+        // the tile's ends first, all loads in flight, then their states
+        int32_t a[kCompactRows], b[kCompactRows];
+        bool kp[kCompactRows];
+#pragma unroll
+        for (int k = 0; k < kCompactRows; ++k) {
+            const int64_t e = t * kCompactTile + (int64_t)k * kCompactBlock + threadIdx.x;
+            a[k] = e < m ? src[e] : 0;
+            b[k] = e < m ? dst[e] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kCompactRows; ++k)   // kept: both ends alive (alive and hub
+            kp[k] = marks                         // marks have the low bit)
+                        ? ((mark_of(marks, a[k]) & mark_of(marks, b[k]) & 1u) != 0)
+                        : (stamp[a[k]] <= 0 && stamp[b[k]] <= 0);
         int c = 0;
+#pragma unroll
         for (int k = 0; k < kCompactRows; ++k) {
             const int64_t e = t * kCompactTile + (int64_t)k * kCompactBlock + threadIdx.x;
             if (e < m) {
-                const bool kp = stamp[src[e]] <= 0 && stamp[dst[e]] <= 0;
-                keep[e] = kp ? 1 : 0;
-                c += kp ? 1 : 0;
+                keep[e] = kp[k] ? 1 : 0;
+                c += kp[k] ? 1 : 0;
             }
         }
         for (int d = kWave / 2; d > 0; d >>= 1) c += __shfl_down(c, d, kWave);
@@ -320,9 +329,12 @@ __global__ void __launch_bounds__(kCompactBlock)
 inline int64_t compact_tiles(int64_t m) { return (m + kCompactTile - 1) / kCompactTile; }
 
 // H's edge list (renumbered by npos) from the kept flags of the nodes
-// (stamp == 0); *kept_dev (device) receives the number of H's edges.
+// (stamp <= 0, or from the marks where given: their 4 MB stay in the L2
+// where the stamps' 64 MB do not); *kept_dev (device) receives the number
+// of H's edges.
 void compact_edges(int64_t m, const int32_t *src, const int32_t *dst, const float *w,
-                   const int32_t *stamp, const int64_t *npos, int32_t *h_src, int32_t *h_dst,
+                   const int32_t *stamp, const uint32_t *marks, const int64_t *npos,
+                   int32_t *h_src, int32_t *h_dst,
                    float *h_w, int64_t *edge_map, uint8_t *keep, int64_t *tile_count,
                    int64_t *tile_offset, int64_t *kept_dev, void *scan_tmp, size_t scan_bytes,
                    hipStream_t s) {
@@ -330,7 +342,7 @@ void compact_edges(int64_t m, const int32_t *src, const int32_t *dst, const floa
     const int64_t nt = compact_tiles(m);
     const unsigned g = (unsigned)std::min<int64_t>(nt, 65536);
     hipLaunchKernelGGL(k_edge_keep_tiles, dim3(g), dim3(kCompactBlock), 0, s, m, src, dst, stamp,
-                       keep, tile_count);
+                       marks, keep, tile_count);
     exclusive_scan_i64(tile_count, tile_offset, nt, kept_dev, scan_tmp, scan_bytes, s);
     if (h_src || h_w || edge_map)
         hipLaunchKernelGGL(k_edge_write_tiles, dim3(g), dim3(kCompactBlock), 0, s, m, src, dst, w,
@@ -524,7 +536,6 @@ PruneResult run_prune_ws(int32_t n, int64_t m, const int32_t *src, const int32_t
     LOWD_HIP(hipMemsetAsync(hist, 0, kBins * sizeof(unsigned long long), s));
     LOWD_HIP(hipMemsetAsync(cursor, 0, kBins * sizeof(unsigned long long), s));
     LOWD_HIP(hipMemsetAsync(stamp, 0, (size_t)n * sizeof(int32_t), s));
-    LOWD_HIP(hipMemsetAsync(marks, 0x55, (nn + 15) / 16 * sizeof(uint32_t), s));   // all alive
     hipLaunchKernelGGL(k_degree_hist, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, n, deg,
                        hist);
     exclusive_scan_i64((const int64_t *)hist, bin_start, kBins, nullptr, scan_tmp, scan_bytes, s);
@@ -535,7 +546,8 @@ PruneResult run_prune_ws(int32_t n, int64_t m, const int32_t *src, const int32_t
     const int32_t *hubs = by_deg + (n - nhubs);   // the highest degrees
     if (nhubs > 0)
         hipLaunchKernelGGL(k_mark_hubs, dim3(grid_for(nhubs, 256)), dim3(256), 0, s, nhubs, hubs,
-                           stamp, marks);
+                           stamp);
+    hipLaunchKernelGGL(k_marks, dim3(gn), dim3(256), 0, s, n, stamp, marks, 0);
     std::array<int64_t, kBins> hstart;
     LOWD_HIP(hipMemcpyAsync(hstart.data(), bin_start, kBins * sizeof(int64_t),
                             hipMemcpyDeviceToHost, s));
@@ -576,8 +588,8 @@ PruneResult run_prune_ws(int32_t n, int64_t m, const int32_t *src, const int32_t
         if (nrm == 0) break;
         LOWD_HIP(hipMemsetAsync(gone, 0, sizeof(unsigned long long), s));
         const unsigned gr = grid_for(nrm, 256);
-        hipLaunchKernelGGL(k_stamp_marks, dim3(gr), dim3(256), 0, s, nrm, rm_list, stamp, marks,
-                           round);
+        hipLaunchKernelGGL(k_stamp, dim3(gr), dim3(256), 0, s, nrm, rm_list, stamp, round);
+        hipLaunchKernelGGL(k_marks, dim3(gn), dim3(256), 0, s, n, stamp, marks, round);
         // at most kRemoveGrid workgroups, each over many removed nodes, so
         // that the hubs' LDS counts are added with few atomics
         if (nrm >= (1 << 18))
@@ -593,7 +605,6 @@ PruneResult run_prune_ws(int32_t n, int64_t m, const int32_t *src, const int32_t
             hipLaunchKernelGGL(k_remove_edges<kRemoveBlock>, dim3(grid_for(nrm, 1, kRemoveGrid)),
                                dim3(kRemoveBlock), 0, s, nrm, rm_list, csr.row_ptr, csr.inc,
                                stamp, marks, deg, gone, hubs, nhubs);
-        hipLaunchKernelGGL(k_mark_dead, dim3(gr), dim3(256), 0, s, nrm, rm_list, marks);
         LOWD_HIP(hipGetLastError());
         unsigned long long g = 0;
         LOWD_HIP(hipMemcpyAsync(&g, gone, sizeof(g), hipMemcpyDeviceToHost, s));
@@ -609,8 +620,8 @@ PruneResult run_prune_ws(int32_t n, int64_t m, const int32_t *src, const int32_t
     if (relabel)
         hipLaunchKernelGGL(k_relabel, dim3(gn), dim3(256), 0, s, n, f_keep, p_keep, relabel);
     if (edges_out) {
-        compact_edges(m, src, dst, nullptr, stamp, p_keep, h_src, h_dst, nullptr, edge_map, ekeep,
-                      tcount, toff, toff + nt, scan_tmp, scan_bytes, s);
+        compact_edges(m, src, dst, nullptr, stamp, marks, p_keep, h_src, h_dst, nullptr,
+                      edge_map, ekeep, tcount, toff, toff + nt, scan_tmp, scan_bytes, s);
         LOWD_HIP(hipStreamSynchronize(s));
     }
     LOWD_HIP(hipGetLastError());
@@ -703,8 +714,8 @@ PruneResult run_prune_weighted(int32_t n, int64_t m, const int32_t *src, const i
         const int64_t nt = compact_tiles(m);
         DBuf<uint8_t> ekeep((size_t)m);
         DBuf<int64_t> tcount((size_t)nt), toff((size_t)nt), etot(1);
-        compact_edges(m, src, dst, w, stamp.p, p_keep.p, h_src, h_dst, h_w, edge_map, ekeep.p,
-                      tcount.p, toff.p, etot.p, scan_tmp.p, scan_tmp.bytes(), s);
+        compact_edges(m, src, dst, w, stamp.p, nullptr, p_keep.p, h_src, h_dst, h_w, edge_map,
+                      ekeep.p, tcount.p, toff.p, etot.p, scan_tmp.p, scan_tmp.bytes(), s);
         LOWD_HIP(hipMemcpyAsync(&mh, etot.p, sizeof(mh), hipMemcpyDeviceToHost, s));
         LOWD_HIP(hipStreamSynchronize(s));
     }
