@@ -134,6 +134,23 @@ inline int64_t radix_tiles(int64_t n) {
     return t < 1 ? 1 : (t > kRadixMaxTiles ? kRadixMaxTiles : t);
 }
 
+// One count of digit d in the LDS counters h, for every active lane: the
+// lanes whose digit equals the first active lane's add theirs with one
+// atomic.  Sorted or clustered keys (a node's incidence entries, a pass's
+// input after the previous pass) put whole waves on one counter, and the
+// LDS serialises atomics to one address: on 520M keys of runs a histogram
+// pass took 1.7 ms against 0.5 ms for random keys, and 0.5 ms counted so.
+__device__ __forceinline__ void count_digit(uint32_t *h, uint32_t d) {
+    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+    const uint64_t same = __ballot(d == d0);
+    if (d == d0) {
+        if ((uint32_t)__lane_id() == (uint32_t)(__ffsll((unsigned long long)same) - 1))
+            atomicAdd(&h[d0], (uint32_t)__popcll(same));
+    } else {
+        atomicAdd(&h[d], 1u);
+    }
+}
+
 // A block counts the digits of its chunk (a multiple of 256 keys, so every
 // 16-byte group of keys is aligned): 16 bytes of keys a lane per load, two
 // loads in flight, the rest one key at a time.
@@ -157,31 +174,34 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_hist(const K *keys, int64
         const Vec b = *(const Vec *)(keys + i + kV * kRadixBlock);
 #pragma unroll
         for (int q = 0; q < kV; ++q) {
-            atomicAdd(&h[(uint32_t)(a.k[q] >> shift) & (kDigits - 1)], 1u);
-            atomicAdd(&h[(uint32_t)(b.k[q] >> shift) & (kDigits - 1)], 1u);
+            count_digit(h, (uint32_t)(a.k[q] >> shift) & (kDigits - 1));
+            count_digit(h, (uint32_t)(b.k[q] >> shift) & (kDigits - 1));
         }
     }
-    for (int64_t i = vend + threadIdx.x; i < end; i += kRadixBlock) {
-        uint32_t d = (uint32_t)(keys[i] >> shift) & (kDigits - 1);
-        atomicAdd(&h[d], 1u);
-    }
+    for (int64_t i = vend + threadIdx.x; i < end; i += kRadixBlock)
+        count_digit(h, (uint32_t)(keys[i] >> shift) & (kDigits - 1));
     __syncthreads();
     blockhist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
-// The scatter stages rounds of 16 tiles (4,096 keys) in LDS in digit
-// order, then writes every digit's run of the round to consecutive
-// addresses: a tile's 256 keys written straight out land on up to 256
-// scattered lines, a round's runs average 16 keys per digit.  (Rounds of 32
-// tiles, whose runs fill whole lines for 4-byte keys, measured slower: at
-// 77 KB of LDS only two blocks fit a CU.)  Within a round wave w owns the
-// contiguous quarter [w R/4, (w+1) R/4) of the keys: it counts its digits
-// in a row of LDS counters of its own, one scan over (digit, wave) in that
-// order gives every wave the first position of each digit, and the wave
-// places its keys chunk by chunk in key order, ranking equal digits among
-// its lanes with eight ballots and moving its own counters on.  Keys keep
-// their order within a digit, so the permutation is the stable one.
-constexpr int kRadixRoundTiles = 16;
+// The scatter stages rounds of tiles in LDS in digit order, then writes
+// every digit's run of the round to consecutive addresses: a tile's 256 keys
+// written straight out land on up to 256 scattered lines, a round's runs
+// average 16 keys per digit at 16 tiles (4,096 keys).  Rounds of 32 tiles
+// (64 KB of LDS, two blocks a CU) measured faster for 8-byte keys alone
+// (2 passes over 260M keys: 3.0 -> 2.8 ms) and slower for 4-byte keys with
+// values (3 passes over 520M pairs: 9.4 -> 10.7 ms), so only the former
+// take them.  Within a round wave w owns the contiguous quarter
+// [w R/4, (w+1) R/4) of the keys: it counts its digits in a row of LDS
+// counters of its own, one scan over (digit, wave) in that order gives every
+// wave the first position of each digit, and the wave places its keys chunk
+// by chunk in key order, ranking equal digits among its lanes with eight
+// ballots and moving its own counters on.  Keys keep their order within a
+// digit, so the permutation is the stable one.
+template <class K, bool kVals>
+constexpr int radix_round_tiles() {
+    return sizeof(K) == 8 && !kVals ? 32 : 16;
+}
 
 template <class K, bool kVals>
 __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter_staged(const K *keys, const uint32_t *vals,
@@ -190,7 +210,7 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter_staged(const K *k
                                                                const int64_t *offsets,
                                                                int64_t nb, int64_t tiles) {
     constexpr int kWaves = kRadixBlock / kWave;
-    constexpr int kRound = kRadixRoundTiles * kRadixBlock;   // keys staged at a time
+    constexpr int kRound = radix_round_tiles<K, kVals>() * kRadixBlock;   // keys staged at a time
     constexpr int kChunks = kRound / kRadixBlock;             // 64-key chunks a wave owns
     __shared__ int64_t running[kDigits];         // next global position of each digit
     __shared__ int64_t scan_lds[kWave + 1];
@@ -223,7 +243,7 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter_staged(const K *k
 #pragma unroll
         for (int c = 0; c < kChunks; ++c)
             if (lo + (int64_t)c * kWave + lane < hi)
-                atomicAdd(&wpos[wave][(uint32_t)(kreg[c] >> shift) & (kDigits - 1)], 1u);
+                count_digit(wpos[wave], (uint32_t)(kreg[c] >> shift) & (kDigits - 1));
         __syncthreads();
         {   // digit totals, their scan, and each wave's first position per digit
             uint32_t t = 0;
