@@ -134,23 +134,6 @@ inline int64_t radix_tiles(int64_t n) {
     return t < 1 ? 1 : (t > kRadixMaxTiles ? kRadixMaxTiles : t);
 }
 
-// One count of digit d in the LDS counters h, for every active lane: the
-// lanes whose digit equals the first active lane's add theirs with one
-// atomic.  Sorted or clustered keys (a node's incidence entries, a pass's
-// input after the previous pass) put whole waves on one counter, and the
-// LDS serialises atomics to one address: on 520M keys of runs a histogram
-// pass took 1.7 ms against 0.5 ms for random keys, and 0.5 ms counted so.
-__device__ __forceinline__ void count_digit(uint32_t *h, uint32_t d) {
-    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-    const uint64_t same = __ballot(d == d0);
-    if (d == d0) {
-        if ((uint32_t)__lane_id() == (uint32_t)(__ffsll((unsigned long long)same) - 1))
-            atomicAdd(&h[d0], (uint32_t)__popcll(same));
-    } else {
-        atomicAdd(&h[d], 1u);
-    }
-}
-
 // A block counts the digits of its chunk (a multiple of 256 keys, so every
 // 16-byte group of keys is aligned): 16 bytes of keys a lane per load, two
 // loads in flight, the rest one key at a time.

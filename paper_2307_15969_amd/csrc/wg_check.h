@@ -128,7 +128,7 @@ __device__ bool wg_radix_sort(uint64_t *ka, uint32_t *ia, uint64_t *kb, uint32_t
 #pragma unroll
             for (int j = 0; j < kGroup; ++j)
                 if (c0 + j * kWave + lane < hi)
-                    atomicAdd(&ls.hw[wave][(uint32_t)(kk[j] >> shift) & (kSortDigits - 1)], 1u);
+                    count_digit(ls.hw[wave], (uint32_t)(kk[j] >> shift) & (kSortDigits - 1));
         }
         __syncthreads();
         if (tid < kSortDigits) {
