@@ -405,12 +405,15 @@ lowd_status lowd_schedule_build(int32_t n, int64_t m, const int32_t *src, const 
 
 /*
  * lowd_solver_info -- sizes of the solver, for reports.
- *   info [host] int64[11] out: n, m, phases, phases run by whole-GPU
+ *   info [host] int64[12] out: n, m, phases, phases run by whole-GPU
  *        launches, phases run inside one workgroup with loads in global
  *        memory, phases run inside one workgroup with loads in LDS, nodes
  *        held in LDS, edges of the LDS phases, edges of the global-memory
  *        single-workgroup phases, state type, load layout (0: stations, 1:
- *        a node-indexed array).
+ *        a node-indexed array), whole-GPU phases that pull their loads
+ *        (phases of at least 2^18 edges, or LOWD_PULL_EDGES: each node's
+ *        load is read at its previous station, which keeps its output,
+ *        instead of being written to its next one).
  */
 lowd_status lowd_solver_info(const lowd_solver *s, int64_t *info);
 

@@ -333,10 +333,10 @@ class Solver:
         return phase[:self.m], center[:self.m], int(P.value)
 
     def info(self) -> dict:
-        a = np.zeros(11, dtype=np.int64)
+        a = np.zeros(12, dtype=np.int64)
         _check(lib().lowd_solver_info(self._h, a.ctypes.data_as(C.c_void_p)))
         keys = ["n", "m", "phases", "grid_phases", "mid_phases", "lds_phases", "lds_nodes",
-                "lds_edges", "mid_edges", "state", "node_layout"]
+                "lds_edges", "mid_edges", "state", "node_layout", "pulled_phases"]
         return {k: int(v) for k, v in zip(keys, a)}
 
 

@@ -155,6 +155,7 @@ struct lowd_solver {
     DBuf<PhaseDesc> tail_desc, mid_desc;
     DBuf<int64_t> slot_edge, edge_slot;
     DBuf<uint32_t> slot_leaf, slot_next, center_next, tail_next, home;
+    DBuf<uint32_t> slot_src, center_src;   // pulled phases' sources (empty: none)
     // state: fractions per slot, loads at their stations
     DBuf<char> slot_x, E;
     DBuf<float> slot_w;
@@ -228,13 +229,17 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
         }
         sv->node_layout = choose_node_layout();
         const int64_t lds = sv->node_layout ? 0 : (int64_t)lds_capacity_bytes();
-        int64_t force0 = -1, force1 = -1;
+        int64_t force0 = -1, force1 = -1, pull_edges = -1;
         if (!sv->node_layout) {
             if (const char *e = getenv("LOWD_TAIL_SPLIT")) force0 = atoll(e);
             if (const char *e = getenv("LOWD_MID_SPLIT")) force1 = atoll(e);
+            // whole-GPU phases this wide gather their loads (random reads)
+            // instead of scattering them (random writes, half the rate)
+            pull_edges = kPullMinEdges;
+            if (const char *e = getenv("LOWD_PULL_EDGES")) pull_edges = atoll(e);
         }
         build_schedule(n, m, hs.data(), hd.data(), star_max, lds, (int64_t)sv->fn.l_bytes, force0,
-                       force1, sv->sch);
+                       force1, sv->sch, false, pull_edges);
         const Schedule &sc = sv->sch;
 
         // device copies of the graph, incidence rows
@@ -290,6 +295,10 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
             upload(sv->center_next, sc.center_next, s);
             upload(sv->tail_next, sc.tail_next, s);
             upload(sv->home, sc.home, s);
+            if (!sc.pull.empty()) {
+                upload(sv->slot_src, sc.slot_src, s);
+                upload(sv->center_src, sc.center_src, s);
+            }
         }
         sv->ntail = (int32_t)sc.tail_nodes.size();
 
@@ -320,9 +329,13 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
                     if (sv->node_layout)
                         sv->fn.phase_node(sc.desc[(size_t)p], sv->tile_center.p, sv->slot_leaf.p,
                                           sv->slot_x.p, sw, sv->E.p, cs);
-                    else
+                    else {
+                        const bool pull = !sc.pull.empty() && sc.pull[(size_t)p];
                         sv->fn.phase(sc.desc[(size_t)p], sc.center_base, sv->center_next.p,
-                                     sv->slot_next.p, sv->slot_x.p, sw, sv->E.p, cs);
+                                     sv->slot_next.p, sv->slot_x.p, sw, sv->E.p,
+                                     pull ? sv->slot_src.p : nullptr,
+                                     pull ? sv->center_src.p : nullptr, cs);
+                    }
                 }
                 if (sc.P1 < sc.P0)
                     sv->fn.mid(sc.P0 - sc.P1, sv->mid_desc.p, sc.center_base, sv->center_next.p,
@@ -807,6 +820,9 @@ lowd_status lowd_solver_info(const lowd_solver *sv, int64_t *info) {
         info[8] = mid_edges;
         info[9] = sv->state;
         info[10] = sv->node_layout ? 1 : 0;
+        int64_t pulled = 0;
+        for (const uint8_t x : sv->sch.pull) pulled += x;
+        info[11] = pulled;
     });
 }
 

@@ -296,6 +296,36 @@ __device__ __forceinline__ void load_static(StationTile<St, kWeighted, D> &tl, c
     tl.sink = (uint32_t)d.sink;
 }
 
+// the loads of a pulled phase, gathered from each node's previous station
+// (the rows' and the lane's source entries first, in one batch)
+template <class St, bool kWeighted, int D>
+__device__ __forceinline__ void pull_loads(StationTile<St, kWeighted, D> &tl, int lane,
+                                           int64_t li, const typename St::L *E,
+                                           const uint32_t *__restrict__ slot_src,
+                                           const uint32_t *__restrict__ center_src) {
+    uint32_t from[D];
+    const uint32_t *ps = slot_src + tl.base + lane;
+    const uint32_t cfrom = center_src[li];
+    if (tl.depth == D) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) from[k] = ps[k * kWave];
+    } else {
+#pragma unroll
+        for (int k = 0; k < D; ++k) from[k] = k < tl.depth ? ps[k * kWave] : 0u;
+    }
+    tl.lc_raw = E[cfrom];
+    if (tl.depth == D) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) tl.ll_raw[k] = E[from[k]];
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        if (k < tl.depth) tl.ll_raw[k] = E[from[k]];
+        else tl.ll_raw[k] = St::infinite();
+    }
+}
+
 // the loads, written by earlier phases
 template <class St, bool kWeighted, int D>
 __device__ __forceinline__ void load_loads(StationTile<St, kWeighted, D> &tl, int lane,
@@ -371,14 +401,18 @@ constexpr int32_t kSpreadWaves = 256;  // spread until about one wave per CU
 // argument fetch (the descriptor and slot_w follow).  full_tiles = T[D-1]:
 // tiles t < full_tiles have depth D and start at slot_base + D * 64 * t.
 // D = 16 for phases whose stars have at most 16 leaves, 32 for deeper ones
-// (a lane then keeps 32 leaves' fractions and loads in registers).
-template <class St, bool kWeighted, int D>
+// (a lane then keeps 32 leaves' fractions and loads in registers).  kPull:
+// a pulled phase, whose loads are gathered through slot_src / center_src
+// (one more dependent round trip; its writes are coalesced instead of
+// scattered, see Schedule).
+template <class St, bool kWeighted, int D, bool kPull>
 __global__ void __launch_bounds__(kPhaseBlock)
 k_phase(int64_t slot_base, int32_t tile0, int32_t tiles, int32_t full_tiles, int32_t spread,
         int64_t center_base, typename St::L *__restrict__ E,
         const uint32_t *__restrict__ slot_next, typename St::X *__restrict__ slot_x,
         const uint32_t *__restrict__ center_next, PhaseDescT<D> d,
-        const float *__restrict__ slot_w) {
+        const float *__restrict__ slot_w, const uint32_t *__restrict__ slot_src,
+        const uint32_t *__restrict__ center_src) {
     const int lane = threadIdx.x & (kWave - 1);
     const int32_t t = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x >> spread));
     if (t >= tiles) return;
@@ -388,9 +422,10 @@ k_phase(int64_t slot_base, int32_t tile0, int32_t tiles, int32_t full_tiles, int
     int64_t base = slot_base + (int64_t)t * (D * kWave);
     if (t >= full_tiles) tile_geometry(d, t, depth, base);
     StationTile<St, kWeighted, D> tl;
-    load_static_at(tl, depth, base, (int64_t)(tile0 + t) * kWave + lane, lane, center_base,
-                   center_next, slot_next, slot_x, slot_w);
-    load_loads(tl, lane, E);
+    const int64_t li = (int64_t)(tile0 + t) * kWave + lane;
+    load_static_at(tl, depth, base, li, lane, center_base, center_next, slot_next, slot_x, slot_w);
+    if (kPull) pull_loads(tl, lane, li, E, slot_src, center_src);
+    else load_loads(tl, lane, E);
     tl.sink = (uint32_t)d.sink;
     // Every load of the tile is needed before the chain.  Waiting for all of
     // them here, on every path, keeps the compiler's per-path wait tracking
@@ -1199,23 +1234,40 @@ static void sweep_launchers(SweepLaunch &fn) {
     };
     fn.phase = [](const PhaseDescWide &d, int64_t center_base, const uint32_t *center_next,
                   const uint32_t *slot_next, void *slot_x, const float *slot_w, void *E,
-                  hipStream_t s) {
+                  const uint32_t *slot_src, const uint32_t *center_src, hipStream_t s) {
         const int32_t tiles = d.T[0];
         int32_t spread = 0;
         while (spread < kMaxSpreadLog2 && ((int64_t)tiles << (spread + 1)) <= kSpreadWaves)
             ++spread;
         const unsigned blocks = (unsigned)((int64_t)tiles << spread);
+        const bool pull = slot_src != nullptr;
         if (desc_depth(d) <= kTierStar) {
             const PhaseDesc n = narrow_desc<kTierStar>(d);
-            hipLaunchKernelGGL((k_phase<St, kW, kTierStar>), dim3(blocks), dim3(kPhaseBlock), 0, s,
-                               n.slot_base, n.tile0, n.T[0], n.T[kTierStar - 1], spread,
-                               center_base, (typename St::L *)E, slot_next,
-                               (typename St::X *)slot_x, center_next, n, slot_w);
+            if (pull)
+                hipLaunchKernelGGL((k_phase<St, kW, kTierStar, true>), dim3(blocks),
+                                   dim3(kPhaseBlock), 0, s, n.slot_base, n.tile0, n.T[0],
+                                   n.T[kTierStar - 1], spread, center_base, (typename St::L *)E,
+                                   slot_next, (typename St::X *)slot_x, center_next, n, slot_w,
+                                   slot_src, center_src);
+            else
+                hipLaunchKernelGGL((k_phase<St, kW, kTierStar, false>), dim3(blocks),
+                                   dim3(kPhaseBlock), 0, s, n.slot_base, n.tile0, n.T[0],
+                                   n.T[kTierStar - 1], spread, center_base, (typename St::L *)E,
+                                   slot_next, (typename St::X *)slot_x, center_next, n, slot_w,
+                                   nullptr, nullptr);
         } else {
-            hipLaunchKernelGGL((k_phase<St, kW, kMaxStar>), dim3(blocks), dim3(kPhaseBlock), 0, s,
-                               d.slot_base, d.tile0, d.T[0], d.T[kMaxStar - 1], spread,
-                               center_base, (typename St::L *)E, slot_next,
-                               (typename St::X *)slot_x, center_next, d, slot_w);
+            if (pull)
+                hipLaunchKernelGGL((k_phase<St, kW, kMaxStar, true>), dim3(blocks),
+                                   dim3(kPhaseBlock), 0, s, d.slot_base, d.tile0, d.T[0],
+                                   d.T[kMaxStar - 1], spread, center_base, (typename St::L *)E,
+                                   slot_next, (typename St::X *)slot_x, center_next, d, slot_w,
+                                   slot_src, center_src);
+            else
+                hipLaunchKernelGGL((k_phase<St, kW, kMaxStar, false>), dim3(blocks),
+                                   dim3(kPhaseBlock), 0, s, d.slot_base, d.tile0, d.T[0],
+                                   d.T[kMaxStar - 1], spread, center_base, (typename St::L *)E,
+                                   slot_next, (typename St::X *)slot_x, center_next, d, slot_w,
+                                   nullptr, nullptr);
         }
     };
     fn.phase_node = [](const PhaseDescWide &d, const int32_t *tile_center,

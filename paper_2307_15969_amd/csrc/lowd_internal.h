@@ -81,6 +81,10 @@ constexpr int kWave = 64;
 // "no next station" (padding slots, lanes without a star); station entries
 // stay below it
 constexpr uint32_t kNoStation = 0x7FFFFFFFu;
+// Whole-GPU phases of at least this many edges are pulled (Schedule::pull);
+// narrower ones, where the extra dependent round trip costs more than the
+// scattered writes, are pushed.
+constexpr int64_t kPullMinEdges = (int64_t)1 << 18;
 
 // ------------------------------------------------------------- schedule --
 // Stars of a phase are sorted by size (descending) and dealt to tiles of 64,
@@ -164,7 +168,12 @@ struct Schedule {
     std::vector<uint32_t> slot_next;      // [nslots] next station | orientation bit; padding: kNoStation
     std::vector<uint32_t> center_next;    // [ntiles*64] next station of the lane's center; empty: kNoStation
     std::vector<uint32_t> tail_next;      // [ntail] station after the tail (the node's first)
-    std::vector<uint32_t> home;           // [n] first station of each node
+    std::vector<uint32_t> home;           // [n] where each node's load rests between sweeps
+    // Pulled phases (empty when none): their stations read each node's load
+    // from its previous station, which keeps its own output.
+    std::vector<uint8_t> pull;            // [P] 1 for a pulled whole-GPU phase
+    std::vector<uint32_t> slot_src;       // [nslots] entry a pulled slot reads
+    std::vector<uint32_t> center_src;     // [ntiles*64] entry a pulled lane's center reads
     std::vector<int64_t> phase_edges;     // [P]
     std::vector<int32_t> phase_depth;     // [P] deepest star
 };
@@ -177,10 +186,11 @@ struct Schedule {
 // fits; P1 clamped to P0); force_p0 == -2 computes the phase assignment only.
 // whole_in_lds: every phase runs from LDS with node ids unchanged (all n
 // nodes staged; dummies n and n + 1) -- the batched form; the caller checks
-// that the graph fits.
+// that the graph fits.  pull_min_edges >= 0: whole-GPU phases of at least
+// that many edges are pulled (Schedule::pull); -1: none.
 void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, int32_t smax,
                     int64_t lds_bytes, int64_t l_bytes, int64_t force_p0, int64_t force_p1,
-                    Schedule &out, bool whole_in_lds = false);
+                    Schedule &out, bool whole_in_lds = false, int64_t pull_min_edges = -1);
 
 // --------------------------------------------------------------- kernels --
 typedef unsigned __int128 u128;

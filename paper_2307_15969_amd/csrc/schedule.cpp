@@ -289,7 +289,7 @@ struct CostModel {
 
 void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, int32_t smax,
                     int64_t lds_bytes, int64_t l_bytes, int64_t force_p0, int64_t force_p1,
-                    Schedule &out, bool whole_in_lds) {
+                    Schedule &out, bool whole_in_lds, int64_t pull_min_edges) {
     out = Schedule();
     if (smax > kMaxStar && force_p0 != -2) {
         // the device layout holds stars of up to kMaxStar leaves; callers that
@@ -783,39 +783,73 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
     // ---- stations -----------------------------------------------------------
     // Each node's stations in sweep order: one per whole-GPU phase it takes
     // part in (its lane as a center, its slot as a leaf), then its tail
-    // entry; each names the next and the last names the first.  Nodes on no
-    // edge get a home entry of their own, numbered in node order after the
-    // tail's entries.
+    // entry; each names where its updated load goes, the last one wrapping
+    // to the first.  A station of a pushed phase is where the node's load
+    // waits for it: its predecessor writes there.  A station of a pulled
+    // phase (a whole-GPU phase of at least pull_min_edges edges) instead
+    // reads the load from its predecessor's station, which keeps its own
+    // output: coalesced writes and random reads, where pushing scatters the
+    // writes.  Nodes on no edge get a home entry of their own, numbered in
+    // node order after the tail's entries.
+    std::vector<uint8_t> pulled((size_t)P, 0);
+    bool any_pull = false;
+    if (pull_min_edges >= 0)
+        for (int32_t p = 0; p < P1; ++p)
+            if (out.phase_edges[(size_t)p] >= pull_min_edges) pulled[(size_t)p] = 1, any_pull = true;
+    if (any_pull) {
+        out.pull.assign(pulled.begin(), pulled.end());
+        // rows and lanes of a pulled phase read their own entries unless a
+        // node's predecessor is named below (padding rows keep +inf there,
+        // empty lanes 0)
+        out.slot_src.resize((size_t)nslots);
+        out.center_src.resize(out.center_next.size());
+        for (int32_t p = 0; p < P1; ++p) {
+            if (!pulled[(size_t)p]) continue;
+            const PhaseDescWide &d = out.desc[(size_t)p];
+            int64_t rows = 0;
+            for (int k = 0; k < kMaxStar; ++k) rows += d.T[k];
+            for (int64_t sl = d.slot_base; sl < d.slot_base + rows * kWave; ++sl)
+                out.slot_src[(size_t)sl] = (uint32_t)sl;
+            for (int64_t li = (int64_t)d.tile0 * kWave; li < (int64_t)(d.tile0 + d.T[0]) * kWave; ++li)
+                out.center_src[(size_t)li] = (uint32_t)(out.center_base + li);
+        }
+    }
     auto set_next = [&](int64_t station, int64_t next) {
         if (station < out.center_base) out.slot_next[(size_t)station] = (uint32_t)next;
         else if (station < out.tail_base)
             out.center_next[(size_t)(station - out.center_base)] = (uint32_t)next;
         else out.tail_next[(size_t)(station - out.tail_base)] = (uint32_t)next;
     };
+    auto set_src = [&](int64_t station, int64_t from) {   // a pulled station's source
+        if (station < out.center_base) out.slot_src[(size_t)station] = (uint32_t)from;
+        else out.center_src[(size_t)(station - out.center_base)] = (uint32_t)from;
+    };
     out.home.assign((size_t)n, kNoStation);
     parallel_nodes(n, 2 * m, [&](int32_t v0, int32_t v1) {
+        std::vector<std::pair<int64_t, bool>> seq;   // (station, pulled)
         for (int32_t v = v0; v < v1; ++v) {
-            int64_t first = -1, prev = -1;
-            auto arrive = [&](int64_t station) {
-                if (prev < 0) first = station;
-                else set_next(prev, station);
-                prev = station;
-            };
+            seq.clear();
             const int64_t b = off[(size_t)v + 1];
             for (int64_t j = off[(size_t)v]; j < b;) {
                 const int32_t p = ph[(size_t)j];
                 int64_t k = j + 1;
                 while (k < b && ph[(size_t)k] == p) ++k;
                 if (p < P0)
-                    arrive(cen[(size_t)j] ? (int64_t)lane_station[(size_t)j]
-                                          : out.edge_slot[(size_t)at[(size_t)j]]);
+                    seq.emplace_back(cen[(size_t)j] ? (int64_t)lane_station[(size_t)j]
+                                                    : out.edge_slot[(size_t)at[(size_t)j]],
+                                     pulled[(size_t)p] != 0);
                 j = k;
             }
-            if (local[(size_t)v] >= 0) arrive(out.tail_base + local[(size_t)v]);
-            if (prev >= 0) {
-                set_next(prev, first);
-                out.home[(size_t)v] = (uint32_t)first;
+            if (local[(size_t)v] >= 0) seq.emplace_back(out.tail_base + local[(size_t)v], false);
+            const size_t k = seq.size();
+            if (k == 0) continue;
+            for (size_t i = 0; i < k; ++i) {
+                const auto &nx = seq[(i + 1) % k];
+                set_next(seq[i].first, nx.second ? seq[i].first : nx.first);
+                if (seq[i].second) set_src(seq[i].first, seq[(i + k - 1) % k].first);
             }
+            // where the load rests between sweeps: what the first station reads
+            out.home[(size_t)v] = (uint32_t)(seq[0].second ? seq[k - 1].first : seq[0].first);
         }
     });
     int64_t entries = out.tail_base + ntail_nodes;
@@ -827,6 +861,11 @@ void build_schedule(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
         fail(LOWD_E_UNSUPPORTED, "graph too large for 31-bit station indices");
     for (PhaseDescWide &d : out.desc) d.sink = (int32_t)entries;
     out.entries = entries + 1;
+    // every index a pulled phase gathers at lies in the entry array
+    for (const uint32_t x : out.slot_src)
+        if ((int64_t)x >= out.entries) fail(LOWD_E_HIP, "pull source out of range");
+    for (const uint32_t x : out.center_src)
+        if ((int64_t)x >= out.entries) fail(LOWD_E_HIP, "pull source out of range");
     // the orientation bit rides on the leaf slot's next station
     parallel_chunks(P0 < P ? out.desc[(size_t)P0].slot_base : nslots, [&](int, int64_t lo, int64_t hi) {
         for (int64_t sl = lo; sl < hi; ++sl)

@@ -190,9 +190,11 @@ struct SweepLaunch {
     void (*init_loads)(int32_t n, const int64_t *row_ptr, const uint32_t *inc, const float *w,
                        const uint32_t *home, const int32_t *big, int32_t nbig, int64_t entries,
                        int64_t center_base, void *E, hipStream_t s);
+    // slot_src / center_src: NULL for a pushed phase; for a pulled one the
+    // entries its slots and lanes read (Schedule::slot_src, center_src)
     void (*phase)(const PhaseDescWide &d, int64_t center_base, const uint32_t *center_next,
                   const uint32_t *slot_next, void *slot_x, const float *slot_w, void *E,
-                  hipStream_t s);
+                  const uint32_t *slot_src, const uint32_t *center_src, hipStream_t s);
     // the node form (loads in a node-indexed array; whole-GPU phases only)
     void (*phase_node)(const PhaseDescWide &d, const int32_t *tile_center,
                        const uint32_t *slot_leaf, void *slot_x, const float *slot_w, void *E,

@@ -385,3 +385,85 @@ def test_node_layout_f32k_and_solve(name, g, monkeypatch):
     _, Lo, _ = oracle_state(g, r64["sweeps"])
     assert r64["D"] == float(Lo.max())
     sv.close()
+
+
+# ------------------------------------------------------- pulled phases ----
+# Whole-GPU phases of at least LOWD_PULL_EDGES edges gather each node's load
+# from its previous station (which keeps its output) instead of receiving it
+# at their own; 0 pulls every whole-GPU phase, the other thresholds mix
+# pulled and pushed phases, so every transition (push to pull, pull to
+# push, pull to pull, and the wrap into the next sweep) occurs.
+PULL_GRAPHS = NODE_GRAPHS
+
+
+@pytest.mark.parametrize("tier", ["auto", "no_lds", "all_mid"])
+@pytest.mark.parametrize("pull_edges", [0, 300, 3000])
+@pytest.mark.parametrize("smax", [16, 32])
+@pytest.mark.parametrize("name,g", PULL_GRAPHS, ids=[n for n, _ in PULL_GRAPHS])
+def test_pulled_phases_sweep_bit_exact(name, g, smax, pull_edges, tier, monkeypatch):
+    """The same bits as the oracle's sequential loop with pulled whole-GPU
+    phases, across launches with eager work in between; D, the extraction,
+    and the initial state after a reset (each node's load where its first
+    station reads it) too."""
+    monkeypatch.setenv("LOWD_PULL_EDGES", str(pull_edges))
+    tail, mid = {"auto": (None, None), "no_lds": (1 << 30, 1 << 30), "all_mid": (1 << 30, 0)}[tier]
+    for var, v in (("LOWD_TAIL_SPLIT", tail), ("LOWD_MID_SPLIT", mid)):
+        if v is None:
+            monkeypatch.delenv(var, raising=False)
+        else:
+            monkeypatch.setenv(var, str(v))
+    sv = lowd.Solver(g.n, g.src, g.dst, g.w, "f64", star_max=smax)
+    info = sv.info()
+    log(f"pull {name} smax={smax} edges>={pull_edges} tier={tier}: {info}")
+    if pull_edges == 0:
+        assert info["pulled_phases"] == info["grid_phases"]
+    T = 7
+    sv.iterate(1)
+    sv.check()
+    sv.iterate(2)
+    sv.extract()
+    sv.iterate(T - 3)
+    x, L = sv.read_state()
+    xo, Lo, _ = oracle_state(g, T, smax=smax)
+    assert np.array_equal(L.cpu().numpy(), Lo), np.flatnonzero(L.cpu().numpy() != Lo)[:10]
+    assert np.array_equal(x.cpu().numpy(), xo)
+    assert sv.check()[0] == float(Lo.max())
+    ex = sv.extract()
+    ro = oracle.extract(g.n, g.src, g.dst, g.w, Lo)
+    assert np.array_equal(ex["in_set"].cpu().numpy(), ro["in_set"])
+    assert ex["den"] == ro["den"] and ex["num_w"] == ro["num_w"]
+    sv.reset()
+    x0, L0 = sv.read_state()
+    xi, Li = oracle.init(g.n, g.src, g.dst, g.w)
+    assert np.array_equal(x0.cpu().numpy(), xi) and np.array_equal(L0.cpu().numpy(), Li)
+    sv.iterate(2)
+    x2, L2 = sv.read_state()
+    xo2, Lo2, _ = oracle_state(g, 2, smax=smax)
+    assert np.array_equal(L2.cpu().numpy(), Lo2) and np.array_equal(x2.cpu().numpy(), xo2)
+    sv.close()
+
+
+@pytest.mark.parametrize("pull_edges", [0, 300])
+@pytest.mark.parametrize("name,g", PULL_GRAPHS, ids=[n for n, _ in PULL_GRAPHS])
+def test_pulled_phases_f32k_and_solve(name, g, pull_edges, monkeypatch):
+    """FP32K with pulled phases within 1e-5 of the FP64 oracle; the kept-load
+    screen, the resync from the fractions and the solve find the bound the
+    state's loads give; the FP64 solve's D is the oracle's."""
+    monkeypatch.setenv("LOWD_PULL_EDGES", str(pull_edges))
+    sv = lowd.Solver(g.n, g.src, g.dst, g.w, "f32k")
+    info = sv.info()
+    if pull_edges == 0:
+        assert info["pulled_phases"] == info["grid_phases"]
+    sv.iterate(6)
+    _, L = sv.read_state()
+    _, Lo, _ = oracle_state(g, 6)
+    assert np.max(np.abs(L.cpu().numpy() - Lo)) <= 1e-5 * np.max(np.abs(Lo))
+    sv.reset()
+    r = sv.solve(TOL)
+    assert r["converged"] and r["D"] == sv.check()[0]
+    sv.close()
+    sv = lowd.Solver(g.n, g.src, g.dst, g.w, "f64")
+    r64 = sv.solve(TOL)
+    _, Lo, _ = oracle_state(g, r64["sweeps"])
+    assert r64["D"] == float(Lo.max())
+    sv.close()
