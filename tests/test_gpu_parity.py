@@ -540,6 +540,75 @@ def test_repeated_pair_is_named_by_its_first_repeat(copies):
         assert f"at index {expect}:" in str(ei.value), str(ei.value)
 
 
+def _first_repeat(src, dst, n):
+    pair = np.minimum(src, dst).astype(np.int64) * n + np.maximum(src, dst)
+    _, first = np.unique(pair, return_index=True)
+    seen = np.zeros(src.size, bool)
+    seen[first] = True
+    return int(np.flatnonzero(~seen)[0])
+
+
+@pytest.mark.parametrize("where", ["hub_row", "hub_pair", "short_rows"])
+def test_prune_finds_a_repeated_pair_in_every_kind_of_row(where):
+    """A repeated pair is found by the prune's check of its edge list and
+    named by its first repeat, whether its smaller end is a hub of 3,000
+    neighbours (hub_row), both ends are (hub_pair), or neither (short_rows:
+    repeats planted at random places of an R-MAT edge list, in either
+    orientation); the same graph without the repeat prunes as the oracle
+    does."""
+    rng = np.random.default_rng(7)
+    n = 1 << 14
+    if where in ("hub_row", "hub_pair"):
+        g = synth.rmat(14, 16, seed=3)
+        src, dst = g.src.astype(np.int32), g.dst.astype(np.int32)
+        hub, hub2 = 5, 9
+        # two hubs of 3,000 neighbours each (pairs not yet in the graph)
+        have = set((np.minimum(src, dst).astype(np.int64) * n + np.maximum(src, dst)).tolist())
+        extra_s, extra_d = [], []
+        for h in (hub, hub2):
+            added = 0
+            for v in rng.permutation(n)[:6000].tolist():
+                if added == 3000:
+                    break
+                a, b = min(h, v), max(h, v)
+                if v != h and a * n + b not in have:
+                    have.add(a * n + b)
+                    extra_s.append(h)
+                    extra_d.append(v)
+                    added += 1
+        if hub * n + hub2 not in have:
+            extra_s.append(hub)
+            extra_d.append(hub2)
+        src = np.concatenate([src, np.array(extra_s, np.int32)])
+        dst = np.concatenate([dst, np.array(extra_d, np.int32)])
+        perm = rng.permutation(src.size)
+        src, dst = src[perm], dst[perm]
+        # no repeat yet: the prune runs and equals the oracle's
+        r = lowd.prune(n, src, dst)
+        keep, rounds, nh, mh = oracle.prune(n, src, dst)
+        assert np.array_equal(r["node_keep"].cpu().numpy(), keep) and r["m_h"] == mh
+        pair = (hub, int(extra_d[len(extra_d) // 3])) if where == "hub_row" else (hub2, hub)
+        cases = [pair]
+    else:
+        g = synth.rmat(14, 16, seed=4)
+        src, dst = g.src.astype(np.int32), g.dst.astype(np.int32)
+        cases = []
+        for k in range(4):
+            e = int(rng.integers(0, src.size))
+            cases.append((int(src[e]), int(dst[e])))
+    for a, b in cases:
+        pos = int(rng.integers(0, src.size + 1))
+        flip = bool(rng.integers(0, 2))
+        s2 = np.insert(src, pos, b if flip else a).astype(np.int32)
+        d2 = np.insert(dst, pos, a if flip else b).astype(np.int32)
+        expect = _first_repeat(s2, d2, n)
+        log(f"{where}: pair ({a}, {b}) again at {pos}, first repeat {expect}")
+        with pytest.raises(lowd.LowdError) as ei:
+            lowd.prune(n, s2, d2)
+        assert ei.value.status == -2
+        assert f"at index {expect}:" in str(ei.value), str(ei.value)
+
+
 # ------------------------------------------------- full-size workload ----
 def test_chunglu_1m_10m_fp64_is_bit_exact():
     """The benchmark workload at full size (Chung-Lu n=1M, ~10M edges,
