@@ -262,13 +262,14 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
         {
             sv->adj.alloc((size_t)(2 * m));
             build_adjacency(m, sv->csr, sv->e_src.p, sv->e_dst.p, sv->adj.p, s);
-            std::vector<int32_t> deg((size_t)n, 0), big;
-            for (int64_t e = 0; e < m; ++e) {
-                ++deg[(size_t)hs[(size_t)e]];
-                ++deg[(size_t)hd[(size_t)e]];
-            }
+            // the nodes of degree >= kBigRow, from the incidence rows' offsets
+            std::vector<int64_t> rp((size_t)n + 1);
+            LOWD_HIP(hipMemcpyAsync(rp.data(), sv->csr.row_ptr.p, rp.size() * sizeof(int64_t),
+                                    hipMemcpyDeviceToHost, s));
+            LOWD_HIP(hipStreamSynchronize(s));
+            std::vector<int32_t> big;
             for (int32_t u = 0; u < n; ++u)
-                if (deg[(size_t)u] >= kBigRow) big.push_back(u);
+                if (rp[(size_t)u + 1] - rp[(size_t)u] >= kBigRow) big.push_back(u);
             upload(sv->big, big, s);
             sv->nbig = (int32_t)big.size();
         }
