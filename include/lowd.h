@@ -411,7 +411,7 @@ lowd_status lowd_schedule_build(int32_t n, int64_t m, const int32_t *src, const 
  *        held in LDS, edges of the LDS phases, edges of the global-memory
  *        single-workgroup phases, state type, load layout (0: stations, 1:
  *        a node-indexed array), whole-GPU phases that pull their loads
- *        (phases of at least 2^20 edges, or LOWD_PULL_EDGES: each node's
+ *        (phases of at least 2^21 edges, or LOWD_PULL_EDGES: each node's
  *        load is read at its previous station, which keeps its output,
  *        instead of being written to its next one).
  */

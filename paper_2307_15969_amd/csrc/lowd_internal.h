@@ -84,8 +84,9 @@ constexpr uint32_t kNoStation = 0x7FFFFFFFu;
 // Whole-GPU phases of at least this many edges are pulled (Schedule::pull);
 // narrower ones, where the extra dependent round trip costs more than the
 // scattered writes, are pushed (pulling every phase of 64K edges or more
-// made a 64M-edge Chung-Lu sweep 4% slower; 2.2M-edge phases gain 7%).
-constexpr int64_t kPullMinEdges = (int64_t)1 << 20;
+// made a 64M-edge Chung-Lu sweep 4% slower, and its phases of 1M to 2M
+// edges lost a little too; uniform 2.2M-edge phases gain 7%).
+constexpr int64_t kPullMinEdges = (int64_t)1 << 21;
 
 // ------------------------------------------------------------- schedule --
 // Stars of a phase are sorted by size (descending) and dealt to tiles of 64,
