@@ -88,11 +88,11 @@ lowd_status lowd_prune(int32_t n, int64_t m, const int32_t *src, const int32_t *
  * lowd_prune_noalloc -- lowd_prune for callers that cannot allocate device
  * memory (tight serving loops, harnesses that forbid hipMalloc): the same
  * arguments, the same results bit for bit, but every device buffer of the
- * validation and the prune (incidence rows, degree buckets, sort and scan
- * scratch) comes from one file-scope device array of 128 MiB that each GPU
+ * validation and the prune (edge lists, degree buckets, radix pass and
+ * scan scratch) comes from one file-scope device array of 128 MiB that each GPU
  * holds from the library's load until the process ends; the call makes no
  * hipMalloc, hipFree or other allocating call.  A graph whose buffers would
- * exceed 128 MiB (about 32 bytes per edge plus 64 per node) is rejected
+ * exceed 128 MiB (about 29 bytes per edge plus 56 per node) is rejected
  * with LOWD_E_UNSUPPORTED before any device work.  Every call on one GPU
  * uses that GPU's one array and keeps what the last call left there, so
  * calls that overlap on one GPU (other threads, other streams) race: the

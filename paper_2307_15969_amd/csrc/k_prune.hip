@@ -4,17 +4,21 @@
 // degree: a round removes every node whose degree is below the current
 // density delta = |E(H)| / |V(H)|, and the nodes of the first round are
 // exactly a prefix of the degree-sorted order.  On the GPU:
-//   1. degrees from the incidence rows; an LDS-privatised degree histogram
-//      (4096 bins, the last one collecting larger degrees) and a wave-scan
+//   1. degrees: one stable radix pass groups the edges' ends by the top
+//      eight bits of the node id, then a workgroup counts a range of at
+//      most 32K node ids in LDS; an LDS-privatised degree histogram (4096
+//      bins, the last one collecting larger degrees) and a wave-scan
 //      exclusive prefix give the bucket starts; a scatter sorts the nodes by
 //      degree bucket;
 //   2. round 1 removes the bucket prefix below delta without looking at the
 //      other nodes; the surviving suffix becomes the alive list;
 //   3. every later round tests the alive list (deg * |V(H)| < |E(H)|, exact
-//      in int64), splits it with two prefix sums into the removed list and
-//      the next alive list, and walks the removed nodes' rows to lower their
-//      neighbours' degrees and count the removed edges;
-//   4. the kept nodes are renumbered by a prefix sum (ascending original id)
+//      in int64) and splits it with two prefix sums into the removed list
+//      and the next alive list;
+//   4. each round then walks the list of H's edges once: an edge with a
+//      removed end leaves H and lowers its other end's degree, the others
+//      form the next, shorter list (|E(H)| is its length);
+//   5. the kept nodes are renumbered by a prefix sum (ascending original id)
 //      and the kept edges compacted by another, in their original order.
 // The alive list shrinks quickly (the number of removed nodes decays
 // exponentially, as the paper observes), so the rounds after the first cost
@@ -32,10 +36,73 @@ namespace {
 
 constexpr int kBins = 4096;
 
-__global__ void k_degrees(int32_t n, const int64_t *row_ptr, int32_t *deg) {
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
-         u += (int64_t)gridDim.x * blockDim.x)
-        deg[u] = (int32_t)(row_ptr[u + 1] - row_ptr[u]);
+// Counts of node ids in [lo, lo + span) of one digit group: the group's ids
+// in two partitioned id arrays (ids in ka grouped by v >> gshift with group
+// starts sa, likewise kb and sb), counted in LDS.  Workgroup g takes group
+// g / (S * P), id range (g / P) % S of it, and piece g % P of the group's
+// ids.  The counts are stored in deg (sub = false) or taken off it (sub =
+// true); with P = 1 a workgroup owns its ids and writes them plainly,
+// otherwise it adds or subtracts with atomics (deg zeroed before, when
+// storing).
+constexpr int kCountBlock = 1024;
+__device__ __forceinline__ void count_id(uint32_t *cnt, uint32_t v, int64_t lo, int64_t hi) {
+    if ((int64_t)v >= lo && (int64_t)v < hi) atomicAdd(&cnt[(int64_t)v - lo], 1u);
+}
+constexpr int kCountBits = 15;   // at most 32K ids counted by a workgroup (128 KB of LDS)
+__global__ void __launch_bounds__(kCountBlock)
+k_count_ids(int32_t n, const uint32_t *ka, const int64_t *sa, const uint32_t *kb,
+            const int64_t *sb, int gshift, int span_bits, int32_t S, int32_t P, bool sub,
+            int32_t *deg) {
+    extern __shared__ uint32_t cnt[];
+    const int32_t g = (int32_t)blockIdx.x;
+    const int32_t grp = g / (S * P), r = (g / P) % S, piece = g % P;
+    const int64_t lo = ((int64_t)grp << gshift) + ((int64_t)r << span_bits);
+    const int64_t span = (int64_t)1 << span_bits;
+    const int64_t hi = lo + span < (int64_t)n ? lo + span : (int64_t)n;
+    if (lo >= hi) return;   // uniform across the block
+    for (int64_t i = threadIdx.x; i < span; i += kCountBlock) cnt[i] = 0;
+    __syncthreads();
+    for (int side = 0; side < 2; ++side) {
+        const uint32_t *keys = side ? kb : ka;
+        const int64_t *st = side ? sb : sa;
+        const int64_t b = st[grp], len = st[grp + 1] - b;
+        const int64_t p0 = b + len * piece / P, p1 = b + len * (piece + 1) / P;
+        // 16-byte loads, four in flight a lane, from the first 16-byte
+        // aligned key on; the ends one key at a time
+        const int64_t skip = (int64_t)((4u - (uint32_t)(((uintptr_t)(keys + p0) & 15u) >> 2)) & 3u);
+        const int64_t a0 = p0 + skip < p1 ? p0 + skip : p1;
+        const int64_t a1 = a0 + ((p1 - a0) & ~(int64_t)3);
+        for (int64_t i = p0 + threadIdx.x; i < a0; i += kCountBlock) count_id(cnt, keys[i], lo, hi);
+        for (int64_t i = a1 + threadIdx.x; i < p1; i += kCountBlock) count_id(cnt, keys[i], lo, hi);
+        constexpr int kU = 4;
+        const uint4 *vk = reinterpret_cast<const uint4 *>(keys + a0);
+        const int64_t nv = (a1 - a0) / 4;
+        for (int64_t j = threadIdx.x; j < nv; j += (int64_t)kU * kCountBlock) {
+            uint4 q[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+                q[u] = j + u * kCountBlock < nv ? vk[j + u * kCountBlock]
+                                                : make_uint4(~0u, ~0u, ~0u, ~0u);
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                count_id(cnt, q[u].x, lo, hi);
+                count_id(cnt, q[u].y, lo, hi);
+                count_id(cnt, q[u].z, lo, hi);
+                count_id(cnt, q[u].w, lo, hi);
+            }
+        }
+    }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < hi - lo; i += kCountBlock) {
+        const int32_t c = (int32_t)cnt[i];
+        if (P == 1) {
+            if (!sub) deg[lo + i] = c;
+            else if (c) deg[lo + i] -= c;
+        } else if (c) {
+            if (sub) atomicSub(&deg[lo + i], c);
+            else atomicAdd(&deg[lo + i], c);
+        }
+    }
 }
 
 __global__ void __launch_bounds__(256) k_degree_hist(int32_t n, const int32_t *deg,
@@ -111,14 +178,14 @@ __global__ void k_split(int64_t c, const int32_t *cand, const int64_t *rm, const
 // stamp[v]: 0 for an alive node, -(slot + 1) for an alive hub (below), r > 0
 // once removed in round r.
 // The kHubs highest-degree nodes (the tail of the degree-bucketed order) are
-// hubs: the removal kernel counts their lost edges per workgroup in LDS and
-// adds each count with one atomic, where the rounds' removed nodes would
-// otherwise send one atomic per edge to the same few degree counters.
+// hubs: the round kernel counts their lost edges per workgroup in LDS and
+// adds each count with one atomic, where the rounds' removed edges would
+// otherwise send one atomic each to the same few degree counters.
 constexpr int kHubs = 4096;
 
-// The removal kernel reads a neighbour's state from 2-bit marks, 16 nodes a
-// word (4 MB for 16M nodes, about an L2's size, where the stamps take 64 MB
-// and every read of one would go past the L2): dead, alive, removed in the
+// The round kernel reads an end's state from 2-bit marks, 16 nodes a word
+// (4 MB for 16M nodes, about an L2's size, where the stamps take 64 MB and
+// every read of one would go past the L2): dead, alive, removed in the
 // current round, alive hub.
 constexpr uint32_t kMarkDead = 0u, kMarkAlive = 1u, kMarkNow = 2u, kMarkHub = 3u;
 __device__ __forceinline__ uint32_t mark_of(const uint32_t *marks, int32_t v) {
@@ -156,64 +223,109 @@ __global__ void k_marks(int32_t n, const int32_t *stamp, uint32_t *marks, int32_
     }
 }
 
-// for each removed node (its row of neighbour ids): lower alive neighbours'
-// degrees; count each removed edge once (an edge between two nodes removed
-// this round by its smaller end).  A neighbour's state comes from its mark;
-// only a hub's stamp is read, for its slot.  G lanes walk one removed node's row (G = 1 for the many short rows
-// of the first round; a wave or the whole workgroup for the later rounds,
-// whose few removed nodes can have long rows).  The counts are summed per
-// wave after the loop, where the whole wave has reconverged, and added with
-// one atomic per wave.
-constexpr int kRemoveBlock = 256;
-constexpr int64_t kRemoveGrid = 2048;
-template <int G>
-__global__ void __launch_bounds__(kRemoveBlock) k_remove_edges(int64_t k, const int32_t *removed,
-                                                               const int64_t *row_ptr,
-                                                               const uint32_t *nbr,
-                                                               const int32_t *stamp,
-                                                               const uint32_t *marks,
-                                                               int32_t *deg,
-                                                               unsigned long long *gone,
-                                                               const int32_t *hubs,
-                                                               int32_t nhubs) {
-    constexpr int kGroups = kRemoveBlock / G;
+// One round over H's edge list (the original src/dst arrays in the first
+// round, packed (src, dst) pairs after it): every edge whose ends are both
+// still alive goes to the next list; every other one leaves H and its end
+// that stays loses a degree: a hub's loss is counted per workgroup in LDS
+// and added once at the end, any other end is written to the list of
+// decrements (counted by node afterwards, where an atomic per edge on the
+// degrees ran at about 14 G/s).  The list's ends are all alive when the
+// round starts, so a mark here is alive, hub or removed now.  A tile of
+// kRoundRows rows of 256 edges loads its ends and then their marks, all in
+// flight together; its kept edges and its decrements each take one range of
+// their list with one atomic, ranked by wave ballots (the order within the
+// lists does not matter: H's final edge list is compacted from the original
+// arrays).
+constexpr int kRoundBlock = 256, kRoundRows = 16;
+constexpr int kRoundWaves = kRoundBlock / kWave;
+constexpr int64_t kRoundTile = (int64_t)kRoundBlock * kRoundRows;
+constexpr int64_t kRoundGrid = 1024;
+__global__ void __launch_bounds__(kRoundBlock)
+k_prune_round(int64_t k, const int32_t *src, const int32_t *dst, const uint2 *in,
+              const uint32_t *marks, const int32_t *stamp, int32_t *deg, const int32_t *hubs,
+              int32_t nhubs, uint2 *out, uint32_t *dec, unsigned long long *counts) {
     __shared__ int32_t hub_lost[kHubs];
-    for (int i = threadIdx.x; i < kHubs; i += kRemoveBlock) hub_lost[i] = 0;
+    __shared__ int wcnt[2][kRoundRows][kRoundWaves];
+    __shared__ unsigned long long tile_base[2];
+    for (int i = threadIdx.x; i < kHubs; i += kRoundBlock) hub_lost[i] = 0;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+    const int64_t ntiles = (k + kRoundTile - 1) / kRoundTile;
     __syncthreads();
-    const int grp = threadIdx.x / G, lane = threadIdx.x % G;
-    unsigned long long cnt = 0;
-    for (int64_t i = (int64_t)blockIdx.x * kGroups + grp; i < k;
-         i += (int64_t)gridDim.x * kGroups) {
-        const int32_t u = removed[i];
-        const int64_t end = row_ptr[u + 1];
-        // four entries a lane at a time: their loads, then their marks,
-        // are independent and in flight together
-        constexpr int kU = 4;
-        for (int64_t j = row_ptr[u] + lane; j < end; j += kU * G) {
-            int32_t v[kU];
-            uint32_t mk[kU];
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {   // uniform across the block
+        int32_t a[kRoundRows], b[kRoundRows];
+        uint32_t ma[kRoundRows], mb[kRoundRows];
+        uint64_t bal[kRoundRows], dbal[kRoundRows];
 #pragma unroll
-            for (int q = 0; q < kU; ++q) v[q] = j + q * G < end ? (int32_t)nbr[j + q * G] : -1;
-#pragma unroll
-            for (int q = 0; q < kU; ++q) mk[q] = v[q] >= 0 ? mark_of(marks, v[q]) : kMarkDead;
-#pragma unroll
-            for (int q = 0; q < kU; ++q) {
-                if (mk[q] == kMarkAlive) {
-                    atomicSub(&deg[v[q]], 1);
-                    ++cnt;
-                } else if (mk[q] == kMarkHub) {
-                    atomicAdd(&hub_lost[-stamp[v[q]] - 1], 1);   // the hub's slot
-                    ++cnt;
-                } else if (mk[q] == kMarkNow && u < v[q]) {
-                    ++cnt;
+        for (int q = 0; q < kRoundRows; ++q) {
+            const int64_t e = t * kRoundTile + (int64_t)q * kRoundBlock + threadIdx.x;
+            a[q] = -1;
+            b[q] = -1;
+            if (e < k) {
+                if (in) {
+                    const uint2 pr = in[e];
+                    a[q] = (int32_t)pr.x;
+                    b[q] = (int32_t)pr.y;
+                } else {
+                    a[q] = src[e];
+                    b[q] = dst[e];
                 }
             }
         }
+#pragma unroll
+        for (int q = 0; q < kRoundRows; ++q) {
+            ma[q] = a[q] >= 0 ? mark_of(marks, a[q]) : kMarkDead;
+            mb[q] = b[q] >= 0 ? mark_of(marks, b[q]) : kMarkDead;
+        }
+#pragma unroll
+        for (int q = 0; q < kRoundRows; ++q) {
+            // alive and hub marks have the low bit, removed-now does not
+            const bool valid = a[q] >= 0;
+            const bool stays = valid && ((ma[q] & mb[q] & 1u) != 0);
+            const bool a_left = (ma[q] & 1u) != 0, b_left = (mb[q] & 1u) != 0;
+            const bool loses = valid && !stays && (a_left || b_left);
+            const uint32_t mv = a_left ? ma[q] : mb[q];
+            // the end that stays, kept in a[q] for the decrement list
+            if (loses && !a_left) a[q] = b[q];
+            if (loses && mv == kMarkHub) atomicAdd(&hub_lost[-stamp[a[q]] - 1], 1);   // its slot
+            bal[q] = __ballot(stays);
+            dbal[q] = __ballot(loses && mv != kMarkHub);
+            if (lane == 0) {
+                wcnt[0][q][wave] = __popcll(bal[q]);
+                wcnt[1][q][wave] = __popcll(dbal[q]);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 2) {
+            int total = 0;
+            for (int q = 0; q < kRoundRows; ++q)
+                for (int w = 0; w < kRoundWaves; ++w) total += wcnt[threadIdx.x][q][w];
+            tile_base[threadIdx.x] =
+                total ? atomicAdd(&counts[threadIdx.x], (unsigned long long)total) : 0ull;
+        }
+        __syncthreads();
+        unsigned long long base = tile_base[0], dbase = tile_base[1];
+#pragma unroll
+        for (int q = 0; q < kRoundRows; ++q) {
+            int before = 0, row = 0, dbefore = 0, drow = 0;
+            for (int w = 0; w < kRoundWaves; ++w) {
+                before += w < wave ? wcnt[0][q][w] : 0;
+                row += wcnt[0][q][w];
+                dbefore += w < wave ? wcnt[1][q][w] : 0;
+                drow += wcnt[1][q][w];
+            }
+            if ((bal[q] >> lane) & 1ull)
+                out[base + (unsigned long long)(before + __popcll(bal[q] & lt))] =
+                    make_uint2((uint32_t)a[q], (uint32_t)b[q]);
+            if ((dbal[q] >> lane) & 1ull)
+                dec[dbase + (unsigned long long)(dbefore + __popcll(dbal[q] & lt))] =
+                    (uint32_t)a[q];
+            base += (unsigned long long)row;
+            dbase += (unsigned long long)drow;
+        }
+        __syncthreads();   // wcnt and tile_base are reused by the next tile
     }
-    for (int o = kWave / 2; o > 0; o >>= 1) cnt += __shfl_down(cnt, o, kWave);
-    if ((threadIdx.x & (kWave - 1)) == 0 && cnt) atomicAdd(gone, cnt);
-    __syncthreads();
-    for (int i = threadIdx.x; i < nhubs; i += kRemoveBlock) {
+    for (int i = threadIdx.x; i < nhubs; i += kRoundBlock) {
         const int32_t c = hub_lost[i];
         if (c) atomicSub(&deg[hubs[i]], c);
     }
@@ -499,6 +611,80 @@ void fixed_point_weights(int64_t m, const float *w, uint64_t *wi, int32_t *q_out
     LOWD_HIP(hipGetLastError());
 }
 
+namespace {
+__global__ void k_whole_group(int64_t m, int64_t *starts) {
+    if (threadIdx.x == 0) {
+        starts[0] = 0;
+        starts[1] = m;
+    }
+}
+
+// Buffers of count_ids for up to `cap` ids a side.
+struct CountBufs {
+    uint32_t *pa, *pb;     // the two sides grouped by digit
+    int64_t *sa, *sb;      // group starts (257 each)
+    char *tmp;             // radix pass scratch
+    size_t tmp_bytes;
+};
+constexpr int kGroups = 256;
+CountBufs take_count_bufs(int64_t cap, Arena &ws) {
+    CountBufs c;
+    const size_t k = (size_t)(cap > 0 ? cap : 1);
+    c.pa = ws.take<uint32_t>(k);
+    c.pb = ws.take<uint32_t>(k);
+    c.sa = ws.take<int64_t>(kGroups + 1);
+    c.sb = ws.take<int64_t>(kGroups + 1);
+    c.tmp_bytes = radix_sort_tmp_bytes(cap);
+    c.tmp = ws.take<char>(c.tmp_bytes);
+    return c;
+}
+
+// deg[v] = (sub ? deg[v] - : ) the number of times v appears in a[0..na)
+// and b[0..nb) (b may be empty).  Node ids of more than kCountBits bits are
+// first grouped by their top eight bits (a stable radix pass over each
+// side), so that every workgroup of k_count_ids reads only the ids of its
+// group; a group's ids are split into pieces where one would exceed
+// kPieceIds.  Neither a nor b may lie in c.pa or c.pb.
+constexpr int64_t kPieceIds = (int64_t)1 << 22;
+void count_ids(int32_t n, const uint32_t *a, int64_t na, const uint32_t *b, int64_t nb,
+               int32_t *deg, bool sub, const CountBufs &c, hipStream_t s) {
+    if (n <= 0) return;
+    int bits = 1;
+    while (bits < 31 && ((int64_t)1 << bits) < (int64_t)n) ++bits;
+    const bool grouped = bits > kCountBits;
+    const int gshift = grouped ? bits - 8 : 0;
+    const int span_bits = grouped ? std::min(gshift, kCountBits) : bits;
+    const int32_t S = grouped ? (int32_t)1 << (gshift - span_bits) : 1;
+    const int32_t ngroups = grouped ? kGroups : 1;
+    if (grouped) {
+        radix_partition_u32(a, c.pa, na, gshift, c.sa, c.tmp, c.tmp_bytes, s);
+        radix_partition_u32(b, c.pb, nb, gshift, c.sb, c.tmp, c.tmp_bytes, s);
+    } else {
+        hipLaunchKernelGGL(k_whole_group, dim3(1), dim3(1), 0, s, na, c.sa);
+        hipLaunchKernelGGL(k_whole_group, dim3(1), dim3(1), 0, s, nb, c.sb);
+    }
+    std::vector<int64_t> ha((size_t)kGroups + 1), hb((size_t)kGroups + 1);
+    LOWD_HIP(hipMemcpyAsync(ha.data(), c.sa, (size_t)(ngroups + 1) * sizeof(int64_t),
+                            hipMemcpyDeviceToHost, s));
+    LOWD_HIP(hipMemcpyAsync(hb.data(), c.sb, (size_t)(ngroups + 1) * sizeof(int64_t),
+                            hipMemcpyDeviceToHost, s));
+    LOWD_HIP(hipStreamSynchronize(s));
+    int64_t most = 0;
+    for (int32_t g = 0; g < ngroups; ++g)
+        most = std::max<int64_t>(most, ha[g + 1] - ha[g] + hb[g + 1] - hb[g]);
+    const int32_t P = (int32_t)std::min<int64_t>(
+        std::max<int64_t>((most + kPieceIds - 1) / kPieceIds, 1), 256);
+    if (P > 1 && !sub) LOWD_HIP(hipMemsetAsync(deg, 0, (size_t)n * sizeof(int32_t), s));
+    const size_t lds = ((size_t)1 << span_bits) * sizeof(uint32_t);
+    LOWD_HIP(hipFuncSetAttribute((const void *)k_count_ids,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_count_ids, dim3((unsigned)((int64_t)ngroups * S * P)), dim3(kCountBlock),
+                       lds, s, n, grouped ? c.pa : a, c.sa, grouped ? c.pb : b, c.sb, gshift,
+                       span_bits, S, P, sub, deg);
+    LOWD_HIP(hipGetLastError());
+}
+}  // namespace
+
 // Every device buffer of the prune comes from `ws`, taken in a fixed order,
 // so a region without a base measures what a call needs (prune_ws_bytes).
 PruneResult run_prune_ws(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
@@ -506,22 +692,23 @@ PruneResult run_prune_ws(int32_t n, int64_t m, const int32_t *src, const int32_t
                          int64_t *edge_map, Arena &ws, hipStream_t s) {
     PruneResult res;
     const unsigned gn = grid_for(n, 256);
-    struct {
-        int64_t *row_ptr;
-        uint32_t *inc;
-    } csr;
-    build_incidence_ws(n, m, src, dst, ws, &csr.row_ptr, &csr.inc, true, s);   // neighbour ids
     const size_t nn = (size_t)n;
+    int32_t *deg = ws.take<int32_t>(nn);
+    const CountBufs cb = take_count_bufs(m, ws);
+    uint32_t *dec = ws.take<uint32_t>((size_t)(m > 0 ? m : 1));   // a round's decrements
     uint32_t *marks = ws.take<uint32_t>((nn + 15) / 16);
-    int32_t *deg = ws.take<int32_t>(nn), *stamp = ws.take<int32_t>(nn),
-            *by_deg = ws.take<int32_t>(nn), *list_a = ws.take<int32_t>(nn),
-            *list_b = ws.take<int32_t>(nn), *removed = ws.take<int32_t>(nn);
+    int32_t *stamp = ws.take<int32_t>(nn), *by_deg = ws.take<int32_t>(nn),
+            *list_a = ws.take<int32_t>(nn), *list_b = ws.take<int32_t>(nn),
+            *removed = ws.take<int32_t>(nn);
     unsigned long long *hist = ws.take<unsigned long long>(kBins),
                        *cursor = ws.take<unsigned long long>(kBins),
-                       *gone = ws.take<unsigned long long>(1);
+                       *counts = ws.take<unsigned long long>(2);
     int64_t *bin_start = ws.take<int64_t>(kBins), *f_rm = ws.take<int64_t>(nn),
             *f_keep = ws.take<int64_t>(nn), *p_rm = ws.take<int64_t>(nn),
             *p_keep = ws.take<int64_t>(nn), *tot = ws.take<int64_t>(2);
+    // H's edge list between rounds, twice (the rounds alternate)
+    uint2 *elist[2] = {ws.take<uint2>((size_t)(m > 0 ? m : 1)),
+                       ws.take<uint2>((size_t)(m > 0 ? m : 1))};
     int64_t big = std::max<int64_t>(std::max<int64_t>(n, compact_tiles(m)), kBins);
     const size_t scan_bytes = exclusive_scan_tmp_bytes(big);
     char *scan_tmp = ws.take<char>(scan_bytes);
@@ -532,7 +719,7 @@ PruneResult run_prune_ws(int32_t n, int64_t m, const int32_t *src, const int32_t
     int64_t *toff = edges_out ? ws.take<int64_t>((size_t)nt + 1) : nullptr;
     if (!ws.base) return res;   // measuring only
 
-    hipLaunchKernelGGL(k_degrees, dim3(gn), dim3(256), 0, s, n, csr.row_ptr, deg);
+    count_ids(n, (const uint32_t *)src, m, (const uint32_t *)dst, m, deg, false, cb, s);
     LOWD_HIP(hipMemsetAsync(hist, 0, kBins * sizeof(unsigned long long), s));
     LOWD_HIP(hipMemsetAsync(cursor, 0, kBins * sizeof(unsigned long long), s));
     LOWD_HIP(hipMemsetAsync(stamp, 0, (size_t)n * sizeof(int32_t), s));
@@ -586,31 +773,24 @@ PruneResult run_prune_ws(int32_t n, int64_t m, const int32_t *src, const int32_t
             nalive = t[1];
         }
         if (nrm == 0) break;
-        LOWD_HIP(hipMemsetAsync(gone, 0, sizeof(unsigned long long), s));
+        LOWD_HIP(hipMemsetAsync(counts, 0, 2 * sizeof(unsigned long long), s));
         const unsigned gr = grid_for(nrm, 256);
         hipLaunchKernelGGL(k_stamp, dim3(gr), dim3(256), 0, s, nrm, rm_list, stamp, round);
         hipLaunchKernelGGL(k_marks, dim3(gn), dim3(256), 0, s, n, stamp, marks, round);
-        // at most kRemoveGrid workgroups, each over many removed nodes, so
-        // that the hubs' LDS counts are added with few atomics
-        if (nrm >= (1 << 18))
-            hipLaunchKernelGGL(k_remove_edges<1>, dim3(grid_for(nrm, kRemoveBlock, kRemoveGrid)),
-                               dim3(kRemoveBlock), 0, s, nrm, rm_list, csr.row_ptr, csr.inc,
-                               stamp, marks, deg, gone, hubs, nhubs);
-        else if (nrm >= (1 << 12))
-            hipLaunchKernelGGL(k_remove_edges<kWave>,
-                               dim3(grid_for(nrm, kRemoveBlock / kWave, kRemoveGrid)),
-                               dim3(kRemoveBlock), 0, s, nrm, rm_list, csr.row_ptr, csr.inc,
-                               stamp, marks, deg, gone, hubs, nhubs);
-        else
-            hipLaunchKernelGGL(k_remove_edges<kRemoveBlock>, dim3(grid_for(nrm, 1, kRemoveGrid)),
-                               dim3(kRemoveBlock), 0, s, nrm, rm_list, csr.row_ptr, csr.inc,
-                               stamp, marks, deg, gone, hubs, nhubs);
+        // at most kRoundGrid workgroups, each over many tiles, so that the
+        // hubs' LDS counts are added with few atomics
+        const uint2 *in = round == 1 ? nullptr : elist[round & 1];
+        uint2 *out = elist[(round + 1) & 1];
+        hipLaunchKernelGGL(k_prune_round, dim3(grid_for(M, (int)kRoundTile, kRoundGrid)),
+                           dim3(kRoundBlock), 0, s, M, src, dst, in, marks, stamp, deg, hubs,
+                           nhubs, out, dec, counts);
         LOWD_HIP(hipGetLastError());
-        unsigned long long g = 0;
-        LOWD_HIP(hipMemcpyAsync(&g, gone, sizeof(g), hipMemcpyDeviceToHost, s));
+        unsigned long long c[2] = {0, 0};
+        LOWD_HIP(hipMemcpyAsync(c, counts, sizeof(c), hipMemcpyDeviceToHost, s));
         LOWD_HIP(hipStreamSynchronize(s));
+        if (c[1] > 0) count_ids(n, dec, (int64_t)c[1], nullptr, 0, deg, true, cb, s);
         N -= nrm;
-        M -= (int64_t)g;
+        M = (int64_t)c[0];
         res.rounds = round;
     }
 

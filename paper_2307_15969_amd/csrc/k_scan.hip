@@ -394,7 +394,42 @@ void radix_sort_impl(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, i
     *result_in_alt = in_alt;
 }
 
+// starts[d] = first position of digit d after a pass (the scanned block
+// histograms hold it at [d][0]); starts[kDigits] = n
+__global__ void k_digit_starts(const int64_t *hist, int64_t nb, int64_t n, int64_t *starts) {
+    const int d = threadIdx.x;
+    if (d < kDigits) starts[d] = hist[(int64_t)d * nb];
+    else if (d == kDigits) starts[kDigits] = n;
+}
+
 }  // namespace
+
+void radix_partition_u32(const uint32_t *keys, uint32_t *keys_out, int64_t n, int shift,
+                         int64_t *starts, void *tmp, size_t tmp_bytes, hipStream_t s) {
+    if (tmp_bytes < radix_sort_tmp_bytes(n)) fail(LOWD_E_ARG, "radix partition scratch too small");
+    if (n <= 0) {
+        LOWD_HIP(hipMemsetAsync(starts, 0, (kDigits + 1) * sizeof(int64_t), s));
+        return;
+    }
+    const int64_t tiles = radix_tiles(n), chunk = tiles * kRadixBlock;
+    const int64_t nb = cdiv(n, chunk), nh = nb * kDigits;
+    int64_t *hist = (int64_t *)tmp;
+    int64_t *scan_tmp = hist + nh;
+    const size_t scan_bytes = tmp_bytes - (size_t)nh * sizeof(int64_t);
+    hipLaunchKernelGGL(k_radix_hist<uint32_t>, dim3((unsigned)nb), dim3(kRadixBlock), 0, s, keys,
+                       n, shift, hist, nb, chunk);
+    exclusive_scan_i64(hist, hist, nh, nullptr, scan_tmp, scan_bytes, s);
+    if (tiles >= kRadixStagedTiles)
+        hipLaunchKernelGGL((k_radix_scatter_staged<uint32_t, false>), dim3((unsigned)nb),
+                           dim3(kRadixBlock), 0, s, keys, nullptr, keys_out, nullptr, n, shift,
+                           hist, nb, tiles);
+    else
+        hipLaunchKernelGGL((k_radix_scatter_tiles<uint32_t, false>), dim3((unsigned)nb),
+                           dim3(kRadixBlock), 0, s, keys, nullptr, keys_out, nullptr, n, shift,
+                           hist, nb, tiles);
+    hipLaunchKernelGGL(k_digit_starts, dim3(1), dim3(kDigits + 1), 0, s, hist, nb, n, starts);
+    LOWD_HIP(hipGetLastError());
+}
 
 // scratch of a scan of up to n values of up to 16 bytes
 size_t exclusive_scan_tmp_bytes(int64_t n) {

@@ -260,6 +260,12 @@ void radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t
                     int64_t n, int bits, void *tmp, size_t tmp_bytes, bool *result_in_alt,
                     hipStream_t s);
 size_t radix_sort_tmp_bytes(int64_t n);
+// One stable pass of that sort over keys alone, on the digit
+// (key >> shift) & 255: keys_out holds the keys grouped by digit, starts
+// (device, 257 entries) the first position of each digit and n at the end.
+// tmp: radix_sort_tmp_bytes(n).
+void radix_partition_u32(const uint32_t *keys, uint32_t *keys_out, int64_t n, int shift,
+                         int64_t *starts, void *tmp, size_t tmp_bytes, hipStream_t s);
 
 // Graph validation (k_graph.hip): first bad edge index or -1 in *bad_dev.
 void launch_validate(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,

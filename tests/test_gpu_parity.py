@@ -342,6 +342,42 @@ def test_prune_with_sorts_large_enough_to_stage():
     assert np.array_equal(r["edge_map"].cpu().numpy(), np.flatnonzero(ek))
 
 
+def _degree_count_shapes():
+    rng = np.random.default_rng(7)
+
+    def skewed(n, ids, k, power):
+        p = 1.0 / np.arange(1, ids.size + 1) ** power
+        p /= p.sum()
+        return synth.canonical(n, ids[rng.choice(ids.size, k, p=p)],
+                               ids[rng.choice(ids.size, k, p=p)])
+
+    # node ids of 25 bits: the ends are grouped by their top 8 bits and each
+    # group is counted in four id ranges of 32K
+    n1 = (1 << 24) + (1 << 22)
+    wide = skewed(n1, rng.choice(n1, 400_000, replace=False), 1_500_000, 0.8)
+    # 32,768 nodes (ids of 15 bits: one group) and over 4M ends: the group
+    # is counted in pieces whose counts are added
+    dense = skewed(1 << 15, rng.permutation(1 << 15), 3_000_000, 0.8)
+    return [("wide_ids", wide), ("dense_pieces", dense)]
+
+
+@pytest.mark.parametrize("name,g", _degree_count_shapes(), ids=["wide_ids", "dense_pieces"])
+def test_prune_degree_count_shapes(name, g):
+    """The degree count's two uncommon shapes: node ids wider than 24 bits
+    (several id ranges per group) and a group with more ends than one
+    workgroup counts (pieces added with atomics); the pruned graph equals
+    the oracle's."""
+    log(f"prune {name} n={g.n} m={g.m}")
+    assert 2 * g.m > (1 << 22) or g.n > (1 << 24)
+    r = lowd.prune(g.n, g.src, g.dst)
+    keep, rounds, nh, mh = oracle.prune(g.n, g.src, g.dst)
+    assert (r["rounds"], r["n_h"], r["m_h"]) == (rounds, nh, mh)
+    assert np.array_equal(r["node_keep"].cpu().numpy(), keep)
+    assert rounds >= 1 and 0 < nh < g.n
+    ek = (keep[g.src] == 1) & (keep[g.dst] == 1)
+    assert np.array_equal(r["edge_map"].cpu().numpy(), np.flatnonzero(ek))
+
+
 def test_prune_then_solve_finds_the_densest_set_of_g():
     g = synth.workload(0)
     r = lowd.prune(g.n, g.src, g.dst)
