@@ -667,6 +667,45 @@ def test_chunglu_1m_10m_fp64_is_bit_exact():
     assert np.array_equal(ex["in_set"].cpu().numpy(), ro["in_set"])
 
 
+def _digest(a) -> str:
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def test_rmat24_full_size_prune_and_three_sweeps():
+    """The headline workload at full size, in the benchmark's configuration:
+    R-MAT scale 24 (260M edges) pruned on the GPU, then the FP64 solver on H
+    with stars of at most 32 leaves, three sweeps.  The prune's rounds,
+    sizes and mask, the loads and fractions after three sweeps and the
+    densest prefix equal the oracle's, bit for bit (digests of the oracle's
+    results, written by tests/golden/make_rmat24_h.py from synth and the
+    oracle alone: its sequential schedule takes minutes at this size)."""
+    import json
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "rmat24_h.json")))
+    g = synth.rmat(24, 16, seed=1, device="cuda")
+    log(f"rmat24 n={g.n} m={g.m}")
+    src = torch.from_numpy(g.src).cuda()
+    dst = torch.from_numpy(g.dst).cuda()
+    del g
+    r = lowd.prune(1 << 24, src, dst)
+    gp = gold["prune"]
+    assert (r["rounds"], r["n_h"], r["m_h"]) == (gp["rounds"], gp["n_h"], gp["m_h"])
+    assert _digest(r["node_keep"].cpu().numpy()) == gp["node_keep_sha256"]
+    hs, hd = r["src"].clone(), r["dst"].clone()
+    del r, src, dst
+    sv = lowd.Solver(gp["n_h"], hs, hd, None, "f64", star_max=gold["star_max"])
+    log(f"  H {gp['n_h']} / {gp['m_h']}, {sv.info()['phases']} phases")
+    assert sv.info()["phases"] == gold["phases"]
+    sv.iterate(gold["sweeps"])
+    x, L = gpu_state(sv)
+    assert _digest(L) == gold["loads_sha256"]
+    assert _digest(x) == gold["fractions_sha256"]
+    ex = sv.extract()
+    ge = gold["extract"]
+    assert (ex["num"], ex["den"]) == (ge["num"], ge["den"])
+    assert _digest(ex["in_set"].cpu().numpy().astype(np.uint8)) == ge["in_set_sha256"]
+
+
 # ------------------------------------------------- weighted pruning --
 def _weighted_prune_graphs():
     rng = np.random.default_rng(17)
