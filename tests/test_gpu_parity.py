@@ -706,6 +706,52 @@ def test_rmat24_full_size_prune_and_three_sweeps():
     assert _digest(ex["in_set"].cpu().numpy().astype(np.uint8)) == ge["in_set_sha256"]
 
 
+def test_chunglu4m_full_size_fp64_and_f32k():
+    """The FP32-compensated workload at full size (Chung-Lu n=4M, about 63M
+    log-normal weights, stars of at most 16 leaves), 22 sweeps as the
+    benchmark's solve takes: the FP64 path's loads and fractions equal the
+    oracle's bit for bit; the FP32K path's loads lie within 1e-5 of the
+    largest load on 4,096 nodes (the 2,048 largest and 2,048 drawn), its D
+    from the recomputed loads within 1e-5 and its load sum within 1e-9 of
+    the oracle's; both give the oracle's densest prefix (digests and exact
+    values from tests/golden/make_chunglu4m.py: synth and the oracle
+    alone)."""
+    import json
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "chunglu4m.json")))
+    g = synth.workload(2, seed=1)
+    log(f"chunglu4m n={g.n} m={g.m}")
+    assert (g.n, g.m) == (gold["n"], gold["m"])
+    src = torch.from_numpy(g.src).cuda()
+    dst = torch.from_numpy(g.dst).cuda()
+    w = torch.from_numpy(g.w).cuda()
+    nodes = np.array(gold["sample_nodes"], dtype=np.int64)
+    lo = np.array([float.fromhex(v) for v in gold["sample_loads"]])
+    Do, so = float.fromhex(gold["D"]), float.fromhex(gold["load_sum"])
+    ge = gold["extract"]
+    T = gold["sweeps"]
+    for state in ("f64", "f32k"):
+        sv = lowd.Solver(g.n, src, dst, w, state, star_max=gold["star_max"])
+        assert sv.info()["phases"] == gold["phases"]
+        sv.iterate(T)
+        x, L = gpu_state(sv)
+        if state == "f64":
+            assert _digest(L) == gold["loads_sha256"]
+            assert _digest(x) == gold["fractions_sha256"]
+        else:
+            err = np.max(np.abs(L[nodes] - lo)) / Do
+            log(f"  f32k: max load error on the sample {err:.3e} of the largest load")
+            assert err <= 1e-5
+            D, s, _ = sv.check()
+            assert abs(D - Do) <= 1e-5 * Do
+            assert abs(s - so) <= 1e-9 * so
+        ex = sv.extract()
+        sv.close()
+        log(f"  {state}: densest prefix {ex['num_w']}/{ex['den']}")
+        assert (ex["num"], ex["den"]) == (ge["num"], ge["den"])
+        assert ex["num_w"] == float.fromhex(ge["num_w"])
+        assert _digest(ex["in_set"].cpu().numpy().astype(np.uint8)) == ge["in_set_sha256"]
+
+
 # ------------------------------------------------- weighted pruning --
 def _weighted_prune_graphs():
     rng = np.random.default_rng(17)
