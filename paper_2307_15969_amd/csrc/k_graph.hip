@@ -33,18 +33,6 @@ __global__ void k_incidence_keys(int64_t m, const int32_t *src, const int32_t *d
     }
 }
 
-// the same with each entry's value the edge's other end
-__global__ void k_incidence_neighbours(int64_t m, const int32_t *src, const int32_t *dst,
-                                       uint32_t *keys, uint32_t *vals) {
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < 2 * m;
-         j += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t e = j >> 1;
-        const uint32_t a = (uint32_t)src[e], b = (uint32_t)dst[e];
-        keys[j] = (j & 1) ? b : a;
-        vals[j] = (j & 1) ? a : b;
-    }
-}
-
 // row_ptr[u] = first position of key u in the sorted keys (lower bound)
 __global__ void k_row_ptr(const uint32_t *sorted, int64_t len, int32_t n, int64_t *row_ptr) {
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u <= n;
@@ -91,46 +79,6 @@ void build_adjacency(int64_t m, const Csr &csr, const int32_t *src, const int32_
     hipLaunchKernelGGL(k_adjacency, dim3(grid_for(2 * m, 256)), dim3(256), 0, s, 2 * m,
                        csr.inc.p, src, dst, adj);
     LOWD_HIP(hipGetLastError());
-}
-
-void build_incidence_ws(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, Arena &ws,
-                        int64_t **row_ptr, uint32_t **inc, bool neighbours, hipStream_t s) {
-    const int64_t len = 2 * m;
-    const size_t cap = (size_t)(len > 0 ? len : 1);
-    *row_ptr = ws.take<int64_t>((size_t)n + 1);
-    *inc = ws.take<uint32_t>(cap);
-    const size_t mk = ws.mark();
-    uint32_t *k0 = ws.take<uint32_t>(cap), *k1 = ws.take<uint32_t>(cap);
-    uint32_t *vt = ws.take<uint32_t>(cap);
-    const size_t tmp_bytes = radix_sort_tmp_bytes(len);
-    char *tmp = ws.take<char>(tmp_bytes);
-    if (ws.base) {
-        int bits = 1;
-        while (bits < 32 && ((int64_t)1 << bits) < (int64_t)n) ++bits;
-        // the sort makes one pass per 8 bits and ends in its second buffers
-        // after an odd number of them: start the values where they end in inc
-        const bool odd = len > 1 && ((bits + 7) / 8) % 2 == 1;
-        uint32_t *v_in = odd ? vt : *inc, *v_alt = odd ? *inc : vt;
-        if (len > 0) {
-            if (neighbours)
-                hipLaunchKernelGGL(k_incidence_neighbours, dim3(grid_for(len, 256)), dim3(256), 0,
-                                   s, m, src, dst, k0, v_in);
-            else
-                hipLaunchKernelGGL(k_incidence_keys, dim3(grid_for(len, 256)), dim3(256), 0, s, m,
-                                   src, dst, k0, v_in);
-        }
-        bool alt = false;
-        radix_sort_u32(k0, v_in, k1, v_alt, len, bits, tmp, tmp_bytes, &alt, s);
-        const uint32_t *keys = alt ? k1 : k0;
-        hipLaunchKernelGGL(k_row_ptr, dim3(grid_for((int64_t)n + 1, 256)), dim3(256), 0, s, keys,
-                           len, n, *row_ptr);
-        if ((alt ? v_alt : v_in) != *inc && len > 0)
-            LOWD_HIP(hipMemcpyAsync(*inc, alt ? v_alt : v_in, (size_t)len * sizeof(uint32_t),
-                                    hipMemcpyDeviceToDevice, s));
-        LOWD_HIP(hipGetLastError());
-        LOWD_HIP(hipStreamSynchronize(s));
-    }
-    ws.release(mk);
 }
 
 void build_incidence(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, Csr &csr,

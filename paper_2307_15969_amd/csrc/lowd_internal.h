@@ -289,11 +289,6 @@ struct Csr {
 };
 void build_incidence(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, Csr &csr,
                      hipStream_t s);
-// The same into row_ptr [n+1] and inc [2m] taken from `ws` (its sort
-// buffers taken after them and released again); with `neighbours` each
-// entry holds the edge's other end instead of (edge << 1 | side).
-void build_incidence_ws(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, Arena &ws,
-                        int64_t **row_ptr, uint32_t **inc, bool neighbours, hipStream_t s);
 // adj[j] = the other end of the edge of incidence entry j ([2m])
 void build_adjacency(int64_t m, const Csr &csr, const int32_t *src, const int32_t *dst,
                      int32_t *adj, hipStream_t s);
