@@ -76,26 +76,19 @@ static size_t lds_capacity_bytes() {
 // without a base only measures them.
 static void validate_graph_ws(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
                               const float *w, Arena &ws, hipStream_t s) {
-    const size_t mk = ws.mark();
-    int64_t *bad = ws.take<int64_t>(1);
-    int64_t b = -1;
-    if (ws.base) {
-        launch_validate(n, m, src, dst, w, bad, s);
-        LOWD_HIP(hipMemcpyAsync(&b, bad, sizeof(b), hipMemcpyDeviceToHost, s));
-        LOWD_HIP(hipStreamSynchronize(s));
-    }
-    const bool in_range = (uint64_t)b == ~0ull;
-    if (in_range || !ws.base) b = find_duplicate_pair_ws(n, m, src, dst, ws, s);
-    ws.release(mk);
-    if (b >= 0 && (uint64_t)b != ~0ull) {
+    int64_t invalid = -1;
+    const int64_t b = find_duplicate_pair_ws(n, m, src, dst, ws, s, w, &invalid);
+    const bool repeated = invalid < 0;
+    const int64_t at = repeated ? b : invalid;
+    if (at >= 0) {
         int32_t a = 0, c = 0;
         float x = 1.0f;
-        LOWD_HIP(hipMemcpyAsync(&a, src + b, 4, hipMemcpyDeviceToHost, s));
-        LOWD_HIP(hipMemcpyAsync(&c, dst + b, 4, hipMemcpyDeviceToHost, s));
-        if (w) LOWD_HIP(hipMemcpyAsync(&x, w + b, 4, hipMemcpyDeviceToHost, s));
+        LOWD_HIP(hipMemcpyAsync(&a, src + at, 4, hipMemcpyDeviceToHost, s));
+        LOWD_HIP(hipMemcpyAsync(&c, dst + at, 4, hipMemcpyDeviceToHost, s));
+        if (w) LOWD_HIP(hipMemcpyAsync(&x, w + at, 4, hipMemcpyDeviceToHost, s));
         LOWD_HIP(hipStreamSynchronize(s));
-        fail(LOWD_E_GRAPH, std::string(in_range ? "repeated pair" : "invalid edge") +
-                               " at index " + std::to_string(b) + ": (" + std::to_string(a) +
+        fail(LOWD_E_GRAPH, std::string(repeated ? "repeated pair" : "invalid edge") +
+                               " at index " + std::to_string(at) + ": (" + std::to_string(a) +
                                ", " + std::to_string(c) + ") weight " + std::to_string(x) +
                                " (n = " + std::to_string(n) + ")");
     }

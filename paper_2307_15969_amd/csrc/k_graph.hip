@@ -163,11 +163,24 @@ __device__ inline uint64_t pair_mix(uint64_t x) {
     return x ^ (x >> 31);
 }
 
+// The bucketed keys; with `bad` the same pass also checks each edge as
+// k_validate does (the keys of an invalid edge are never sorted: the check
+// stops there).
 __global__ void k_bucketed_pair_keys(int64_t m, const int32_t *src, const int32_t *dst, int nb,
-                                     int bits, uint64_t *keys) {
+                                     int bits, uint64_t *keys, int32_t n, const float *w,
+                                     unsigned long long *bad) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
          e += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t a = (uint32_t)src[e], b = (uint32_t)dst[e];
+        const int32_t sa = src[e], sb = dst[e];
+        if (bad) {
+            bool ok = sa >= 0 && sa < n && sb >= 0 && sb < n && sa != sb;
+            if (w) {
+                const float x = w[e];
+                ok = ok && (x > 0.0f) && (x <= 3.402823466e38f);   // positive and finite
+            }
+            if (!ok) atomicMin(bad, (unsigned long long)e);
+        }
+        const uint64_t a = (uint32_t)sa, b = (uint32_t)sb;
         const uint64_t pair = a < b ? (a << nb) | b : (b << nb) | a;
         keys[e] = (pair << bits) | (pair_mix(pair) >> (64 - bits));
     }
@@ -229,10 +242,29 @@ __global__ void __launch_bounds__(kRepeatBlock)
 // Whether any pair repeats is decided first, by hash buckets (a radix sort
 // of 8 to 24 bucket bits) or, where the ids are too wide for them or a
 // bucket is too large, by a sort of the packed pairs; only when a pair
-// repeats does an indexed sort of the pairs name the edge.
+// repeats does an indexed sort of the pairs name the edge.  With `invalid`
+// the edges are first checked as launch_validate does (in the pass that
+// forms the bucketed keys, where the pairs are bucketed): *invalid receives
+// the first invalid edge or -1, and the search for repeats runs only when
+// there is none.
 int64_t find_duplicate_pair_ws(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
-                               Arena &ws, hipStream_t s) {
-    if (m < 2) return -1;
+                               Arena &ws, hipStream_t s, const float *w, int64_t *invalid) {
+    if (invalid) *invalid = -1;
+    if (m < 2) {
+        if (invalid && m > 0 && ws.base) {
+            const size_t mk = ws.mark();
+            int64_t *bad = ws.take<int64_t>(1);
+            launch_validate(n, m, src, dst, w, bad, s);
+            int64_t b = -1;
+            LOWD_HIP(hipMemcpyAsync(&b, bad, sizeof(b), hipMemcpyDeviceToHost, s));
+            LOWD_HIP(hipStreamSynchronize(s));
+            if ((uint64_t)b != ~0ull) *invalid = b;
+            ws.release(mk);
+        } else if (invalid && m > 0) {
+            (void)ws.take<int64_t>(1);
+        }
+        return -1;
+    }
     int nb = 1;
     while (nb < 32 && ((int64_t)1 << nb) < (int64_t)n) ++nb;
     // bucket bits: buckets of at most about 2,048 pairs on average (well
@@ -263,8 +295,21 @@ int64_t find_duplicate_pair_ws(int32_t n, int64_t m, const int32_t *src, const i
             }();
             (void)lds_set;
             LOWD_HIP(hipMemcpyAsync(flags, zero, sizeof(zero), hipMemcpyHostToDevice, s));
+            const unsigned long long none = ~0ull;
+            if (invalid)
+                LOWD_HIP(hipMemcpyAsync(bad, &none, sizeof(none), hipMemcpyHostToDevice, s));
             hipLaunchKernelGGL(k_bucketed_pair_keys, dim3(grid_for(m, 256)), dim3(256), 0, s, m,
-                               src, dst, nb, bits, k0);
+                               src, dst, nb, bits, k0, n, w, invalid ? bad : nullptr);
+            if (invalid) {
+                unsigned long long b = ~0ull;
+                LOWD_HIP(hipMemcpyAsync(&b, bad, sizeof(b), hipMemcpyDeviceToHost, s));
+                LOWD_HIP(hipStreamSynchronize(s));
+                if (b != ~0ull) {
+                    *invalid = (int64_t)b;
+                    ws.release(mk);
+                    return -1;
+                }
+            }
             bool alt = false;
             radix_sort_u64(k0, nullptr, k1, nullptr, m, bits, tmp, tmp_bytes, &alt, s);
             const uint64_t *keys = alt ? k1 : k0;
@@ -276,6 +321,17 @@ int64_t find_duplicate_pair_ws(int32_t n, int64_t m, const int32_t *src, const i
             LOWD_HIP(hipGetLastError());
             LOWD_HIP(hipMemcpyAsync(found, flags, sizeof(found), hipMemcpyDeviceToHost, s));
             LOWD_HIP(hipStreamSynchronize(s));
+        }
+        if (!bucketed && invalid) {
+            launch_validate(n, m, src, dst, w, (int64_t *)bad, s);
+            unsigned long long b = ~0ull;
+            LOWD_HIP(hipMemcpyAsync(&b, bad, sizeof(b), hipMemcpyDeviceToHost, s));
+            LOWD_HIP(hipStreamSynchronize(s));
+            if (b != ~0ull) {
+                *invalid = (int64_t)b;
+                ws.release(mk);
+                return -1;
+            }
         }
         if (found[1]) {
             // the packed keys alone, sorted (2 nb bits)

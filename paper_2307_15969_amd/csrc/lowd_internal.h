@@ -273,9 +273,13 @@ void launch_validate(int32_t n, int64_t m, const int32_t *src, const int32_t *ds
 // Index of the later edge of the first repeated unordered pair, or -1.
 int64_t find_duplicate_pair(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
                             hipStream_t s);
-// The same with its sort buffers taken from `ws` (released again on return).
+// The same with its sort buffers taken from `ws` (released again on return);
+// with `invalid` it also checks the edges as launch_validate does (w: the
+// weights or NULL), *invalid = the first invalid edge or -1, and looks for
+// a repeat only when there is none.
 int64_t find_duplicate_pair_ws(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
-                               Arena &ws, hipStream_t s);
+                               Arena &ws, hipStream_t s, const float *w = nullptr,
+                               int64_t *invalid = nullptr);
 // Incidence CSR, rows in ascending edge index: entry j = 2*e + side
 // (side 0: the row node is src[e]; side 1: dst[e]).  row_ptr has n+1 entries.
 // Rows (incidence rows, i.e. node degrees) of at least this length are

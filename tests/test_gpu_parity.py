@@ -523,8 +523,13 @@ def test_batch_degenerate_graphs_and_tiny_batches():
     ([0, 1], [1, 2], [1.0, float("nan")], "nan weight"),
     ([0, 1], [1, 2], [1.0, -2.0], "negative weight"),
     ([0, 2], [1, 1], None, "reversed duplicate is fine"),
+    ([3], [3], None, "single self-loop"),
+    ([0], [7], None, "single out of range"),
+    ([0, 0, 1], [1, 1, 1], None, "repeated pair before a self-loop"),
 ])
 def test_invalid_graphs_are_rejected(src, dst, w, what):
+    """Every kind of invalid edge list is rejected, and the message names the
+    first invalid edge ahead of any repeated pair."""
     args = (5, np.array(src, np.int32), np.array(dst, np.int32),
             None if w is None else np.array(w, np.float32))
     if what.endswith("fine"):
@@ -533,6 +538,10 @@ def test_invalid_graphs_are_rejected(src, dst, w, what):
     with pytest.raises(lowd.LowdError) as ei:
         lowd.Solver(*args)
     assert ei.value.status == -2, what
+    kind = "repeated pair" if what == "repeated" else "invalid edge"
+    assert kind in str(ei.value), (what, str(ei.value))
+    if what == "repeated pair before a self-loop":
+        assert "at index 2:" in str(ei.value)
 
 
 def test_repeated_pair_in_reverse_orientation_is_rejected():
