@@ -308,6 +308,8 @@ PRUNE_GRAPHS = [("workload0", synth.workload(0)),
                 ("chunglu20k", GRAPHS[2][1]),
                 ("gnp", synth.random_small(np.random.default_rng(1), 400, 0.03)),
                 ("empty", synth.canonical(7, np.zeros(0, np.int64), np.zeros(0, np.int64))),
+                ("one_edge", synth.canonical(3, np.array([2]), np.array([0]))),
+                ("star", synth.canonical(5000, np.zeros(4999, np.int64), np.arange(1, 5000))),
                 ("rmat14", synth.rmat(14, 16, seed=2))]
 
 
@@ -358,15 +360,26 @@ def _degree_count_shapes():
     # 32,768 nodes (ids of 15 bits: one group) and over 4M ends: the group
     # is counted in pieces whose counts are added
     dense = skewed(1 << 15, rng.permutation(1 << 15), 3_000_000, 0.8)
-    return [("wide_ids", wide), ("dense_pieces", dense)]
+    # 8,192 core nodes and 24,576 others joined to about 400 core nodes each:
+    # the first round removes the others, and the degrees lost by the core
+    # nodes outside the 4,096 hubs (about 4.7M) are taken off in pieces
+    r2 = np.random.default_rng(11)
+    n3, core = 1 << 15, 8192
+    per = np.repeat(np.arange(core, n3), 400)
+    pieces = synth.canonical(
+        n3, np.concatenate([r2.integers(0, core, 4_200_000), per]),
+        np.concatenate([r2.integers(0, core, 4_200_000), r2.integers(0, core, per.size)]))
+    return [("wide_ids", wide), ("dense_pieces", dense), ("decrement_pieces", pieces)]
 
 
-@pytest.mark.parametrize("name,g", _degree_count_shapes(), ids=["wide_ids", "dense_pieces"])
+@pytest.mark.parametrize("name,g", _degree_count_shapes(),
+                         ids=["wide_ids", "dense_pieces", "decrement_pieces"])
 def test_prune_degree_count_shapes(name, g):
-    """The degree count's two uncommon shapes: node ids wider than 24 bits
-    (several id ranges per group) and a group with more ends than one
-    workgroup counts (pieces added with atomics); the pruned graph equals
-    the oracle's."""
+    """The degree count's uncommon shapes: node ids wider than 24 bits
+    (several id ranges per group), a group with more ends than one workgroup
+    counts (pieces added with atomics), and a round whose decrements need
+    such pieces (taken off with atomics); the pruned graph equals the
+    oracle's."""
     log(f"prune {name} n={g.n} m={g.m}")
     assert 2 * g.m > (1 << 22) or g.n > (1 << 24)
     r = lowd.prune(g.n, g.src, g.dst)
