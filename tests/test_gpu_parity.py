@@ -726,6 +726,13 @@ def test_rmat24_full_size_prune_and_three_sweeps():
     ge = gold["extract"]
     assert (ex["num"], ex["den"]) == (ge["num"], ge["den"])
     assert _digest(ex["in_set"].cpu().numpy().astype(np.uint8)) == ge["in_set_sha256"]
+    # the benchmark's solve (lowd_solve to a certified 1e-6 gap) stops after
+    # those three sweeps with that set
+    sv.reset()
+    r = sv.solve(1e-6)
+    assert r["converged"] and r["gap"] <= 1e-6 and r["sweeps"] == gold["sweeps"]
+    assert (r["num"], r["den"]) == (ge["num"], ge["den"])
+    assert _digest(r["in_set"].cpu().numpy().astype(np.uint8)) == ge["in_set_sha256"]
 
 
 def test_chunglu4m_full_size_fp64_and_f32k():
@@ -767,11 +774,20 @@ def test_chunglu4m_full_size_fp64_and_f32k():
             assert abs(D - Do) <= 1e-5 * Do
             assert abs(s - so) <= 1e-9 * so
         ex = sv.extract()
-        sv.close()
         log(f"  {state}: densest prefix {ex['num_w']}/{ex['den']}")
         assert (ex["num"], ex["den"]) == (ge["num"], ge["den"])
         assert ex["num_w"] == float.fromhex(ge["num_w"])
         assert _digest(ex["in_set"].cpu().numpy().astype(np.uint8)) == ge["in_set_sha256"]
+        # the benchmark's solve to a certified 1e-6 gap ends on the same set
+        sv.reset()
+        r = sv.solve(1e-6)
+        sv.close()
+        log(f"  {state}: solve {r['sweeps']} sweeps, gap {r['gap']:.2e}")
+        assert r["converged"] and r["gap"] <= 1e-6
+        if state == "f64":
+            assert r["sweeps"] == T
+        assert (r["num"], r["den"], r["num_w"]) == (ge["num"], ge["den"], float.fromhex(ge["num_w"]))
+        assert _digest(r["in_set"].cpu().numpy().astype(np.uint8)) == ge["in_set_sha256"]
 
 
 # ------------------------------------------------- weighted pruning --
