@@ -141,6 +141,7 @@ struct lowd_solver {
     // weighted: each weight over 2^wq as an exact integer (the extraction's
     // densities are decided exactly)
     DBuf<uint64_t> e_wi;
+    DBuf<uint64_t> e_wi_inc;   // [2m] weighted: e_wi of each incidence entry's edge
     int32_t wq = 0;
     Csr csr;
     // schedule layout
@@ -252,6 +253,10 @@ lowd_status lowd_init_loads(int32_t n, int64_t m, const int32_t *src, const int3
             fixed_point_weights(m, sv->e_w.p, sv->e_wi.p, &sv->wq, range.p, s);
         }
         build_incidence(n, m, sv->e_src.p, sv->e_dst.p, sv->csr, s);
+        if (sv->weighted) {
+            sv->e_wi_inc.alloc((size_t)(2 * m));
+            build_entry_weights(m, sv->csr.inc.p, sv->e_wi.p, sv->e_wi_inc.p, s);
+        }
         {
             sv->adj.alloc((size_t)(2 * m));
             build_adjacency(m, sv->csr, sv->e_src.p, sv->e_dst.p, sv->adj.p, s);
@@ -427,6 +432,7 @@ static void extract_api(lowd_solver *sv, bool kept, uint8_t *in_set, int64_t *nu
     a.dst = sv->e_dst.p;
     a.w = sv->weighted ? sv->e_w.p : nullptr;
     a.wi = sv->weighted ? sv->e_wi.p : nullptr;
+    a.wi_inc = sv->weighted ? sv->e_wi_inc.p : nullptr;
     a.wq = sv->wq;
     if (sv->m > 0) {
         a.adj = sv->adj.p;
@@ -748,6 +754,7 @@ lowd_status lowd_ldd_readout(lowd_solver *sv, int32_t *level, int64_t *k_end, do
         a.dst = sv->e_dst.p;
         a.w = sv->weighted ? sv->e_w.p : nullptr;
         a.wi = sv->weighted ? sv->e_wi.p : nullptr;
+        a.wi_inc = sv->weighted ? sv->e_wi_inc.p : nullptr;
         a.wq = sv->wq;
         if (sv->m > 0) {
             a.adj = sv->adj.p;

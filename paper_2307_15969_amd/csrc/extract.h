@@ -19,6 +19,7 @@ struct ExtractArgs {
     const int32_t *dst = nullptr;
     const float *w = nullptr;         // [m] or nullptr
     const uint64_t *wi = nullptr;     // [m] weighted: w / 2^wq as exact integers
+    const uint64_t *wi_inc = nullptr; // [2m] weighted: wi of each incidence entry's edge
     int32_t wq = 0;
     // optional: the other end of each incidence entry and the nodes of
     // degree >= kBigRow (counted a workgroup each)
@@ -96,5 +97,11 @@ struct BatchExtractArgs {
     double *D = nullptr;               // [G] out: largest load per graph
 };
 void launch_extract_batch(const BatchExtractArgs &a, BatchExtractScratch &sc, hipStream_t s);
+
+// wi_inc[j] = wi[edge of incidence entry j] for the 2m entries, so that the
+// weighted extraction reads each row's weights in row order instead of
+// gathering them by edge
+void build_entry_weights(int64_t m, const uint32_t *inc, const uint64_t *wi, uint64_t *wi_inc,
+                         hipStream_t s);
 
 }  // namespace lowd

@@ -101,8 +101,9 @@ __global__ void __launch_bounds__(kBigBlock) k_towards_higher_big(const int32_t 
 // Weighted: the weight from node u towards nodes at higher positions, stored
 // at pos[u], summed exactly: each weight is the integer wi[e] (the weight
 // over 2^q, see fixed_point_weights), so the sums are exact 128-bit integers
-// in any order.  Groups of 8 lanes per node of degree below kBigRow (the
-// others: k_towards_higher_w_big).
+// in any order.  The weights are read per incidence entry (wi_inc, in row
+// order) rather than gathered by edge.  Groups of 8 lanes per node of
+// degree below kBigRow (the others: k_towards_higher_w_big).
 __device__ __forceinline__ u128 shfl_down_u128(u128 v, int d, int width) {
     struct Words {
         int w[4];
@@ -114,9 +115,9 @@ __device__ __forceinline__ u128 shfl_down_u128(u128 v, int d, int width) {
 }
 
 __global__ void __launch_bounds__(256) k_towards_higher_w(int32_t n, const int64_t *row_ptr,
-                                                          const uint32_t *inc, const int32_t *adj,
-                                                          const uint64_t *wi, const int32_t *pos,
-                                                          u128 *hist) {
+                                                          const int32_t *adj,
+                                                          const uint64_t *wi_inc,
+                                                          const int32_t *pos, u128 *hist) {
     const int sub = threadIdx.x & (kRowLanes - 1);
     const int64_t groups = (int64_t)gridDim.x * (blockDim.x / kRowLanes);
     for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / kRowLanes) + threadIdx.x / kRowLanes;
@@ -126,7 +127,7 @@ __global__ void __launch_bounds__(256) k_towards_higher_w(int32_t n, const int64
         const int32_t pu = pos[u];
         u128 acc = 0;
         for (int64_t j = b + sub; j < e; j += kRowLanes)
-            if (pos[adj[j]] > pu) acc += (u128)wi[inc[j] >> 1];
+            if (pos[adj[j]] > pu) acc += (u128)wi_inc[j];
         for (int d = kRowLanes / 2; d > 0; d >>= 1) acc += shfl_down_u128(acc, d, kRowLanes);
         if (sub == 0) hist[pu] = acc;
     }
@@ -134,14 +135,14 @@ __global__ void __launch_bounds__(256) k_towards_higher_w(int32_t n, const int64
 
 // the same for one node of degree >= kBigRow per workgroup
 __global__ void __launch_bounds__(kBigBlock) k_towards_higher_w_big(
-    const int32_t *big, const int64_t *row_ptr, const uint32_t *inc, const int32_t *adj,
-    const uint64_t *wi, const int32_t *pos, u128 *hist) {
+    const int32_t *big, const int64_t *row_ptr, const int32_t *adj, const uint64_t *wi_inc,
+    const int32_t *pos, u128 *hist) {
     __shared__ u128 part[kBigBlock / kWave];
     const int32_t u = big[blockIdx.x];
     const int32_t pu = pos[u];
     u128 acc = 0;
     for (int64_t j = row_ptr[u] + threadIdx.x; j < row_ptr[u + 1]; j += kBigBlock)
-        if (pos[adj[j]] > pu) acc += (u128)wi[inc[j] >> 1];
+        if (pos[adj[j]] > pu) acc += (u128)wi_inc[j];
     for (int d = kWave / 2; d > 0; d >>= 1) acc += shfl_down_u128(acc, d, kWave);
     if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = acc;
     __syncthreads();
@@ -251,13 +252,14 @@ void extract_impl(const ExtractArgs &a, ExtractScratch &sc, hipStream_t s) {
             hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(2 * (int64_t)n, 256)), dim3(256), 0, s,
                                2 * (int64_t)n, (int64_t *)hist);
         } else {
-            if (!a.adj || !a.wi) fail(LOWD_E_ARG, "weighted extraction needs the adjacency");
+            if (!a.adj || !a.wi_inc)
+                fail(LOWD_E_ARG, "weighted extraction needs the adjacency and entry weights");
             hipLaunchKernelGGL(k_towards_higher_w, dim3(grid_for((int64_t)n * kRowLanes, 256)),
-                               dim3(256), 0, s, n, a.row_ptr, a.inc, a.adj, a.wi, sc.pos.p, hist);
+                               dim3(256), 0, s, n, a.row_ptr, a.adj, a.wi_inc, sc.pos.p, hist);
         }
         if (a.m > 0 && a.nbig > 0)
             hipLaunchKernelGGL(k_towards_higher_w_big, dim3((unsigned)a.nbig), dim3(kBigBlock), 0,
-                               s, a.big, a.row_ptr, a.inc, a.adj, a.wi, sc.pos.p, hist);
+                               s, a.big, a.row_ptr, a.adj, a.wi_inc, sc.pos.p, hist);
     } else if (a.adj) {
         hipLaunchKernelGGL(k_towards_higher_small, dim3(grid_for((int64_t)n * kRowLanes, 256)),
                            dim3(256), 0, s, n, a.row_ptr, a.adj, sc.pos.p,
@@ -704,6 +706,23 @@ void launch_extract_batch(const BatchExtractArgs &a, BatchExtractScratch &sc, hi
                        a.seg, a.node_ptr, Na, sc.W.p, a.L64, sc.best.p, a.num, a.den, a.D);
     hipLaunchKernelGGL(k_in_set_batch, dim3(ga), dim3(256), 0, s, a.A, a.act, a.seg, a.node_ptr,
                        sc.pos.p, sc.best.p, a.in_set);
+    LOWD_HIP(hipGetLastError());
+}
+
+namespace {
+__global__ void k_entry_weights(int64_t len, const uint32_t *inc, const uint64_t *wi,
+                                uint64_t *wi_inc) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < len;
+         j += (int64_t)gridDim.x * blockDim.x)
+        wi_inc[j] = wi[inc[j] >> 1];
+}
+}  // namespace
+
+void build_entry_weights(int64_t m, const uint32_t *inc, const uint64_t *wi, uint64_t *wi_inc,
+                         hipStream_t s) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_entry_weights, dim3(grid_for(2 * m, 256)), dim3(256), 0, s, 2 * m, inc,
+                       wi, wi_inc);
     LOWD_HIP(hipGetLastError());
 }
 
